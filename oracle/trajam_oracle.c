@@ -1,0 +1,522 @@
+/*
+ * trajam_oracle.c -- plain, slow, FP64 CPU oracle of the batched
+ * alternating-minimization (AM) projection of Bernstein-polynomial trajectories.
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this file's library.  The product path (the HIP
+ * library under paper_2408_10731_amd/) shares no code, header, table or helper
+ * with it.
+ *
+ * What it computes (thesis ch. 6, "Projection Optimization"):
+ *   project every sample xi_i onto {A xi = b_eq, g(xi) <= 0} by the AM fixed
+ *   point of eqs (fixed_point_1)-(fixed_point_2): per iteration k
+ *     1. waypoints p = P xb, v = Pd xb, a = Pdd xb          (eq parameter)
+ *     2. polar step for every obstacle j and time t          (eqs comp_alpha..comp_d,
+ *        closed forms eqs zeta_2, compute_d_mij, d_max; spherical form eq collision_priest)
+ *     3. polar step for the velocity / acceleration bounds   (eqs fv_priest, fa_priest,
+ *        closed forms eqs alpha_v, alpha_a, compute_dv, compute_da)
+ *     4. residual r = F xb - e and its 2-norm               (Alg 3, "compute the residuals")
+ *     5. multiplier  lam <- lam - rho F^T (F xb - e)        (eq lag)
+ *     6. QP          [I + rho F^T F, A^T; A, 0] [xb; nu] = [xi + lam + rho F^T e; b_eq]
+ *                                                            (eqs affine_trans, matrix_vec)
+ *   F stacks, per axis, P once per obstacle, then Pd and Pdd (eq f_e); it is never
+ *   formed: F^T F = n_o P^T P + Pd^T Pd + Pdd^T Pdd and F^T e sums block by block.
+ *
+ * Readings of the thesis taken here (each one is listed with its reason in the
+ * design notes of the repository):
+ *   - the sign of rho F^T e in eta is '+', from the stationarity of the augmented
+ *     Lagrangian (eq lagrange); the printed '-' is a typo;
+ *   - the multiplier update uses the freshly projected e of the same iteration;
+ *   - the multiplier lives in coefficient space (one entry per coefficient);
+ *   - time grid t_k = k T / (n_p - 1), endpoints included;
+ *   - four boundary rows per axis: position, velocity, acceleration at t = 0 and
+ *     position at t = T;
+ *   - for an ellipse/ellipsoid the angles are taken in coordinates scaled by the
+ *     semi-axes: alpha = atan2(y~/s_y, x~/s_x), beta = atan2(hypot(x~/s_x, y~/s_y), z~/s_z);
+ *     d then follows eq d_max;
+ *   - the velocity / acceleration scale is the 1-D projection min(1, |v|/v_max),
+ *     which makes the kinematic step the exact projection onto the ball;
+ *   - a point exactly at an obstacle centre takes atan2(+0, +0) = 0 (and beta = 0 in
+ *     3D): it is pushed along +x in 2D and along +z in 3D; a zero velocity gives e_v = 0;
+ *   - rho is one fixed scalar for all blocks.
+ *
+ * Build: gcc -O2 -fopenmp -shared -fPIC (no fast-math).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int dims;          /* 2 or 3 */
+    int degree;        /* Bernstein degree n; n_v = n + 1 coefficients per axis */
+    int n_steps;       /* n_p time samples */
+    double horizon;    /* T [s] */
+    double v_max;      /* <= 0 removes the velocity block from F */
+    double a_max;      /* <= 0 removes the acceleration block from F */
+    double rho;        /* penalty weight of the augmented Lagrangian */
+    int n_obs;         /* n_o obstacles (each contributes one copy of P to F) */
+} orc_problem;
+
+/* Deliberate-mistake switch used only by the mutation tests: each code plants
+ * one plausible error in this oracle so the tests can show that a pin catches it.
+ * 0 = correct oracle. */
+static int g_fault = 0;
+void orc_set_fault(int code) { g_fault = code; }
+
+/* ------------------------------------------------------------------ basis -- */
+
+static double binom(int n, int k)
+{
+    double r = 1.0;
+    int i;
+    if (k < 0 || k > n) return 0.0;
+    for (i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+    return r;
+}
+
+/* Bernstein polynomial B_{m,n}(tau) = C(n,m) tau^m (1-tau)^(n-m); 0 outside 0..n. */
+static double bern(int m, int n, double tau)
+{
+    if (m < 0 || m > n || n < 0) return 0.0;
+    return binom(n, m) * pow(tau, m) * pow(1.0 - tau, n - m);
+}
+
+/* Basis matrices of eq (parameter) for a Bernstein basis, row-major [n_p][n_v].
+ * Derivatives use d/dt B_{m,n}(t/T) = (n/T)(B_{m-1,n-1} - B_{m,n-1}). */
+int orc_bernstein(int n, int n_p, double T, double *P, double *Pd, double *Pdd)
+{
+    int k, m, nv = n + 1;
+    if (n < 2 || n_p < 2 || !(T > 0.0)) return -1;
+    for (k = 0; k < n_p; ++k) {
+        double tau = (double)k / (double)(n_p - 1);
+        for (m = 0; m < nv; ++m) {
+            P[k * nv + m] = bern(m, n, tau);
+            Pd[k * nv + m] = (double)n / T * (bern(m - 1, n - 1, tau) - bern(m, n - 1, tau));
+            Pdd[k * nv + m] = (double)n * (double)(n - 1) / (T * T) *
+                              (bern(m - 2, n - 2, tau) - 2.0 * bern(m - 1, n - 2, tau) +
+                               bern(m, n - 2, tau));
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------- fixed matrices -- */
+
+/* A = [P_0; Pd_0; Pdd_0; P_{-1}] (4 x n_v) and H = I + rho F^T F (n_v x n_v). */
+int orc_constraint_matrices(const orc_problem *pr, double *A, double *H)
+{
+    int nv = pr->degree + 1, np = pr->n_steps, i, j, k;
+    double *P = malloc(sizeof(double) * np * nv), *Pd = malloc(sizeof(double) * np * nv),
+           *Pdd = malloc(sizeof(double) * np * nv);
+    if (orc_bernstein(pr->degree, np, pr->horizon, P, Pd, Pdd) != 0) {
+        free(P); free(Pd); free(Pdd);
+        return -1;
+    }
+    for (j = 0; j < nv; ++j) {
+        A[0 * nv + j] = P[0 * nv + j];
+        A[1 * nv + j] = Pd[0 * nv + j];
+        A[2 * nv + j] = Pdd[0 * nv + j];
+        A[3 * nv + j] = P[(np - 1) * nv + j];
+    }
+    for (i = 0; i < nv; ++i)
+        for (j = 0; j < nv; ++j) {
+            double ff = 0.0;
+            for (k = 0; k < np; ++k) {
+                ff += (double)pr->n_obs * P[k * nv + i] * P[k * nv + j];
+                if (pr->v_max > 0.0) ff += Pd[k * nv + i] * Pd[k * nv + j];
+                if (pr->a_max > 0.0) ff += Pdd[k * nv + i] * Pdd[k * nv + j];
+            }
+            H[i * nv + j] = (i == j ? 1.0 : 0.0) + pr->rho * ff;
+        }
+    free(P); free(Pd); free(Pdd);
+    return 0;
+}
+
+/* KKT matrix [[H, A^T], [A, 0]] of eq (matrix_vec), row-major (n_v+4)^2. */
+int orc_kkt_matrix(const orc_problem *pr, double *K)
+{
+    int nv = pr->degree + 1, N = nv + 4, i, j;
+    double *A = malloc(sizeof(double) * 4 * nv), *H = malloc(sizeof(double) * nv * nv);
+    int rc = orc_constraint_matrices(pr, A, H);
+    if (rc == 0) {
+        memset(K, 0, sizeof(double) * N * N);
+        for (i = 0; i < nv; ++i)
+            for (j = 0; j < nv; ++j) K[i * N + j] = H[i * nv + j];
+        for (i = 0; i < 4; ++i)
+            for (j = 0; j < nv; ++j) {
+                K[(nv + i) * N + j] = A[i * nv + j];
+                K[j * N + nv + i] = A[i * nv + j];
+            }
+    }
+    free(A); free(H);
+    return rc;
+}
+
+/* In-place LU with partial pivoting (Doolittle); returns -1 on a zero pivot. */
+int orc_lu_factor(int n, double *M, int *piv)
+{
+    int i, j, k;
+    for (k = 0; k < n; ++k) {
+        int p = k;
+        double best = fabs(M[k * n + k]);
+        for (i = k + 1; i < n; ++i)
+            if (fabs(M[i * n + k]) > best) { best = fabs(M[i * n + k]); p = i; }
+        piv[k] = p;
+        if (best == 0.0) return -1;
+        if (p != k)
+            for (j = 0; j < n; ++j) {
+                double t = M[k * n + j]; M[k * n + j] = M[p * n + j]; M[p * n + j] = t;
+            }
+        for (i = k + 1; i < n; ++i) {
+            double l = M[i * n + k] / M[k * n + k];
+            M[i * n + k] = l;
+            for (j = k + 1; j < n; ++j) M[i * n + j] -= l * M[k * n + j];
+        }
+    }
+    return 0;
+}
+
+void orc_lu_solve(int n, const double *LU, const int *piv, double *x)
+{
+    int i, j;
+    for (i = 0; i < n; ++i)
+        if (piv[i] != i) { double t = x[i]; x[i] = x[piv[i]]; x[piv[i]] = t; }
+    for (i = 0; i < n; ++i)
+        for (j = 0; j < i; ++j) x[i] -= LU[i * n + j] * x[j];
+    for (i = n - 1; i >= 0; --i) {
+        for (j = i + 1; j < n; ++j) x[i] -= LU[i * n + j] * x[j];
+        x[i] /= LU[i * n + i];
+    }
+}
+
+/* One equality-constrained QP (eq over_2 / matrix_vec) solved through the KKT LU:
+ * out = argmin 1/2 x^T H x - q^T x  s.t. A x = b.   q, out: [n_v]; b: [4]. */
+int orc_kkt_solve(const orc_problem *pr, const double *q, const double *b, double *out)
+{
+    int nv = pr->degree + 1, N = nv + 4, i, rc;
+    double *K = malloc(sizeof(double) * N * N), *x = malloc(sizeof(double) * N);
+    int *piv = malloc(sizeof(int) * N);
+    rc = orc_kkt_matrix(pr, K);
+    if (rc == 0) rc = orc_lu_factor(N, K, piv);
+    if (rc == 0) {
+        for (i = 0; i < nv; ++i) x[i] = q[i];
+        for (i = 0; i < 4; ++i) x[nv + i] = b[i];
+        orc_lu_solve(N, K, piv, x);
+        for (i = 0; i < nv; ++i) out[i] = x[i];
+    }
+    free(K); free(x); free(piv);
+    return rc;
+}
+
+/* The same QP by a second, independent route (test cross-check only): the four
+ * boundary rows fix xi_0, xi_1, xi_2 and xi_n; the free block then solves
+ * H_ff x_f = q_f - H_fb x_b by Cholesky. */
+int orc_qp_nullspace(const orc_problem *pr, const double *q, const double *b, double *out)
+{
+    int n = pr->degree, nv = n + 1, nf = nv - 4, i, j, k;
+    double T = pr->horizon;
+    double *A = malloc(sizeof(double) * 4 * nv), *H = malloc(sizeof(double) * nv * nv);
+    double *L = malloc(sizeof(double) * (nf > 0 ? nf * nf : 1));
+    double *y = malloc(sizeof(double) * (nf > 0 ? nf : 1));
+    int rc = orc_constraint_matrices(pr, A, H);
+    if (rc != 0 || n < 3) { free(A); free(H); free(L); free(y); return -1; }
+    out[0] = b[0];
+    out[1] = b[0] + b[1] * T / n;
+    out[2] = b[0] + 2.0 * b[1] * T / n + b[2] * T * T / ((double)n * (n - 1));
+    out[n] = b[3];
+    for (i = 0; i < nf; ++i) {
+        int fi = 3 + i;
+        y[i] = q[fi] - H[fi * nv + 0] * out[0] - H[fi * nv + 1] * out[1] -
+               H[fi * nv + 2] * out[2] - H[fi * nv + n] * out[n];
+        for (j = 0; j <= i; ++j) {
+            double s = H[fi * nv + 3 + j];
+            for (k = 0; k < j; ++k) s -= L[i * nf + k] * L[j * nf + k];
+            if (i == j) {
+                if (s <= 0.0) { free(A); free(H); free(L); free(y); return -1; }
+                L[i * nf + i] = sqrt(s);
+            } else {
+                L[i * nf + j] = s / L[j * nf + j];
+            }
+        }
+    }
+    for (i = 0; i < nf; ++i) {
+        for (k = 0; k < i; ++k) y[i] -= L[i * nf + k] * y[k];
+        y[i] /= L[i * nf + i];
+    }
+    for (i = nf - 1; i >= 0; --i) {
+        for (k = i + 1; k < nf; ++k) y[i] -= L[k * nf + i] * y[k];
+        y[i] /= L[i * nf + i];
+    }
+    for (i = 0; i < nf; ++i) out[3 + i] = y[i];
+    free(A); free(H); free(L); free(y);
+    return 0;
+}
+
+/* ------------------------------------------------------------ polar steps -- */
+
+/* Obstacle polar step for one (obstacle, time) pair: given x~ = p - c and the
+ * semi-axes s, return alpha, beta, d (eqs zeta_2, compute_d_mij, d_max) and the
+ * offset s .* d .* dir(alpha, beta), so that e = c + offset. */
+void orc_polar_obstacle(int D, const double *xt, const double *s, double *alpha,
+                        double *beta, double *d, double *off)
+{
+    double u[3] = {0, 0, 0}, rn = 0.0, al, be, dd, dir[3];
+    int i;
+    for (i = 0; i < D; ++i) { u[i] = xt[i] / s[i]; rn += u[i] * u[i]; }
+    rn = sqrt(rn);
+    al = atan2(u[1], u[0]);
+    be = (D == 3) ? atan2(hypot(u[0], u[1]), u[2]) : M_PI / 2.0;
+    dd = rn > 1.0 ? rn : 1.0;                     /* d >= 1 (eq collision_d) */
+    if (g_fault == 5) dd = rn;                    /* planted: lower bound on d dropped */
+    if (D == 3) {
+        dir[0] = cos(al) * sin(be);
+        dir[1] = sin(al) * sin(be);
+        dir[2] = cos(be);
+    } else {
+        dir[0] = cos(al);
+        dir[1] = sin(al);
+    }
+    for (i = 0; i < D; ++i) off[i] = s[i] * dd * dir[i];
+    *alpha = al;
+    *beta = be;
+    *d = dd;
+}
+
+/* Velocity / acceleration polar step (eqs alpha_v, compute_dv): target of
+ * magnitude bound * d, d = min(1, |v| / bound) in [0, 1], along (alpha, beta). */
+void orc_polar_bound(int D, const double *v, double bound, double *e)
+{
+    double nrm = 0.0, al, be, dd, dir[3];
+    int i;
+    for (i = 0; i < D; ++i) nrm += v[i] * v[i];
+    nrm = sqrt(nrm);
+    al = atan2(v[1], v[0]);
+    be = (D == 3) ? atan2(hypot(v[0], v[1]), v[2]) : M_PI / 2.0;
+    dd = nrm / bound;
+    if (dd > 1.0) dd = 1.0;
+    if (D == 3) {
+        dir[0] = cos(al) * sin(be);
+        dir[1] = sin(al) * sin(be);
+        dir[2] = cos(be);
+    } else {
+        dir[0] = cos(al);
+        dir[1] = sin(al);
+    }
+    for (i = 0; i < D; ++i) e[i] = bound * dd * dir[i];
+}
+
+/* ------------------------------------------------------ one trajectory -- */
+
+typedef struct {
+    const orc_problem *pr;
+    int nv, np, D;
+    const double *P, *Pd, *Pdd;       /* [n_p][n_v] */
+    const double *oc, *ow, *os;       /* obstacles [n_o][D] */
+} orc_ctx;
+
+/* Steps 1-4 at coefficients xb ([D][n_v]).  Outputs (any may be NULL):
+ *   FtE[D][n_v] = F^T e, FtR[D][n_v] = F^T (F xb - e), r2 = |F xb - e|^2,
+ *   rmax = max |component of F xb - e|. */
+static void polar_and_residual(const orc_ctx *c, const double *xb, double *FtE,
+                               double *FtR, double *r2, double *rmax)
+{
+    const orc_problem *pr = c->pr;
+    int D = c->D, nv = c->nv, np = c->np, t, j, ax, m;
+    double acc = 0.0, mx = 0.0;
+    if (FtE) memset(FtE, 0, sizeof(double) * D * nv);
+    if (FtR) memset(FtR, 0, sizeof(double) * D * nv);
+    for (t = 0; t < np; ++t) {
+        double tk = (double)t * pr->horizon / (double)(np - 1);
+        double p[3] = {0, 0, 0}, v[3] = {0, 0, 0}, a[3] = {0, 0, 0};
+        double eo[3] = {0, 0, 0}, ro[3] = {0, 0, 0}, ev[3] = {0, 0, 0}, ea[3] = {0, 0, 0};
+        double rv[3] = {0, 0, 0}, ra[3] = {0, 0, 0};
+        for (ax = 0; ax < D; ++ax)
+            for (m = 0; m < nv; ++m) {
+                p[ax] += c->P[t * nv + m] * xb[ax * nv + m];
+                v[ax] += c->Pd[t * nv + m] * xb[ax * nv + m];
+                a[ax] += c->Pdd[t * nv + m] * xb[ax * nv + m];
+            }
+        for (j = 0; j < pr->n_obs; ++j) {
+            double ctr[3], xt[3], off[3], al, be, dd;
+            for (ax = 0; ax < D; ++ax) {
+                ctr[ax] = c->oc[j * D + ax] + c->ow[j * D + ax] * tk;
+                xt[ax] = p[ax] - ctr[ax];
+            }
+            orc_polar_obstacle(D, xt, &c->os[j * D], &al, &be, &dd, off);
+            for (ax = 0; ax < D; ++ax) {
+                double e = ctr[ax] + off[ax], r = p[ax] - e;
+                eo[ax] += e;
+                ro[ax] += r;
+                acc += r * r;
+                if (fabs(r) > mx) mx = fabs(r);
+            }
+        }
+        if (pr->v_max > 0.0) {
+            orc_polar_bound(D, v, pr->v_max, ev);
+            for (ax = 0; ax < D; ++ax) {
+                rv[ax] = v[ax] - ev[ax];
+                acc += rv[ax] * rv[ax];
+                if (fabs(rv[ax]) > mx) mx = fabs(rv[ax]);
+            }
+        }
+        if (pr->a_max > 0.0) {
+            orc_polar_bound(D, a, pr->a_max, ea);
+            for (ax = 0; ax < D; ++ax) {
+                ra[ax] = a[ax] - ea[ax];
+                acc += ra[ax] * ra[ax];
+                if (fabs(ra[ax]) > mx) mx = fabs(ra[ax]);
+            }
+        }
+        for (ax = 0; ax < D; ++ax)
+            for (m = 0; m < nv; ++m) {
+                /* F^T stacks P^T once per obstacle, then Pd^T and Pdd^T */
+                double pm = c->P[t * nv + m];
+                if (g_fault == 3) pm = c->P[t * nv + (nv - 1 - m)]; /* planted: column order */
+                if (FtE) {
+                    FtE[ax * nv + m] += pm * eo[ax];
+                    if (g_fault != 2) FtE[ax * nv + m] += c->Pd[t * nv + m] * ev[ax];
+                    FtE[ax * nv + m] += c->Pdd[t * nv + m] * ea[ax];
+                }
+                if (FtR)
+                    FtR[ax * nv + m] += pm * ro[ax] + c->Pd[t * nv + m] * rv[ax] +
+                                        c->Pdd[t * nv + m] * ra[ax];
+            }
+    }
+    if (r2) *r2 = acc;
+    if (rmax) *rmax = mx;
+}
+
+/* ---------------------------------------------------------------- public -- */
+
+/* Projects B samples.  Layouts (row-major, float64):
+ *   xi, xi_bar, lam : [B][D][n_v]   (xi_bar, lam: in = initial values, out = final)
+ *   oc, ow, os      : [n_o][D] obstacle centre at t = 0, velocity, semi-axes
+ *   bnd             : [D][4] = (x0, v0, a0, xf) per axis
+ *   res_trace       : [iters][B] 2-norm of F xb^k - e^{k+1} (may be NULL)
+ *   resmax_trace    : [iters][B] max-abs of the same vector (may be NULL)
+ *   freeze_lambda   : 1 keeps lam fixed (test variant)
+ *   n_threads       : OpenMP threads over trajectories (<= 0: runtime default)
+ * Returns 0, or -1 for an invalid problem / singular KKT. */
+int orc_project(const orc_problem *pr, int B, const double *xi, const double *oc,
+                const double *ow, const double *os, const double *bnd, double *xi_bar,
+                double *lam, int iters, double *res_trace, double *resmax_trace,
+                int freeze_lambda, int n_threads)
+{
+    int D = pr->dims, nv = pr->degree + 1, np = pr->n_steps, N = nv + 4;
+    double *P, *Pd, *Pdd, *K;
+    int *piv, rc = 0, i;
+    orc_ctx c;
+    if ((D != 2 && D != 3) || pr->degree < 3 || np < 2 || B < 0 || iters < 0) return -1;
+    P = malloc(sizeof(double) * np * nv);
+    Pd = malloc(sizeof(double) * np * nv);
+    Pdd = malloc(sizeof(double) * np * nv);
+    K = malloc(sizeof(double) * N * N);
+    piv = malloc(sizeof(int) * N);
+    if (orc_bernstein(pr->degree, np, pr->horizon, P, Pd, Pdd) != 0 ||
+        orc_kkt_matrix(pr, K) != 0 || orc_lu_factor(N, K, piv) != 0) {
+        rc = -1;
+        goto done;
+    }
+    c.pr = pr; c.nv = nv; c.np = np; c.D = D;
+    c.P = P; c.Pd = Pd; c.Pdd = Pdd; c.oc = oc; c.ow = ow; c.os = os;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (i = 0; i < B; ++i) {
+        double *xb = xi_bar + (size_t)i * D * nv, *lm = lam + (size_t)i * D * nv;
+        const double *x0 = xi + (size_t)i * D * nv;
+        double *FtE = malloc(sizeof(double) * D * nv), *FtR = malloc(sizeof(double) * D * nv);
+        double *rhs = malloc(sizeof(double) * N);
+        int k, ax, m;
+        for (k = 0; k < iters; ++k) {
+            double r2, rmax;
+            polar_and_residual(&c, xb, FtE, FtR, &r2, &rmax);
+            if (res_trace) res_trace[(size_t)k * B + i] = sqrt(r2);
+            if (resmax_trace) resmax_trace[(size_t)k * B + i] = rmax;
+            if (!freeze_lambda)
+                for (m = 0; m < D * nv; ++m) {
+                    if (g_fault == 4) lm[m] += pr->rho * FtR[m];   /* planted: sign */
+                    else lm[m] -= pr->rho * FtR[m];
+                }
+            for (ax = 0; ax < D; ++ax) {
+                for (m = 0; m < nv; ++m) {
+                    double fe = pr->rho * FtE[ax * nv + m];
+                    if (g_fault == 1) fe = -fe;                    /* planted: printed sign */
+                    rhs[m] = x0[ax * nv + m] + lm[ax * nv + m] + fe;
+                }
+                for (m = 0; m < 4; ++m) rhs[nv + m] = bnd[ax * 4 + m];
+                orc_lu_solve(N, K, piv, rhs);
+                for (m = 0; m < nv; ++m) xb[ax * nv + m] = rhs[m];
+            }
+        }
+        free(FtE); free(FtR); free(rhs);
+    }
+done:
+    free(P); free(Pd); free(Pdd); free(K); free(piv);
+    return rc;
+}
+
+/* Steps 1-4 only, at the given coefficients: res_l2[B], res_max[B]. */
+int orc_residuals(const orc_problem *pr, int B, const double *xi_bar, const double *oc,
+                  const double *ow, const double *os, double *res_l2, double *res_max,
+                  int n_threads)
+{
+    int D = pr->dims, nv = pr->degree + 1, np = pr->n_steps, i;
+    double *P, *Pd, *Pdd;
+    orc_ctx c;
+    if ((D != 2 && D != 3) || pr->degree < 2 || np < 2 || B < 0) return -1;
+    P = malloc(sizeof(double) * np * nv);
+    Pd = malloc(sizeof(double) * np * nv);
+    Pdd = malloc(sizeof(double) * np * nv);
+    if (orc_bernstein(pr->degree, np, pr->horizon, P, Pd, Pdd) != 0) {
+        free(P); free(Pd); free(Pdd);
+        return -1;
+    }
+    c.pr = pr; c.nv = nv; c.np = np; c.D = D;
+    c.P = P; c.Pd = Pd; c.Pdd = Pdd; c.oc = oc; c.ow = ow; c.os = os;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (i = 0; i < B; ++i) {
+        double r2, mx;
+        polar_and_residual(&c, xi_bar + (size_t)i * D * nv, NULL, NULL, &r2, &mx);
+        res_l2[i] = sqrt(r2);
+        if (res_max) res_max[i] = mx;
+    }
+    free(P); free(Pd); free(Pdd);
+    return 0;
+}
+
+/* F^T e and F^T r at one coefficient vector (test access to steps 1-4). */
+int orc_polar_products(const orc_problem *pr, const double *xb, const double *oc,
+                       const double *ow, const double *os, double *FtE, double *FtR,
+                       double *r2)
+{
+    int D = pr->dims, nv = pr->degree + 1, np = pr->n_steps;
+    double *P = malloc(sizeof(double) * np * nv), *Pd = malloc(sizeof(double) * np * nv),
+           *Pdd = malloc(sizeof(double) * np * nv);
+    orc_ctx c;
+    if (orc_bernstein(pr->degree, np, pr->horizon, P, Pd, Pdd) != 0) {
+        free(P); free(Pd); free(Pdd);
+        return -1;
+    }
+    c.pr = pr; c.nv = nv; c.np = np; c.D = D;
+    c.P = P; c.Pd = Pd; c.Pdd = Pdd; c.oc = oc; c.ow = ow; c.os = os;
+    polar_and_residual(&c, xb, FtE, FtR, r2, NULL);
+    free(P); free(Pd); free(Pdd);
+    return 0;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,185 @@
+"""Seeded synthetic inputs for the batched alternating-minimization projection.
+
+This module only draws random numbers and lays them out.  It holds none of the
+method's arithmetic, so both the CPU oracle (through the tests) and the HIP path
+consume exactly the same host arrays.
+
+The thesis evaluates on BARN, crowd simulations and real robots, none of which is
+available; the recipes below stand in for them with the shapes and value
+distributions of the five evaluation configurations (2D/3D point robot, circular or
+ellipsoidal obstacles, Bernstein trajectories with a fixed horizon):
+
+* samples: the straight start-goal line written as Bernstein coefficients
+  (coefficient m at s + (m/n)(g - s)) plus i.i.d. N(0, sigma^2) per coefficient;
+* obstacles: centres uniform in a box, semi-axes uniform in a range (one radius for
+  circles/spheres, independent per axis for ellipsoids), optional constant velocity
+  with each component uniform in [-v, v];  an obstacle whose centre lies within
+  (largest semi-axis + 0.5 m) of the start or the goal is redrawn;
+* boundary: start and goal positions, zero initial velocity and acceleration.
+
+Arrays use float64; the HIP path casts to its own precision on upload.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+MASTER_SEED = 240810731
+
+
+@dataclasses.dataclass
+class Workload:
+    """One projection problem plus a batch of samples to project."""
+
+    name: str
+    dims: int
+    degree: int
+    n_steps: int
+    horizon: float
+    v_max: float
+    a_max: float
+    rho: float
+    obs_centre: np.ndarray  # [n_o, D]
+    obs_vel: np.ndarray  # [n_o, D]
+    obs_axes: np.ndarray  # [n_o, D]
+    boundary: np.ndarray  # [D, 4] = (x0, v0, a0, xf) per axis
+    xi: np.ndarray  # [B, D, n_v]
+    iters: int
+    precision: str = "fp64"
+    n_agents: int = 1
+    agent_radius: float = 0.0
+
+    @property
+    def n_v(self) -> int:
+        return self.degree + 1
+
+    @property
+    def n_obs(self) -> int:
+        return int(self.obs_centre.shape[0])
+
+    @property
+    def batch(self) -> int:
+        return int(self.xi.shape[0])
+
+    def subset(self, batch: int) -> "Workload":
+        """Same problem, the first `batch` samples."""
+        return dataclasses.replace(self, xi=np.ascontiguousarray(self.xi[:batch]))
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def draw_obstacles(rng, n_o, dims, lo, hi, axes_range, per_axis, start, goal,
+                   speed=0.0, clearance=0.5):
+    """Rejection-sampled obstacles; returns centre, velocity, semi-axes [n_o, D]."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    start = np.asarray(start, dtype=np.float64)
+    goal = np.asarray(goal, dtype=np.float64)
+    centre = np.zeros((n_o, dims))
+    axes = np.zeros((n_o, dims))
+    for j in range(n_o):
+        while True:
+            c = rng.uniform(lo, hi)
+            if per_axis:
+                s = rng.uniform(axes_range[0], axes_range[1], size=dims)
+            else:
+                s = np.full(dims, rng.uniform(axes_range[0], axes_range[1]))
+            reach = s.max() + clearance
+            if np.linalg.norm(c - start) > reach and np.linalg.norm(c - goal) > reach:
+                break
+        centre[j] = c
+        axes[j] = s
+    if speed > 0.0:
+        vel = rng.uniform(-speed, speed, size=(n_o, dims))
+    else:
+        vel = np.zeros((n_o, dims))
+    return centre, vel, axes
+
+
+def line_samples(rng, batch, degree, start, goal, sigma):
+    """Straight start-goal line as Bernstein coefficients plus Gaussian noise."""
+    start = np.asarray(start, dtype=np.float64)
+    goal = np.asarray(goal, dtype=np.float64)
+    dims = start.shape[0]
+    frac = np.arange(degree + 1, dtype=np.float64) / degree
+    line = start[:, None] + frac[None, :] * (goal - start)[:, None]  # [D, n_v]
+    noise = rng.normal(0.0, sigma, size=(batch, dims, degree + 1))
+    return np.ascontiguousarray(line[None] + noise)
+
+
+def boundary_rows(start, goal):
+    start = np.asarray(start, dtype=np.float64)
+    goal = np.asarray(goal, dtype=np.float64)
+    b = np.zeros((start.shape[0], 4))
+    b[:, 0] = start
+    b[:, 3] = goal
+    return b
+
+
+def config1(batch: int = 64, seed: Optional[int] = None) -> Workload:
+    """2D, degree 10, 100 steps over 10 s, 10 circles r~U(0.4,0.6) in [0,10]^2, FP64."""
+    rng = _rng(MASTER_SEED + 1 if seed is None else seed)
+    start, goal = (0.0, 5.0), (10.0, 5.0)
+    c, w, s = draw_obstacles(rng, 10, 2, (0, 0), (10, 10), (0.4, 0.6), False, start, goal)
+    xi = line_samples(rng, batch, 10, start, goal, 0.5)
+    return Workload("cfg1-2d-fp64", 2, 10, 100, 10.0, 1.5, 2.0, 1.0, c, w, s,
+                    boundary_rows(start, goal), xi, 100, "fp64")
+
+
+def config2(batch: int = 1024, seed: Optional[int] = None) -> Workload:
+    """2D, degree 10, 100 steps over 30 s, 50 circles r~U(0.3,0.8) in [0,30]^2, FP32."""
+    rng = _rng(MASTER_SEED + 2 if seed is None else seed)
+    start, goal = (0.0, 15.0), (30.0, 15.0)
+    c, w, s = draw_obstacles(rng, 50, 2, (0, 0), (30, 30), (0.3, 0.8), False, start, goal)
+    xi = line_samples(rng, batch, 10, start, goal, 0.5)
+    return Workload("cfg2-2d-fp32", 2, 10, 100, 30.0, 1.5, 2.0, 1.0, c, w, s,
+                    boundary_rows(start, goal), xi, 50, "fp32")
+
+
+def config3(batch: int = 4096, seed: Optional[int] = None) -> Workload:
+    """3D, degree 15, 150 steps over 20 s, 200 ellipsoids (semi-axes U(0.3,1.0) each)."""
+    rng = _rng(MASTER_SEED + 3 if seed is None else seed)
+    start, goal = (0.0, 10.0, 3.0), (20.0, 10.0, 3.0)
+    c, w, s = draw_obstacles(rng, 200, 3, (0, 0, 0), (20, 20, 6), (0.3, 1.0), True,
+                             start, goal)
+    xi = line_samples(rng, batch, 15, start, goal, 0.5)
+    return Workload("cfg3-3d-bf16", 3, 15, 150, 20.0, 1.5, 2.0, 1.0, c, w, s,
+                    boundary_rows(start, goal), xi, 50, "bf16")
+
+
+def config4_scene(seed: int, n_obs: int = 100, batch: int = 2000) -> Workload:
+    """2D, degree 10, 100 steps over 30 s, 100 moving circles (velocity U(-1,1) m/s)."""
+    rng = _rng(seed)
+    start, goal = (0.0, 15.0), (30.0, 15.0)
+    c, w, s = draw_obstacles(rng, n_obs, 2, (0, 0), (30, 30), (0.3, 0.8), False,
+                             start, goal, speed=1.0)
+    xi = line_samples(rng, batch, 10, start, goal, 0.5)
+    return Workload("cfg4-2d-dynamic", 2, 10, 100, 30.0, 1.5, 2.0, 1.0, c, w, s,
+                    boundary_rows(start, goal), xi, 15, "fp32")
+
+
+def config4(batch: int = 2000, seed: Optional[int] = None) -> Workload:
+    return config4_scene(MASTER_SEED + 4 if seed is None else seed, batch=batch)
+
+
+def tiny(dims: int = 2, batch: int = 3, n_obs: int = 2, degree: int = 5,
+         n_steps: int = 9, seed: int = 7, speed: float = 0.0,
+         per_axis: bool = False) -> Workload:
+    """A very small problem for brute-force and by-hand checks."""
+    rng = _rng(seed)
+    start = (0.0,) * (dims - 1) + (0.0,)
+    goal = (4.0,) + (0.0,) * (dims - 1)
+    lo = (0.5,) + (-1.0,) * (dims - 1)
+    hi = (3.5,) + (1.0,) * (dims - 1)
+    c, w, s = draw_obstacles(rng, n_obs, dims, lo, hi, (0.3, 0.7), per_axis, start, goal,
+                             speed=speed, clearance=0.1)
+    xi = line_samples(rng, batch, degree, start, goal, 0.4)
+    return Workload(f"tiny-{dims}d", dims, degree, n_steps, 4.0, 1.5, 2.0, 1.0, c, w, s,
+                    boundary_rows(start, goal), xi, 5, "fp64")
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
