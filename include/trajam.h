@@ -1,0 +1,187 @@
+/*
+ * trajam.h -- C ABI of the MI355X (gfx950) batched alternating-minimization (AM)
+ * projection of Bernstein-polynomial trajectories.
+ *
+ * The operation (thesis ch. 6, "Projection Optimization", eqs projection_cost to
+ * comp_zeta): every sample xi_i of a batch is projected onto
+ *     { A xi = b_eq,  obstacle avoidance,  |velocity| <= v_max,  |acceleration| <= a_max }
+ * by the AM fixed point of eqs (fixed_point_1)-(fixed_point_2).  One iteration is
+ *   (a)  the closed-form polar step (alpha, beta, d) for every (sample, obstacle,
+ *        time) and for the velocity / acceleration bounds of every (sample, time)
+ *        (ch. 4 eqs collision_x..d_max, ch. 5 eqs zeta_2..compute_da);
+ *   (c)  the multiplier update lam <- lam - rho F^T (F xb - e) (ch. 6 eq lag) and
+ *        the residual |F xb - e|_2 (Alg 3, "compute the residuals");
+ *   (b)  the equality-constrained QP with the fixed matrix [I + rho F^T F, A^T; A, 0]
+ *        (ch. 6 eqs affine_trans / matrix_vec; ch. 5 eqs over_1..over_3), applied to
+ *        all samples at once with a precomputed inverse.
+ *
+ * Conventions for every entry point:
+ *   - every call returns a trajam_status; 0 is success and nothing else is;
+ *   - no C++ exception crosses this boundary;
+ *   - all argument validation happens on the host before any device work, so an
+ *     invalid call never launches a kernel;
+ *   - "device pointer" means memory the caller allocated on the current HIP device
+ *     (for example a PyTorch tensor); the caller owns it, the library never frees it;
+ *   - calls are asynchronous on the HIP stream the caller passes (NULL = the null
+ *     stream); device errors surface as TRAJAM_ERR_DEVICE from the call that
+ *     launched, or from a later call;
+ *   - one solver handle is used by one host thread at a time.
+ *
+ * Layouts (row-major, C order):
+ *   xi, xi_bar, lambda      [batch][dims][degree + 1]   scalar = solver precision
+ *   obs_centre, obs_vel,
+ *   obs_axes                [n_obstacles][dims]         scalar = solver precision
+ *                           centre at t = 0 [m], constant velocity [m/s],
+ *                           semi-axes [m] (> 0); obstacle centre at time t is
+ *                           centre + t * vel
+ *   boundary_host           [dims][4] double, HOST memory: (x0, v0, a0, xf) per axis
+ *   res_trace               [iters][batch]   scalar = solver precision
+ *   flags                   [batch] uint32
+ * The solver precision is double for TRAJAM_FP64 and float for TRAJAM_FP32 and
+ * TRAJAM_BF16_REFINE.
+ */
+#ifndef TRAJAM_H
+#define TRAJAM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TRAJAM_OK = 0,
+    TRAJAM_ERR_INVALID = -1,     /* bad argument or problem description */
+    TRAJAM_ERR_UNSUPPORTED = -2, /* valid request outside what this build supports */
+    TRAJAM_ERR_NUMERIC = -3,     /* singular or non-finite fixed matrix at init */
+    TRAJAM_ERR_DEVICE = -4,      /* a HIP call failed (allocation, launch, fault) */
+    TRAJAM_ERR_CAPACITY = -5     /* batch larger than max_batch given at init */
+} trajam_status;
+
+typedef enum {
+    TRAJAM_FP64 = 0,        /* every step in double */
+    TRAJAM_FP32 = 1,        /* every step in float; fixed matrices computed in double */
+    TRAJAM_BF16_REFINE = 2  /* float state; the QP product on bf16 matrix cores with
+                               a hi/lo split, fp32 accumulation and one refinement
+                               pass; boundary coefficients set from double values */
+} trajam_precision;
+
+/* Obstacle shape (thesis ch. 6 eq coll_multiagent_priest: axis-aligned ellipsoids;
+ * ch. 4-5 use circles).  The polar step is the same closed form for both; the
+ * sphere model only lets the kernel test |x~|^2 < r^2 without per-axis scaling. */
+typedef enum {
+    TRAJAM_ELLIPSOID = 0, /* semi-axes obs_axes[j][0..dims) */
+    TRAJAM_SPHERE = 1     /* radius obs_axes[j][0]; the other entries are ignored */
+} trajam_obstacle_model;
+
+/* Per-sample status bits written to `flags`. */
+#define TRAJAM_FLAG_NONFINITE 1u /* a residual or coefficient became NaN / Inf */
+#define TRAJAM_FLAG_GREW 2u      /* last residual of the call exceeds the first */
+
+/* One problem class: everything that fixes the KKT matrix (thesis ch. 6, the
+ * "one-time computation" of M in eq affine_trans).  Host values. */
+typedef struct {
+    int32_t dims;          /* 2 or 3 */
+    int32_t degree;        /* Bernstein degree n, 3 <= n <= 15; n + 1 coefficients per axis */
+    int32_t n_steps;       /* n_p time samples, n + 1 <= n_p <= 256; t_k = k T / (n_p - 1) */
+    double horizon;        /* T > 0 [s] */
+    double v_max;          /* > 0: velocity bound; <= 0 removes that block from F */
+    double a_max;          /* > 0: acceleration bound; <= 0 removes that block from F */
+    double rho;            /* augmented-Lagrangian weight, > 0 */
+    int32_t n_obstacles;   /* n_o >= 0; each obstacle adds one copy of P to F */
+    int32_t n_agents;      /* 1 (single robot); other values are rejected by this build */
+    double agent_radius;   /* unused when n_agents == 1 */
+    int32_t max_batch;     /* largest batch a call may pass (>= 1) */
+    int32_t precision;     /* a trajam_precision value */
+    int32_t obstacle_model; /* a trajam_obstacle_model value */
+} trajam_problem;
+
+typedef struct trajam_solver trajam_solver; /* opaque; owns device constants */
+
+/* Validates `p`, computes the fixed matrices in double on the host (Bernstein
+ * basis, H = I + rho F^T F, the inverse of its free block), uploads them and
+ * returns a handle in *out.  Uses the current HIP device.
+ * Errors: INVALID (bad field), UNSUPPORTED (n_agents != 1), NUMERIC (H not
+ * positive definite), DEVICE (allocation / copy failed).  On error *out is NULL. */
+trajam_status trajam_init(const trajam_problem *p, trajam_solver **out);
+
+/* Frees the handle and its device memory (never the caller's buffers).  NULL is a
+ * no-op.  The caller must make sure no work using the handle is still queued. */
+void trajam_destroy(trajam_solver *s);
+
+/* Runs `iters` AM iterations on `batch` samples (thesis ch. 6 eqs comp_alpha to
+ * comp_zeta, in that order), in one launch.
+ *   xi            device, [batch][dims][n+1]: the samples to project (read only)
+ *   boundary_host host,   [dims][4]: (x0, v0, a0, xf) of eq eq_modify11
+ *   obs_*         device, [n_obstacles][dims] (see layouts above); obs_centre and
+ *                 obs_axes may be NULL only when n_obstacles == 0; obs_vel == NULL
+ *                 means static obstacles (a faster loop than passing zeros)
+ *   xi_bar        device, [batch][dims][n+1]: in = initial iterate (a copy of xi for a
+ *                 cold start, or a warm start), out = iterate after `iters` steps
+ *   lambda        device, [batch][dims][n+1]: in = initial multiplier (zeros for a
+ *                 cold start), out = multiplier after `iters` steps
+ *   res_trace     device, [iters][batch] or NULL: res_trace[k][i] = |F xb_i^k - e|_2,
+ *                 the residual of iterate k after its own polar step
+ *   flags         device, [batch] or NULL: TRAJAM_FLAG_* bits of this call
+ *   stream        hipStream_t or NULL
+ * The state of the iteration is (xi_bar, lambda), so a call with iters = a followed
+ * by a call with iters = b gives the same result as one call with iters = a + b.
+ * Errors: INVALID (NULL handle or required pointer, iters < 0, batch < 0),
+ * CAPACITY (batch > max_batch), DEVICE (launch failed).  batch == 0 or iters == 0
+ * is a successful no-op. */
+trajam_status trajam_project(trajam_solver *s, int32_t batch, const void *xi,
+                             const double *boundary_host, const void *obs_centre,
+                             const void *obs_vel, const void *obs_axes, void *xi_bar,
+                             void *lambda, int32_t iters, void *res_trace, uint32_t *flags,
+                             void *stream);
+
+/* Steps (a) and the residual norm only, at the given coefficients, without
+ * touching any multiplier (thesis Alg 3, "compute the residuals set r").
+ *   xi_bar   device, [batch][dims][n+1]
+ *   res_l2   device, [batch]: |F xb - e|_2
+ *   res_max  device, [batch] or NULL: largest |component| of F xb - e
+ * Errors: as trajam_project. */
+trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const void *xi_bar,
+                               const void *obs_centre, const void *obs_vel,
+                               const void *obs_axes, void *res_l2, void *res_max,
+                               void *stream);
+
+/* The fixed matrices trajam_init computes and uploads, returned in double on the
+ * host for inspection and CPU tests.  Host only: no device work, no handle.
+ * Any output pointer may be NULL.
+ *   P, Pd, Pdd  [n_steps][n+1]  basis rows and their first / second time derivatives
+ *   H           [n+1][n+1]      I + rho F^T F (one axis; every axis is the same)
+ *   W           [n-3][n+1]      the QP update operator of the free coefficients
+ *                               3..n-1: delta_free = W z, where z holds the KKT
+ *                               defect g at free coefficients and the boundary
+ *                               defect (xi*_b - xb_b) at coefficients 0, 1, 2, n
+ * Errors: INVALID, UNSUPPORTED (as trajam_init), NUMERIC. */
+trajam_status trajam_fixed_matrices(const trajam_problem *p, double *P, double *Pd,
+                                    double *Pdd, double *H, double *W);
+
+/* Launch shape of trajam_project / trajam_residuals: samples per workgroup.  Each
+ * sample takes n_steps rounded up to a multiple of 64 lanes and a workgroup holds
+ * at most 256 lanes, so tb is in [1, 256 / roundup64(n_steps)].  The autotuner
+ * picks it; the result does not depend on it (every sample runs the same
+ * arithmetic in the same order).  Errors: INVALID. */
+trajam_status trajam_set_samples_per_workgroup(trajam_solver *s, int32_t tb);
+int32_t trajam_samples_per_workgroup(const trajam_solver *s); /* -1 for NULL */
+
+/* Boundary coefficients xi_0, xi_1, xi_2, xi_n implied by (x0, v0, a0, xf) for
+ * one axis (the unique solution of the four boundary rows).  Host only. */
+trajam_status trajam_boundary_coefficients(const trajam_problem *p, const double *b4,
+                                           double *coef4);
+
+/* Static description of a status code.  Never NULL. */
+const char *trajam_status_string(trajam_status st);
+
+/* Message of the last failed call on this handle (empty if none).  Valid until
+ * the next call on the handle.  NULL handle: the message of the last failed
+ * trajam_init on this thread. */
+const char *trajam_last_error(const trajam_solver *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRAJAM_H */

@@ -1,0 +1,65 @@
+// Internal interface between the C-ABI layer (trajam_api.cpp) and the gfx950
+// kernels (am_kernels.hip).  Not installed; not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace trajam {
+
+// Largest workgroup the AM kernels are built for (four wave64s).
+constexpr int kMaxThreads = 256;
+// Largest Bernstein degree + 1 supported (coefficient registers are sized for it).
+constexpr int kMaxCoeffs = 16;
+
+// Everything one fused AM launch needs.  T is double (FP64) or float (FP32 and
+// BF16_REFINE).  Passed by value as kernel arguments.
+template <typename T>
+struct AmArgs {
+    int batch;       // samples in this call
+    int n_p;         // time samples
+    int nv;          // coefficients per axis (degree + 1)
+    int n_o;         // obstacles
+    int iters;       // AM iterations in this launch
+    int tpad;        // threads per trajectory: n_p rounded up to a multiple of 64
+    int tb;          // trajectories per workgroup
+    int use_v, use_a;
+    int sphere;      // obstacles are spheres/circles of radius axes[j][0]
+    int dynamic;     // obstacles move (velocity given)
+    T rho, vmax, amax, dt;  // dt = T / (n_p - 1)
+    T xiB[3][4];            // closed-form boundary coefficients (xi_0, xi_1, xi_2, xi_n) per axis
+    const T *phi;           // [3][n_p][NVP]: rows of P, Pd, Pdd, zero padded to NVP
+    const T *W;             // [NVP - 4 rows used: nv - 4][NVP] QP update operator
+    const T *obs;           // packed obstacles [n_o][REC] (see obstacle_record_len)
+    const T *xi;            // [batch][D][nv]
+    T *xb;                  // [batch][D][nv] in/out
+    T *lam;                 // [batch][D][nv] in/out
+    T *res;                 // [iters][batch] or null
+    uint32_t *flags;        // [batch] or null
+    T *res_max;             // residual-only launches: [batch] or null
+    // BF16_REFINE: the QP operator split into bf16 hi and lo parts, and H_ff for the
+    // refinement pass (only read when the launch uses the matrix-core QP step).
+    const uint16_t *Whi;    // [16][16] bf16 bits, rows = free index, cols = coefficient
+    const uint16_t *Wlo;    // [16][16]
+    const T *Hff;           // [16][16] free-free block of H (zero padded)
+};
+
+// Packed obstacle record length (scalars), any dims.
+constexpr int kObstacleRecord = 16;
+
+// Launchers.  Return the HIP error of the launch.  `nvp` is the padded coefficient
+// count (8, 12 or 16); `mfma_qp` selects the bf16 matrix-core QP step.
+hipError_t launch_project_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st);
+hipError_t launch_project_f32(int dims, int nvp, bool mfma_qp, const AmArgs<float> &a,
+                              hipStream_t st);
+hipError_t launch_residual_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st);
+hipError_t launch_residual_f32(int dims, int nvp, const AmArgs<float> &a, hipStream_t st);
+hipError_t launch_pack_obstacles_f64(int dims, int n_o, const double *c, const double *w,
+                                     const double *s, double *out, hipStream_t st);
+hipError_t launch_pack_obstacles_f32(int dims, int n_o, const float *c, const float *w,
+                                     const float *s, float *out, hipStream_t st);
+
+// Dynamic LDS bytes of one AM workgroup.
+size_t project_lds_bytes(int dims, int nvp, int tpad, int tb, size_t scalar);
+
+}  // namespace trajam

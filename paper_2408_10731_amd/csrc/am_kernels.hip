@@ -1,0 +1,672 @@
+// gfx950 kernels of the batched alternating-minimization (AM) projection of
+// Bernstein trajectories (thesis ch. 6, eqs comp_alpha .. comp_zeta).
+//
+// Design (MI355X first):
+//  * Samples are independent for the whole iteration, so one launch runs all K
+//    iterations: each workgroup owns `tb` samples and keeps their state (xb in LDS,
+//    lambda and xi in registers of the owning lanes) on chip from the first
+//    iteration to the last.  HBM sees xi / xb / lambda once in and once out, plus
+//    the residual trace: the kernel is bound by the VALU, not by memory.
+//  * Lane layout: `tpad` lanes per sample (n_p rounded up to whole wave64s), lane t
+//    owns time sample t.  Its rows of P, Pd, Pdd stay in registers for the whole
+//    launch, so the waypoint map (eq parameter) and its transpose are register FMAs.
+//  * The obstacle loop reads one packed obstacle record per step at a wave-uniform
+//    address, which the compiler turns into scalar loads: obstacle data sits in
+//    SGPRs and costs no VGPR, LDS or vector-memory traffic.
+//  * The multiplier step needs F^T r, a sum over all time samples of every lane's
+//    P-row times its residual.  Each wave reduces its D*NVP partial products with a
+//    butterfly reduce-scatter (about one shuffle per value instead of log2(64) per
+//    value); waves whose residuals are all zero (the common case near convergence)
+//    skip it.
+//  * The QP (eq affine_trans) uses the precomputed inverse of the free block of
+//    I + rho F^T F in delta form (see trajam_api.cpp): the fixed matrix is applied to
+//    the defect, which tends to zero, so reduced precision only perturbs the step.
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include "am_internal.h"
+
+namespace trajam {
+namespace {
+
+__device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+
+// ---- cross-lane exchanges (gfx950) ------------------------------------------
+// v_permlane32_swap exchanges the upper 32 lanes of one VGPR with the lower 32 lanes
+// of another; v_permlane16_swap does the same for the odd 16-lane rows of one and
+// the even rows of the other.  DPP moves data inside 16-lane rows for free as an
+// operand modifier of the consuming add.
+__device__ __forceinline__ void swap32(float &a, float &b)
+{
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap16(float &a, float &b)
+{
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap32(double &a, double &b)
+{
+    const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+    auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+    auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    a = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    b = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ __forceinline__ void swap16(double &a, double &b)
+{
+    const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+    auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+    auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+    a = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    b = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+
+// DPP controls: rotate a 16-lane row by 8 (= lane ^ 8), mirror each 8-lane half row
+// (lane i <-> 7 - i), and the quad permutations lane ^ 2, lane ^ 1.
+constexpr int kDppRor8 = 0x128, kDppHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x)
+{
+    const long long u = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// One halving step inside 16-lane rows: lanes with `up` keep the upper half of the
+// n values, their partner (selected by CTRL) keeps the lower half, and each adds
+// the half it keeps from its partner.  The empty asm keeps the two candidates as
+// register values so the select never becomes a runtime index into the array.
+template <typename T, int CTRL>
+__device__ __forceinline__ void halve_dpp(T *c, int n, bool up)
+{
+#pragma unroll
+    for (int i = 0; i < n / 2; ++i) {
+        T lo = c[i], hi = c[i + n / 2];
+        asm volatile("" : "+v"(lo), "+v"(hi));
+        const T keep = up ? hi : lo;
+        const T send = up ? lo : hi;
+        c[i] = keep + dpp<CTRL>(send);
+    }
+}
+
+// Butterfly reduce-scatter over a wave64: on entry every lane holds V partial
+// values c[0..V); on exit the lane returns the sum over all 64 lanes of
+// c[lane >> (6 - log2 V)].  Step s halves the live values: the lanes whose lane bit
+// (5 - s) is set keep the upper half.  About V exchanges in total instead of
+// V log2(64).
+template <typename T, int V>
+__device__ __forceinline__ T reduce_scatter(T *c, int lane)
+{
+    static_assert(V >= 16 && V <= 64, "reduce-scatter width");
+    int n = V;
+#pragma unroll
+    for (int i = 0; i < V / 2; ++i) {  // lane bit 5
+        swap32(c[i], c[i + V / 2]);
+        c[i] = c[i] + c[i + V / 2];
+    }
+    n = V / 2;
+#pragma unroll
+    for (int i = 0; i < V / 4; ++i) {  // lane bit 4
+        swap16(c[i], c[i + V / 4]);
+        c[i] = c[i] + c[i + V / 4];
+    }
+    n = V / 4;
+    halve_dpp<T, kDppRor8>(c, n, (lane & 8) != 0);  // lane bit 3
+    n /= 2;
+    halve_dpp<T, kDppHalfMirror>(c, n, (lane & 4) != 0);  // lane bit 2
+    n /= 2;
+    T v;
+    if (V == 16) {
+        v = c[0];
+        v += dpp<kDppXor2>(v);
+        v += dpp<kDppXor1>(v);
+    } else if (V == 32) {
+        halve_dpp<T, kDppXor2>(c, n, (lane & 2) != 0);  // lane bit 1
+        v = c[0];
+        v += dpp<kDppXor1>(v);
+    } else {
+        halve_dpp<T, kDppXor2>(c, n, (lane & 2) != 0);
+        halve_dpp<T, kDppXor1>(c, n / 2, (lane & 1) != 0);  // lane bit 0
+        v = c[0];
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+constexpr int pow2ceil(int x) { return x <= 1 ? 1 : 2 * pow2ceil((x + 1) / 2); }
+
+// Obstacle records are read through the constant address space: the address is
+// wave-uniform and the data is never written by the kernel, so the loads become
+// scalar loads into SGPRs (no VGPR, LDS or vector-memory cost).
+#define TRAJAM_CONST_AS __attribute__((address_space(4)))
+
+// Record slots (see pack_obstacles_kernel): centre, -velocity, 1/semi-axes,
+// semi-axes, -radius^2, radius.
+constexpr int kOC = 0, kOW = 3, kOI = 6, kOS = 9, kONR2 = 12, kOR = 13;
+
+// Signed inside test of one obstacle at one lane: q < 0 iff the point is inside.
+// Spheres/circles: q = |x~|^2 - r^2; ellipsoids: q = |x~ ./ s|^2 - 1.
+template <typename T, int D, bool SPH, bool DYN>
+__device__ __forceinline__ T obstacle_q(const TRAJAM_CONST_AS T *o, const T (&p)[D], T tt)
+{
+    T dx[D];
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        dx[ax] = p[ax] - o[kOC + ax];
+        if (DYN) dx[ax] = fma(o[kOW + ax], tt, dx[ax]);
+    }
+    T q;
+    if (SPH) {
+        q = fma(dx[D - 1], dx[D - 1], o[kONR2]);
+#pragma unroll
+        for (int ax = D - 2; ax >= 0; --ax) q = fma(dx[ax], dx[ax], q);
+    } else {
+        q = T(-1);
+#pragma unroll
+        for (int ax = D - 1; ax >= 0; --ax) {
+            const T u = dx[ax] * o[kOI + ax];
+            q = fma(u, u, q);
+        }
+    }
+    return q;
+}
+
+// Residual of one obstacle for a lane known to be inside (rare path): the point is
+// pushed onto the surface along the (scaled) ray from the centre, r = x~ (1 - 1/|u|);
+// at the exact centre the angles are atan2(0, 0) = 0, i.e. the push is along +x (2D)
+// or +z (3D), and r = -s along that axis.
+template <typename T, int D, bool SPH, bool DYN>
+__device__ __forceinline__ void obstacle_inside(const TRAJAM_CONST_AS T *o, const T (&p)[D], T tt,
+                                                T (&R)[D], T &r2, T &rmax)
+{
+    T dx[D], nn = T(0);
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        dx[ax] = p[ax] - o[kOC + ax];
+        if (DYN) dx[ax] = fma(o[kOW + ax], tt, dx[ax]);
+        const T u = SPH ? dx[ax] : dx[ax] * o[kOI + ax];
+        nn = fma(u, u, nn);
+    }
+    T r[D];
+    if (nn > T(0)) {
+        const T f = SPH ? (T(1) - o[kOR] * rsqrt_t(nn)) : (T(1) - rsqrt_t(nn));
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) r[ax] = dx[ax] * f;
+    } else {
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) r[ax] = T(0);
+        constexpr int push = (D == 2) ? 0 : 2;
+        r[push] = SPH ? -o[kOR] : -o[kOS + push];
+    }
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        R[ax] += r[ax];
+        r2 = fma(r[ax], r[ax], r2);
+        rmax = fmax(rmax, fabs(r[ax]));
+    }
+}
+
+// Obstacle polar step summed over all obstacles for one (sample, time) pair
+// (eqs collision_priest, zeta_2, compute_d_mij, d_max).  The residual r_j = p - e_j
+// is zero outside obstacle j (d = |u| >= 1), so the loop tests four obstacles at a
+// time and enters the residual path only if one of them contains a lane's point.
+template <typename T, int D, bool SPH, bool DYN>
+__device__ __forceinline__ void obstacle_loop(const TRAJAM_CONST_AS T *obs, int n_o, T tt,
+                                              const T (&p)[D], T (&R)[D], T &r2, T &rmax)
+{
+    constexpr int REC = kObstacleRecord;
+    int j = 0;
+    for (; j + 4 <= n_o; j += 4) {
+        const TRAJAM_CONST_AS T *o = obs + j * REC;
+        const T q0 = obstacle_q<T, D, SPH, DYN>(o, p, tt);
+        const T q1 = obstacle_q<T, D, SPH, DYN>(o + REC, p, tt);
+        const T q2 = obstacle_q<T, D, SPH, DYN>(o + 2 * REC, p, tt);
+        const T q3 = obstacle_q<T, D, SPH, DYN>(o + 3 * REC, p, tt);
+        if (fmin(fmin(q0, q1), fmin(q2, q3)) < T(0)) {
+            if (q0 < T(0)) obstacle_inside<T, D, SPH, DYN>(o, p, tt, R, r2, rmax);
+            if (q1 < T(0)) obstacle_inside<T, D, SPH, DYN>(o + REC, p, tt, R, r2, rmax);
+            if (q2 < T(0)) obstacle_inside<T, D, SPH, DYN>(o + 2 * REC, p, tt, R, r2, rmax);
+            if (q3 < T(0)) obstacle_inside<T, D, SPH, DYN>(o + 3 * REC, p, tt, R, r2, rmax);
+        }
+    }
+    for (; j < n_o; ++j) {
+        const TRAJAM_CONST_AS T *o = obs + j * REC;
+        if (obstacle_q<T, D, SPH, DYN>(o, p, tt) < T(0))
+            obstacle_inside<T, D, SPH, DYN>(o, p, tt, R, r2, rmax);
+    }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void obstacle_residuals(const T *obs_generic, int n_o, int sphere,
+                                                   int dynamic, T tt, const T (&p)[D], T (&R)[D],
+                                                   T &r2, T &rmax)
+{
+    const TRAJAM_CONST_AS T *obs = (const TRAJAM_CONST_AS T *)obs_generic;
+    if (sphere) {
+        if (dynamic) obstacle_loop<T, D, true, true>(obs, n_o, tt, p, R, r2, rmax);
+        else obstacle_loop<T, D, true, false>(obs, n_o, tt, p, R, r2, rmax);
+    } else {
+        if (dynamic) obstacle_loop<T, D, false, true>(obs, n_o, tt, p, R, r2, rmax);
+        else obstacle_loop<T, D, false, false>(obs, n_o, tt, p, R, r2, rmax);
+    }
+}
+
+// Velocity / acceleration polar step (eqs fv_priest, alpha_v, compute_dv): the
+// residual is v (1 - bound / |v|) outside the ball of radius `bound`, else 0.
+template <typename T, int D>
+__device__ __forceinline__ void bound_residual(const T (&v)[D], T bound, T (&r)[D], T &r2,
+                                               T &rmax)
+{
+    T vv = T(0);
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) vv = fma(v[ax], v[ax], vv);
+    if (vv > bound * bound) {
+        const T f = T(1) - bound * rsqrt_t(vv);
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            r[ax] = v[ax] * f;
+            r2 = fma(r[ax], r[ax], r2);
+            rmax = fmax(rmax, fabs(r[ax]));
+        }
+    } else {
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) r[ax] = T(0);
+    }
+}
+
+// Shared-memory carve-up of one AM workgroup (units of T).
+template <int D, int NVP>
+struct Lds {
+    static constexpr int S = D * NVP;           // coefficients of one sample
+    static constexpr int V = pow2ceil(D * NVP); // reduce-scatter width
+    __host__ __device__ static int xbuf(int) { return 0; }
+    __host__ __device__ static int gbuf(int tb) { return 2 * tb * S; }
+    __host__ __device__ static int part(int tb) { return 3 * tb * S; }
+    __host__ __device__ static int r2p(int tb, int wpt) { return part(tb) + tb * wpt * V; }
+    __host__ __device__ static int wmat(int tb, int wpt) { return r2p(tb, wpt) + tb * wpt; }
+    __host__ __device__ static int total(int tb, int wpt) { return wmat(tb, wpt) + NVP * NVP; }
+};
+
+// ----------------------------------------------------------------------------
+// The fused AM kernel: `a.iters` iterations for `a.tb` samples per workgroup.
+template <typename T, int D, int NVP>
+__global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
+{
+    using L = Lds<D, NVP>;
+    constexpr int S = L::S;
+    constexpr int V = L::V;
+    constexpr int LOGV = (V >= 64) ? 6 : (V >= 32) ? 5 : (V >= 16) ? 4 : 3;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *smem = reinterpret_cast<T *>(smem_raw);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wpt = a.tpad >> 6;               // waves per sample
+    const int ls = tid / a.tpad;               // local sample
+    const int lt = tid - ls * a.tpad;          // time sample (or output index)
+    const int wave_in_s = lt >> 6;
+    const int sample = blockIdx.x * a.tb + ls;
+    const bool live = sample < a.batch;
+    const bool valid = live && lt < a.n_p;
+    const int nf = a.nv - 4;
+
+    T *xbuf = smem + L::xbuf(a.tb);
+    T *gbuf = smem + L::gbuf(a.tb);
+    T *part = smem + L::part(a.tb);
+    T *r2p = smem + L::r2p(a.tb, wpt);
+    T *wmat = smem + L::wmat(a.tb, wpt);
+
+    // Fixed QP operator into LDS (rows of free coefficients; zero padded).
+    for (int i = tid; i < NVP * NVP; i += blockDim.x) {
+        const int f = i / NVP, m = i - f * NVP;
+        wmat[i] = (f < nf) ? a.W[f * NVP + m] : T(0);
+    }
+    // Basis rows of this lane's time sample stay in registers.
+    T phi0[NVP], phi1[NVP], phi2[NVP];
+#pragma unroll
+    for (int m = 0; m < NVP; ++m) {
+        phi0[m] = valid ? a.phi[(0 * a.n_p + lt) * NVP + m] : T(0);
+        phi1[m] = valid ? a.phi[(1 * a.n_p + lt) * NVP + m] : T(0);
+        phi2[m] = valid ? a.phi[(2 * a.n_p + lt) * NVP + m] : T(0);
+    }
+    const T tt = T(lt) * a.dt;
+
+    // Output lanes: lane lt < S owns coefficient (axis, m) of its sample.
+    const bool owner = live && lt < S;
+    const int o_ax = lt / NVP, o_m = lt - (lt / NVP) * NVP;
+    const bool o_real = owner && o_m < a.nv;
+    const bool o_free = o_real && o_m >= 3 && o_m < a.nv - 1;
+    const size_t gidx = (size_t)sample * D * a.nv + (size_t)o_ax * a.nv + o_m;
+    T xi_o = T(0), lam_o = T(0), xb_o = T(0);
+    if (o_real) {
+        xi_o = a.xi[gidx];
+        lam_o = a.lam[gidx];
+        xb_o = a.xb[gidx];
+    }
+    T bnd_o = T(0);
+    if (o_real && !o_free) {
+        const int bi = (o_m == a.nv - 1) ? 3 : o_m;
+        bnd_o = a.xiB[o_ax][bi];
+    }
+    if (lt < S && ls < a.tb) xbuf[ls * S + lt] = xb_o;  // buffer 0; padding entries are 0
+    __syncthreads();
+
+    T res_first = T(0), res_last = T(0);
+    bool nonfinite = false;
+    int cur = 0;
+    for (int k = 0; k < a.iters; ++k) {
+        const T *xs = xbuf + (cur * a.tb + ls) * S;
+        // ---- step (a): waypoints and polar steps (eqs parameter, comp_alpha..comp_d)
+        T p[D], v[D], acc[D];
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            T s0 = T(0), s1 = T(0), s2 = T(0);
+#pragma unroll
+            for (int m = 0; m < NVP; ++m) {
+                const T c = xs[ax * NVP + m];
+                s0 = fma(phi0[m], c, s0);
+                s1 = fma(phi1[m], c, s1);
+                s2 = fma(phi2[m], c, s2);
+            }
+            p[ax] = s0; v[ax] = s1; acc[ax] = s2;
+        }
+        T R[D], rv[D], ra[D], r2 = T(0), rmax = T(0);
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) { R[ax] = T(0); rv[ax] = T(0); ra[ax] = T(0); }
+        if (valid) {
+            obstacle_residuals<T, D>(a.obs, a.n_o, a.sphere, a.dynamic, tt, p, R, r2, rmax);
+            if (a.use_v) bound_residual<T, D>(v, a.vmax, rv, r2, rmax);
+            if (a.use_a) bound_residual<T, D>(acc, a.amax, ra, r2, rmax);
+        }
+        // ---- F^T r: each lane's rows times its residuals, reduced over the wave
+        bool nz = false;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) nz = nz || R[ax] != T(0) || rv[ax] != T(0) || ra[ax] != T(0);
+        T *mypart = part + (ls * wpt + wave_in_s) * V;
+        if (__any(nz)) {
+            T c[V];
+#pragma unroll
+            for (int i = 0; i < V; ++i) c[i] = T(0);
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+                for (int m = 0; m < NVP; ++m)
+                    c[ax * NVP + m] = fma(phi0[m], R[ax], fma(phi1[m], rv[ax], phi2[m] * ra[ax]));
+            const T s = reduce_scatter<T, V>(c, lane);
+            if ((lane & ((64 >> LOGV) - 1)) == 0) mypart[lane >> (6 - LOGV)] = s;
+        } else if (lane < V) {
+            mypart[lane] = T(0);
+        }
+        const T r2w = wave_sum(r2);
+        if (lane == 0) r2p[ls * wpt + wave_in_s] = r2w;
+        __syncthreads();
+
+        // ---- step (c): multiplier (eq lag) and the QP right-hand side defect
+        if (owner) {
+            T ftr = T(0);
+            for (int w = 0; w < wpt; ++w) ftr += part[(ls * wpt + w) * V + lt];
+            T gv = T(0);
+            if (o_real) {
+                lam_o = fma(-a.rho, ftr, lam_o);
+                gv = o_free ? (xi_o - xb_o + lam_o - a.rho * ftr) : (bnd_o - xb_o);
+            }
+            gbuf[ls * S + lt] = gv;
+            if (lt == 0) {
+                T rs = T(0);
+                for (int w = 0; w < wpt; ++w) rs += r2p[ls * wpt + w];
+                rs = sqrt(rs);
+                if (a.res) a.res[(size_t)k * a.batch + sample] = rs;
+                if (k == 0) res_first = rs;
+                res_last = rs;
+                nonfinite = nonfinite || !isfinite(rs);
+            }
+        }
+        __syncthreads();
+
+        // ---- step (b): xb_free += W [g_free ; boundary defect]  (eq affine_trans)
+        const int nxt = cur ^ 1;
+        if (owner) {
+            if (o_free) {
+                const T *wr = wmat + (o_m - 3) * NVP;
+                const T *g = gbuf + ls * S + o_ax * NVP;
+                T d = T(0);
+#pragma unroll
+                for (int m = 0; m < NVP; ++m) d = fma(wr[m], g[m], d);
+                xb_o += d;
+            } else if (o_real) {
+                xb_o = bnd_o;
+            }
+            xbuf[(nxt * a.tb + ls) * S + lt] = xb_o;
+        }
+        cur = nxt;
+        __syncthreads();
+    }
+
+    if (o_real) {
+        a.xb[gidx] = xb_o;
+        a.lam[gidx] = lam_o;
+        nonfinite = nonfinite || !isfinite(xb_o) || !isfinite(lam_o);
+    }
+    if (a.flags && a.iters > 0) {
+        // fold the per-lane non-finite bits of this sample into its first lane
+        const bool anyb = __any(nonfinite && owner);
+        if (owner && lt == 0) {
+            uint32_t fl = 0;
+            if (anyb) fl |= 1u;
+            if (res_last > res_first) fl |= 2u;
+            a.flags[sample] = fl;
+        }
+    }
+}
+
+// Residual only: steps (a) and the residual norms at the given coefficients.
+template <typename T, int D, int NVP>
+__global__ __launch_bounds__(kMaxThreads) void am_residual_kernel(AmArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *smem = reinterpret_cast<T *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wpt = a.tpad >> 6;
+    const int ls = tid / a.tpad;
+    const int lt = tid - ls * a.tpad;
+    const int sample = blockIdx.x * a.tb + ls;
+    const bool valid = sample < a.batch && lt < a.n_p;
+    T *r2p = smem;                  // [tb][wpt]
+    T *rmp = smem + a.tb * wpt;     // [tb][wpt]
+    T p[D], v[D], acc[D];
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) { p[ax] = T(0); v[ax] = T(0); acc[ax] = T(0); }
+    if (valid) {
+        const T *x = a.xb + (size_t)sample * D * a.nv;
+        for (int m = 0; m < a.nv; ++m) {
+            const T f0 = a.phi[(0 * a.n_p + lt) * NVP + m];
+            const T f1 = a.phi[(1 * a.n_p + lt) * NVP + m];
+            const T f2 = a.phi[(2 * a.n_p + lt) * NVP + m];
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) {
+                const T c = x[ax * a.nv + m];
+                p[ax] = fma(f0, c, p[ax]);
+                v[ax] = fma(f1, c, v[ax]);
+                acc[ax] = fma(f2, c, acc[ax]);
+            }
+        }
+    }
+    T R[D], rv[D], ra[D], r2 = T(0), rmax = T(0);
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) R[ax] = T(0);
+    if (valid) {
+        obstacle_residuals<T, D>(a.obs, a.n_o, a.sphere, a.dynamic, T(lt) * a.dt, p, R, r2, rmax);
+        if (a.use_v) bound_residual<T, D>(v, a.vmax, rv, r2, rmax);
+        if (a.use_a) bound_residual<T, D>(acc, a.amax, ra, r2, rmax);
+    }
+    const T s = wave_sum(r2);
+    const T mx = wave_max(rmax);
+    if (lane == 0) {
+        r2p[ls * wpt + (lt >> 6)] = s;
+        rmp[ls * wpt + (lt >> 6)] = mx;
+    }
+    __syncthreads();
+    if (lt == 0 && sample < a.batch) {
+        T rs = T(0), rm = T(0);
+        for (int w = 0; w < wpt; ++w) {
+            rs += r2p[ls * wpt + w];
+            rm = fmax(rm, rmp[ls * wpt + w]);
+        }
+        a.res[sample] = sqrt(rs);
+        if (a.res_max) a.res_max[sample] = rm;
+    }
+}
+
+// Packs the caller's obstacle arrays into one 16-slot record per obstacle:
+// centre[3], -velocity[3], 1/semi-axes[3], semi-axes[3], -radius^2, radius
+// (radius = first semi-axis, used by the sphere model), zero padded.
+template <typename T, int D>
+__global__ void pack_obstacles_kernel(int n_o, const T *__restrict__ c, const T *__restrict__ w,
+                                      const T *__restrict__ s, T *__restrict__ out)
+{
+    constexpr int REC = kObstacleRecord;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_o) return;
+    T *o = out + (size_t)j * REC;
+#pragma unroll
+    for (int i = 0; i < REC; ++i) o[i] = T(0);
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        o[kOC + ax] = c[j * D + ax];
+        o[kOW + ax] = w ? -w[j * D + ax] : T(0);
+        o[kOI + ax] = T(1) / s[j * D + ax];
+        o[kOS + ax] = s[j * D + ax];
+    }
+    o[kONR2] = -s[j * D] * s[j * D];
+    o[kOR] = s[j * D];
+}
+
+template <typename T, int D, int NVP>
+hipError_t launch_project_t(const AmArgs<T> &a, hipStream_t st)
+{
+    using L = Lds<D, NVP>;
+    const int wpt = a.tpad / 64;
+    const size_t lds = sizeof(T) * (size_t)L::total(a.tb, wpt);
+    const int threads = a.tb * a.tpad;
+    const int blocks = (a.batch + a.tb - 1) / a.tb;
+    hipLaunchKernelGGL((am_project_kernel<T, D, NVP>), dim3(blocks), dim3(threads), lds, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int D, int NVP>
+hipError_t launch_residual_t(const AmArgs<T> &a, hipStream_t st)
+{
+    const int wpt = a.tpad / 64;
+    const size_t lds = sizeof(T) * 2 * (size_t)a.tb * wpt;
+    const int threads = a.tb * a.tpad;
+    const int blocks = (a.batch + a.tb - 1) / a.tb;
+    hipLaunchKernelGGL((am_residual_kernel<T, D, NVP>), dim3(blocks), dim3(threads), lds, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, template <typename, int, int> class F>
+struct Dispatch;
+
+#define TRAJAM_DISPATCH(FN, T, dims, nvp, ...)                                          \
+    do {                                                                                \
+        if ((dims) == 2) {                                                              \
+            if ((nvp) == 8) return FN<T, 2, 8>(__VA_ARGS__);                            \
+            if ((nvp) == 12) return FN<T, 2, 12>(__VA_ARGS__);                          \
+            if ((nvp) == 16) return FN<T, 2, 16>(__VA_ARGS__);                          \
+        } else if ((dims) == 3) {                                                       \
+            if ((nvp) == 8) return FN<T, 3, 8>(__VA_ARGS__);                            \
+            if ((nvp) == 12) return FN<T, 3, 12>(__VA_ARGS__);                          \
+            if ((nvp) == 16) return FN<T, 3, 16>(__VA_ARGS__);                          \
+        }                                                                               \
+        return hipErrorInvalidValue;                                                    \
+    } while (0)
+
+}  // namespace
+
+size_t project_lds_bytes(int dims, int nvp, int tpad, int tb, size_t scalar)
+{
+    const int S = dims * nvp;
+    const int V = pow2ceil(S);
+    const int wpt = tpad / 64;
+    return scalar * (size_t)(3 * tb * S + tb * wpt * V + tb * wpt + nvp * nvp);
+}
+
+hipError_t launch_project_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st)
+{
+    TRAJAM_DISPATCH(launch_project_t, double, dims, nvp, a, st);
+}
+
+hipError_t launch_project_f32(int dims, int nvp, bool mfma_qp, const AmArgs<float> &a,
+                              hipStream_t st)
+{
+    if (mfma_qp) return hipErrorNotSupported;
+    TRAJAM_DISPATCH(launch_project_t, float, dims, nvp, a, st);
+}
+
+hipError_t launch_residual_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st)
+{
+    TRAJAM_DISPATCH(launch_residual_t, double, dims, nvp, a, st);
+}
+
+hipError_t launch_residual_f32(int dims, int nvp, const AmArgs<float> &a, hipStream_t st)
+{
+    TRAJAM_DISPATCH(launch_residual_t, float, dims, nvp, a, st);
+}
+
+template <typename T>
+static hipError_t pack_t(int dims, int n_o, const T *c, const T *w, const T *s, T *out,
+                         hipStream_t st)
+{
+    if (n_o <= 0) return hipSuccess;
+    const int threads = 64, blocks = (n_o + threads - 1) / threads;
+    if (dims == 2)
+        hipLaunchKernelGGL((pack_obstacles_kernel<T, 2>), dim3(blocks), dim3(threads), 0, st, n_o,
+                           c, w, s, out);
+    else
+        hipLaunchKernelGGL((pack_obstacles_kernel<T, 3>), dim3(blocks), dim3(threads), 0, st, n_o,
+                           c, w, s, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_obstacles_f64(int dims, int n_o, const double *c, const double *w,
+                                     const double *s, double *out, hipStream_t st)
+{
+    return pack_t<double>(dims, n_o, c, w, s, out, st);
+}
+
+hipError_t launch_pack_obstacles_f32(int dims, int n_o, const float *c, const float *w,
+                                     const float *s, float *out, hipStream_t st)
+{
+    return pack_t<float>(dims, n_o, c, w, s, out, st);
+}
+
+}  // namespace trajam

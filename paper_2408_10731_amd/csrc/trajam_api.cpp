@@ -1,0 +1,552 @@
+// C-ABI layer of the MI355X AM projection: argument validation, the one-time FP64
+// precompute of the fixed matrices, device constants, and kernel launches.
+//
+// Fixed matrices (thesis ch. 6, "Scalability": M needs a one-time computation):
+//  * Bernstein basis P, Pd, Pdd at t_k = k T / (n_p - 1) (eq parameter), evaluated
+//    here with the triangular recurrence B_{m,r} = (1 - tau) B_{m,r-1} + tau B_{m-1,r-1},
+//    which yields the degree n, n-1 and n-2 rows the derivatives need.
+//  * H = I + rho F^T F with F^T F = n_o P^T P + Pd^T Pd + Pdd^T Pdd (eq f_e stacks P
+//    once per obstacle), identical for every axis.
+//  * The four boundary rows [P_0; Pd_0; Pdd_0; P_{-1}] touch only coefficients
+//    0, 1, 2 and n of a Bernstein basis, so the KKT system of eq matrix_vec splits:
+//    those four coefficients are fixed by the boundary values in closed form and the
+//    n - 3 free ones solve H_ff x_f = q_f - H_fb x_b.  The library stores
+//    W_ff = H_ff^{-1} (Cholesky, FP64) and the operator
+//        W = [ W_ff | -W_ff H_fb ]   (n - 3) x (n + 1), columns in coefficient order,
+//    and applies it in delta form: with g = q - H xb^k (the KKT defect of the
+//    current iterate) and Delta_b = xb*_b - xb^k_b,
+//        xb^{k+1}_f = xb^k_f + W_ff (g_f - H_fb Delta_b),   xb^{k+1}_b = xb*_b.
+//    This equals the KKT solve exactly; in reduced precision the product only
+//    touches the defect, which tends to zero.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/trajam.h"
+#include "am_internal.h"
+
+using trajam::AmArgs;
+
+struct trajam_solver {
+    trajam_problem prob;
+    int nv, nf, nvp, tpad, tb;
+    int device;
+    // host FP64 copies
+    std::vector<double> P, Pd, Pdd, H, W, Wff;
+    // device constants (precision scalar)
+    void *d_phi = nullptr;   // [3][n_p][nvp]
+    void *d_W = nullptr;     // [nvp][nvp] (rows >= nf zero)
+    void *d_obs = nullptr;   // [n_o][REC]
+    void *d_bf16 = nullptr;  // BF16_REFINE: Whi, Wlo [16][16] uint16 each
+    void *d_Hff = nullptr;   // BF16_REFINE: [16][16] float
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_init_err;
+
+int pad_coeffs(int nv) { return nv <= 8 ? 8 : (nv <= 12 ? 12 : 16); }
+
+trajam_status fail(trajam_solver *s, trajam_status st, const std::string &msg)
+{
+    if (s) s->err = msg;
+    else g_init_err = msg;
+    return st;
+}
+
+trajam_status validate(const trajam_problem *p, std::string &why)
+{
+    if (!p) { why = "problem is NULL"; return TRAJAM_ERR_INVALID; }
+    if (p->dims != 2 && p->dims != 3) { why = "dims must be 2 or 3"; return TRAJAM_ERR_INVALID; }
+    if (p->degree < 3 || p->degree + 1 > trajam::kMaxCoeffs) {
+        why = "degree must be in [3, 15]";
+        return TRAJAM_ERR_INVALID;
+    }
+    if (p->n_steps < p->degree + 1 || p->n_steps > trajam::kMaxThreads) {
+        why = "n_steps must be in [degree + 1, 256]";
+        return TRAJAM_ERR_INVALID;
+    }
+    if (!(p->horizon > 0.0) || !std::isfinite(p->horizon)) {
+        why = "horizon must be finite and > 0";
+        return TRAJAM_ERR_INVALID;
+    }
+    if (!(p->rho > 0.0) || !std::isfinite(p->rho)) { why = "rho must be finite and > 0"; return TRAJAM_ERR_INVALID; }
+    if (!std::isfinite(p->v_max) || !std::isfinite(p->a_max)) {
+        why = "v_max and a_max must be finite";
+        return TRAJAM_ERR_INVALID;
+    }
+    if (p->n_obstacles < 0) { why = "n_obstacles must be >= 0"; return TRAJAM_ERR_INVALID; }
+    if (p->max_batch < 1) { why = "max_batch must be >= 1"; return TRAJAM_ERR_INVALID; }
+    if (p->precision != TRAJAM_FP64 && p->precision != TRAJAM_FP32 &&
+        p->precision != TRAJAM_BF16_REFINE) {
+        why = "unknown precision";
+        return TRAJAM_ERR_INVALID;
+    }
+    if (p->obstacle_model != TRAJAM_ELLIPSOID && p->obstacle_model != TRAJAM_SPHERE) {
+        why = "unknown obstacle model";
+        return TRAJAM_ERR_INVALID;
+    }
+    if (p->n_agents != 1) { why = "only n_agents == 1 is supported"; return TRAJAM_ERR_UNSUPPORTED; }
+    return TRAJAM_OK;
+}
+
+// Bernstein rows of degree n, n-1, n-2 at tau by the triangular recurrence.
+void bernstein_rows(int n, double tau, std::vector<double> &bn, std::vector<double> &bn1,
+                    std::vector<double> &bn2)
+{
+    std::vector<double> row(n + 1, 0.0), next(n + 1, 0.0);
+    row[0] = 1.0;  // degree 0
+    bn1.assign(n + 1, 0.0);
+    bn2.assign(n + 1, 0.0);
+    for (int r = 1; r <= n; ++r) {
+        for (int m = 0; m <= r; ++m) {
+            const double left = (m >= 1) ? row[m - 1] : 0.0;
+            const double same = (m <= r - 1) ? row[m] : 0.0;
+            next[m] = (1.0 - tau) * same + tau * left;
+        }
+        row.swap(next);
+        if (r == n - 2) bn2.assign(row.begin(), row.begin() + n + 1);
+        if (r == n - 1) bn1.assign(row.begin(), row.begin() + n + 1);
+    }
+    if (n == 1) bn2.assign(n + 1, 0.0);
+    bn = row;
+    bn.resize(n + 1);
+}
+
+// Basis and derivative matrices, row-major [n_p][n+1].
+void basis(int n, int np, double T, std::vector<double> &P, std::vector<double> &Pd,
+           std::vector<double> &Pdd)
+{
+    const int nv = n + 1;
+    P.assign((size_t)np * nv, 0.0);
+    Pd.assign((size_t)np * nv, 0.0);
+    Pdd.assign((size_t)np * nv, 0.0);
+    std::vector<double> bn, bn1, bn2;
+    for (int k = 0; k < np; ++k) {
+        const double tau = (double)k / (double)(np - 1);
+        bernstein_rows(n, tau, bn, bn1, bn2);
+        for (int m = 0; m < nv; ++m) {
+            auto b1 = [&](int i) { return (i >= 0 && i <= n - 1) ? bn1[i] : 0.0; };
+            auto b2 = [&](int i) { return (i >= 0 && i <= n - 2) ? bn2[i] : 0.0; };
+            P[(size_t)k * nv + m] = bn[m];
+            Pd[(size_t)k * nv + m] = n / T * (b1(m - 1) - b1(m));
+            Pdd[(size_t)k * nv + m] = (double)n * (n - 1) / (T * T) * (b2(m - 2) - 2.0 * b2(m - 1) + b2(m));
+        }
+    }
+}
+
+// Inverse of a symmetric positive-definite matrix via Cholesky (false if not SPD).
+bool spd_inverse(int n, const std::vector<double> &A, std::vector<double> &Ainv)
+{
+    std::vector<double> L((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double d = A[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(d > 0.0) || !std::isfinite(d)) return false;
+        L[(size_t)j * n + j] = std::sqrt(d);
+        for (int i = j + 1; i < n; ++i) {
+            double s = A[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) s -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = s / L[(size_t)j * n + j];
+        }
+    }
+    Ainv.assign((size_t)n * n, 0.0);
+    std::vector<double> col(n);
+    for (int c = 0; c < n; ++c) {
+        for (int i = 0; i < n; ++i) {  // L y = e_c
+            double s = (i == c) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) s -= L[(size_t)i * n + k] * col[k];
+            col[i] = s / L[(size_t)i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {  // L^T x = y
+            double s = col[i];
+            for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * col[k];
+            col[i] = s / L[(size_t)i * n + i];
+        }
+        for (int i = 0; i < n; ++i) Ainv[(size_t)i * n + c] = col[i];
+    }
+    return true;
+}
+
+bool is_boundary(int m, int n) { return m == 0 || m == 1 || m == 2 || m == n; }
+
+void boundary_coeffs(int n, double T, const double *b4, double *c4)
+{
+    const double x0 = b4[0], v0 = b4[1], a0 = b4[2], xf = b4[3];
+    c4[0] = x0;
+    c4[1] = x0 + v0 * T / n;
+    c4[2] = x0 + 2.0 * v0 * T / n + a0 * T * T / ((double)n * (n - 1));
+    c4[3] = xf;
+}
+
+// Host FP64 precompute of every fixed matrix of one problem class.
+trajam_status precompute(const trajam_problem &pr, std::vector<double> &P, std::vector<double> &Pd,
+                         std::vector<double> &Pdd, std::vector<double> &H,
+                         std::vector<double> &Wff, std::vector<double> &W, std::string &msg)
+{
+    const trajam_problem *p = &pr;
+    const int n = p->degree, nv = n + 1, np = p->n_steps, nf = nv - 4;
+    basis(n, np, p->horizon, P, Pd, Pdd);
+    H.assign((size_t)nv * nv, 0.0);
+    for (int i = 0; i < nv; ++i)
+        for (int j = 0; j < nv; ++j) {
+            double ff = 0.0;
+            for (int k = 0; k < np; ++k) {
+                const size_t ri = (size_t)k * nv;
+                ff += p->n_obstacles * P[ri + i] * P[ri + j];
+                if (p->v_max > 0.0) ff += Pd[ri + i] * Pd[ri + j];
+                if (p->a_max > 0.0) ff += Pdd[ri + i] * Pdd[ri + j];
+            }
+            H[(size_t)i * nv + j] = (i == j ? 1.0 : 0.0) + p->rho * ff;
+        }
+    std::vector<double> Hff((size_t)std::max(nf, 1) * std::max(nf, 1), 0.0);
+    for (int a = 0; a < nf; ++a)
+        for (int b = 0; b < nf; ++b) Hff[(size_t)a * nf + b] = H[(size_t)(3 + a) * nv + (3 + b)];
+    Wff.clear();
+    if (nf > 0 && !spd_inverse(nf, Hff, Wff)) {
+        msg = "free block of I + rho F^T F is not positive definite";
+        return TRAJAM_ERR_NUMERIC;
+    }
+    // W = [W_ff | -W_ff H_fb] in coefficient order, rows = free coefficients
+    W.assign((size_t)std::max(nf, 0) * nv, 0.0);
+    for (int a = 0; a < nf; ++a)
+        for (int m = 0; m < nv; ++m) {
+            double v = 0.0;
+            if (!is_boundary(m, n)) {
+                v = Wff[(size_t)a * nf + (m - 3)];
+            } else {
+                for (int b = 0; b < nf; ++b) v -= Wff[(size_t)a * nf + b] * H[(size_t)(3 + b) * nv + m];
+            }
+            W[(size_t)a * nv + m] = v;
+        }
+    for (double v : W)
+        if (!std::isfinite(v)) {
+            msg = "non-finite QP operator";
+            return TRAJAM_ERR_NUMERIC;
+        }
+    return TRAJAM_OK;
+}
+
+template <typename T>
+hipError_t upload(void **dst, const std::vector<double> &src)
+{
+    std::vector<T> tmp(src.size());
+    for (size_t i = 0; i < src.size(); ++i) tmp[i] = (T)src[i];
+    hipError_t e = hipMalloc(dst, sizeof(T) * (tmp.size() ? tmp.size() : 1));
+    if (e != hipSuccess) return e;
+    if (tmp.empty()) return hipSuccess;
+    return hipMemcpy(*dst, tmp.data(), sizeof(T) * tmp.size(), hipMemcpyHostToDevice);
+}
+
+uint16_t bf16_bits(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+float bf16_value(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *trajam_status_string(trajam_status st)
+{
+    switch (st) {
+    case TRAJAM_OK: return "ok";
+    case TRAJAM_ERR_INVALID: return "invalid argument";
+    case TRAJAM_ERR_UNSUPPORTED: return "unsupported";
+    case TRAJAM_ERR_NUMERIC: return "numerically singular fixed matrix";
+    case TRAJAM_ERR_DEVICE: return "HIP device error";
+    case TRAJAM_ERR_CAPACITY: return "batch exceeds max_batch";
+    }
+    return "unknown status";
+}
+
+const char *trajam_last_error(const trajam_solver *s) { return s ? s->err.c_str() : g_init_err.c_str(); }
+
+trajam_status trajam_boundary_coefficients(const trajam_problem *p, const double *b4, double *c4)
+{
+    std::string why;
+    trajam_status st = validate(p, why);
+    if (st != TRAJAM_OK && st != TRAJAM_ERR_UNSUPPORTED) return fail(nullptr, st, why);
+    if (!b4 || !c4) return fail(nullptr, TRAJAM_ERR_INVALID, "NULL pointer");
+    boundary_coeffs(p->degree, p->horizon, b4, c4);
+    return TRAJAM_OK;
+}
+
+void trajam_destroy(trajam_solver *s)
+{
+    if (!s) return;
+    if (s->d_phi) (void)hipFree(s->d_phi);
+    if (s->d_W) (void)hipFree(s->d_W);
+    if (s->d_obs) (void)hipFree(s->d_obs);
+    if (s->d_bf16) (void)hipFree(s->d_bf16);
+    if (s->d_Hff) (void)hipFree(s->d_Hff);
+    delete s;
+}
+
+trajam_status trajam_init(const trajam_problem *p, trajam_solver **out)
+{
+    if (!out) return fail(nullptr, TRAJAM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    trajam_status st = validate(p, why);
+    if (st != TRAJAM_OK) return fail(nullptr, st, why);
+
+    trajam_solver *s = new (std::nothrow) trajam_solver();
+    if (!s) return fail(nullptr, TRAJAM_ERR_DEVICE, "host allocation failed");
+    s->prob = *p;
+    const int n = p->degree, nv = n + 1, np = p->n_steps;
+    s->nv = nv;
+    s->nf = nv - 4;
+    s->nvp = pad_coeffs(nv);
+    s->tpad = ((np + 63) / 64) * 64;
+    s->tb = std::max(1, std::min(trajam::kMaxThreads / s->tpad, 1));
+
+    std::string msg;
+    st = precompute(*p, s->P, s->Pd, s->Pdd, s->H, s->Wff, s->W, msg);
+    if (st != TRAJAM_OK) {
+        trajam_destroy(s);
+        return fail(nullptr, st, msg);
+    }
+    const int nf = s->nf;
+    std::vector<double> Hff((size_t)std::max(nf, 1) * std::max(nf, 1), 0.0);
+    for (int a = 0; a < nf; ++a)
+        for (int b = 0; b < nf; ++b) Hff[(size_t)a * nf + b] = s->H[(size_t)(3 + a) * nv + (3 + b)];
+    // padded device layouts
+    const int nvp = s->nvp;
+    std::vector<double> phi((size_t)3 * np * nvp, 0.0), Wp((size_t)nvp * nvp, 0.0);
+    for (int k = 0; k < np; ++k)
+        for (int m = 0; m < nv; ++m) {
+            phi[((size_t)0 * np + k) * nvp + m] = s->P[(size_t)k * nv + m];
+            phi[((size_t)1 * np + k) * nvp + m] = s->Pd[(size_t)k * nv + m];
+            phi[((size_t)2 * np + k) * nvp + m] = s->Pdd[(size_t)k * nv + m];
+        }
+    for (int a = 0; a < nf; ++a)
+        for (int m = 0; m < nv; ++m) Wp[(size_t)a * nvp + m] = s->W[(size_t)a * nv + m];
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        trajam_destroy(s);
+        return fail(nullptr, TRAJAM_ERR_DEVICE, "hipGetDevice failed (no GPU?)");
+    }
+    const bool f64 = p->precision == TRAJAM_FP64;
+    const size_t rec = trajam::kObstacleRecord;
+    std::vector<double> zeros_obs((size_t)std::max(p->n_obstacles, 1) * rec, 0.0);
+    hipError_t e = f64 ? upload<double>(&s->d_phi, phi) : upload<float>(&s->d_phi, phi);
+    if (e == hipSuccess) e = f64 ? upload<double>(&s->d_W, Wp) : upload<float>(&s->d_W, Wp);
+    if (e == hipSuccess) e = f64 ? upload<double>(&s->d_obs, zeros_obs) : upload<float>(&s->d_obs, zeros_obs);
+    if (e == hipSuccess && p->precision == TRAJAM_BF16_REFINE) {
+        // hi/lo bf16 split of W_ff (rows free, cols coefficient order, 16 x 16)
+        std::vector<uint16_t> hl(2 * 256, 0);
+        for (int a = 0; a < nf; ++a)
+            for (int m = 0; m < nv; ++m) {
+                const float w = (float)s->W[(size_t)a * nv + m];
+                const uint16_t hi = bf16_bits(w);
+                const uint16_t lo = bf16_bits(w - bf16_value(hi));
+                hl[a * 16 + m] = hi;
+                hl[256 + a * 16 + m] = lo;
+            }
+        e = hipMalloc(&s->d_bf16, hl.size() * sizeof(uint16_t));
+        if (e == hipSuccess)
+            e = hipMemcpy(s->d_bf16, hl.data(), hl.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+        std::vector<double> H16(256, 0.0);
+        for (int a = 0; a < nf; ++a)
+            for (int b = 0; b < nf; ++b) H16[a * 16 + b] = Hff[(size_t)a * nf + b];
+        if (e == hipSuccess) e = upload<float>(&s->d_Hff, H16);
+    }
+    if (e != hipSuccess) {
+        std::string m = std::string("device allocation/copy failed: ") + hipGetErrorString(e);
+        trajam_destroy(s);
+        return fail(nullptr, TRAJAM_ERR_DEVICE, m);
+    }
+    *out = s;
+    return TRAJAM_OK;
+}
+
+trajam_status trajam_fixed_matrices(const trajam_problem *p, double *P, double *Pd, double *Pdd,
+                                    double *H, double *W)
+{
+    std::string why;
+    trajam_status st = validate(p, why);
+    if (st != TRAJAM_OK) return fail(nullptr, st, why);
+    std::vector<double> vP, vPd, vPdd, vH, vWff, vW;
+    st = precompute(*p, vP, vPd, vPdd, vH, vWff, vW, why);
+    if (st != TRAJAM_OK) return fail(nullptr, st, why);
+    if (P) std::memcpy(P, vP.data(), sizeof(double) * vP.size());
+    if (Pd) std::memcpy(Pd, vPd.data(), sizeof(double) * vPd.size());
+    if (Pdd) std::memcpy(Pdd, vPdd.data(), sizeof(double) * vPdd.size());
+    if (H) std::memcpy(H, vH.data(), sizeof(double) * vH.size());
+    if (W && !vW.empty()) std::memcpy(W, vW.data(), sizeof(double) * vW.size());
+    return TRAJAM_OK;
+}
+
+trajam_status trajam_set_samples_per_workgroup(trajam_solver *s, int32_t tb)
+{
+    if (!s) return TRAJAM_ERR_INVALID;
+    if (tb < 1 || tb * s->tpad > trajam::kMaxThreads)
+        return fail(s, TRAJAM_ERR_INVALID, "samples per workgroup must be >= 1 and fit 256 threads");
+    s->tb = tb;
+    return TRAJAM_OK;
+}
+
+int32_t trajam_samples_per_workgroup(const trajam_solver *s) { return s ? s->tb : -1; }
+
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+void fill_args(const trajam_solver *s, AmArgs<T> &a, int batch, int iters)
+{
+    const trajam_problem &p = s->prob;
+    std::memset(&a, 0, sizeof(a));
+    a.batch = batch;
+    a.n_p = p.n_steps;
+    a.nv = s->nv;
+    a.n_o = p.n_obstacles;
+    a.iters = iters;
+    a.tpad = s->tpad;
+    a.tb = s->tb;
+    a.use_v = p.v_max > 0.0;
+    a.use_a = p.a_max > 0.0;
+    a.sphere = p.obstacle_model == TRAJAM_SPHERE;
+    a.rho = (T)p.rho;
+    a.vmax = (T)p.v_max;
+    a.amax = (T)p.a_max;
+    a.dt = (T)(p.horizon / (p.n_steps - 1));
+    a.phi = (const T *)s->d_phi;
+    a.W = (const T *)s->d_W;
+    a.obs = (const T *)s->d_obs;
+    if (s->d_bf16) {
+        a.Whi = (const uint16_t *)s->d_bf16;
+        a.Wlo = (const uint16_t *)s->d_bf16 + 256;
+    }
+    a.Hff = (const T *)s->d_Hff;
+}
+
+trajam_status pack(trajam_solver *s, const void *c, const void *w, const void *ax, hipStream_t st)
+{
+    const trajam_problem &p = s->prob;
+    if (p.n_obstacles == 0) return TRAJAM_OK;
+    if (!c || !ax) return fail(s, TRAJAM_ERR_INVALID, "obstacle centre/axes pointer is NULL");
+    hipError_t e = (p.precision == TRAJAM_FP64)
+                       ? trajam::launch_pack_obstacles_f64(p.dims, p.n_obstacles, (const double *)c,
+                                                           (const double *)w, (const double *)ax,
+                                                           (double *)s->d_obs, st)
+                       : trajam::launch_pack_obstacles_f32(p.dims, p.n_obstacles, (const float *)c,
+                                                           (const float *)w, (const float *)ax,
+                                                           (float *)s->d_obs, st);
+    if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("obstacle pack launch: ") + hipGetErrorString(e));
+    return TRAJAM_OK;
+}
+
+}  // namespace
+
+extern "C" trajam_status trajam_project(trajam_solver *s, int32_t batch, const void *xi,
+                                        const double *boundary_host, const void *obs_centre,
+                                        const void *obs_vel, const void *obs_axes, void *xi_bar,
+                                        void *lambda, int32_t iters, void *res_trace,
+                                        uint32_t *flags, void *stream)
+{
+    if (!s) return TRAJAM_ERR_INVALID;
+    s->err.clear();
+    if (batch < 0 || iters < 0) return fail(s, TRAJAM_ERR_INVALID, "batch and iters must be >= 0");
+    if (batch > s->prob.max_batch) return fail(s, TRAJAM_ERR_CAPACITY, "batch > max_batch");
+    if (batch == 0 || iters == 0) return TRAJAM_OK;
+    if (!xi || !xi_bar || !lambda || !boundary_host)
+        return fail(s, TRAJAM_ERR_INVALID, "xi, xi_bar, lambda and boundary must not be NULL");
+    for (int i = 0; i < s->prob.dims * 4; ++i)
+        if (!std::isfinite(boundary_host[i])) return fail(s, TRAJAM_ERR_INVALID, "non-finite boundary value");
+    hipStream_t st = (hipStream_t)stream;
+    trajam_status ps = pack(s, obs_centre, obs_vel, obs_axes, st);
+    if (ps != TRAJAM_OK) return ps;
+    const trajam_problem &p = s->prob;
+    const int dynamic = obs_vel != nullptr;
+    hipError_t e;
+    if (p.precision == TRAJAM_FP64) {
+        AmArgs<double> a;
+        fill_args(s, a, batch, iters);
+        a.dynamic = dynamic;
+        for (int ax = 0; ax < p.dims; ++ax) {
+            double c4[4];
+            boundary_coeffs(p.degree, p.horizon, boundary_host + 4 * ax, c4);
+            for (int i = 0; i < 4; ++i) a.xiB[ax][i] = c4[i];
+        }
+        a.xi = (const double *)xi;
+        a.xb = (double *)xi_bar;
+        a.lam = (double *)lambda;
+        a.res = (double *)res_trace;
+        a.flags = flags;
+        e = trajam::launch_project_f64(p.dims, s->nvp, a, st);
+    } else {
+        AmArgs<float> a;
+        fill_args(s, a, batch, iters);
+        a.dynamic = dynamic;
+        for (int ax = 0; ax < p.dims; ++ax) {
+            double c4[4];
+            boundary_coeffs(p.degree, p.horizon, boundary_host + 4 * ax, c4);
+            for (int i = 0; i < 4; ++i) a.xiB[ax][i] = (float)c4[i];
+        }
+        a.xi = (const float *)xi;
+        a.xb = (float *)xi_bar;
+        a.lam = (float *)lambda;
+        a.res = (float *)res_trace;
+        a.flags = flags;
+        e = trajam::launch_project_f32(p.dims, s->nvp, p.precision == TRAJAM_BF16_REFINE, a, st);
+    }
+    if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("AM launch: ") + hipGetErrorString(e));
+    return TRAJAM_OK;
+}
+
+extern "C" trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const void *xi_bar,
+                                          const void *obs_centre, const void *obs_vel,
+                                          const void *obs_axes, void *res_l2, void *res_max,
+                                          void *stream)
+{
+    if (!s) return TRAJAM_ERR_INVALID;
+    s->err.clear();
+    if (batch < 0) return fail(s, TRAJAM_ERR_INVALID, "batch must be >= 0");
+    if (batch > s->prob.max_batch) return fail(s, TRAJAM_ERR_CAPACITY, "batch > max_batch");
+    if (batch == 0) return TRAJAM_OK;
+    if (!xi_bar || !res_l2) return fail(s, TRAJAM_ERR_INVALID, "xi_bar and res_l2 must not be NULL");
+    hipStream_t st = (hipStream_t)stream;
+    trajam_status ps = pack(s, obs_centre, obs_vel, obs_axes, st);
+    if (ps != TRAJAM_OK) return ps;
+    const trajam_problem &p = s->prob;
+    hipError_t e;
+    if (p.precision == TRAJAM_FP64) {
+        AmArgs<double> a;
+        fill_args(s, a, batch, 0);
+        a.dynamic = obs_vel != nullptr;
+        a.xb = (double *)xi_bar;
+        a.res = (double *)res_l2;
+        a.res_max = (double *)res_max;
+        e = trajam::launch_residual_f64(p.dims, s->nvp, a, st);
+    } else {
+        AmArgs<float> a;
+        fill_args(s, a, batch, 0);
+        a.dynamic = obs_vel != nullptr;
+        a.xb = (float *)xi_bar;
+        a.res = (float *)res_l2;
+        a.res_max = (float *)res_max;
+        e = trajam::launch_residual_f32(p.dims, s->nvp, a, st);
+    }
+    if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("residual launch: ") + hipGetErrorString(e));
+    return TRAJAM_OK;
+}

@@ -1,0 +1,280 @@
+"""Thin Python binding of libtrajam.so (the gfx950 AM projection).
+
+Argument marshalling only: every step of the projection runs in the HIP kernels of
+the library.  The functions keep the C names; `Solver` adds shape / dtype / device
+checks around them for PyTorch tensors.  If the library is not built, or no GPU is
+present, calls fail with an exception -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtrajam.so")
+
+TRAJAM_OK = 0
+TRAJAM_ERR_INVALID = -1
+TRAJAM_ERR_UNSUPPORTED = -2
+TRAJAM_ERR_NUMERIC = -3
+TRAJAM_ERR_DEVICE = -4
+TRAJAM_ERR_CAPACITY = -5
+
+TRAJAM_FP64 = 0
+TRAJAM_FP32 = 1
+TRAJAM_BF16_REFINE = 2
+PRECISIONS = {"fp64": TRAJAM_FP64, "fp32": TRAJAM_FP32, "bf16": TRAJAM_BF16_REFINE}
+
+TRAJAM_ELLIPSOID = 0
+TRAJAM_SPHERE = 1
+
+FLAG_NONFINITE = 1
+FLAG_GREW = 2
+
+# every symbol include/trajam.h declares
+EXPORTS = [
+    "trajam_init", "trajam_destroy", "trajam_project", "trajam_residuals",
+    "trajam_fixed_matrices", "trajam_set_samples_per_workgroup",
+    "trajam_samples_per_workgroup", "trajam_boundary_coefficients",
+    "trajam_status_string", "trajam_last_error",
+]
+
+
+class TrajamError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"trajam status {status}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("dims", ctypes.c_int32),
+        ("degree", ctypes.c_int32),
+        ("n_steps", ctypes.c_int32),
+        ("horizon", ctypes.c_double),
+        ("v_max", ctypes.c_double),
+        ("a_max", ctypes.c_double),
+        ("rho", ctypes.c_double),
+        ("n_obstacles", ctypes.c_int32),
+        ("n_agents", ctypes.c_int32),
+        ("agent_radius", ctypes.c_double),
+        ("max_batch", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("obstacle_model", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load libtrajam.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:
+        import torch  # noqa: F401  -- HIP runtime of the process comes from torch
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.trajam_init.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(vp)]
+    L.trajam_init.restype = ctypes.c_int
+    L.trajam_destroy.argtypes = [vp]
+    L.trajam_destroy.restype = None
+    L.trajam_project.argtypes = [vp, ctypes.c_int32, vp, dp, vp, vp, vp, vp, vp,
+                                 ctypes.c_int32, vp, vp, vp]
+    L.trajam_project.restype = ctypes.c_int
+    L.trajam_residuals.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
+    L.trajam_residuals.restype = ctypes.c_int
+    L.trajam_fixed_matrices.argtypes = [ctypes.POINTER(Problem), dp, dp, dp, dp, dp]
+    L.trajam_fixed_matrices.restype = ctypes.c_int
+    L.trajam_set_samples_per_workgroup.argtypes = [vp, ctypes.c_int32]
+    L.trajam_set_samples_per_workgroup.restype = ctypes.c_int
+    L.trajam_samples_per_workgroup.argtypes = [vp]
+    L.trajam_samples_per_workgroup.restype = ctypes.c_int32
+    L.trajam_boundary_coefficients.argtypes = [ctypes.POINTER(Problem), dp, dp]
+    L.trajam_boundary_coefficients.restype = ctypes.c_int
+    L.trajam_status_string.argtypes = [ctypes.c_int]
+    L.trajam_status_string.restype = ctypes.c_char_p
+    L.trajam_last_error.argtypes = [vp]
+    L.trajam_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(st: int, handle=None):
+    if st != TRAJAM_OK:
+        L = load()
+        msg = L.trajam_last_error(handle).decode()
+        raise TrajamError(st, f"{L.trajam_status_string(st).decode()}: {msg}")
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ------------------------------------------------------------------ C names --
+
+
+def trajam_init(problem: Problem) -> int:
+    h = ctypes.c_void_p()
+    _check(load().trajam_init(ctypes.byref(problem), ctypes.byref(h)))
+    return h.value
+
+
+def trajam_destroy(handle: int) -> None:
+    load().trajam_destroy(handle)
+
+
+def trajam_project(handle, batch, xi, boundary_host, obs_centre, obs_vel, obs_axes,
+                   xi_bar, lam, iters, res_trace, flags, stream) -> None:
+    """All array arguments are raw device pointers (ints) except boundary_host,
+    a float64 numpy array [dims, 4]."""
+    b = np.ascontiguousarray(boundary_host, dtype=np.float64)
+    _check(load().trajam_project(handle, int(batch), xi, _dp(b), obs_centre, obs_vel,
+                                 obs_axes, xi_bar, lam, int(iters), res_trace, flags, stream),
+           handle)
+
+
+def trajam_residuals(handle, batch, xi_bar, obs_centre, obs_vel, obs_axes, res_l2, res_max,
+                     stream) -> None:
+    _check(load().trajam_residuals(handle, int(batch), xi_bar, obs_centre, obs_vel, obs_axes,
+                                   res_l2, res_max, stream), handle)
+
+
+def trajam_fixed_matrices(problem: Problem):
+    """(P, Pd, Pdd, H, W) in float64, computed on the host (no GPU needed)."""
+    nv = problem.degree + 1
+    P = np.zeros((problem.n_steps, nv)); Pd = np.zeros_like(P); Pdd = np.zeros_like(P)
+    H = np.zeros((nv, nv)); W = np.zeros((max(nv - 4, 0), nv))
+    _check(load().trajam_fixed_matrices(ctypes.byref(problem), _dp(P), _dp(Pd), _dp(Pdd),
+                                        _dp(H), _dp(W) if W.size else None))
+    return P, Pd, Pdd, H, W
+
+
+def trajam_set_samples_per_workgroup(handle, tb: int) -> None:
+    _check(load().trajam_set_samples_per_workgroup(handle, int(tb)), handle)
+
+
+def trajam_samples_per_workgroup(handle) -> int:
+    return int(load().trajam_samples_per_workgroup(handle))
+
+
+def trajam_boundary_coefficients(problem: Problem, b4) -> np.ndarray:
+    b = np.ascontiguousarray(b4, dtype=np.float64)
+    out = np.zeros(4)
+    _check(load().trajam_boundary_coefficients(ctypes.byref(problem), _dp(b), _dp(out)))
+    return out
+
+
+# ----------------------------------------------------------- torch wrapper --
+
+
+def make_problem(dims, degree, n_steps, horizon, v_max, a_max, rho, n_obstacles,
+                 max_batch, precision="fp64", sphere=True, n_agents=1,
+                 agent_radius=0.0) -> Problem:
+    return Problem(int(dims), int(degree), int(n_steps), float(horizon), float(v_max),
+                   float(a_max), float(rho), int(n_obstacles), int(n_agents),
+                   float(agent_radius), int(max_batch), PRECISIONS.get(precision, precision),
+                   TRAJAM_SPHERE if sphere else TRAJAM_ELLIPSOID)
+
+
+class Solver:
+    """Owns one trajam_solver handle; methods take torch tensors on the GPU."""
+
+    def __init__(self, problem: Problem):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("trajam needs a ROCm GPU; torch.cuda.is_available() is False")
+        self.problem = problem
+        self.dims = problem.dims
+        self.nv = problem.degree + 1
+        self.dtype = torch.float64 if problem.precision == TRAJAM_FP64 else torch.float32
+        self.handle = trajam_init(problem)
+
+    @classmethod
+    def for_workload(cls, w, max_batch=None, precision=None, sphere=None):
+        prec = precision or w.precision
+        if sphere is None:
+            sphere = bool(np.all(w.obs_axes == w.obs_axes[:, :1]))
+        return cls(make_problem(w.dims, w.degree, w.n_steps, w.horizon, w.v_max, w.a_max,
+                                w.rho, w.n_obs, max_batch or w.batch, prec, sphere))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            trajam_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _t(self, x, shape, name):
+        import torch
+        if x.dtype != self.dtype or not x.is_cuda or not x.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous {self.dtype} CUDA tensor")
+        if tuple(x.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(x.shape)}, expected {tuple(shape)}")
+        return x.data_ptr()
+
+    def obstacles(self, centre, vel, axes):
+        n = self.problem.n_obstacles
+        if n == 0:
+            return None, None, None
+        c = self._t(centre, (n, self.dims), "obs_centre")
+        v = None if vel is None else self._t(vel, (n, self.dims), "obs_vel")
+        a = self._t(axes, (n, self.dims), "obs_axes")
+        return c, v, a
+
+    def project(self, xi, boundary, obs, xi_bar, lam, iters, res_trace=None, flags=None,
+                stream=None):
+        import torch
+        B = xi.shape[0]
+        shape = (B, self.dims, self.nv)
+        c, v, a = self.obstacles(*obs)
+        rt = None if res_trace is None else self._t(res_trace, (iters, B), "res_trace")
+        fl = None
+        if flags is not None:
+            if flags.dtype != torch.int32 or not flags.is_cuda or flags.numel() != B:
+                raise TypeError("flags must be an int32 CUDA tensor of length batch")
+            fl = flags.data_ptr()
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        trajam_project(self.handle, B, self._t(xi, shape, "xi"), boundary, c, v, a,
+                       self._t(xi_bar, shape, "xi_bar"), self._t(lam, shape, "lambda"),
+                       iters, rt, fl, st)
+
+    def residuals(self, xi_bar, obs, res_l2, res_max=None, stream=None):
+        import torch
+        B = xi_bar.shape[0]
+        c, v, a = self.obstacles(*obs)
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        trajam_residuals(self.handle, B, self._t(xi_bar, (B, self.dims, self.nv), "xi_bar"),
+                         c, v, a, self._t(res_l2, (B,), "res_l2"),
+                         None if res_max is None else self._t(res_max, (B,), "res_max"), st)
+
+    def set_samples_per_workgroup(self, tb: int):
+        trajam_set_samples_per_workgroup(self.handle, tb)
+
+    def samples_per_workgroup(self) -> int:
+        return trajam_samples_per_workgroup(self.handle)
+
+
+def device_workload(w, dtype, device="cuda", static=None):
+    """Upload a workload's arrays; returns (xi, obs=(centre, vel|None, axes))."""
+    import torch
+    xi = torch.as_tensor(w.xi, dtype=dtype, device=device).contiguous()
+    c = torch.as_tensor(w.obs_centre, dtype=dtype, device=device).contiguous()
+    a = torch.as_tensor(w.obs_axes, dtype=dtype, device=device).contiguous()
+    if static is None:
+        static = not np.any(w.obs_vel)
+    v = None if static else torch.as_tensor(w.obs_vel, dtype=dtype, device=device).contiguous()
+    return xi, (c, v, a)

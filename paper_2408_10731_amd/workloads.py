@@ -63,6 +63,13 @@ class Workload:
     def batch(self) -> int:
         return int(self.xi.shape[0])
 
+    def rounded(self, dtype=np.float32) -> "Workload":
+        """Same problem with every array rounded to `dtype` (kept as float64), i.e.
+        exactly the values a reduced-precision device path receives."""
+        r = lambda a: np.asarray(a, dtype=dtype).astype(np.float64)
+        return dataclasses.replace(self, obs_centre=r(self.obs_centre), obs_vel=r(self.obs_vel),
+                                   obs_axes=r(self.obs_axes), xi=r(self.xi))
+
     def subset(self, batch: int) -> "Workload":
         """Same problem, the first `batch` samples."""
         return dataclasses.replace(self, xi=np.ascontiguousarray(self.xi[:batch]))
