@@ -39,9 +39,9 @@ struct AmArgs {
     T *res_max;             // residual-only launches: [batch] or null
     // BF16_REFINE: the QP operator split into bf16 hi and lo parts, and H_ff for the
     // refinement pass (only read when the launch uses the matrix-core QP step).
-    const uint16_t *Whi;    // [16][16] bf16 bits, rows = free index, cols = coefficient
-    const uint16_t *Wlo;    // [16][16]
-    const T *Hff;           // [16][16] free-free block of H (zero padded)
+    const uint16_t *Whi;    // [16][16] bf16 bits of W_ff = H_ff^-1 (zero padded)
+    const uint16_t *Wlo;    // [16][16] bf16 bits of W_ff - Whi
+    const float *Hmq;       // H_ff [16][16] then H_fb [16][4] (coefficients 0, 1, 2, n), fp32
 };
 
 // Packed obstacle record length (scalars), any dims.

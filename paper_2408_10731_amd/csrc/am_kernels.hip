@@ -302,6 +302,43 @@ __device__ __forceinline__ void bound_residual(const T (&v)[D], T bound, T (&r)[
     }
 }
 
+// ---- bf16 matrix-core QP step (TRAJAM_BF16_REFINE) ----------------------------
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_rn(float x)
+{
+    unsigned u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_f(short h) { return __uint_as_float(((unsigned)(unsigned short)h) << 16); }
+
+// delta = W_ff v for one 16 x 16 tile on the matrix cores with both operands split
+// into bf16 hi + lo parts: W v ~ Whi vhi + Whi vlo + Wlo vhi (the dropped Wlo vlo term
+// is 2^-16 relative), accumulated in fp32.  Operand layout of
+// v_mfma_f32_16x16x16_bf16: lane l holds A[l % 16][4 (l / 16) + i], B[4 (l / 16) + i][l % 16]
+// and returns D[4 (l / 16) + i][l % 16], i = 0..3.
+__device__ __forceinline__ f32x4 qp_mfma(bf16x4 ahi, bf16x4 alo, const float (&v)[4])
+{
+    bf16x4 bhi, blo;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const short h = bf16_rn(v[i]);
+        bhi[i] = h;
+        blo[i] = bf16_rn(v[i] - bf16_f(h));
+    }
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc, 0, 0, 0);
+    return acc;
+}
+
+// LDS of the matrix-core QP step (floats): y and delta tiles [16 columns][16 rows],
+// H_ff [16][16] and H_fb [16][4] (boundary coefficients 0, 1, 2, n).
+constexpr int kMqFloats = 256 + 256 + 256 + 64;
+
 // Shared-memory carve-up of one AM workgroup (units of T).
 template <int D, int NVP>
 struct Lds {
@@ -317,7 +354,7 @@ struct Lds {
 
 // ----------------------------------------------------------------------------
 // The fused AM kernel: `a.iters` iterations for `a.tb` samples per workgroup.
-template <typename T, int D, int NVP>
+template <typename T, int D, int NVP, bool MQP>
 __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
 {
     using L = Lds<D, NVP>;
@@ -348,6 +385,18 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
     for (int i = tid; i < NVP * NVP; i += blockDim.x) {
         const int f = i / NVP, m = i - f * NVP;
         wmat[i] = (f < nf) ? a.W[f * NVP + m] : T(0);
+    }
+    // Matrix-core QP: W_ff hi/lo A operands in registers, H_ff and H_fb in LDS.
+    float *mq = reinterpret_cast<float *>(smem + L::total(a.tb, wpt));
+    bf16x4 ahi = {0, 0, 0, 0}, alo = {0, 0, 0, 0};
+    if constexpr (MQP) {
+        const int m = lane & 15, k0 = 4 * (lane >> 4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ahi[i] = (short)a.Whi[m * 16 + k0 + i];
+            alo[i] = (short)a.Wlo[m * 16 + k0 + i];
+        }
+        for (int i = tid; i < 256 + 64; i += blockDim.x) mq[512 + i] = a.Hmq[i];
     }
     // Basis rows of this lane's time sample stay in registers.
     T phi0[NVP], phi1[NVP], phi2[NVP];
@@ -453,18 +502,69 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
 
         // ---- step (b): xb_free += W [g_free ; boundary defect]  (eq affine_trans)
         const int nxt = cur ^ 1;
-        if (owner) {
-            if (o_free) {
-                const T *wr = wmat + (o_m - 3) * NVP;
-                const T *g = gbuf + ls * S + o_ax * NVP;
-                T d = T(0);
-#pragma unroll
-                for (int m = 0; m < NVP; ++m) d = fma(wr[m], g[m], d);
-                xb_o += d;
-            } else if (o_real) {
-                xb_o = bnd_o;
+        if constexpr (MQP) {
+            // y = g_f - H_fb Delta_b per (sample, axis) column; delta = W_ff y on the
+            // matrix cores, then one refinement pass delta += W_ff (y - H_ff delta).
+            float *yb = mq, *db = mq + 256;
+            const float *hff = mq + 512, *hfb = mq + 768;
+            const int cols = a.tb * D;
+            for (int i = tid; i < 256; i += blockDim.x) {
+                const int col = i >> 4, f = i & 15;
+                float y = 0.f;
+                if (col < cols && f < nf) {
+                    const int sl = col / D, ax = col - sl * D;
+                    const T *z = gbuf + sl * S + ax * NVP;
+                    y = (float)z[3 + f] - (hfb[f * 4 + 0] * (float)z[0] + hfb[f * 4 + 1] * (float)z[1] +
+                                           hfb[f * 4 + 2] * (float)z[2] + hfb[f * 4 + 3] * (float)z[a.nv - 1]);
+                }
+                yb[i] = y;
             }
-            xbuf[(nxt * a.tb + ls) * S + lt] = xb_o;
+            __syncthreads();
+            const int cn = lane & 15, k0 = 4 * (lane >> 4);
+            if (tid < 64) {
+                float yv[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) yv[i] = yb[cn * 16 + k0 + i];
+                const f32x4 d0 = qp_mfma(ahi, alo, yv);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) db[cn * 16 + k0 + i] = d0[i];
+            }
+            __syncthreads();
+            if (tid < 64) {
+                float rv[4], dv[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) dv[k] = db[cn * 16 + k];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float r = yb[cn * 16 + k0 + i];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) r = fmaf(-hff[(k0 + i) * 16 + k], dv[k], r);
+                    rv[i] = r;
+                }
+                const f32x4 d1 = qp_mfma(ahi, alo, rv);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) db[cn * 16 + k0 + i] = dv[k0 + i] + d1[i];
+            }
+            __syncthreads();
+            if (owner) {
+                if (o_free) xb_o += (T)db[(ls * D + o_ax) * 16 + (o_m - 3)];
+                else if (o_real) xb_o = bnd_o;
+                xbuf[(nxt * a.tb + ls) * S + lt] = xb_o;
+            }
+        } else {
+            if (owner) {
+                if (o_free) {
+                    const T *wr = wmat + (o_m - 3) * NVP;
+                    const T *g = gbuf + ls * S + o_ax * NVP;
+                    T d = T(0);
+#pragma unroll
+                    for (int m = 0; m < NVP; ++m) d = fma(wr[m], g[m], d);
+                    xb_o += d;
+                } else if (o_real) {
+                    xb_o = bnd_o;
+                }
+                xbuf[(nxt * a.tb + ls) * S + lt] = xb_o;
+            }
         }
         cur = nxt;
         __syncthreads();
@@ -570,17 +670,22 @@ __global__ void pack_obstacles_kernel(int n_o, const T *__restrict__ c, const T 
     o[kOR] = s[j * D];
 }
 
-template <typename T, int D, int NVP>
+template <typename T, int D, int NVP, bool MQP>
 hipError_t launch_project_t(const AmArgs<T> &a, hipStream_t st)
 {
     using L = Lds<D, NVP>;
     const int wpt = a.tpad / 64;
-    const size_t lds = sizeof(T) * (size_t)L::total(a.tb, wpt);
+    const size_t lds = sizeof(T) * (size_t)L::total(a.tb, wpt) + (MQP ? sizeof(float) * kMqFloats : 0);
     const int threads = a.tb * a.tpad;
     const int blocks = (a.batch + a.tb - 1) / a.tb;
-    hipLaunchKernelGGL((am_project_kernel<T, D, NVP>), dim3(blocks), dim3(threads), lds, st, a);
+    if (MQP && (a.tb * D > 16 || a.nv - 4 > 16)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((am_project_kernel<T, D, NVP, MQP>), dim3(blocks), dim3(threads), lds, st, a);
     return hipGetLastError();
 }
+template <typename T, int D, int NVP>
+hipError_t launch_project_plain(const AmArgs<T> &a, hipStream_t st) { return launch_project_t<T, D, NVP, false>(a, st); }
+template <typename T, int D, int NVP>
+hipError_t launch_project_mqp(const AmArgs<T> &a, hipStream_t st) { return launch_project_t<T, D, NVP, true>(a, st); }
 
 template <typename T, int D, int NVP>
 hipError_t launch_residual_t(const AmArgs<T> &a, hipStream_t st)
@@ -622,14 +727,14 @@ size_t project_lds_bytes(int dims, int nvp, int tpad, int tb, size_t scalar)
 
 hipError_t launch_project_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st)
 {
-    TRAJAM_DISPATCH(launch_project_t, double, dims, nvp, a, st);
+    TRAJAM_DISPATCH(launch_project_plain, double, dims, nvp, a, st);
 }
 
 hipError_t launch_project_f32(int dims, int nvp, bool mfma_qp, const AmArgs<float> &a,
                               hipStream_t st)
 {
-    if (mfma_qp) return hipErrorNotSupported;
-    TRAJAM_DISPATCH(launch_project_t, float, dims, nvp, a, st);
+    if (mfma_qp) TRAJAM_DISPATCH(launch_project_mqp, float, dims, nvp, a, st);
+    TRAJAM_DISPATCH(launch_project_plain, float, dims, nvp, a, st);
 }
 
 hipError_t launch_residual_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st)

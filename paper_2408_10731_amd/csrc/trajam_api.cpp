@@ -352,23 +352,26 @@ trajam_status trajam_init(const trajam_problem *p, trajam_solver **out)
     if (e == hipSuccess) e = f64 ? upload<double>(&s->d_W, Wp) : upload<float>(&s->d_W, Wp);
     if (e == hipSuccess) e = f64 ? upload<double>(&s->d_obs, zeros_obs) : upload<float>(&s->d_obs, zeros_obs);
     if (e == hipSuccess && p->precision == TRAJAM_BF16_REFINE) {
-        // hi/lo bf16 split of W_ff (rows free, cols coefficient order, 16 x 16)
+        // bf16 hi/lo split of W_ff = H_ff^-1 (16 x 16, zero padded), and H_ff, H_fb in fp32
         std::vector<uint16_t> hl(2 * 256, 0);
         for (int a = 0; a < nf; ++a)
-            for (int m = 0; m < nv; ++m) {
-                const float w = (float)s->W[(size_t)a * nv + m];
+            for (int b = 0; b < nf; ++b) {
+                const float w = (float)s->Wff[(size_t)a * nf + b];
                 const uint16_t hi = bf16_bits(w);
                 const uint16_t lo = bf16_bits(w - bf16_value(hi));
-                hl[a * 16 + m] = hi;
-                hl[256 + a * 16 + m] = lo;
+                hl[a * 16 + b] = hi;
+                hl[256 + a * 16 + b] = lo;
             }
         e = hipMalloc(&s->d_bf16, hl.size() * sizeof(uint16_t));
         if (e == hipSuccess)
             e = hipMemcpy(s->d_bf16, hl.data(), hl.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
-        std::vector<double> H16(256, 0.0);
-        for (int a = 0; a < nf; ++a)
-            for (int b = 0; b < nf; ++b) H16[a * 16 + b] = Hff[(size_t)a * nf + b];
-        if (e == hipSuccess) e = upload<float>(&s->d_Hff, H16);
+        std::vector<double> Hm(256 + 64, 0.0);
+        const int bidx[4] = {0, 1, 2, n};
+        for (int a = 0; a < nf; ++a) {
+            for (int b = 0; b < nf; ++b) Hm[a * 16 + b] = Hff[(size_t)a * nf + b];
+            for (int j = 0; j < 4; ++j) Hm[256 + a * 4 + j] = s->H[(size_t)(3 + a) * nv + bidx[j]];
+        }
+        if (e == hipSuccess) e = upload<float>(&s->d_Hff, Hm);
     }
     if (e != hipSuccess) {
         std::string m = std::string("device allocation/copy failed: ") + hipGetErrorString(e);
@@ -437,7 +440,7 @@ void fill_args(const trajam_solver *s, AmArgs<T> &a, int batch, int iters)
         a.Whi = (const uint16_t *)s->d_bf16;
         a.Wlo = (const uint16_t *)s->d_bf16 + 256;
     }
-    a.Hff = (const T *)s->d_Hff;
+    a.Hmq = (const float *)s->d_Hff;
 }
 
 trajam_status pack(trajam_solver *s, const void *c, const void *w, const void *ax, hipStream_t st)

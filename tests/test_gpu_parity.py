@@ -9,6 +9,8 @@ Tolerances:
   residual; boundary rows met to 1e-10 with the boundary values of these workloads
   (exactly representable in float).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -233,3 +235,59 @@ def test_fp32_config2_sampled_long_run():
     w = wl.config2(batch=96)
     say("case: cfg2 fp32 100 iterations")
     _fp32_check(w, 100)
+
+
+# ------------------------------------------------------------------ BF16 --
+
+
+def _sampled_check(w, precision, iters, idx, tol_wp=1e-3, tol_res=1e-4, sphere=None):
+    """GPU at the full batch (the benchmark's launch), oracle on sampled samples."""
+    w = w.rounded(np.float32)
+    xb_g, lam_g, tr_g, fl = run_gpu(w, iters, precision=precision, sphere=sphere)
+    ws = dataclasses.replace(w, xi=np.ascontiguousarray(w.xi[idx]))
+    xb_o, _, _, _ = oracle.project(ws, iters=iters)
+    xg = xb_g[idx]
+    wp = np.abs(waypoints(ws, xg) - waypoints(ws, xb_o)).max(axis=(1, 2))
+    r_g = oracle.residuals(ws, xg)[0]
+    r_o = oracle.residuals(ws, xb_o)[0]
+    dr = np.abs(r_g - r_o)
+    say(f"  {precision} vs FP64 oracle: waypoint err max {wp.max():.3e} median "
+        f"{np.median(wp):.3e} m; residual err max {dr.max():.3e} median {np.median(dr):.3e}")
+    assert wp.max() <= tol_wp
+    assert dr.max() <= tol_res
+    assert not np.any(fl & 1)
+    n = w.degree
+    for ax in range(w.dims):
+        assert np.abs(xb_g[:, ax, 0] - w.boundary[ax, 0]).max() <= 1e-10
+        assert np.abs(xb_g[:, ax, n] - w.boundary[ax, 3]).max() <= 1e-10
+    return wp, dr
+
+
+def test_bf16_config3_full_launch_sampled():
+    """Config 3 (3D, degree 15, 150 steps, 200 ellipsoids, B = 4096, 50 iterations):
+    QP product on bf16 matrix cores with hi/lo split and one refinement pass."""
+    w = wl.config3()
+    idx = np.arange(0, w.batch, 43)
+    say("case: cfg3 bf16 full launch, sampled", len(idx))
+    _sampled_check(w, "bf16", w.iters, idx, sphere=False)
+
+
+def test_fp32_config3_full_launch_sampled():
+    w = wl.config3()
+    idx = np.arange(7, w.batch, 97)
+    say("case: cfg3 fp32 full launch, sampled", len(idx))
+    _sampled_check(w, "fp32", w.iters, idx, sphere=False)
+
+
+@pytest.mark.parametrize("tb", [1, 2])
+def test_bf16_small_2d_tiles(tb):
+    """bf16 matrix-core QP with several samples per workgroup (16-column tile holds
+    tb x dims columns), including a ragged last workgroup."""
+    w = wl.config2(batch=203)
+    say("case: bf16 2D tiles", tb)
+    w = w.rounded(np.float32)
+    xb_o, _, _, _ = oracle.project(w, iters=30)
+    xb_g, _, _, _ = run_gpu(w, 30, precision="bf16", tb=tb)
+    wp = np.abs(waypoints(w, xb_g) - waypoints(w, xb_o)).max()
+    say(f"  waypoint err {wp:.3e}")
+    assert wp <= 1e-3
