@@ -159,13 +159,24 @@ trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const void *xi_b
 trajam_status trajam_fixed_matrices(const trajam_problem *p, double *P, double *Pd,
                                     double *Pdd, double *H, double *W);
 
-/* Launch shape of trajam_project / trajam_residuals: samples per workgroup.  Each
- * sample takes n_steps rounded up to a multiple of 64 lanes and a workgroup holds
- * at most 256 lanes, so tb is in [1, 256 / roundup64(n_steps)].  The autotuner
- * picks it; the result does not depend on it (every sample runs the same
- * arithmetic in the same order).  Errors: INVALID. */
-trajam_status trajam_set_samples_per_workgroup(trajam_solver *s, int32_t tb);
-int32_t trajam_samples_per_workgroup(const trajam_solver *s); /* -1 for NULL */
+/* Kernel variants of trajam_project.  Both run every iteration of a call in one
+ * launch and compute the same arithmetic per sample; they differ in how a sample's
+ * time samples map to lanes. */
+typedef enum {
+    TRAJAM_KERNEL_MULTIWAVE = 0, /* one lane per time sample: ceil(n_steps / 64) waves per
+                                    sample, exchanging partial sums through LDS */
+    TRAJAM_KERNEL_WAVE = 1       /* one wave per sample: ceil(n_steps / 64) time samples
+                                    per lane, no block barrier inside the iteration */
+} trajam_kernel;
+
+/* Launch shape of trajam_project: kernel variant and samples per workgroup (spw).
+ * MULTIWAVE needs spw * roundup64(n_steps) <= 256, WAVE needs spw * 64 <= 256.
+ * The autotuner picks it; results do not depend on spw, and the two variants agree
+ * to rounding (they sum F^T r over time samples in different orders).
+ * Errors: INVALID. */
+trajam_status trajam_set_launch(trajam_solver *s, int32_t kernel, int32_t samples_per_workgroup);
+trajam_status trajam_get_launch(const trajam_solver *s, int32_t *kernel,
+                                int32_t *samples_per_workgroup);
 
 /* Boundary coefficients xi_0, xi_1, xi_2, xi_n implied by (x0, v0, a0, xf) for
  * one axis (the unique solution of the four boundary rows).  Host only. */

@@ -30,7 +30,8 @@ struct AmArgs {
     T xiB[3][4];            // closed-form boundary coefficients (xi_0, xi_1, xi_2, xi_n) per axis
     const T *phi;           // [3][n_p][NVP]: rows of P, Pd, Pdd, zero padded to NVP
     const T *W;             // [NVP - 4 rows used: nv - 4][NVP] QP update operator
-    const T *obs;           // packed obstacles [n_o][REC] (see obstacle_record_len)
+    const T *obs;           // packed obstacle records [n_o][kObstacleRecord]
+    const T *obs_soa;       // grouped inside-test fields [groups][kObstacleFields][group]
     const T *xi;            // [batch][D][nv]
     T *xb;                  // [batch][D][nv] in/out
     T *lam;                 // [batch][D][nv] in/out
@@ -46,18 +47,31 @@ struct AmArgs {
 
 // Packed obstacle record length (scalars), any dims.
 constexpr int kObstacleRecord = 16;
+// Inside-test fields per obstacle in the grouped layout, and obstacles per group
+// (one 64-byte scalar load per field and group in float, 64 bytes in double).
+constexpr int kObstacleFields = 10;
+template <typename T>
+constexpr int kGroupStore = sizeof(T) == 4 ? 16 : 8;
+constexpr size_t group_store(size_t scalar) { return scalar == 4 ? 16 : 8; }
+inline int obstacle_groups(int n_o, size_t scalar) { return (n_o + (int)group_store(scalar) - 1) / (int)group_store(scalar); }
 
 // Launchers.  Return the HIP error of the launch.  `nvp` is the padded coefficient
 // count (8, 12 or 16); `mfma_qp` selects the bf16 matrix-core QP step.
-hipError_t launch_project_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st);
-hipError_t launch_project_f32(int dims, int nvp, bool mfma_qp, const AmArgs<float> &a,
+// Kernel variants: several waves per sample (one lane per time sample, tb samples
+// per workgroup) or one wave per sample (ceil(n_p / 64) time samples per lane, tb
+// samples = waves per workgroup).
+constexpr int kVariantMultiWave = 0;
+constexpr int kVariantWave = 1;
+hipError_t launch_project_f64(int dims, int nvp, int variant, const AmArgs<double> &a,
                               hipStream_t st);
+hipError_t launch_project_f32(int dims, int nvp, int variant, bool mfma_qp,
+                              const AmArgs<float> &a, hipStream_t st);
 hipError_t launch_residual_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st);
 hipError_t launch_residual_f32(int dims, int nvp, const AmArgs<float> &a, hipStream_t st);
 hipError_t launch_pack_obstacles_f64(int dims, int n_o, const double *c, const double *w,
-                                     const double *s, double *out, hipStream_t st);
+                                     const double *s, double *out, double *soa, hipStream_t st);
 hipError_t launch_pack_obstacles_f32(int dims, int n_o, const float *c, const float *w,
-                                     const float *s, float *out, hipStream_t st);
+                                     const float *s, float *out, float *soa, hipStream_t st);
 
 // Dynamic LDS bytes of one AM workgroup.
 size_t project_lds_bytes(int dims, int nvp, int tpad, int tb, size_t scalar);

@@ -145,58 +145,79 @@ __device__ __forceinline__ T reduce_scatter(T *c, int lane)
     return v;
 }
 
+// Sum / max over the 64 lanes of a wave, result in every lane: quad and row steps by
+// DPP, then the two permlane swaps combine rows and halves.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    v += dpp<kDppXor1>(v);
+    v += dpp<kDppXor2>(v);
+    v += dpp<kDppHalfMirror>(v);
+    v += dpp<kDppRor8>(v);
+    T a = v, b = v;
+    swap16(a, b);
+    v = a + b;
+    a = v;
+    b = v;
+    swap32(a, b);
+    return a + b;
 }
 
 template <typename T>
 __device__ __forceinline__ T wave_max(T v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-    return v;
+    v = fmax(v, dpp<kDppXor1>(v));
+    v = fmax(v, dpp<kDppXor2>(v));
+    v = fmax(v, dpp<kDppHalfMirror>(v));
+    v = fmax(v, dpp<kDppRor8>(v));
+    T a = v, b = v;
+    swap16(a, b);
+    v = fmax(a, b);
+    a = v;
+    b = v;
+    swap32(a, b);
+    return fmax(a, b);
 }
 
 constexpr int pow2ceil(int x) { return x <= 1 ? 1 : 2 * pow2ceil((x + 1) / 2); }
 
-// Obstacle records are read through the constant address space: the address is
-// wave-uniform and the data is never written by the kernel, so the loads become
-// scalar loads into SGPRs (no VGPR, LDS or vector-memory cost).
+// Obstacle data is read through the constant address space: the address is
+// wave-uniform and the kernel never writes it, so the loads become scalar loads into
+// SGPRs (no VGPR, LDS or vector-memory cost).
 #define TRAJAM_CONST_AS __attribute__((address_space(4)))
 
-// Record slots (see pack_obstacles_kernel): centre, -velocity, 1/semi-axes,
-// semi-axes, -radius^2, radius.
+// Full per-obstacle record (used on the rare inside path): centre, -velocity,
+// 1/semi-axes, semi-axes, -radius^2, radius.
 constexpr int kOC = 0, kOW = 3, kOI = 6, kOS = 9, kONR2 = 12, kOR = 13;
 
-// Signed inside test of one obstacle at one lane: q < 0 iff the point is inside.
-// Spheres/circles: q = |x~|^2 - r^2; ellipsoids: q = |x~ ./ s|^2 - 1.
-template <typename T, int D, bool SPH, bool DYN>
-__device__ __forceinline__ T obstacle_q(const TRAJAM_CONST_AS T *o, const T (&p)[D], T tt)
+// Inside-test data in groups: kGroupStore<T> obstacles per group, field-major, so
+// that one scalar load brings one field of a whole (sub)group into SGPRs.  Groups
+// are padded with sentinels far away that are never inside.
+constexpr int kFCX = 0, kFWX = 3, kFIX = 6, kFNR2 = 9;
+
+template <typename T, int G>
+struct Lanes {
+    T v[G];
+};
+
+// One field of a G-obstacle batch from the constant address space; adjacent
+// uniform loads are merged into one wide scalar load.
+template <typename T, int G>
+__device__ __forceinline__ Lanes<T, G> load_field(const TRAJAM_CONST_AS T *p)
 {
-    T dx[D];
+    Lanes<T, G> r;
 #pragma unroll
-    for (int ax = 0; ax < D; ++ax) {
-        dx[ax] = p[ax] - o[kOC + ax];
-        if (DYN) dx[ax] = fma(o[kOW + ax], tt, dx[ax]);
-    }
-    T q;
-    if (SPH) {
-        q = fma(dx[D - 1], dx[D - 1], o[kONR2]);
-#pragma unroll
-        for (int ax = D - 2; ax >= 0; --ax) q = fma(dx[ax], dx[ax], q);
-    } else {
-        q = T(-1);
-#pragma unroll
-        for (int ax = D - 1; ax >= 0; --ax) {
-            const T u = dx[ax] * o[kOI + ax];
-            q = fma(u, u, q);
-        }
-    }
-    return q;
+    for (int u = 0; u < G; ++u) r.v[u] = p[u];
+    return r;
+}
+
+// Obstacles tested per scalar-load batch: as many as fit ~48 SGPRs of fields.
+template <typename T, int D, bool SPH, bool DYN>
+constexpr int test_group()
+{
+    constexpr int fields = D + (DYN ? D : 0) + (SPH ? 1 : D);
+    constexpr int g32 = fields <= 3 ? 16 : (fields <= 6 ? 8 : 4);
+    return sizeof(T) == 4 ? g32 : g32 / 2;
 }
 
 // Residual of one obstacle for a lane known to be inside (rare path): the point is
@@ -234,49 +255,109 @@ __device__ __forceinline__ void obstacle_inside(const TRAJAM_CONST_AS T *o, cons
     }
 }
 
-// Obstacle polar step summed over all obstacles for one (sample, time) pair
-// (eqs collision_priest, zeta_2, compute_d_mij, d_max).  The residual r_j = p - e_j
-// is zero outside obstacle j (d = |u| >= 1), so the loop tests four obstacles at a
-// time and enters the residual path only if one of them contains a lane's point.
-template <typename T, int D, bool SPH, bool DYN>
-__device__ __forceinline__ void obstacle_loop(const TRAJAM_CONST_AS T *obs, int n_o, T tt,
-                                              const T (&p)[D], T (&R)[D], T &r2, T &rmax)
+// Obstacle polar step summed over all obstacles for NPT (sample, time) points of one
+// lane (eqs collision_priest, zeta_2, compute_d_mij, d_max).  The residual
+// r_j = p - e_j is zero outside obstacle j (d = |u| >= 1), so the loop evaluates the
+// signed inside test q = |x~|^2 - r^2 (spheres) or |x~ ./ s|^2 - 1 (ellipsoids) for a
+// batch of G obstacles whose fields sit in SGPRs, and enters the residual path only
+// if a lane's point is inside one of them.  Points that must not contribute are
+// placed far away (-1e30) by the caller and are never inside; the padding
+// obstacles sit at +1e30.
+template <typename T, int D, bool SPH, bool DYN, int NPT>
+__device__ __forceinline__ void obstacle_loop(const TRAJAM_CONST_AS T *soa,
+                                              const TRAJAM_CONST_AS T *aos, int n_o,
+                                              const T (&tt)[NPT], const T (&p)[NPT][D],
+                                              T (&R)[NPT][D], T &r2, T &rmax)
 {
-    constexpr int REC = kObstacleRecord;
-    int j = 0;
-    for (; j + 4 <= n_o; j += 4) {
-        const TRAJAM_CONST_AS T *o = obs + j * REC;
-        const T q0 = obstacle_q<T, D, SPH, DYN>(o, p, tt);
-        const T q1 = obstacle_q<T, D, SPH, DYN>(o + REC, p, tt);
-        const T q2 = obstacle_q<T, D, SPH, DYN>(o + 2 * REC, p, tt);
-        const T q3 = obstacle_q<T, D, SPH, DYN>(o + 3 * REC, p, tt);
-        if (fmin(fmin(q0, q1), fmin(q2, q3)) < T(0)) {
-            if (q0 < T(0)) obstacle_inside<T, D, SPH, DYN>(o, p, tt, R, r2, rmax);
-            if (q1 < T(0)) obstacle_inside<T, D, SPH, DYN>(o + REC, p, tt, R, r2, rmax);
-            if (q2 < T(0)) obstacle_inside<T, D, SPH, DYN>(o + 2 * REC, p, tt, R, r2, rmax);
-            if (q3 < T(0)) obstacle_inside<T, D, SPH, DYN>(o + 3 * REC, p, tt, R, r2, rmax);
+    constexpr int GS = kGroupStore<T>;
+    constexpr int G0 = test_group<T, D, SPH, DYN>();
+    constexpr int G = NPT > 2 ? (G0 >= 8 ? G0 / 2 : G0) : G0;
+    using V = Lanes<T, G>;
+    const int n_sub = ((n_o + GS - 1) / GS) * (GS / G);
+    for (int sg = 0; sg < n_sub; ++sg) {
+        const int g = sg / (GS / G), h = sg - g * (GS / G);
+        const TRAJAM_CONST_AS T *base = soa + (size_t)g * kObstacleFields * GS + h * G;
+        V c[D], w[D], is[D], nr2;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            c[ax] = load_field<T, G>(base + (kFCX + ax) * GS);
+            if (DYN) w[ax] = load_field<T, G>(base + (kFWX + ax) * GS);
+            if (!SPH) is[ax] = load_field<T, G>(base + (kFIX + ax) * GS);
         }
-    }
-    for (; j < n_o; ++j) {
-        const TRAJAM_CONST_AS T *o = obs + j * REC;
-        if (obstacle_q<T, D, SPH, DYN>(o, p, tt) < T(0))
-            obstacle_inside<T, D, SPH, DYN>(o, p, tt, R, r2, rmax);
+        if (SPH) nr2 = load_field<T, G>(base + kFNR2 * GS);
+        T q[NPT][G];
+        T qmin = T(1);
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+#pragma unroll
+            for (int i = 0; i < NPT; ++i) {
+                T dx[D];
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax) {
+                    dx[ax] = p[i][ax] - c[ax].v[u];
+                    if (DYN) dx[ax] = fma(w[ax].v[u], tt[i], dx[ax]);
+                }
+                T acc;
+                if (SPH) {
+                    acc = fma(dx[D - 1], dx[D - 1], nr2.v[u]);
+#pragma unroll
+                    for (int ax = D - 2; ax >= 0; --ax) acc = fma(dx[ax], dx[ax], acc);
+                } else {
+                    acc = T(-1);
+#pragma unroll
+                    for (int ax = D - 1; ax >= 0; --ax) {
+                        const T uu = dx[ax] * is[ax].v[u];
+                        acc = fma(uu, uu, acc);
+                    }
+                }
+                q[i][u] = acc;
+                qmin = fmin(qmin, acc);
+            }
+        }
+        if (qmin < T(0)) {
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int j = g * GS + h * G + u;  // padding sentinels are never inside;
+                if (j >= n_o) break;               // the record array ends at n_o
+                const TRAJAM_CONST_AS T *o = aos + (size_t)j * kObstacleRecord;
+#pragma unroll
+                for (int i = 0; i < NPT; ++i)
+                    if (q[i][u] < T(0)) obstacle_inside<T, D, SPH, DYN>(o, p[i], tt[i], R[i], r2, rmax);
+            }
+        }
     }
 }
 
-template <typename T, int D>
-__device__ __forceinline__ void obstacle_residuals(const T *obs_generic, int n_o, int sphere,
-                                                   int dynamic, T tt, const T (&p)[D], T (&R)[D],
-                                                   T &r2, T &rmax)
+template <typename T, int D, int NPT>
+__device__ __forceinline__ void obstacle_residuals(const T *soa_g, const T *aos_g, int n_o,
+                                                   int sphere, int dynamic, const T (&tt)[NPT],
+                                                   const T (&p)[NPT][D], T (&R)[NPT][D], T &r2,
+                                                   T &rmax)
 {
-    const TRAJAM_CONST_AS T *obs = (const TRAJAM_CONST_AS T *)obs_generic;
+    const TRAJAM_CONST_AS T *soa = (const TRAJAM_CONST_AS T *)soa_g;
+    const TRAJAM_CONST_AS T *aos = (const TRAJAM_CONST_AS T *)aos_g;
     if (sphere) {
-        if (dynamic) obstacle_loop<T, D, true, true>(obs, n_o, tt, p, R, r2, rmax);
-        else obstacle_loop<T, D, true, false>(obs, n_o, tt, p, R, r2, rmax);
+        if (dynamic) obstacle_loop<T, D, true, true, NPT>(soa, aos, n_o, tt, p, R, r2, rmax);
+        else obstacle_loop<T, D, true, false, NPT>(soa, aos, n_o, tt, p, R, r2, rmax);
     } else {
-        if (dynamic) obstacle_loop<T, D, false, true>(obs, n_o, tt, p, R, r2, rmax);
-        else obstacle_loop<T, D, false, false>(obs, n_o, tt, p, R, r2, rmax);
+        if (dynamic) obstacle_loop<T, D, false, true, NPT>(soa, aos, n_o, tt, p, R, r2, rmax);
+        else obstacle_loop<T, D, false, false, NPT>(soa, aos, n_o, tt, p, R, r2, rmax);
     }
+}
+
+// Single-point form used by the multi-wave and residual kernels.
+template <typename T, int D>
+__device__ __forceinline__ void obstacle_residuals1(const T *soa_g, const T *aos_g, int n_o,
+                                                    int sphere, int dynamic, T tt, const T (&p)[D],
+                                                    T (&R)[D], T &r2, T &rmax)
+{
+    T tt1[1] = {tt};
+    T p1[1][D], R1[1][D];
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) { p1[0][ax] = p[ax]; R1[0][ax] = R[ax]; }
+    obstacle_residuals<T, D, 1>(soa_g, aos_g, n_o, sphere, dynamic, tt1, p1, R1, r2, rmax);
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) R[ax] = R1[0][ax];
 }
 
 // Velocity / acceleration polar step (eqs fv_priest, alpha_v, compute_dv): the
@@ -451,7 +532,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
 #pragma unroll
         for (int ax = 0; ax < D; ++ax) { R[ax] = T(0); rv[ax] = T(0); ra[ax] = T(0); }
         if (valid) {
-            obstacle_residuals<T, D>(a.obs, a.n_o, a.sphere, a.dynamic, tt, p, R, r2, rmax);
+            obstacle_residuals1<T, D>(a.obs_soa, a.obs, a.n_o, a.sphere, a.dynamic, tt, p, R, r2, rmax);
             if (a.use_v) bound_residual<T, D>(v, a.vmax, rv, r2, rmax);
             if (a.use_a) bound_residual<T, D>(acc, a.amax, ra, r2, rmax);
         }
@@ -498,11 +579,10 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
                 nonfinite = nonfinite || !isfinite(rs);
             }
         }
-        __syncthreads();
-
         // ---- step (b): xb_free += W [g_free ; boundary defect]  (eq affine_trans)
         const int nxt = cur ^ 1;
         if constexpr (MQP) {
+            __syncthreads();
             // y = g_f - H_fb Delta_b per (sample, axis) column; delta = W_ff y on the
             // matrix cores, then one refinement pass delta += W_ff (y - H_ff delta).
             float *yb = mq, *db = mq + 256;
@@ -552,6 +632,11 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
                 xbuf[(nxt * a.tb + ls) * S + lt] = xb_o;
             }
         } else {
+            // The owners of a sample are lanes of one wave: their LDS writes of g are
+            // visible to each other after a wavefront-scope fence, no block barrier.
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (owner) {
                 if (o_free) {
                     const T *wr = wmat + (o_m - 3) * NVP;
@@ -579,6 +664,240 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
         // fold the per-lane non-finite bits of this sample into its first lane
         const bool anyb = __any(nonfinite && owner);
         if (owner && lt == 0) {
+            uint32_t fl = 0;
+            if (anyb) fl |= 1u;
+            if (res_last > res_first) fl |= 2u;
+            a.flags[sample] = fl;
+        }
+    }
+}
+
+// Orders this wave's LDS writes before its later LDS reads (lanes of one wave
+// exchanging data through LDS); no other wave takes part, so no block barrier.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ----------------------------------------------------------------------------
+// Wave-per-sample AM kernel: lane l owns time samples l, l + 64, ... (TPL of them),
+// so one sample's whole iteration stays inside one wavefront.  The only block
+// barrier is the one after the constant set-up; the F^T r reduce-scatter leaves
+// coefficient o's sum in lane o << (6 - log2 V), which is also its owner lane for
+// the multiplier, the defect and the QP update.  `a.tb` samples per workgroup
+// (= waves per workgroup), each wave independent of the others.
+template <typename T, int D, int NVP, int TPL, bool MQP>
+__global__ __launch_bounds__(kMaxThreads) void am_wave_kernel(AmArgs<T> a)
+{
+    constexpr int S = D * NVP;
+    constexpr int V = pow2ceil(S);
+    constexpr int LOGV = (V >= 64) ? 6 : (V >= 32) ? 5 : (V >= 16) ? 4 : 3;
+    constexpr int OSH = 6 - LOGV;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *smem = reinterpret_cast<T *>(smem_raw);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int sample = blockIdx.x * a.tb + wv;
+    const bool live = sample < a.batch;
+    const int nf = a.nv - 4;
+
+    T *wmat = smem;                                   // [NVP][NVP]
+    T *xs = smem + NVP * NVP + wv * 2 * S;            // this wave's xb
+    T *gs = xs + S;                                   // this wave's defect
+    float *mqbase = reinterpret_cast<float *>(smem + NVP * NVP + a.tb * 2 * S);
+    float *db = mqbase + wv * 256;                    // MQP: delta tile [16 cols][16 rows]
+    float *hff = mqbase + a.tb * 256;                 // MQP: H_ff [16][16]
+    float *hfb = hff + 256;                           // MQP: H_fb [16][4]
+
+    for (int i = tid; i < NVP * NVP; i += blockDim.x) {
+        const int f = i / NVP, m = i - f * NVP;
+        wmat[i] = (f < nf) ? a.W[f * NVP + m] : T(0);
+    }
+    bf16x4 ahi = {0, 0, 0, 0}, alo = {0, 0, 0, 0};
+    if constexpr (MQP) {
+        const int m = lane & 15, k0 = 4 * (lane >> 4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ahi[i] = (short)a.Whi[m * 16 + k0 + i];
+            alo[i] = (short)a.Wlo[m * 16 + k0 + i];
+        }
+        for (int i = tid; i < 256 + 64; i += blockDim.x) hff[i] = a.Hmq[i];
+    }
+    __syncthreads();
+    if (!live) return;  // waves are independent from here on
+
+    // This lane's time samples and their basis rows (registers for the launch).
+    T tt[TPL], phi0[TPL][NVP], phi1[TPL][NVP], phi2[TPL][NVP];
+    bool valid[TPL];
+#pragma unroll
+    for (int i = 0; i < TPL; ++i) {
+        const int t = lane + 64 * i;
+        valid[i] = t < a.n_p;
+        tt[i] = T(t) * a.dt;
+#pragma unroll
+        for (int m = 0; m < NVP; ++m) {
+            phi0[i][m] = valid[i] ? a.phi[(0 * a.n_p + t) * NVP + m] : T(0);
+            phi1[i][m] = valid[i] ? a.phi[(1 * a.n_p + t) * NVP + m] : T(0);
+            phi2[i][m] = valid[i] ? a.phi[(2 * a.n_p + t) * NVP + m] : T(0);
+        }
+    }
+
+    const int o = lane >> OSH;
+    const bool owner = (lane & ((1 << OSH) - 1)) == 0 && o < S;
+    const int o_ax = o / NVP, o_m = o - (o / NVP) * NVP;
+    const bool o_real = owner && o_m < a.nv;
+    const bool o_free = o_real && o_m >= 3 && o_m < a.nv - 1;
+    const size_t gidx = (size_t)sample * D * a.nv + (size_t)o_ax * a.nv + o_m;
+    T xi_o = T(0), lam_o = T(0), xb_o = T(0), bnd_o = T(0);
+    if (o_real) {
+        xi_o = a.xi[gidx];
+        lam_o = a.lam[gidx];
+        xb_o = a.xb[gidx];
+        if (!o_free) bnd_o = a.xiB[o_ax][(o_m == a.nv - 1) ? 3 : o_m];
+    }
+    if (owner) xs[o] = xb_o;
+    wave_lds_sync();
+
+    T res_first = T(0), res_last = T(0);
+    bool nonfinite = false;
+    for (int k = 0; k < a.iters; ++k) {
+        // ---- step (a): waypoints and polar steps
+        T p[TPL][D], v[TPL][D], acc[TPL][D];
+#pragma unroll
+        for (int i = 0; i < TPL; ++i)
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) { p[i][ax] = T(0); v[i][ax] = T(0); acc[i][ax] = T(0); }
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+            for (int m = 0; m < NVP; ++m) {
+                const T c = xs[ax * NVP + m];
+#pragma unroll
+                for (int i = 0; i < TPL; ++i) {
+                    p[i][ax] = fma(phi0[i][m], c, p[i][ax]);
+                    v[i][ax] = fma(phi1[i][m], c, v[i][ax]);
+                    acc[i][ax] = fma(phi2[i][m], c, acc[i][ax]);
+                }
+            }
+        // Lanes past n_p sit at -1e30: never inside an obstacle, and far from the
+        // padding sentinels at +1e30 as well.
+#pragma unroll
+        for (int i = 0; i < TPL; ++i)
+            if (!valid[i])
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax) p[i][ax] = T(-1e30);
+        T R[TPL][D], rv[TPL][D], ra[TPL][D], r2 = T(0), rmax = T(0);
+#pragma unroll
+        for (int i = 0; i < TPL; ++i)
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) { R[i][ax] = T(0); rv[i][ax] = T(0); ra[i][ax] = T(0); }
+        obstacle_residuals<T, D, TPL>(a.obs_soa, a.obs, a.n_o, a.sphere, a.dynamic, tt, p, R, r2, rmax);
+#pragma unroll
+        for (int i = 0; i < TPL; ++i) {
+            if (a.use_v) bound_residual<T, D>(v[i], a.vmax, rv[i], r2, rmax);
+            if (a.use_a) bound_residual<T, D>(acc[i], a.amax, ra[i], r2, rmax);
+        }
+        // ---- F^T r over the wave
+        bool nz = false;
+#pragma unroll
+        for (int i = 0; i < TPL; ++i)
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax)
+                nz = nz || R[i][ax] != T(0) || rv[i][ax] != T(0) || ra[i][ax] != T(0);
+        T ftr = T(0);
+        if (__any(nz)) {
+            T c[V];
+#pragma unroll
+            for (int j = 0; j < V; ++j) c[j] = T(0);
+#pragma unroll
+            for (int i = 0; i < TPL; ++i)
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+                    for (int m = 0; m < NVP; ++m)
+                        c[ax * NVP + m] = fma(phi0[i][m], R[i][ax],
+                                              fma(phi1[i][m], rv[i][ax], fma(phi2[i][m], ra[i][ax], c[ax * NVP + m])));
+            ftr = reduce_scatter<T, V>(c, lane);
+        }
+        const T r2w = wave_sum(r2);
+        // ---- step (c): multiplier (eq lag) and the QP defect
+        if (owner) {
+            T gv = T(0);
+            if (o_real) {
+                lam_o = fma(-a.rho, ftr, lam_o);
+                gv = o_free ? (xi_o - xb_o + lam_o - a.rho * ftr) : (bnd_o - xb_o);
+            }
+            gs[o] = gv;
+        }
+        if (lane == 0) {
+            const T rs = sqrt(r2w);
+            if (a.res) a.res[(size_t)k * a.batch + sample] = rs;
+            if (k == 0) res_first = rs;
+            res_last = rs;
+            nonfinite = nonfinite || !isfinite(rs);
+        }
+        wave_lds_sync();
+        // ---- step (b): the fixed-matrix QP on the defect (eq affine_trans)
+        if constexpr (MQP) {
+            const int cn = lane & 15, k0 = 4 * (lane >> 4);
+            float yv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int f = k0 + i;
+                float y = 0.f;
+                if (cn < D && f < nf) {
+                    const T *z = gs + cn * NVP;
+                    y = (float)z[3 + f] - (hfb[f * 4 + 0] * (float)z[0] + hfb[f * 4 + 1] * (float)z[1] +
+                                           hfb[f * 4 + 2] * (float)z[2] + hfb[f * 4 + 3] * (float)z[a.nv - 1]);
+                }
+                yv[i] = y;
+            }
+            const f32x4 d0 = qp_mfma(ahi, alo, yv);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) db[cn * 16 + k0 + i] = d0[i];
+            wave_lds_sync();
+            float dv[16], rv4[4];
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) dv[kk] = db[cn * 16 + kk];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float r = yv[i];
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) r = fmaf(-hff[(k0 + i) * 16 + kk], dv[kk], r);
+                rv4[i] = r;
+            }
+            const f32x4 d1 = qp_mfma(ahi, alo, rv4);
+            wave_lds_sync();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) db[cn * 16 + k0 + i] = d0[i] + d1[i];
+            wave_lds_sync();
+            if (o_free) xb_o += (T)db[o_ax * 16 + (o_m - 3)];
+            else if (o_real) xb_o = bnd_o;
+        } else {
+            if (o_free) {
+                const T *wr = wmat + (o_m - 3) * NVP;
+                const T *g = gs + o_ax * NVP;
+                T d = T(0);
+#pragma unroll
+                for (int m = 0; m < NVP; ++m) d = fma(wr[m], g[m], d);
+                xb_o += d;
+            } else if (o_real) {
+                xb_o = bnd_o;
+            }
+        }
+        if (owner) xs[o] = xb_o;
+        wave_lds_sync();
+    }
+
+    if (o_real) {
+        a.xb[gidx] = xb_o;
+        a.lam[gidx] = lam_o;
+        nonfinite = nonfinite || !isfinite(xb_o) || !isfinite(lam_o);
+    }
+    if (a.flags && a.iters > 0) {
+        const bool anyb = __any(nonfinite);
+        if (lane == 0) {
             uint32_t fl = 0;
             if (anyb) fl |= 1u;
             if (res_last > res_first) fl |= 2u;
@@ -624,7 +943,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_residual_kernel(AmArgs<T> a)
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) R[ax] = T(0);
     if (valid) {
-        obstacle_residuals<T, D>(a.obs, a.n_o, a.sphere, a.dynamic, T(lt) * a.dt, p, R, r2, rmax);
+        obstacle_residuals1<T, D>(a.obs_soa, a.obs, a.n_o, a.sphere, a.dynamic, T(lt) * a.dt, p, R, r2, rmax);
         if (a.use_v) bound_residual<T, D>(v, a.vmax, rv, r2, rmax);
         if (a.use_a) bound_residual<T, D>(acc, a.amax, ra, r2, rmax);
     }
@@ -646,28 +965,56 @@ __global__ __launch_bounds__(kMaxThreads) void am_residual_kernel(AmArgs<T> a)
     }
 }
 
-// Packs the caller's obstacle arrays into one 16-slot record per obstacle:
-// centre[3], -velocity[3], 1/semi-axes[3], semi-axes[3], -radius^2, radius
-// (radius = first semi-axis, used by the sphere model), zero padded.
+// Packs the caller's obstacle arrays.  (1) One 16-slot record per obstacle:
+// centre[3], -velocity[3], 1/semi-axes[3], semi-axes[3], -radius^2, radius (radius =
+// first semi-axis, used by the sphere model).  (2) The inside-test fields in groups of
+// kGroupStore obstacles, field-major: centre[3], -velocity[3], 1/semi-axes[3],
+// -radius^2.  Slots past n_o hold a sentinel (centre 1e30, unit scale, zero radius)
+// whose test value is +inf or huge, so it is never inside.
 template <typename T, int D>
-__global__ void pack_obstacles_kernel(int n_o, const T *__restrict__ c, const T *__restrict__ w,
-                                      const T *__restrict__ s, T *__restrict__ out)
+__global__ void pack_obstacles_kernel(int n_o, int n_pad, const T *__restrict__ c,
+                                      const T *__restrict__ w, const T *__restrict__ s,
+                                      T *__restrict__ out, T *__restrict__ soa)
 {
     constexpr int REC = kObstacleRecord;
+    constexpr int GS = kGroupStore<T>;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_o) return;
-    T *o = out + (size_t)j * REC;
+    if (j >= n_pad) return;
+    T f[kObstacleFields];
+    if (j < n_o) {
+        T *o = out + (size_t)j * REC;
 #pragma unroll
-    for (int i = 0; i < REC; ++i) o[i] = T(0);
+        for (int i = 0; i < REC; ++i) o[i] = T(0);
 #pragma unroll
-    for (int ax = 0; ax < D; ++ax) {
-        o[kOC + ax] = c[j * D + ax];
-        o[kOW + ax] = w ? -w[j * D + ax] : T(0);
-        o[kOI + ax] = T(1) / s[j * D + ax];
-        o[kOS + ax] = s[j * D + ax];
+        for (int ax = 0; ax < D; ++ax) {
+            o[kOC + ax] = c[j * D + ax];
+            o[kOW + ax] = w ? -w[j * D + ax] : T(0);
+            o[kOI + ax] = T(1) / s[j * D + ax];
+            o[kOS + ax] = s[j * D + ax];
+        }
+        o[kONR2] = -s[j * D] * s[j * D];
+        o[kOR] = s[j * D];
+#pragma unroll
+        for (int i = 0; i < kObstacleFields; ++i) f[i] = T(0);
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            f[kFCX + ax] = o[kOC + ax];
+            f[kFWX + ax] = o[kOW + ax];
+            f[kFIX + ax] = o[kOI + ax];
+        }
+        f[kFNR2] = o[kONR2];
+    } else {
+#pragma unroll
+        for (int i = 0; i < kObstacleFields; ++i) f[i] = T(0);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            f[kFCX + ax] = T(1e30);
+            f[kFIX + ax] = T(1);
+        }
     }
-    o[kONR2] = -s[j * D] * s[j * D];
-    o[kOR] = s[j * D];
+    const int g = j / GS, u = j - g * GS;
+#pragma unroll
+    for (int i = 0; i < kObstacleFields; ++i) soa[((size_t)g * kObstacleFields + i) * GS + u] = f[i];
 }
 
 template <typename T, int D, int NVP, bool MQP>
@@ -682,6 +1029,28 @@ hipError_t launch_project_t(const AmArgs<T> &a, hipStream_t st)
     hipLaunchKernelGGL((am_project_kernel<T, D, NVP, MQP>), dim3(blocks), dim3(threads), lds, st, a);
     return hipGetLastError();
 }
+template <typename T, int D, int NVP, bool MQP>
+hipError_t launch_wave_t(const AmArgs<T> &a, hipStream_t st)
+{
+    const size_t lds = sizeof(T) * (size_t)(NVP * NVP + a.tb * 2 * D * NVP) +
+                       (MQP ? sizeof(float) * (size_t)(a.tb * 256 + 320) : 0);
+    const int threads = a.tb * 64;
+    const int blocks = (a.batch + a.tb - 1) / a.tb;
+    const int tpl = (a.n_p + 63) / 64;
+    if (a.tb < 1 || threads > kMaxThreads) return hipErrorInvalidValue;
+    switch (tpl) {
+    case 1: hipLaunchKernelGGL((am_wave_kernel<T, D, NVP, 1, MQP>), dim3(blocks), dim3(threads), lds, st, a); break;
+    case 2: hipLaunchKernelGGL((am_wave_kernel<T, D, NVP, 2, MQP>), dim3(blocks), dim3(threads), lds, st, a); break;
+    case 3: hipLaunchKernelGGL((am_wave_kernel<T, D, NVP, 3, MQP>), dim3(blocks), dim3(threads), lds, st, a); break;
+    case 4: hipLaunchKernelGGL((am_wave_kernel<T, D, NVP, 4, MQP>), dim3(blocks), dim3(threads), lds, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template <typename T, int D, int NVP>
+hipError_t launch_wave_plain(const AmArgs<T> &a, hipStream_t st) { return launch_wave_t<T, D, NVP, false>(a, st); }
+template <typename T, int D, int NVP>
+hipError_t launch_wave_mqp(const AmArgs<T> &a, hipStream_t st) { return launch_wave_t<T, D, NVP, true>(a, st); }
 template <typename T, int D, int NVP>
 hipError_t launch_project_plain(const AmArgs<T> &a, hipStream_t st) { return launch_project_t<T, D, NVP, false>(a, st); }
 template <typename T, int D, int NVP>
@@ -725,14 +1094,20 @@ size_t project_lds_bytes(int dims, int nvp, int tpad, int tb, size_t scalar)
     return scalar * (size_t)(3 * tb * S + tb * wpt * V + tb * wpt + nvp * nvp);
 }
 
-hipError_t launch_project_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st)
+hipError_t launch_project_f64(int dims, int nvp, int variant, const AmArgs<double> &a,
+                              hipStream_t st)
 {
+    if (variant == kVariantWave) TRAJAM_DISPATCH(launch_wave_plain, double, dims, nvp, a, st);
     TRAJAM_DISPATCH(launch_project_plain, double, dims, nvp, a, st);
 }
 
-hipError_t launch_project_f32(int dims, int nvp, bool mfma_qp, const AmArgs<float> &a,
+hipError_t launch_project_f32(int dims, int nvp, int variant, bool mfma_qp, const AmArgs<float> &a,
                               hipStream_t st)
 {
+    if (variant == kVariantWave) {
+        if (mfma_qp) TRAJAM_DISPATCH(launch_wave_mqp, float, dims, nvp, a, st);
+        TRAJAM_DISPATCH(launch_wave_plain, float, dims, nvp, a, st);
+    }
     if (mfma_qp) TRAJAM_DISPATCH(launch_project_mqp, float, dims, nvp, a, st);
     TRAJAM_DISPATCH(launch_project_plain, float, dims, nvp, a, st);
 }
@@ -748,30 +1123,31 @@ hipError_t launch_residual_f32(int dims, int nvp, const AmArgs<float> &a, hipStr
 }
 
 template <typename T>
-static hipError_t pack_t(int dims, int n_o, const T *c, const T *w, const T *s, T *out,
+static hipError_t pack_t(int dims, int n_o, const T *c, const T *w, const T *s, T *out, T *soa,
                          hipStream_t st)
 {
     if (n_o <= 0) return hipSuccess;
-    const int threads = 64, blocks = (n_o + threads - 1) / threads;
+    const int n_pad = obstacle_groups(n_o, sizeof(T)) * (int)group_store(sizeof(T));
+    const int threads = 64, blocks = (n_pad + threads - 1) / threads;
     if (dims == 2)
         hipLaunchKernelGGL((pack_obstacles_kernel<T, 2>), dim3(blocks), dim3(threads), 0, st, n_o,
-                           c, w, s, out);
+                           n_pad, c, w, s, out, soa);
     else
         hipLaunchKernelGGL((pack_obstacles_kernel<T, 3>), dim3(blocks), dim3(threads), 0, st, n_o,
-                           c, w, s, out);
+                           n_pad, c, w, s, out, soa);
     return hipGetLastError();
 }
 
 hipError_t launch_pack_obstacles_f64(int dims, int n_o, const double *c, const double *w,
-                                     const double *s, double *out, hipStream_t st)
+                                     const double *s, double *out, double *soa, hipStream_t st)
 {
-    return pack_t<double>(dims, n_o, c, w, s, out, st);
+    return pack_t<double>(dims, n_o, c, w, s, out, soa, st);
 }
 
 hipError_t launch_pack_obstacles_f32(int dims, int n_o, const float *c, const float *w,
-                                     const float *s, float *out, hipStream_t st)
+                                     const float *s, float *out, float *soa, hipStream_t st)
 {
-    return pack_t<float>(dims, n_o, c, w, s, out, st);
+    return pack_t<float>(dims, n_o, c, w, s, out, soa, st);
 }
 
 }  // namespace trajam

@@ -36,6 +36,7 @@ using trajam::AmArgs;
 struct trajam_solver {
     trajam_problem prob;
     int nv, nf, nvp, tpad, tb;
+    int variant;  // trajam::kVariant*
     int device;
     // host FP64 copies
     std::vector<double> P, Pd, Pdd, H, W, Wff;
@@ -43,6 +44,7 @@ struct trajam_solver {
     void *d_phi = nullptr;   // [3][n_p][nvp]
     void *d_W = nullptr;     // [nvp][nvp] (rows >= nf zero)
     void *d_obs = nullptr;   // [n_o][REC]
+    void *d_soa = nullptr;   // [groups][fields][group]
     void *d_bf16 = nullptr;  // BF16_REFINE: Whi, Wlo [16][16] uint16 each
     void *d_Hff = nullptr;   // BF16_REFINE: [16][16] float
     std::string err;
@@ -297,6 +299,7 @@ void trajam_destroy(trajam_solver *s)
     if (s->d_phi) (void)hipFree(s->d_phi);
     if (s->d_W) (void)hipFree(s->d_W);
     if (s->d_obs) (void)hipFree(s->d_obs);
+    if (s->d_soa) (void)hipFree(s->d_soa);
     if (s->d_bf16) (void)hipFree(s->d_bf16);
     if (s->d_Hff) (void)hipFree(s->d_Hff);
     delete s;
@@ -318,7 +321,8 @@ trajam_status trajam_init(const trajam_problem *p, trajam_solver **out)
     s->nf = nv - 4;
     s->nvp = pad_coeffs(nv);
     s->tpad = ((np + 63) / 64) * 64;
-    s->tb = std::max(1, std::min(trajam::kMaxThreads / s->tpad, 1));
+    s->variant = TRAJAM_KERNEL_MULTIWAVE;
+    s->tb = 1;
 
     std::string msg;
     st = precompute(*p, s->P, s->Pd, s->Pdd, s->H, s->Wff, s->W, msg);
@@ -351,6 +355,10 @@ trajam_status trajam_init(const trajam_problem *p, trajam_solver **out)
     hipError_t e = f64 ? upload<double>(&s->d_phi, phi) : upload<float>(&s->d_phi, phi);
     if (e == hipSuccess) e = f64 ? upload<double>(&s->d_W, Wp) : upload<float>(&s->d_W, Wp);
     if (e == hipSuccess) e = f64 ? upload<double>(&s->d_obs, zeros_obs) : upload<float>(&s->d_obs, zeros_obs);
+    const size_t scal = f64 ? sizeof(double) : sizeof(float);
+    std::vector<double> zeros_soa((size_t)std::max(trajam::obstacle_groups(p->n_obstacles, scal), 1) *
+                                      trajam::kObstacleFields * trajam::group_store(scal), 0.0);
+    if (e == hipSuccess) e = f64 ? upload<double>(&s->d_soa, zeros_soa) : upload<float>(&s->d_soa, zeros_soa);
     if (e == hipSuccess && p->precision == TRAJAM_BF16_REFINE) {
         // bf16 hi/lo split of W_ff = H_ff^-1 (16 x 16, zero padded), and H_ff, H_fb in fp32
         std::vector<uint16_t> hl(2 * 256, 0);
@@ -399,16 +407,30 @@ trajam_status trajam_fixed_matrices(const trajam_problem *p, double *P, double *
     return TRAJAM_OK;
 }
 
-trajam_status trajam_set_samples_per_workgroup(trajam_solver *s, int32_t tb)
+trajam_status trajam_set_launch(trajam_solver *s, int32_t kernel, int32_t spw)
 {
     if (!s) return TRAJAM_ERR_INVALID;
-    if (tb < 1 || tb * s->tpad > trajam::kMaxThreads)
-        return fail(s, TRAJAM_ERR_INVALID, "samples per workgroup must be >= 1 and fit 256 threads");
-    s->tb = tb;
+    if (kernel == TRAJAM_KERNEL_MULTIWAVE) {
+        if (spw < 1 || spw * s->tpad > trajam::kMaxThreads)
+            return fail(s, TRAJAM_ERR_INVALID, "multi-wave kernel: spw * roundup64(n_steps) must be in [64, 256]");
+    } else if (kernel == TRAJAM_KERNEL_WAVE) {
+        if (spw < 1 || spw * 64 > trajam::kMaxThreads)
+            return fail(s, TRAJAM_ERR_INVALID, "wave kernel: spw must be in [1, 4]");
+    } else {
+        return fail(s, TRAJAM_ERR_INVALID, "unknown kernel variant");
+    }
+    s->variant = kernel;
+    s->tb = spw;
     return TRAJAM_OK;
 }
 
-int32_t trajam_samples_per_workgroup(const trajam_solver *s) { return s ? s->tb : -1; }
+trajam_status trajam_get_launch(const trajam_solver *s, int32_t *kernel, int32_t *spw)
+{
+    if (!s) return TRAJAM_ERR_INVALID;
+    if (kernel) *kernel = s->variant;
+    if (spw) *spw = s->tb;
+    return TRAJAM_OK;
+}
 
 }  // extern "C"
 
@@ -436,6 +458,7 @@ void fill_args(const trajam_solver *s, AmArgs<T> &a, int batch, int iters)
     a.phi = (const T *)s->d_phi;
     a.W = (const T *)s->d_W;
     a.obs = (const T *)s->d_obs;
+    a.obs_soa = (const T *)s->d_soa;
     if (s->d_bf16) {
         a.Whi = (const uint16_t *)s->d_bf16;
         a.Wlo = (const uint16_t *)s->d_bf16 + 256;
@@ -451,10 +474,10 @@ trajam_status pack(trajam_solver *s, const void *c, const void *w, const void *a
     hipError_t e = (p.precision == TRAJAM_FP64)
                        ? trajam::launch_pack_obstacles_f64(p.dims, p.n_obstacles, (const double *)c,
                                                            (const double *)w, (const double *)ax,
-                                                           (double *)s->d_obs, st)
+                                                           (double *)s->d_obs, (double *)s->d_soa, st)
                        : trajam::launch_pack_obstacles_f32(p.dims, p.n_obstacles, (const float *)c,
                                                            (const float *)w, (const float *)ax,
-                                                           (float *)s->d_obs, st);
+                                                           (float *)s->d_obs, (float *)s->d_soa, st);
     if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("obstacle pack launch: ") + hipGetErrorString(e));
     return TRAJAM_OK;
 }
@@ -496,7 +519,7 @@ extern "C" trajam_status trajam_project(trajam_solver *s, int32_t batch, const v
         a.lam = (double *)lambda;
         a.res = (double *)res_trace;
         a.flags = flags;
-        e = trajam::launch_project_f64(p.dims, s->nvp, a, st);
+        e = trajam::launch_project_f64(p.dims, s->nvp, s->variant, a, st);
     } else {
         AmArgs<float> a;
         fill_args(s, a, batch, iters);
@@ -511,7 +534,7 @@ extern "C" trajam_status trajam_project(trajam_solver *s, int32_t batch, const v
         a.lam = (float *)lambda;
         a.res = (float *)res_trace;
         a.flags = flags;
-        e = trajam::launch_project_f32(p.dims, s->nvp, p.precision == TRAJAM_BF16_REFINE, a, st);
+        e = trajam::launch_project_f32(p.dims, s->nvp, s->variant, p.precision == TRAJAM_BF16_REFINE, a, st);
     }
     if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("AM launch: ") + hipGetErrorString(e));
     return TRAJAM_OK;

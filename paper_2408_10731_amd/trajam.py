@@ -31,14 +31,17 @@ PRECISIONS = {"fp64": TRAJAM_FP64, "fp32": TRAJAM_FP32, "bf16": TRAJAM_BF16_REFI
 TRAJAM_ELLIPSOID = 0
 TRAJAM_SPHERE = 1
 
+TRAJAM_KERNEL_MULTIWAVE = 0
+TRAJAM_KERNEL_WAVE = 1
+
 FLAG_NONFINITE = 1
 FLAG_GREW = 2
 
 # every symbol include/trajam.h declares
 EXPORTS = [
     "trajam_init", "trajam_destroy", "trajam_project", "trajam_residuals",
-    "trajam_fixed_matrices", "trajam_set_samples_per_workgroup",
-    "trajam_samples_per_workgroup", "trajam_boundary_coefficients",
+    "trajam_fixed_matrices", "trajam_set_launch", "trajam_get_launch",
+    "trajam_boundary_coefficients",
     "trajam_status_string", "trajam_last_error",
 ]
 
@@ -95,10 +98,10 @@ def load():
     L.trajam_residuals.restype = ctypes.c_int
     L.trajam_fixed_matrices.argtypes = [ctypes.POINTER(Problem), dp, dp, dp, dp, dp]
     L.trajam_fixed_matrices.restype = ctypes.c_int
-    L.trajam_set_samples_per_workgroup.argtypes = [vp, ctypes.c_int32]
-    L.trajam_set_samples_per_workgroup.restype = ctypes.c_int
-    L.trajam_samples_per_workgroup.argtypes = [vp]
-    L.trajam_samples_per_workgroup.restype = ctypes.c_int32
+    L.trajam_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.trajam_set_launch.restype = ctypes.c_int
+    L.trajam_get_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    L.trajam_get_launch.restype = ctypes.c_int
     L.trajam_boundary_coefficients.argtypes = [ctypes.POINTER(Problem), dp, dp]
     L.trajam_boundary_coefficients.restype = ctypes.c_int
     L.trajam_status_string.argtypes = [ctypes.c_int]
@@ -159,12 +162,14 @@ def trajam_fixed_matrices(problem: Problem):
     return P, Pd, Pdd, H, W
 
 
-def trajam_set_samples_per_workgroup(handle, tb: int) -> None:
-    _check(load().trajam_set_samples_per_workgroup(handle, int(tb)), handle)
+def trajam_set_launch(handle, kernel: int, samples_per_workgroup: int) -> None:
+    _check(load().trajam_set_launch(handle, int(kernel), int(samples_per_workgroup)), handle)
 
 
-def trajam_samples_per_workgroup(handle) -> int:
-    return int(load().trajam_samples_per_workgroup(handle))
+def trajam_get_launch(handle):
+    k = ctypes.c_int32(); t = ctypes.c_int32()
+    _check(load().trajam_get_launch(handle, ctypes.byref(k), ctypes.byref(t)), handle)
+    return int(k.value), int(t.value)
 
 
 def trajam_boundary_coefficients(problem: Problem, b4) -> np.ndarray:
@@ -261,11 +266,11 @@ class Solver:
                          c, v, a, self._t(res_l2, (B,), "res_l2"),
                          None if res_max is None else self._t(res_max, (B,), "res_max"), st)
 
-    def set_samples_per_workgroup(self, tb: int):
-        trajam_set_samples_per_workgroup(self.handle, tb)
+    def set_launch(self, kernel: int, samples_per_workgroup: int):
+        trajam_set_launch(self.handle, kernel, samples_per_workgroup)
 
-    def samples_per_workgroup(self) -> int:
-        return trajam_samples_per_workgroup(self.handle)
+    def launch(self):
+        return trajam_get_launch(self.handle)
 
 
 def device_workload(w, dtype, device="cuda", static=None):

@@ -75,7 +75,8 @@ def test_null_handles_are_rejected():
         tj.TRAJAM_ERR_INVALID
     assert L.trajam_init(None, None) == tj.TRAJAM_ERR_INVALID
     L.trajam_destroy(None)
-    assert L.trajam_samples_per_workgroup(None) == -1
+    assert L.trajam_set_launch(None, 0, 1) == tj.TRAJAM_ERR_INVALID
+    assert L.trajam_get_launch(None, None, None) == tj.TRAJAM_ERR_INVALID
 
 
 @pytest.mark.parametrize("dims,degree,n_steps,T,n_obs,vm,am", [

@@ -31,11 +31,13 @@ def say(*a):
 
 
 def run_gpu(w, iters, precision="fp64", xi_bar=None, lam=None, tb=None, sphere=None,
-            static=None, split=None):
+            static=None, split=None, kernel=None):
+    """kernel: None (library default), 0 multi-wave, 1 wave-per-sample; tb: samples
+    per workgroup (default 1 when a kernel is named)."""
     tj = _tj()
     solver = tj.Solver.for_workload(w, precision=precision, sphere=sphere)
-    if tb is not None:
-        solver.set_samples_per_workgroup(tb)
+    if kernel is not None or tb is not None:
+        solver.set_launch(1 if kernel is None else kernel, 1 if tb is None else tb)
     dt = solver.dtype
     xi, obs = tj.device_workload(w, dt, static=static)
     xb = (xi.clone() if xi_bar is None else torch.as_tensor(xi_bar, dtype=dt, device="cuda").contiguous())
@@ -111,10 +113,12 @@ def test_fp64_shapes_and_obstacle_models(dims, degree, n_steps, n_obs, batch, sp
     xb_o, lam_o, tr_o, _ = oracle.project(w, iters=K)
     # ellipsoid model always valid; sphere model when the semi-axes are equal
     for sphere in ([False, True] if not per_axis else [False]):
-        xb_g, lam_g, tr_g, _ = run_gpu(w, K, sphere=sphere, static=(speed == 0.0))
-        assert np.abs(tr_g - tr_o).max() <= 1e-9
-        assert np.abs(xb_g - xb_o).max() <= 1e-9
-        assert np.abs(lam_g - lam_o).max() <= 1e-9
+        for kernel in (0, 1):
+            xb_g, lam_g, tr_g, _ = run_gpu(w, K, sphere=sphere, static=(speed == 0.0),
+                                           kernel=kernel)
+            assert np.abs(tr_g - tr_o).max() <= 1e-9, (sphere, kernel)
+            assert np.abs(xb_g - xb_o).max() <= 1e-9, (sphere, kernel)
+            assert np.abs(lam_g - lam_o).max() <= 1e-9, (sphere, kernel)
 
 
 def test_fp64_kinematic_blocks_off_and_no_obstacles():
@@ -164,18 +168,19 @@ def test_fp64_residuals_entry_point():
 
 
 def test_fp64_resumable_tile_invariant_and_deterministic():
-    w = wl.config1(batch=37)  # ragged for 2 samples per workgroup
+    w = wl.config1(batch=37)  # ragged for 2 and 4 samples per workgroup
     say("case: resumable / tile invariance")
-    a = run_gpu(w, 20, tb=1)
-    b = run_gpu(w, 20, tb=2)
-    c = run_gpu(w, 20, tb=1, split=[7, 13])
-    d = run_gpu(w, 20, tb=1)
+    for kernel, tbs in ((0, (1, 2)), (1, (1, 2, 4))):
+        runs = [run_gpu(w, 20, kernel=kernel, tb=tb) for tb in tbs]
+        runs.append(run_gpu(w, 20, kernel=kernel, tb=tbs[0], split=[7, 13]))
+        runs.append(run_gpu(w, 20, kernel=kernel, tb=tbs[0]))
+        for r in runs[1:]:
+            for x, y in zip(runs[0][:3], r[:3]):
+                assert np.array_equal(x, y), kernel
+    a = run_gpu(w, 20, kernel=0)
+    b = run_gpu(w, 20, kernel=1)
     for x, y in zip(a[:3], b[:3]):
-        assert np.array_equal(x, y)
-    for x, y in zip(a[:3], c[:3]):
-        assert np.array_equal(x, y)
-    for x, y in zip(a[:3], d[:3]):
-        assert np.array_equal(x, y)
+        assert np.abs(x - y).max() <= 1e-11
 
 
 def test_zero_batch_zero_iters_and_capacity():
@@ -201,10 +206,10 @@ def test_zero_batch_zero_iters_and_capacity():
 # ------------------------------------------------------------------ FP32 --
 
 
-def _fp32_check(w, iters, tol_wp=1e-3, tol_res=1e-4):
+def _fp32_check(w, iters, tol_wp=1e-3, tol_res=1e-4, kernel=None):
     w = w.rounded(np.float32)   # both sides see the float32 inputs the device gets
     xb_o, lam_o, tr_o, _ = oracle.project(w, iters=iters)
-    xb_g, lam_g, tr_g, fl = run_gpu(w, iters, precision="fp32")
+    xb_g, lam_g, tr_g, fl = run_gpu(w, iters, precision="fp32", kernel=kernel)
     wp = np.abs(waypoints(w, xb_g) - waypoints(w, xb_o)).max(axis=(1, 2))
     r_g = oracle.residuals(w, xb_g)[0]
     r_o = oracle.residuals(w, xb_o)[0]
@@ -224,11 +229,12 @@ def _fp32_check(w, iters, tol_wp=1e-3, tol_res=1e-4):
     return wp, r_g, r_o
 
 
-def test_fp32_config2_full_size():
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_fp32_config2_full_size(kernel):
     """Config 2 at full size (B = 1024, 50 circles, 50 iterations), the bench launch."""
     w = wl.config2()
-    say("case: cfg2 fp32 full")
-    _fp32_check(w, w.iters)
+    say("case: cfg2 fp32 full, kernel", kernel)
+    _fp32_check(w, w.iters, kernel=kernel)
 
 
 def test_fp32_config2_sampled_long_run():
@@ -240,10 +246,12 @@ def test_fp32_config2_sampled_long_run():
 # ------------------------------------------------------------------ BF16 --
 
 
-def _sampled_check(w, precision, iters, idx, tol_wp=1e-3, tol_res=1e-4, sphere=None):
+def _sampled_check(w, precision, iters, idx, tol_wp=1e-3, tol_res=1e-4, sphere=None,
+                   kernel=None):
     """GPU at the full batch (the benchmark's launch), oracle on sampled samples."""
     w = w.rounded(np.float32)
-    xb_g, lam_g, tr_g, fl = run_gpu(w, iters, precision=precision, sphere=sphere)
+    xb_g, lam_g, tr_g, fl = run_gpu(w, iters, precision=precision, sphere=sphere,
+                                    kernel=kernel)
     ws = dataclasses.replace(w, xi=np.ascontiguousarray(w.xi[idx]))
     xb_o, _, _, _ = oracle.project(ws, iters=iters)
     xg = xb_g[idx]
@@ -263,13 +271,14 @@ def _sampled_check(w, precision, iters, idx, tol_wp=1e-3, tol_res=1e-4, sphere=N
     return wp, dr
 
 
-def test_bf16_config3_full_launch_sampled():
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_bf16_config3_full_launch_sampled(kernel):
     """Config 3 (3D, degree 15, 150 steps, 200 ellipsoids, B = 4096, 50 iterations):
     QP product on bf16 matrix cores with hi/lo split and one refinement pass."""
     w = wl.config3()
-    idx = np.arange(0, w.batch, 43)
-    say("case: cfg3 bf16 full launch, sampled", len(idx))
-    _sampled_check(w, "bf16", w.iters, idx, sphere=False)
+    idx = np.arange(kernel, w.batch, 43)
+    say("case: cfg3 bf16 full launch, sampled", len(idx), "kernel", kernel)
+    _sampled_check(w, "bf16", w.iters, idx, sphere=False, kernel=kernel)
 
 
 def test_fp32_config3_full_launch_sampled():
@@ -279,15 +288,15 @@ def test_fp32_config3_full_launch_sampled():
     _sampled_check(w, "fp32", w.iters, idx, sphere=False)
 
 
-@pytest.mark.parametrize("tb", [1, 2])
-def test_bf16_small_2d_tiles(tb):
+@pytest.mark.parametrize("kernel,tb", [(0, 1), (0, 2), (1, 1), (1, 3)])
+def test_bf16_small_2d_tiles(kernel, tb):
     """bf16 matrix-core QP with several samples per workgroup (16-column tile holds
     tb x dims columns), including a ragged last workgroup."""
     w = wl.config2(batch=203)
     say("case: bf16 2D tiles", tb)
     w = w.rounded(np.float32)
     xb_o, _, _, _ = oracle.project(w, iters=30)
-    xb_g, _, _, _ = run_gpu(w, 30, precision="bf16", tb=tb)
+    xb_g, _, _, _ = run_gpu(w, 30, precision="bf16", tb=tb, kernel=kernel)
     wp = np.abs(waypoints(w, xb_g) - waypoints(w, xb_o)).max()
     say(f"  waypoint err {wp:.3e}")
     assert wp <= 1e-3
