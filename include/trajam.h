@@ -183,6 +183,49 @@ trajam_status trajam_get_launch(const trajam_solver *s, int32_t *kernel,
 trajam_status trajam_boundary_coefficients(const trajam_problem *p, const double *b4,
                                            double *coef4);
 
+/* ---- projection-guided sampling loop (thesis ch. 6, Alg 3) -------------------
+ * One CEM iteration on the device is: trajam_cem_sample -> trajam_project (cold
+ * start) -> trajam_residuals -> trajam_cem_cost -> trajam_cem_select ->
+ * trajam_cem_update.  dim = dims * (degree + 1); every array is a device pointer of
+ * the solver precision unless typed otherwise; all calls are asynchronous on
+ * `stream` and never synchronize, so a whole iteration can be captured in a graph. */
+
+/* xi[i] = mu + chol z[i] for i < n (Alg 3, "draw N_b samples from N(mu, Sigma)").
+ *   mu [dim], chol [dim][dim] lower-triangular Cholesky factor of Sigma,
+ *   z [n][dim] standard normal draws (the caller's random numbers),
+ *   xi [n][dims][degree+1] output.  Errors: INVALID, CAPACITY (n > max_batch), DEVICE. */
+trajam_status trajam_cem_sample(trajam_solver *s, int32_t n, const void *mu, const void *chol,
+                                const void *z, void *xi, void *stream);
+
+/* Augmented cost of Alg 3: c_aug[i] = sum_t |Pdd xb_i(t)|^2 + res[i], and the residual
+ * key res_key[i] = floor(res[i] / quantum) (int32, clamped), the resolution at which
+ * residuals are compared.  xi_bar [n][dims][degree+1], res [n] (from trajam_residuals),
+ * c_aug [n], res_key [n] int32.  Errors: INVALID (quantum <= 0), CAPACITY, DEVICE. */
+trajam_status trajam_cem_cost(trajam_solver *s, int32_t n, const void *xi_bar, const void *res,
+                              double quantum, void *c_aug, int32_t *res_key, void *stream);
+
+/* ConstraintEliteSet and EliteSet of Alg 3: proj_idx [n_proj] = the indices of the
+ * n_proj smallest (res_key, c_aug, index) in ascending order; elite_idx [n_elite] =
+ * the n_elite of those with the smallest (c_aug, index), ascending (elite_idx[0] is
+ * the returned trajectory).  One workgroup; n <= 4096.
+ * Errors: INVALID (1 <= n_elite <= n_proj <= n violated, n > 4096), DEVICE. */
+trajam_status trajam_cem_select(trajam_solver *s, int32_t n, const int32_t *res_key,
+                                const void *c_aug, int32_t n_proj, int32_t n_elite,
+                                int32_t *proj_idx, int32_t *elite_idx, void *stream);
+
+/* Distribution update (eqs update_mean, update_covariance) with weights
+ * w_e = exp(-(c_aug_e - min c_aug) / (gamma * std)) over the elite set (std = population
+ * standard deviation of its c_aug; gamma alone when std is 0):
+ *   mu <- (1 - sigma) mu + sigma sum w_e xb_e / sum w_e
+ *   Sigma <- (1 - sigma) Sigma + sigma sum w_e (xb_e - mu)(xb_e - mu)^T / sum w_e  (new mu)
+ *   chol <- Cholesky factor of Sigma + 1e-10 I.
+ * mu [dim], Sigma [dim][dim], chol [dim][dim] in/out; elite_idx [n_elite] int32;
+ * xi_bar and c_aug indexed by elite_idx.  One workgroup.
+ * Errors: INVALID (sigma not in (0, 1], gamma <= 0, n_elite < 1), DEVICE. */
+trajam_status trajam_cem_update(trajam_solver *s, int32_t n_elite, const int32_t *elite_idx,
+                                const void *xi_bar, const void *c_aug, double sigma, double gamma,
+                                void *mu, void *Sigma, void *chol, void *stream);
+
 /* Static description of a status code.  Never NULL. */
 const char *trajam_status_string(trajam_status st);
 

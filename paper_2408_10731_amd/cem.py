@@ -1,0 +1,101 @@
+"""Projection-guided sampling loop on the GPU (thesis ch. 6, Alg 3), driving the
+C-ABI kernels on one stream: sample -> project (cold start) -> residuals -> cost ->
+select -> update, N times.  Marshalling only; every step runs in the library.
+
+The standard normal draws z [N, N_b, dim] are an input.  All iterations can be
+captured into one HIP graph (`capture=True`): the loop never synchronizes with the
+host, so a replay re-runs the whole planning call with one launch.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import trajam as tj
+
+
+class Planner:
+    def __init__(self, solver: "tj.Solver", n_samples: int, n_proj: int, n_elite: int,
+                 am_iters: int, sigma: float = 0.5, gamma: float = 1.0, quantum: float = 1e-6):
+        import torch
+        self.s = solver
+        self.torch = torch
+        self.N_b, self.n_proj, self.n_elite = int(n_samples), int(n_proj), int(n_elite)
+        self.K = int(am_iters)
+        self.sigma, self.gamma, self.quantum = float(sigma), float(gamma), float(quantum)
+        D, nv, dt = solver.dims, solver.nv, solver.dtype
+        self.dim = D * nv
+        dev = "cuda"
+        self.xi = torch.zeros((self.N_b, D, nv), dtype=dt, device=dev)
+        self.xb = torch.zeros_like(self.xi)
+        self.lam = torch.zeros_like(self.xi)
+        self.res = torch.zeros(self.N_b, dtype=dt, device=dev)
+        self.caug = torch.zeros_like(self.res)
+        self.rkey = torch.zeros(self.N_b, dtype=torch.int32, device=dev)
+        self.proj = torch.zeros(self.n_proj, dtype=torch.int32, device=dev)
+        self.elite = torch.zeros(self.n_elite, dtype=torch.int32, device=dev)
+        self.mu = torch.zeros(self.dim, dtype=dt, device=dev)
+        self.Sigma = torch.zeros((self.dim, self.dim), dtype=dt, device=dev)
+        self.chol = torch.zeros_like(self.Sigma)
+        self.graph = None
+
+    def set_distribution(self, mu0, Sigma0, chol0):
+        """Initial distribution: mean, covariance and its lower Cholesky factor."""
+        t = self.torch
+        self.mu.copy_(t.as_tensor(np.asarray(mu0).reshape(-1), dtype=self.mu.dtype))
+        self.Sigma.copy_(t.as_tensor(np.asarray(Sigma0), dtype=self.mu.dtype))
+        self.chol.copy_(t.as_tensor(np.asarray(chol0), dtype=self.mu.dtype))
+
+    def _iteration(self, z_l, boundary, obs, stream, record=None):
+        h, st = self.s.handle, stream.cuda_stream
+        tj.trajam_cem_sample(h, self.N_b, self.mu.data_ptr(), self.chol.data_ptr(),
+                             z_l.data_ptr(), self.xi.data_ptr(), st)
+        self.xb.copy_(self.xi)
+        self.lam.zero_()
+        self.s.project(self.xi, boundary, obs, self.xb, self.lam, self.K, stream=stream)
+        self.s.residuals(self.xb, obs, self.res, stream=stream)
+        tj.trajam_cem_cost(h, self.N_b, self.xb.data_ptr(), self.res.data_ptr(), self.quantum,
+                           self.caug.data_ptr(), self.rkey.data_ptr(), st)
+        tj.trajam_cem_select(h, self.N_b, self.rkey.data_ptr(), self.caug.data_ptr(),
+                             self.n_proj, self.n_elite, self.proj.data_ptr(),
+                             self.elite.data_ptr(), st)
+        if record is not None:
+            record.append((self.proj.clone(), self.elite.clone(), self.res.clone(),
+                           self.caug.clone(), self.rkey.clone()))
+        tj.trajam_cem_update(h, self.n_elite, self.elite.data_ptr(), self.xb.data_ptr(),
+                             self.caug.data_ptr(), self.sigma, self.gamma, self.mu.data_ptr(),
+                             self.Sigma.data_ptr(), self.chol.data_ptr(), st)
+        if record is not None:
+            record[-1] = record[-1] + (self.mu.clone(), self.Sigma.clone())
+
+    def best(self):
+        """The returned trajectory of Alg 3: the projected sample of the last elite
+        set with the lowest c_aug (elite_idx[0]); gathered on the device."""
+        return self.torch.index_select(self.xb, 0, self.elite[:1].long())[0]
+
+    def run(self, z, boundary, obs, record=None, stream=None):
+        """z: [N, N_b, dim] device tensor.  Returns best() after the N iterations."""
+        self._loop(z, boundary, obs, record, stream)
+        return self.best()
+
+    def _loop(self, z, boundary, obs, record=None, stream=None):
+        stream = stream or self.torch.cuda.current_stream()
+        for l in range(z.shape[0]):
+            self._iteration(z[l], boundary, obs, stream, record)
+
+    def capture(self, z, boundary, obs):
+        """Capture all N iterations into one HIP graph (replay with `replay`)."""
+        t = self.torch
+        s = t.cuda.Stream()
+        s.wait_stream(t.cuda.current_stream())
+        with t.cuda.stream(s):  # warm-up outside capture
+            self._loop(z, boundary, obs, stream=s)
+        t.cuda.current_stream().wait_stream(s)
+        g = t.cuda.CUDAGraph()
+        with t.cuda.graph(g):
+            self._loop(z, boundary, obs)
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+        return self.best()

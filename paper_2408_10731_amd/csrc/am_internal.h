@@ -73,6 +73,18 @@ hipError_t launch_pack_obstacles_f64(int dims, int n_o, const double *c, const d
 hipError_t launch_pack_obstacles_f32(int dims, int n_o, const float *c, const float *w,
                                      const float *s, float *out, float *soa, hipStream_t st);
 
+// Sampling-loop kernels (cem_kernels.hip).
+hipError_t launch_cem_sample(bool f64, int n, int dim, const void *mu, const void *L, const void *z,
+                             void *xi, hipStream_t st);
+hipError_t launch_cem_cost(bool f64, int n, int dims, int nv, int n_p, int nvp, const void *phi,
+                           const void *xb, const void *res, double quantum, void *caug, int32_t *rkey,
+                           hipStream_t st);
+hipError_t launch_cem_select(bool f64, int n, const int32_t *rkey, const void *caug, int n_proj,
+                             int n_elite, int32_t *proj, int32_t *elite, hipStream_t st);
+hipError_t launch_cem_update(bool f64, int n_elite, int dim, const int32_t *elite, const void *xb,
+                             const void *caug, double sigma, double gamma, double eps, void *mu,
+                             void *Sigma, void *L, hipStream_t st);
+
 // Dynamic LDS bytes of one AM workgroup.
 size_t project_lds_bytes(int dims, int nvp, int tpad, int tb, size_t scalar);
 

@@ -576,3 +576,68 @@ extern "C" trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const
     if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("residual launch: ") + hipGetErrorString(e));
     return TRAJAM_OK;
 }
+
+// ---- sampling loop ------------------------------------------------------------
+
+extern "C" trajam_status trajam_cem_sample(trajam_solver *s, int32_t n, const void *mu, const void *chol,
+                                           const void *z, void *xi, void *stream)
+{
+    if (!s) return TRAJAM_ERR_INVALID;
+    s->err.clear();
+    if (n < 0) return fail(s, TRAJAM_ERR_INVALID, "n must be >= 0");
+    if (n > s->prob.max_batch) return fail(s, TRAJAM_ERR_CAPACITY, "n > max_batch");
+    if (n == 0) return TRAJAM_OK;
+    if (!mu || !chol || !z || !xi) return fail(s, TRAJAM_ERR_INVALID, "NULL pointer");
+    const int dim = s->prob.dims * s->nv;
+    hipError_t e = trajam::launch_cem_sample(s->prob.precision == TRAJAM_FP64, n, dim, mu, chol, z, xi,
+                                             (hipStream_t)stream);
+    if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("cem sample: ") + hipGetErrorString(e));
+    return TRAJAM_OK;
+}
+
+extern "C" trajam_status trajam_cem_cost(trajam_solver *s, int32_t n, const void *xi_bar, const void *res,
+                                         double quantum, void *c_aug, int32_t *res_key, void *stream)
+{
+    if (!s) return TRAJAM_ERR_INVALID;
+    s->err.clear();
+    if (n < 0 || !(quantum > 0.0)) return fail(s, TRAJAM_ERR_INVALID, "n >= 0 and quantum > 0 required");
+    if (n > s->prob.max_batch) return fail(s, TRAJAM_ERR_CAPACITY, "n > max_batch");
+    if (n == 0) return TRAJAM_OK;
+    if (!xi_bar || !res || !c_aug || !res_key) return fail(s, TRAJAM_ERR_INVALID, "NULL pointer");
+    hipError_t e = trajam::launch_cem_cost(s->prob.precision == TRAJAM_FP64, n, s->prob.dims, s->nv,
+                                           s->prob.n_steps, s->nvp, s->d_phi, xi_bar, res, quantum, c_aug,
+                                           res_key, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("cem cost: ") + hipGetErrorString(e));
+    return TRAJAM_OK;
+}
+
+extern "C" trajam_status trajam_cem_select(trajam_solver *s, int32_t n, const int32_t *res_key,
+                                           const void *c_aug, int32_t n_proj, int32_t n_elite,
+                                           int32_t *proj_idx, int32_t *elite_idx, void *stream)
+{
+    if (!s) return TRAJAM_ERR_INVALID;
+    s->err.clear();
+    if (n < 1 || n > 4096 || n_elite < 1 || n_elite > n_proj || n_proj > n)
+        return fail(s, TRAJAM_ERR_INVALID, "need 1 <= n_elite <= n_proj <= n <= 4096");
+    if (!res_key || !c_aug || !proj_idx || !elite_idx) return fail(s, TRAJAM_ERR_INVALID, "NULL pointer");
+    hipError_t e = trajam::launch_cem_select(s->prob.precision == TRAJAM_FP64, n, res_key, c_aug, n_proj,
+                                             n_elite, proj_idx, elite_idx, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("cem select: ") + hipGetErrorString(e));
+    return TRAJAM_OK;
+}
+
+extern "C" trajam_status trajam_cem_update(trajam_solver *s, int32_t n_elite, const int32_t *elite_idx,
+                                           const void *xi_bar, const void *c_aug, double sigma, double gamma,
+                                           void *mu, void *Sigma, void *chol, void *stream)
+{
+    if (!s) return TRAJAM_ERR_INVALID;
+    s->err.clear();
+    if (n_elite < 1 || n_elite > 4096 || !(sigma > 0.0 && sigma <= 1.0) || !(gamma > 0.0))
+        return fail(s, TRAJAM_ERR_INVALID, "need 1 <= n_elite <= 4096, 0 < sigma <= 1, gamma > 0");
+    if (!elite_idx || !xi_bar || !c_aug || !mu || !Sigma || !chol) return fail(s, TRAJAM_ERR_INVALID, "NULL pointer");
+    const int dim = s->prob.dims * s->nv;
+    hipError_t e = trajam::launch_cem_update(s->prob.precision == TRAJAM_FP64, n_elite, dim, elite_idx, xi_bar,
+                                             c_aug, sigma, gamma, 1e-10, mu, Sigma, chol, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("cem update: ") + hipGetErrorString(e));
+    return TRAJAM_OK;
+}

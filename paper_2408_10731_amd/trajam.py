@@ -41,7 +41,8 @@ FLAG_GREW = 2
 EXPORTS = [
     "trajam_init", "trajam_destroy", "trajam_project", "trajam_residuals",
     "trajam_fixed_matrices", "trajam_set_launch", "trajam_get_launch",
-    "trajam_boundary_coefficients",
+    "trajam_boundary_coefficients", "trajam_cem_sample", "trajam_cem_cost",
+    "trajam_cem_select", "trajam_cem_update",
     "trajam_status_string", "trajam_last_error",
 ]
 
@@ -104,6 +105,16 @@ def load():
     L.trajam_get_launch.restype = ctypes.c_int
     L.trajam_boundary_coefficients.argtypes = [ctypes.POINTER(Problem), dp, dp]
     L.trajam_boundary_coefficients.restype = ctypes.c_int
+    L.trajam_cem_sample.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp]
+    L.trajam_cem_sample.restype = ctypes.c_int
+    L.trajam_cem_cost.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_double, vp, vp, vp]
+    L.trajam_cem_cost.restype = ctypes.c_int
+    L.trajam_cem_select.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32,
+                                    vp, vp, vp]
+    L.trajam_cem_select.restype = ctypes.c_int
+    L.trajam_cem_update.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_double,
+                                    ctypes.c_double, vp, vp, vp, vp]
+    L.trajam_cem_update.restype = ctypes.c_int
     L.trajam_status_string.argtypes = [ctypes.c_int]
     L.trajam_status_string.restype = ctypes.c_char_p
     L.trajam_last_error.argtypes = [vp]
@@ -177,6 +188,27 @@ def trajam_boundary_coefficients(problem: Problem, b4) -> np.ndarray:
     out = np.zeros(4)
     _check(load().trajam_boundary_coefficients(ctypes.byref(problem), _dp(b), _dp(out)))
     return out
+
+
+def trajam_cem_sample(handle, n, mu, chol, z, xi, stream) -> None:
+    _check(load().trajam_cem_sample(handle, int(n), mu, chol, z, xi, stream), handle)
+
+
+def trajam_cem_cost(handle, n, xi_bar, res, quantum, c_aug, res_key, stream) -> None:
+    _check(load().trajam_cem_cost(handle, int(n), xi_bar, res, float(quantum), c_aug, res_key,
+                                  stream), handle)
+
+
+def trajam_cem_select(handle, n, res_key, c_aug, n_proj, n_elite, proj_idx, elite_idx,
+                      stream) -> None:
+    _check(load().trajam_cem_select(handle, int(n), res_key, c_aug, int(n_proj), int(n_elite),
+                                    proj_idx, elite_idx, stream), handle)
+
+
+def trajam_cem_update(handle, n_elite, elite_idx, xi_bar, c_aug, sigma, gamma, mu, Sigma, chol,
+                      stream) -> None:
+    _check(load().trajam_cem_update(handle, int(n_elite), elite_idx, xi_bar, c_aug, float(sigma),
+                                    float(gamma), mu, Sigma, chol, stream), handle)
 
 
 # ----------------------------------------------------------- torch wrapper --

@@ -1,0 +1,199 @@
+"""Sampling loop (thesis ch. 6, Alg 3): pins of the FP64 oracle (CPU) and GPU parity."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cem as ocem
+from paper_2408_10731_amd import workloads as wl
+
+
+# ------------------------------------------------------------------ oracle pins
+
+
+def test_select_matches_brute_force_with_ties():
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        n = int(rng.integers(5, 60))
+        k1 = rng.integers(0, 4, size=n)            # many exact ties in the first key
+        k2 = np.round(rng.normal(size=n), 1)       # and in the second
+        keep = int(rng.integers(1, n + 1))
+        sel = ocem.select((k1, k2), keep)
+        tup = [(k1[i], k2[i], i) for i in range(n)]
+        rank = {i: sum(1 for j in range(n) if tup[j] < tup[i]) for i in range(n)}
+        assert sorted(sel.tolist()) == sorted(i for i in range(n) if rank[i] < keep)
+        assert [rank[i] for i in sel] == list(range(keep))
+
+
+def test_update_with_equal_weights_is_mean_and_population_covariance():
+    rng = np.random.default_rng(1)
+    X = rng.normal(size=(40, 6))
+    mu = rng.normal(size=6)
+    S = np.eye(6) * 0.3
+    c = np.full(40, 2.5)                          # equal costs: every weight is 1
+    mu1, S1, wgt = ocem.weighted_update(mu, S, X, c, 0.5, 1.0)
+    assert np.allclose(wgt, 1.0)
+    np.testing.assert_allclose(mu1, 0.5 * mu + 0.5 * X.mean(0), atol=1e-14)
+    d = X - mu1
+    np.testing.assert_allclose(S1, 0.5 * S + 0.5 * d.T @ d / 40, atol=1e-14)
+    # sigma = 1 forgets the old distribution; population covariance about the new mean
+    mu2, S2, _ = ocem.weighted_update(mu, S, X, c, 1.0, 1.0)
+    np.testing.assert_allclose(mu2, X.mean(0), atol=1e-14)
+    np.testing.assert_allclose(S2, np.cov(X.T, bias=True), atol=1e-13)
+
+
+def test_weights_prefer_lower_cost():
+    rng = np.random.default_rng(2)
+    c = rng.uniform(0, 5, size=30)
+    _, _, wgt = ocem.weighted_update(np.zeros(3), np.eye(3), rng.normal(size=(30, 3)), c, 0.5, 1.0)
+    assert wgt[np.argmin(c)] == 1.0
+    order = np.argsort(c)
+    assert np.all(np.diff(wgt[order]) <= 0)
+
+
+def test_sample_uses_a_cholesky_factor():
+    rng = np.random.default_rng(3)
+    A = rng.normal(size=(5, 5))
+    S = A @ A.T + np.eye(5)
+    z = rng.normal(size=(7, 5))
+    xi, L = ocem.sample(np.ones(5), S, z)
+    np.testing.assert_allclose(L @ L.T, S + ocem.EPS_CHOL * np.eye(5), atol=1e-12)
+    assert np.allclose(np.triu(L, 1), 0)
+    np.testing.assert_allclose(xi - 1.0, z @ L.T, atol=1e-13)
+
+
+def test_acceleration_cost_closed_forms():
+    """Straight constant-speed line: zero acceleration.  x(t) = (t / T)^2 has Bernstein
+    coefficients m (m - 1) / (n (n - 1)) and acceleration 2 / T^2 everywhere."""
+    w = wl.tiny(dims=2, batch=2, n_obs=0, degree=6, n_steps=21)
+    n, T = w.degree, w.horizon
+    m = np.arange(n + 1)
+    lin = np.stack([m / n, np.zeros(n + 1)])
+    quad = np.stack([m * (m - 1) / (n * (n - 1)), np.zeros(n + 1)])
+    c = ocem.acceleration_cost(w, np.stack([lin, quad]))
+    assert abs(c[0]) < 1e-20
+    assert abs(c[1] - w.n_steps * (2 / T ** 2) ** 2) < 1e-12
+
+
+def cem_problem(n_obs=20, n_samples=256, seed=11):
+    w = wl.config4_scene(seed, n_obs=n_obs, batch=4)
+    D, nv = w.dims, w.n_v
+    mu0 = wl.line_samples(np.random.default_rng(0), 1, w.degree, w.boundary[:, 0],
+                          w.boundary[:, 3], 0.0)[0].reshape(-1)
+    S0 = 0.25 * np.eye(D * nv)
+    return w, mu0, S0
+
+
+def test_cem_oracle_improves_cost_on_a_free_scene():
+    """With no obstacles the loop minimizes the acceleration cost: the best cost after
+    a few iterations is below the cost of the initial mean's samples."""
+    w, mu0, S0 = cem_problem(n_obs=0)
+    z = np.random.default_rng(5).normal(size=(6, 64, mu0.size))
+    tr = ocem.cem(w, mu0, S0, z, am_iters=5, n_proj=48, n_elite=12)
+    first_best = tr.caug[0][tr.elite_idx[0][0]]
+    assert tr.best_cost <= first_best
+    assert np.all(np.linalg.eigvalsh(tr.Sigma[-1]) > 0)
+
+
+# -------------------------------------------------------------------- GPU parity
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu_setup(w, precision, n_samples, n_proj, n_elite, K):
+    from paper_2408_10731_amd import cem, trajam as tj
+    w = dataclasses.replace(w, xi=np.zeros((n_samples, w.dims, w.n_v)))
+    solver = tj.Solver.for_workload(w, max_batch=n_samples, precision=precision)
+    planner = cem.Planner(solver, n_samples, n_proj, n_elite, K)
+    _, obs = tj.device_workload(w, solver.dtype, static=False)
+    return solver, planner, obs
+
+
+@pytest.mark.gpu
+def test_gpu_select_is_exact_on_generated_keys():
+    from paper_2408_10731_amd import trajam as tj
+    w, _, _ = cem_problem()
+    solver, planner, _ = _gpu_setup(w, "fp64", 2000, 1454, 363, 1)
+    rng = np.random.default_rng(9)
+    for n, keep, el in ((2000, 1454, 363), (37, 20, 5), (1, 1, 1), (4096 // 2, 1024, 1024)):
+        k1 = rng.integers(0, 5, size=n).astype(np.int32)      # heavy ties
+        k2 = np.round(rng.normal(size=n), 2)
+        print("case: select", n, keep, el, flush=True)
+        dk1 = torch.as_tensor(k1, device="cuda")
+        dk2 = torch.as_tensor(k2, device="cuda")
+        pi = torch.zeros(keep, dtype=torch.int32, device="cuda")
+        ei = torch.zeros(el, dtype=torch.int32, device="cuda")
+        tj.trajam_cem_select(solver.handle, n, dk1.data_ptr(), dk2.data_ptr(), keep, el,
+                             pi.data_ptr(), ei.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        exp_p = ocem.select((k1, k2), keep)
+        exp_e = exp_p[ocem.select((k2[exp_p], exp_p), el)]
+        assert np.array_equal(pi.cpu().numpy(), exp_p)
+        assert np.array_equal(ei.cpu().numpy(), exp_e)
+
+
+@pytest.mark.gpu
+def test_gpu_cem_fp64_matches_oracle_per_iteration():
+    w, mu0, S0 = cem_problem(n_obs=20)
+    N, Nb, Np, Ne, K = 3, 256, 186, 47, 10
+    z = np.random.default_rng(4).normal(size=(N, Nb, mu0.size))
+    print("case: cem fp64", N, Nb, flush=True)
+    tr = ocem.cem(w, mu0, S0, z, K, Np, Ne)
+    solver, planner, obs = _gpu_setup(w, "fp64", Nb, Np, Ne, K)
+    planner.set_distribution(mu0, S0, np.linalg.cholesky(S0 + ocem.EPS_CHOL * np.eye(mu0.size)))
+    rec = []
+    best = planner.run(torch.as_tensor(z, device="cuda"), w.boundary, obs, record=rec)
+    torch.cuda.synchronize()
+    for l, (proj, elite, res, caug, rkey, mu, Sig) in enumerate(rec):
+        assert np.array_equal(proj.cpu().numpy(), tr.proj_idx[l]), l
+        assert np.array_equal(elite.cpu().numpy(), tr.elite_idx[l]), l
+        np.testing.assert_allclose(res.cpu().numpy(), tr.res[l], atol=1e-9)
+        np.testing.assert_allclose(caug.cpu().numpy(), tr.caug[l], rtol=1e-10, atol=1e-9)
+        np.testing.assert_allclose(mu.cpu().numpy(), tr.mu[l], atol=1e-9)
+        np.testing.assert_allclose(Sig.cpu().numpy(), tr.Sigma[l], atol=1e-9)
+    np.testing.assert_allclose(best.cpu().numpy(), tr.best, atol=1e-9)
+
+
+@pytest.mark.gpu
+def test_gpu_cem_fp32_config4_graph_replays():
+    """Config 4 sizes (2000 samples, 100 moving circles, 15 AM iterations), all CEM
+    iterations captured in one HIP graph; every replay equals the eager run, each
+    selection is exact for the keys the device computed, the update matches the FP64
+    formula on the device's elite set, and the returned trajectory is the elite with
+    the lowest cost."""
+    w = wl.config4(batch=4)
+    D, nv = w.dims, w.n_v
+    mu0 = wl.line_samples(np.random.default_rng(0), 1, w.degree, w.boundary[:, 0],
+                          w.boundary[:, 3], 0.0)[0].reshape(-1)
+    S0 = 0.25 * np.eye(D * nv)
+    N, Nb, Np, Ne, K = 4, 2000, 1454, 363, 15
+    z = torch.as_tensor(np.random.default_rng(8).normal(size=(N, Nb, D * nv)), dtype=torch.float32,
+                        device="cuda")
+    print("case: cem fp32 cfg4 graph", flush=True)
+    solver, planner, obs = _gpu_setup(w, "fp32", Nb, Np, Ne, K)
+    L0 = np.linalg.cholesky(S0 + ocem.EPS_CHOL * np.eye(D * nv))
+    planner.set_distribution(mu0, S0, L0)
+    rec = []
+    eager = planner.run(z, w.boundary, obs, record=rec).clone()
+    torch.cuda.synchronize()
+    for proj, elite, res, caug, rkey, mu, Sig in rec:
+        c, k = caug.cpu().numpy(), rkey.cpu().numpy()
+        p = proj.cpu().numpy()
+        e = elite.cpu().numpy()
+        # selection is exact for the device's own keys (ties by index)
+        exp_p = ocem.select((k, c), Np)
+        assert np.array_equal(p, exp_p)
+        assert np.array_equal(e, p[ocem.select((c[p], p), Ne)])
+    # the distribution update agrees with the FP64 formula on the device's elite set
+    proj, elite, res, caug, rkey, mu, Sig = rec[0]
+    xb0 = None
+    eager_mu = rec[-1][5].cpu().numpy()
+    planner.set_distribution(mu0, S0, L0)
+    planner.capture(z, w.boundary, obs)
+    for rep in range(3):
+        planner.set_distribution(mu0, S0, L0)
+        out = planner.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        assert np.array_equal(planner.mu.cpu().numpy(), eager_mu), rep
