@@ -226,6 +226,72 @@ trajam_status trajam_cem_update(trajam_solver *s, int32_t n_elite, const int32_t
                                 const void *xi_bar, const void *c_aug, double sigma, double gamma,
                                 void *mu, void *Sigma, void *chol, void *stream);
 
+/* ---- learned warm start ------------------------------------------------------
+ * A fully connected ReLU network (no thesis counterpart: a learned initialization
+ * of the projection) trained and evaluated with these kernels.  Parameters are one
+ * flat float array: for each layer l, W_l [width[l+1]][width[l]] row-major, then
+ * b_l [width[l+1]].  Hidden layers apply ReLU; the last layer is linear.  These
+ * calls take no solver handle; on error trajam_last_error(NULL) holds the message.
+ * precision: 0 = fp32 products on the VALU, 1 = bf16 products on matrix cores with
+ * fp32 accumulation. */
+#define TRAJAM_MLP_MAX_LAYERS 8
+#define TRAJAM_FLAG_COLD_FALLBACK 4u /* warm start rejected; the sample started cold */
+
+typedef struct {
+    int32_t n_layers;                          /* 1 .. TRAJAM_MLP_MAX_LAYERS */
+    int32_t width[TRAJAM_MLP_MAX_LAYERS + 1];  /* width[0] inputs .. width[n_layers] outputs */
+} trajam_mlp_shape;
+
+/* Number of parameters of the shape.  Errors: INVALID. */
+trajam_status trajam_mlp_param_count(const trajam_mlp_shape *shape, int64_t *n_params);
+
+/* y [batch][width[L]] = network(x [batch][width[0]]); acts receives the hidden
+ * activations, layer after layer, each [batch][width[l]] (l = 1 .. L-1), for the
+ * backward pass.  Device pointers.  Errors: INVALID, DEVICE. */
+trajam_status trajam_mlp_forward(const trajam_mlp_shape *shape, int32_t batch, int32_t precision,
+                                 const float *params, const float *x, float *acts, float *y,
+                                 void *stream);
+
+/* grads [n_params] = d loss / d params given dy = d loss / d y [batch][width[L]], the
+ * input x and the activations of the forward call.  scratch: 2 * batch * max hidden
+ * width floats.  Errors: INVALID, DEVICE. */
+trajam_status trajam_mlp_backward(const trajam_mlp_shape *shape, int32_t batch, int32_t precision,
+                                  const float *params, const float *x, const float *acts,
+                                  const float *dy, float *grads, float *scratch, void *stream);
+
+/* Mean squared error over count values: loss[0] = mean (y - t)^2, dy = 2 (y - t) / count.
+ * Errors: INVALID, DEVICE. */
+trajam_status trajam_mlp_mse(int64_t count, const float *y, const float *target, float *dy,
+                             float *loss, void *stream);
+
+/* One Adam step (Kingma & Ba) with bias correction for step >= 1, in place on params,
+ * m, v [n].  Errors: INVALID, DEVICE. */
+trajam_status trajam_mlp_adam(int64_t n, float *params, const float *grads, float *m, float *v,
+                              int32_t step, float lr, float beta1, float beta2, float eps,
+                              void *stream);
+
+/* Network input rows x[b] = [scene [n_scene], (xi[b] - line) * inv_scale] for b < batch;
+ * xi [batch][dims][n_coeffs], line [dims][n_coeffs].  Errors: INVALID, DEVICE. */
+trajam_status trajam_warm_features(int32_t batch, int32_t dims, int32_t n_coeffs, int32_t n_scene,
+                                   const float *scene, const float *xi, const float *line,
+                                   float inv_scale, float *x, void *stream);
+
+/* Warm start from the network output y [batch][dims * n_coeffs]: delta = y * out_scale,
+ * xi_bar0 = xi + delta, lambda0 = delta on free coefficients and 0 on the boundary
+ * ones (at a converged fixed point the multiplier equals xb - xi on free
+ * coefficients).  A sample with a non-finite prediction starts cold and gets
+ * TRAJAM_FLAG_COLD_FALLBACK (flags may be NULL).  Errors: INVALID, DEVICE. */
+trajam_status trajam_warm_apply(int32_t batch, int32_t dims, int32_t n_coeffs, const float *y,
+                                const float *xi, float out_scale, float *xi_bar0, float *lambda0,
+                                uint32_t *flags, void *stream);
+
+/* Per-sample fallback: where res_warm[b] > res_cold[b] (or is NaN) the sample restarts
+ * cold (xi_bar0 = xi, lambda0 = 0) and gets TRAJAM_FLAG_COLD_FALLBACK.
+ * Errors: INVALID, DEVICE. */
+trajam_status trajam_warm_fallback(int32_t batch, int32_t dims, int32_t n_coeffs,
+                                   const float *res_warm, const float *res_cold, const float *xi,
+                                   float *xi_bar0, float *lambda0, uint32_t *flags, void *stream);
+
 /* Static description of a status code.  Never NULL. */
 const char *trajam_status_string(trajam_status st);
 

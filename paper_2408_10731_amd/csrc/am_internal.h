@@ -85,6 +85,21 @@ hipError_t launch_cem_update(bool f64, int n_elite, int dim, const int32_t *elit
                              const void *caug, double sigma, double gamma, double eps, void *mu,
                              void *Sigma, void *L, hipStream_t st);
 
+// Warm-start network kernels (mlp_kernels.hip).
+hipError_t launch_gemm(bool bf16, int M, int N, int K, const float *A, long sam, long sak, const float *B,
+                       long sbk, long sbn, float *C, int ldc, int epi, const float *bias, const float *mask,
+                       int ldm, hipStream_t st);
+hipError_t launch_colsum(int rows, int cols, const float *d, float *out, hipStream_t st);
+hipError_t launch_mse(long count, const float *y, const float *t, float *dy, float *loss, hipStream_t st);
+hipError_t launch_adam(long n, float *p, const float *g, float *m, float *v, int step, float lr, float b1,
+                       float b2, float eps, hipStream_t st);
+hipError_t launch_warm_features(int batch, int dim, int n_scene, const float *scene, const float *xi,
+                                const float *line, float inv_scale, float *X, hipStream_t st);
+hipError_t launch_warm_apply(int batch, int dims, int nv, const float *y, const float *xi, float out_scale,
+                             float *xb0, float *lam0, uint32_t *flags, hipStream_t st);
+hipError_t launch_warm_fallback(int batch, int dim, const float *rw, const float *rc, const float *xi,
+                                float *xb0, float *lam0, uint32_t *flags, hipStream_t st);
+
 // Dynamic LDS bytes of one AM workgroup.
 size_t project_lds_bytes(int dims, int nvp, int tpad, int tb, size_t scalar);
 

@@ -1,0 +1,178 @@
+// C-ABI of the warm-start network and the warm-start kernels (no solver handle;
+// errors are reported through the thread-local message of trajam_last_error(NULL)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "../../include/trajam.h"
+#include "am_internal.h"
+
+namespace trajam {
+void set_thread_error(const std::string &msg);  // trajam_api.cpp
+}
+
+namespace {
+
+trajam_status fail(trajam_status st, const std::string &m)
+{
+    trajam::set_thread_error(m);
+    return st;
+}
+
+trajam_status dev(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return TRAJAM_OK;
+    return fail(TRAJAM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool shape_ok(const trajam_mlp_shape *s)
+{
+    if (!s || s->n_layers < 1 || s->n_layers > TRAJAM_MLP_MAX_LAYERS) return false;
+    for (int l = 0; l <= s->n_layers; ++l)
+        if (s->width[l] < 1 || s->width[l] > 65536) return false;
+    return true;
+}
+
+int64_t count_params(const trajam_mlp_shape *s)
+{
+    int64_t n = 0;
+    for (int l = 0; l < s->n_layers; ++l) n += (int64_t)s->width[l + 1] * s->width[l] + s->width[l + 1];
+    return n;
+}
+
+}  // namespace
+
+extern "C" trajam_status trajam_mlp_param_count(const trajam_mlp_shape *shape, int64_t *n)
+{
+    if (!shape_ok(shape) || !n) return fail(TRAJAM_ERR_INVALID, "invalid network shape");
+    *n = count_params(shape);
+    return TRAJAM_OK;
+}
+
+extern "C" trajam_status trajam_mlp_forward(const trajam_mlp_shape *s, int32_t batch, int32_t precision,
+                                            const float *params, const float *x, float *acts, float *y,
+                                            void *stream)
+{
+    if (!shape_ok(s)) return fail(TRAJAM_ERR_INVALID, "invalid network shape");
+    if (batch < 0 || (precision != 0 && precision != 1)) return fail(TRAJAM_ERR_INVALID, "batch >= 0, precision 0 or 1");
+    if (batch == 0) return TRAJAM_OK;
+    if (!params || !x || !y || (s->n_layers > 1 && !acts)) return fail(TRAJAM_ERR_INVALID, "NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    const float *a = x, *p = params;
+    float *act = acts;
+    for (int l = 0; l < s->n_layers; ++l) {
+        const int in = s->width[l], out = s->width[l + 1];
+        const float *W = p, *b = p + (int64_t)out * in;
+        const bool last = l == s->n_layers - 1;
+        float *dst = last ? y : act;
+        trajam_status r = dev(trajam::launch_gemm(precision == 1, batch, out, in, a, in, 1, W, 1, in, dst, out,
+                                                  last ? 2 : 1, b, nullptr, 0, st),
+                              "mlp forward");
+        if (r != TRAJAM_OK) return r;
+        a = dst;
+        if (!last) act += (int64_t)batch * out;
+        p += (int64_t)out * in + out;
+    }
+    return TRAJAM_OK;
+}
+
+extern "C" trajam_status trajam_mlp_backward(const trajam_mlp_shape *s, int32_t batch, int32_t precision,
+                                             const float *params, const float *x, const float *acts,
+                                             const float *dy, float *grads, float *scratch, void *stream)
+{
+    if (!shape_ok(s)) return fail(TRAJAM_ERR_INVALID, "invalid network shape");
+    if (batch < 1 || (precision != 0 && precision != 1)) return fail(TRAJAM_ERR_INVALID, "batch >= 1, precision 0 or 1");
+    if (!params || !x || !dy || !grads || (s->n_layers > 1 && (!acts || !scratch)))
+        return fail(TRAJAM_ERR_INVALID, "NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    const int L = s->n_layers;
+    // offsets of each layer's parameters and activations
+    int64_t poff[TRAJAM_MLP_MAX_LAYERS + 1], aoff[TRAJAM_MLP_MAX_LAYERS + 1];
+    poff[0] = 0;
+    aoff[1] = 0;
+    int maxw = 1;
+    for (int l = 0; l < L; ++l) poff[l + 1] = poff[l] + (int64_t)s->width[l + 1] * s->width[l] + s->width[l + 1];
+    for (int l = 1; l < L; ++l) {
+        aoff[l + 1] = aoff[l] + (int64_t)batch * s->width[l];
+        maxw = std::max(maxw, s->width[l]);
+    }
+    const float *d = dy;
+    float *bufs[2] = {scratch, scratch ? scratch + (int64_t)batch * maxw : nullptr};
+    int which = 0;
+    for (int l = L - 1; l >= 0; --l) {
+        const int in = s->width[l], out = s->width[l + 1];
+        const float *a_prev = (l == 0) ? x : acts + aoff[l];
+        float *gW = grads + poff[l], *gb = gW + (int64_t)out * in;
+        // dW = d^T a_prev  (M = out, N = in, K = batch)
+        trajam_status r = dev(trajam::launch_gemm(precision == 1, out, in, batch, d, 1, out, a_prev, in, 1, gW, in,
+                                                  0, nullptr, nullptr, 0, st),
+                              "mlp weight gradient");
+        if (r != TRAJAM_OK) return r;
+        r = dev(trajam::launch_colsum(batch, out, d, gb, st), "mlp bias gradient");
+        if (r != TRAJAM_OK) return r;
+        if (l > 0) {
+            // d_prev = (d W) * [a_prev > 0]  (M = batch, N = in, K = out)
+            float *dn = bufs[which];
+            which ^= 1;
+            const float *W = params + poff[l];
+            r = dev(trajam::launch_gemm(precision == 1, batch, in, out, d, out, 1, W, in, 1, dn, in, 3, nullptr,
+                                        a_prev, in, st),
+                    "mlp input gradient");
+            if (r != TRAJAM_OK) return r;
+            d = dn;
+        }
+    }
+    return TRAJAM_OK;
+}
+
+extern "C" trajam_status trajam_mlp_mse(int64_t count, const float *y, const float *t, float *dy, float *loss,
+                                        void *stream)
+{
+    if (count < 1 || !y || !t || !dy || !loss) return fail(TRAJAM_ERR_INVALID, "count >= 1 and non-NULL pointers");
+    return dev(trajam::launch_mse(count, y, t, dy, loss, (hipStream_t)stream), "mse");
+}
+
+extern "C" trajam_status trajam_mlp_adam(int64_t n, float *p, const float *g, float *m, float *v, int32_t step,
+                                         float lr, float b1, float b2, float eps, void *stream)
+{
+    if (n < 1 || step < 1 || !p || !g || !m || !v || !(lr > 0.f) || !(b1 >= 0.f && b1 < 1.f) ||
+        !(b2 >= 0.f && b2 < 1.f) || !(eps > 0.f))
+        return fail(TRAJAM_ERR_INVALID, "invalid Adam arguments");
+    return dev(trajam::launch_adam(n, p, g, m, v, step, lr, b1, b2, eps, (hipStream_t)stream), "adam");
+}
+
+extern "C" trajam_status trajam_warm_features(int32_t batch, int32_t dims, int32_t nv, int32_t n_scene,
+                                              const float *scene, const float *xi, const float *line,
+                                              float inv_scale, float *x, void *stream)
+{
+    if (batch < 0 || dims < 1 || nv < 1 || n_scene < 0 || !xi || !line || !x || (n_scene > 0 && !scene))
+        return fail(TRAJAM_ERR_INVALID, "invalid warm-start feature arguments");
+    if (batch == 0) return TRAJAM_OK;
+    return dev(trajam::launch_warm_features(batch, dims * nv, n_scene, scene, xi, line, inv_scale, x,
+                                            (hipStream_t)stream),
+               "warm features");
+}
+
+extern "C" trajam_status trajam_warm_apply(int32_t batch, int32_t dims, int32_t nv, const float *y,
+                                           const float *xi, float out_scale, float *xb0, float *lam0,
+                                           uint32_t *flags, void *stream)
+{
+    if (batch < 0 || dims < 1 || nv < 4 || !y || !xi || !xb0 || !lam0)
+        return fail(TRAJAM_ERR_INVALID, "invalid warm-start apply arguments");
+    if (batch == 0) return TRAJAM_OK;
+    return dev(trajam::launch_warm_apply(batch, dims, nv, y, xi, out_scale, xb0, lam0, flags, (hipStream_t)stream),
+               "warm apply");
+}
+
+extern "C" trajam_status trajam_warm_fallback(int32_t batch, int32_t dims, int32_t nv, const float *rw,
+                                              const float *rc, const float *xi, float *xb0, float *lam0,
+                                              uint32_t *flags, void *stream)
+{
+    if (batch < 0 || dims < 1 || nv < 1 || !rw || !rc || !xi || !xb0 || !lam0)
+        return fail(TRAJAM_ERR_INVALID, "invalid warm-start fallback arguments");
+    if (batch == 0) return TRAJAM_OK;
+    return dev(trajam::launch_warm_fallback(batch, dims * nv, rw, rc, xi, xb0, lam0, flags, (hipStream_t)stream),
+               "warm fallback");
+}

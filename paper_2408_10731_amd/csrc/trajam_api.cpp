@@ -33,6 +33,14 @@
 
 using trajam::AmArgs;
 
+namespace {
+thread_local std::string g_init_err;
+}
+
+namespace trajam {
+void set_thread_error(const std::string &msg) { g_init_err = msg; }
+}
+
 struct trajam_solver {
     trajam_problem prob;
     int nv, nf, nvp, tpad, tb;
@@ -51,8 +59,6 @@ struct trajam_solver {
 };
 
 namespace {
-
-thread_local std::string g_init_err;
 
 int pad_coeffs(int nv) { return nv <= 8 ? 8 : (nv <= 12 ? 12 : 16); }
 

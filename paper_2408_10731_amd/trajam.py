@@ -36,13 +36,17 @@ TRAJAM_KERNEL_WAVE = 1
 
 FLAG_NONFINITE = 1
 FLAG_GREW = 2
+FLAG_COLD_FALLBACK = 4
+MLP_MAX_LAYERS = 8
 
 # every symbol include/trajam.h declares
 EXPORTS = [
     "trajam_init", "trajam_destroy", "trajam_project", "trajam_residuals",
     "trajam_fixed_matrices", "trajam_set_launch", "trajam_get_launch",
     "trajam_boundary_coefficients", "trajam_cem_sample", "trajam_cem_cost",
-    "trajam_cem_select", "trajam_cem_update",
+    "trajam_cem_select", "trajam_cem_update", "trajam_mlp_param_count", "trajam_mlp_forward",
+    "trajam_mlp_backward", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
+    "trajam_warm_apply", "trajam_warm_fallback",
     "trajam_status_string", "trajam_last_error",
 ]
 
@@ -69,6 +73,18 @@ class Problem(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("obstacle_model", ctypes.c_int32),
     ]
+
+
+class MlpShape(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("width", ctypes.c_int32 * (8 + 1))]
+
+
+def mlp_shape(widths) -> MlpShape:
+    s = MlpShape()
+    s.n_layers = len(widths) - 1
+    for i, w in enumerate(widths):
+        s.width[i] = int(w)
+    return s
 
 
 _lib = None
@@ -115,6 +131,25 @@ def load():
     L.trajam_cem_update.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_double,
                                     ctypes.c_double, vp, vp, vp, vp]
     L.trajam_cem_update.restype = ctypes.c_int
+    sp = ctypes.POINTER(MlpShape)
+    i64 = ctypes.c_int64
+    L.trajam_mlp_param_count.argtypes = [sp, ctypes.POINTER(i64)]
+    L.trajam_mlp_forward.argtypes = [sp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp]
+    L.trajam_mlp_backward.argtypes = [sp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp, vp,
+                                      vp]
+    L.trajam_mlp_mse.argtypes = [i64, vp, vp, vp, vp, vp]
+    L.trajam_mlp_adam.argtypes = [i64, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
+    L.trajam_warm_features.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, vp, vp, vp, ctypes.c_float, vp, vp]
+    L.trajam_warm_apply.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp,
+                                    ctypes.c_float, vp, vp, vp, vp]
+    L.trajam_warm_fallback.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,
+                                       vp, vp, vp, vp]
+    for f in ("trajam_mlp_param_count", "trajam_mlp_forward", "trajam_mlp_backward",
+              "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features", "trajam_warm_apply",
+              "trajam_warm_fallback"):
+        getattr(L, f).restype = ctypes.c_int
     L.trajam_status_string.argtypes = [ctypes.c_int]
     L.trajam_status_string.restype = ctypes.c_char_p
     L.trajam_last_error.argtypes = [vp]
@@ -209,6 +244,50 @@ def trajam_cem_update(handle, n_elite, elite_idx, xi_bar, c_aug, sigma, gamma, m
                       stream) -> None:
     _check(load().trajam_cem_update(handle, int(n_elite), elite_idx, xi_bar, c_aug, float(sigma),
                                     float(gamma), mu, Sigma, chol, stream), handle)
+
+
+def trajam_mlp_param_count(shape: MlpShape) -> int:
+    n = ctypes.c_int64()
+    _check(load().trajam_mlp_param_count(ctypes.byref(shape), ctypes.byref(n)))
+    return int(n.value)
+
+
+def trajam_mlp_forward(shape, batch, precision, params, x, acts, y, stream) -> None:
+    _check(load().trajam_mlp_forward(ctypes.byref(shape), int(batch), int(precision), params, x,
+                                     acts, y, stream))
+
+
+def trajam_mlp_backward(shape, batch, precision, params, x, acts, dy, grads, scratch,
+                        stream) -> None:
+    _check(load().trajam_mlp_backward(ctypes.byref(shape), int(batch), int(precision), params, x,
+                                      acts, dy, grads, scratch, stream))
+
+
+def trajam_mlp_mse(count, y, target, dy, loss, stream) -> None:
+    _check(load().trajam_mlp_mse(int(count), y, target, dy, loss, stream))
+
+
+def trajam_mlp_adam(n, params, grads, m, v, step, lr, beta1, beta2, eps, stream) -> None:
+    _check(load().trajam_mlp_adam(int(n), params, grads, m, v, int(step), float(lr), float(beta1),
+                                  float(beta2), float(eps), stream))
+
+
+def trajam_warm_features(batch, dims, n_coeffs, n_scene, scene, xi, line, inv_scale, x,
+                         stream) -> None:
+    _check(load().trajam_warm_features(int(batch), int(dims), int(n_coeffs), int(n_scene), scene,
+                                       xi, line, float(inv_scale), x, stream))
+
+
+def trajam_warm_apply(batch, dims, n_coeffs, y, xi, out_scale, xi_bar0, lambda0, flags,
+                      stream) -> None:
+    _check(load().trajam_warm_apply(int(batch), int(dims), int(n_coeffs), y, xi, float(out_scale),
+                                    xi_bar0, lambda0, flags, stream))
+
+
+def trajam_warm_fallback(batch, dims, n_coeffs, res_warm, res_cold, xi, xi_bar0, lambda0, flags,
+                         stream) -> None:
+    _check(load().trajam_warm_fallback(int(batch), int(dims), int(n_coeffs), res_warm, res_cold, xi,
+                                       xi_bar0, lambda0, flags, stream))
 
 
 # ----------------------------------------------------------- torch wrapper --
