@@ -51,6 +51,175 @@ def median_time_to_residual(trace: np.ndarray, tol: float = 1e-3):
     return (int(hit[0]) if hit.size else None), med
 
 
+def _graph(fn):
+    """Capture fn() (after a warm-up run on a side stream) into a graph."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return g
+
+
+def _time(fn, reps, stream):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def train_warm_start(w, scenes, epochs, seed0=20_000, batch=1024):
+    """Network of the learned warm start, trained on the GPU on solver-generated scenes
+    of the workload's family (seeds disjoint from the benchmark scene's)."""
+    import torch
+    from paper_2408_10731_amd import warmstart as ws
+    t0 = time.perf_counter()
+    k_obs = w.n_obs
+    data = ws.generate(ws.family_scene("cfg2"), list(range(seed0, seed0 + scenes)), 256, k_obs,
+                       iters=300)
+    net = ws.Net(ws.widths_for(w, k_obs), seed=0, precision=0, max_batch=max(batch, w.batch))
+    curve = ws.train(net, data, epochs=epochs, batch=batch, lr=1e-3)
+    torch.cuda.synchronize()
+    info = {"pairs": int(data.x.shape[0]), "scenes": scenes, "epochs": epochs,
+            "loss_first": curve[0], "loss_last": curve[-1],
+            "seconds": time.perf_counter() - t0}
+    return net, info
+
+
+def time_to_residual(args, w, solver, xi, obs, stream, tol=1e-3, net=None, info=None):
+    """Iterations and time until the batch-median residual first reaches tol, from a
+    cold start and from the learned warm start.  Times are per replay of a captured
+    graph (cold: resets + projection; warm: features, network, apply, two residual
+    launches, fallback + projection), and the same work launched eagerly."""
+    import torch
+    from paper_2408_10731_amd import warmstart as ws
+
+    cap = args.ttr_cap
+    out = {"tol": tol, "cap": cap}
+    tr = torch.zeros((cap, w.batch), dtype=torch.float32, device="cuda")
+    xb, lam = xi.clone(), torch.zeros_like(xi)
+    solver.project(xi, w.boundary, obs, xb, lam, cap, res_trace=tr)
+    torch.cuda.synchronize()
+    hit, _ = median_time_to_residual(tr.cpu().numpy(), tol)
+    out["cold_iters"] = None if hit is None else hit + 1
+    if net is None:
+        net, info = train_warm_start(w, args.ws_scenes, args.ws_epochs)
+    out["warm_training"] = info
+    ctx = ws.WarmContext(solver, net, w, w.n_obs, w.batch)
+    xb0, lam0, fl = ctx.run(xi, obs)
+    trw = torch.zeros_like(tr)
+    solver.project(xi, w.boundary, obs, xb0, lam0, cap, res_trace=trw)
+    torch.cuda.synchronize()
+    hw, _ = median_time_to_residual(trw.cpu().numpy(), tol)
+    out["warm_iters"] = None if hw is None else hw + 1
+    out["warm_fallbacks"] = int(((fl.cpu().numpy() & 4) != 0).sum())
+    reps = 20
+    if hit is not None:
+        def cold():
+            xb.copy_(xi)
+            lam.zero_()
+            solver.project(xi, w.boundary, obs, xb, lam, hit + 1)
+        out["cold_ms_eager"] = _time(cold, reps, stream)
+        g = _graph(cold)
+        out["cold_ms"] = _time(g.replay, reps, stream)
+        del g
+    if hw is not None:
+        def warm():
+            b0, l0, _ = ctx.run(xi, obs)
+            solver.project(xi, w.boundary, obs, b0, l0, hw + 1)
+        out["warm_ms_eager"] = _time(warm, reps, stream)
+        g = _graph(warm)
+        out["warm_ms"] = _time(g.replay, reps, stream)
+        del g
+    return out
+
+
+def ragged_bench(args):
+    """Many independent problems in one persistent launch: n_obs ~ U{5..300}, batch ~
+    U{32..2048}; even problems are 2D (config-2 geometry), odd ones 3D single-robot
+    sphere problems (degree 10, 100 steps).  Times the eager launch and the same launch
+    replayed from a captured graph; reports traj-iters/s over the whole set."""
+    import torch
+    from paper_2408_10731_amd import trajam as tj
+    from paper_2408_10731_amd import workloads as wl
+
+    ws = wl.ragged_set(args.ragged_problems, iters=args.iters)
+    K = args.iters
+    solvers, items, keep = [], [], []
+    for w in ws:
+        s = tj.Solver.for_workload(w, precision="fp32")
+        xi, obs = tj.device_workload(w, torch.float32)
+        s.set_obstacles(obs)
+        xb, lam = xi.clone(), torch.zeros_like(xi)
+        solvers.append(s)
+        items.append((s, xi, w.boundary, xb, lam))
+        keep.append((xi, xb, lam))
+    plan = tj.RaggedPlan(items, K)
+    stream = torch.cuda.current_stream()
+
+    def reset():
+        for xi, xb, lam in keep:
+            xb.copy_(xi)
+            lam.zero_()
+
+    reset()
+    plan.launch()
+    torch.cuda.synchronize()
+    launch_ms = []
+    for _ in range(args.ragged_steps):
+        reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        launch_ms.append(e0.elapsed_time(e1))
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        reset()
+        plan.launch()
+    stream.wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        reset()
+        plan.launch()
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.ragged_steps):
+        g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / args.ragged_steps
+    samples = sum(w.batch for w in ws)
+    ops = sum(algorithmic_ops_per_traj_iter(w) * w.batch for w in ws) * K
+    kern = float(np.mean(launch_ms))
+    out = {"problems": len(ws), "samples": samples, "iterations": K,
+           "launch_ms": kern, "graph_step_ms": graph_ms,
+           "traj_iters_per_s": samples * K / (graph_ms * 1e-3),
+           "alu_frac": ops / (kern * 1e-3) / PEAK_VALU_OPS,
+           "mix": "even problems 2D (config-2 geometry), odd 3D single robot; "
+                  "n_obs~U{5..300}, batch~U{32..2048}; graph step includes the resets"}
+    del g
+    plan.close()
+    for s in solvers:
+        s.close()
+    return out
+
+
 def cpu_baseline(w, iters_sample: int):
     import oracle
     threads = oracle.max_threads()
@@ -72,6 +241,10 @@ def main():
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ttr-cap", type=int, default=300)
+    ap.add_argument("--ws-scenes", type=int, default=1024)
+    ap.add_argument("--ws-epochs", type=int, default=40)
+    ap.add_argument("--ragged-problems", type=int, default=256, help="0 skips the ragged set")
+    ap.add_argument("--ragged-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -130,23 +303,8 @@ def main():
                 "ops_per_traj_iter": algorithmic_ops_per_traj_iter(w),
                 "launch_ms": launch_ms}
 
-    # time to batch-median residual <= 1e-3, cold start
-    cap = args.ttr_cap
-    tr_long = torch.zeros((cap, w.batch), dtype=torch.float32, device="cuda")
-    xb.copy_(xi); lam.zero_()
-    solver.project(xi, w.boundary, obs, xb, lam, cap, res_trace=tr_long)
-    torch.cuda.synchronize()
-    hit, med = median_time_to_residual(tr_long.cpu().numpy())
-    ttr = {"cold_iters": None if hit is None else hit + 1, "cold_ms": None, "cap": cap}
-    if hit is not None:
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        xb.copy_(xi); lam.zero_()
-        torch.cuda.synchronize()
-        e0.record(stream)
-        solver.project(xi, w.boundary, obs, xb, lam, hit + 1)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ttr["cold_ms"] = e0.elapsed_time(e1)
+    ttr = time_to_residual(args, w, solver, xi, obs, stream) if args.ttr_cap > 0 else None
+    ragged = ragged_bench(args) if args.ragged_problems > 0 else None
 
     out = {
         "metric": "traj-iters/s & time-to-residual<=1e-3, learned warm-start vs cold, 1 MI355X",
@@ -160,6 +318,7 @@ def main():
                    "timesteps": w.n_steps, "degree": w.degree, "precision": "fp32"},
         "roofline": roofline,
         "time_to_residual": ttr,
+        "ragged": ragged,
         "wall_s_timed_region": wall,
     }
     if not args.no_cpu:

@@ -183,6 +183,56 @@ trajam_status trajam_get_launch(const trajam_solver *s, int32_t *kernel,
 trajam_status trajam_boundary_coefficients(const trajam_problem *p, const double *b4,
                                            double *coef4);
 
+/* Packs obstacles into the solver (the same packing trajam_project does per call) so
+ * that calls which take no obstacle arguments -- trajam_ragged_launch -- use them.
+ * Same layouts and NULL rules as trajam_project.  Errors: INVALID, DEVICE. */
+trajam_status trajam_set_obstacles(trajam_solver *s, const void *obs_centre, const void *obs_vel,
+                                   const void *obs_axes, void *stream);
+
+/* Autotuner: times every launch shape of trajam_project (both kernel variants, each
+ * valid samples-per-workgroup) for `probe_iters` iterations on the given inputs with
+ * HIP events, applies the fastest with trajam_set_launch and returns it.  Results are
+ * cached per process, keyed by (GPU architecture, dims, n_steps, n_obstacles rounded
+ * up to a power of two, batch rounded up to a power of two, precision); a cached key
+ * is applied without timing.  When the environment variable TRAJAM_AUTOTUNE_CACHE
+ * names a file, the cache is read from and appended to it (one key per line).
+ * xi_bar and lambda are overwritten (used as scratch).  Synchronizes the stream.
+ * Errors: as trajam_project. */
+trajam_status trajam_autotune(trajam_solver *s, int32_t batch, const void *xi,
+                              const double *boundary_host, const void *obs_centre,
+                              const void *obs_vel, const void *obs_axes, void *xi_bar,
+                              void *lambda, int32_t probe_iters, int32_t *kernel,
+                              int32_t *samples_per_workgroup, void *stream);
+
+/* ---- ragged batches: many problems in one persistent launch ---------------------
+ * Each item is one problem (its own solver, hence fixed matrices and obstacles, and
+ * its own batch).  A plan uploads the problem table once; every launch zeroes a
+ * device work counter and runs one persistent kernel whose waves take (problem,
+ * sample) units longest-problem-first until none is left.  Launches never allocate
+ * or synchronize, so they can be captured in a graph.  Restrictions of this build:
+ * FP32 solvers, degree <= 11, n_steps <= 128, obstacles set with
+ * trajam_set_obstacles before the plan is created. */
+typedef struct {
+    trajam_solver *solver;       /* problem class (FP32) */
+    int32_t batch;               /* samples of this problem (<= max_batch) */
+    const void *xi;              /* device [batch][dims][degree+1] */
+    const double *boundary_host; /* host [dims][4], read at plan creation */
+    void *xi_bar;                /* device in/out, as trajam_project */
+    void *lambda;                /* device in/out */
+    void *res_trace;             /* device [iters][batch] float or NULL */
+    uint32_t *flags;             /* device [batch] or NULL */
+} trajam_ragged_item;
+
+typedef struct trajam_ragged_plan trajam_ragged_plan;
+
+/* Errors: INVALID (bad item), UNSUPPORTED (item outside the restrictions above),
+ * DEVICE (allocation / copy).  On error *out is NULL. */
+trajam_status trajam_ragged_plan_create(const trajam_ragged_item *items, int32_t n_items,
+                                        int32_t iters, trajam_ragged_plan **out);
+/* Runs `iters` AM iterations for every sample of every item.  Errors: INVALID, DEVICE. */
+trajam_status trajam_ragged_launch(trajam_ragged_plan *plan, void *stream);
+void trajam_ragged_plan_destroy(trajam_ragged_plan *plan);
+
 /* ---- projection-guided sampling loop (thesis ch. 6, Alg 3) -------------------
  * One CEM iteration on the device is: trajam_cem_sample -> trajam_project (cold
  * start) -> trajam_residuals -> trajam_cem_cost -> trajam_cem_select ->
@@ -276,14 +326,17 @@ trajam_status trajam_warm_features(int32_t batch, int32_t dims, int32_t n_coeffs
                                    const float *scene, const float *xi, const float *line,
                                    float inv_scale, float *x, void *stream);
 
-/* Warm start from the network output y [batch][dims * n_coeffs]: delta = y * out_scale,
- * xi_bar0 = xi + delta, lambda0 = delta on free coefficients and 0 on the boundary
- * ones (at a converged fixed point the multiplier equals xb - xi on free
- * coefficients).  A sample with a non-finite prediction starts cold and gets
+/* Warm start from the network output y [batch][dims * n_coeffs]: delta = y * out_scale;
+ * on the free coefficients xi_bar0 = xi + delta and lambda0 = delta (at a converged
+ * fixed point the multiplier equals xb - xi there); on the boundary coefficients
+ * (0, 1, 2, n) lambda0 = 0 and xi_bar0 = boundary_coeffs, the host array
+ * [dims][4] = (xi_0, xi_1, xi_2, xi_n) per axis that trajam_boundary_coefficients
+ * returns (dims <= 3; NULL: xi + delta there too).  A sample with a non-finite
+ * prediction starts cold (xi_bar0 = xi, lambda0 = 0) and gets
  * TRAJAM_FLAG_COLD_FALLBACK (flags may be NULL).  Errors: INVALID, DEVICE. */
 trajam_status trajam_warm_apply(int32_t batch, int32_t dims, int32_t n_coeffs, const float *y,
-                                const float *xi, float out_scale, float *xi_bar0, float *lambda0,
-                                uint32_t *flags, void *stream);
+                                const float *xi, float out_scale, const double *boundary_coeffs,
+                                float *xi_bar0, float *lambda0, uint32_t *flags, void *stream);
 
 /* Per-sample fallback: where res_warm[b] > res_cold[b] (or is NaN) the sample restarts
  * cold (xi_bar0 = xi, lambda0 = 0) and gets TRAJAM_FLAG_COLD_FALLBACK.

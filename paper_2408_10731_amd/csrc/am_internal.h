@@ -17,6 +17,7 @@ constexpr int kMaxCoeffs = 16;
 template <typename T>
 struct AmArgs {
     int batch;       // samples in this call
+    int dims;        // 2 or 3 (read by the ragged kernel's dispatch)
     int n_p;         // time samples
     int nv;          // coefficients per axis (degree + 1)
     int n_o;         // obstacles
@@ -95,10 +96,20 @@ hipError_t launch_adam(long n, float *p, const float *g, float *m, float *v, int
                        float b2, float eps, hipStream_t st);
 hipError_t launch_warm_features(int batch, int dim, int n_scene, const float *scene, const float *xi,
                                 const float *line, float inv_scale, float *X, hipStream_t st);
+// Boundary coefficients (xi_0, xi_1, xi_2, xi_n per axis) written exactly by the warm
+// start; set = 0 leaves xi + delta there.
+struct WarmBoundary {
+    float c[3][4];
+    int set;
+};
 hipError_t launch_warm_apply(int batch, int dims, int nv, const float *y, const float *xi, float out_scale,
-                             float *xb0, float *lam0, uint32_t *flags, hipStream_t st);
+                             const WarmBoundary &bc, float *xb0, float *lam0, uint32_t *flags, hipStream_t st);
 hipError_t launch_warm_fallback(int batch, int dim, const float *rw, const float *rc, const float *xi,
                                 float *xb0, float *lam0, uint32_t *flags, hipStream_t st);
+
+// Ragged persistent launch (FP32): zeroes the counter, then runs the work queue.
+hipError_t launch_ragged(const AmArgs<float> *probs, const int *offsets, int n_probs, int total, int *counter,
+                         int blocks, hipStream_t st);
 
 // Dynamic LDS bytes of one AM workgroup.
 size_t project_lds_bytes(int dims, int nvp, int tpad, int tb, size_t scalar);

@@ -682,51 +682,23 @@ __device__ __forceinline__ void wave_lds_sync()
 }
 
 // ----------------------------------------------------------------------------
-// Wave-per-sample AM kernel: lane l owns time samples l, l + 64, ... (TPL of them),
-// so one sample's whole iteration stays inside one wavefront.  The only block
-// barrier is the one after the constant set-up; the F^T r reduce-scatter leaves
-// coefficient o's sum in lane o << (6 - log2 V), which is also its owner lane for
-// the multiplier, the defect and the QP update.  `a.tb` samples per workgroup
-// (= waves per workgroup), each wave independent of the others.
-template <typename T, int D, int NVP, int TPL, bool MQP>
-__global__ __launch_bounds__(kMaxThreads) void am_wave_kernel(AmArgs<T> a)
+// One sample's whole projection on one wavefront: lane l owns time samples l,
+// l + 64, ... (TPL of them).  The F^T r reduce-scatter leaves coefficient o's sum in
+// lane o << (6 - log2 V), which is also its owner lane for the multiplier, the defect
+// and the QP update, so the iteration needs no block barrier.  wmat [NVP][NVP] holds
+// the QP operator, xs / gs [D*NVP] this wave's iterate and defect (LDS); db, hff,
+// hfb and the A operands are used by the bf16 matrix-core QP only.
+template <typename T, int D, int NVP, int TPL, bool MQP, typename A>
+__device__ __forceinline__ void wave_sample(const A &a, const int sample, const int lane,
+                                            const T *wmat, T *xs, T *gs, float *db,
+                                            const float *hff, const float *hfb, bf16x4 ahi,
+                                            bf16x4 alo)
 {
     constexpr int S = D * NVP;
     constexpr int V = pow2ceil(S);
     constexpr int LOGV = (V >= 64) ? 6 : (V >= 32) ? 5 : (V >= 16) ? 4 : 3;
     constexpr int OSH = 6 - LOGV;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *smem = reinterpret_cast<T *>(smem_raw);
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int sample = blockIdx.x * a.tb + wv;
-    const bool live = sample < a.batch;
     const int nf = a.nv - 4;
-
-    T *wmat = smem;                                   // [NVP][NVP]
-    T *xs = smem + NVP * NVP + wv * 2 * S;            // this wave's xb
-    T *gs = xs + S;                                   // this wave's defect
-    float *mqbase = reinterpret_cast<float *>(smem + NVP * NVP + a.tb * 2 * S);
-    float *db = mqbase + wv * 256;                    // MQP: delta tile [16 cols][16 rows]
-    float *hff = mqbase + a.tb * 256;                 // MQP: H_ff [16][16]
-    float *hfb = hff + 256;                           // MQP: H_fb [16][4]
-
-    for (int i = tid; i < NVP * NVP; i += blockDim.x) {
-        const int f = i / NVP, m = i - f * NVP;
-        wmat[i] = (f < nf) ? a.W[f * NVP + m] : T(0);
-    }
-    bf16x4 ahi = {0, 0, 0, 0}, alo = {0, 0, 0, 0};
-    if constexpr (MQP) {
-        const int m = lane & 15, k0 = 4 * (lane >> 4);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            ahi[i] = (short)a.Whi[m * 16 + k0 + i];
-            alo[i] = (short)a.Wlo[m * 16 + k0 + i];
-        }
-        for (int i = tid; i < 256 + 64; i += blockDim.x) hff[i] = a.Hmq[i];
-    }
-    __syncthreads();
-    if (!live) return;  // waves are independent from here on
-
     // This lane's time samples and their basis rows (registers for the launch).
     T tt[TPL], phi0[TPL][NVP], phi1[TPL][NVP], phi2[TPL][NVP];
     bool valid[TPL];
@@ -905,6 +877,112 @@ __global__ __launch_bounds__(kMaxThreads) void am_wave_kernel(AmArgs<T> a)
         }
     }
 }
+
+// Wave-per-sample AM kernel: `a.tb` samples per workgroup (= waves per workgroup),
+// each wave independent of the others after the constant set-up.
+template <typename T, int D, int NVP, int TPL, bool MQP>
+__global__ __launch_bounds__(kMaxThreads) void am_wave_kernel(AmArgs<T> a)
+{
+    constexpr int S = D * NVP;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *smem = reinterpret_cast<T *>(smem_raw);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int sample = blockIdx.x * a.tb + wv;
+    const int nf = a.nv - 4;
+
+    T *wmat = smem;                                   // [NVP][NVP]
+    T *xs = smem + NVP * NVP + wv * 2 * S;            // this wave's xb
+    T *gs = xs + S;                                   // this wave's defect
+    float *mqbase = reinterpret_cast<float *>(smem + NVP * NVP + a.tb * 2 * S);
+    float *db = mqbase + wv * 256;                    // MQP: delta tile [16 cols][16 rows]
+    float *hff = mqbase + a.tb * 256;                 // MQP: H_ff [16][16]
+    float *hfb = hff + 256;                           // MQP: H_fb [16][4]
+
+    for (int i = tid; i < NVP * NVP; i += blockDim.x) {
+        const int f = i / NVP, m = i - f * NVP;
+        wmat[i] = (f < nf) ? a.W[f * NVP + m] : T(0);
+    }
+    bf16x4 ahi = {0, 0, 0, 0}, alo = {0, 0, 0, 0};
+    if constexpr (MQP) {
+        const int m = lane & 15, k0 = 4 * (lane >> 4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ahi[i] = (short)a.Whi[m * 16 + k0 + i];
+            alo[i] = (short)a.Wlo[m * 16 + k0 + i];
+        }
+        for (int i = tid; i < 256 + 64; i += blockDim.x) hff[i] = a.Hmq[i];
+    }
+    __syncthreads();
+    if (sample >= a.batch) return;  // waves are independent from here on
+    wave_sample<T, D, NVP, TPL, MQP>(a, sample, lane, wmat, xs, gs, db, hff, hfb, ahi, alo);
+}
+
+// ----------------------------------------------------------------------------
+// Ragged persistent launch: many independent problems (each its own fixed matrices,
+// obstacles, batch) in one launch.  Every wave repeatedly takes the next work unit
+// (problem, sample) from a device counter and runs that sample's whole projection;
+// problems are ordered longest-first on the host, so the expensive units start first
+// and the short ones fill the tail.  Every wave exits once the counter passes the
+// last unit.  FP32; per unit the kernel dispatches to the (dims, padded coefficients,
+// time samples per lane) instantiation of the problem.
+constexpr int kRaggedWaveLds = 16 * 16 + 2 * 3 * 16;  // floats per wave: W, xb, defect
+
+using RaggedArgs = TRAJAM_CONST_AS AmArgs<float>;
+
+template <int D, int NVP, int TPL>
+__device__ __forceinline__ void ragged_unit(const RaggedArgs &a, int sample, int lane, float *wl)
+{
+    constexpr int S = D * NVP;
+    const int nf = a.nv - 4;
+    for (int i = lane; i < NVP * NVP; i += 64) {
+        const int f = i / NVP, m = i - f * NVP;
+        wl[i] = (f < nf) ? a.W[f * NVP + m] : 0.f;
+    }
+    wave_lds_sync();
+    const bf16x4 z = {0, 0, 0, 0};
+    float *xs = wl + 256;
+    wave_sample<float, D, NVP, TPL, false, RaggedArgs>(a, sample, lane, wl, xs, xs + S, nullptr, nullptr, nullptr,
+                                                       z, z);
+    wave_lds_sync();  // this wave's LDS is reused by its next unit
+}
+
+__global__ __launch_bounds__(kMaxThreads) void am_ragged_kernel(const AmArgs<float> *__restrict__ probs_g,
+                                                                const int *__restrict__ offsets_g, int n_probs,
+                                                                int total, int *__restrict__ counter)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float *wl = reinterpret_cast<float *>(smem_raw) + (threadIdx.x >> 6) * kRaggedWaveLds;
+    const int lane = threadIdx.x & 63;
+    // The table and the offsets are read-only for the launch: constant address space,
+    // so with a wave-uniform unit index every field is a scalar load.
+    const RaggedArgs *probs = (const RaggedArgs *)probs_g;
+    const TRAJAM_CONST_AS int *offsets = (const TRAJAM_CONST_AS int *)offsets_g;
+    for (;;) {
+        int u = 0;
+        if (lane == 0) u = atomicAdd(counter, 1);
+        u = __builtin_amdgcn_readfirstlane(__shfl(u, 0));
+        if (u >= total) break;
+        int lo = 0, hi = n_probs;  // largest lo with offsets[lo] <= u
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (offsets[mid] <= u) lo = mid;
+            else hi = mid;
+        }
+        const RaggedArgs &a = probs[lo];
+        const int sample = u - offsets[lo];
+        const int nvp = a.nv <= 8 ? 8 : 12;
+        const int tpl = (a.n_p + 63) >> 6;
+        if (a.dims == 2) {
+            if (nvp == 8) { if (tpl == 1) ragged_unit<2, 8, 1>(a, sample, lane, wl); else ragged_unit<2, 8, 2>(a, sample, lane, wl); }
+            else          { if (tpl == 1) ragged_unit<2, 12, 1>(a, sample, lane, wl); else ragged_unit<2, 12, 2>(a, sample, lane, wl); }
+        } else {
+            if (nvp == 8) { if (tpl == 1) ragged_unit<3, 8, 1>(a, sample, lane, wl); else ragged_unit<3, 8, 2>(a, sample, lane, wl); }
+            else          { if (tpl == 1) ragged_unit<3, 12, 1>(a, sample, lane, wl); else ragged_unit<3, 12, 2>(a, sample, lane, wl); }
+        }
+    }
+}
+
+__global__ void zero_counter_kernel(int *counter) { *counter = 0; }
 
 // Residual only: steps (a) and the residual norms at the given coefficients.
 template <typename T, int D, int NVP>
@@ -1085,6 +1163,18 @@ struct Dispatch;
     } while (0)
 
 }  // namespace
+
+hipError_t launch_ragged(const AmArgs<float> *probs, const int *offsets, int n_probs, int total, int *counter,
+                         int blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, st, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = sizeof(float) * (size_t)kRaggedWaveLds * (kMaxThreads / 64);
+    hipLaunchKernelGGL(am_ragged_kernel, dim3(blocks), dim3(kMaxThreads), lds, st, probs, offsets, n_probs, total,
+                       counter);
+    return hipGetLastError();
+}
 
 size_t project_lds_bytes(int dims, int nvp, int tpad, int tb, size_t scalar)
 {

@@ -156,13 +156,23 @@ extern "C" trajam_status trajam_warm_features(int32_t batch, int32_t dims, int32
 }
 
 extern "C" trajam_status trajam_warm_apply(int32_t batch, int32_t dims, int32_t nv, const float *y,
-                                           const float *xi, float out_scale, float *xb0, float *lam0,
-                                           uint32_t *flags, void *stream)
+                                           const float *xi, float out_scale, const double *boundary_coeffs,
+                                           float *xb0, float *lam0, uint32_t *flags, void *stream)
 {
     if (batch < 0 || dims < 1 || nv < 4 || !y || !xi || !xb0 || !lam0)
         return fail(TRAJAM_ERR_INVALID, "invalid warm-start apply arguments");
+    if (boundary_coeffs && dims > 3) return fail(TRAJAM_ERR_INVALID, "boundary coefficients need dims <= 3");
+    trajam::WarmBoundary bc{};
+    if (boundary_coeffs) {
+        for (int i = 0; i < dims * 4; ++i) {
+            if (!std::isfinite(boundary_coeffs[i])) return fail(TRAJAM_ERR_INVALID, "non-finite boundary coefficient");
+            bc.c[i / 4][i % 4] = (float)boundary_coeffs[i];
+        }
+        bc.set = 1;
+    }
     if (batch == 0) return TRAJAM_OK;
-    return dev(trajam::launch_warm_apply(batch, dims, nv, y, xi, out_scale, xb0, lam0, flags, (hipStream_t)stream),
+    return dev(trajam::launch_warm_apply(batch, dims, nv, y, xi, out_scale, bc, xb0, lam0, flags,
+                                         (hipStream_t)stream),
                "warm apply");
 }
 

@@ -171,12 +171,14 @@ __global__ void warm_features_kernel(int batch, int dim, int n_scene, const floa
     X[i] = f < n_scene ? scene[f] : (xi[(long)b * dim + (f - n_scene)] - line[f - n_scene]) * inv_scale;
 }
 
-// One thread per sample: delta = y * out_scale; xb0 = xi + delta; lambda0 = delta on
-// the free coefficients (the converged multiplier of a fixed point equals
-// xb - xi there) and 0 on the boundary ones; non-finite predictions fall back cold.
+// One thread per sample: delta = y * out_scale; xb0 = xi + delta on the free
+// coefficients and the exact boundary coefficients on the others (when given);
+// lambda0 = delta on the free coefficients (the converged multiplier of a fixed point
+// equals xb - xi there) and 0 on the boundary ones; non-finite predictions fall back
+// cold.
 __global__ void warm_apply_kernel(int batch, int dims, int nv, const float *__restrict__ y,
-                                  const float *__restrict__ xi, float out_scale, float *__restrict__ xb0,
-                                  float *__restrict__ lam0, uint32_t *__restrict__ flags)
+                                  const float *__restrict__ xi, float out_scale, WarmBoundary bc,
+                                  float *__restrict__ xb0, float *__restrict__ lam0, uint32_t *__restrict__ flags)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
@@ -188,7 +190,7 @@ __global__ void warm_apply_kernel(int batch, int dims, int nv, const float *__re
         const int m = r % nv;
         const bool bnd = m <= 2 || m == nv - 1;
         const float d = finite ? y[i] * out_scale : 0.f;
-        xb0[i] = xi[i] + d;
+        xb0[i] = (finite && bnd && bc.set) ? bc.c[r / nv][m == nv - 1 ? 3 : m] : xi[i] + d;
         lam0[i] = bnd ? 0.f : d;
     }
     if (flags) flags[b] = finite ? 0u : 4u;
@@ -260,10 +262,10 @@ hipError_t launch_warm_features(int batch, int dim, int n_scene, const float *sc
 }
 
 hipError_t launch_warm_apply(int batch, int dims, int nv, const float *y, const float *xi, float out_scale,
-                             float *xb0, float *lam0, uint32_t *flags, hipStream_t st)
+                             const WarmBoundary &bc, float *xb0, float *lam0, uint32_t *flags, hipStream_t st)
 {
     hipLaunchKernelGGL(warm_apply_kernel, dim3((batch + 255) / 256), dim3(256), 0, st, batch, dims, nv, y, xi,
-                       out_scale, xb0, lam0, flags);
+                       out_scale, bc, xb0, lam0, flags);
     return hipGetLastError();
 }
 

@@ -23,8 +23,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -45,6 +50,8 @@ struct trajam_solver {
     trajam_problem prob;
     int nv, nf, nvp, tpad, tb;
     int variant;  // trajam::kVariant*
+    bool packed = false;   // obstacles set with trajam_set_obstacles
+    bool dynamic = false;  // ... with velocities
     int device;
     // host FP64 copies
     std::vector<double> P, Pd, Pdd, H, W, Wff;
@@ -448,6 +455,7 @@ void fill_args(const trajam_solver *s, AmArgs<T> &a, int batch, int iters)
     const trajam_problem &p = s->prob;
     std::memset(&a, 0, sizeof(a));
     a.batch = batch;
+    a.dims = p.dims;
     a.n_p = p.n_steps;
     a.nv = s->nv;
     a.n_o = p.n_obstacles;
@@ -645,5 +653,233 @@ extern "C" trajam_status trajam_cem_update(trajam_solver *s, int32_t n_elite, co
     hipError_t e = trajam::launch_cem_update(s->prob.precision == TRAJAM_FP64, n_elite, dim, elite_idx, xi_bar,
                                              c_aug, sigma, gamma, 1e-10, mu, Sigma, chol, (hipStream_t)stream);
     if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("cem update: ") + hipGetErrorString(e));
+    return TRAJAM_OK;
+}
+
+// ---- obstacles as solver state, autotuner, ragged plans -------------------------
+
+extern "C" trajam_status trajam_set_obstacles(trajam_solver *s, const void *c, const void *v, const void *ax,
+                                              void *stream)
+{
+    if (!s) return TRAJAM_ERR_INVALID;
+    s->err.clear();
+    trajam_status st = pack(s, c, v, ax, (hipStream_t)stream);
+    if (st != TRAJAM_OK) return st;
+    s->packed = true;
+    s->dynamic = v != nullptr;
+    return TRAJAM_OK;
+}
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune;
+bool g_tune_loaded = false;
+
+int pow2_at_least(int x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+std::string tune_key(const trajam_solver *s, int batch)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, s->device) == hipSuccess) arch = prop.gcnArchName;
+    for (char &ch : arch)
+        if (ch == ' ') ch = '_';
+    std::ostringstream k;
+    k << arch << "|d" << s->prob.dims << "|np" << s->prob.n_steps << "|no" << pow2_at_least(std::max(1, s->prob.n_obstacles))
+      << "|b" << pow2_at_least(std::max(1, batch)) << "|p" << s->prob.precision << "|m" << s->prob.obstacle_model;
+    return k.str();
+}
+
+void tune_load_file()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("TRAJAM_AUTOTUNE_CACHE");
+    if (!path) return;
+    std::ifstream f(path);
+    std::string key;
+    int kern, spw;
+    while (f >> key >> kern >> spw) g_tune[key] = {kern, spw};
+}
+
+void tune_store(const std::string &key, int kern, int spw)
+{
+    g_tune[key] = {kern, spw};
+    const char *path = std::getenv("TRAJAM_AUTOTUNE_CACHE");
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << kern << " " << spw << "\n";
+}
+
+}  // namespace
+
+extern "C" trajam_status trajam_autotune(trajam_solver *s, int32_t batch, const void *xi, const double *boundary,
+                                         const void *c, const void *v, const void *ax, void *xb, void *lam,
+                                         int32_t probe_iters, int32_t *kernel_out, int32_t *spw_out, void *stream)
+{
+    if (!s) return TRAJAM_ERR_INVALID;
+    if (batch < 1 || probe_iters < 1 || !xi || !xb || !lam || !boundary)
+        return fail(s, TRAJAM_ERR_INVALID, "autotune needs batch >= 1, probe_iters >= 1 and buffers");
+    if (batch > s->prob.max_batch) return fail(s, TRAJAM_ERR_CAPACITY, "batch > max_batch");
+    hipStream_t st = (hipStream_t)stream;
+    const std::string key = tune_key(s, batch);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_file();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            trajam_status r = trajam_set_launch(s, it->second.first, it->second.second);
+            if (r == TRAJAM_OK) {
+                if (kernel_out) *kernel_out = it->second.first;
+                if (spw_out) *spw_out = it->second.second;
+                return TRAJAM_OK;
+            }
+        }
+    }
+    const size_t bytes = (size_t)batch * s->prob.dims * s->nv *
+                         (s->prob.precision == TRAJAM_FP64 ? sizeof(double) : sizeof(float));
+    std::vector<std::pair<int, int>> cands;
+    for (int spw = 1; spw * s->tpad <= trajam::kMaxThreads; spw *= 2) cands.push_back({TRAJAM_KERNEL_MULTIWAVE, spw});
+    for (int spw = 1; spw * 64 <= trajam::kMaxThreads; spw *= 2) cands.push_back({TRAJAM_KERNEL_WAVE, spw});
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(s, TRAJAM_ERR_DEVICE, "hipEventCreate failed");
+    float best = 1e30f;
+    std::pair<int, int> pick = {s->variant, s->tb};
+    trajam_status status = TRAJAM_OK;
+    for (const auto &cd : cands) {
+        if (trajam_set_launch(s, cd.first, cd.second) != TRAJAM_OK) continue;
+        float t_best = 1e30f;
+        for (int rep = 0; rep < 3 && status == TRAJAM_OK; ++rep) {
+            if (hipMemcpyAsync(xb, xi, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                hipMemsetAsync(lam, 0, bytes, st) != hipSuccess) {
+                status = fail(s, TRAJAM_ERR_DEVICE, "autotune reset failed");
+                break;
+            }
+            hipEventRecord(e0, st);
+            status = trajam_project(s, batch, xi, boundary, c, v, ax, xb, lam, probe_iters, nullptr, nullptr, stream);
+            hipEventRecord(e1, st);
+            if (status != TRAJAM_OK) break;
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                status = fail(s, TRAJAM_ERR_DEVICE, "autotune timing failed");
+                break;
+            }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) t_best = std::min(t_best, ms);  // first run warms caches
+        }
+        if (status != TRAJAM_OK) break;
+        if (t_best < best) {
+            best = t_best;
+            pick = cd;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (status != TRAJAM_OK) return status;
+    trajam_set_launch(s, pick.first, pick.second);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_store(key, pick.first, pick.second);
+    }
+    if (kernel_out) *kernel_out = pick.first;
+    if (spw_out) *spw_out = pick.second;
+    return TRAJAM_OK;
+}
+
+struct trajam_ragged_plan {
+    void *d_probs = nullptr;
+    int *d_offsets = nullptr;
+    int *d_counter = nullptr;
+    int n = 0, total = 0, blocks = 0;
+};
+
+extern "C" void trajam_ragged_plan_destroy(trajam_ragged_plan *p)
+{
+    if (!p) return;
+    if (p->d_probs) (void)hipFree(p->d_probs);
+    if (p->d_offsets) (void)hipFree(p->d_offsets);
+    if (p->d_counter) (void)hipFree(p->d_counter);
+    delete p;
+}
+
+extern "C" trajam_status trajam_ragged_plan_create(const trajam_ragged_item *items, int32_t n, int32_t iters,
+                                                   trajam_ragged_plan **out)
+{
+    if (!out) return fail(nullptr, TRAJAM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!items || n < 1 || iters < 0) return fail(nullptr, TRAJAM_ERR_INVALID, "need items, n >= 1, iters >= 0");
+    std::vector<AmArgs<float>> args(n);
+    std::vector<double> cost(n);
+    for (int i = 0; i < n; ++i) {
+        const trajam_ragged_item &it = items[i];
+        trajam_solver *s = it.solver;
+        if (!s) return fail(nullptr, TRAJAM_ERR_INVALID, "item without solver");
+        const trajam_problem &p = s->prob;
+        if (p.precision != TRAJAM_FP32) return fail(nullptr, TRAJAM_ERR_UNSUPPORTED, "ragged launches need FP32 solvers");
+        if (s->nv > 12 || p.n_steps > 128) return fail(nullptr, TRAJAM_ERR_UNSUPPORTED, "ragged: degree <= 11, n_steps <= 128");
+        if (p.n_obstacles > 0 && !s->packed) return fail(nullptr, TRAJAM_ERR_INVALID, "ragged: call trajam_set_obstacles first");
+        if (it.batch < 0 || it.batch > p.max_batch) return fail(nullptr, TRAJAM_ERR_INVALID, "ragged: bad batch");
+        if (it.batch > 0 && (!it.xi || !it.xi_bar || !it.lambda || !it.boundary_host))
+            return fail(nullptr, TRAJAM_ERR_INVALID, "ragged: NULL buffer");
+        if (it.batch > 0)
+            for (int q = 0; q < p.dims * 4; ++q)
+                if (!std::isfinite(it.boundary_host[q])) return fail(nullptr, TRAJAM_ERR_INVALID, "ragged: non-finite boundary");
+        AmArgs<float> &a = args[i];
+        fill_args(s, a, it.batch, iters);
+        a.dynamic = s->dynamic;
+        if (it.batch > 0)
+            for (int ax = 0; ax < p.dims; ++ax) {
+                double c4[4];
+                boundary_coeffs(p.degree, p.horizon, it.boundary_host + 4 * ax, c4);
+                for (int k = 0; k < 4; ++k) a.xiB[ax][k] = (float)c4[k];
+            }
+        a.xi = (const float *)it.xi;
+        a.xb = (float *)it.xi_bar;
+        a.lam = (float *)it.lambda;
+        a.res = (float *)it.res_trace;
+        a.flags = it.flags;
+        cost[i] = (double)(p.n_obstacles + 2) * p.n_steps * p.dims;
+    }
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<AmArgs<float>> sorted(n);
+    std::vector<int> offsets(n + 1, 0);
+    for (int k = 0; k < n; ++k) {
+        sorted[k] = args[order[k]];
+        offsets[k + 1] = offsets[k] + sorted[k].batch;
+    }
+    trajam_ragged_plan *plan = new (std::nothrow) trajam_ragged_plan();
+    if (!plan) return fail(nullptr, TRAJAM_ERR_DEVICE, "host allocation failed");
+    plan->n = n;
+    plan->total = offsets[n];
+    plan->blocks = std::max(1, std::min((plan->total + 3) / 4, 2048));
+    hipError_t e = hipMalloc(&plan->d_probs, sizeof(AmArgs<float>) * n);
+    if (e == hipSuccess) e = hipMalloc(&plan->d_offsets, sizeof(int) * (n + 1));
+    if (e == hipSuccess) e = hipMalloc(&plan->d_counter, sizeof(int));
+    if (e == hipSuccess) e = hipMemcpy(plan->d_probs, sorted.data(), sizeof(AmArgs<float>) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(plan->d_offsets, offsets.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        trajam_ragged_plan_destroy(plan);
+        return fail(nullptr, TRAJAM_ERR_DEVICE, std::string("ragged plan upload: ") + hipGetErrorString(e));
+    }
+    *out = plan;
+    return TRAJAM_OK;
+}
+
+extern "C" trajam_status trajam_ragged_launch(trajam_ragged_plan *p, void *stream)
+{
+    if (!p) return fail(nullptr, TRAJAM_ERR_INVALID, "plan is NULL");
+    if (p->total == 0) return TRAJAM_OK;
+    hipError_t e = trajam::launch_ragged((const AmArgs<float> *)p->d_probs, p->d_offsets, p->n, p->total,
+                                         p->d_counter, p->blocks, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, TRAJAM_ERR_DEVICE, std::string("ragged launch: ") + hipGetErrorString(e));
     return TRAJAM_OK;
 }

@@ -46,7 +46,8 @@ EXPORTS = [
     "trajam_boundary_coefficients", "trajam_cem_sample", "trajam_cem_cost",
     "trajam_cem_select", "trajam_cem_update", "trajam_mlp_param_count", "trajam_mlp_forward",
     "trajam_mlp_backward", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
-    "trajam_warm_apply", "trajam_warm_fallback",
+    "trajam_warm_apply", "trajam_warm_fallback", "trajam_set_obstacles", "trajam_autotune",
+    "trajam_ragged_plan_create", "trajam_ragged_launch", "trajam_ragged_plan_destroy",
     "trajam_status_string", "trajam_last_error",
 ]
 
@@ -77,6 +78,19 @@ class Problem(ctypes.Structure):
 
 class MlpShape(ctypes.Structure):
     _fields_ = [("n_layers", ctypes.c_int32), ("width", ctypes.c_int32 * (8 + 1))]
+
+
+class RaggedItem(ctypes.Structure):
+    _fields_ = [
+        ("solver", ctypes.c_void_p),
+        ("batch", ctypes.c_int32),
+        ("xi", ctypes.c_void_p),
+        ("boundary_host", ctypes.POINTER(ctypes.c_double)),
+        ("xi_bar", ctypes.c_void_p),
+        ("lam", ctypes.c_void_p),
+        ("res_trace", ctypes.c_void_p),
+        ("flags", ctypes.c_void_p),
+    ]
 
 
 def mlp_shape(widths) -> MlpShape:
@@ -143,9 +157,21 @@ def load():
     L.trajam_warm_features.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, vp, vp, vp, ctypes.c_float, vp, vp]
     L.trajam_warm_apply.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp,
-                                    ctypes.c_float, vp, vp, vp, vp]
+                                    ctypes.c_float, dp, vp, vp, vp, vp]
     L.trajam_warm_fallback.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,
                                        vp, vp, vp, vp]
+    L.trajam_set_obstacles.argtypes = [vp, vp, vp, vp, vp]
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    L.trajam_autotune.argtypes = [vp, ctypes.c_int32, vp, dp, vp, vp, vp, vp, vp, ctypes.c_int32,
+                                  i32p, i32p, vp]
+    L.trajam_ragged_plan_create.argtypes = [ctypes.POINTER(RaggedItem), ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.POINTER(vp)]
+    L.trajam_ragged_launch.argtypes = [vp, vp]
+    L.trajam_ragged_plan_destroy.argtypes = [vp]
+    L.trajam_ragged_plan_destroy.restype = None
+    for f in ("trajam_set_obstacles", "trajam_autotune", "trajam_ragged_plan_create",
+              "trajam_ragged_launch"):
+        getattr(L, f).restype = ctypes.c_int
     for f in ("trajam_mlp_param_count", "trajam_mlp_forward", "trajam_mlp_backward",
               "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features", "trajam_warm_apply",
               "trajam_warm_fallback"):
@@ -278,10 +304,14 @@ def trajam_warm_features(batch, dims, n_coeffs, n_scene, scene, xi, line, inv_sc
                                        xi, line, float(inv_scale), x, stream))
 
 
-def trajam_warm_apply(batch, dims, n_coeffs, y, xi, out_scale, xi_bar0, lambda0, flags,
-                      stream) -> None:
+def trajam_warm_apply(batch, dims, n_coeffs, y, xi, out_scale, boundary_coeffs, xi_bar0,
+                      lambda0, flags, stream) -> None:
+    """boundary_coeffs: host [dims][4] float64 array or None."""
+    arr = None if boundary_coeffs is None else np.ascontiguousarray(boundary_coeffs,
+                                                                    dtype=np.float64)
     _check(load().trajam_warm_apply(int(batch), int(dims), int(n_coeffs), y, xi, float(out_scale),
-                                    xi_bar0, lambda0, flags, stream))
+                                    None if arr is None else _dp(arr), xi_bar0, lambda0, flags,
+                                    stream))
 
 
 def trajam_warm_fallback(batch, dims, n_coeffs, res_warm, res_cold, xi, xi_bar0, lambda0, flags,
@@ -291,6 +321,35 @@ def trajam_warm_fallback(batch, dims, n_coeffs, res_warm, res_cold, xi, xi_bar0,
 
 
 # ----------------------------------------------------------- torch wrapper --
+
+
+def trajam_set_obstacles(handle, obs_centre, obs_vel, obs_axes, stream) -> None:
+    _check(load().trajam_set_obstacles(handle, obs_centre, obs_vel, obs_axes, stream), handle)
+
+
+def trajam_autotune(handle, batch, xi, boundary_host, obs_centre, obs_vel, obs_axes, xi_bar,
+                    lam, probe_iters, stream):
+    b = np.ascontiguousarray(boundary_host, dtype=np.float64)
+    k, t = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().trajam_autotune(handle, batch, xi, _dp(b), obs_centre, obs_vel, obs_axes, xi_bar,
+                                  lam, probe_iters, ctypes.byref(k), ctypes.byref(t), stream),
+           handle)
+    return k.value, t.value
+
+
+def trajam_ragged_plan_create(items, iters) -> int:
+    arr = (RaggedItem * len(items))(*items)
+    out = ctypes.c_void_p()
+    _check(load().trajam_ragged_plan_create(arr, len(items), iters, ctypes.byref(out)))
+    return out.value
+
+
+def trajam_ragged_launch(plan, stream) -> None:
+    _check(load().trajam_ragged_launch(plan, stream))
+
+
+def trajam_ragged_plan_destroy(plan) -> None:
+    load().trajam_ragged_plan_destroy(plan)
 
 
 def make_problem(dims, degree, n_steps, horizon, v_max, a_max, rho, n_obstacles,
@@ -380,8 +439,65 @@ class Solver:
     def set_launch(self, kernel: int, samples_per_workgroup: int):
         trajam_set_launch(self.handle, kernel, samples_per_workgroup)
 
+    def set_obstacles(self, obs, stream=None):
+        import torch
+        c, v, a = self.obstacles(*obs)
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        trajam_set_obstacles(self.handle, c, v, a, st)
+
+    def autotune(self, xi, boundary, obs, xi_bar, lam, probe_iters=20, stream=None):
+        """Time every launch shape, apply the fastest; returns (kernel, samples/WG)."""
+        import torch
+        B = xi.shape[0]
+        shape = (B, self.dims, self.nv)
+        c, v, a = self.obstacles(*obs)
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        return trajam_autotune(self.handle, B, self._t(xi, shape, "xi"), boundary, c, v, a,
+                               self._t(xi_bar, shape, "xi_bar"), self._t(lam, shape, "lambda"),
+                               probe_iters, st)
+
     def launch(self):
         return trajam_get_launch(self.handle)
+
+
+class RaggedPlan:
+    """Many problems (FP32 solvers with obstacles set) in one persistent launch.
+
+    `items` holds (solver, xi, boundary, xi_bar, lam[, res_trace]) tuples of torch
+    tensors; the plan keeps references to them, since the device table points at
+    their memory."""
+
+    def __init__(self, items, iters):
+        keep, cit = [], []
+        for it in items:
+            solver, xi, boundary, xb, lam = it[:5]
+            rt = it[5] if len(it) > 5 else None
+            B = xi.shape[0]
+            shape = (B, solver.dims, solver.nv)
+            b = np.ascontiguousarray(boundary, dtype=np.float64)
+            keep.append((solver, xi, xb, lam, rt, b))
+            cit.append(RaggedItem(solver.handle, B, solver._t(xi, shape, "xi"), _dp(b),
+                                  solver._t(xb, shape, "xi_bar"), solver._t(lam, shape, "lambda"),
+                                  None if rt is None else solver._t(rt, (iters, B), "res_trace"),
+                                  None))
+        self._keep = keep
+        self.iters = iters
+        self.handle = trajam_ragged_plan_create(cit, iters)
+
+    def launch(self, stream=None):
+        import torch
+        trajam_ragged_launch(self.handle, (stream or torch.cuda.current_stream()).cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            trajam_ragged_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def device_workload(w, dtype, device="cuda", static=None):

@@ -3,10 +3,13 @@ chapter names learning-based methods).  Marshalling around the library's kernels
 the network is trained and evaluated by trajam_mlp_* and applied by trajam_warm_*.
 
 What the network predicts.  For a scene (obstacles, start, goal) and a sample xi it
-predicts delta = xb* - xi, the correction of the converged projection.  At a
-converged fixed point the residual is zero, so the QP's stationarity leaves
-lambda* = xb* - xi on the free coefficients; the warm start is therefore
-    xb0 = xi + delta_hat,   lambda0 = delta_hat (free coefficients), 0 (boundary ones),
+predicts delta = xb* - xi on the free coefficients, the correction of the converged
+projection (the boundary coefficients of xb* are known exactly from the boundary
+conditions, so they are not learned).  At a converged fixed point the residual is
+zero, so the QP's stationarity leaves lambda* = xb* - xi on the free coefficients;
+the warm start is therefore
+    xb0 = xi + delta_hat (free), the exact boundary coefficients (boundary);
+    lambda0 = delta_hat (free), 0 (boundary),
 from which the first polar step recovers the polar variables.  A sample starts cold
 (xb0 = xi, lambda0 = 0) when the prediction is not finite or when the warm start's
 residual exceeds the cold start's.
@@ -139,26 +142,75 @@ def build_inputs(w, xi, k_obs, out=None):
     return x
 
 
-def generate(scene_fn, seeds, samples_per_scene, k_obs, iters=300, tol=1e-3):
-    """Solver-generated pairs: each scene's samples projected `iters` AM iterations
-    from a cold start on the GPU; converged samples (residual <= tol) are kept."""
+def boundary_coeffs(solver: "tj.Solver", w) -> np.ndarray:
+    """[D][4] Bernstein coefficients (xi_0, xi_1, xi_2, xi_n) fixed by the boundary rows."""
+    return np.stack([tj.trajam_boundary_coefficients(solver.problem, w.boundary[ax])
+                     for ax in range(w.dims)])
+
+
+def generate(scene_fn, seeds, samples_per_scene, k_obs, iters=300, tol=1e-3, chunk=256):
+    """Solver-generated pairs.  The scenes (one obstacle count per family) are taken
+    `chunk` at a time: a fixed pool of solvers and device buffers is refilled with the
+    chunk's obstacles and samples, all samples are projected `iters` AM iterations from
+    a cold start in one ragged launch, and converged samples (residual <= tol) are
+    kept."""
     import torch
+    seeds = [int(x) for x in seeds]
+    B = int(samples_per_scene)
+    w0 = scene_fn(seeds[0], B)
+    n = min(chunk, len(seeds))
+    D, nv, no = w0.dims, w0.n_v, w0.n_obs
+    solvers = [tj.Solver.for_workload(w0, precision="fp32", max_batch=B) for _ in range(n)]
+    xi = torch.zeros((n, B, D, nv), device="cuda")
+    xb, lam = torch.zeros_like(xi), torch.zeros_like(xi)
+    oc = torch.zeros((n, max(no, 1), D), device="cuda")
+    ov, oa = torch.zeros_like(oc), torch.zeros_like(oc)
+    res = torch.zeros((n, B), device="cuda")
+    plan, plan_key = None, None
     xs, ts = [], []
-    for seed in seeds:
-        w = scene_fn(int(seed), samples_per_scene)
-        solver = tj.Solver.for_workload(w, precision="fp32")
-        xi, obs = tj.device_workload(w, torch.float32)
-        xb = xi.clone()
-        lam = torch.zeros_like(xi)
-        solver.project(xi, w.boundary, obs, xb, lam, iters)
-        res = torch.zeros(w.batch, device="cuda")
-        solver.residuals(xb, obs, res)
-        keep = res <= tol
-        x = build_inputs(w, xi, k_obs)
-        t = ((xb - xi) / OUT_SCALE).reshape(w.batch, -1)
-        xs.append(x[keep])
-        ts.append(t[keep])
-        solver.close()
+    for c0 in range(0, len(seeds), n):
+        ws = [scene_fn(sd, B) for sd in seeds[c0:c0 + n]]
+        m = len(ws)
+        for w in ws:
+            if w.n_obs != no or w.dims != D or w.n_v != nv:
+                raise ValueError("generate: scenes of one family must share dims, degree and n_obs")
+        bnd = ws[0].boundary
+        if any(not np.array_equal(w.boundary, bnd) for w in ws):
+            raise ValueError("generate: scenes of one chunk must share the boundary conditions")
+        xi[:m].copy_(torch.from_numpy(np.stack([w.xi for w in ws]).astype(np.float32)))
+        dynamic = any(np.any(w.obs_vel) for w in ws)
+        if no:
+            oc[:m].copy_(torch.from_numpy(np.stack([w.obs_centre for w in ws]).astype(np.float32)))
+            ov[:m].copy_(torch.from_numpy(np.stack([w.obs_vel for w in ws]).astype(np.float32)))
+            oa[:m].copy_(torch.from_numpy(np.stack([w.obs_axes for w in ws]).astype(np.float32)))
+        obs = [(oc[i], ov[i] if dynamic else None, oa[i]) for i in range(m)]
+        for i in range(m):
+            solvers[i].set_obstacles(obs[i])
+        key = (m, dynamic, bnd.tobytes())   # a plan bakes these in
+        if key != plan_key:
+            if plan is not None:
+                plan.close()
+            plan = tj.RaggedPlan([(solvers[i], xi[i], bnd, xb[i], lam[i]) for i in range(m)],
+                                 iters)
+            plan_key = key
+        xb[:m].copy_(xi[:m])
+        lam[:m].zero_()
+        plan.launch()
+        xs_c = []
+        for i, w in enumerate(ws):
+            solvers[i].residuals(xb[i], obs[i], res[i])
+            xs_c.append(build_inputs(w, xi[i], k_obs))
+        keep = (res[:m] <= tol).reshape(-1)
+        # the warm start writes the boundary coefficients exactly, so only the free
+        # coefficients' correction is learned
+        delta = xb[:m] - xi[:m]
+        delta[:, :, :, [0, 1, 2, nv - 1]] = 0.0
+        xs.append(torch.cat(xs_c)[keep])
+        ts.append((delta / OUT_SCALE).reshape(m * B, -1)[keep])
+    torch.cuda.synchronize()
+    plan.close()
+    for s_ in solvers:
+        s_.close()
     return Dataset(torch.cat(xs).contiguous(), torch.cat(ts).contiguous(), len(seeds))
 
 
@@ -183,25 +235,54 @@ def train(net: Net, data: Dataset, epochs: int, batch: int = 1024, lr: float = 1
     return curve
 
 
-def warm_start(solver: "tj.Solver", net: Net, w, xi, obs, k_obs, flags=None):
+class WarmContext:
+    """Per-scene state of the warm start: scene features, reference line and boundary
+    coefficients on the device, and every work buffer, allocated once.  `run` only
+    launches kernels (features, the network, apply, two residuals, fallback), so it
+    can be captured in a graph together with the projection that follows."""
+
+    def __init__(self, solver: "tj.Solver", net: Net, w, k_obs: int, max_batch: int):
+        import torch
+        self.solver, self.net, self.w, self.k_obs = solver, net, w, k_obs
+        self.scene = torch.as_tensor(scene_features(w, k_obs), device="cuda")
+        self.line = torch.as_tensor(straight_line(w), device="cuda")
+        self.bc = boundary_coeffs(solver, w)
+        n_in = self.scene.numel() + w.dims * w.n_v
+        assert n_in == net.widths[0] and max_batch <= net.max_batch
+        self.x = torch.zeros((max_batch, n_in), device="cuda")
+        shape = (max_batch, w.dims, w.n_v)
+        self.xb0 = torch.zeros(shape, device="cuda")
+        self.lam0 = torch.zeros(shape, device="cuda")
+        self.rw = torch.zeros(max_batch, device="cuda")
+        self.rc = torch.zeros(max_batch, device="cuda")
+        self.flags = torch.zeros(max_batch, dtype=torch.int32, device="cuda")
+
+    def run(self, xi, obs):
+        """(xb0, lam0, flags) views for the samples xi [B, D, n_v]."""
+        import torch
+        w, B = self.w, xi.shape[0]
+        st = torch.cuda.current_stream().cuda_stream
+        x = self.x[:B]
+        tj.trajam_warm_features(B, w.dims, w.n_v, self.scene.numel(), self.scene.data_ptr(),
+                                xi.data_ptr(), self.line.data_ptr(), 1.0 / IN_SCALE, x.data_ptr(),
+                                st)
+        y = self.net.forward(x)
+        xb0, lam0, fl = self.xb0[:B], self.lam0[:B], self.flags[:B]
+        tj.trajam_warm_apply(B, w.dims, w.n_v, y.data_ptr(), xi.data_ptr(), OUT_SCALE, self.bc,
+                             xb0.data_ptr(), lam0.data_ptr(), fl.data_ptr(), st)
+        rw, rc = self.rw[:B], self.rc[:B]
+        self.solver.residuals(xb0, obs, rw)
+        self.solver.residuals(xi, obs, rc)
+        tj.trajam_warm_fallback(B, w.dims, w.n_v, rw.data_ptr(), rc.data_ptr(), xi.data_ptr(),
+                                xb0.data_ptr(), lam0.data_ptr(), fl.data_ptr(), st)
+        return xb0, lam0, fl
+
+
+def warm_start(solver: "tj.Solver", net: Net, w, xi, obs, k_obs):
     """(xb0, lam0, flags): network prediction with the per-sample cold fallback."""
-    import torch
-    st = torch.cuda.current_stream().cuda_stream
-    B = xi.shape[0]
-    x = build_inputs(w, xi, k_obs)
-    y = net.forward(x)
-    xb0 = torch.empty_like(xi)
-    lam0 = torch.empty_like(xi)
-    fl = flags if flags is not None else torch.zeros(B, dtype=torch.int32, device="cuda")
-    tj.trajam_warm_apply(B, w.dims, w.n_v, y.data_ptr(), xi.data_ptr(), OUT_SCALE,
-                         xb0.data_ptr(), lam0.data_ptr(), fl.data_ptr(), st)
-    rw = torch.empty(B, device="cuda")
-    rc = torch.empty(B, device="cuda")
-    solver.residuals(xb0, obs, rw)
-    solver.residuals(xi, obs, rc)
-    tj.trajam_warm_fallback(B, w.dims, w.n_v, rw.data_ptr(), rc.data_ptr(), xi.data_ptr(),
-                            xb0.data_ptr(), lam0.data_ptr(), fl.data_ptr(), st)
-    return xb0, lam0, fl
+    ctx = WarmContext(solver, net, w, k_obs, xi.shape[0])
+    xb0, lam0, fl = ctx.run(xi, obs)
+    return xb0.clone(), lam0.clone(), fl.clone()
 
 
 def family_scene(family: str):

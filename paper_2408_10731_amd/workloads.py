@@ -189,4 +189,44 @@ def tiny(dims: int = 2, batch: int = 3, n_obs: int = 2, degree: int = 5,
                     boundary_rows(start, goal), xi, 5, "fp64")
 
 
+def problem2d(seed: int, n_obs: int, batch: int, iters: int = 50) -> Workload:
+    """The 2D single-robot geometry of config 2 with n_obs circles and `batch` samples."""
+    rng = _rng(seed)
+    start, goal = (0.0, 15.0), (30.0, 15.0)
+    c, w, s = draw_obstacles(rng, n_obs, 2, (0, 0), (30, 30), (0.3, 0.8), False, start, goal)
+    xi = line_samples(rng, batch, 10, start, goal, 0.5)
+    return Workload(f"2d-n{n_obs}-b{batch}", 2, 10, 100, 30.0, 1.5, 2.0, 1.0, c, w, s,
+                    boundary_rows(start, goal), xi, iters, "fp32")
+
+
+def problem3d(seed: int, n_obs: int, batch: int, iters: int = 50) -> Workload:
+    """3D single robot: static spheres r~U(0.3,1.0) in [-10,10]^2 x [0,6], from a point
+    of the radius-8 m circle at z = 3 to its antipode in 10 s, degree 10, 100 steps,
+    v_max = a_max = 3 (the straight line needs 1.6 m/s)."""
+    rng = _rng(seed)
+    ang = rng.uniform(0.0, 2.0 * np.pi)
+    start = (8.0 * np.cos(ang), 8.0 * np.sin(ang), 3.0)
+    goal = (-start[0], -start[1], 3.0)
+    c, w, s = draw_obstacles(rng, n_obs, 3, (-10, -10, 0), (10, 10, 6), (0.3, 1.0), False,
+                             start, goal)
+    xi = line_samples(rng, batch, 10, start, goal, 0.5)
+    return Workload(f"3d-n{n_obs}-b{batch}", 3, 10, 100, 10.0, 3.0, 3.0, 1.0, c, w, s,
+                    boundary_rows(start, goal), xi, iters, "fp32")
+
+
+def ragged_set(n_problems: int = 256, seed: Optional[int] = None, n_obs=(5, 300),
+               batch=(32, 2048), iters: int = 50, dims3_every: int = 2):
+    """Many independent problems: n_obs ~ U{n_obs}, batch ~ U{batch} per problem;
+    every `dims3_every`-th problem is 3D (problem3d), the rest 2D (problem2d)."""
+    base = MASTER_SEED + 5 if seed is None else seed
+    pick = _rng(base)
+    out = []
+    for k in range(n_problems):
+        no = int(pick.integers(n_obs[0], n_obs[1] + 1))
+        b = int(pick.integers(batch[0], batch[1] + 1))
+        gen = problem3d if (dims3_every and k % dims3_every == dims3_every - 1) else problem2d
+        out.append(gen(base + 1000 + k, no, b, iters))
+    return out
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}

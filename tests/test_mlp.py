@@ -194,8 +194,8 @@ def test_gpu_warm_apply_nan_and_fallback():
     xb0 = torch.empty_like(xi)
     lam0 = torch.empty_like(xi)
     fl = torch.zeros(B, dtype=torch.int32, device="cuda")
-    tj.trajam_warm_apply(B, D, nv, y.data_ptr(), xi.data_ptr(), 0.5, xb0.data_ptr(), lam0.data_ptr(),
-                         fl.data_ptr(), st)
+    tj.trajam_warm_apply(B, D, nv, y.data_ptr(), xi.data_ptr(), 0.5, None, xb0.data_ptr(),
+                         lam0.data_ptr(), fl.data_ptr(), st)
     torch.cuda.synchronize()
     d = (y * 0.5).reshape(B, D, nv)
     assert fl.cpu().tolist() == [0, 0, 4, 0, 0]
@@ -204,6 +204,20 @@ def test_gpu_warm_apply_nan_and_fallback():
         torch.testing.assert_close(xb0[b], xi[b] + d[b])
         assert torch.all(lam0[b][:, [0, 1, 2, nv - 1]] == 0)
         torch.testing.assert_close(lam0[b][:, 3:nv - 1], d[b][:, 3:nv - 1])
+    # with boundary coefficients: those are written exactly, the free ones as before
+    bc = np.array([[1.0, 1.25, 1.5, 7.0], [-2.0, -2.0, -2.0, 3.5]])
+    xb1 = torch.empty_like(xi)
+    lam1 = torch.empty_like(xi)
+    fl1 = torch.zeros(B, dtype=torch.int32, device="cuda")
+    tj.trajam_warm_apply(B, D, nv, y.data_ptr(), xi.data_ptr(), 0.5, bc, xb1.data_ptr(),
+                         lam1.data_ptr(), fl1.data_ptr(), st)
+    torch.cuda.synchronize()
+    assert torch.equal(xb1[2], xi[2]) and fl1.cpu().tolist() == [0, 0, 4, 0, 0]
+    for b in (0, 1, 3, 4):
+        got = xb1[b].cpu().numpy()
+        np.testing.assert_array_equal(got[:, [0, 1, 2, nv - 1]], bc.astype(np.float32))
+        torch.testing.assert_close(xb1[b][:, 3:nv - 1], xi[b][:, 3:nv - 1] + d[b][:, 3:nv - 1])
+        assert torch.equal(lam1[b], lam0[b])
     rw = torch.tensor([0.1, 0.5, 0.0, float("nan"), 0.2], device="cuda")
     rc = torch.tensor([0.2, 0.4, 0.0, 0.3, 0.2], device="cuda")
     before = xb0.clone()
@@ -231,7 +245,7 @@ def test_gpu_trained_warm_start_gains_over_cold_start():
     from paper_2408_10731_amd import trajam as tj, warmstart as ws
     fam = ws.family_scene("cfg2")
     k_obs = 50
-    train_seeds = np.arange(10_000, 10_096)
+    train_seeds = np.arange(10_000, 10_512)
     data = ws.generate(fam, train_seeds, 256, k_obs, iters=300)
     print(f"case: warm-start gain, {data.x.shape[0]} training pairs", flush=True)
     w0 = fam(int(train_seeds[0]), 4)

@@ -1,0 +1,225 @@
+"""Ragged persistent launches (many problems, one kernel) and the autotuner.
+
+* A ragged launch runs, per sample, the same arithmetic as the single-problem
+  wave-per-sample kernel: its results are compared with those launches element by
+  element (and reported bitwise), and with the FP64 oracle to the FP32 bar (final
+  waypoints within 1e-3 m, residual within 1e-4).
+* The launch captured in a graph replays to the eager result, with eager work and
+  synchronizations between replays.
+* The autotuner picks a valid launch shape, caches it by problem key, and the tuned
+  launch stays within the FP32 bar of the oracle.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_10731_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _tj():
+    from paper_2408_10731_amd import trajam as tj
+    return tj
+
+
+class Set:
+    """Solvers and device buffers of a list of workloads."""
+
+    def __init__(self, ws, iters):
+        tj = _tj()
+        self.ws, self.iters = ws, iters
+        self.solvers, self.bufs = [], []
+        for w in ws:
+            s = tj.Solver.for_workload(w, precision="fp32", max_batch=max(w.batch, 1))
+            xi, obs = tj.device_workload(w, torch.float32)
+            s.set_obstacles(obs)
+            xb, lam = xi.clone(), torch.zeros_like(xi)
+            tr = torch.zeros((iters, w.batch), dtype=torch.float32, device="cuda")
+            self.solvers.append(s)
+            self.bufs.append((xi, obs, xb, lam, tr))
+
+    def reset(self):
+        for xi, _, xb, lam, tr in self.bufs:
+            xb.copy_(xi)
+            lam.zero_()
+            tr.zero_()
+
+    def plan(self):
+        tj = _tj()
+        return tj.RaggedPlan([(s, b[0], w.boundary, b[2], b[3], b[4])
+                              for s, w, b in zip(self.solvers, self.ws, self.bufs)], self.iters)
+
+    def single(self):
+        """Each problem on its own with the wave-per-sample kernel."""
+        for s, w, (xi, obs, xb, lam, tr) in zip(self.solvers, self.ws, self.bufs):
+            s.set_launch(1, 1)
+            s.project(xi, w.boundary, obs, xb, lam, self.iters, res_trace=tr)
+
+    def results(self):
+        torch.cuda.synchronize()
+        return [(b[2].double().cpu().numpy(), b[3].double().cpu().numpy(),
+                 b[4].double().cpu().numpy()) for b in self.bufs]
+
+    def close(self):
+        for s in self.solvers:
+            s.close()
+
+
+def _mixed(n, seed, n_obs, batch, iters=25):
+    ws = wl.ragged_set(n, seed=seed, n_obs=n_obs, batch=batch, iters=iters)
+    return [w.rounded(np.float32) for w in ws]
+
+
+def test_ragged_matches_single_problem_launches():
+    ws = _mixed(20, 777, (0, 80), (1, 300))
+    ws.append(wl.problem2d(31, 7, 1).rounded(np.float32))       # batch 1
+    ws.append(wl.problem3d(32, 0, 5).rounded(np.float32))       # no obstacles
+    ws.append(wl.problem2d(33, 3, 0).rounded(np.float32))       # empty batch
+    say("case: ragged vs single launches,", len(ws), "problems,",
+        sum(w.batch for w in ws), "samples")
+    S = Set(ws, 25)
+    plan = S.plan()
+    S.reset()
+    plan.launch()
+    rag = S.results()
+    S.reset()
+    S.single()
+    one = S.results()
+    bitwise = True
+    for w, r, o in zip(ws, rag, one):
+        for a, b in zip(r, o):
+            bitwise &= bool(np.array_equal(a, b))
+            scale = max(1.0, float(np.abs(b).max()) if b.size else 1.0)
+            np.testing.assert_allclose(a, b, rtol=0, atol=1e-5 * scale, err_msg=w.name)
+    say("  ragged == single-problem launches bitwise:", bitwise)
+    plan.close()
+    S.close()
+
+
+def test_ragged_oracle_parity():
+    ws = _mixed(6, 4242, (3, 40), (5, 24), iters=30)
+    say("case: ragged vs oracle,", [(w.dims, w.n_obs, w.batch) for w in ws])
+    S = Set(ws, 30)
+    plan = S.plan()
+    S.reset()
+    plan.launch()
+    res = S.results()
+    for w, (xb_g, _, _) in zip(ws, res):
+        xb_o, _, _, _ = oracle.project(w, iters=30)
+        P, _, _ = oracle.bernstein(w.degree, w.n_steps, w.horizon)
+        wp = np.abs(np.einsum("tm,bdm->btd", P, xb_g - xb_o)).max()
+        dr = np.abs(oracle.residuals(w, xb_g)[0] - oracle.residuals(w, xb_o)[0]).max()
+        say(f"  {w.name}: waypoint err {wp:.2e} m, residual err {dr:.2e}")
+        assert wp <= 1e-3 and dr <= 1e-4
+        for ax in range(w.dims):
+            assert np.abs(xb_g[:, ax, 0] - w.boundary[ax, 0]).max() <= 1e-5
+            assert np.abs(xb_g[:, ax, -1] - w.boundary[ax, 3]).max() <= 1e-5
+    plan.close()
+    S.close()
+
+
+def test_ragged_graph_replays_match_eager():
+    ws = _mixed(12, 99, (5, 60), (16, 200), iters=20)
+    say("case: ragged graph capture,", len(ws), "problems")
+    S = Set(ws, 20)
+    plan = S.plan()
+    S.reset()
+    plan.launch()
+    ref = S.results()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        S.reset()
+        plan.launch()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        S.reset()
+        plan.launch()
+    for rep in range(3):
+        for _, _, xb, lam, _ in S.bufs:   # eager work between replays
+            xb.mul_(0.5)
+            lam.add_(1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        got = S.results()
+        for r, o in zip(got, ref):
+            for a, b in zip(r, o):
+                assert np.array_equal(a, b), f"replay {rep}"
+    say("  3 replays bitwise equal to the eager launch")
+    del g
+    plan.close()
+    S.close()
+
+
+def test_ragged_plan_validation():
+    tj = _tj()
+    w = wl.problem2d(5, 4, 8).rounded(np.float32)
+    xi, obs = tj.device_workload(w, torch.float32)
+    xb, lam = xi.clone(), torch.zeros_like(xi)
+    s64 = tj.Solver.for_workload(w, precision="fp64")
+    xi64, obs64 = tj.device_workload(w, torch.float64)
+    s64.set_obstacles(obs64)
+    with pytest.raises(tj.TrajamError) as e:
+        tj.RaggedPlan([(s64, xi64, w.boundary, xi64.clone(), torch.zeros_like(xi64))], 5)
+    assert e.value.status == tj.TRAJAM_ERR_UNSUPPORTED
+    s32 = tj.Solver.for_workload(w, precision="fp32")
+    with pytest.raises(tj.TrajamError) as e:   # obstacles never set
+        tj.RaggedPlan([(s32, xi, w.boundary, xb, lam)], 5)
+    assert e.value.status == tj.TRAJAM_ERR_INVALID
+    s32.set_obstacles(obs)
+    bad = w.boundary.copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(tj.TrajamError) as e:
+        tj.RaggedPlan([(s32, xi, bad, xb, lam)], 5)
+    assert e.value.status == tj.TRAJAM_ERR_INVALID
+    small = tj.Solver.for_workload(w, precision="fp32", max_batch=4)
+    small.set_obstacles(obs)
+    with pytest.raises(tj.TrajamError):
+        tj.RaggedPlan([(small, xi, w.boundary, xb, lam)], 5)
+    s64.close()
+    s32.close()
+    small.close()
+
+
+def test_autotune_picks_cached_valid_launch(tmp_path):
+    tj = _tj()
+    cache = tmp_path / "tune.txt"
+    os.environ["TRAJAM_AUTOTUNE_CACHE"] = str(cache)
+    try:
+        w = wl.config2(batch=256).rounded(np.float32)
+        say("case: autotune cfg2 B=256")
+        s = tj.Solver.for_workload(w, precision="fp32")
+        xi, obs = tj.device_workload(w, torch.float32)
+        xb, lam = xi.clone(), torch.zeros_like(xi)
+        k, t = s.autotune(xi, w.boundary, obs, xb, lam, probe_iters=10)
+        say("  picked kernel", k, "samples/WG", t)
+        assert (k, t) == s.launch()
+        assert k in (0, 1) and t >= 1
+        assert cache.exists() and len(cache.read_text().split()) == 3
+        s.set_launch(0 if k else 1, 1)
+        assert s.autotune(xi, w.boundary, obs, xb, lam, probe_iters=10) == (k, t)  # cached
+        xb.copy_(xi)
+        lam.zero_()
+        s.project(xi, w.boundary, obs, xb, lam, 30)
+        torch.cuda.synchronize()
+        ws = w.subset(64)
+        xb_o, _, _, _ = oracle.project(ws, iters=30)
+        xg = xb.double().cpu().numpy()[:64]
+        P, _, _ = oracle.bernstein(w.degree, w.n_steps, w.horizon)
+        wp = np.abs(np.einsum("tm,bdm->btd", P, xg - xb_o)).max()
+        dr = np.abs(oracle.residuals(ws, xg)[0] - oracle.residuals(ws, xb_o)[0]).max()
+        say(f"  tuned launch vs oracle: waypoint {wp:.2e} m, residual {dr:.2e}")
+        assert wp <= 1e-3 and dr <= 1e-4
+        s.close()
+    finally:
+        os.environ.pop("TRAJAM_AUTOTUNE_CACHE", None)
