@@ -6,7 +6,7 @@ oracle never imports the product package: the two share no code.  Both sides onl
 consume the same host arrays drawn by the seeded input generator.
 
 `trajam_oracle.c` holds the projection (basis, KKT LU, polar steps, multiplier,
-residual); `mlp.py` and `cem.py` hold the numpy FP64 oracles of the learned warm
+residual) for one robot and for N agents with pairwise avoidance; `mlp.py` and `cem.py` hold the numpy FP64 oracles of the learned warm
 start and of the sampling loop.
 """
 from __future__ import annotations
@@ -68,6 +68,15 @@ def lib():
                                   dp, dp, ctypes.c_int, ctypes.c_int]
         L.orc_residuals.argtypes = [pp, ctypes.c_int, dp, dp, dp, dp, dp, dp, ctypes.c_int]
         L.orc_polar_products.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_agents_kkt_matrix.argtypes = [pp, ctypes.c_int, dp]
+        L.orc_agents_qp.argtypes = [pp, ctypes.c_int, dp, dp, dp]
+        L.orc_agents_polar_products.argtypes = [pp, ctypes.c_int, ctypes.c_double, dp, dp, dp,
+                                                dp, dp, dp, dp]
+        L.orc_project_agents.argtypes = [pp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp,
+                                         dp, dp, dp, dp, dp, dp, ctypes.c_int, dp, dp,
+                                         ctypes.c_int]
+        L.orc_residuals_agents.argtypes = [pp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp,
+                                           dp, dp, dp, dp, dp, ctypes.c_int]
         L.orc_set_fault.argtypes = [ctypes.c_int]
         L.orc_set_fault.restype = None
         L.orc_max_threads.restype = ctypes.c_int
@@ -205,3 +214,71 @@ def polar_products(w, xb_one):
                              _p(_f64(w.obs_vel)), _p(_f64(w.obs_axes)), _p(fte), _p(ftr),
                              _p(r2))
     return fte, ftr, float(r2[0])
+
+
+# ------------------------------------------------------------ multi-agent --
+
+
+def _combined_radius(w):
+    return 2.0 * float(w.agent_radius)
+
+
+def agents_kkt_matrix(pr: Problem, n_agents: int):
+    S = n_agents * (pr.degree + 5)
+    K = np.zeros((S, S))
+    if lib().orc_agents_kkt_matrix(ctypes.byref(pr), int(n_agents), _p(K)) != 0:
+        raise ValueError("invalid problem")
+    return K
+
+
+def agents_qp(pr: Problem, q, b):
+    """Joint QP of one axis: q [N, n_v], b [N, 4] -> [N, n_v]."""
+    q = _f64(q); b = _f64(b); out = np.zeros_like(q)
+    if lib().orc_agents_qp(ctypes.byref(pr), q.shape[0], _p(q), _p(b), _p(out)) != 0:
+        raise ValueError("singular joint KKT")
+    return out
+
+
+def agents_polar_products(w, xb_joint):
+    """(F^T e, F^T r [N, D, n_v], |r|^2) of the joint problem at one joint sample."""
+    pr = problem_of(w)
+    xb = _f64(xb_joint)
+    fte = np.zeros_like(xb); ftr = np.zeros_like(xb); r2 = np.zeros(1)
+    lib().orc_agents_polar_products(ctypes.byref(pr), xb.shape[0], _combined_radius(w), _p(xb),
+                                    _p(_f64(w.obs_centre)), _p(_f64(w.obs_vel)),
+                                    _p(_f64(w.obs_axes)), _p(fte), _p(ftr), _p(r2))
+    return fte, ftr, float(r2[0])
+
+
+def project_agents(w, xi_bar=None, lam=None, iters=None, n_threads=0):
+    """Joint AM projection of workload `w` (xi [B, N, D, n_v], boundary [N, D, 4]).
+
+    Returns (xi_bar, lam [B, N, D, n_v], res_trace [K, B], resmax_trace [K, B])."""
+    pr = problem_of(w)
+    xi = _f64(w.xi)
+    B, N = xi.shape[0], xi.shape[1]
+    xb = _f64(xi if xi_bar is None else xi_bar).copy()
+    lm = np.zeros_like(xi) if lam is None else _f64(lam).copy()
+    K = int(w.iters if iters is None else iters)
+    tr = np.zeros((max(K, 1), B)); tm = np.zeros((max(K, 1), B))
+    rc = lib().orc_project_agents(ctypes.byref(pr), N, _combined_radius(w), B, _p(xi),
+                                  _p(_f64(w.obs_centre)), _p(_f64(w.obs_vel)),
+                                  _p(_f64(w.obs_axes)), _p(_f64(w.boundary)), _p(xb), _p(lm), K,
+                                  _p(tr), _p(tm), int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle rejected the problem")
+    return xb, lm, tr[:K], tm[:K]
+
+
+def residuals_agents(w, xi_bar, n_threads=0):
+    """(res_l2 [B], res_max [B]) of the joint polar step at xi_bar [B, N, D, n_v]."""
+    pr = problem_of(w)
+    xb = _f64(xi_bar)
+    B, N = xb.shape[0], xb.shape[1]
+    r2 = np.zeros(B); mx = np.zeros(B)
+    rc = lib().orc_residuals_agents(ctypes.byref(pr), N, _combined_radius(w), B, _p(xb),
+                                    _p(_f64(w.obs_centre)), _p(_f64(w.obs_vel)),
+                                    _p(_f64(w.obs_axes)), _p(r2), _p(mx), int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle rejected the problem")
+    return r2, mx

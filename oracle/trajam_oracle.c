@@ -520,3 +520,263 @@ int orc_max_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------ multi-agent -- */
+/*
+ * Joint projection of N agents (thesis ch. 8, Paper IV, in the projection form of
+ * ch. 6).  Each agent a has its own trajectory xi_a ([D][n_v]), its own boundary
+ * rows, and the single-robot rows of the problem (every obstacle, velocity and
+ * acceleration bounds).  In addition every unordered pair a < b and time t has the
+ * row  p_a(t) - p_b(t) = e_ab(t)  with the polar target of a sphere of combined
+ * radius R around the other agent: e_ab = R d dir(alpha, beta), d >= 1, where
+ * alpha, beta, d follow the same closed forms as an obstacle (eqs sphere_proposed,
+ * com_alpha_i, com_beta_i, com_d_i; a pair is counted once).  The AM steps are those
+ * of the single robot with F now the joint matrix:
+ *   (F^T e)_a = (single-robot part)_a + sum_{b > a} P^T e_ab - sum_{b < a} P^T e_ba
+ * and likewise for F^T r; the multiplier lam_a <- lam_a - rho (F^T r)_a; the QP is
+ * the joint KKT system per axis,
+ *   [H_J  A_J^T; A_J  0] [xb; nu] = [xi + lam + rho F^T e; b]
+ * with H_J = blockdiag(H) + rho sum_{a<b} (E_a - E_b)^T P^T P (E_a - E_b) assembled
+ * pair by pair here (E_a selects agent a's block) and A_J = blockdiag(A).
+ */
+
+/* Pair polar rows at joint coefficients xb ([N][D][n_v]); adds to FtE, FtR
+ * ([N][D][n_v]), r2 and rmax.  R = combined radius. */
+static void pair_rows(const orc_ctx *c, int N, double R, const double *xb, double *FtE,
+                      double *FtR, double *r2, double *rmax)
+{
+    int D = c->D, nv = c->nv, np = c->np, t, a, b, ax, m;
+    double *p = malloc(sizeof(double) * N * D);
+    double s[3] = {R, R, R};
+    for (t = 0; t < np; ++t) {
+        for (a = 0; a < N; ++a)
+            for (ax = 0; ax < D; ++ax) {
+                double acc = 0.0;
+                for (m = 0; m < nv; ++m) acc += c->P[t * nv + m] * xb[(a * D + ax) * nv + m];
+                p[a * D + ax] = acc;
+            }
+        for (a = 0; a < N; ++a)
+            for (b = a + 1; b < N; ++b) {
+                double xt[3], off[3], al, be, dd;
+                for (ax = 0; ax < D; ++ax) xt[ax] = p[a * D + ax] - p[b * D + ax];
+                orc_polar_obstacle(D, xt, s, &al, &be, &dd, off);
+                for (ax = 0; ax < D; ++ax) {
+                    double r = xt[ax] - off[ax];
+                    double sb = (g_fault == 6) ? 1.0 : -1.0;   /* planted: sign for agent b */
+                    *r2 += r * r;
+                    if (fabs(r) > *rmax) *rmax = fabs(r);
+                    for (m = 0; m < nv; ++m) {
+                        double pm = c->P[t * nv + m];
+                        if (FtE) {
+                            FtE[(a * D + ax) * nv + m] += pm * off[ax];
+                            FtE[(b * D + ax) * nv + m] += sb * pm * off[ax];
+                        }
+                        if (FtR) {
+                            FtR[(a * D + ax) * nv + m] += pm * r;
+                            FtR[(b * D + ax) * nv + m] += sb * pm * r;
+                        }
+                    }
+                }
+            }
+    }
+    free(p);
+}
+
+/* Joint KKT matrix of N agents (one axis), row-major, size N (n_v + 4):
+ * variables agent-major, then the 4 N boundary multipliers. */
+int orc_agents_kkt_matrix(const orc_problem *pr, int N, double *K)
+{
+    int nv = pr->degree + 1, np = pr->n_steps, S = N * (nv + 4), a, b, i, j, k;
+    double *A = malloc(sizeof(double) * 4 * nv), *H = malloc(sizeof(double) * nv * nv);
+    double *P = malloc(sizeof(double) * np * nv), *Pd = malloc(sizeof(double) * np * nv),
+           *Pdd = malloc(sizeof(double) * np * nv), *G = malloc(sizeof(double) * nv * nv);
+    int rc = orc_constraint_matrices(pr, A, H);
+    if (rc == 0) rc = orc_bernstein(pr->degree, np, pr->horizon, P, Pd, Pdd);
+    if (rc == 0) {
+        for (i = 0; i < nv; ++i)
+            for (j = 0; j < nv; ++j) {
+                double g = 0.0;
+                for (k = 0; k < np; ++k) g += P[k * nv + i] * P[k * nv + j];
+                G[i * nv + j] = pr->rho * g;
+            }
+        memset(K, 0, sizeof(double) * S * S);
+        for (a = 0; a < N; ++a)
+            for (i = 0; i < nv; ++i)
+                for (j = 0; j < nv; ++j) K[(a * nv + i) * S + a * nv + j] = H[i * nv + j];
+        /* rho (P_a - P_b)^T (P_a - P_b) for every pair */
+        for (a = 0; a < N; ++a)
+            for (b = a + 1; b < N; ++b)
+                for (i = 0; i < nv; ++i)
+                    for (j = 0; j < nv; ++j) {
+                        double g = G[i * nv + j];
+                        K[(a * nv + i) * S + a * nv + j] += g;
+                        K[(b * nv + i) * S + b * nv + j] += (g_fault == 7) ? 2.0 * g : g;
+                        K[(a * nv + i) * S + b * nv + j] -= g;
+                        K[(b * nv + i) * S + a * nv + j] -= g;
+                    }
+        for (a = 0; a < N; ++a)
+            for (i = 0; i < 4; ++i)
+                for (j = 0; j < nv; ++j) {
+                    K[(N * nv + a * 4 + i) * S + a * nv + j] = A[i * nv + j];
+                    K[(a * nv + j) * S + N * nv + a * 4 + i] = A[i * nv + j];
+                }
+    }
+    free(A); free(H); free(P); free(Pd); free(Pdd); free(G);
+    return rc;
+}
+
+/* One joint QP (one axis): out = argmin sum_a 1/2 x_a^T H x_a
+ *   + rho/2 sum_{a<b} |P (x_a - x_b)|^2 - sum_a q_a^T x_a   s.t. A x_a = b_a.
+ * q, out: [N][n_v]; b: [N][4]. */
+int orc_agents_qp(const orc_problem *pr, int N, const double *q, const double *b, double *out)
+{
+    int nv = pr->degree + 1, S = N * (nv + 4), i, rc;
+    double *K = malloc(sizeof(double) * S * S), *x = malloc(sizeof(double) * S);
+    int *piv = malloc(sizeof(int) * S);
+    rc = orc_agents_kkt_matrix(pr, N, K);
+    if (rc == 0) rc = orc_lu_factor(S, K, piv);
+    if (rc == 0) {
+        for (i = 0; i < N * nv; ++i) x[i] = q[i];
+        for (i = 0; i < 4 * N; ++i) x[N * nv + i] = b[i];
+        orc_lu_solve(S, K, piv, x);
+        for (i = 0; i < N * nv; ++i) out[i] = x[i];
+    }
+    free(K); free(x); free(piv);
+    return rc;
+}
+
+/* Steps 1-4 of the joint problem at xb ([N][D][n_v]): FtE, FtR ([N][D][n_v], may be
+ * NULL), r2 = |F xb - e|^2 over all rows of all agents and pairs, rmax. */
+static void agents_polar(const orc_ctx *c, int N, double R, const double *xb, double *FtE,
+                         double *FtR, double *r2, double *rmax)
+{
+    int D = c->D, nv = c->nv, a;
+    double acc = 0.0, mx = 0.0;
+    for (a = 0; a < N; ++a) {
+        double ra, ma;
+        polar_and_residual(c, xb + (size_t)a * D * nv, FtE ? FtE + (size_t)a * D * nv : NULL,
+                           FtR ? FtR + (size_t)a * D * nv : NULL, &ra, &ma);
+        acc += ra;
+        if (ma > mx) mx = ma;
+    }
+    pair_rows(c, N, R, xb, FtE, FtR, &acc, &mx);
+    *r2 = acc;
+    *rmax = mx;
+}
+
+static int agents_ctx(const orc_problem *pr, const double *oc, const double *ow,
+                      const double *os, orc_ctx *c, double **bufs)
+{
+    int nv = pr->degree + 1, np = pr->n_steps;
+    bufs[0] = malloc(sizeof(double) * np * nv);
+    bufs[1] = malloc(sizeof(double) * np * nv);
+    bufs[2] = malloc(sizeof(double) * np * nv);
+    if (orc_bernstein(pr->degree, np, pr->horizon, bufs[0], bufs[1], bufs[2]) != 0) return -1;
+    c->pr = pr; c->nv = nv; c->np = np; c->D = pr->dims;
+    c->P = bufs[0]; c->Pd = bufs[1]; c->Pdd = bufs[2]; c->oc = oc; c->ow = ow; c->os = os;
+    return 0;
+}
+
+/* F^T e, F^T r and |r|^2 of the joint problem at one joint coefficient vector. */
+int orc_agents_polar_products(const orc_problem *pr, int N, double R, const double *xb,
+                              const double *oc, const double *ow, const double *os,
+                              double *FtE, double *FtR, double *r2)
+{
+    int D = pr->dims, nv = pr->degree + 1, rc;
+    double *bufs[3] = {NULL, NULL, NULL}, mx;
+    orc_ctx c;
+    rc = agents_ctx(pr, oc, ow, os, &c, bufs);
+    if (rc == 0) {
+        if (FtE) memset(FtE, 0, sizeof(double) * N * D * nv);
+        if (FtR) memset(FtR, 0, sizeof(double) * N * D * nv);
+        agents_polar(&c, N, R, xb, FtE, FtR, r2, &mx);
+    }
+    free(bufs[0]); free(bufs[1]); free(bufs[2]);
+    return rc;
+}
+
+/* Projects B joint samples of N agents.  Layouts (row-major, float64):
+ *   xi, xi_bar, lam : [B][N][D][n_v];  bnd : [N][D][4];  obstacles as orc_project;
+ *   res_trace, resmax_trace : [iters][B] (may be NULL).  R = combined radius. */
+int orc_project_agents(const orc_problem *pr, int N, double R, int B, const double *xi,
+                       const double *oc, const double *ow, const double *os,
+                       const double *bnd, double *xi_bar, double *lam, int iters,
+                       double *res_trace, double *resmax_trace, int n_threads)
+{
+    int D = pr->dims, nv = pr->degree + 1, S = N * (nv + 4), rc = 0, i;
+    double *bufs[3] = {NULL, NULL, NULL}, *K = NULL;
+    int *piv = NULL;
+    orc_ctx c;
+    if ((D != 2 && D != 3) || pr->degree < 3 || pr->n_steps < 2 || N < 1 || B < 0 ||
+        iters < 0 || !(R >= 0.0))
+        return -1;
+    K = malloc(sizeof(double) * S * S);
+    piv = malloc(sizeof(int) * S);
+    if (agents_ctx(pr, oc, ow, os, &c, bufs) != 0 || orc_agents_kkt_matrix(pr, N, K) != 0 ||
+        orc_lu_factor(S, K, piv) != 0) {
+        rc = -1;
+        goto done;
+    }
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (i = 0; i < B; ++i) {
+        size_t J = (size_t)N * D * nv;
+        double *xb = xi_bar + i * J, *lm = lam + i * J;
+        const double *x0 = xi + i * J;
+        double *FtE = malloc(sizeof(double) * J), *FtR = malloc(sizeof(double) * J);
+        double *rhs = malloc(sizeof(double) * S);
+        int k, a, ax, m;
+        for (k = 0; k < iters; ++k) {
+            double r2, rmax;
+            memset(FtE, 0, sizeof(double) * J);
+            memset(FtR, 0, sizeof(double) * J);
+            agents_polar(&c, N, R, xb, FtE, FtR, &r2, &rmax);
+            if (res_trace) res_trace[(size_t)k * B + i] = sqrt(r2);
+            if (resmax_trace) resmax_trace[(size_t)k * B + i] = rmax;
+            for (m = 0; m < (int)J; ++m) lm[m] -= pr->rho * FtR[m];
+            for (ax = 0; ax < D; ++ax) {
+                for (a = 0; a < N; ++a) {
+                    for (m = 0; m < nv; ++m) {
+                        size_t g = ((size_t)a * D + ax) * nv + m;
+                        rhs[a * nv + m] = x0[g] + lm[g] + pr->rho * FtE[g];
+                    }
+                    for (m = 0; m < 4; ++m) rhs[N * nv + a * 4 + m] = bnd[(a * D + ax) * 4 + m];
+                }
+                orc_lu_solve(S, K, piv, rhs);
+                for (a = 0; a < N; ++a)
+                    for (m = 0; m < nv; ++m) xb[((size_t)a * D + ax) * nv + m] = rhs[a * nv + m];
+            }
+        }
+        free(FtE); free(FtR); free(rhs);
+    }
+done:
+    free(bufs[0]); free(bufs[1]); free(bufs[2]); free(K); free(piv);
+    return rc;
+}
+
+/* Joint residuals at xb ([B][N][D][n_v]): res_l2[B], res_max[B]. */
+int orc_residuals_agents(const orc_problem *pr, int N, double R, int B, const double *xi_bar,
+                         const double *oc, const double *ow, const double *os, double *res_l2,
+                         double *res_max, int n_threads)
+{
+    int D = pr->dims, nv = pr->degree + 1, rc, i;
+    double *bufs[3] = {NULL, NULL, NULL};
+    orc_ctx c;
+    rc = agents_ctx(pr, oc, ow, os, &c, bufs);
+    if (rc == 0) {
+#ifdef _OPENMP
+        if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+        for (i = 0; i < B; ++i) {
+            double r2, mx;
+            agents_polar(&c, N, R, xi_bar + (size_t)i * N * D * nv, NULL, NULL, &r2, &mx);
+            res_l2[i] = sqrt(r2);
+            if (res_max) res_max[i] = mx;
+        }
+    }
+    free(bufs[0]); free(bufs[1]); free(bufs[2]);
+    return rc;
+}

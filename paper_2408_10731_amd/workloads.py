@@ -214,6 +214,72 @@ def problem3d(seed: int, n_obs: int, batch: int, iters: int = 50) -> Workload:
                     boundary_rows(start, goal), xi, iters, "fp32")
 
 
+def _far_from(c, s, points, clearance):
+    reach = s.max() + clearance
+    return all(np.linalg.norm(c - q) > reach for q in points)
+
+
+def agents3d(seed: int, n_agents: int, n_obs: int, batch: int, iters: int = 50,
+             radius: float = 8.0, agent_radius: float = 0.3, sigma: float = 0.5) -> Workload:
+    """N agents in 3D: evenly spaced on a horizontal circle (radius 8 m, z = 3, random
+    phase), each flying to its antipode in 10 s; agent radius 0.3 m (pair clearance
+    0.6 m); static spheres r~U(0.3,1.0) in [-10,10]^2 x [0,6], kept 0.5 m clear of
+    every start and goal; degree 10, 100 steps, v_max = a_max = 3.  xi [B, N, 3, 11]:
+    each agent's straight line plus N(0, sigma^2) per coefficient; boundary [N, 3, 4]."""
+    rng = _rng(seed)
+    phase = rng.uniform(0.0, 2.0 * np.pi)
+    ang = phase + 2.0 * np.pi * np.arange(n_agents) / n_agents
+    starts = np.stack([radius * np.cos(ang), radius * np.sin(ang), np.full(n_agents, 3.0)], 1)
+    goals = starts * np.array([-1.0, -1.0, 1.0])
+    pts = np.concatenate([starts, goals])
+    centre = np.zeros((n_obs, 3))
+    axes = np.zeros((n_obs, 3))
+    for j in range(n_obs):
+        while True:
+            c = rng.uniform((-10, -10, 0), (10, 10, 6))
+            s = np.full(3, rng.uniform(0.3, 1.0))
+            if _far_from(c, s, pts, 0.5):
+                break
+        centre[j] = c
+        axes[j] = s
+    xi = np.stack([line_samples(rng, batch, 10, starts[a], goals[a], sigma)
+                   for a in range(n_agents)], 1)
+    bnd = np.stack([boundary_rows(starts[a], goals[a]) for a in range(n_agents)])
+    return Workload(f"agents3d-N{n_agents}-n{n_obs}-b{batch}", 3, 10, 100, 10.0, 3.0, 3.0, 1.0,
+                    centre, np.zeros((n_obs, 3)), axes, bnd, np.ascontiguousarray(xi), iters,
+                    "fp32", n_agents, agent_radius)
+
+
+def tiny_agents(dims: int = 2, n_agents: int = 3, batch: int = 2, n_obs: int = 1,
+                degree: int = 5, n_steps: int = 9, seed: int = 11,
+                agent_radius: float = 0.4) -> Workload:
+    """A few agents crossing a small square (each to the opposite corner region) for
+    brute-force and by-hand checks of the joint projection."""
+    rng = _rng(seed)
+    ang = rng.uniform(0, 2 * np.pi) + 2 * np.pi * np.arange(n_agents) / n_agents
+    ring = np.stack([2.0 * np.cos(ang), 2.0 * np.sin(ang)], 1)
+    if dims == 3:
+        ring = np.concatenate([ring, rng.uniform(-0.3, 0.3, size=(n_agents, 1))], 1)
+    starts, goals = ring, -ring
+    pts = np.concatenate([starts, goals])
+    centre = np.zeros((n_obs, dims))
+    axes = np.zeros((n_obs, dims))
+    for j in range(n_obs):
+        while True:
+            c = rng.uniform(-1.5, 1.5, size=dims)
+            s = np.full(dims, rng.uniform(0.2, 0.4))
+            if _far_from(c, s, pts, 0.1):
+                break
+        centre[j] = c
+        axes[j] = s
+    xi = np.stack([line_samples(rng, batch, degree, starts[a], goals[a], 0.3)
+                   for a in range(n_agents)], 1)
+    bnd = np.stack([boundary_rows(starts[a], goals[a]) for a in range(n_agents)])
+    return Workload(f"tiny-agents-{dims}d", dims, degree, n_steps, 4.0, 3.0, 4.0, 1.0, centre,
+                    np.zeros((n_obs, dims)), axes, bnd, np.ascontiguousarray(xi), 5, "fp64",
+                    n_agents, agent_radius)
+
+
 def ragged_set(n_problems: int = 256, seed: Optional[int] = None, n_obs=(5, 300),
                batch=(32, 2048), iters: int = 50, dims3_every: int = 2):
     """Many independent problems: n_obs ~ U{n_obs}, batch ~ U{batch} per problem;
