@@ -7,11 +7,13 @@ Workload (one "step"): one full projection of the 2D point-robot problem with
 HBM when the timed region starts.
 
 metric: traj-iters/s = batch * iterations / (wall time of one projection).
-Also reported: time until the batch-median residual first reaches 1e-3 (cold
-start; learned warm start when a trained network is available), the roofline of
-the fused AM kernel (VALU-bound: algorithmic lane-ops / kernel time against the
-chip's 256 CU x 64 lanes x 2.4 GHz), and the FP64 CPU oracle timed on a bounded
-sample of the same workload on the host cores.
+Also reported: time until the batch-median residual first reaches 1e-3 from a cold
+start and from the learned warm start (network trained here first, untimed), the
+roofline of the fused AM kernel (VALU-bound: algorithmic lane-ops / kernel time
+against the chip's 256 CU x 64 lanes x 2.4 GHz), the ragged set of 256 problems
+(half of them multi-agent) in one plan, one graph-replayed planning call of the
+sampling loop, and the FP64 CPU oracle timed on a bounded sample of the main
+workload on the host cores.
 """
 from __future__ import annotations
 
@@ -79,16 +81,16 @@ def _time(fn, reps, stream):
     return e0.elapsed_time(e1) / reps
 
 
-def train_warm_start(w, scenes, epochs, seed0=20_000, batch=1024):
-    """Network of the learned warm start, trained on the GPU on solver-generated scenes
-    of the workload's family (seeds disjoint from the benchmark scene's)."""
+def train_warm_start(w, scenes, epochs, seed0=20_000, batch=512):
+    """Network of the learned warm start, trained on the GPU on solver-generated pairs
+    (probe state -> state at the first residual <= 1e-3) of the workload's family,
+    with scene seeds disjoint from the benchmark scene's."""
     import torch
     from paper_2408_10731_amd import warmstart as ws
     t0 = time.perf_counter()
-    k_obs = w.n_obs
-    data = ws.generate(ws.family_scene("cfg2"), list(range(seed0, seed0 + scenes)), 256, k_obs,
-                       iters=300)
-    net = ws.Net(ws.widths_for(w, k_obs), seed=0, precision=0, max_batch=max(batch, w.batch))
+    data = ws.generate(ws.family_scene("cfg2"), list(range(seed0, seed0 + scenes)), 64,
+                       k0=ws.K0, cap=150)
+    net = ws.Net(ws.widths_for(w), seed=0, precision=0, max_batch=max(batch, w.batch))
     curve = ws.train(net, data, epochs=epochs, batch=batch, lr=1e-3)
     torch.cuda.synchronize()
     info = {"pairs": int(data.x.shape[0]), "scenes": scenes, "epochs": epochs,
@@ -97,47 +99,45 @@ def train_warm_start(w, scenes, epochs, seed0=20_000, batch=1024):
     return net, info
 
 
-def time_to_residual(args, w, solver, xi, obs, stream, tol=1e-3, net=None, info=None):
-    """Iterations and time until the batch-median residual first reaches tol, from a
-    cold start and from the learned warm start.  Times are per replay of a captured
-    graph (cold: resets + projection; warm: features, network, apply, two residual
-    launches, fallback + projection), and the same work launched eagerly."""
+def ttr_scene(w, solver, xi, obs, net, cap, stream, tol=1e-3, reps=20):
+    """Cold vs learned warm start on one scene: AM iterations until the batch-median
+    residual first reaches tol (the warm start's 3-iteration probe included) and the
+    time of that work, per replay of a captured graph (cold: resets + projection;
+    warm: probe, features, fused network, jump, residual, check + projection) and
+    launched eagerly."""
     import torch
     from paper_2408_10731_amd import warmstart as ws
 
-    cap = args.ttr_cap
-    out = {"tol": tol, "cap": cap}
+    out = {}
     tr = torch.zeros((cap, w.batch), dtype=torch.float32, device="cuda")
     xb, lam = xi.clone(), torch.zeros_like(xi)
     solver.project(xi, w.boundary, obs, xb, lam, cap, res_trace=tr)
     torch.cuda.synchronize()
-    hit, _ = median_time_to_residual(tr.cpu().numpy(), tol)
-    out["cold_iters"] = None if hit is None else hit + 1
-    if net is None:
-        net, info = train_warm_start(w, args.ws_scenes, args.ws_epochs)
-    out["warm_training"] = info
-    ctx = ws.WarmContext(solver, net, w, w.n_obs, w.batch)
-    xb0, lam0, fl = ctx.run(xi, obs)
-    trw = torch.zeros_like(tr)
-    solver.project(xi, w.boundary, obs, xb0, lam0, cap, res_trace=trw)
+    ic = ws.iterations_to(tr.cpu().numpy(), tol)
+    out["cold_iters"] = ic
+    ctx = ws.WarmContext(solver, net, w.batch)
+    xw, lw, fl, trp = ctx.run(xi, w.boundary, obs)
+    trw = torch.zeros((cap - ws.K0, w.batch), dtype=torch.float32, device="cuda")
+    solver.project(xi, w.boundary, obs, xw, lw, cap - ws.K0, res_trace=trw)
     torch.cuda.synchronize()
-    hw, _ = median_time_to_residual(trw.cpu().numpy(), tol)
-    out["warm_iters"] = None if hw is None else hw + 1
+    iw = ws.iterations_to(np.concatenate([trp.cpu().numpy(), trw.cpu().numpy()]), tol)
+    out["warm_iters"] = iw
     out["warm_fallbacks"] = int(((fl.cpu().numpy() & 4) != 0).sum())
-    reps = 20
-    if hit is not None:
+    if ic is not None:
         def cold():
             xb.copy_(xi)
             lam.zero_()
-            solver.project(xi, w.boundary, obs, xb, lam, hit + 1)
+            solver.project(xi, w.boundary, obs, xb, lam, ic)
         out["cold_ms_eager"] = _time(cold, reps, stream)
         g = _graph(cold)
         out["cold_ms"] = _time(g.replay, reps, stream)
         del g
-    if hw is not None:
+    if iw is not None:
+        rest = max(iw - ws.K0, 0)
+
         def warm():
-            b0, l0, _ = ctx.run(xi, obs)
-            solver.project(xi, w.boundary, obs, b0, l0, hw + 1)
+            b0, l0, _, _ = ctx.run(xi, w.boundary, obs)
+            solver.project(xi, w.boundary, obs, b0, l0, rest)
         out["warm_ms_eager"] = _time(warm, reps, stream)
         g = _graph(warm)
         out["warm_ms"] = _time(g.replay, reps, stream)
@@ -145,16 +145,49 @@ def time_to_residual(args, w, solver, xi, obs, stream, tol=1e-3, net=None, info=
     return out
 
 
+def time_to_residual(args, w, solver, xi, obs, stream, tol=1e-3, net=None, info=None):
+    """The learned warm start against the cold start: on the benchmark scene, and summed
+    over 8 held-out scenes of the same family (scene seeds disjoint from the training
+    ones); a scene whose median never reaches tol within the cap counts the cap."""
+    import torch
+    from paper_2408_10731_amd import trajam as tj
+    from paper_2408_10731_amd import warmstart as ws
+    from paper_2408_10731_amd import workloads as wl
+
+    cap = args.ttr_cap
+    if net is None:
+        net, info = train_warm_start(w, args.ws_scenes, args.ws_epochs)
+    out = {"tol": tol, "cap": cap, "probe_iters": ws.K0, "warm_training": info,
+           "scene": ttr_scene(w, solver, xi, obs, net, cap, stream, tol)}
+    per, tot = [], {"cold_iters": 0, "warm_iters": 0, "cold_ms": 0.0, "warm_ms": 0.0}
+    for seed in range(90_001, 90_009):
+        ws_ = wl.config2(batch=w.batch, seed=seed)
+        s = tj.Solver.for_workload(ws_, precision="fp32")
+        x_, o_ = tj.device_workload(ws_, torch.float32)
+        r = ttr_scene(ws_, s, x_, o_, net, cap, stream, tol, reps=10)
+        s.close()
+        per.append({"seed": seed, **{k: r.get(k) for k in ("cold_iters", "warm_iters",
+                                                           "cold_ms", "warm_ms")}})
+        tot["cold_iters"] += r["cold_iters"] if r["cold_iters"] is not None else cap
+        tot["warm_iters"] += r["warm_iters"] if r["warm_iters"] is not None else cap
+        tot["cold_ms"] += r.get("cold_ms", float("nan"))
+        tot["warm_ms"] += r.get("warm_ms", float("nan"))
+    out["held_out"] = {"scenes": per, "total": tot}
+    return out
+
+
 def ragged_bench(args):
-    """Many independent problems in one persistent launch: n_obs ~ U{5..300}, batch ~
-    U{32..2048}; even problems are 2D (config-2 geometry), odd ones 3D single-robot
-    sphere problems (degree 10, 100 steps).  Times the eager launch and the same launch
-    replayed from a captured graph; reports traj-iters/s over the whole set."""
+    """Ragged set of many independent problems in one plan: n_obs ~ U{5..300}, batch ~
+    U{32..2048}; even problems are 2D single robots (config-2 geometry), odd ones 3D
+    multi-agent problems with N ~ U{16..64} agents (pair clearance 0.6 m; a batch entry
+    is a joint sample).  Times the eager launch and the same launch replayed from a
+    captured graph; reports trajectory-iterations per second over the whole set (a
+    joint sample of N agents counts N trajectories)."""
     import torch
     from paper_2408_10731_amd import trajam as tj
     from paper_2408_10731_amd import workloads as wl
 
-    ws = wl.ragged_set(args.ragged_problems, iters=args.iters)
+    ws = wl.config5(args.ragged_problems, iters=args.iters)
     K = args.iters
     solvers, items, keep = [], [], []
     for w in ws:
@@ -204,19 +237,60 @@ def ragged_bench(args):
     e1.record(stream)
     torch.cuda.synchronize()
     graph_ms = e0.elapsed_time(e1) / args.ragged_steps
-    samples = sum(w.batch for w in ws)
-    ops = sum(algorithmic_ops_per_traj_iter(w) * w.batch for w in ws) * K
+    trajs = sum(w.batch * w.n_agents for w in ws)
     kern = float(np.mean(launch_ms))
-    out = {"problems": len(ws), "samples": samples, "iterations": K,
-           "launch_ms": kern, "graph_step_ms": graph_ms,
-           "traj_iters_per_s": samples * K / (graph_ms * 1e-3),
-           "alu_frac": ops / (kern * 1e-3) / PEAK_VALU_OPS,
-           "mix": "even problems 2D (config-2 geometry), odd 3D single robot; "
-                  "n_obs~U{5..300}, batch~U{32..2048}; graph step includes the resets"}
+    elements = sum(w.batch * (w.n_agents * w.n_obs + w.n_agents * (w.n_agents - 1) // 2)
+                   * w.n_steps for w in ws)
+    out = {"problems": len(ws), "multi_agent_problems": sum(w.n_agents > 1 for w in ws),
+           "joint_samples": sum(w.batch for w in ws), "trajectories": trajs,
+           "iterations": K, "launch_ms": kern, "graph_step_ms": graph_ms,
+           "traj_iters_per_s": trajs * K / (graph_ms * 1e-3),
+           "polar_elements_per_s": elements * K / (kern * 1e-3),
+           "mix": "even problems 2D single robot (config-2 geometry), odd 3D multi-agent "
+                  "N~U{16..64}; n_obs~U{5..300}, batch~U{32..2048}; graph step includes "
+                  "the resets"}
     del g
     plan.close()
     for s in solvers:
         s.close()
+    return out
+
+
+def cem_bench(args):
+    """One planning call of the projection-guided sampling loop at config-4 sizes:
+    30 iterations, each drawing 2000 samples, projecting them with 15 AM iterations
+    (100 moving circles), selecting 1454 by residual and 363 elites by cost, and
+    updating the Gaussian; the whole call replayed from one captured graph."""
+    import torch
+    from paper_2408_10731_amd import cem
+    from paper_2408_10731_amd import trajam as tj
+    from paper_2408_10731_amd import workloads as wl
+
+    w = wl.config4(batch=4)
+    D, nv = w.dims, w.n_v
+    N, Nb, Np, Ne, K = 30, 2000, 1454, 363, 15
+    solver = tj.Solver.for_workload(w, precision="fp32", max_batch=Nb)
+    _, obs = tj.device_workload(w, torch.float32)
+    planner = cem.Planner(solver, Nb, Np, Ne, K)
+    mu0 = wl.line_samples(np.random.default_rng(0), 1, w.degree, w.boundary[:, 0],
+                          w.boundary[:, 3], 0.0)[0].reshape(-1)
+    S0 = 0.25 * np.eye(D * nv)
+    L0 = np.linalg.cholesky(S0 + 1e-10 * np.eye(D * nv))
+    z = torch.as_tensor(np.random.default_rng(1).normal(size=(N, Nb, D * nv)),
+                        dtype=torch.float32, device="cuda")
+    planner.set_distribution(mu0, S0, L0)
+    planner.capture(z, w.boundary, obs)
+    stream = torch.cuda.current_stream()
+
+    def call():
+        planner.set_distribution(mu0, S0, L0)
+        planner.replay()
+
+    ms = _time(call, args.cem_calls, stream)
+    out = {"config": "30 CEM iterations x 2000 samples x 15 AM iterations, 100 moving "
+                     "circles, 1454 projected / 363 elite, fp32, one graph replay per call",
+           "ms_per_planning_call": ms, "traj_iters_per_s": N * Nb * K / (ms * 1e-3)}
+    solver.close()
     return out
 
 
@@ -241,10 +315,11 @@ def main():
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ttr-cap", type=int, default=300)
-    ap.add_argument("--ws-scenes", type=int, default=1024)
-    ap.add_argument("--ws-epochs", type=int, default=40)
+    ap.add_argument("--ws-scenes", type=int, default=2048)
+    ap.add_argument("--ws-epochs", type=int, default=20)
     ap.add_argument("--ragged-problems", type=int, default=256, help="0 skips the ragged set")
     ap.add_argument("--ragged-steps", type=int, default=3)
+    ap.add_argument("--cem-calls", type=int, default=5, help="0 skips the sampling loop")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -305,6 +380,7 @@ def main():
 
     ttr = time_to_residual(args, w, solver, xi, obs, stream) if args.ttr_cap > 0 else None
     ragged = ragged_bench(args) if args.ragged_problems > 0 else None
+    cem_out = cem_bench(args) if args.cem_calls > 0 else None
 
     out = {
         "metric": "traj-iters/s & time-to-residual<=1e-3, learned warm-start vs cold, 1 MI355X",
@@ -319,6 +395,7 @@ def main():
         "roofline": roofline,
         "time_to_residual": ttr,
         "ragged": ragged,
+        "cem": cem_out,
         "wall_s_timed_region": wall,
     }
     if not args.no_cpu:

@@ -89,8 +89,12 @@ typedef struct {
     double a_max;          /* > 0: acceleration bound; <= 0 removes that block from F */
     double rho;            /* augmented-Lagrangian weight, > 0 */
     int32_t n_obstacles;   /* n_o >= 0; each obstacle adds one copy of P to F */
-    int32_t n_agents;      /* 1 (single robot); other values are rejected by this build */
-    double agent_radius;   /* unused when n_agents == 1 */
+    int32_t n_agents;      /* 1 (single robot) or N in [2, 64] agents planned jointly
+                              (thesis ch. 8): each agent has every single-robot row and
+                              every unordered pair of agents adds one row per time
+                              sample keeping them 2 * agent_radius apart; needs
+                              precision FP64 or FP32 and degree <= 11 */
+    double agent_radius;   /* > 0 when n_agents > 1 [m]; unused otherwise */
     int32_t max_batch;     /* largest batch a call may pass (>= 1) */
     int32_t precision;     /* a trajam_precision value */
     int32_t obstacle_model; /* a trajam_obstacle_model value */
@@ -101,8 +105,13 @@ typedef struct trajam_solver trajam_solver; /* opaque; owns device constants */
 /* Validates `p`, computes the fixed matrices in double on the host (Bernstein
  * basis, H = I + rho F^T F, the inverse of its free block), uploads them and
  * returns a handle in *out.  Uses the current HIP device.
- * Errors: INVALID (bad field), UNSUPPORTED (n_agents != 1), NUMERIC (H not
- * positive definite), DEVICE (allocation / copy failed).  On error *out is NULL. */
+ * For n_agents > 1 it also builds the operator of the agents' deviations from their
+ * mean (the pair rows' Gram is the complete-graph Laplacian, so the joint QP splits
+ * exactly into the agent mean, moved by the single-robot operator, and the
+ * deviations, moved by the operator of H + n_agents rho P^T P).
+ * Errors: INVALID (bad field), UNSUPPORTED (a multi-agent problem in BF16_REFINE or
+ * with degree > 11), NUMERIC (H not positive definite), DEVICE (allocation / copy
+ * failed).  On error *out is NULL. */
 trajam_status trajam_init(const trajam_problem *p, trajam_solver **out);
 
 /* Frees the handle and its device memory (never the caller's buffers).  NULL is a
@@ -126,6 +135,15 @@ void trajam_destroy(trajam_solver *s);
  *   stream        hipStream_t or NULL
  * The state of the iteration is (xi_bar, lambda), so a call with iters = a followed
  * by a call with iters = b gives the same result as one call with iters = a + b.
+ * Multi-agent problems (n_agents = N > 1): a sample is a joint sample of N
+ * trajectories, so xi, xi_bar and lambda are [batch][N][dims][n+1] and
+ * boundary_host is [N][dims][4]; res_trace and flags stay per joint sample, and the
+ * residual covers every row of every agent and every pair once.  Each agent has the
+ * obstacle and kinematic rows; a pair's row targets the exterior of a sphere of
+ * radius 2 * agent_radius around the other agent (eqs sphere_proposed to com_d_i).
+ * The per-agent boundary coefficients live on the device and are re-uploaded only
+ * when boundary_host changes; such a call synchronizes the stream (so, under graph
+ * capture, keep the boundary of the captured call).
  * Errors: INVALID (NULL handle or required pointer, iters < 0, batch < 0),
  * CAPACITY (batch > max_batch), DEVICE (launch failed).  batch == 0 or iters == 0
  * is a successful no-op. */
@@ -137,7 +155,7 @@ trajam_status trajam_project(trajam_solver *s, int32_t batch, const void *xi,
 
 /* Steps (a) and the residual norm only, at the given coefficients, without
  * touching any multiplier (thesis Alg 3, "compute the residuals set r").
- *   xi_bar   device, [batch][dims][n+1]
+ *   xi_bar   device, [batch][dims][n+1] ([batch][N][dims][n+1] for N > 1 agents)
  *   res_l2   device, [batch]: |F xb - e|_2
  *   res_max  device, [batch] or NULL: largest |component| of F xb - e
  * Errors: as trajam_project. */
@@ -208,15 +226,19 @@ trajam_status trajam_autotune(trajam_solver *s, int32_t batch, const void *xi,
  * Each item is one problem (its own solver, hence fixed matrices and obstacles, and
  * its own batch).  A plan uploads the problem table once; every launch zeroes a
  * device work counter and runs one persistent kernel whose waves take (problem,
- * sample) units longest-problem-first until none is left.  Launches never allocate
- * or synchronize, so they can be captured in a graph.  Restrictions of this build:
- * FP32 solvers, degree <= 11, n_steps <= 128, obstacles set with
- * trajam_set_obstacles before the plan is created. */
+ * sample) units longest-problem-first until none is left (single-robot and
+ * multi-agent problems each have their own table, counter and kernel, launched one
+ * after the other).  Launches never allocate or synchronize, so they can be
+ * captured in a graph.  Multi-agent items take [batch][N][dims][n+1] buffers and
+ * [N][dims][4] boundary rows.  Restrictions of this build: FP32 solvers,
+ * degree <= 11, n_steps <= 128, obstacles set with trajam_set_obstacles before the
+ * plan is created. */
 typedef struct {
     trajam_solver *solver;       /* problem class (FP32) */
     int32_t batch;               /* samples of this problem (<= max_batch) */
     const void *xi;              /* device [batch][dims][degree+1] */
-    const double *boundary_host; /* host [dims][4], read at plan creation */
+    const double *boundary_host; /* host [dims][4] ([N][dims][4] for N agents), read at
+                                    plan creation */
     void *xi_bar;                /* device in/out, as trajam_project */
     void *lambda;                /* device in/out */
     void *res_trace;             /* device [iters][batch] float or NULL */
@@ -285,7 +307,7 @@ trajam_status trajam_cem_update(trajam_solver *s, int32_t n_elite, const int32_t
  * precision: 0 = fp32 products on the VALU, 1 = bf16 products on matrix cores with
  * fp32 accumulation. */
 #define TRAJAM_MLP_MAX_LAYERS 8
-#define TRAJAM_FLAG_COLD_FALLBACK 4u /* warm start rejected; the sample started cold */
+#define TRAJAM_FLAG_COLD_FALLBACK 4u /* warm start rejected; the sample continues from its cold probe */
 
 typedef struct {
     int32_t n_layers;                          /* 1 .. TRAJAM_MLP_MAX_LAYERS */
@@ -301,6 +323,13 @@ trajam_status trajam_mlp_param_count(const trajam_mlp_shape *shape, int64_t *n_p
 trajam_status trajam_mlp_forward(const trajam_mlp_shape *shape, int32_t batch, int32_t precision,
                                  const float *params, const float *x, float *acts, float *y,
                                  void *stream);
+
+/* Inference only: y [batch][width[L]] = network(x) in one launch (fp32 products,
+ * activations kept on chip; every width <= 512).  Same result as
+ * trajam_mlp_forward with precision 0 up to the order of the sums.
+ * Errors: INVALID, UNSUPPORTED (a width above 512), DEVICE. */
+trajam_status trajam_mlp_infer(const trajam_mlp_shape *shape, int32_t batch, const float *params,
+                               const float *x, float *y, void *stream);
 
 /* grads [n_params] = d loss / d params given dy = d loss / d y [batch][width[L]], the
  * input x and the activations of the forward call.  scratch: 2 * batch * max hidden
@@ -320,30 +349,35 @@ trajam_status trajam_mlp_adam(int64_t n, float *params, const float *grads, floa
                               int32_t step, float lr, float beta1, float beta2, float eps,
                               void *stream);
 
-/* Network input rows x[b] = [scene [n_scene], (xi[b] - line) * inv_scale] for b < batch;
- * xi [batch][dims][n_coeffs], line [dims][n_coeffs].  Errors: INVALID, DEVICE. */
-trajam_status trajam_warm_features(int32_t batch, int32_t dims, int32_t n_coeffs, int32_t n_scene,
-                                   const float *scene, const float *xi, const float *line,
-                                   float inv_scale, float *x, void *stream);
+/* The warm start is a learned jump of the AM state: a short cold probe (k0 AM
+ * iterations with trajam_project from xi_bar = xi, lambda = 0) gives the state
+ * (xb, lam); the network maps it to the state at which the cold iteration would
+ * first reach the residual tolerance, (xb + d_xb, lam + d_lam); a per-sample check
+ * keeps the probe state wherever the jump does not lower the residual.
+ *
+ * Network input rows x[b] = [(xb[b] - xi[b]), lam[b]] * inv_scale, each
+ * [dims][n_coeffs]: x is [batch][2 * dims * n_coeffs].  Errors: INVALID, DEVICE. */
+trajam_status trajam_warm_features(int32_t batch, int32_t dims, int32_t n_coeffs, const float *xi,
+                                   const float *xb, const float *lam, float inv_scale, float *x,
+                                   void *stream);
 
-/* Warm start from the network output y [batch][dims * n_coeffs]: delta = y * out_scale;
- * on the free coefficients xi_bar0 = xi + delta and lambda0 = delta (at a converged
- * fixed point the multiplier equals xb - xi there); on the boundary coefficients
- * (0, 1, 2, n) lambda0 = 0 and xi_bar0 = boundary_coeffs, the host array
- * [dims][4] = (xi_0, xi_1, xi_2, xi_n) per axis that trajam_boundary_coefficients
- * returns (dims <= 3; NULL: xi + delta there too).  A sample with a non-finite
- * prediction starts cold (xi_bar0 = xi, lambda0 = 0) and gets
- * TRAJAM_FLAG_COLD_FALLBACK (flags may be NULL).  Errors: INVALID, DEVICE. */
+/* Jump from the network output y [batch][dims * n_coeffs] = d_xb / out_scale: on the
+ * free coefficients (3 .. n-1) xb_out = xb + out_scale * d_xb and lam_out = xb_out - xi;
+ * on the boundary ones xb_out = xb (already exact) and lam_out = lam.  Outputs must
+ * not alias xb or lam (the fallback needs the probe state).  Errors: INVALID, DEVICE. */
 trajam_status trajam_warm_apply(int32_t batch, int32_t dims, int32_t n_coeffs, const float *y,
-                                const float *xi, float out_scale, const double *boundary_coeffs,
-                                float *xi_bar0, float *lambda0, uint32_t *flags, void *stream);
+                                float out_scale, const float *xi, const float *xb, const float *lam,
+                                float *xb_out, float *lam_out, void *stream);
 
-/* Per-sample fallback: where res_warm[b] > res_cold[b] (or is NaN) the sample restarts
- * cold (xi_bar0 = xi, lambda0 = 0) and gets TRAJAM_FLAG_COLD_FALLBACK.
+/* Per-sample fallback: where res_warm[b] (residual of the jumped state xb) is not
+ * below res_cold[b] (the probe's last residual), or is NaN, or the jumped state is
+ * not finite, the sample keeps the probe state (xb = xb_src, lam = lam_src) and
+ * flags[b] = TRAJAM_FLAG_COLD_FALLBACK; otherwise flags[b] = 0 (flags may be NULL).
  * Errors: INVALID, DEVICE. */
 trajam_status trajam_warm_fallback(int32_t batch, int32_t dims, int32_t n_coeffs,
-                                   const float *res_warm, const float *res_cold, const float *xi,
-                                   float *xi_bar0, float *lambda0, uint32_t *flags, void *stream);
+                                   const float *res_warm, const float *res_cold, const float *xb_src,
+                                   const float *lam_src, float *xb, float *lam, uint32_t *flags,
+                                   void *stream);
 
 /* Static description of a status code.  Never NULL. */
 const char *trajam_status_string(trajam_status st);

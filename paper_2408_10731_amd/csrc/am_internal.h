@@ -44,6 +44,12 @@ struct AmArgs {
     const uint16_t *Whi;    // [16][16] bf16 bits of W_ff = H_ff^-1 (zero padded)
     const uint16_t *Wlo;    // [16][16] bf16 bits of W_ff - Whi
     const float *Hmq;       // H_ff [16][16] then H_fb [16][4] (coefficients 0, 1, 2, n), fp32
+    // Multi-agent problems (n_agents > 1): samples are joint samples of n_agents
+    // trajectories, xi / xb / lam are [batch][n_agents][D][nv].
+    int n_agents;
+    T pair_r;               // combined radius of a pair (twice the agent radius)
+    const T *W2;            // [NVP][NVP] QP operator of H + n_agents rho P^T P (agent deviations)
+    const T *xiB_ag;        // [n_agents][D][4] boundary coefficients per agent
 };
 
 // Packed obstacle record length (scalars), any dims.
@@ -68,6 +74,12 @@ hipError_t launch_project_f64(int dims, int nvp, int variant, const AmArgs<doubl
 hipError_t launch_project_f32(int dims, int nvp, int variant, bool mfma_qp,
                               const AmArgs<float> &a, hipStream_t st);
 hipError_t launch_residual_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st);
+// Multi-agent joint projection / residuals: one wave per joint sample, one lane per
+// agent (n_agents <= 64, nvp 8 or 12), a.tb joint samples per workgroup.
+hipError_t launch_agents_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st);
+hipError_t launch_agents_f32(int dims, int nvp, const AmArgs<float> &a, hipStream_t st);
+hipError_t launch_agents_residual_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st);
+hipError_t launch_agents_residual_f32(int dims, int nvp, const AmArgs<float> &a, hipStream_t st);
 hipError_t launch_residual_f32(int dims, int nvp, const AmArgs<float> &a, hipStream_t st);
 hipError_t launch_pack_obstacles_f64(int dims, int n_o, const double *c, const double *w,
                                      const double *s, double *out, double *soa, hipStream_t st);
@@ -94,22 +106,18 @@ hipError_t launch_colsum(int rows, int cols, const float *d, float *out, hipStre
 hipError_t launch_mse(long count, const float *y, const float *t, float *dy, float *loss, hipStream_t st);
 hipError_t launch_adam(long n, float *p, const float *g, float *m, float *v, int step, float lr, float b1,
                        float b2, float eps, hipStream_t st);
-hipError_t launch_warm_features(int batch, int dim, int n_scene, const float *scene, const float *xi,
-                                const float *line, float inv_scale, float *X, hipStream_t st);
-// Boundary coefficients (xi_0, xi_1, xi_2, xi_n per axis) written exactly by the warm
-// start; set = 0 leaves xi + delta there.
-struct WarmBoundary {
-    float c[3][4];
-    int set;
-};
-hipError_t launch_warm_apply(int batch, int dims, int nv, const float *y, const float *xi, float out_scale,
-                             const WarmBoundary &bc, float *xb0, float *lam0, uint32_t *flags, hipStream_t st);
-hipError_t launch_warm_fallback(int batch, int dim, const float *rw, const float *rc, const float *xi,
-                                float *xb0, float *lam0, uint32_t *flags, hipStream_t st);
+hipError_t launch_warm_features(int batch, int dim, const float *xi, const float *xb, const float *lam,
+                                float inv_scale, float *X, hipStream_t st);
+hipError_t launch_warm_apply(int batch, int dims, int nv, const float *y, float out_scale, const float *xi,
+                             const float *xb, const float *lam, float *xbo, float *lamo, hipStream_t st);
+hipError_t launch_mlp_infer(int n_layers, const int *width, int batch, const float *params, const float *x,
+                            float *y, hipStream_t st);
+hipError_t launch_warm_fallback(int batch, int dim, const float *rw, const float *rc, const float *xs,
+                                const float *ls, float *xb, float *lam, uint32_t *flags, hipStream_t st);
 
 // Ragged persistent launch (FP32): zeroes the counter, then runs the work queue.
 hipError_t launch_ragged(const AmArgs<float> *probs, const int *offsets, int n_probs, int total, int *counter,
-                         int blocks, hipStream_t st);
+                         int blocks, bool agents, hipStream_t st);
 
 // Dynamic LDS bytes of one AM workgroup.
 size_t project_lds_bytes(int dims, int nvp, int tpad, int tb, size_t scalar);

@@ -179,6 +179,22 @@ __device__ __forceinline__ T wave_max(T v)
     return fmax(a, b);
 }
 
+template <typename T>
+__device__ __forceinline__ T wave_min(T v)
+{
+    v = fmin(v, dpp<kDppXor1>(v));
+    v = fmin(v, dpp<kDppXor2>(v));
+    v = fmin(v, dpp<kDppHalfMirror>(v));
+    v = fmin(v, dpp<kDppRor8>(v));
+    T a = v, b = v;
+    swap16(a, b);
+    v = fmin(a, b);
+    a = v;
+    b = v;
+    swap32(a, b);
+    return fmin(a, b);
+}
+
 constexpr int pow2ceil(int x) { return x <= 1 ? 1 : 2 * pow2ceil((x + 1) / 2); }
 
 // Obstacle data is read through the constant address space: the address is
@@ -360,6 +376,139 @@ __device__ __forceinline__ void obstacle_residuals1(const T *soa_g, const T *aos
     for (int ax = 0; ax < D; ++ax) R[ax] = R1[0][ax];
 }
 
+template <typename T>
+__device__ __forceinline__ T readlane_t(T v, int l);
+template <>
+__device__ __forceinline__ float readlane_t<float>(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <>
+__device__ __forceinline__ double readlane_t<double>(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The same obstacle polar step for the points of one wave, with exact culling: the
+// wave's points span a small box (a stretch of one trajectory), and an obstacle
+// whose bounding box -- swept over the wave's time range for moving obstacles, and
+// widened by a margin far above the rounding of the inside test -- misses that box
+// cannot contain any of the points, so its residual is zero.  Lane j of a chunk
+// tests obstacle j against the box (one vector compare for 64 obstacles); the
+// candidates' fields then come from v_readlane and get exactly the inside test of
+// obstacle_loop, in obstacle order, so the result is bit-identical to testing every
+// obstacle.  Every row stays in F and in H; only provably zero terms are skipped.
+// Must be called by the whole wave (uniform control flow); points that must not
+// contribute sit at -1e30 and are flagged false in `ok`.
+template <typename T, int D, bool SPH, bool DYN, int NPT>
+__device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, int n_o, const T (&tt)[NPT],
+                                                   const T (&p)[NPT][D], const bool (&ok)[NPT],
+                                                   T (&R)[NPT][D], T &r2, T &rmax)
+{
+    const T big = T(1e30);
+    T lo[D], hi[D], tlo = T(0), thi = T(0);
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        T mn = big, mx = -big;
+#pragma unroll
+        for (int i = 0; i < NPT; ++i)
+            if (ok[i]) { mn = fmin(mn, p[i][ax]); mx = fmax(mx, p[i][ax]); }
+        lo[ax] = wave_min(mn);
+        hi[ax] = wave_max(mx);
+    }
+    if (DYN) {
+        T mn = big, mx = -big;
+#pragma unroll
+        for (int i = 0; i < NPT; ++i)
+            if (ok[i]) { mn = fmin(mn, tt[i]); mx = fmax(mx, tt[i]); }
+        tlo = wave_min(mn);
+        thi = wave_max(mx);
+    }
+    if (!(lo[0] <= hi[0])) return;  // no point of this wave takes part
+    const TRAJAM_CONST_AS T *aos = (const TRAJAM_CONST_AS T *)aos_g;
+    const int lane = threadIdx.x & 63;
+    const T tabs = fmax(fabs(tlo), fabs(thi));
+    for (int base = 0; base < n_o; base += 64) {
+        const int j = base + lane;
+        const bool has = j < n_o;
+        const T *o = aos_g + (size_t)(has ? j : 0) * kObstacleRecord;
+        T c[D], w[D], is[D], nr2 = T(0);
+        bool cand = has;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            c[ax] = o[kOC + ax];
+            w[ax] = DYN ? o[kOW + ax] : T(0);
+            if (!SPH) is[ax] = o[kOI + ax];
+            const T e = SPH ? o[kOR] : o[kOS + ax];
+            T cmin = c[ax], cmax = c[ax], m = fma(e, T(1.0001), T(1e-4)) + T(1e-5) * fabs(c[ax]);
+            if (DYN) {
+                const T c1 = fma(-w[ax], tlo, c[ax]), c2 = fma(-w[ax], thi, c[ax]);
+                cmin = fmin(c1, c2);
+                cmax = fmax(c1, c2);
+                m += T(1e-5) * (fabs(w[ax]) * tabs + fabs(cmin) + fabs(cmax));
+            }
+            cand = cand && (cmin - m <= hi[ax]) && (cmax + m >= lo[ax]);
+        }
+        if (SPH) nr2 = o[kONR2];
+        unsigned long long mask = __ballot(cand);
+        while (mask) {
+            const int u = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            T cu[D], wu[D], iu[D];
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) {
+                cu[ax] = readlane_t<T>(c[ax], u);
+                if (DYN) wu[ax] = readlane_t<T>(w[ax], u);
+                if (!SPH) iu[ax] = readlane_t<T>(is[ax], u);
+            }
+            const T nu = SPH ? readlane_t<T>(nr2, u) : T(0);
+#pragma unroll
+            for (int i = 0; i < NPT; ++i) {
+                T dx[D];
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax) {
+                    dx[ax] = p[i][ax] - cu[ax];
+                    if (DYN) dx[ax] = fma(wu[ax], tt[i], dx[ax]);
+                }
+                T acc;
+                if (SPH) {
+                    acc = fma(dx[D - 1], dx[D - 1], nu);
+#pragma unroll
+                    for (int ax = D - 2; ax >= 0; --ax) acc = fma(dx[ax], dx[ax], acc);
+                } else {
+                    acc = T(-1);
+#pragma unroll
+                    for (int ax = D - 1; ax >= 0; --ax) {
+                        const T uu = dx[ax] * iu[ax];
+                        acc = fma(uu, uu, acc);
+                    }
+                }
+                if (acc < T(0))
+                    obstacle_inside<T, D, SPH, DYN>(aos + (size_t)(base + u) * kObstacleRecord, p[i], tt[i], R[i],
+                                                    r2, rmax);
+            }
+        }
+    }
+}
+
+template <typename T, int D, int NPT>
+__device__ __forceinline__ void obstacle_residuals_culled(const T *aos_g, int n_o, int sphere, int dynamic,
+                                                          const T (&tt)[NPT], const T (&p)[NPT][D],
+                                                          const bool (&ok)[NPT], T (&R)[NPT][D], T &r2,
+                                                          T &rmax)
+{
+    if (sphere) {
+        if (dynamic) obstacle_cull_loop<T, D, true, true, NPT>(aos_g, n_o, tt, p, ok, R, r2, rmax);
+        else obstacle_cull_loop<T, D, true, false, NPT>(aos_g, n_o, tt, p, ok, R, r2, rmax);
+    } else {
+        if (dynamic) obstacle_cull_loop<T, D, false, true, NPT>(aos_g, n_o, tt, p, ok, R, r2, rmax);
+        else obstacle_cull_loop<T, D, false, false, NPT>(aos_g, n_o, tt, p, ok, R, r2, rmax);
+    }
+}
+
 // Velocity / acceleration polar step (eqs fv_priest, alpha_v, compute_dv): the
 // residual is v (1 - bound / |v|) outside the ball of radius `bound`, else 0.
 template <typename T, int D>
@@ -531,8 +680,20 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
         T R[D], rv[D], ra[D], r2 = T(0), rmax = T(0);
 #pragma unroll
         for (int ax = 0; ax < D; ++ax) { R[ax] = T(0); rv[ax] = T(0); ra[ax] = T(0); }
+        {
+            const T tt1[1] = {tt};
+            const bool ok1[1] = {valid};
+            T p1[1][D], R1[1][D];
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) {
+                p1[0][ax] = valid ? p[ax] : T(-1e30);
+                R1[0][ax] = T(0);
+            }
+            obstacle_residuals_culled<T, D, 1>(a.obs, a.n_o, a.sphere, a.dynamic, tt1, p1, ok1, R1, r2, rmax);
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) R[ax] = R1[0][ax];
+        }
         if (valid) {
-            obstacle_residuals1<T, D>(a.obs_soa, a.obs, a.n_o, a.sphere, a.dynamic, tt, p, R, r2, rmax);
             if (a.use_v) bound_residual<T, D>(v, a.vmax, rv, r2, rmax);
             if (a.use_a) bound_residual<T, D>(acc, a.amax, ra, r2, rmax);
         }
@@ -764,7 +925,7 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
         for (int i = 0; i < TPL; ++i)
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) { R[i][ax] = T(0); rv[i][ax] = T(0); ra[i][ax] = T(0); }
-        obstacle_residuals<T, D, TPL>(a.obs_soa, a.obs, a.n_o, a.sphere, a.dynamic, tt, p, R, r2, rmax);
+        obstacle_residuals_culled<T, D, TPL>(a.obs, a.n_o, a.sphere, a.dynamic, tt, p, valid, R, r2, rmax);
 #pragma unroll
         for (int i = 0; i < TPL; ++i) {
             if (a.use_v) bound_residual<T, D>(v[i], a.vmax, rv[i], r2, rmax);
@@ -918,8 +1079,271 @@ __global__ __launch_bounds__(kMaxThreads) void am_wave_kernel(AmArgs<T> a)
 }
 
 // ----------------------------------------------------------------------------
+// Multi-agent joint projection (thesis ch. 8 in the projection form of ch. 6).
+// One wave per joint sample, lane a = agent a: each lane keeps its agent's
+// coefficients, multiplier and F^T r in registers and walks the time samples; the
+// basis rows and the obstacles are wave-uniform (scalar loads), and the other
+// agents' positions at the current time come from v_readlane, so the pair rows need
+// no LDS and no barrier.  A pair (a, b) is evaluated by both of its lanes on
+// x~ = p_a - p_b resp. p_b - p_a; the residual of the exterior-of-a-sphere polar
+// step (eqs sphere_proposed, com_alpha_i, com_beta_i, com_d_i) is an odd function of
+// x~, so both lanes get the exact negatives of each other and each adds its own sign;
+// only the exact tie x~ = 0 is not odd, and there the lower-index agent is pushed
+// along +x (2D) / +z (3D) and the other one the opposite way.  The squared residual
+// counts every pair once (lane a < b).
+//
+// Joint QP: with L = N I - 1 1^T the Gram of the pair rows, the free block of the
+// joint Hessian is I (x) A + L (x) B (A = H_ff, B = rho (P^T P)_ff).  Splitting every
+// agent's defect vector u_a (free defect, boundary shift) into the agent mean u_m and
+// the deviation u_a - u_m diagonalizes it exactly: the mean moves by the single-robot
+// operator W and each deviation by W2, the same operator built for H + N rho P^T P.
+
+// Polar step of every (agent, obstacle), kinematic bound and pair row at time t for
+// this lane's position p, velocity v, acceleration acc.  Adds the summed position
+// residual to S and the velocity / acceleration residuals to rv / ra.
+template <typename T, int D, typename A>
+__device__ __forceinline__ void agents_rows(const A &a, int lane, bool active, T tt, const T (&p)[D],
+                                            const T (&v)[D], const T (&acc)[D], T (&S)[D], T (&rv)[D],
+                                            T (&ra)[D], T &r2, T &rmax)
+{
+    const int N = a.n_agents;
+    {
+        T p1[1][D], S1[1][D], tt1[1] = {tt};
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            p1[0][ax] = active ? p[ax] : T(-1e30);
+            S1[0][ax] = T(0);
+        }
+        obstacle_residuals<T, D, 1>(a.obs_soa, a.obs, a.n_o, a.sphere, a.dynamic, tt1, p1, S1, r2, rmax);
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) S[ax] = S1[0][ax];
+    }
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) { rv[ax] = T(0); ra[ax] = T(0); }
+    if (active) {
+        if (a.use_v) bound_residual<T, D>(v, a.vmax, rv, r2, rmax);
+        if (a.use_a) bound_residual<T, D>(acc, a.amax, ra, r2, rmax);
+    }
+    const T R = a.pair_r, R2 = R * R;
+    for (int b = 0; b < N; ++b) {
+        T x[D], nn = T(0);
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            x[ax] = p[ax] - readlane_t<T>(p[ax], b);
+            nn = fma(x[ax], x[ax], nn);
+        }
+        if (active && b != lane && nn < R2) {
+            T r[D];
+            if (nn > T(0)) {
+                const T f = T(1) - R * rsqrt_t(nn);
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax) r[ax] = x[ax] * f;
+            } else {
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax) r[ax] = T(0);
+                r[D == 2 ? 0 : 2] = lane < b ? -R : R;
+            }
+            T rr = T(0);
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) {
+                S[ax] += r[ax];
+                rr = fma(r[ax], r[ax], rr);
+                rmax = fmax(rmax, fabs(r[ax]));
+            }
+            if (lane < b) r2 += rr;
+        }
+    }
+}
+
+// One joint sample's whole projection on one wavefront (n_agents <= 64 lanes).
+template <typename T, int D, int NVP, typename A>
+__device__ __forceinline__ void agents_sample(const A &a, const int sample, const int lane)
+{
+    const int N = a.n_agents, nv = a.nv, n_p = a.n_p;
+    const bool active = lane < N;
+    const TRAJAM_CONST_AS T *phi = (const TRAJAM_CONST_AS T *)a.phi;
+    const TRAJAM_CONST_AS T *W1 = (const TRAJAM_CONST_AS T *)a.W;
+    const TRAJAM_CONST_AS T *W2 = (const TRAJAM_CONST_AS T *)a.W2;
+    T xi[D][NVP], xb[D][NVP], lam[D][NVP], bnd[D][4];
+    const size_t base = ((size_t)sample * N + (active ? lane : 0)) * D * nv;
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+#pragma unroll
+        for (int m = 0; m < NVP; ++m) {
+            const bool real = active && m < nv;
+            xi[ax][m] = real ? a.xi[base + ax * nv + m] : T(0);
+            xb[ax][m] = real ? a.xb[base + ax * nv + m] : T(0);
+            lam[ax][m] = real ? a.lam[base + ax * nv + m] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bnd[ax][i] = active ? a.xiB_ag[((active ? lane : 0) * D + ax) * 4 + i] : T(0);
+    }
+    T res_first = T(0), res_last = T(0);
+    bool nonfinite = false;
+    for (int k = 0; k < a.iters; ++k) {
+        T ftr[D][NVP];
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+            for (int m = 0; m < NVP; ++m) ftr[ax][m] = T(0);
+        T r2 = T(0), rmax = T(0);
+        for (int t = 0; t < n_p; ++t) {
+            const TRAJAM_CONST_AS T *r0 = phi + (size_t)(0 * n_p + t) * NVP;
+            const TRAJAM_CONST_AS T *r1 = phi + (size_t)(1 * n_p + t) * NVP;
+            const TRAJAM_CONST_AS T *rr = phi + (size_t)(2 * n_p + t) * NVP;
+            T p[D], v[D], acc[D];
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) {
+                T sp = T(0), sv = T(0), sa = T(0);
+#pragma unroll
+                for (int m = 0; m < NVP; ++m) {
+                    sp = fma(r0[m], xb[ax][m], sp);
+                    sv = fma(r1[m], xb[ax][m], sv);
+                    sa = fma(rr[m], xb[ax][m], sa);
+                }
+                p[ax] = sp;
+                v[ax] = sv;
+                acc[ax] = sa;
+            }
+            T S[D], rv[D], ra[D];
+            agents_rows<T, D, A>(a, lane, active, T(t) * a.dt, p, v, acc, S, rv, ra, r2, rmax);
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+                for (int m = 0; m < NVP; ++m)
+                    ftr[ax][m] = fma(r0[m], S[ax], fma(r1[m], rv[ax], fma(rr[m], ra[ax], ftr[ax][m])));
+        }
+        const T r2w = wave_sum(r2);
+        if (lane == 0) {
+            const T rs = sqrt(r2w);
+            if (a.res) a.res[(size_t)k * a.batch + sample] = rs;
+            if (k == 0) res_first = rs;
+            res_last = rs;
+            nonfinite = nonfinite || !isfinite(rs);
+        }
+        // step (c): multiplier; then the defect u of every coefficient
+        T u[D][NVP];
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+            for (int m = 0; m < NVP; ++m) {
+                T uv = T(0);
+                if (active && m < nv) {
+                    lam[ax][m] = fma(-a.rho, ftr[ax][m], lam[ax][m]);
+                    const int bi = (m == nv - 1) ? 3 : m;
+                    uv = (m >= 3 && m < nv - 1) ? (xi[ax][m] - xb[ax][m] + lam[ax][m] - a.rho * ftr[ax][m])
+                                                : (bnd[ax][bi] - xb[ax][m]);
+                }
+                u[ax][m] = uv;
+            }
+        // step (b): agent mean by the single-robot operator, deviations by W2
+        const T invN = T(1) / T(N);
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            T um[NVP];
+#pragma unroll
+            for (int m = 0; m < NVP; ++m) um[m] = (m < nv) ? wave_sum(u[ax][m]) * invN : T(0);
+#pragma unroll
+            for (int f = 0; f < NVP - 4; ++f) {
+                if (f < nv - 4) {
+                    T d = T(0);
+#pragma unroll
+                    for (int m = 0; m < NVP; ++m)
+                        d = fma(W1[f * NVP + m], um[m], fma(W2[f * NVP + m], u[ax][m] - um[m], d));
+                    if (active) xb[ax][3 + f] += d;
+                }
+            }
+            if (active) {
+                xb[ax][0] = bnd[ax][0];
+                xb[ax][1] = bnd[ax][1];
+                xb[ax][2] = bnd[ax][2];
+#pragma unroll
+                for (int m = 3; m < NVP; ++m)
+                    if (m == nv - 1) xb[ax][m] = bnd[ax][3];
+            }
+        }
+    }
+    if (active) {
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+            for (int m = 0; m < NVP; ++m)
+                if (m < nv) {
+                    a.xb[base + ax * nv + m] = xb[ax][m];
+                    a.lam[base + ax * nv + m] = lam[ax][m];
+                    nonfinite = nonfinite || !isfinite(xb[ax][m]) || !isfinite(lam[ax][m]);
+                }
+    }
+    if (a.flags && a.iters > 0) {
+        const bool anyb = __any(nonfinite);
+        if (lane == 0) {
+            uint32_t fl = 0;
+            if (anyb) fl |= 1u;
+            if (res_last > res_first) fl |= 2u;
+            a.flags[sample] = fl;
+        }
+    }
+}
+
+// Residual only, at the given joint coefficients: res[sample] = 2-norm, res_max.
+template <typename T, int D, int NVP, typename A>
+__device__ __forceinline__ void agents_residual(const A &a, const int sample, const int lane)
+{
+    const int N = a.n_agents, nv = a.nv, n_p = a.n_p;
+    const bool active = lane < N;
+    const TRAJAM_CONST_AS T *phi = (const TRAJAM_CONST_AS T *)a.phi;
+    T xb[D][NVP];
+    const size_t base = ((size_t)sample * N + (active ? lane : 0)) * D * nv;
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+        for (int m = 0; m < NVP; ++m) xb[ax][m] = (active && m < nv) ? a.xb[base + ax * nv + m] : T(0);
+    T r2 = T(0), rmax = T(0);
+    for (int t = 0; t < n_p; ++t) {
+        T p[D], v[D], acc[D];
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            T sp = T(0), sv = T(0), sa = T(0);
+#pragma unroll
+            for (int m = 0; m < NVP; ++m) {
+                sp = fma(phi[(size_t)(0 * n_p + t) * NVP + m], xb[ax][m], sp);
+                sv = fma(phi[(size_t)(1 * n_p + t) * NVP + m], xb[ax][m], sv);
+                sa = fma(phi[(size_t)(2 * n_p + t) * NVP + m], xb[ax][m], sa);
+            }
+            p[ax] = sp;
+            v[ax] = sv;
+            acc[ax] = sa;
+        }
+        T S[D], rv[D], ra[D];
+        agents_rows<T, D, A>(a, lane, active, T(t) * a.dt, p, v, acc, S, rv, ra, r2, rmax);
+    }
+    const T r2w = wave_sum(r2), mx = wave_max(rmax);
+    if (lane == 0) {
+        a.res[sample] = sqrt(r2w);
+        if (a.res_max) a.res_max[sample] = mx;
+    }
+}
+
+template <typename T, int D, int NVP>
+__global__ __launch_bounds__(kMaxThreads) void am_agents_kernel(AmArgs<T> a)
+{
+    const int sample = blockIdx.x * a.tb + (threadIdx.x >> 6);
+    if (sample >= a.batch) return;  // whole waves leave together
+    agents_sample<T, D, NVP, AmArgs<T>>(a, sample, threadIdx.x & 63);
+}
+
+template <typename T, int D, int NVP>
+__global__ __launch_bounds__(kMaxThreads) void am_agents_residual_kernel(AmArgs<T> a)
+{
+    const int sample = blockIdx.x * a.tb + (threadIdx.x >> 6);
+    if (sample >= a.batch) return;
+    agents_residual<T, D, NVP, AmArgs<T>>(a, sample, threadIdx.x & 63);
+}
+
+// ----------------------------------------------------------------------------
 // Ragged persistent launch: many independent problems (each its own fixed matrices,
-// obstacles, batch) in one launch.  Every wave repeatedly takes the next work unit
+// obstacles, batch) in one launch; single-robot and multi-agent problems go to two
+// instantiations (their register budgets differ by a wave per SIMD).  Every wave repeatedly takes the next work unit
 // (problem, sample) from a device counter and runs that sample's whole projection;
 // problems are ordered longest-first on the host, so the expensive units start first
 // and the short ones fill the tail.  Every wave exits once the counter passes the
@@ -946,6 +1370,7 @@ __device__ __forceinline__ void ragged_unit(const RaggedArgs &a, int sample, int
     wave_lds_sync();  // this wave's LDS is reused by its next unit
 }
 
+template <bool AGENTS>
 __global__ __launch_bounds__(kMaxThreads) void am_ragged_kernel(const AmArgs<float> *__restrict__ probs_g,
                                                                 const int *__restrict__ offsets_g, int n_probs,
                                                                 int total, int *__restrict__ counter)
@@ -972,12 +1397,18 @@ __global__ __launch_bounds__(kMaxThreads) void am_ragged_kernel(const AmArgs<flo
         const int sample = u - offsets[lo];
         const int nvp = a.nv <= 8 ? 8 : 12;
         const int tpl = (a.n_p + 63) >> 6;
+        if constexpr (AGENTS) {
+            if (a.dims == 2) { if (nvp == 8) agents_sample<float, 2, 8, RaggedArgs>(a, sample, lane); else agents_sample<float, 2, 12, RaggedArgs>(a, sample, lane); }
+            else             { if (nvp == 8) agents_sample<float, 3, 8, RaggedArgs>(a, sample, lane); else agents_sample<float, 3, 12, RaggedArgs>(a, sample, lane); }
+            continue;
+        } else {
         if (a.dims == 2) {
             if (nvp == 8) { if (tpl == 1) ragged_unit<2, 8, 1>(a, sample, lane, wl); else ragged_unit<2, 8, 2>(a, sample, lane, wl); }
             else          { if (tpl == 1) ragged_unit<2, 12, 1>(a, sample, lane, wl); else ragged_unit<2, 12, 2>(a, sample, lane, wl); }
         } else {
             if (nvp == 8) { if (tpl == 1) ragged_unit<3, 8, 1>(a, sample, lane, wl); else ragged_unit<3, 8, 2>(a, sample, lane, wl); }
             else          { if (tpl == 1) ragged_unit<3, 12, 1>(a, sample, lane, wl); else ragged_unit<3, 12, 2>(a, sample, lane, wl); }
+        }
         }
     }
 }
@@ -1164,15 +1595,57 @@ struct Dispatch;
 
 }  // namespace
 
+template <typename T>
+hipError_t launch_agents_t(int dims, int nvp, const AmArgs<T> &a, bool residual, hipStream_t st)
+{
+    if (a.batch <= 0) return hipSuccess;
+    if (a.n_agents < 1 || a.n_agents > 64 || a.tb < 1 || a.tb > kMaxThreads / 64) return hipErrorInvalidValue;
+    const dim3 grid((a.batch + a.tb - 1) / a.tb), block(64 * a.tb);
+#define TRAJAM_AGENTS(DD, NN)                                                                            \
+    if (dims == DD && nvp == NN) {                                                                       \
+        if (residual) hipLaunchKernelGGL((am_agents_residual_kernel<T, DD, NN>), grid, block, 0, st, a); \
+        else hipLaunchKernelGGL((am_agents_kernel<T, DD, NN>), grid, block, 0, st, a);                   \
+        return hipGetLastError();                                                                        \
+    }
+    TRAJAM_AGENTS(2, 8)
+    TRAJAM_AGENTS(2, 12)
+    TRAJAM_AGENTS(3, 8)
+    TRAJAM_AGENTS(3, 12)
+#undef TRAJAM_AGENTS
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_agents_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st)
+{
+    return launch_agents_t<double>(dims, nvp, a, false, st);
+}
+hipError_t launch_agents_f32(int dims, int nvp, const AmArgs<float> &a, hipStream_t st)
+{
+    return launch_agents_t<float>(dims, nvp, a, false, st);
+}
+hipError_t launch_agents_residual_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st)
+{
+    return launch_agents_t<double>(dims, nvp, a, true, st);
+}
+hipError_t launch_agents_residual_f32(int dims, int nvp, const AmArgs<float> &a, hipStream_t st)
+{
+    return launch_agents_t<float>(dims, nvp, a, true, st);
+}
+
 hipError_t launch_ragged(const AmArgs<float> *probs, const int *offsets, int n_probs, int total, int *counter,
-                         int blocks, hipStream_t st)
+                         int blocks, bool agents, hipStream_t st)
 {
     hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds = sizeof(float) * (size_t)kRaggedWaveLds * (kMaxThreads / 64);
-    hipLaunchKernelGGL(am_ragged_kernel, dim3(blocks), dim3(kMaxThreads), lds, st, probs, offsets, n_probs, total,
-                       counter);
+    if (agents) {
+        hipLaunchKernelGGL(am_ragged_kernel<true>, dim3(blocks), dim3(kMaxThreads), 0, st, probs, offsets, n_probs,
+                           total, counter);
+    } else {
+        const size_t lds = sizeof(float) * (size_t)kRaggedWaveLds * (kMaxThreads / 64);
+        hipLaunchKernelGGL(am_ragged_kernel<false>, dim3(blocks), dim3(kMaxThreads), lds, st, probs, offsets,
+                           n_probs, total, counter);
+    }
     return hipGetLastError();
 }
 

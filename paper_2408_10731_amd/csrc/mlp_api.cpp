@@ -78,6 +78,18 @@ extern "C" trajam_status trajam_mlp_forward(const trajam_mlp_shape *s, int32_t b
     return TRAJAM_OK;
 }
 
+extern "C" trajam_status trajam_mlp_infer(const trajam_mlp_shape *s, int32_t batch, const float *params,
+                                          const float *x, float *y, void *stream)
+{
+    if (!shape_ok(s)) return fail(TRAJAM_ERR_INVALID, "invalid network shape");
+    for (int l = 0; l <= s->n_layers; ++l)
+        if (s->width[l] > 512) return fail(TRAJAM_ERR_UNSUPPORTED, "trajam_mlp_infer: widths <= 512");
+    if (batch < 0) return fail(TRAJAM_ERR_INVALID, "batch >= 0");
+    if (batch == 0) return TRAJAM_OK;
+    if (!params || !x || !y) return fail(TRAJAM_ERR_INVALID, "NULL pointer");
+    return dev(trajam::launch_mlp_infer(s->n_layers, s->width, batch, params, x, y, (hipStream_t)stream), "mlp infer");
+}
+
 extern "C" trajam_status trajam_mlp_backward(const trajam_mlp_shape *s, int32_t batch, int32_t precision,
                                              const float *params, const float *x, const float *acts,
                                              const float *dy, float *grads, float *scratch, void *stream)
@@ -143,46 +155,37 @@ extern "C" trajam_status trajam_mlp_adam(int64_t n, float *p, const float *g, fl
     return dev(trajam::launch_adam(n, p, g, m, v, step, lr, b1, b2, eps, (hipStream_t)stream), "adam");
 }
 
-extern "C" trajam_status trajam_warm_features(int32_t batch, int32_t dims, int32_t nv, int32_t n_scene,
-                                              const float *scene, const float *xi, const float *line,
-                                              float inv_scale, float *x, void *stream)
+extern "C" trajam_status trajam_warm_features(int32_t batch, int32_t dims, int32_t nv, const float *xi,
+                                              const float *xb, const float *lam, float inv_scale, float *x,
+                                              void *stream)
 {
-    if (batch < 0 || dims < 1 || nv < 1 || n_scene < 0 || !xi || !line || !x || (n_scene > 0 && !scene))
+    if (batch < 0 || dims < 1 || nv < 1 || !xi || !xb || !lam || !x)
         return fail(TRAJAM_ERR_INVALID, "invalid warm-start feature arguments");
     if (batch == 0) return TRAJAM_OK;
-    return dev(trajam::launch_warm_features(batch, dims * nv, n_scene, scene, xi, line, inv_scale, x,
-                                            (hipStream_t)stream),
+    return dev(trajam::launch_warm_features(batch, dims * nv, xi, xb, lam, inv_scale, x, (hipStream_t)stream),
                "warm features");
 }
 
-extern "C" trajam_status trajam_warm_apply(int32_t batch, int32_t dims, int32_t nv, const float *y,
-                                           const float *xi, float out_scale, const double *boundary_coeffs,
-                                           float *xb0, float *lam0, uint32_t *flags, void *stream)
+extern "C" trajam_status trajam_warm_apply(int32_t batch, int32_t dims, int32_t nv, const float *y, float out_scale,
+                                           const float *xi, const float *xb, const float *lam, float *xb_out,
+                                           float *lam_out, void *stream)
 {
-    if (batch < 0 || dims < 1 || nv < 4 || !y || !xi || !xb0 || !lam0)
+    if (batch < 0 || dims < 1 || nv < 4 || !y || !xi || !xb || !lam || !xb_out || !lam_out)
         return fail(TRAJAM_ERR_INVALID, "invalid warm-start apply arguments");
-    if (boundary_coeffs && dims > 3) return fail(TRAJAM_ERR_INVALID, "boundary coefficients need dims <= 3");
-    trajam::WarmBoundary bc{};
-    if (boundary_coeffs) {
-        for (int i = 0; i < dims * 4; ++i) {
-            if (!std::isfinite(boundary_coeffs[i])) return fail(TRAJAM_ERR_INVALID, "non-finite boundary coefficient");
-            bc.c[i / 4][i % 4] = (float)boundary_coeffs[i];
-        }
-        bc.set = 1;
-    }
     if (batch == 0) return TRAJAM_OK;
-    return dev(trajam::launch_warm_apply(batch, dims, nv, y, xi, out_scale, bc, xb0, lam0, flags,
+    return dev(trajam::launch_warm_apply(batch, dims, nv, y, out_scale, xi, xb, lam, xb_out, lam_out,
                                          (hipStream_t)stream),
                "warm apply");
 }
 
 extern "C" trajam_status trajam_warm_fallback(int32_t batch, int32_t dims, int32_t nv, const float *rw,
-                                              const float *rc, const float *xi, float *xb0, float *lam0,
-                                              uint32_t *flags, void *stream)
+                                              const float *rc, const float *xb_src, const float *lam_src,
+                                              float *xb, float *lam, uint32_t *flags, void *stream)
 {
-    if (batch < 0 || dims < 1 || nv < 1 || !rw || !rc || !xi || !xb0 || !lam0)
+    if (batch < 0 || dims < 1 || nv < 1 || !rw || !rc || !xb_src || !lam_src || !xb || !lam)
         return fail(TRAJAM_ERR_INVALID, "invalid warm-start fallback arguments");
     if (batch == 0) return TRAJAM_OK;
-    return dev(trajam::launch_warm_fallback(batch, dims * nv, rw, rc, xi, xb0, lam0, flags, (hipStream_t)stream),
+    return dev(trajam::launch_warm_fallback(batch, dims * nv, rw, rc, xb_src, lam_src, xb, lam, flags,
+                                            (hipStream_t)stream),
                "warm fallback");
 }

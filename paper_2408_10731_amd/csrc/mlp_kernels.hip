@@ -46,16 +46,35 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const fl
     mlp_f32x4 macc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) macc[i][j] = mlp_f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    // Global -> register tile loads, mapped so that consecutive threads read
+    // consecutive addresses whichever stride of the operand is 1, with the next tile
+    // prefetched into registers while the current one is multiplied out of LDS.
+    const bool a_k = sak == 1, b_k = sbk == 1;
+    float ra[4], rb[4];
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int e = tid + 256 * r;
-            const int ml = e & (BM - 1), kl = e / BM;
-            const int m = m0 + ml, k = k0 + kl;
-            As[kl][ml] = (m < M && k < K) ? A[(long)m * sam + (long)k * sak] : 0.f;
-            const int n = n0 + ml;
-            Bs[kl][ml] = (n < N && k < K) ? B[(long)k * sbk + (long)n * sbn] : 0.f;
+            const int ma = a_k ? (e >> 4) : (e & (BM - 1)), ka = a_k ? (e & (BK - 1)) : (e >> 6);
+            const int m = m0 + ma, k = k0 + ka;
+            ra[r] = (m < M && k < K) ? A[(long)m * sam + (long)k * sak] : 0.f;
+            const int nb = b_k ? (e >> 4) : (e & (BN - 1)), kb = b_k ? (e & (BK - 1)) : (e >> 6);
+            const int n = n0 + nb, kk = k0 + kb;
+            rb[r] = (n < N && kk < K) ? B[(long)kk * sbk + (long)n * sbn] : 0.f;
         }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = tid + 256 * r;
+            As[a_k ? (e & (BK - 1)) : (e >> 6)][a_k ? (e >> 4) : (e & (BM - 1))] = ra[r];
+            Bs[b_k ? (e & (BK - 1)) : (e >> 6)][b_k ? (e >> 4) : (e & (BN - 1))] = rb[r];
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        stash();
+        if (k0 + BK < K) fetch(k0 + BK);
         __syncthreads();
         if constexpr (!BF16) {
             const int ty = tid >> 4, tx = tid & 15;
@@ -159,59 +178,140 @@ __global__ void adam_kernel(long n, float *__restrict__ p, const float *__restri
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// X[b] = [scene features, (xi[b] - line) * inv_scale]
-__global__ void warm_features_kernel(int batch, int dim, int n_scene, const float *__restrict__ scene,
-                                     const float *__restrict__ xi, const float *__restrict__ line,
-                                     float inv_scale, float *__restrict__ X)
-{
-    const int width = n_scene + dim;
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long)batch * width) return;
-    const int b = (int)(i / width), f = (int)(i - (long)b * width);
-    X[i] = f < n_scene ? scene[f] : (xi[(long)b * dim + (f - n_scene)] - line[f - n_scene]) * inv_scale;
-}
+// Fused inference: the whole network for kInferSamples samples per workgroup, the
+// activations of one layer kept in LDS as act[k][s] (the samples of one input feature
+// contiguous, read as one 128-bit broadcast), the weights read straight from L2
+// (every workgroup reads the same rows).  An output is computed by g lanes that split
+// its inputs (g = 256 / out rounded down to a power of two, at most 64), combined by
+// a butterfly over the g lanes, so thin layers keep the workgroup busy.  fp32 products,
+// the same sums as the layer-by-layer forward up to their order.
+constexpr int kInferSamples = 8;
+constexpr int kInferMaxWidth = 512;
 
-// One thread per sample: delta = y * out_scale; xb0 = xi + delta on the free
-// coefficients and the exact boundary coefficients on the others (when given);
-// lambda0 = delta on the free coefficients (the converged multiplier of a fixed point
-// equals xb - xi there) and 0 on the boundary ones; non-finite predictions fall back
-// cold.
-__global__ void warm_apply_kernel(int batch, int dims, int nv, const float *__restrict__ y,
-                                  const float *__restrict__ xi, float out_scale, WarmBoundary bc,
-                                  float *__restrict__ xb0, float *__restrict__ lam0, uint32_t *__restrict__ flags)
+struct InferShape {
+    int n_layers;
+    int width[9];
+};
+
+__global__ __launch_bounds__(256) void mlp_infer_kernel(InferShape sh, int batch, const float *__restrict__ params,
+                                                         const float *__restrict__ x, float *__restrict__ y)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= batch) return;
-    const int dim = dims * nv;
-    bool finite = true;
-    for (int r = 0; r < dim; ++r) finite = finite && isfinite(y[(long)b * dim + r]);
-    for (int r = 0; r < dim; ++r) {
-        const long i = (long)b * dim + r;
-        const int m = r % nv;
-        const bool bnd = m <= 2 || m == nv - 1;
-        const float d = finite ? y[i] * out_scale : 0.f;
-        xb0[i] = (finite && bnd && bc.set) ? bc.c[r / nv][m == nv - 1 ? 3 : m] : xi[i] + d;
-        lam0[i] = bnd ? 0.f : d;
+    constexpr int SB = kInferSamples;
+    __shared__ __align__(16) float act[2][kInferMaxWidth][SB];
+    const int tid = threadIdx.x;
+    const int s0 = blockIdx.x * SB;
+    const int ns = min(SB, batch - s0);
+    const int w0 = sh.width[0];
+    for (int e = tid; e < w0 * SB; e += 256) {
+        const int s = e / w0, k = e - s * w0;
+        act[0][k][s] = s < ns ? x[(long)(s0 + s) * w0 + k] : 0.f;
     }
-    if (flags) flags[b] = finite ? 0u : 4u;
-}
-
-// Per-sample fallback: when the warm start's residual exceeds the cold start's, the
-// sample restarts cold (xb0 = xi, lambda0 = 0) and is flagged.
-__global__ void warm_fallback_kernel(int batch, int dim, const float *__restrict__ rw,
-                                     const float *__restrict__ rc, const float *__restrict__ xi,
-                                     float *__restrict__ xb0, float *__restrict__ lam0,
-                                     uint32_t *__restrict__ flags)
-{
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= batch) return;
-    if (!(rw[b] <= rc[b])) {
-        for (int r = 0; r < dim; ++r) {
-            xb0[(long)b * dim + r] = xi[(long)b * dim + r];
-            lam0[(long)b * dim + r] = 0.f;
+    __syncthreads();
+    const float *p = params;
+    int cur = 0;
+    for (int l = 0; l < sh.n_layers; ++l) {
+        const int in = sh.width[l], out = sh.width[l + 1];
+        const float *W = p, *bias = p + (long)out * in;
+        p += (long)out * in + out;
+        const bool last = l == sh.n_layers - 1;
+        int g = 1;
+        while (g < 64 && g * 2 * out <= 256) g *= 2;
+        const int part = tid & (g - 1);
+        for (int o0 = 0; o0 < out * g; o0 += 256) {
+            const int o = (o0 + tid) / g;
+            const bool live = (o0 + tid) < out * g;
+            float acc[SB];
+#pragma unroll
+            for (int s = 0; s < SB; ++s) acc[s] = 0.f;
+            if (live) {
+                const float *wr = W + (long)o * in;
+                for (int k = part; k < in; k += g) {
+                    const float wv = wr[k];
+                    const float4 a0 = *reinterpret_cast<const float4 *>(&act[cur][k][0]);
+                    const float4 a1 = *reinterpret_cast<const float4 *>(&act[cur][k][4]);
+                    acc[0] = fmaf(wv, a0.x, acc[0]);
+                    acc[1] = fmaf(wv, a0.y, acc[1]);
+                    acc[2] = fmaf(wv, a0.z, acc[2]);
+                    acc[3] = fmaf(wv, a0.w, acc[3]);
+                    acc[4] = fmaf(wv, a1.x, acc[4]);
+                    acc[5] = fmaf(wv, a1.y, acc[5]);
+                    acc[6] = fmaf(wv, a1.z, acc[6]);
+                    acc[7] = fmaf(wv, a1.w, acc[7]);
+                }
+            }
+            for (int m = 1; m < g; m *= 2)
+#pragma unroll
+                for (int s = 0; s < SB; ++s) acc[s] += __shfl_xor(acc[s], m);
+            if (live && part == 0) {
+                const float bo = bias[o];
+#pragma unroll
+                for (int s = 0; s < SB; ++s) {
+                    const float v = acc[s] + bo;
+                    act[cur ^ 1][o][s] = last ? v : fmaxf(v, 0.f);
+                }
+            }
         }
-        if (flags) flags[b] |= 4u;
+        __syncthreads();
+        cur ^= 1;
     }
+    const int wl = sh.width[sh.n_layers];
+    for (int e = tid; e < wl * SB; e += 256) {
+        const int s = e / wl, o = e - s * wl;
+        if (s < ns) y[(long)(s0 + s) * wl + o] = act[cur][o][s];
+    }
+}
+
+// Probe features: X[b] = [(xb[b] - xi[b]), lam[b]] * inv_scale, each [dim].
+__global__ void warm_features_kernel(int batch, int dim, const float *__restrict__ xi, const float *__restrict__ xb,
+                                     const float *__restrict__ lam, float inv_scale, float *__restrict__ X)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)batch * 2 * dim) return;
+    const int b = (int)(i / (2 * dim)), f = (int)(i - (long)b * 2 * dim);
+    const long e = (long)b * dim + (f < dim ? f : f - dim);
+    X[i] = (f < dim ? xb[e] - xi[e] : lam[e]) * inv_scale;
+}
+
+// Jump: y[b] = d_xb [dim] / out_scale.  xb_out = xb + d_xb on the free coefficients
+// (the boundary ones are already exact); the multiplier of a free coefficient is set
+// to xb_out - xi, the value it has at a fixed point of the iteration, and the
+// boundary ones keep the probe's.  One thread per coefficient.
+__global__ void warm_apply_kernel(int batch, int dims, int nv, const float *__restrict__ y, float out_scale,
+                                  const float *__restrict__ xi, const float *__restrict__ xb,
+                                  const float *__restrict__ lam, float *__restrict__ xbo, float *__restrict__ lamo)
+{
+    const int dim = dims * nv;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)batch * dim) return;
+    const int m = (int)(i % nv);
+    const bool bnd = m <= 2 || m == nv - 1;
+    const float xn = bnd ? xb[i] : fmaf(y[i], out_scale, xb[i]);
+    xbo[i] = xn;
+    lamo[i] = bnd ? lam[i] : xn - xi[i];
+}
+
+// Per-sample fallback, one wave per sample: where the jumped state's residual is not
+// below the probe's (or is NaN), or the jumped state is not finite, the sample keeps
+// the probe state (xb_src, lam_src) and is flagged.
+__global__ void warm_fallback_kernel(int batch, int dim, const float *__restrict__ rw, const float *__restrict__ rc,
+                                     const float *__restrict__ xs, const float *__restrict__ ls,
+                                     float *__restrict__ xb, float *__restrict__ lam, uint32_t *__restrict__ flags)
+{
+    const int b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (b >= batch) return;  // whole waves
+    bool finite = true;
+    for (int r = lane; r < dim; r += 64) {
+        const long e = (long)b * dim + r;
+        finite = finite && isfinite(xb[e]) && isfinite(lam[e]);
+    }
+    const bool bad = __any(!finite) || !(rw[b] <= rc[b]);
+    if (bad)
+        for (int r = lane; r < dim; r += 64) {
+            const long e = (long)b * dim + r;
+            xb[e] = xs[e];
+            lam[e] = ls[e];
+        }
+    if (lane == 0 && flags) flags[b] = bad ? 4u : 0u;
 }
 
 }  // namespace
@@ -252,28 +352,44 @@ hipError_t launch_adam(long n, float *p, const float *g, float *m, float *v, int
     return hipGetLastError();
 }
 
-hipError_t launch_warm_features(int batch, int dim, int n_scene, const float *scene, const float *xi,
-                                const float *line, float inv_scale, float *X, hipStream_t st)
+hipError_t launch_mlp_infer(int n_layers, const int *width, int batch, const float *params, const float *x,
+                            float *y, hipStream_t st)
 {
-    const long total = (long)batch * (n_scene + dim);
+    if (n_layers < 1 || n_layers > 8) return hipErrorInvalidValue;
+    InferShape sh{};
+    sh.n_layers = n_layers;
+    for (int l = 0; l <= n_layers; ++l) {
+        if (width[l] < 1 || width[l] > kInferMaxWidth) return hipErrorInvalidValue;
+        sh.width[l] = width[l];
+    }
+    hipLaunchKernelGGL(mlp_infer_kernel, dim3((batch + kInferSamples - 1) / kInferSamples), dim3(256), 0, st, sh,
+                       batch, params, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_warm_features(int batch, int dim, const float *xi, const float *xb, const float *lam,
+                                float inv_scale, float *X, hipStream_t st)
+{
+    const long total = (long)batch * 2 * dim;
     hipLaunchKernelGGL(warm_features_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, batch, dim,
-                       n_scene, scene, xi, line, inv_scale, X);
+                       xi, xb, lam, inv_scale, X);
     return hipGetLastError();
 }
 
-hipError_t launch_warm_apply(int batch, int dims, int nv, const float *y, const float *xi, float out_scale,
-                             const WarmBoundary &bc, float *xb0, float *lam0, uint32_t *flags, hipStream_t st)
+hipError_t launch_warm_apply(int batch, int dims, int nv, const float *y, float out_scale, const float *xi,
+                             const float *xb, const float *lam, float *xbo, float *lamo, hipStream_t st)
 {
-    hipLaunchKernelGGL(warm_apply_kernel, dim3((batch + 255) / 256), dim3(256), 0, st, batch, dims, nv, y, xi,
-                       out_scale, bc, xb0, lam0, flags);
+    const long total = (long)batch * dims * nv;
+    hipLaunchKernelGGL(warm_apply_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, batch, dims, nv,
+                       y, out_scale, xi, xb, lam, xbo, lamo);
     return hipGetLastError();
 }
 
-hipError_t launch_warm_fallback(int batch, int dim, const float *rw, const float *rc, const float *xi,
-                                float *xb0, float *lam0, uint32_t *flags, hipStream_t st)
+hipError_t launch_warm_fallback(int batch, int dim, const float *rw, const float *rc, const float *xs,
+                                const float *ls, float *xb, float *lam, uint32_t *flags, hipStream_t st)
 {
-    hipLaunchKernelGGL(warm_fallback_kernel, dim3((batch + 255) / 256), dim3(256), 0, st, batch, dim, rw, rc, xi,
-                       xb0, lam0, flags);
+    hipLaunchKernelGGL(warm_fallback_kernel, dim3((batch + 3) / 4), dim3(256), 0, st, batch, dim, rw, rc, xs, ls, xb,
+                       lam, flags);
     return hipGetLastError();
 }
 

@@ -62,6 +62,10 @@ struct trajam_solver {
     void *d_soa = nullptr;   // [groups][fields][group]
     void *d_bf16 = nullptr;  // BF16_REFINE: Whi, Wlo [16][16] uint16 each
     void *d_Hff = nullptr;   // BF16_REFINE: [16][16] float
+    // multi-agent problems
+    void *d_W2 = nullptr;    // [nvp][nvp] QP operator of H + n_agents rho P^T P
+    void *d_xiBag = nullptr; // [n_agents][D][4] boundary coefficients per agent
+    std::vector<double> bnd_cache;  // boundary rows the device copy was built from
     std::string err;
 };
 
@@ -108,7 +112,18 @@ trajam_status validate(const trajam_problem *p, std::string &why)
         why = "unknown obstacle model";
         return TRAJAM_ERR_INVALID;
     }
-    if (p->n_agents != 1) { why = "only n_agents == 1 is supported"; return TRAJAM_ERR_UNSUPPORTED; }
+    if (p->n_agents < 1 || p->n_agents > 64) { why = "n_agents must be in [1, 64]"; return TRAJAM_ERR_INVALID; }
+    if (p->n_agents > 1) {
+        if (!(p->agent_radius > 0.0) || !std::isfinite(p->agent_radius)) {
+            why = "agent_radius must be finite and > 0";
+            return TRAJAM_ERR_INVALID;
+        }
+        if (p->precision == TRAJAM_BF16_REFINE) {
+            why = "multi-agent problems run in FP64 or FP32";
+            return TRAJAM_ERR_UNSUPPORTED;
+        }
+        if (p->degree + 1 > 12) { why = "multi-agent problems need degree <= 11"; return TRAJAM_ERR_UNSUPPORTED; }
+    }
     return TRAJAM_OK;
 }
 
@@ -201,6 +216,39 @@ void boundary_coeffs(int n, double T, const double *b4, double *c4)
     c4[3] = xf;
 }
 
+// QP update operator of a Hessian H (n_v x n_v): W_ff = H_ff^-1 and, in coefficient
+// order with rows = free coefficients, W = [W_ff | -W_ff H_fb].
+trajam_status qp_operator(const std::vector<double> &H, int n, std::vector<double> &Wff,
+                          std::vector<double> &W, std::string &msg)
+{
+    const int nv = n + 1, nf = nv - 4;
+    std::vector<double> Hff((size_t)std::max(nf, 1) * std::max(nf, 1), 0.0);
+    for (int a = 0; a < nf; ++a)
+        for (int b = 0; b < nf; ++b) Hff[(size_t)a * nf + b] = H[(size_t)(3 + a) * nv + (3 + b)];
+    Wff.clear();
+    if (nf > 0 && !spd_inverse(nf, Hff, Wff)) {
+        msg = "free block of the QP Hessian is not positive definite";
+        return TRAJAM_ERR_NUMERIC;
+    }
+    W.assign((size_t)std::max(nf, 0) * nv, 0.0);
+    for (int a = 0; a < nf; ++a)
+        for (int m = 0; m < nv; ++m) {
+            double v = 0.0;
+            if (!is_boundary(m, n)) {
+                v = Wff[(size_t)a * nf + (m - 3)];
+            } else {
+                for (int b = 0; b < nf; ++b) v -= Wff[(size_t)a * nf + b] * H[(size_t)(3 + b) * nv + m];
+            }
+            W[(size_t)a * nv + m] = v;
+        }
+    for (double v : W)
+        if (!std::isfinite(v)) {
+            msg = "non-finite QP operator";
+            return TRAJAM_ERR_NUMERIC;
+        }
+    return TRAJAM_OK;
+}
+
 // Host FP64 precompute of every fixed matrix of one problem class.
 trajam_status precompute(const trajam_problem &pr, std::vector<double> &P, std::vector<double> &Pd,
                          std::vector<double> &Pdd, std::vector<double> &H,
@@ -221,32 +269,7 @@ trajam_status precompute(const trajam_problem &pr, std::vector<double> &P, std::
             }
             H[(size_t)i * nv + j] = (i == j ? 1.0 : 0.0) + p->rho * ff;
         }
-    std::vector<double> Hff((size_t)std::max(nf, 1) * std::max(nf, 1), 0.0);
-    for (int a = 0; a < nf; ++a)
-        for (int b = 0; b < nf; ++b) Hff[(size_t)a * nf + b] = H[(size_t)(3 + a) * nv + (3 + b)];
-    Wff.clear();
-    if (nf > 0 && !spd_inverse(nf, Hff, Wff)) {
-        msg = "free block of I + rho F^T F is not positive definite";
-        return TRAJAM_ERR_NUMERIC;
-    }
-    // W = [W_ff | -W_ff H_fb] in coefficient order, rows = free coefficients
-    W.assign((size_t)std::max(nf, 0) * nv, 0.0);
-    for (int a = 0; a < nf; ++a)
-        for (int m = 0; m < nv; ++m) {
-            double v = 0.0;
-            if (!is_boundary(m, n)) {
-                v = Wff[(size_t)a * nf + (m - 3)];
-            } else {
-                for (int b = 0; b < nf; ++b) v -= Wff[(size_t)a * nf + b] * H[(size_t)(3 + b) * nv + m];
-            }
-            W[(size_t)a * nv + m] = v;
-        }
-    for (double v : W)
-        if (!std::isfinite(v)) {
-            msg = "non-finite QP operator";
-            return TRAJAM_ERR_NUMERIC;
-        }
-    return TRAJAM_OK;
+    return qp_operator(H, n, Wff, W, msg);
 }
 
 template <typename T>
@@ -315,6 +338,8 @@ void trajam_destroy(trajam_solver *s)
     if (s->d_soa) (void)hipFree(s->d_soa);
     if (s->d_bf16) (void)hipFree(s->d_bf16);
     if (s->d_Hff) (void)hipFree(s->d_Hff);
+    if (s->d_W2) (void)hipFree(s->d_W2);
+    if (s->d_xiBag) (void)hipFree(s->d_xiBag);
     delete s;
 }
 
@@ -393,6 +418,27 @@ trajam_status trajam_init(const trajam_problem *p, trajam_solver **out)
             for (int j = 0; j < 4; ++j) Hm[256 + a * 4 + j] = s->H[(size_t)(3 + a) * nv + bidx[j]];
         }
         if (e == hipSuccess) e = upload<float>(&s->d_Hff, Hm);
+    }
+    if (e == hipSuccess && p->n_agents > 1) {
+        // deviations of the agents from their mean see H + N rho P^T P
+        std::vector<double> H2 = s->H, Wff2, W2;
+        for (int i = 0; i < nv; ++i)
+            for (int j = 0; j < nv; ++j) {
+                double g = 0.0;
+                for (int k = 0; k < np; ++k) g += s->P[(size_t)k * nv + i] * s->P[(size_t)k * nv + j];
+                H2[(size_t)i * nv + j] += p->n_agents * p->rho * g;
+            }
+        st = qp_operator(H2, n, Wff2, W2, msg);
+        if (st != TRAJAM_OK) {
+            trajam_destroy(s);
+            return fail(nullptr, st, msg);
+        }
+        std::vector<double> W2p((size_t)nvp * nvp, 0.0);
+        for (int a = 0; a < nf; ++a)
+            for (int m = 0; m < nv; ++m) W2p[(size_t)a * nvp + m] = W2[(size_t)a * nv + m];
+        std::vector<double> zb((size_t)p->n_agents * p->dims * 4, 0.0);
+        e = f64 ? upload<double>(&s->d_W2, W2p) : upload<float>(&s->d_W2, W2p);
+        if (e == hipSuccess) e = f64 ? upload<double>(&s->d_xiBag, zb) : upload<float>(&s->d_xiBag, zb);
     }
     if (e != hipSuccess) {
         std::string m = std::string("device allocation/copy failed: ") + hipGetErrorString(e);
@@ -478,6 +524,44 @@ void fill_args(const trajam_solver *s, AmArgs<T> &a, int batch, int iters)
         a.Wlo = (const uint16_t *)s->d_bf16 + 256;
     }
     a.Hmq = (const float *)s->d_Hff;
+    a.n_agents = p.n_agents;
+    a.pair_r = (T)(2.0 * p.agent_radius);
+    a.W2 = (const T *)s->d_W2;
+    a.xiB_ag = (const T *)s->d_xiBag;
+}
+
+// Boundary coefficients of every agent ([n_agents][D][4]) from boundary rows
+// [n_agents][D][4] (x0, v0, a0, xf).
+std::vector<double> agent_boundary_coeffs(const trajam_problem &p, const double *rows)
+{
+    std::vector<double> c((size_t)p.n_agents * p.dims * 4);
+    for (int i = 0; i < p.n_agents * p.dims; ++i) boundary_coeffs(p.degree, p.horizon, rows + 4 * i, &c[4 * (size_t)i]);
+    return c;
+}
+
+// Multi-agent boundary: the device copy is rebuilt only when the rows change; a
+// change waits for the stream (no graph capture then) and copies synchronously.
+trajam_status agents_boundary(trajam_solver *s, const double *rows, hipStream_t st)
+{
+    const trajam_problem &p = s->prob;
+    const size_t cnt = (size_t)p.n_agents * p.dims * 4;
+    for (size_t i = 0; i < cnt; ++i)
+        if (!std::isfinite(rows[i])) return fail(s, TRAJAM_ERR_INVALID, "non-finite boundary value");
+    if (s->bnd_cache.size() == cnt && std::equal(s->bnd_cache.begin(), s->bnd_cache.end(), rows))
+        return TRAJAM_OK;
+    std::vector<double> c = agent_boundary_coeffs(p, rows);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) {
+        if (p.precision == TRAJAM_FP64) {
+            e = hipMemcpy(s->d_xiBag, c.data(), sizeof(double) * cnt, hipMemcpyHostToDevice);
+        } else {
+            std::vector<float> cf(c.begin(), c.end());
+            e = hipMemcpy(s->d_xiBag, cf.data(), sizeof(float) * cnt, hipMemcpyHostToDevice);
+        }
+    }
+    if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("agent boundary upload: ") + hipGetErrorString(e));
+    s->bnd_cache.assign(rows, rows + cnt);
+    return TRAJAM_OK;
 }
 
 trajam_status pack(trajam_solver *s, const void *c, const void *w, const void *ax, hipStream_t st)
@@ -519,6 +603,33 @@ extern "C" trajam_status trajam_project(trajam_solver *s, int32_t batch, const v
     const trajam_problem &p = s->prob;
     const int dynamic = obs_vel != nullptr;
     hipError_t e;
+    if (p.n_agents > 1) {
+        ps = agents_boundary(s, boundary_host, st);
+        if (ps != TRAJAM_OK) return ps;
+        if (p.precision == TRAJAM_FP64) {
+            AmArgs<double> a;
+            fill_args(s, a, batch, iters);
+            a.dynamic = dynamic;
+            a.xi = (const double *)xi;
+            a.xb = (double *)xi_bar;
+            a.lam = (double *)lambda;
+            a.res = (double *)res_trace;
+            a.flags = flags;
+            e = trajam::launch_agents_f64(p.dims, s->nvp, a, st);
+        } else {
+            AmArgs<float> a;
+            fill_args(s, a, batch, iters);
+            a.dynamic = dynamic;
+            a.xi = (const float *)xi;
+            a.xb = (float *)xi_bar;
+            a.lam = (float *)lambda;
+            a.res = (float *)res_trace;
+            a.flags = flags;
+            e = trajam::launch_agents_f32(p.dims, s->nvp, a, st);
+        }
+        if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("multi-agent launch: ") + hipGetErrorString(e));
+        return TRAJAM_OK;
+    }
     if (p.precision == TRAJAM_FP64) {
         AmArgs<double> a;
         fill_args(s, a, batch, iters);
@@ -577,7 +688,8 @@ extern "C" trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const
         a.xb = (double *)xi_bar;
         a.res = (double *)res_l2;
         a.res_max = (double *)res_max;
-        e = trajam::launch_residual_f64(p.dims, s->nvp, a, st);
+        e = p.n_agents > 1 ? trajam::launch_agents_residual_f64(p.dims, s->nvp, a, st)
+                           : trajam::launch_residual_f64(p.dims, s->nvp, a, st);
     } else {
         AmArgs<float> a;
         fill_args(s, a, batch, 0);
@@ -585,7 +697,8 @@ extern "C" trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const
         a.xb = (float *)xi_bar;
         a.res = (float *)res_l2;
         a.res_max = (float *)res_max;
-        e = trajam::launch_residual_f32(p.dims, s->nvp, a, st);
+        e = p.n_agents > 1 ? trajam::launch_agents_residual_f32(p.dims, s->nvp, a, st)
+                           : trajam::launch_residual_f32(p.dims, s->nvp, a, st);
     }
     if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("residual launch: ") + hipGetErrorString(e));
     return TRAJAM_OK;
@@ -598,6 +711,7 @@ extern "C" trajam_status trajam_cem_sample(trajam_solver *s, int32_t n, const vo
 {
     if (!s) return TRAJAM_ERR_INVALID;
     s->err.clear();
+    if (s->prob.n_agents != 1) return fail(s, TRAJAM_ERR_UNSUPPORTED, "the sampling loop is single-robot");
     if (n < 0) return fail(s, TRAJAM_ERR_INVALID, "n must be >= 0");
     if (n > s->prob.max_batch) return fail(s, TRAJAM_ERR_CAPACITY, "n > max_batch");
     if (n == 0) return TRAJAM_OK;
@@ -614,6 +728,7 @@ extern "C" trajam_status trajam_cem_cost(trajam_solver *s, int32_t n, const void
 {
     if (!s) return TRAJAM_ERR_INVALID;
     s->err.clear();
+    if (s->prob.n_agents != 1) return fail(s, TRAJAM_ERR_UNSUPPORTED, "the sampling loop is single-robot");
     if (n < 0 || !(quantum > 0.0)) return fail(s, TRAJAM_ERR_INVALID, "n >= 0 and quantum > 0 required");
     if (n > s->prob.max_batch) return fail(s, TRAJAM_ERR_CAPACITY, "n > max_batch");
     if (n == 0) return TRAJAM_OK;
@@ -631,6 +746,7 @@ extern "C" trajam_status trajam_cem_select(trajam_solver *s, int32_t n, const in
 {
     if (!s) return TRAJAM_ERR_INVALID;
     s->err.clear();
+    if (s->prob.n_agents != 1) return fail(s, TRAJAM_ERR_UNSUPPORTED, "the sampling loop is single-robot");
     if (n < 1 || n > 4096 || n_elite < 1 || n_elite > n_proj || n_proj > n)
         return fail(s, TRAJAM_ERR_INVALID, "need 1 <= n_elite <= n_proj <= n <= 4096");
     if (!res_key || !c_aug || !proj_idx || !elite_idx) return fail(s, TRAJAM_ERR_INVALID, "NULL pointer");
@@ -646,6 +762,7 @@ extern "C" trajam_status trajam_cem_update(trajam_solver *s, int32_t n_elite, co
 {
     if (!s) return TRAJAM_ERR_INVALID;
     s->err.clear();
+    if (s->prob.n_agents != 1) return fail(s, TRAJAM_ERR_UNSUPPORTED, "the sampling loop is single-robot");
     if (n_elite < 1 || n_elite > 4096 || !(sigma > 0.0 && sigma <= 1.0) || !(gamma > 0.0))
         return fail(s, TRAJAM_ERR_INVALID, "need 1 <= n_elite <= 4096, 0 < sigma <= 1, gamma > 0");
     if (!elite_idx || !xi_bar || !c_aug || !mu || !Sigma || !chol) return fail(s, TRAJAM_ERR_INVALID, "NULL pointer");
@@ -742,10 +859,12 @@ extern "C" trajam_status trajam_autotune(trajam_solver *s, int32_t batch, const 
             }
         }
     }
-    const size_t bytes = (size_t)batch * s->prob.dims * s->nv *
+    const size_t bytes = (size_t)batch * s->prob.n_agents * s->prob.dims * s->nv *
                          (s->prob.precision == TRAJAM_FP64 ? sizeof(double) : sizeof(float));
     std::vector<std::pair<int, int>> cands;
-    for (int spw = 1; spw * s->tpad <= trajam::kMaxThreads; spw *= 2) cands.push_back({TRAJAM_KERNEL_MULTIWAVE, spw});
+    // multi-agent launches have one shape parameter: joint samples (waves) per workgroup
+    if (s->prob.n_agents == 1)
+        for (int spw = 1; spw * s->tpad <= trajam::kMaxThreads; spw *= 2) cands.push_back({TRAJAM_KERNEL_MULTIWAVE, spw});
     for (int spw = 1; spw * 64 <= trajam::kMaxThreads; spw *= 2) cands.push_back({TRAJAM_KERNEL_WAVE, spw});
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -793,19 +912,25 @@ extern "C" trajam_status trajam_autotune(trajam_solver *s, int32_t batch, const 
     return TRAJAM_OK;
 }
 
+// Two work queues: single-robot problems (group 0) and multi-agent problems (group 1),
+// each a table sorted longest-first, its unit offsets and its counter.
 struct trajam_ragged_plan {
-    void *d_probs = nullptr;
-    int *d_offsets = nullptr;
-    int *d_counter = nullptr;
-    int n = 0, total = 0, blocks = 0;
+    void *d_bnd = nullptr;  // boundary coefficients of the multi-agent items
+    void *d_probs[2] = {nullptr, nullptr};
+    int *d_offsets[2] = {nullptr, nullptr};
+    int *d_counter = nullptr;  // [2]
+    int n[2] = {0, 0}, total[2] = {0, 0}, blocks[2] = {0, 0};
 };
 
 extern "C" void trajam_ragged_plan_destroy(trajam_ragged_plan *p)
 {
     if (!p) return;
-    if (p->d_probs) (void)hipFree(p->d_probs);
-    if (p->d_offsets) (void)hipFree(p->d_offsets);
+    for (int g = 0; g < 2; ++g) {
+        if (p->d_probs[g]) (void)hipFree(p->d_probs[g]);
+        if (p->d_offsets[g]) (void)hipFree(p->d_offsets[g]);
+    }
     if (p->d_counter) (void)hipFree(p->d_counter);
+    if (p->d_bnd) (void)hipFree(p->d_bnd);
     delete p;
 }
 
@@ -817,6 +942,8 @@ extern "C" trajam_status trajam_ragged_plan_create(const trajam_ragged_item *ite
     if (!items || n < 1 || iters < 0) return fail(nullptr, TRAJAM_ERR_INVALID, "need items, n >= 1, iters >= 0");
     std::vector<AmArgs<float>> args(n);
     std::vector<double> cost(n);
+    std::vector<float> agent_bnd;        // all multi-agent items' boundary coefficients
+    std::vector<size_t> agent_off(n, 0);
     for (int i = 0; i < n; ++i) {
         const trajam_ragged_item &it = items[i];
         trajam_solver *s = it.solver;
@@ -834,7 +961,16 @@ extern "C" trajam_status trajam_ragged_plan_create(const trajam_ragged_item *ite
         AmArgs<float> &a = args[i];
         fill_args(s, a, it.batch, iters);
         a.dynamic = s->dynamic;
-        if (it.batch > 0)
+        if (p.n_agents > 1) {
+            const size_t cnt = (size_t)p.n_agents * p.dims * 4;
+            if (it.batch > 0)
+                for (size_t q = 0; q < cnt; ++q)
+                    if (!std::isfinite(it.boundary_host[q])) return fail(nullptr, TRAJAM_ERR_INVALID, "ragged: non-finite boundary");
+            std::vector<double> c(cnt, 0.0);
+            if (it.batch > 0) c = agent_boundary_coeffs(p, it.boundary_host);
+            agent_off[i] = agent_bnd.size();
+            agent_bnd.insert(agent_bnd.end(), c.begin(), c.end());
+        } else if (it.batch > 0)
             for (int ax = 0; ax < p.dims; ++ax) {
                 double c4[4];
                 boundary_coeffs(p.degree, p.horizon, it.boundary_host + 4 * ax, c4);
@@ -845,27 +981,40 @@ extern "C" trajam_status trajam_ragged_plan_create(const trajam_ragged_item *ite
         a.lam = (float *)it.lambda;
         a.res = (float *)it.res_trace;
         a.flags = it.flags;
-        cost[i] = (double)(p.n_obstacles + 2) * p.n_steps * p.dims;
-    }
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-    std::vector<AmArgs<float>> sorted(n);
-    std::vector<int> offsets(n + 1, 0);
-    for (int k = 0; k < n; ++k) {
-        sorted[k] = args[order[k]];
-        offsets[k + 1] = offsets[k] + sorted[k].batch;
+        cost[i] = (double)p.n_agents * (p.n_obstacles + p.n_agents + 2) * p.n_steps * p.dims;
     }
     trajam_ragged_plan *plan = new (std::nothrow) trajam_ragged_plan();
     if (!plan) return fail(nullptr, TRAJAM_ERR_DEVICE, "host allocation failed");
-    plan->n = n;
-    plan->total = offsets[n];
-    plan->blocks = std::max(1, std::min((plan->total + 3) / 4, 2048));
-    hipError_t e = hipMalloc(&plan->d_probs, sizeof(AmArgs<float>) * n);
-    if (e == hipSuccess) e = hipMalloc(&plan->d_offsets, sizeof(int) * (n + 1));
-    if (e == hipSuccess) e = hipMalloc(&plan->d_counter, sizeof(int));
-    if (e == hipSuccess) e = hipMemcpy(plan->d_probs, sorted.data(), sizeof(AmArgs<float>) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(plan->d_offsets, offsets.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
+    hipError_t e = hipSuccess;
+    if (!agent_bnd.empty()) {
+        e = hipMalloc(&plan->d_bnd, sizeof(float) * agent_bnd.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(plan->d_bnd, agent_bnd.data(), sizeof(float) * agent_bnd.size(), hipMemcpyHostToDevice);
+        for (int i = 0; i < n; ++i)
+            if (args[i].n_agents > 1) args[i].xiB_ag = (const float *)plan->d_bnd + agent_off[i];
+    }
+    if (e == hipSuccess) e = hipMalloc(&plan->d_counter, 2 * sizeof(int));
+    for (int g = 0; g < 2 && e == hipSuccess; ++g) {
+        std::vector<int> order;
+        for (int i = 0; i < n; ++i)
+            if ((args[i].n_agents > 1) == (g == 1)) order.push_back(i);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+        const int m = (int)order.size();
+        std::vector<AmArgs<float>> sorted(m);
+        std::vector<int> offsets(m + 1, 0);
+        for (int k = 0; k < m; ++k) {
+            sorted[k] = args[order[k]];
+            offsets[k + 1] = offsets[k] + sorted[k].batch;
+        }
+        plan->n[g] = m;
+        plan->total[g] = offsets[m];
+        plan->blocks[g] = std::max(1, std::min((plan->total[g] + 3) / 4, 2048));
+        if (m == 0) continue;
+        e = hipMalloc(&plan->d_probs[g], sizeof(AmArgs<float>) * m);
+        if (e == hipSuccess) e = hipMalloc(&plan->d_offsets[g], sizeof(int) * (m + 1));
+        if (e == hipSuccess) e = hipMemcpy(plan->d_probs[g], sorted.data(), sizeof(AmArgs<float>) * m, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(plan->d_offsets[g], offsets.data(), sizeof(int) * (m + 1), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         trajam_ragged_plan_destroy(plan);
         return fail(nullptr, TRAJAM_ERR_DEVICE, std::string("ragged plan upload: ") + hipGetErrorString(e));
@@ -877,9 +1026,13 @@ extern "C" trajam_status trajam_ragged_plan_create(const trajam_ragged_item *ite
 extern "C" trajam_status trajam_ragged_launch(trajam_ragged_plan *p, void *stream)
 {
     if (!p) return fail(nullptr, TRAJAM_ERR_INVALID, "plan is NULL");
-    if (p->total == 0) return TRAJAM_OK;
-    hipError_t e = trajam::launch_ragged((const AmArgs<float> *)p->d_probs, p->d_offsets, p->n, p->total,
-                                         p->d_counter, p->blocks, (hipStream_t)stream);
-    if (e != hipSuccess) return fail(nullptr, TRAJAM_ERR_DEVICE, std::string("ragged launch: ") + hipGetErrorString(e));
+    for (int g = 0; g < 2; ++g) {
+        if (p->total[g] == 0) continue;
+        hipError_t e = trajam::launch_ragged((const AmArgs<float> *)p->d_probs[g], p->d_offsets[g], p->n[g],
+                                             p->total[g], p->d_counter + g, p->blocks[g], g == 1,
+                                             (hipStream_t)stream);
+        if (e != hipSuccess)
+            return fail(nullptr, TRAJAM_ERR_DEVICE, std::string("ragged launch: ") + hipGetErrorString(e));
+    }
     return TRAJAM_OK;
 }

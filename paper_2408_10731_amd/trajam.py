@@ -45,7 +45,7 @@ EXPORTS = [
     "trajam_fixed_matrices", "trajam_set_launch", "trajam_get_launch",
     "trajam_boundary_coefficients", "trajam_cem_sample", "trajam_cem_cost",
     "trajam_cem_select", "trajam_cem_update", "trajam_mlp_param_count", "trajam_mlp_forward",
-    "trajam_mlp_backward", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
+    "trajam_mlp_backward", "trajam_mlp_infer", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
     "trajam_warm_apply", "trajam_warm_fallback", "trajam_set_obstacles", "trajam_autotune",
     "trajam_ragged_plan_create", "trajam_ragged_launch", "trajam_ragged_plan_destroy",
     "trajam_status_string", "trajam_last_error",
@@ -154,12 +154,14 @@ def load():
     L.trajam_mlp_mse.argtypes = [i64, vp, vp, vp, vp, vp]
     L.trajam_mlp_adam.argtypes = [i64, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float,
                                   ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
-    L.trajam_warm_features.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                       ctypes.c_int32, vp, vp, vp, ctypes.c_float, vp, vp]
-    L.trajam_warm_apply.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp,
-                                    ctypes.c_float, dp, vp, vp, vp, vp]
+    L.trajam_warm_features.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp,
+                                       vp, ctypes.c_float, vp, vp]
+    L.trajam_warm_apply.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
+                                    ctypes.c_float, vp, vp, vp, vp, vp, vp]
+    L.trajam_mlp_infer.argtypes = [sp, ctypes.c_int32, vp, vp, vp, vp]
+    L.trajam_mlp_infer.restype = ctypes.c_int
     L.trajam_warm_fallback.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,
-                                       vp, vp, vp, vp]
+                                       vp, vp, vp, vp, vp]
     L.trajam_set_obstacles.argtypes = [vp, vp, vp, vp, vp]
     i32p = ctypes.POINTER(ctypes.c_int32)
     L.trajam_autotune.argtypes = [vp, ctypes.c_int32, vp, dp, vp, vp, vp, vp, vp, ctypes.c_int32,
@@ -298,29 +300,25 @@ def trajam_mlp_adam(n, params, grads, m, v, step, lr, beta1, beta2, eps, stream)
                                   float(beta2), float(eps), stream))
 
 
-def trajam_warm_features(batch, dims, n_coeffs, n_scene, scene, xi, line, inv_scale, x,
-                         stream) -> None:
-    _check(load().trajam_warm_features(int(batch), int(dims), int(n_coeffs), int(n_scene), scene,
-                                       xi, line, float(inv_scale), x, stream))
+def trajam_warm_features(batch, dims, n_coeffs, xi, xb, lam, inv_scale, x, stream) -> None:
+    _check(load().trajam_warm_features(int(batch), int(dims), int(n_coeffs), xi, xb, lam,
+                                       float(inv_scale), x, stream))
 
 
-def trajam_warm_apply(batch, dims, n_coeffs, y, xi, out_scale, boundary_coeffs, xi_bar0,
-                      lambda0, flags, stream) -> None:
-    """boundary_coeffs: host [dims][4] float64 array or None."""
-    arr = None if boundary_coeffs is None else np.ascontiguousarray(boundary_coeffs,
-                                                                    dtype=np.float64)
-    _check(load().trajam_warm_apply(int(batch), int(dims), int(n_coeffs), y, xi, float(out_scale),
-                                    None if arr is None else _dp(arr), xi_bar0, lambda0, flags,
-                                    stream))
+def trajam_warm_apply(batch, dims, n_coeffs, y, out_scale, xi, xb, lam, xb_out, lam_out,
+                      stream) -> None:
+    _check(load().trajam_warm_apply(int(batch), int(dims), int(n_coeffs), y, float(out_scale), xi,
+                                    xb, lam, xb_out, lam_out, stream))
 
 
-def trajam_warm_fallback(batch, dims, n_coeffs, res_warm, res_cold, xi, xi_bar0, lambda0, flags,
-                         stream) -> None:
-    _check(load().trajam_warm_fallback(int(batch), int(dims), int(n_coeffs), res_warm, res_cold, xi,
-                                       xi_bar0, lambda0, flags, stream))
+def trajam_mlp_infer(shape: MlpShape, batch, params, x, y, stream) -> None:
+    _check(load().trajam_mlp_infer(ctypes.byref(shape), int(batch), params, x, y, stream))
 
 
-# ----------------------------------------------------------- torch wrapper --
+def trajam_warm_fallback(batch, dims, n_coeffs, res_warm, res_cold, xb_src, lam_src, xb, lam,
+                         flags, stream) -> None:
+    _check(load().trajam_warm_fallback(int(batch), int(dims), int(n_coeffs), res_warm, res_cold,
+                                       xb_src, lam_src, xb, lam, flags, stream))
 
 
 def trajam_set_obstacles(handle, obs_centre, obs_vel, obs_axes, stream) -> None:
@@ -371,6 +369,10 @@ class Solver:
         self.problem = problem
         self.dims = problem.dims
         self.nv = problem.degree + 1
+        self.n_agents = problem.n_agents
+        # per-sample layout: [D, n_v], or [N, D, n_v] for a joint sample of N agents
+        self.sample_shape = ((self.n_agents, self.dims, self.nv) if self.n_agents > 1
+                             else (self.dims, self.nv))
         self.dtype = torch.float64 if problem.precision == TRAJAM_FP64 else torch.float32
         self.handle = trajam_init(problem)
 
@@ -380,7 +382,8 @@ class Solver:
         if sphere is None:
             sphere = bool(np.all(w.obs_axes == w.obs_axes[:, :1]))
         return cls(make_problem(w.dims, w.degree, w.n_steps, w.horizon, w.v_max, w.a_max,
-                                w.rho, w.n_obs, max_batch or w.batch, prec, sphere))
+                                w.rho, w.n_obs, max_batch or w.batch, prec, sphere,
+                                n_agents=w.n_agents, agent_radius=w.agent_radius))
 
     def close(self):
         if getattr(self, "handle", None):
@@ -414,7 +417,7 @@ class Solver:
                 stream=None):
         import torch
         B = xi.shape[0]
-        shape = (B, self.dims, self.nv)
+        shape = (B,) + self.sample_shape
         c, v, a = self.obstacles(*obs)
         rt = None if res_trace is None else self._t(res_trace, (iters, B), "res_trace")
         fl = None
@@ -432,7 +435,7 @@ class Solver:
         B = xi_bar.shape[0]
         c, v, a = self.obstacles(*obs)
         st = (stream or torch.cuda.current_stream()).cuda_stream
-        trajam_residuals(self.handle, B, self._t(xi_bar, (B, self.dims, self.nv), "xi_bar"),
+        trajam_residuals(self.handle, B, self._t(xi_bar, (B,) + self.sample_shape, "xi_bar"),
                          c, v, a, self._t(res_l2, (B,), "res_l2"),
                          None if res_max is None else self._t(res_max, (B,), "res_max"), st)
 
@@ -449,7 +452,7 @@ class Solver:
         """Time every launch shape, apply the fastest; returns (kernel, samples/WG)."""
         import torch
         B = xi.shape[0]
-        shape = (B, self.dims, self.nv)
+        shape = (B,) + self.sample_shape
         c, v, a = self.obstacles(*obs)
         st = (stream or torch.cuda.current_stream()).cuda_stream
         return trajam_autotune(self.handle, B, self._t(xi, shape, "xi"), boundary, c, v, a,
@@ -473,7 +476,7 @@ class RaggedPlan:
             solver, xi, boundary, xb, lam = it[:5]
             rt = it[5] if len(it) > 5 else None
             B = xi.shape[0]
-            shape = (B, solver.dims, solver.nv)
+            shape = (B,) + solver.sample_shape
             b = np.ascontiguousarray(boundary, dtype=np.float64)
             keep.append((solver, xi, xb, lam, rt, b))
             cit.append(RaggedItem(solver.handle, B, solver._t(xi, shape, "xi"), _dp(b),

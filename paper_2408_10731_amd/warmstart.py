@@ -1,56 +1,40 @@
 """Learned warm start of the projection (no thesis counterpart; its future-work
 chapter names learning-based methods).  Marshalling around the library's kernels:
-the network is trained and evaluated by trajam_mlp_* and applied by trajam_warm_*.
+the network is trained and evaluated by trajam_mlp_*, and the warm start is built by
+trajam_project, trajam_warm_* and trajam_residuals.
 
-What the network predicts.  For a scene (obstacles, start, goal) and a sample xi it
-predicts delta = xb* - xi on the free coefficients, the correction of the converged
-projection (the boundary coefficients of xb* are known exactly from the boundary
-conditions, so they are not learned).  At a converged fixed point the residual is
-zero, so the QP's stationarity leaves lambda* = xb* - xi on the free coefficients;
-the warm start is therefore
-    xb0 = xi + delta_hat (free), the exact boundary coefficients (boundary);
-    lambda0 = delta_hat (free), 0 (boundary),
-from which the first polar step recovers the polar variables.  A sample starts cold
-(xb0 = xi, lambda0 = 0) when the prediction is not finite or when the warm start's
-residual exceeds the cold start's.
+Why a jump of the AM state.  The multiplier of the projection lives in coefficient
+space, so every feasible xb with lam = xb - xi is a fixed point of the iteration:
+where the iteration lands depends on its path, and the converged state is not a
+function of the scene and the sample that a network could learn.  What is a smooth
+function is the map from an early state of the cold iteration to the state at which
+the cold iteration first reaches the residual tolerance.  So the warm start is
 
-Scene encoding (host, once per scene): obstacles sorted by distance of their t = 0
-centre to the start, each (centre - start) / L, velocity, radius, padded with zeros
-to `k_obs` obstacles; then start / L and goal / L (L = |goal - start|).  The sample
-part of the input, (xi - straight line) / in_scale, is built on the device.
+    probe:  k0 cold AM iterations from (xi, 0)            -> (xb_p, lam_p)
+    jump:   xb_w = xb_p + network(xb_p - xi, lam_p) on the free coefficients,
+            lam_w = xb_w - xi there (the multiplier of a fixed point)
+    check:  per sample, keep the probe state unless the jump lowers the residual
+
+and the projection continues from (xb_w, lam_w).  With the fixed-point multiplier a
+feasible jump is a fixed point, and an almost feasible one settles nearby instead of
+following the cold iteration's oscillations.  The network is trained on
+solver-generated pairs (probe state -> coefficients of the first state with
+residual <= tol); the boundary coefficients are untouched (exact after the first
+iteration).
 """
 from __future__ import annotations
 
 import dataclasses
 import math
-from typing import Optional
 
 import numpy as np
 
 from . import trajam as tj
 from . import workloads as wl
 
-IN_SCALE = 0.5
-OUT_SCALE = 0.5
-
-
-def scene_features(w, k_obs: int) -> np.ndarray:
-    start, goal = w.boundary[:, 0], w.boundary[:, 3]
-    L = max(float(np.linalg.norm(goal - start)), 1e-9)
-    c = np.asarray(w.obs_centre, dtype=np.float64)
-    order = np.argsort(np.linalg.norm(c - start[None], axis=1), kind="stable")[:k_obs]
-    D = w.dims
-    feat = np.zeros((k_obs, 2 * D + 1))
-    feat[:len(order), :D] = (c[order] - start[None]) / L
-    feat[:len(order), D:2 * D] = np.asarray(w.obs_vel)[order]
-    feat[:len(order), 2 * D] = np.asarray(w.obs_axes)[order, 0]
-    return np.concatenate([feat.reshape(-1), start / L, goal / L]).astype(np.float32)
-
-
-def straight_line(w) -> np.ndarray:
-    start, goal = w.boundary[:, 0], w.boundary[:, 3]
-    frac = np.arange(w.degree + 1) / w.degree
-    return (start[:, None] + frac[None, :] * (goal - start)[:, None]).astype(np.float32)
+K0 = 3          # cold iterations of the probe
+IN_SCALE = 1.0
+OUT_SCALE = 1.0
 
 
 def init_params(widths, seed: int) -> np.ndarray:
@@ -63,6 +47,12 @@ def init_params(widths, seed: int) -> np.ndarray:
         parts.append(rng.uniform(-bound, bound, size=out * fan_in))
         parts.append(np.zeros(out))
     return np.concatenate(parts).astype(np.float32)
+
+
+def widths_for(w, hidden: int = 256):
+    """[2 D n_v, hidden, hidden, D n_v]: probe state in, coefficient jump out."""
+    dim = w.dims * w.n_v
+    return [2 * dim, hidden, hidden, dim]
 
 
 class Net:
@@ -123,49 +113,32 @@ class Net:
 
 @dataclasses.dataclass
 class Dataset:
-    x: object       # [N, n_in] device float32
-    t: object       # [N, dim] device float32 (delta / OUT_SCALE)
+    x: object       # [N, 2 dim] device float32: probe features
+    t: object       # [N, dim] device float32: (coefficients at first hit - probe) / OUT_SCALE
     n_scenes: int
 
 
-def build_inputs(w, xi, k_obs, out=None):
-    """Network inputs for the samples xi (device [B, D, nv]) of scene w."""
-    import torch
-    scene = torch.as_tensor(scene_features(w, k_obs), device="cuda")
-    line = torch.as_tensor(straight_line(w), device="cuda")
-    B = xi.shape[0]
-    n_in = scene.numel() + w.dims * w.n_v
-    x = out if out is not None else torch.zeros((B, n_in), device="cuda")
-    tj.trajam_warm_features(B, w.dims, w.n_v, scene.numel(), scene.data_ptr(), xi.data_ptr(),
-                            line.data_ptr(), 1.0 / IN_SCALE, x.data_ptr(),
-                            torch.cuda.current_stream().cuda_stream)
-    return x
-
-
-def boundary_coeffs(solver: "tj.Solver", w) -> np.ndarray:
-    """[D][4] Bernstein coefficients (xi_0, xi_1, xi_2, xi_n) fixed by the boundary rows."""
-    return np.stack([tj.trajam_boundary_coefficients(solver.problem, w.boundary[ax])
-                     for ax in range(w.dims)])
-
-
-def generate(scene_fn, seeds, samples_per_scene, k_obs, iters=300, tol=1e-3, chunk=256):
-    """Solver-generated pairs.  The scenes (one obstacle count per family) are taken
-    `chunk` at a time: a fixed pool of solvers and device buffers is refilled with the
-    chunk's obstacles and samples, all samples are projected `iters` AM iterations from
-    a cold start in one ragged launch, and converged samples (residual <= tol) are
-    kept."""
+def generate(scene_fn, seeds, samples_per_scene, k0=K0, cap=150, tol=1e-3, chunk=256):
+    """Solver-generated pairs.  The scenes of one family are taken `chunk` at a time:
+    a fixed pool of solvers and device buffers is refilled with the chunk's obstacles
+    and samples, and the cold iteration runs one AM iteration per ragged launch over
+    the whole chunk; the probe state after k0 iterations is kept, and each sample's
+    first state (after the probe) whose residual is <= tol is recorded.  Samples that
+    reach tol within `cap` iterations give one pair each."""
     import torch
     seeds = [int(x) for x in seeds]
     B = int(samples_per_scene)
     w0 = scene_fn(seeds[0], B)
     n = min(chunk, len(seeds))
     D, nv, no = w0.dims, w0.n_v, w0.n_obs
+    dim = D * nv
     solvers = [tj.Solver.for_workload(w0, precision="fp32", max_batch=B) for _ in range(n)]
     xi = torch.zeros((n, B, D, nv), device="cuda")
     xb, lam = torch.zeros_like(xi), torch.zeros_like(xi)
+    tr = torch.zeros((n, 1, B), device="cuda")
     oc = torch.zeros((n, max(no, 1), D), device="cuda")
     ov, oa = torch.zeros_like(oc), torch.zeros_like(oc)
-    res = torch.zeros((n, B), device="cuda")
+    x_all = torch.zeros((n * B, 2 * dim), device="cuda")
     plan, plan_key = None, None
     xs, ts = [], []
     for c0 in range(0, len(seeds), n):
@@ -183,30 +156,37 @@ def generate(scene_fn, seeds, samples_per_scene, k_obs, iters=300, tol=1e-3, chu
             oc[:m].copy_(torch.from_numpy(np.stack([w.obs_centre for w in ws]).astype(np.float32)))
             ov[:m].copy_(torch.from_numpy(np.stack([w.obs_vel for w in ws]).astype(np.float32)))
             oa[:m].copy_(torch.from_numpy(np.stack([w.obs_axes for w in ws]).astype(np.float32)))
-        obs = [(oc[i], ov[i] if dynamic else None, oa[i]) for i in range(m)]
         for i in range(m):
-            solvers[i].set_obstacles(obs[i])
+            solvers[i].set_obstacles((oc[i], ov[i] if dynamic else None, oa[i]))
         key = (m, dynamic, bnd.tobytes())   # a plan bakes these in
         if key != plan_key:
             if plan is not None:
                 plan.close()
-            plan = tj.RaggedPlan([(solvers[i], xi[i], bnd, xb[i], lam[i]) for i in range(m)],
-                                 iters)
+            plan = tj.RaggedPlan([(solvers[i], xi[i], bnd, xb[i], lam[i], tr[i]) for i in range(m)], 1)
             plan_key = key
         xb[:m].copy_(xi[:m])
         lam[:m].zero_()
-        plan.launch()
-        xs_c = []
-        for i, w in enumerate(ws):
-            solvers[i].residuals(xb[i], obs[i], res[i])
-            xs_c.append(build_inputs(w, xi[i], k_obs))
-        keep = (res[:m] <= tol).reshape(-1)
-        # the warm start writes the boundary coefficients exactly, so only the free
-        # coefficients' correction is learned
-        delta = xb[:m] - xi[:m]
-        delta[:, :, :, [0, 1, 2, nv - 1]] = 0.0
-        xs.append(torch.cat(xs_c)[keep])
-        ts.append((delta / OUT_SCALE).reshape(m * B, -1)[keep])
+        for _ in range(k0):
+            plan.launch()
+        xp, lp = xb[:m].clone(), lam[:m].clone()
+        hx = torch.zeros_like(xp)
+        hit = torch.zeros((m, B), dtype=torch.bool, device="cuda")
+        for k in range(k0, cap):
+            px = xb[:m].clone()
+            plan.launch()   # the trace holds the residual of the state before the launch
+            new = (~hit) & (tr[:m, 0] <= tol)
+            sel = new[:, :, None, None]
+            hx = torch.where(sel, px, hx)
+            hit |= new
+            if (k - k0) % 16 == 15 and bool(hit.all()):
+                break
+        x = x_all[:m * B]
+        tj.trajam_warm_features(m * B, D, nv, xi[:m].data_ptr(), xp.data_ptr(), lp.data_ptr(),
+                                1.0 / IN_SCALE, x.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        t = (hx - xp).reshape(m * B, dim) / OUT_SCALE
+        keep = hit.reshape(-1)
+        xs.append(x[keep].clone())
+        ts.append(t[keep])
     torch.cuda.synchronize()
     plan.close()
     for s_ in solvers:
@@ -236,53 +216,65 @@ def train(net: Net, data: Dataset, epochs: int, batch: int = 1024, lr: float = 1
 
 
 class WarmContext:
-    """Per-scene state of the warm start: scene features, reference line and boundary
-    coefficients on the device, and every work buffer, allocated once.  `run` only
-    launches kernels (features, the network, apply, two residuals, fallback), so it
-    can be captured in a graph together with the projection that follows."""
+    """The warm start of one solver: every buffer allocated once, `run` only launches
+    kernels (probe projection, features, the fused network inference, jump, residual,
+    check), so it can be captured in a graph together with the projection that
+    continues from it."""
 
-    def __init__(self, solver: "tj.Solver", net: Net, w, k_obs: int, max_batch: int):
+    def __init__(self, solver: "tj.Solver", net: Net, max_batch: int, k0: int = K0):
         import torch
-        self.solver, self.net, self.w, self.k_obs = solver, net, w, k_obs
-        self.scene = torch.as_tensor(scene_features(w, k_obs), device="cuda")
-        self.line = torch.as_tensor(straight_line(w), device="cuda")
-        self.bc = boundary_coeffs(solver, w)
-        n_in = self.scene.numel() + w.dims * w.n_v
-        assert n_in == net.widths[0] and max_batch <= net.max_batch
-        self.x = torch.zeros((max_batch, n_in), device="cuda")
-        shape = (max_batch, w.dims, w.n_v)
-        self.xb0 = torch.zeros(shape, device="cuda")
-        self.lam0 = torch.zeros(shape, device="cuda")
+        self.solver, self.net, self.k0 = solver, net, int(k0)
+        D, nv = solver.dims, solver.nv
+        self.dim = D * nv
+        assert net.widths[0] == 2 * self.dim and net.widths[-1] == self.dim
+        assert max(net.widths) <= 512
+        assert max_batch <= net.max_batch
+        shape = (max_batch, D, nv)
+        self.xp = torch.zeros(shape, device="cuda")
+        self.lp = torch.zeros(shape, device="cuda")
+        self.xw = torch.zeros(shape, device="cuda")
+        self.lw = torch.zeros(shape, device="cuda")
+        self.x = torch.zeros((max_batch, 2 * self.dim), device="cuda")
+        self.y = torch.zeros((max_batch, self.dim), device="cuda")
+        self.trace = torch.zeros((self.k0, max_batch), device="cuda")
         self.rw = torch.zeros(max_batch, device="cuda")
-        self.rc = torch.zeros(max_batch, device="cuda")
         self.flags = torch.zeros(max_batch, dtype=torch.int32, device="cuda")
 
-    def run(self, xi, obs):
-        """(xb0, lam0, flags) views for the samples xi [B, D, n_v]."""
+    def run(self, xi, boundary, obs):
+        """(xb_w, lam_w, flags, probe_trace) for the samples xi [B, D, n_v]: the state
+        after the probe and the jump; the projection continues from it."""
         import torch
-        w, B = self.w, xi.shape[0]
+        s = self.solver
+        B = xi.shape[0]
+        D, nv = s.dims, s.nv
         st = torch.cuda.current_stream().cuda_stream
+        xp, lp, xw, lw = self.xp[:B], self.lp[:B], self.xw[:B], self.lw[:B]
+        tr = self.trace[:, :B]
+        xp.copy_(xi)
+        lp.zero_()
+        s.project(xi, boundary, obs, xp, lp, self.k0, res_trace=tr)
         x = self.x[:B]
-        tj.trajam_warm_features(B, w.dims, w.n_v, self.scene.numel(), self.scene.data_ptr(),
-                                xi.data_ptr(), self.line.data_ptr(), 1.0 / IN_SCALE, x.data_ptr(),
-                                st)
-        y = self.net.forward(x)
-        xb0, lam0, fl = self.xb0[:B], self.lam0[:B], self.flags[:B]
-        tj.trajam_warm_apply(B, w.dims, w.n_v, y.data_ptr(), xi.data_ptr(), OUT_SCALE, self.bc,
-                             xb0.data_ptr(), lam0.data_ptr(), fl.data_ptr(), st)
-        rw, rc = self.rw[:B], self.rc[:B]
-        self.solver.residuals(xb0, obs, rw)
-        self.solver.residuals(xi, obs, rc)
-        tj.trajam_warm_fallback(B, w.dims, w.n_v, rw.data_ptr(), rc.data_ptr(), xi.data_ptr(),
-                                xb0.data_ptr(), lam0.data_ptr(), fl.data_ptr(), st)
-        return xb0, lam0, fl
+        tj.trajam_warm_features(B, D, nv, xi.data_ptr(), xp.data_ptr(), lp.data_ptr(),
+                                1.0 / IN_SCALE, x.data_ptr(), st)
+        y = self.y[:B]
+        tj.trajam_mlp_infer(self.net.shape, B, self.net.params.data_ptr(), x.data_ptr(),
+                            y.data_ptr(), st)
+        tj.trajam_warm_apply(B, D, nv, y.data_ptr(), OUT_SCALE, xi.data_ptr(), xp.data_ptr(),
+                             lp.data_ptr(), xw.data_ptr(), lw.data_ptr(), st)
+        rw = self.rw[:B]
+        s.residuals(xw, obs, rw)
+        fl = self.flags[:B]
+        tj.trajam_warm_fallback(B, D, nv, rw.data_ptr(), tr[self.k0 - 1].data_ptr(),
+                                xp.data_ptr(), lp.data_ptr(), xw.data_ptr(), lw.data_ptr(),
+                                fl.data_ptr(), st)
+        return xw, lw, fl, tr
 
 
-def warm_start(solver: "tj.Solver", net: Net, w, xi, obs, k_obs):
-    """(xb0, lam0, flags): network prediction with the per-sample cold fallback."""
-    ctx = WarmContext(solver, net, w, k_obs, xi.shape[0])
-    xb0, lam0, fl = ctx.run(xi, obs)
-    return xb0.clone(), lam0.clone(), fl.clone()
+def iterations_to(trace, tol=1e-3):
+    """1-based index of the first iteration whose batch-median residual is <= tol."""
+    med = np.median(np.asarray(trace), axis=1)
+    hit = np.nonzero(med <= tol)[0]
+    return int(hit[0]) + 1 if hit.size else None
 
 
 def family_scene(family: str):
@@ -292,8 +284,3 @@ def family_scene(family: str):
     if family == "cfg4":
         return lambda seed, batch: wl.config4_scene(seed, batch=batch)
     raise ValueError(family)
-
-
-def widths_for(w, k_obs: int, hidden: int = 256):
-    n_in = k_obs * (2 * w.dims + 1) + 2 * w.dims + w.dims * w.n_v
-    return [n_in, hidden, hidden, w.dims * w.n_v]

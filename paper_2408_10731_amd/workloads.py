@@ -216,7 +216,7 @@ def problem3d(seed: int, n_obs: int, batch: int, iters: int = 50) -> Workload:
 
 def _far_from(c, s, points, clearance):
     reach = s.max() + clearance
-    return all(np.linalg.norm(c - q) > reach for q in points)
+    return bool(np.min(np.linalg.norm(points - c[None], axis=1)) > reach)
 
 
 def agents3d(seed: int, n_agents: int, n_obs: int, batch: int, iters: int = 50,
@@ -295,4 +295,23 @@ def ragged_set(n_problems: int = 256, seed: Optional[int] = None, n_obs=(5, 300)
     return out
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
+def config5(n_problems: int = 256, seed: Optional[int] = None, iters: int = 50,
+            n_obs=(5, 300), batch=(32, 2048), agents=(16, 64)):
+    """Ragged set: n_obs ~ U{n_obs} and batch ~ U{batch} per problem; even problems are
+    2D single robots in the config-2 geometry (problem2d), odd ones 3D multi-agent
+    problems with N ~ U{agents} agents (agents3d; a batch entry is a joint sample)."""
+    base = MASTER_SEED + 50 if seed is None else seed
+    pick = _rng(base)
+    out = []
+    for k in range(n_problems):
+        no = int(pick.integers(n_obs[0], n_obs[1] + 1))
+        b = int(pick.integers(batch[0], batch[1] + 1))
+        na = int(pick.integers(agents[0], agents[1] + 1))
+        if k % 2 == 0:
+            out.append(problem2d(base + 1000 + k, no, b, iters))
+        else:
+            out.append(agents3d(base + 1000 + k, na, no, b, iters))
+    return out
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}

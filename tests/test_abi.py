@@ -56,7 +56,12 @@ def _problem(**kw):
     (dict(max_batch=0), tj.TRAJAM_ERR_INVALID),
     (dict(precision=7), tj.TRAJAM_ERR_INVALID),
     (dict(v_max=float("nan")), tj.TRAJAM_ERR_INVALID),
-    (dict(n_agents=3), tj.TRAJAM_ERR_UNSUPPORTED),
+    (dict(n_agents=0), tj.TRAJAM_ERR_INVALID),
+    (dict(n_agents=65, agent_radius=0.3), tj.TRAJAM_ERR_INVALID),
+    (dict(n_agents=3, agent_radius=0.0), tj.TRAJAM_ERR_INVALID),
+    (dict(n_agents=3, agent_radius=float("inf")), tj.TRAJAM_ERR_INVALID),
+    (dict(n_agents=3, agent_radius=0.3, precision="bf16"), tj.TRAJAM_ERR_UNSUPPORTED),
+    (dict(n_agents=3, agent_radius=0.3, degree=12, n_steps=100), tj.TRAJAM_ERR_UNSUPPORTED),
 ])
 def test_invalid_problems_rejected_on_host(kw, status):
     L = tj.load()
