@@ -122,9 +122,11 @@ void trajam_destroy(trajam_solver *s);
  * comp_zeta, in that order), in one launch.
  *   xi            device, [batch][dims][n+1]: the samples to project (read only)
  *   boundary_host host,   [dims][4]: (x0, v0, a0, xf) of eq eq_modify11
- *   obs_*         device, [n_obstacles][dims] (see layouts above); obs_centre and
- *                 obs_axes may be NULL only when n_obstacles == 0; obs_vel == NULL
- *                 means static obstacles (a faster loop than passing zeros)
+ *   obs_*         device, [n_obstacles][dims] (see layouts above); obs_vel == NULL
+ *                 means static obstacles (a faster loop than passing zeros).  All
+ *                 three NULL: reuse the obstacles packed last (by a previous call or by
+ *                 trajam_set_obstacles), which skips the packing launch; otherwise
+ *                 obs_centre and obs_axes may be NULL only when n_obstacles == 0
  *   xi_bar        device, [batch][dims][n+1]: in = initial iterate (a copy of xi for a
  *                 cold start, or a warm start), out = iterate after `iters` steps
  *   lambda        device, [batch][dims][n+1]: in = initial multiplier (zeros for a
@@ -324,11 +326,16 @@ trajam_status trajam_mlp_forward(const trajam_mlp_shape *shape, int32_t batch, i
                                  const float *params, const float *x, float *acts, float *y,
                                  void *stream);
 
-/* Inference only: y [batch][width[L]] = network(x) in one launch (fp32 products,
- * activations kept on chip; every width <= 512).  Same result as
- * trajam_mlp_forward with precision 0 up to the order of the sums.
- * Errors: INVALID, UNSUPPORTED (a width above 512), DEVICE. */
-trajam_status trajam_mlp_infer(const trajam_mlp_shape *shape, int32_t batch, const float *params,
+/* Inference layout of the parameters: per layer W^T [in][out] (transposed), then the
+ * bias, in a separate buffer of n_params floats.  Errors: INVALID, DEVICE. */
+trajam_status trajam_mlp_pack_infer(const trajam_mlp_shape *shape, const float *params,
+                                    float *packed, void *stream);
+
+/* Inference only: y [batch][width[L]] = network(x) in one launch from the packed
+ * parameters of trajam_mlp_pack_infer (fp32 products, activations kept on chip;
+ * every width <= 512).  Same result as trajam_mlp_forward with precision 0 up to the
+ * order of the sums.  Errors: INVALID, UNSUPPORTED (a width above 512), DEVICE. */
+trajam_status trajam_mlp_infer(const trajam_mlp_shape *shape, int32_t batch, const float *packed,
                                const float *x, float *y, void *stream);
 
 /* grads [n_params] = d loss / d params given dy = d loss / d y [batch][width[L]], the

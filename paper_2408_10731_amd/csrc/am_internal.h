@@ -110,8 +110,9 @@ hipError_t launch_warm_features(int batch, int dim, const float *xi, const float
                                 float inv_scale, float *X, hipStream_t st);
 hipError_t launch_warm_apply(int batch, int dims, int nv, const float *y, float out_scale, const float *xi,
                              const float *xb, const float *lam, float *xbo, float *lamo, hipStream_t st);
-hipError_t launch_mlp_infer(int n_layers, const int *width, int batch, const float *params, const float *x,
+hipError_t launch_mlp_infer(int n_layers, const int *width, int batch, const float *packed, const float *x,
                             float *y, hipStream_t st);
+hipError_t launch_mlp_pack_infer(int n_layers, const int *width, const float *params, float *packed, hipStream_t st);
 hipError_t launch_warm_fallback(int batch, int dim, const float *rw, const float *rc, const float *xs,
                                 const float *ls, float *xb, float *lam, uint32_t *flags, hipStream_t st);
 

@@ -78,6 +78,15 @@ extern "C" trajam_status trajam_mlp_forward(const trajam_mlp_shape *s, int32_t b
     return TRAJAM_OK;
 }
 
+extern "C" trajam_status trajam_mlp_pack_infer(const trajam_mlp_shape *s, const float *params, float *packed,
+                                               void *stream)
+{
+    if (!shape_ok(s)) return fail(TRAJAM_ERR_INVALID, "invalid network shape");
+    if (!params || !packed || params == packed) return fail(TRAJAM_ERR_INVALID, "distinct non-NULL pointers");
+    return dev(trajam::launch_mlp_pack_infer(s->n_layers, s->width, params, packed, (hipStream_t)stream),
+               "mlp pack");
+}
+
 extern "C" trajam_status trajam_mlp_infer(const trajam_mlp_shape *s, int32_t batch, const float *params,
                                           const float *x, float *y, void *stream)
 {

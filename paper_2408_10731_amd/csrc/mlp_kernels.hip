@@ -180,11 +180,13 @@ __global__ void adam_kernel(long n, float *__restrict__ p, const float *__restri
 
 // Fused inference: the whole network for kInferSamples samples per workgroup, the
 // activations of one layer kept in LDS as act[k][s] (the samples of one input feature
-// contiguous, read as one 128-bit broadcast), the weights read straight from L2
-// (every workgroup reads the same rows).  An output is computed by g lanes that split
-// its inputs (g = 256 / out rounded down to a power of two, at most 64), combined by
-// a butterfly over the g lanes, so thin layers keep the workgroup busy.  fp32 products,
-// the same sums as the layer-by-layer forward up to their order.
+// contiguous, read as one 128-bit broadcast), the weights read from L2 in the packed
+// layout (per layer W^T [in][out], then the bias), so that the lanes of a wave read
+// consecutive outputs of one input; eight weights are loaded before they are used.
+// An output is computed by g lanes that split its inputs (g = 256 / out rounded down
+// to a power of two, at most 64), combined by a butterfly over the g lanes, so thin
+// layers keep the workgroup busy.  fp32 products, the same sums as the layer-by-layer
+// forward up to their order.
 constexpr int kInferSamples = 8;
 constexpr int kInferMaxWidth = 512;
 
@@ -193,7 +195,21 @@ struct InferShape {
     int width[9];
 };
 
-__global__ __launch_bounds__(256) void mlp_infer_kernel(InferShape sh, int batch, const float *__restrict__ params,
+__device__ __forceinline__ void infer_fma(float (&acc)[kInferSamples], float wv, const float *a)
+{
+    const float4 a0 = *reinterpret_cast<const float4 *>(a);
+    const float4 a1 = *reinterpret_cast<const float4 *>(a + 4);
+    acc[0] = fmaf(wv, a0.x, acc[0]);
+    acc[1] = fmaf(wv, a0.y, acc[1]);
+    acc[2] = fmaf(wv, a0.z, acc[2]);
+    acc[3] = fmaf(wv, a0.w, acc[3]);
+    acc[4] = fmaf(wv, a1.x, acc[4]);
+    acc[5] = fmaf(wv, a1.y, acc[5]);
+    acc[6] = fmaf(wv, a1.z, acc[6]);
+    acc[7] = fmaf(wv, a1.w, acc[7]);
+}
+
+__global__ __launch_bounds__(256) void mlp_infer_kernel(InferShape sh, int batch, const float *__restrict__ packed,
                                                          const float *__restrict__ x, float *__restrict__ y)
 {
     constexpr int SB = kInferSamples;
@@ -207,11 +223,11 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(InferShape sh, int batch
         act[0][k][s] = s < ns ? x[(long)(s0 + s) * w0 + k] : 0.f;
     }
     __syncthreads();
-    const float *p = params;
+    const float *p = packed;
     int cur = 0;
     for (int l = 0; l < sh.n_layers; ++l) {
         const int in = sh.width[l], out = sh.width[l + 1];
-        const float *W = p, *bias = p + (long)out * in;
+        const float *Wt = p, *bias = p + (long)out * in;
         p += (long)out * in + out;
         const bool last = l == sh.n_layers - 1;
         int g = 1;
@@ -224,20 +240,16 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(InferShape sh, int batch
 #pragma unroll
             for (int s = 0; s < SB; ++s) acc[s] = 0.f;
             if (live) {
-                const float *wr = W + (long)o * in;
-                for (int k = part; k < in; k += g) {
-                    const float wv = wr[k];
-                    const float4 a0 = *reinterpret_cast<const float4 *>(&act[cur][k][0]);
-                    const float4 a1 = *reinterpret_cast<const float4 *>(&act[cur][k][4]);
-                    acc[0] = fmaf(wv, a0.x, acc[0]);
-                    acc[1] = fmaf(wv, a0.y, acc[1]);
-                    acc[2] = fmaf(wv, a0.z, acc[2]);
-                    acc[3] = fmaf(wv, a0.w, acc[3]);
-                    acc[4] = fmaf(wv, a1.x, acc[4]);
-                    acc[5] = fmaf(wv, a1.y, acc[5]);
-                    acc[6] = fmaf(wv, a1.z, acc[6]);
-                    acc[7] = fmaf(wv, a1.w, acc[7]);
+                const float *wc = Wt + o;
+                int k = part;
+                for (; k + 7 * g < in; k += 8 * g) {
+                    float wv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) wv[u] = wc[(long)(k + u * g) * out];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) infer_fma(acc, wv[u], &act[cur][k + u * g][0]);
                 }
+                for (; k < in; k += g) infer_fma(acc, wc[(long)k * out], &act[cur][k][0]);
             }
             for (int m = 1; m < g; m *= 2)
 #pragma unroll
@@ -258,6 +270,20 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(InferShape sh, int batch
     for (int e = tid; e < wl * SB; e += 256) {
         const int s = e / wl, o = e - s * wl;
         if (s < ns) y[(long)(s0 + s) * wl + o] = act[cur][o][s];
+    }
+}
+
+// Packed inference layout of one layer: W [out][in] -> W^T [in][out], bias copied.
+__global__ void mlp_pack_layer_kernel(int in, int out, const float *__restrict__ src, float *__restrict__ dst)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long nw = (long)in * out;
+    if (i >= nw + out) return;
+    if (i < nw) {
+        const int o = (int)(i / in), k = (int)(i - (long)o * in);
+        dst[(long)k * out + o] = src[i];
+    } else {
+        dst[i] = src[i];
     }
 }
 
@@ -350,6 +376,20 @@ hipError_t launch_adam(long n, float *p, const float *g, float *m, float *v, int
     hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, p, g, m, v, lr, b1,
                        b2, eps, c1, c2);
     return hipGetLastError();
+}
+
+hipError_t launch_mlp_pack_infer(int n_layers, const int *width, const float *params, float *packed, hipStream_t st)
+{
+    long off = 0;
+    for (int l = 0; l < n_layers; ++l) {
+        const long n = (long)width[l] * width[l + 1] + width[l + 1];
+        hipLaunchKernelGGL(mlp_pack_layer_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, width[l],
+                           width[l + 1], params + off, packed + off);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        off += n;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_mlp_infer(int n_layers, const int *width, int batch, const float *params, const float *x,

@@ -564,11 +564,14 @@ trajam_status agents_boundary(trajam_solver *s, const double *rows, hipStream_t 
     return TRAJAM_OK;
 }
 
+// Packs the obstacles of a call into the solver.  With obs_centre and obs_axes both
+// NULL, the obstacles packed last (by a call or by trajam_set_obstacles) are reused.
 trajam_status pack(trajam_solver *s, const void *c, const void *w, const void *ax, hipStream_t st)
 {
     const trajam_problem &p = s->prob;
     if (p.n_obstacles == 0) return TRAJAM_OK;
-    if (!c || !ax) return fail(s, TRAJAM_ERR_INVALID, "obstacle centre/axes pointer is NULL");
+    if (!c && !ax && !w && s->packed) return TRAJAM_OK;
+    if (!c || !ax) return fail(s, TRAJAM_ERR_INVALID, "obstacle centre/axes pointer is NULL (and none packed)");
     hipError_t e = (p.precision == TRAJAM_FP64)
                        ? trajam::launch_pack_obstacles_f64(p.dims, p.n_obstacles, (const double *)c,
                                                            (const double *)w, (const double *)ax,
@@ -577,6 +580,8 @@ trajam_status pack(trajam_solver *s, const void *c, const void *w, const void *a
                                                            (const float *)w, (const float *)ax,
                                                            (float *)s->d_obs, (float *)s->d_soa, st);
     if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("obstacle pack launch: ") + hipGetErrorString(e));
+    s->packed = true;
+    s->dynamic = w != nullptr;
     return TRAJAM_OK;
 }
 
@@ -601,7 +606,7 @@ extern "C" trajam_status trajam_project(trajam_solver *s, int32_t batch, const v
     trajam_status ps = pack(s, obs_centre, obs_vel, obs_axes, st);
     if (ps != TRAJAM_OK) return ps;
     const trajam_problem &p = s->prob;
-    const int dynamic = obs_vel != nullptr;
+    const int dynamic = s->dynamic;
     hipError_t e;
     if (p.n_agents > 1) {
         ps = agents_boundary(s, boundary_host, st);
@@ -684,7 +689,7 @@ extern "C" trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const
     if (p.precision == TRAJAM_FP64) {
         AmArgs<double> a;
         fill_args(s, a, batch, 0);
-        a.dynamic = obs_vel != nullptr;
+        a.dynamic = s->dynamic;
         a.xb = (double *)xi_bar;
         a.res = (double *)res_l2;
         a.res_max = (double *)res_max;
@@ -693,7 +698,7 @@ extern "C" trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const
     } else {
         AmArgs<float> a;
         fill_args(s, a, batch, 0);
-        a.dynamic = obs_vel != nullptr;
+        a.dynamic = s->dynamic;
         a.xb = (float *)xi_bar;
         a.res = (float *)res_l2;
         a.res_max = (float *)res_max;
@@ -780,11 +785,8 @@ extern "C" trajam_status trajam_set_obstacles(trajam_solver *s, const void *c, c
 {
     if (!s) return TRAJAM_ERR_INVALID;
     s->err.clear();
-    trajam_status st = pack(s, c, v, ax, (hipStream_t)stream);
-    if (st != TRAJAM_OK) return st;
-    s->packed = true;
-    s->dynamic = v != nullptr;
-    return TRAJAM_OK;
+    if (s->prob.n_obstacles > 0 && (!c || !ax)) return fail(s, TRAJAM_ERR_INVALID, "obstacle centre/axes pointer is NULL");
+    return pack(s, c, v, ax, (hipStream_t)stream);
 }
 
 namespace {

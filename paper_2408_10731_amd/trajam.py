@@ -45,7 +45,7 @@ EXPORTS = [
     "trajam_fixed_matrices", "trajam_set_launch", "trajam_get_launch",
     "trajam_boundary_coefficients", "trajam_cem_sample", "trajam_cem_cost",
     "trajam_cem_select", "trajam_cem_update", "trajam_mlp_param_count", "trajam_mlp_forward",
-    "trajam_mlp_backward", "trajam_mlp_infer", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
+    "trajam_mlp_backward", "trajam_mlp_infer", "trajam_mlp_pack_infer", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
     "trajam_warm_apply", "trajam_warm_fallback", "trajam_set_obstacles", "trajam_autotune",
     "trajam_ragged_plan_create", "trajam_ragged_launch", "trajam_ragged_plan_destroy",
     "trajam_status_string", "trajam_last_error",
@@ -160,6 +160,8 @@ def load():
                                     ctypes.c_float, vp, vp, vp, vp, vp, vp]
     L.trajam_mlp_infer.argtypes = [sp, ctypes.c_int32, vp, vp, vp, vp]
     L.trajam_mlp_infer.restype = ctypes.c_int
+    L.trajam_mlp_pack_infer.argtypes = [sp, vp, vp, vp]
+    L.trajam_mlp_pack_infer.restype = ctypes.c_int
     L.trajam_warm_fallback.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,
                                        vp, vp, vp, vp, vp]
     L.trajam_set_obstacles.argtypes = [vp, vp, vp, vp, vp]
@@ -311,8 +313,12 @@ def trajam_warm_apply(batch, dims, n_coeffs, y, out_scale, xi, xb, lam, xb_out, 
                                     xb, lam, xb_out, lam_out, stream))
 
 
-def trajam_mlp_infer(shape: MlpShape, batch, params, x, y, stream) -> None:
-    _check(load().trajam_mlp_infer(ctypes.byref(shape), int(batch), params, x, y, stream))
+def trajam_mlp_infer(shape: MlpShape, batch, packed, x, y, stream) -> None:
+    _check(load().trajam_mlp_infer(ctypes.byref(shape), int(batch), packed, x, y, stream))
+
+
+def trajam_mlp_pack_infer(shape: MlpShape, params, packed, stream) -> None:
+    _check(load().trajam_mlp_pack_infer(ctypes.byref(shape), params, packed, stream))
 
 
 def trajam_warm_fallback(batch, dims, n_coeffs, res_warm, res_cold, xb_src, lam_src, xb, lam,
@@ -404,9 +410,10 @@ class Solver:
             raise ValueError(f"{name} has shape {tuple(x.shape)}, expected {tuple(shape)}")
         return x.data_ptr()
 
-    def obstacles(self, centre, vel, axes):
+    def obstacles(self, centre=None, vel=None, axes=None):
+        """Device pointers of the obstacles; all None reuses the ones packed last."""
         n = self.problem.n_obstacles
-        if n == 0:
+        if n == 0 or (centre is None and vel is None and axes is None):
             return None, None, None
         c = self._t(centre, (n, self.dims), "obs_centre")
         v = None if vel is None else self._t(vel, (n, self.dims), "obs_vel")
@@ -418,7 +425,7 @@ class Solver:
         import torch
         B = xi.shape[0]
         shape = (B,) + self.sample_shape
-        c, v, a = self.obstacles(*obs)
+        c, v, a = self.obstacles(*(obs or ()))
         rt = None if res_trace is None else self._t(res_trace, (iters, B), "res_trace")
         fl = None
         if flags is not None:
@@ -433,7 +440,7 @@ class Solver:
     def residuals(self, xi_bar, obs, res_l2, res_max=None, stream=None):
         import torch
         B = xi_bar.shape[0]
-        c, v, a = self.obstacles(*obs)
+        c, v, a = self.obstacles(*(obs or ()))
         st = (stream or torch.cuda.current_stream()).cuda_stream
         trajam_residuals(self.handle, B, self._t(xi_bar, (B,) + self.sample_shape, "xi_bar"),
                          c, v, a, self._t(res_l2, (B,), "res_l2"),
@@ -444,6 +451,8 @@ class Solver:
 
     def set_obstacles(self, obs, stream=None):
         import torch
+        if self.problem.n_obstacles and (obs is None or obs[0] is None or obs[2] is None):
+            raise ValueError("set_obstacles needs centre and axes tensors")
         c, v, a = self.obstacles(*obs)
         st = (stream or torch.cuda.current_stream()).cuda_stream
         trajam_set_obstacles(self.handle, c, v, a, st)
@@ -453,7 +462,7 @@ class Solver:
         import torch
         B = xi.shape[0]
         shape = (B,) + self.sample_shape
-        c, v, a = self.obstacles(*obs)
+        c, v, a = self.obstacles(*(obs or ()))
         st = (stream or torch.cuda.current_stream()).cuda_stream
         return trajam_autotune(self.handle, B, self._t(xi, shape, "xi"), boundary, c, v, a,
                                self._t(xi_bar, shape, "xi_bar"), self._t(lam, shape, "lambda"),

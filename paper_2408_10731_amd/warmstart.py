@@ -236,9 +236,17 @@ class WarmContext:
         self.lw = torch.zeros(shape, device="cuda")
         self.x = torch.zeros((max_batch, 2 * self.dim), device="cuda")
         self.y = torch.zeros((max_batch, self.dim), device="cuda")
+        self.packed = torch.zeros_like(net.params)
+        self.refresh()
         self.trace = torch.zeros((self.k0, max_batch), device="cuda")
         self.rw = torch.zeros(max_batch, device="cuda")
         self.flags = torch.zeros(max_batch, dtype=torch.int32, device="cuda")
+
+    def refresh(self):
+        """Re-pack the network's parameters for inference (after training steps)."""
+        import torch
+        tj.trajam_mlp_pack_infer(self.net.shape, self.net.params.data_ptr(), self.packed.data_ptr(),
+                                 torch.cuda.current_stream().cuda_stream)
 
     def run(self, xi, boundary, obs):
         """(xb_w, lam_w, flags, probe_trace) for the samples xi [B, D, n_v]: the state
@@ -257,8 +265,8 @@ class WarmContext:
         tj.trajam_warm_features(B, D, nv, xi.data_ptr(), xp.data_ptr(), lp.data_ptr(),
                                 1.0 / IN_SCALE, x.data_ptr(), st)
         y = self.y[:B]
-        tj.trajam_mlp_infer(self.net.shape, B, self.net.params.data_ptr(), x.data_ptr(),
-                            y.data_ptr(), st)
+        tj.trajam_mlp_infer(self.net.shape, B, self.packed.data_ptr(), x.data_ptr(), y.data_ptr(),
+                            st)
         tj.trajam_warm_apply(B, D, nv, y.data_ptr(), OUT_SCALE, xi.data_ptr(), xp.data_ptr(),
                              lp.data_ptr(), xw.data_ptr(), lw.data_ptr(), st)
         rw = self.rw[:B]

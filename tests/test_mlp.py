@@ -200,8 +200,11 @@ def test_gpu_fused_inference_matches_oracle(widths, batch):
     pd = torch.as_tensor(params, device="cuda")
     xd = torch.as_tensor(x, device="cuda")
     y = torch.full((batch, widths[-1]), float("nan"), device="cuda")
-    tj.trajam_mlp_infer(tj.mlp_shape(widths), batch, pd.data_ptr(), xd.data_ptr(), y.data_ptr(),
-                        torch.cuda.current_stream().cuda_stream)
+    packed = torch.full_like(pd, float("nan"))
+    st = torch.cuda.current_stream().cuda_stream
+    tj.trajam_mlp_pack_infer(tj.mlp_shape(widths), pd.data_ptr(), packed.data_ptr(), st)
+    tj.trajam_mlp_infer(tj.mlp_shape(widths), batch, packed.data_ptr(), xd.data_ptr(), y.data_ptr(),
+                        st)
     torch.cuda.synchronize()
     got = y.double().cpu().numpy()
     err = np.abs(got - want).max() / max(1.0, np.abs(want).max())
