@@ -30,6 +30,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_VALU_OPS = 256 * 64 * 2.4e9  # lane-ops/s, one FMA = one op (no packed FP32)
+# HBM bytes per launch of the main kernel from FETCH_SIZE / WRITE_SIZE counter runs
+# scaled by a copy of known size (profiles/am_project_kernel_cfg2_fp32.md): 918 KiB
+# read + 1,824 KiB written.  Re-measure whenever the kernel changes.
+TRAFFIC_BYTES_PER_LAUNCH = (918 + 1824) * 1024
 
 
 def algorithmic_ops_per_traj_iter(w) -> float:
@@ -323,7 +327,19 @@ def main():
     ap.add_argument("--ragged-problems", type=int, default=256, help="0 skips the ragged set")
     ap.add_argument("--ragged-steps", type=int, default=3)
     ap.add_argument("--cem-calls", type=int, default=5, help="0 skips the sampling loop")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB buffer 3 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(samples are independent: a multi-GPU run shards the batch "
@@ -342,7 +358,10 @@ def main():
     lam = torch.zeros_like(xi)
     trace = torch.zeros((K, w.batch), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
-    solver.set_obstacles(obs)   # the scene's obstacles, packed once before timing
+    # launch shape from the autotuner (setup, untimed), then the scene's obstacles,
+    # packed once before timing
+    kern, spw = solver.autotune(xi, w.boundary, obs, xb, lam, probe_iters=K)
+    solver.set_obstacles(obs)
 
     def step():
         xb.copy_(xi)
@@ -377,8 +396,10 @@ def main():
     ops = algorithmic_ops_per_traj_iter(w) * w.batch * K
     achieved = ops / (launch_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12,
-                "unit": "Tops/s", "frac": achieved / PEAK_VALU_OPS, "traffic": None,
-                "kernel": "am_project_kernel<float,2,12>",
+                "unit": "Tops/s", "frac": achieved / PEAK_VALU_OPS,
+                "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+                "kernel": ("am_project_kernel<float,2,12>" if kern == 0 else
+                           "am_wave_kernel<float,2,12,2>") + f", {spw} sample(s)/workgroup",
                 "ops_per_traj_iter": algorithmic_ops_per_traj_iter(w),
                 "launch_ms": launch_ms}
 

@@ -210,8 +210,10 @@ trajam_status trajam_set_obstacles(trajam_solver *s, const void *obs_centre, con
                                    const void *obs_axes, void *stream);
 
 /* Autotuner: times every launch shape of trajam_project (both kernel variants, each
- * valid samples-per-workgroup) for `probe_iters` iterations on the given inputs with
- * HIP events, applies the fastest with trajam_set_launch and returns it.  Results are
+ * valid samples-per-workgroup; joint samples per workgroup for multi-agent problems)
+ * for `probe_iters` iterations on the given inputs with HIP events, applies the
+ * fastest with trajam_set_launch and returns it; the current shape is kept unless
+ * another is more than 3 % faster.  Results are
  * cached per process, keyed by (GPU architecture, dims, n_steps, n_obstacles rounded
  * up to a power of two, batch rounded up to a power of two, precision); a cached key
  * is applied without timing.  When the environment variable TRAJAM_AUTOTUNE_CACHE

@@ -863,7 +863,9 @@ extern "C" trajam_status trajam_autotune(trajam_solver *s, int32_t batch, const 
     }
     const size_t bytes = (size_t)batch * s->prob.n_agents * s->prob.dims * s->nv *
                          (s->prob.precision == TRAJAM_FP64 ? sizeof(double) : sizeof(float));
-    std::vector<std::pair<int, int>> cands;
+    // The current launch shape is timed first and stays unless another one is more
+    // than 3 % faster (timing noise must not flip the choice between runs).
+    std::vector<std::pair<int, int>> cands{{s->variant, s->tb}};
     // multi-agent launches have one shape parameter: joint samples (waves) per workgroup
     if (s->prob.n_agents == 1)
         for (int spw = 1; spw * s->tpad <= trajam::kMaxThreads; spw *= 2) cands.push_back({TRAJAM_KERNEL_MULTIWAVE, spw});
@@ -896,7 +898,7 @@ extern "C" trajam_status trajam_autotune(trajam_solver *s, int32_t batch, const 
             if (rep > 0) t_best = std::min(t_best, ms);  // first run warms caches
         }
         if (status != TRAJAM_OK) break;
-        if (t_best < best) {
+        if (best >= 1e29f || t_best < 0.97f * best) {
             best = t_best;
             pick = cd;
         }
