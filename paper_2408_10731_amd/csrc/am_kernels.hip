@@ -195,6 +195,26 @@ __device__ __forceinline__ T wave_min(T v)
     return fmin(a, b);
 }
 
+// Orders this wave's LDS writes before its later LDS reads (lanes of one wave
+// exchanging data through LDS); no other wave takes part, so no block barrier.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// Workgroup barrier that orders LDS only: inside the iteration loops the threads of a
+// workgroup exchange data through LDS alone (the residual trace is written, never
+// read back), so the barrier need not wait for outstanding global stores.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+
 constexpr int pow2ceil(int x) { return x <= 1 ? 1 : 2 * pow2ceil((x + 1) / 2); }
 
 // Obstacle data is read through the constant address space: the address is
@@ -403,9 +423,35 @@ __device__ __forceinline__ double readlane_t<double>(double v, int l)
 // obstacle.  Every row stays in F and in H; only provably zero terms are skipped.
 // Must be called by the whole wave (uniform control flow); points that must not
 // contribute sit at -1e30 and are flagged false in `ok`.
+// One 64-obstacle chunk of packed records, lane j holding obstacle base + j (zeros past
+// n_o).  The first chunk is loaded once per launch, before the iteration loop.
+template <typename T, int D>
+struct ObsChunk {
+    T c[D], w[D], is[D], s[D], nr2, r;
+};
+
+template <typename T, int D>
+__device__ __forceinline__ ObsChunk<T, D> load_obs_chunk(const T *aos_g, int n_o, int base, int lane)
+{
+    ObsChunk<T, D> k;
+    const int j = base + lane;
+    const bool has = j < n_o;
+    const T *o = aos_g + (size_t)(has ? j : 0) * kObstacleRecord;
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        k.c[ax] = has ? o[kOC + ax] : T(0);
+        k.w[ax] = has ? o[kOW + ax] : T(0);
+        k.is[ax] = has ? o[kOI + ax] : T(0);
+        k.s[ax] = has ? o[kOS + ax] : T(0);
+    }
+    k.nr2 = has ? o[kONR2] : T(0);
+    k.r = has ? o[kOR] : T(0);
+    return k;
+}
+
 template <typename T, int D, bool SPH, bool DYN, int NPT>
-__device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, int n_o, const T (&tt)[NPT],
-                                                   const T (&p)[NPT][D], const bool (&ok)[NPT],
+__device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, int n_o, const ObsChunk<T, D> &first,
+                                                   const T (&tt)[NPT], const T (&p)[NPT][D], const bool (&ok)[NPT],
                                                    T (&R)[NPT][D], T &r2, T &rmax)
 {
     const T big = T(1e30);
@@ -432,27 +478,20 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, int n_o, cons
     const int lane = threadIdx.x & 63;
     const T tabs = fmax(fabs(tlo), fabs(thi));
     for (int base = 0; base < n_o; base += 64) {
-        const int j = base + lane;
-        const bool has = j < n_o;
-        const T *o = aos_g + (size_t)(has ? j : 0) * kObstacleRecord;
-        T c[D], w[D], is[D], nr2 = T(0);
-        bool cand = has;
+        const ObsChunk<T, D> k = base == 0 ? first : load_obs_chunk<T, D>(aos_g, n_o, base, lane);
+        bool cand = base + lane < n_o;
 #pragma unroll
         for (int ax = 0; ax < D; ++ax) {
-            c[ax] = o[kOC + ax];
-            w[ax] = DYN ? o[kOW + ax] : T(0);
-            if (!SPH) is[ax] = o[kOI + ax];
-            const T e = SPH ? o[kOR] : o[kOS + ax];
-            T cmin = c[ax], cmax = c[ax], m = fma(e, T(1.0001), T(1e-4)) + T(1e-5) * fabs(c[ax]);
+            const T e = SPH ? k.r : k.s[ax];
+            T cmin = k.c[ax], cmax = k.c[ax], m = fma(e, T(1.0001), T(1e-4)) + T(1e-5) * fabs(k.c[ax]);
             if (DYN) {
-                const T c1 = fma(-w[ax], tlo, c[ax]), c2 = fma(-w[ax], thi, c[ax]);
+                const T c1 = fma(-k.w[ax], tlo, k.c[ax]), c2 = fma(-k.w[ax], thi, k.c[ax]);
                 cmin = fmin(c1, c2);
                 cmax = fmax(c1, c2);
-                m += T(1e-5) * (fabs(w[ax]) * tabs + fabs(cmin) + fabs(cmax));
+                m += T(1e-5) * (fabs(k.w[ax]) * tabs + fabs(cmin) + fabs(cmax));
             }
             cand = cand && (cmin - m <= hi[ax]) && (cmax + m >= lo[ax]);
         }
-        if (SPH) nr2 = o[kONR2];
         unsigned long long mask = __ballot(cand);
         while (mask) {
             const int u = __builtin_ctzll(mask);
@@ -460,11 +499,11 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, int n_o, cons
             T cu[D], wu[D], iu[D];
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) {
-                cu[ax] = readlane_t<T>(c[ax], u);
-                if (DYN) wu[ax] = readlane_t<T>(w[ax], u);
-                if (!SPH) iu[ax] = readlane_t<T>(is[ax], u);
+                cu[ax] = readlane_t<T>(k.c[ax], u);
+                if (DYN) wu[ax] = readlane_t<T>(k.w[ax], u);
+                if (!SPH) iu[ax] = readlane_t<T>(k.is[ax], u);
             }
-            const T nu = SPH ? readlane_t<T>(nr2, u) : T(0);
+            const T nu = SPH ? readlane_t<T>(k.nr2, u) : T(0);
 #pragma unroll
             for (int i = 0; i < NPT; ++i) {
                 T dx[D];
@@ -496,16 +535,16 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, int n_o, cons
 
 template <typename T, int D, int NPT>
 __device__ __forceinline__ void obstacle_residuals_culled(const T *aos_g, int n_o, int sphere, int dynamic,
-                                                          const T (&tt)[NPT], const T (&p)[NPT][D],
-                                                          const bool (&ok)[NPT], T (&R)[NPT][D], T &r2,
-                                                          T &rmax)
+                                                          const ObsChunk<T, D> &first, const T (&tt)[NPT],
+                                                          const T (&p)[NPT][D], const bool (&ok)[NPT],
+                                                          T (&R)[NPT][D], T &r2, T &rmax)
 {
     if (sphere) {
-        if (dynamic) obstacle_cull_loop<T, D, true, true, NPT>(aos_g, n_o, tt, p, ok, R, r2, rmax);
-        else obstacle_cull_loop<T, D, true, false, NPT>(aos_g, n_o, tt, p, ok, R, r2, rmax);
+        if (dynamic) obstacle_cull_loop<T, D, true, true, NPT>(aos_g, n_o, first, tt, p, ok, R, r2, rmax);
+        else obstacle_cull_loop<T, D, true, false, NPT>(aos_g, n_o, first, tt, p, ok, R, r2, rmax);
     } else {
-        if (dynamic) obstacle_cull_loop<T, D, false, true, NPT>(aos_g, n_o, tt, p, ok, R, r2, rmax);
-        else obstacle_cull_loop<T, D, false, false, NPT>(aos_g, n_o, tt, p, ok, R, r2, rmax);
+        if (dynamic) obstacle_cull_loop<T, D, false, true, NPT>(aos_g, n_o, first, tt, p, ok, R, r2, rmax);
+        else obstacle_cull_loop<T, D, false, false, NPT>(aos_g, n_o, first, tt, p, ok, R, r2, rmax);
     }
 }
 
@@ -658,6 +697,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
     if (lt < S && ls < a.tb) xbuf[ls * S + lt] = xb_o;  // buffer 0; padding entries are 0
     __syncthreads();
 
+    const ObsChunk<T, D> oc0 = load_obs_chunk<T, D>(a.obs, a.n_o, 0, threadIdx.x & 63);
     T res_first = T(0), res_last = T(0);
     bool nonfinite = false;
     int cur = 0;
@@ -689,7 +729,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
                 p1[0][ax] = valid ? p[ax] : T(-1e30);
                 R1[0][ax] = T(0);
             }
-            obstacle_residuals_culled<T, D, 1>(a.obs, a.n_o, a.sphere, a.dynamic, tt1, p1, ok1, R1, r2, rmax);
+            obstacle_residuals_culled<T, D, 1>(a.obs, a.n_o, a.sphere, a.dynamic, oc0, tt1, p1, ok1, R1, r2, rmax);
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) R[ax] = R1[0][ax];
         }
@@ -718,7 +758,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
         }
         const T r2w = wave_sum(r2);
         if (lane == 0) r2p[ls * wpt + wave_in_s] = r2w;
-        __syncthreads();
+        lds_barrier();
 
         // ---- step (c): multiplier (eq lag) and the QP right-hand side defect
         if (owner) {
@@ -743,7 +783,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
         // ---- step (b): xb_free += W [g_free ; boundary defect]  (eq affine_trans)
         const int nxt = cur ^ 1;
         if constexpr (MQP) {
-            __syncthreads();
+            lds_barrier();
             // y = g_f - H_fb Delta_b per (sample, axis) column; delta = W_ff y on the
             // matrix cores, then one refinement pass delta += W_ff (y - H_ff delta).
             float *yb = mq, *db = mq + 256;
@@ -760,7 +800,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
                 }
                 yb[i] = y;
             }
-            __syncthreads();
+            lds_barrier();
             const int cn = lane & 15, k0 = 4 * (lane >> 4);
             if (tid < 64) {
                 float yv[4];
@@ -770,7 +810,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) db[cn * 16 + k0 + i] = d0[i];
             }
-            __syncthreads();
+            lds_barrier();
             if (tid < 64) {
                 float rv[4], dv[16];
 #pragma unroll
@@ -786,7 +826,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) db[cn * 16 + k0 + i] = dv[k0 + i] + d1[i];
             }
-            __syncthreads();
+            lds_barrier();
             if (owner) {
                 if (o_free) xb_o += (T)db[(ls * D + o_ax) * 16 + (o_m - 3)];
                 else if (o_real) xb_o = bnd_o;
@@ -813,7 +853,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
             }
         }
         cur = nxt;
-        __syncthreads();
+        lds_barrier();
     }
 
     if (o_real) {
@@ -833,14 +873,6 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
     }
 }
 
-// Orders this wave's LDS writes before its later LDS reads (lanes of one wave
-// exchanging data through LDS); no other wave takes part, so no block barrier.
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // ----------------------------------------------------------------------------
 // One sample's whole projection on one wavefront: lane l owns time samples l,
@@ -892,6 +924,7 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
     if (owner) xs[o] = xb_o;
     wave_lds_sync();
 
+    const ObsChunk<T, D> oc0 = load_obs_chunk<T, D>(a.obs, a.n_o, 0, lane);
     T res_first = T(0), res_last = T(0);
     bool nonfinite = false;
     for (int k = 0; k < a.iters; ++k) {
@@ -925,7 +958,7 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
         for (int i = 0; i < TPL; ++i)
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) { R[i][ax] = T(0); rv[i][ax] = T(0); ra[i][ax] = T(0); }
-        obstacle_residuals_culled<T, D, TPL>(a.obs, a.n_o, a.sphere, a.dynamic, tt, p, valid, R, r2, rmax);
+        obstacle_residuals_culled<T, D, TPL>(a.obs, a.n_o, a.sphere, a.dynamic, oc0, tt, p, valid, R, r2, rmax);
 #pragma unroll
         for (int i = 0; i < TPL; ++i) {
             if (a.use_v) bound_residual<T, D>(v[i], a.vmax, rv[i], r2, rmax);
