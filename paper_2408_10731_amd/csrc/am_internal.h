@@ -47,10 +47,16 @@ struct AmArgs {
     // Multi-agent problems (n_agents > 1): samples are joint samples of n_agents
     // trajectories, xi / xb / lam are [batch][n_agents][D][nv].
     int n_agents;
+    int cull_lds;           // multi-agent: floats of the per-wave LDS obstacle stage, 0 = none
     T pair_r;               // combined radius of a pair (twice the agent radius)
     const T *W2;            // [NVP][NVP] QP operator of H + n_agents rho P^T P (agent deviations)
     const T *xiB_ag;        // [n_agents][D][4] boundary coefficients per agent
 };
+
+// Obstacle fields per obstacle in the multi-agent kernels' LDS stage, and the largest
+// stage per wave (floats) for which the stage is used (4 waves x 16 KiB).
+__host__ __device__ constexpr int stage_fields(int dims, bool sphere) { return sphere ? 2 * dims + 2 : 4 * dims; }
+constexpr int kStageMaxFloats = 4096;
 
 // Packed obstacle record length (scalars), any dims.
 constexpr int kObstacleRecord = 16;
@@ -118,7 +124,7 @@ hipError_t launch_warm_fallback(int batch, int dim, const float *rw, const float
 
 // Ragged persistent launch (FP32): zeroes the counter, then runs the work queue.
 hipError_t launch_ragged(const AmArgs<float> *probs, const int *offsets, int n_probs, int total, int *counter,
-                         int blocks, bool agents, hipStream_t st);
+                         int blocks, bool agents, int agent_stage, hipStream_t st);
 
 // Dynamic LDS bytes of one AM workgroup.
 size_t project_lds_bytes(int dims, int nvp, int tpad, int tb, size_t scalar);

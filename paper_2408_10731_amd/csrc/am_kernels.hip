@@ -449,8 +449,56 @@ __device__ __forceinline__ ObsChunk<T, D> load_obs_chunk(const T *aos_g, int n_o
     return k;
 }
 
-template <typename T, int D, bool SPH, bool DYN, int NPT>
-__device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, int n_o, const ObsChunk<T, D> &first,
+// Obstacle fields staged in a wave's LDS (multi-agent kernels): per obstacle
+// centre[D], -velocity[D], then -r^2 and r (spheres) or semi-axes[D] and their
+// inverses[D] (ellipsoids), each field an array over the obstacles
+// (stage_fields(D, sphere) arrays).
+
+template <typename T, int D>
+__device__ __forceinline__ void stage_obstacles(T *ol, const T *aos_g, int n_o, int sphere, int lane)
+{
+    for (int j = lane; j < n_o; j += 64) {
+        const T *o = aos_g + (size_t)j * kObstacleRecord;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            ol[ax * n_o + j] = o[kOC + ax];
+            ol[(D + ax) * n_o + j] = o[kOW + ax];
+            if (!sphere) {
+                ol[(2 * D + ax) * n_o + j] = o[kOS + ax];
+                ol[(3 * D + ax) * n_o + j] = o[kOI + ax];
+            }
+        }
+        if (sphere) {
+            ol[2 * D * n_o + j] = o[kONR2];
+            ol[(2 * D + 1) * n_o + j] = o[kOR];
+        }
+    }
+    wave_lds_sync();
+}
+
+template <typename T, int D, bool SPH>
+__device__ __forceinline__ ObsChunk<T, D> lds_obs_chunk(const T *ol, int n_o, int base, int lane)
+{
+    ObsChunk<T, D> k;
+    const int j = base + lane;
+    const int jj = j < n_o ? j : 0;
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        k.c[ax] = ol[ax * n_o + jj];
+        k.w[ax] = ol[(D + ax) * n_o + jj];
+        k.s[ax] = SPH ? T(0) : ol[(2 * D + ax) * n_o + jj];
+        k.is[ax] = SPH ? T(0) : ol[(3 * D + ax) * n_o + jj];
+    }
+    k.nr2 = SPH ? ol[2 * D * n_o + jj] : T(0);
+    k.r = SPH ? ol[(2 * D + 1) * n_o + jj] : T(0);
+    return k;
+}
+
+// Chunks of 64 obstacles (lane j: obstacle base + j) come from the LDS stage `ol`
+// (STAGED) or from the packed records, the first one from `first`, loaded once per
+// launch by the caller.
+template <typename T, int D, bool SPH, bool DYN, int NPT, bool STAGED>
+__device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, const T *ol, int n_o, const ObsChunk<T, D> first,
                                                    const T (&tt)[NPT], const T (&p)[NPT][D], const bool (&ok)[NPT],
                                                    T (&R)[NPT][D], T &r2, T &rmax)
 {
@@ -478,7 +526,8 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, int n_o, cons
     const int lane = threadIdx.x & 63;
     const T tabs = fmax(fabs(tlo), fabs(thi));
     for (int base = 0; base < n_o; base += 64) {
-        const ObsChunk<T, D> k = base == 0 ? first : load_obs_chunk<T, D>(aos_g, n_o, base, lane);
+        const ObsChunk<T, D> k = STAGED ? lds_obs_chunk<T, D, SPH>(ol, n_o, base, lane)
+                                        : (base == 0 ? first : load_obs_chunk<T, D>(aos_g, n_o, base, lane));
         bool cand = base + lane < n_o;
 #pragma unroll
         for (int ax = 0; ax < D; ++ax) {
@@ -535,16 +584,32 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, int n_o, cons
 
 template <typename T, int D, int NPT>
 __device__ __forceinline__ void obstacle_residuals_culled(const T *aos_g, int n_o, int sphere, int dynamic,
-                                                          const ObsChunk<T, D> &first, const T (&tt)[NPT],
+                                                          const ObsChunk<T, D> first, const T (&tt)[NPT],
                                                           const T (&p)[NPT][D], const bool (&ok)[NPT],
                                                           T (&R)[NPT][D], T &r2, T &rmax)
 {
     if (sphere) {
-        if (dynamic) obstacle_cull_loop<T, D, true, true, NPT>(aos_g, n_o, first, tt, p, ok, R, r2, rmax);
-        else obstacle_cull_loop<T, D, true, false, NPT>(aos_g, n_o, first, tt, p, ok, R, r2, rmax);
+        if (dynamic) obstacle_cull_loop<T, D, true, true, NPT, false>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax);
+        else obstacle_cull_loop<T, D, true, false, NPT, false>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax);
     } else {
-        if (dynamic) obstacle_cull_loop<T, D, false, true, NPT>(aos_g, n_o, first, tt, p, ok, R, r2, rmax);
-        else obstacle_cull_loop<T, D, false, false, NPT>(aos_g, n_o, first, tt, p, ok, R, r2, rmax);
+        if (dynamic) obstacle_cull_loop<T, D, false, true, NPT, false>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax);
+        else obstacle_cull_loop<T, D, false, false, NPT, false>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax);
+    }
+}
+
+// The culled loop on obstacles staged in this wave's LDS (`ol`).
+template <typename T, int D, int NPT>
+__device__ __forceinline__ void obstacle_residuals_staged(const T *ol, const T *aos_g, int n_o, int sphere,
+                                                          int dynamic, const T (&tt)[NPT], const T (&p)[NPT][D],
+                                                          const bool (&ok)[NPT], T (&R)[NPT][D], T &r2, T &rmax)
+{
+    const ObsChunk<T, D> none{};
+    if (sphere) {
+        if (dynamic) obstacle_cull_loop<T, D, true, true, NPT, true>(aos_g, ol, n_o, none, tt, p, ok, R, r2, rmax);
+        else obstacle_cull_loop<T, D, true, false, NPT, true>(aos_g, ol, n_o, none, tt, p, ok, R, r2, rmax);
+    } else {
+        if (dynamic) obstacle_cull_loop<T, D, false, true, NPT, true>(aos_g, ol, n_o, none, tt, p, ok, R, r2, rmax);
+        else obstacle_cull_loop<T, D, false, false, NPT, true>(aos_g, ol, n_o, none, tt, p, ok, R, r2, rmax);
     }
 }
 
@@ -1135,19 +1200,23 @@ __global__ __launch_bounds__(kMaxThreads) void am_wave_kernel(AmArgs<T> a)
 // this lane's position p, velocity v, acceleration acc.  Adds the summed position
 // residual to S and the velocity / acceleration residuals to rv / ra.
 template <typename T, int D, typename A>
-__device__ __forceinline__ void agents_rows(const A &a, int lane, bool active, T tt, const T (&p)[D],
+__device__ __forceinline__ void agents_rows(const A &a, const T *ol, int lane, bool active, T tt, const T (&p)[D],
                                             const T (&v)[D], const T (&acc)[D], T (&S)[D], T (&rv)[D],
                                             T (&ra)[D], T &r2, T &rmax)
 {
     const int N = a.n_agents;
     {
         T p1[1][D], S1[1][D], tt1[1] = {tt};
+        const bool ok1[1] = {active};
 #pragma unroll
         for (int ax = 0; ax < D; ++ax) {
             p1[0][ax] = active ? p[ax] : T(-1e30);
             S1[0][ax] = T(0);
         }
-        obstacle_residuals<T, D, 1>(a.obs_soa, a.obs, a.n_o, a.sphere, a.dynamic, tt1, p1, S1, r2, rmax);
+        // obstacles staged in LDS: only those whose box meets the agents' positions
+        // at this time are tested (exactly; see obstacle_cull_loop)
+        if (ol) obstacle_residuals_staged<T, D, 1>(ol, a.obs, a.n_o, a.sphere, a.dynamic, tt1, p1, ok1, S1, r2, rmax);
+        else obstacle_residuals<T, D, 1>(a.obs_soa, a.obs, a.n_o, a.sphere, a.dynamic, tt1, p1, S1, r2, rmax);
 #pragma unroll
         for (int ax = 0; ax < D; ++ax) S[ax] = S1[0][ax];
     }
@@ -1190,8 +1259,9 @@ __device__ __forceinline__ void agents_rows(const A &a, int lane, bool active, T
 
 // One joint sample's whole projection on one wavefront (n_agents <= 64 lanes).
 template <typename T, int D, int NVP, typename A>
-__device__ __forceinline__ void agents_sample(const A &a, const int sample, const int lane)
+__device__ __forceinline__ void agents_sample(const A &a, const int sample, const int lane, T *ol)
 {
+    if (ol) stage_obstacles<T, D>(ol, a.obs, a.n_o, a.sphere, lane);
     const int N = a.n_agents, nv = a.nv, n_p = a.n_p;
     const bool active = lane < N;
     const TRAJAM_CONST_AS T *phi = (const TRAJAM_CONST_AS T *)a.phi;
@@ -1239,7 +1309,7 @@ __device__ __forceinline__ void agents_sample(const A &a, const int sample, cons
                 acc[ax] = sa;
             }
             T S[D], rv[D], ra[D];
-            agents_rows<T, D, A>(a, lane, active, T(t) * a.dt, p, v, acc, S, rv, ra, r2, rmax);
+            agents_rows<T, D, A>(a, ol, lane, active, T(t) * a.dt, p, v, acc, S, rv, ra, r2, rmax);
 #pragma unroll
             for (int ax = 0; ax < D; ++ax)
 #pragma unroll
@@ -1320,8 +1390,9 @@ __device__ __forceinline__ void agents_sample(const A &a, const int sample, cons
 
 // Residual only, at the given joint coefficients: res[sample] = 2-norm, res_max.
 template <typename T, int D, int NVP, typename A>
-__device__ __forceinline__ void agents_residual(const A &a, const int sample, const int lane)
+__device__ __forceinline__ void agents_residual(const A &a, const int sample, const int lane, T *ol)
 {
+    if (ol) stage_obstacles<T, D>(ol, a.obs, a.n_o, a.sphere, lane);
     const int N = a.n_agents, nv = a.nv, n_p = a.n_p;
     const bool active = lane < N;
     const TRAJAM_CONST_AS T *phi = (const TRAJAM_CONST_AS T *)a.phi;
@@ -1348,7 +1419,7 @@ __device__ __forceinline__ void agents_residual(const A &a, const int sample, co
             acc[ax] = sa;
         }
         T S[D], rv[D], ra[D];
-        agents_rows<T, D, A>(a, lane, active, T(t) * a.dt, p, v, acc, S, rv, ra, r2, rmax);
+        agents_rows<T, D, A>(a, ol, lane, active, T(t) * a.dt, p, v, acc, S, rv, ra, r2, rmax);
     }
     const T r2w = wave_sum(r2), mx = wave_max(rmax);
     if (lane == 0) {
@@ -1357,20 +1428,25 @@ __device__ __forceinline__ void agents_residual(const A &a, const int sample, co
     }
 }
 
+// a.cull_lds: per-wave LDS stage of the obstacles (floats per wave), 0 = no culling.
 template <typename T, int D, int NVP>
 __global__ __launch_bounds__(kMaxThreads) void am_agents_kernel(AmArgs<T> a)
 {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int sample = blockIdx.x * a.tb + (threadIdx.x >> 6);
     if (sample >= a.batch) return;  // whole waves leave together
-    agents_sample<T, D, NVP, AmArgs<T>>(a, sample, threadIdx.x & 63);
+    T *ol = a.cull_lds ? reinterpret_cast<T *>(smem_raw) + (threadIdx.x >> 6) * a.cull_lds : nullptr;
+    agents_sample<T, D, NVP, AmArgs<T>>(a, sample, threadIdx.x & 63, ol);
 }
 
 template <typename T, int D, int NVP>
 __global__ __launch_bounds__(kMaxThreads) void am_agents_residual_kernel(AmArgs<T> a)
 {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     const int sample = blockIdx.x * a.tb + (threadIdx.x >> 6);
     if (sample >= a.batch) return;
-    agents_residual<T, D, NVP, AmArgs<T>>(a, sample, threadIdx.x & 63);
+    T *ol = a.cull_lds ? reinterpret_cast<T *>(smem_raw) + (threadIdx.x >> 6) * a.cull_lds : nullptr;
+    agents_residual<T, D, NVP, AmArgs<T>>(a, sample, threadIdx.x & 63, ol);
 }
 
 // ----------------------------------------------------------------------------
@@ -1406,10 +1482,10 @@ __device__ __forceinline__ void ragged_unit(const RaggedArgs &a, int sample, int
 template <bool AGENTS>
 __global__ __launch_bounds__(kMaxThreads) void am_ragged_kernel(const AmArgs<float> *__restrict__ probs_g,
                                                                 const int *__restrict__ offsets_g, int n_probs,
-                                                                int total, int *__restrict__ counter)
+                                                                int total, int *__restrict__ counter, int wave_lds)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float *wl = reinterpret_cast<float *>(smem_raw) + (threadIdx.x >> 6) * kRaggedWaveLds;
+    float *wl = reinterpret_cast<float *>(smem_raw) + (threadIdx.x >> 6) * wave_lds;
     const int lane = threadIdx.x & 63;
     // The table and the offsets are read-only for the launch: constant address space,
     // so with a wave-uniform unit index every field is a scalar load.
@@ -1431,8 +1507,11 @@ __global__ __launch_bounds__(kMaxThreads) void am_ragged_kernel(const AmArgs<flo
         const int nvp = a.nv <= 8 ? 8 : 12;
         const int tpl = (a.n_p + 63) >> 6;
         if constexpr (AGENTS) {
-            if (a.dims == 2) { if (nvp == 8) agents_sample<float, 2, 8, RaggedArgs>(a, sample, lane); else agents_sample<float, 2, 12, RaggedArgs>(a, sample, lane); }
-            else             { if (nvp == 8) agents_sample<float, 3, 8, RaggedArgs>(a, sample, lane); else agents_sample<float, 3, 12, RaggedArgs>(a, sample, lane); }
+            // per-wave obstacle stage: wl points at this wave's LDS slot (cull_lds floats)
+            float *ol = a.cull_lds ? wl : nullptr;
+            if (a.dims == 2) { if (nvp == 8) agents_sample<float, 2, 8, RaggedArgs>(a, sample, lane, ol); else agents_sample<float, 2, 12, RaggedArgs>(a, sample, lane, ol); }
+            else             { if (nvp == 8) agents_sample<float, 3, 8, RaggedArgs>(a, sample, lane, ol); else agents_sample<float, 3, 12, RaggedArgs>(a, sample, lane, ol); }
+            wave_lds_sync();  // the next unit restages
             continue;
         } else {
         if (a.dims == 2) {
@@ -1633,11 +1712,15 @@ hipError_t launch_agents_t(int dims, int nvp, const AmArgs<T> &a, bool residual,
 {
     if (a.batch <= 0) return hipSuccess;
     if (a.n_agents < 1 || a.n_agents > 64 || a.tb < 1 || a.tb > kMaxThreads / 64) return hipErrorInvalidValue;
+    // the obstacle stages of a workgroup's waves stay within 64 KiB of LDS
+    if (a.cull_lds < 0 || (size_t)a.cull_lds * sizeof(T) * a.tb > (size_t)kStageMaxFloats * sizeof(float) * 4)
+        return hipErrorInvalidValue;
     const dim3 grid((a.batch + a.tb - 1) / a.tb), block(64 * a.tb);
+    const size_t lds = sizeof(T) * (size_t)a.cull_lds * a.tb;
 #define TRAJAM_AGENTS(DD, NN)                                                                            \
     if (dims == DD && nvp == NN) {                                                                       \
-        if (residual) hipLaunchKernelGGL((am_agents_residual_kernel<T, DD, NN>), grid, block, 0, st, a); \
-        else hipLaunchKernelGGL((am_agents_kernel<T, DD, NN>), grid, block, 0, st, a);                   \
+        if (residual) hipLaunchKernelGGL((am_agents_residual_kernel<T, DD, NN>), grid, block, lds, st, a); \
+        else hipLaunchKernelGGL((am_agents_kernel<T, DD, NN>), grid, block, lds, st, a);                   \
         return hipGetLastError();                                                                        \
     }
     TRAJAM_AGENTS(2, 8)
@@ -1666,18 +1749,20 @@ hipError_t launch_agents_residual_f32(int dims, int nvp, const AmArgs<float> &a,
 }
 
 hipError_t launch_ragged(const AmArgs<float> *probs, const int *offsets, int n_probs, int total, int *counter,
-                         int blocks, bool agents, hipStream_t st)
+                         int blocks, bool agents, int agent_stage, hipStream_t st)
 {
     hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (agents) {
-        hipLaunchKernelGGL(am_ragged_kernel<true>, dim3(blocks), dim3(kMaxThreads), 0, st, probs, offsets, n_probs,
-                           total, counter);
+        if (agent_stage < 0 || agent_stage > kStageMaxFloats) return hipErrorInvalidValue;
+        const size_t lds = sizeof(float) * (size_t)agent_stage * (kMaxThreads / 64);
+        hipLaunchKernelGGL(am_ragged_kernel<true>, dim3(blocks), dim3(kMaxThreads), lds, st, probs, offsets, n_probs,
+                           total, counter, agent_stage);
     } else {
         const size_t lds = sizeof(float) * (size_t)kRaggedWaveLds * (kMaxThreads / 64);
         hipLaunchKernelGGL(am_ragged_kernel<false>, dim3(blocks), dim3(kMaxThreads), lds, st, probs, offsets,
-                           n_probs, total, counter);
+                           n_probs, total, counter, kRaggedWaveLds);
     }
     return hipGetLastError();
 }

@@ -539,6 +539,16 @@ std::vector<double> agent_boundary_coeffs(const trajam_problem &p, const double 
     return c;
 }
 
+// Floats of the per-wave LDS obstacle stage of the multi-agent kernels (0: the
+// obstacles are tested without the stage, when there are none or they do not fit).
+int agent_stage(const trajam_solver *s, size_t scalar, int waves)
+{
+    const trajam_problem &p = s->prob;
+    if (p.n_obstacles == 0) return 0;
+    const int st = trajam::stage_fields(p.dims, p.obstacle_model == TRAJAM_SPHERE) * p.n_obstacles;
+    return (size_t)st * scalar * waves <= (size_t)trajam::kStageMaxFloats * sizeof(float) * 4 ? st : 0;
+}
+
 // Multi-agent boundary: the device copy is rebuilt only when the rows change; a
 // change waits for the stream (no graph capture then) and copies synchronously.
 trajam_status agents_boundary(trajam_solver *s, const double *rows, hipStream_t st)
@@ -615,6 +625,7 @@ extern "C" trajam_status trajam_project(trajam_solver *s, int32_t batch, const v
             AmArgs<double> a;
             fill_args(s, a, batch, iters);
             a.dynamic = dynamic;
+            a.cull_lds = agent_stage(s, sizeof(double), a.tb);
             a.xi = (const double *)xi;
             a.xb = (double *)xi_bar;
             a.lam = (double *)lambda;
@@ -625,6 +636,7 @@ extern "C" trajam_status trajam_project(trajam_solver *s, int32_t batch, const v
             AmArgs<float> a;
             fill_args(s, a, batch, iters);
             a.dynamic = dynamic;
+            a.cull_lds = agent_stage(s, sizeof(float), a.tb);
             a.xi = (const float *)xi;
             a.xb = (float *)xi_bar;
             a.lam = (float *)lambda;
@@ -693,6 +705,7 @@ extern "C" trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const
         a.xb = (double *)xi_bar;
         a.res = (double *)res_l2;
         a.res_max = (double *)res_max;
+        if (p.n_agents > 1) a.cull_lds = agent_stage(s, sizeof(double), a.tb);
         e = p.n_agents > 1 ? trajam::launch_agents_residual_f64(p.dims, s->nvp, a, st)
                            : trajam::launch_residual_f64(p.dims, s->nvp, a, st);
     } else {
@@ -702,6 +715,7 @@ extern "C" trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const
         a.xb = (float *)xi_bar;
         a.res = (float *)res_l2;
         a.res_max = (float *)res_max;
+        if (p.n_agents > 1) a.cull_lds = agent_stage(s, sizeof(float), a.tb);
         e = p.n_agents > 1 ? trajam::launch_agents_residual_f32(p.dims, s->nvp, a, st)
                            : trajam::launch_residual_f32(p.dims, s->nvp, a, st);
     }
@@ -924,6 +938,7 @@ struct trajam_ragged_plan {
     int *d_offsets[2] = {nullptr, nullptr};
     int *d_counter = nullptr;  // [2]
     int n[2] = {0, 0}, total[2] = {0, 0}, blocks[2] = {0, 0};
+    int agent_stage = 0;  // floats per wave of the multi-agent kernel's obstacle stage
 };
 
 extern "C" void trajam_ragged_plan_destroy(trajam_ragged_plan *p)
@@ -966,6 +981,10 @@ extern "C" trajam_status trajam_ragged_plan_create(const trajam_ragged_item *ite
         fill_args(s, a, it.batch, iters);
         a.dynamic = s->dynamic;
         if (p.n_agents > 1) {
+            if (p.n_obstacles > 0) {
+                const int stg = trajam::stage_fields(p.dims, p.obstacle_model == TRAJAM_SPHERE) * p.n_obstacles;
+                a.cull_lds = stg <= trajam::kStageMaxFloats ? stg : 0;
+            }
             const size_t cnt = (size_t)p.n_agents * p.dims * 4;
             if (it.batch > 0)
                 for (size_t q = 0; q < cnt; ++q)
@@ -989,6 +1008,7 @@ extern "C" trajam_status trajam_ragged_plan_create(const trajam_ragged_item *ite
     }
     trajam_ragged_plan *plan = new (std::nothrow) trajam_ragged_plan();
     if (!plan) return fail(nullptr, TRAJAM_ERR_DEVICE, "host allocation failed");
+    for (int i = 0; i < n; ++i) plan->agent_stage = std::max(plan->agent_stage, args[i].cull_lds);
     hipError_t e = hipSuccess;
     if (!agent_bnd.empty()) {
         e = hipMalloc(&plan->d_bnd, sizeof(float) * agent_bnd.size());
@@ -1033,7 +1053,7 @@ extern "C" trajam_status trajam_ragged_launch(trajam_ragged_plan *p, void *strea
     for (int g = 0; g < 2; ++g) {
         if (p->total[g] == 0) continue;
         hipError_t e = trajam::launch_ragged((const AmArgs<float> *)p->d_probs[g], p->d_offsets[g], p->n[g],
-                                             p->total[g], p->d_counter + g, p->blocks[g], g == 1,
+                                             p->total[g], p->d_counter + g, p->blocks[g], g == 1, p->agent_stage,
                                              (hipStream_t)stream);
         if (e != hipSuccess)
             return fail(nullptr, TRAJAM_ERR_DEVICE, std::string("ragged launch: ") + hipGetErrorString(e));
