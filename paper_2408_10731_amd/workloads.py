@@ -252,7 +252,8 @@ def agents3d(seed: int, n_agents: int, n_obs: int, batch: int, iters: int = 50,
 
 def tiny_agents(dims: int = 2, n_agents: int = 3, batch: int = 2, n_obs: int = 1,
                 degree: int = 5, n_steps: int = 9, seed: int = 11,
-                agent_radius: float = 0.4) -> Workload:
+                agent_radius: float = 0.4, speed: float = 0.0,
+                per_axis: bool = False) -> Workload:
     """A few agents crossing a small square (each to the opposite corner region) for
     brute-force and by-hand checks of the joint projection."""
     rng = _rng(seed)
@@ -267,17 +268,20 @@ def tiny_agents(dims: int = 2, n_agents: int = 3, batch: int = 2, n_obs: int = 1
     for j in range(n_obs):
         while True:
             c = rng.uniform(-1.5, 1.5, size=dims)
-            s = np.full(dims, rng.uniform(0.2, 0.4))
+            if per_axis:
+                s = rng.uniform(0.2, 0.4, size=dims)
+            else:
+                s = np.full(dims, rng.uniform(0.2, 0.4))
             if _far_from(c, s, pts, 0.1):
                 break
         centre[j] = c
         axes[j] = s
+    vel = rng.uniform(-speed, speed, size=(n_obs, dims)) if speed > 0 else np.zeros((n_obs, dims))
     xi = np.stack([line_samples(rng, batch, degree, starts[a], goals[a], 0.3)
                    for a in range(n_agents)], 1)
     bnd = np.stack([boundary_rows(starts[a], goals[a]) for a in range(n_agents)])
     return Workload(f"tiny-agents-{dims}d", dims, degree, n_steps, 4.0, 3.0, 4.0, 1.0, centre,
-                    np.zeros((n_obs, dims)), axes, bnd, np.ascontiguousarray(xi), 5, "fp64",
-                    n_agents, agent_radius)
+                    vel, axes, bnd, np.ascontiguousarray(xi), 5, "fp64", n_agents, agent_radius)
 
 
 def ragged_set(n_problems: int = 256, seed: Optional[int] = None, n_obs=(5, 300),

@@ -29,15 +29,20 @@ def _tj():
     return tj
 
 
-@pytest.mark.parametrize("dims,N,n_obs", [(2, 3, 1), (3, 4, 2), (2, 5, 0), (3, 2, 3)])
-def test_fp64_every_iterate(dims, N, n_obs):
+@pytest.mark.parametrize("dims,N,n_obs,speed,per_axis", [
+    (2, 3, 1, 0.0, False), (3, 4, 2, 0.0, False), (2, 5, 0, 0.0, False), (3, 2, 3, 0.0, False),
+    (2, 4, 3, 0.3, False), (3, 3, 3, 0.3, True), (2, 3, 2, 0.0, True)])
+def test_fp64_every_iterate(dims, N, n_obs, speed, per_axis):
+    """Every iterate of the joint projection against the oracle, also with moving
+    obstacles and with ellipsoids (the obstacle stage's other field layouts)."""
     tj = _tj()
-    w = wl.tiny_agents(dims=dims, n_agents=N, n_obs=n_obs, batch=3)
+    w = wl.tiny_agents(dims=dims, n_agents=N, n_obs=n_obs, batch=3, speed=speed,
+                       per_axis=per_axis, seed=11 + N)
     K = 12
-    say(f"case: agents fp64 dims {dims} N {N} n_obs {n_obs}")
-    s = tj.Solver.for_workload(w, precision="fp64")
+    say(f"case: agents fp64 dims {dims} N {N} n_obs {n_obs} speed {speed} ellipsoids {per_axis}")
+    s = tj.Solver.for_workload(w, precision="fp64", sphere=not per_axis)
     s.set_launch(1, 2)
-    xi, obs = tj.device_workload(w, torch.float64)
+    xi, obs = tj.device_workload(w, torch.float64, static=speed == 0.0)
     xb, lam = xi.clone(), torch.zeros_like(xi)
     tr = torch.zeros((1, w.batch), dtype=torch.float64, device="cuda")
     for k in range(1, K + 1):
@@ -205,3 +210,28 @@ def test_agents_capture_after_boundary_is_cached():
         assert torch.equal(xb, ref)
     del g
     s.close()
+
+
+def test_fp32_many_obstacles_use_the_unstaged_loop():
+    """600 spheres do not fit the per-wave LDS stage (8 fields x 600 floats): the
+    multi-agent kernel tests them without the stage, with the same FP32 bar."""
+    w = wl.agents3d(9, 8, 600, 4, iters=20)
+    say("case: agents fp32 N=8 n_obs=600 (unstaged)")
+    _fp32_sampled(w, 20, np.array([0, 3]))
+
+
+def test_packed_obstacles_reused_bitwise():
+    """A call without obstacle pointers reuses the obstacles packed last and gives
+    the same bits as passing them again (single robot and multi-agent)."""
+    tj = _tj()
+    for w in (wl.problem2d(41, 30, 64, 10).rounded(np.float32),
+              wl.agents3d(42, 6, 20, 8, iters=10).rounded(np.float32)):
+        s = tj.Solver.for_workload(w, precision="fp32")
+        xi, obs = tj.device_workload(w, torch.float32)
+        xa, la = xi.clone(), torch.zeros_like(xi)
+        s.project(xi, w.boundary, obs, xa, la, 10)
+        xb, lb = xi.clone(), torch.zeros_like(xi)
+        s.project(xi, w.boundary, None, xb, lb, 10)
+        torch.cuda.synchronize()
+        assert torch.equal(xa, xb) and torch.equal(la, lb)
+        s.close()
