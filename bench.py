@@ -286,6 +286,8 @@ def cem_bench(args):
     z = torch.as_tensor(np.random.default_rng(1).normal(size=(N, Nb, D * nv)),
                         dtype=torch.float32, device="cuda")
     planner.set_distribution(mu0, S0, L0)
+    shape = planner.autotune(z[0], w.boundary, obs)
+    planner.set_distribution(mu0, S0, L0)
     planner.capture(z, w.boundary, obs)
     stream = torch.cuda.current_stream()
 
@@ -296,7 +298,8 @@ def cem_bench(args):
     ms = _time(call, args.cem_calls, stream)
     out = {"config": "30 CEM iterations x 2000 samples x 15 AM iterations, 100 moving "
                      "circles, 1454 projected / 363 elite, fp32, one graph replay per call",
-           "ms_per_planning_call": ms, "traj_iters_per_s": N * Nb * K / (ms * 1e-3)}
+           "ms_per_planning_call": ms, "traj_iters_per_s": N * Nb * K / (ms * 1e-3),
+           "launch_shape": list(shape)}
     solver.close()
     return out
 

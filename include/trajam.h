@@ -269,9 +269,13 @@ void trajam_ragged_plan_destroy(trajam_ragged_plan *plan);
 /* xi[i] = mu + chol z[i] for i < n (Alg 3, "draw N_b samples from N(mu, Sigma)").
  *   mu [dim], chol [dim][dim] lower-triangular Cholesky factor of Sigma,
  *   z [n][dim] standard normal draws (the caller's random numbers),
- *   xi [n][dims][degree+1] output.  Errors: INVALID, CAPACITY (n > max_batch), DEVICE. */
+ *   xi [n][dims][degree+1] output.
+ *   xi_bar, lambda [n][dims][degree+1]: optional outputs, NULL to skip; when given
+ *   they receive the cold start of the projection that follows (xi_bar = xi,
+ *   lambda = 0) from the same launch.
+ * Errors: INVALID, CAPACITY (n > max_batch), DEVICE. */
 trajam_status trajam_cem_sample(trajam_solver *s, int32_t n, const void *mu, const void *chol,
-                                const void *z, void *xi, void *stream);
+                                const void *z, void *xi, void *xi_bar, void *lambda, void *stream);
 
 /* Augmented cost of Alg 3: c_aug[i] = sum_t |Pdd xb_i(t)|^2 + res[i], and the residual
  * key res_key[i] = floor(res[i] / quantum) (int32, clamped), the resolution at which

@@ -1,6 +1,7 @@
 """Projection-guided sampling loop on the GPU (thesis ch. 6, Alg 3), driving the
-C-ABI kernels on one stream: sample -> project (cold start) -> residuals -> cost ->
-select -> update, N times.  Marshalling only; every step runs in the library.
+C-ABI kernels on one stream: the obstacles are packed once per call, then sample
+(with the projection's cold start) -> project -> residuals -> cost -> select ->
+update, N times.  Marshalling only; every step runs in the library.
 
 The standard normal draws z [N, N_b, dim] are an input.  All iterations can be
 captured into one HIP graph (`capture=True`): the loop never synchronizes with the
@@ -48,11 +49,11 @@ class Planner:
     def _iteration(self, z_l, boundary, obs, stream, record=None):
         h, st = self.s.handle, stream.cuda_stream
         tj.trajam_cem_sample(h, self.N_b, self.mu.data_ptr(), self.chol.data_ptr(),
-                             z_l.data_ptr(), self.xi.data_ptr(), st)
-        self.xb.copy_(self.xi)
-        self.lam.zero_()
-        self.s.project(self.xi, boundary, obs, self.xb, self.lam, self.K, stream=stream)
-        self.s.residuals(self.xb, obs, self.res, stream=stream)
+                             z_l.data_ptr(), self.xi.data_ptr(), self.xb.data_ptr(),
+                             self.lam.data_ptr(), st)
+        # obstacles were packed once for the whole call (None reuses them)
+        self.s.project(self.xi, boundary, None, self.xb, self.lam, self.K, stream=stream)
+        self.s.residuals(self.xb, None, self.res, stream=stream)
         tj.trajam_cem_cost(h, self.N_b, self.xb.data_ptr(), self.res.data_ptr(), self.quantum,
                            self.caug.data_ptr(), self.rkey.data_ptr(), st)
         tj.trajam_cem_select(h, self.N_b, self.rkey.data_ptr(), self.caug.data_ptr(),
@@ -67,6 +68,16 @@ class Planner:
         if record is not None:
             record[-1] = record[-1] + (self.mu.clone(), self.Sigma.clone())
 
+    def autotune(self, z0, boundary, obs):
+        """Pick the projection's launch shape for this planner's batch: draws one batch
+        from the current distribution with the draws z0 [N_b, dim] and times every
+        shape on it with the planner's iteration count.  Returns (kernel, samples/WG)."""
+        st = self.torch.cuda.current_stream()
+        tj.trajam_cem_sample(self.s.handle, self.N_b, self.mu.data_ptr(), self.chol.data_ptr(),
+                             z0.data_ptr(), self.xi.data_ptr(), self.xb.data_ptr(),
+                             self.lam.data_ptr(), st.cuda_stream)
+        return self.s.autotune(self.xi, boundary, obs, self.xb, self.lam, probe_iters=self.K)
+
     def best(self):
         """The returned trajectory of Alg 3: the projected sample of the last elite
         set with the lowest c_aug (elite_idx[0]); gathered on the device."""
@@ -79,6 +90,8 @@ class Planner:
 
     def _loop(self, z, boundary, obs, record=None, stream=None):
         stream = stream or self.torch.cuda.current_stream()
+        if self.s.problem.n_obstacles:
+            self.s.set_obstacles(obs, stream=stream)
         for l in range(z.shape[0]):
             self._iteration(z[l], boundary, obs, stream, record)
 

@@ -94,7 +94,7 @@ hipError_t launch_pack_obstacles_f32(int dims, int n_o, const float *c, const fl
 
 // Sampling-loop kernels (cem_kernels.hip).
 hipError_t launch_cem_sample(bool f64, int n, int dim, const void *mu, const void *L, const void *z,
-                             void *xi, hipStream_t st);
+                             void *xi, void *xb, void *lam, hipStream_t st);
 hipError_t launch_cem_cost(bool f64, int n, int dims, int nv, int n_p, int nvp, const void *phi,
                            const void *xb, const void *res, double quantum, void *caug, int32_t *rkey,
                            hipStream_t st);

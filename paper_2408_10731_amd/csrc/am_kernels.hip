@@ -1646,6 +1646,7 @@ hipError_t launch_project_t(const AmArgs<T> &a, hipStream_t st)
     const size_t lds = sizeof(T) * (size_t)L::total(a.tb, wpt) + (MQP ? sizeof(float) * kMqFloats : 0);
     const int threads = a.tb * a.tpad;
     const int blocks = (a.batch + a.tb - 1) / a.tb;
+    if (a.tb < 1 || threads > kMaxThreads) return hipErrorInvalidValue;
     if (MQP && (a.tb * D > 16 || a.nv - 4 > 16)) return hipErrorInvalidValue;
     hipLaunchKernelGGL((am_project_kernel<T, D, NVP, MQP>), dim3(blocks), dim3(threads), lds, st, a);
     return hipGetLastError();
@@ -1684,6 +1685,7 @@ hipError_t launch_residual_t(const AmArgs<T> &a, hipStream_t st)
     const size_t lds = sizeof(T) * 2 * (size_t)a.tb * wpt;
     const int threads = a.tb * a.tpad;
     const int blocks = (a.batch + a.tb - 1) / a.tb;
+    if (a.tb < 1 || threads > kMaxThreads) return hipErrorInvalidValue;
     hipLaunchKernelGGL((am_residual_kernel<T, D, NVP>), dim3(blocks), dim3(threads), lds, st, a);
     return hipGetLastError();
 }

@@ -1,21 +1,24 @@
 // gfx950 kernels of the projection-guided sampling loop (thesis ch. 6, Alg 3):
-// Gaussian sampling from (mu, L), the augmented cost and residual key, a one-
-// workgroup bitonic top-k with lexicographic keys, and the weighted mean /
-// covariance update (eqs update_mean, update_covariance) with the Cholesky factor
+// Gaussian sampling from (mu, L), the augmented cost and residual key, top-k
+// selection by rank with lexicographic keys, and the weighted mean / covariance
+// update (eqs update_mean, update_covariance) with the Cholesky factor
 // for the next draw.  The projection between sampling and cost is the AM kernel.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "am_internal.h"
 
 namespace trajam {
 namespace {
 
-// xi[i][r] = mu[r] + sum_{c <= r} L[r][c] z[i][c]
+// xi[i][r] = mu[r] + sum_{c <= r} L[r][c] z[i][c]; optionally the cold start of the
+// projection, xb = xi and lam = 0, from the same thread.
 template <typename T>
 __global__ void cem_sample_kernel(int n, int dim, const T *__restrict__ mu,
                                   const T *__restrict__ L, const T *__restrict__ z,
-                                  T *__restrict__ xi)
+                                  T *__restrict__ xi, T *__restrict__ xb, T *__restrict__ lam)
 {
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= n * dim) return;
@@ -23,6 +26,8 @@ __global__ void cem_sample_kernel(int n, int dim, const T *__restrict__ mu,
     T acc = mu[r];
     for (int c = 0; c <= r; ++c) acc = fma(L[r * dim + c], z[(size_t)i * dim + c], acc);
     xi[gid] = acc;
+    if (xb) xb[gid] = acc;
+    if (lam) lam[gid] = T(0);
 }
 
 template <typename T>
@@ -61,66 +66,74 @@ __global__ void cem_cost_kernel(int n, int dims, int nv, int n_p, int nvp,
     }
 }
 
-// Lexicographic (k1, k2, idx) comparison.
-template <typename T>
-__device__ __forceinline__ bool key_less(int32_t a1, T a2, int32_t ai, int32_t b1, T b2, int32_t bi)
+// Order-preserving unsigned images of the sort keys: a < b as numbers iff
+// ord(a) < ord(b).  -0 maps to +0 and every NaN to the largest image, so NaNs sort
+// after +inf and tie among themselves (then by index), as a stable lexicographic
+// sort of the numbers does.
+__device__ __forceinline__ uint32_t ord_key(int32_t v) { return (uint32_t)v ^ 0x80000000u; }
+
+__device__ __forceinline__ uint64_t ord_key(float v)
 {
-    if (a1 != b1) return a1 < b1;
-    if (a2 != b2) return a2 < b2;
-    return ai < bi;
+    if (v != v) return 0xffffffffull;
+    const uint32_t b = __float_as_uint(v == 0.f ? 0.f : v);
+    return (b & 0x80000000u) ? (uint64_t)(~b) : (uint64_t)(b | 0x80000000u);
 }
 
-template <typename T>
-__device__ void bitonic_sort(int32_t *k1, T *k2, int32_t *id, int len)
+__device__ __forceinline__ uint64_t ord_key(double v)
 {
-    for (int size = 2; size <= len; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = threadIdx.x; t < len / 2; t += blockDim.x) {
-                const int lo = 2 * t - (t & (stride - 1));
-                const int hi = lo + stride;
-                const bool up = ((lo & size) == 0);
-                const bool lt = key_less(k1[hi], k2[hi], id[hi], k1[lo], k2[lo], id[lo]);
-                if (lt == up) {
-                    int32_t a = k1[lo]; k1[lo] = k1[hi]; k1[hi] = a;
-                    T b = k2[lo]; k2[lo] = k2[hi]; k2[hi] = b;
-                    int32_t c = id[lo]; id[lo] = id[hi]; id[hi] = c;
-                }
-            }
-            __syncthreads();
-        }
-    }
+    if (v != v) return ~0ull;
+    const uint64_t b = (uint64_t)__double_as_longlong(v == 0.0 ? 0.0 : v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
 
-// One workgroup: the n_proj smallest (rkey, caug, index) and, among those, the
-// n_elite smallest (caug, index).  len = n rounded up to a power of two (<= 4096).
-template <typename T>
-__global__ void cem_select_kernel(int n, int len, const int32_t *__restrict__ rkey,
-                                  const T *__restrict__ caug, int n_proj, int n_elite,
-                                  int32_t *__restrict__ proj_idx, int32_t *__restrict__ elite_idx)
+constexpr int kRankThreads = 256, kRankSub = 16, kRankPerBlock = kRankThreads / kRankSub;
+
+// Selection by rank.  Keys are unique (the index breaks every tie), so the rank of
+// element i, the number of keys below its key, is its position in the sorted order;
+// an element whose rank is below n_keep writes its index to out[rank].  Every block
+// stages all n keys in LDS and ranks kRankPerBlock elements, kRankSub threads per
+// element each counting a strided slice of the keys.
+//   SUBSET = false: element i has key (rkey[i], caug[i], i).
+//   SUBSET = true : element e is list[e] with key (caug[list[e]], list[e]).
+template <typename T, bool SUBSET>
+__global__ __launch_bounds__(kRankThreads) void cem_rank_kernel(int n, const int32_t *__restrict__ rkey,
+                                                               const T *__restrict__ caug,
+                                                               const int32_t *__restrict__ list, int n_keep,
+                                                               int32_t *__restrict__ out)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *k2 = reinterpret_cast<T *>(smem_raw);
-    int32_t *k1 = reinterpret_cast<int32_t *>(k2 + len);
-    int32_t *id = k1 + len;
-    for (int i = threadIdx.x; i < len; i += blockDim.x) {
-        const bool real = i < n;
-        k1[i] = real ? rkey[i] : 2147483647;
-        k2[i] = real ? caug[i] : T(INFINITY);
-        id[i] = real ? i : 2147483647;
+    uint64_t *k2 = reinterpret_cast<uint64_t *>(smem_raw);   // [n] caug image
+    uint32_t *k1 = reinterpret_cast<uint32_t *>(k2 + n);     // [n] rkey image, or the index
+#pragma unroll 4
+    for (int j = threadIdx.x; j < n; j += kRankThreads) {
+        if (SUBSET) {
+            const int32_t p = list[j];
+            k2[j] = ord_key(caug[p]);
+            k1[j] = (uint32_t)p;
+        } else {
+            k2[j] = ord_key(caug[j]);
+            k1[j] = ord_key(rkey[j]);
+        }
     }
     __syncthreads();
-    bitonic_sort<T>(k1, k2, id, len);
-    for (int i = threadIdx.x; i < n_proj; i += blockDim.x) proj_idx[i] = id[i];
-    __syncthreads();
-    // second stage: the ConstraintEliteSet by (caug, index)
-    for (int i = threadIdx.x; i < len; i += blockDim.x) {
-        const bool real = i < n_proj;
-        k1[i] = real ? 0 : 2147483647;
-        if (!real) { k2[i] = T(INFINITY); id[i] = 2147483647; }
+    const int e = blockIdx.x * kRankPerBlock + (int)(threadIdx.x / kRankSub);
+    const int sub = threadIdx.x & (kRankSub - 1);
+    const int ee = e < n ? e : n - 1;
+    const uint32_t a1 = k1[ee];
+    const uint64_t a2 = k2[ee];
+    int cnt = 0;
+#pragma unroll 4
+    for (int j = sub; j < n; j += kRankSub) {
+        const uint32_t b1 = k1[j];
+        const uint64_t b2 = k2[j];
+        bool lt;
+        if (SUBSET) lt = b2 < a2 || (b2 == a2 && b1 < a1);            // (caug, index)
+        else lt = b1 < a1 || (b1 == a1 && (b2 < a2 || (b2 == a2 && j < ee)));  // (rkey, caug, index)
+        cnt += lt ? 1 : 0;
     }
-    __syncthreads();
-    bitonic_sort<T>(k1, k2, id, len);
-    for (int i = threadIdx.x; i < n_elite; i += blockDim.x) elite_idx[i] = id[i];
+#pragma unroll
+    for (int off = kRankSub / 2; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if (sub == 0 && e < n && cnt < n_keep) out[cnt] = SUBSET ? (int32_t)a1 : e;
 }
 
 enum class Red { kSum, kMin };
@@ -143,87 +156,218 @@ __device__ T block_reduce(T v, T *scratch, Red op)
     return r;
 }
 
-// One workgroup: weights, new mean and covariance, and L = chol(Sigma + eps I).
+// Orders the LDS accesses of one wave around this point (the wave's lanes exchange
+// values through LDS; no other wave takes part).
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+constexpr int kUpdThreads = 256;
+constexpr size_t kUpdLds = 65536;
+
+// LDS layout of cem_update_kernel: wgt[n_elite] | mun[MAXD] | part[256] | scratch[16] |
+// X[rows][MAXD] (a chunk of elite rows, later the matrix to factor).  Rows are padded
+// to MAXD columns so that the unrolled loops over a row need no bounds tests.
 template <typename T>
-__global__ void cem_update_kernel(int n_elite, int dim, const int32_t *__restrict__ elite,
-                                  const T *__restrict__ xb, const T *__restrict__ caug, T sigma,
-                                  T gamma, T eps, T *__restrict__ mu, T *__restrict__ Sigma,
-                                  T *__restrict__ L)
+__host__ __device__ inline size_t upd_fixed_bytes(int n_elite, int maxd)
+{
+    return sizeof(T) * ((size_t)n_elite + maxd + kUpdThreads + 16);
+}
+
+// One workgroup: weights, new mean and covariance (eqs update_mean,
+// update_covariance) and L = chol(Sigma + eps I).  Elite rows are staged in LDS in
+// chunks of `rows` (all of them when they fit); the mean is a sum of per-thread
+// strided partials, each lower-triangle covariance entry is one thread's sum over
+// the elites (SL entries per thread), and the factor is computed by one wave with
+// row r in lane r's registers (dim <= MAXD <= 64).
+template <typename T, int MAXD, int SL>
+__global__ __launch_bounds__(kUpdThreads) void cem_update_kernel(int n_elite, int dim, int rows,
+                                                                 const int32_t *__restrict__ elite,
+                                                                 const T *__restrict__ xb,
+                                                                 const T *__restrict__ caug, T sigma, T gamma,
+                                                                 T eps, T *__restrict__ mu,
+                                                                 T *__restrict__ Sigma, T *__restrict__ L)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *wgt = reinterpret_cast<T *>(smem_raw);       // [n_elite]
-    T *mun = wgt + n_elite;                          // [dim]
-    T *A = mun + dim;                                // [dim][dim]
-    T *scratch = A + dim * dim;                      // [16]
+    T *wgt = reinterpret_cast<T *>(smem_raw);   // [n_elite]
+    T *mun = wgt + n_elite;                      // [MAXD], zero past dim
+    T *part = mun + MAXD;                        // [256]
+    T *scratch = part + kUpdThreads;             // [16]
+    T *X = scratch + 16;                         // [rows][MAXD], then [MAXD][MAXD]
     const int tid = threadIdx.x;
-    // delta = min c_aug, spread = population std over the elite set
+    const bool resident = rows >= n_elite;
+    // row e of the elite set -> X[e - c0][:]; one thread per row so that a row costs
+    // one round trip of independent loads (columns past dim repeat the last one)
+    auto load_rows = [&](int c0, int cn) {
+        for (int e = tid; e < cn; e += kUpdThreads) {
+            const T *src = xb + (size_t)elite[c0 + e] * dim;
+            T v[MAXD];
+#pragma unroll
+            for (int c = 0; c < MAXD; ++c) v[c] = src[min(c, dim - 1)];
+#pragma unroll
+            for (int c = 0; c < MAXD; ++c) X[e * MAXD + c] = v[c];
+        }
+    };
     T mn = T(INFINITY), s = T(0);
-    for (int e = tid; e < n_elite; e += blockDim.x) {
+#pragma unroll 4
+    for (int e = tid; e < n_elite; e += kUpdThreads) {
         const T c = caug[elite[e]];
+        wgt[e] = c;
         mn = fmin(mn, c);
         s += c;
     }
+    if (resident) load_rows(0, n_elite);
+    // delta = min c_aug, spread = population std over the elite set
     const T delta = block_reduce(mn, scratch, Red::kMin);
     const T mean = block_reduce(s, scratch, Red::kSum) / T(n_elite);
     T v = T(0);
-    for (int e = tid; e < n_elite; e += blockDim.x) {
-        const T d = caug[elite[e]] - mean;
+    for (int e = tid; e < n_elite; e += kUpdThreads) {
+        const T d = wgt[e] - mean;
         v = fma(d, d, v);
     }
     const T spread = sqrt(block_reduce(v, scratch, Red::kSum) / T(n_elite));
     const T scale = spread > T(0) ? gamma * spread : T(1);
     T sw = T(0);
-    for (int e = tid; e < n_elite; e += blockDim.x) {
-        const T wv = exp(-(caug[elite[e]] - delta) / scale);
+    for (int e = tid; e < n_elite; e += kUpdThreads) {
+        const T wv = exp(-(wgt[e] - delta) / scale);
         wgt[e] = wv;
         sw += wv;
     }
-    const T wsum = block_reduce(sw, scratch, Red::kSum);
-    __syncthreads();
-    for (int r = tid; r < dim; r += blockDim.x) {
-        T acc = T(0);
-        for (int e = 0; e < n_elite; ++e) acc = fma(wgt[e], xb[(size_t)elite[e] * dim + r], acc);
-        mun[r] = (T(1) - sigma) * mu[r] + sigma * acc / wsum;
+    const T wsum = block_reduce(sw, scratch, Red::kSum);  // ends with a barrier: wgt[] complete
+
+    // mean: thread (r, sl) sums elites sl, sl + S, ... of every chunk for coordinate r
+    const int S = kUpdThreads / dim;
+    const int mr = tid % dim, msl = tid / dim;
+    T macc = T(0);
+    for (int c0 = 0; c0 < n_elite; c0 += rows) {
+        const int cn = min(rows, n_elite - c0);
+        if (!resident) load_rows(c0, cn);
+        __syncthreads();
+        if (msl < S)
+#pragma unroll 4
+            for (int e = msl; e < cn; e += S) macc = fma(wgt[c0 + e], X[e * MAXD + mr], macc);
+        __syncthreads();
     }
+    if (msl < S) part[tid] = macc;
     __syncthreads();
-    for (int i = tid; i < dim * dim; i += blockDim.x) {
-        const int r = i / dim, c = i - (i / dim) * dim;
-        T acc = T(0);
-        for (int e = 0; e < n_elite; ++e) {
-            const T *x = xb + (size_t)elite[e] * dim;
-            acc = fma(wgt[e] * (x[r] - mun[r]), x[c] - mun[c], acc);
+    if (tid < MAXD) {
+        T m = T(0);
+        if (tid < dim) {
+            T a = T(0);
+            for (int k = 0; k < S; ++k) a += part[k * dim + tid];
+            m = (T(1) - sigma) * mu[tid] + sigma * a / wsum;
+            mu[tid] = m;
         }
-        const T sn = (T(1) - sigma) * Sigma[i] + sigma * acc / wsum;
-        Sigma[i] = sn;
-        A[i] = sn + (r == c ? eps : T(0));
+        mun[tid] = m;
     }
-    for (int r = tid; r < dim; r += blockDim.x) mu[r] = mun[r];
-    __syncthreads();
-    // right-looking Cholesky in LDS: column j, then the trailing update
-    for (int j = 0; j < dim; ++j) {
-        if (tid == 0) A[j * dim + j] = sqrt(A[j * dim + j]);
+    // covariance: slot k of thread tid holds lower-triangle entry q = tid + 256 k,
+    // q = r (r + 1) / 2 + c; slots past the triangle accumulate entry (0, 0) and are
+    // dropped, so the elite loop has no per-lane branches
+    const int n_ent = dim * (dim + 1) / 2;
+    int er[SL], ec[SL];
+    T cacc[SL];
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int q = tid + k * kUpdThreads;
+        int r = (int)((sqrtf(8.f * (float)q + 1.f) - 1.f) * 0.5f);
+        while (r * (r + 1) / 2 > q) --r;
+        while ((r + 1) * (r + 2) / 2 <= q) ++r;
+        const bool on = q < n_ent;
+        er[k] = on ? r : 0;
+        ec[k] = on ? q - r * (r + 1) / 2 : 0;
+        cacc[k] = T(0);
+    }
+    for (int c0 = 0; c0 < n_elite; c0 += rows) {
+        const int cn = min(rows, n_elite - c0);
+        if (!resident) load_rows(c0, cn);
+        __syncthreads();   // chunk loaded; mun[] visible
+        for (int e = tid; e < cn; e += kUpdThreads)
+#pragma unroll
+            for (int c = 0; c < MAXD; ++c) X[e * MAXD + c] -= mun[c];
         __syncthreads();
-        for (int r = j + 1 + tid; r < dim; r += blockDim.x) A[r * dim + j] /= A[j * dim + j];
-        __syncthreads();
-        for (int i = tid; i < dim * dim; i += blockDim.x) {
-            const int r = i / dim, c = i - (i / dim) * dim;
-            if (r > j && c > j && c <= r) A[i] = fma(-A[r * dim + j], A[c * dim + j], A[i]);
+#pragma unroll 4
+        for (int e = 0; e < cn; ++e) {
+            const T w = wgt[c0 + e];
+            const T *x = X + e * MAXD;
+#pragma unroll
+            for (int k = 0; k < SL; ++k) cacc[k] = fma(w * x[er[k]], x[ec[k]], cacc[k]);
         }
         __syncthreads();
     }
-    for (int i = tid; i < dim * dim; i += blockDim.x) {
-        const int r = i / dim, c = i - (i / dim) * dim;
-        L[i] = c <= r ? A[i] : T(0);
+    // Sigma' = (1 - sigma) Sigma + sigma C / wsum from the lower triangle, mirrored;
+    // A = Sigma' + eps I overwrites the staged rows
+    T *A = X;
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        if (tid + k * kUpdThreads >= n_ent) continue;
+        const int r = er[k], c = ec[k];
+        const T sn = (T(1) - sigma) * Sigma[r * dim + c] + sigma * cacc[k] / wsum;
+        Sigma[r * dim + c] = sn;
+        Sigma[c * dim + r] = sn;
+        A[r * MAXD + c] = sn + (r == c ? eps : T(0));
+    }
+    __syncthreads();
+    if (tid >= 64) return;
+    // right-looking Cholesky by one wave, row r in lane r's registers; column j's
+    // scaled entries L[.][j] reach the other lanes through LDS (part[] is free now).
+    // Entries above the diagonal, and rows and columns past dim, carry values that
+    // are never read back nor stored, so the unrolled update needs no masks.
+    const int r = tid;
+    T *col = part;
+    T a[MAXD];
+#pragma unroll
+    for (int c = 0; c < MAXD; ++c) a[c] = (r < dim && c <= r) ? A[r * MAXD + c] : T(0);
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j) {
+        if (j < dim) {
+            if (r == j) col[0] = a[j];
+            wave_sync_lds();
+            const T d = sqrt(col[0]);
+            const T l = r == j ? d : a[j] / d;
+            a[j] = l;
+            col[1 + r] = l;
+            wave_sync_lds();
+#pragma unroll
+            for (int c = j + 1; c < MAXD; ++c) a[c] = fma(-l, col[1 + c], a[c]);
+            wave_sync_lds();
+        }
+    }
+    // rows back through LDS, then L written coalesced (zero above the diagonal)
+    if (r < dim)
+#pragma unroll
+        for (int c = 0; c < MAXD; ++c) A[r * MAXD + c] = a[c];
+    wave_sync_lds();
+    for (int i = r; i < dim * dim; i += 64) {
+        const int rr = i / dim, cc = i - rr * dim;
+        L[i] = cc <= rr ? A[rr * MAXD + cc] : T(0);
     }
 }
 
+template <typename T, int MAXD, int SL>
+hipError_t update_launch(int n_elite, int dim, const int32_t *elite, const void *xb, const void *caug,
+                         double sigma, double gamma, double eps, void *mu, void *Sigma, void *L, hipStream_t st)
+{
+    const size_t fixed = upd_fixed_bytes<T>(n_elite, MAXD);
+    const size_t row_bytes = (size_t)MAXD * sizeof(T);
+    if (fixed + (size_t)MAXD * row_bytes > kUpdLds) return hipErrorInvalidValue;
+    const int rows = (int)std::min<size_t>((size_t)n_elite, (kUpdLds - fixed) / row_bytes);
+    const size_t lds = fixed + (size_t)std::max(rows, MAXD) * row_bytes;
+    hipLaunchKernelGGL((cem_update_kernel<T, MAXD, SL>), dim3(1), dim3(kUpdThreads), lds, st, n_elite, dim, rows,
+                       elite, (const T *)xb, (const T *)caug, (T)sigma, (T)gamma, (T)eps, (T *)mu, (T *)Sigma,
+                       (T *)L);
+    return hipGetLastError();
+}
+
 template <typename T>
-hipError_t sample_t(int n, int dim, const void *mu, const void *L, const void *z, void *xi,
-                    hipStream_t st)
+hipError_t sample_t(int n, int dim, const void *mu, const void *L, const void *z, void *xi, void *xb,
+                    void *lam, hipStream_t st)
 {
     const int total = n * dim, threads = 256;
     hipLaunchKernelGGL(cem_sample_kernel<T>, dim3((total + threads - 1) / threads), dim3(threads), 0, st,
-                       n, dim, (const T *)mu, (const T *)L, (const T *)z, (T *)xi);
+                       n, dim, (const T *)mu, (const T *)L, (const T *)z, (T *)xi, (T *)xb, (T *)lam);
     return hipGetLastError();
 }
 
@@ -242,12 +386,18 @@ template <typename T>
 hipError_t select_t(int n, const int32_t *rkey, const void *caug, int n_proj, int n_elite,
                     int32_t *proj, int32_t *elite, hipStream_t st)
 {
-    int len = 1;
-    while (len < n) len <<= 1;
-    if (len < 2) len = 2;
-    const size_t lds = (size_t)len * (sizeof(T) + 2 * sizeof(int32_t));
-    hipLaunchKernelGGL(cem_select_kernel<T>, dim3(1), dim3(1024), lds, st, n, len, rkey, (const T *)caug,
-                       n_proj, n_elite, proj, elite);
+    // first the n_proj smallest (rkey, caug, index), then among those the n_elite
+    // smallest (caug, index); the second launch ranks the first one's output
+    const size_t lds1 = (size_t)n * (sizeof(uint64_t) + sizeof(uint32_t));
+    hipLaunchKernelGGL((cem_rank_kernel<T, false>), dim3((n + kRankPerBlock - 1) / kRankPerBlock),
+                       dim3(kRankThreads), lds1, st, n, rkey, (const T *)caug, (const int32_t *)nullptr, n_proj,
+                       proj);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds2 = (size_t)n_proj * (sizeof(uint64_t) + sizeof(uint32_t));
+    hipLaunchKernelGGL((cem_rank_kernel<T, true>), dim3((n_proj + kRankPerBlock - 1) / kRankPerBlock),
+                       dim3(kRankThreads), lds2, st, n_proj, (const int32_t *)nullptr, (const T *)caug,
+                       (const int32_t *)proj, n_elite, elite);
     return hipGetLastError();
 }
 
@@ -256,19 +406,22 @@ hipError_t update_t(int n_elite, int dim, const int32_t *elite, const void *xb, 
                     double sigma, double gamma, double eps, void *mu, void *Sigma, void *L,
                     hipStream_t st)
 {
-    const size_t lds = sizeof(T) * ((size_t)n_elite + dim + (size_t)dim * dim + 16);
-    hipLaunchKernelGGL(cem_update_kernel<T>, dim3(1), dim3(256), lds, st, n_elite, dim, elite,
-                       (const T *)xb, (const T *)caug, (T)sigma, (T)gamma, (T)eps, (T *)mu,
-                       (T *)Sigma, (T *)L);
-    return hipGetLastError();
+    // instances (MAXD, SL): dim <= MAXD and dim (dim + 1) / 2 <= 256 SL
+    if (dim < 1 || dim > 48) return hipErrorInvalidValue;
+    if (dim <= 16) return update_launch<T, 16, 1>(n_elite, dim, elite, xb, caug, sigma, gamma, eps, mu, Sigma, L, st);
+    if (dim <= 22) return update_launch<T, 24, 1>(n_elite, dim, elite, xb, caug, sigma, gamma, eps, mu, Sigma, L, st);
+    if (dim <= 24) return update_launch<T, 24, 2>(n_elite, dim, elite, xb, caug, sigma, gamma, eps, mu, Sigma, L, st);
+    if (dim <= 32) return update_launch<T, 32, 3>(n_elite, dim, elite, xb, caug, sigma, gamma, eps, mu, Sigma, L, st);
+    return update_launch<T, 48, 5>(n_elite, dim, elite, xb, caug, sigma, gamma, eps, mu, Sigma, L, st);
 }
 
 }  // namespace
 
 hipError_t launch_cem_sample(bool f64, int n, int dim, const void *mu, const void *L, const void *z,
-                             void *xi, hipStream_t st)
+                             void *xi, void *xb, void *lam, hipStream_t st)
 {
-    return f64 ? sample_t<double>(n, dim, mu, L, z, xi, st) : sample_t<float>(n, dim, mu, L, z, xi, st);
+    return f64 ? sample_t<double>(n, dim, mu, L, z, xi, xb, lam, st)
+               : sample_t<float>(n, dim, mu, L, z, xi, xb, lam, st);
 }
 
 hipError_t launch_cem_cost(bool f64, int n, int dims, int nv, int n_p, int nvp, const void *phi,

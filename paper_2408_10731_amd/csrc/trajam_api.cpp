@@ -530,6 +530,11 @@ void fill_args(const trajam_solver *s, AmArgs<T> &a, int batch, int iters)
     a.xiB_ag = (const T *)s->d_xiBag;
 }
 
+// Samples per workgroup of the single-robot residual kernel (roundup64(n_steps)
+// threads per sample): its own shape, independent of the projection's launch
+// variant, whose samples-per-workgroup count means 64-lane waves for the wave kernel.
+int residual_spw(const trajam_solver *s) { return std::max(1, trajam::kMaxThreads / s->tpad); }
+
 // Boundary coefficients of every agent ([n_agents][D][4]) from boundary rows
 // [n_agents][D][4] (x0, v0, a0, xf).
 std::vector<double> agent_boundary_coeffs(const trajam_problem &p, const double *rows)
@@ -701,6 +706,7 @@ extern "C" trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const
     if (p.precision == TRAJAM_FP64) {
         AmArgs<double> a;
         fill_args(s, a, batch, 0);
+        if (p.n_agents == 1) a.tb = residual_spw(s);
         a.dynamic = s->dynamic;
         a.xb = (double *)xi_bar;
         a.res = (double *)res_l2;
@@ -711,6 +717,7 @@ extern "C" trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const
     } else {
         AmArgs<float> a;
         fill_args(s, a, batch, 0);
+        if (p.n_agents == 1) a.tb = residual_spw(s);
         a.dynamic = s->dynamic;
         a.xb = (float *)xi_bar;
         a.res = (float *)res_l2;
@@ -726,7 +733,7 @@ extern "C" trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const
 // ---- sampling loop ------------------------------------------------------------
 
 extern "C" trajam_status trajam_cem_sample(trajam_solver *s, int32_t n, const void *mu, const void *chol,
-                                           const void *z, void *xi, void *stream)
+                                           const void *z, void *xi, void *xi_bar, void *lambda, void *stream)
 {
     if (!s) return TRAJAM_ERR_INVALID;
     s->err.clear();
@@ -736,8 +743,8 @@ extern "C" trajam_status trajam_cem_sample(trajam_solver *s, int32_t n, const vo
     if (n == 0) return TRAJAM_OK;
     if (!mu || !chol || !z || !xi) return fail(s, TRAJAM_ERR_INVALID, "NULL pointer");
     const int dim = s->prob.dims * s->nv;
-    hipError_t e = trajam::launch_cem_sample(s->prob.precision == TRAJAM_FP64, n, dim, mu, chol, z, xi,
-                                             (hipStream_t)stream);
+    hipError_t e = trajam::launch_cem_sample(s->prob.precision == TRAJAM_FP64, n, dim, mu, chol, z, xi, xi_bar,
+                                             lambda, (hipStream_t)stream);
     if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("cem sample: ") + hipGetErrorString(e));
     return TRAJAM_OK;
 }
@@ -899,16 +906,25 @@ extern "C" trajam_status trajam_autotune(trajam_solver *s, int32_t batch, const 
                 status = fail(s, TRAJAM_ERR_DEVICE, "autotune reset failed");
                 break;
             }
-            hipEventRecord(e0, st);
+            if (hipEventRecord(e0, st) != hipSuccess) {
+                status = fail(s, TRAJAM_ERR_DEVICE, "autotune timing failed");
+                break;
+            }
             status = trajam_project(s, batch, xi, boundary, c, v, ax, xb, lam, probe_iters, nullptr, nullptr, stream);
-            hipEventRecord(e1, st);
             if (status != TRAJAM_OK) break;
+            if (hipEventRecord(e1, st) != hipSuccess) {
+                status = fail(s, TRAJAM_ERR_DEVICE, "autotune timing failed");
+                break;
+            }
             if (hipEventSynchronize(e1) != hipSuccess) {
                 status = fail(s, TRAJAM_ERR_DEVICE, "autotune timing failed");
                 break;
             }
             float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                status = fail(s, TRAJAM_ERR_DEVICE, "autotune timing failed");
+                break;
+            }
             if (rep > 0) t_best = std::min(t_best, ms);  // first run warms caches
         }
         if (status != TRAJAM_OK) break;
@@ -917,8 +933,8 @@ extern "C" trajam_status trajam_autotune(trajam_solver *s, int32_t batch, const 
             pick = cd;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (status != TRAJAM_OK) return status;
     trajam_set_launch(s, pick.first, pick.second);
     {

@@ -135,7 +135,7 @@ def load():
     L.trajam_get_launch.restype = ctypes.c_int
     L.trajam_boundary_coefficients.argtypes = [ctypes.POINTER(Problem), dp, dp]
     L.trajam_boundary_coefficients.restype = ctypes.c_int
-    L.trajam_cem_sample.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp]
+    L.trajam_cem_sample.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
     L.trajam_cem_sample.restype = ctypes.c_int
     L.trajam_cem_cost.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_double, vp, vp, vp]
     L.trajam_cem_cost.restype = ctypes.c_int
@@ -255,8 +255,8 @@ def trajam_boundary_coefficients(problem: Problem, b4) -> np.ndarray:
     return out
 
 
-def trajam_cem_sample(handle, n, mu, chol, z, xi, stream) -> None:
-    _check(load().trajam_cem_sample(handle, int(n), mu, chol, z, xi, stream), handle)
+def trajam_cem_sample(handle, n, mu, chol, z, xi, xi_bar, lam, stream) -> None:
+    _check(load().trajam_cem_sample(handle, int(n), mu, chol, z, xi, xi_bar, lam, stream), handle)
 
 
 def trajam_cem_cost(handle, n, xi_bar, res, quantum, c_aug, res_key, stream) -> None:

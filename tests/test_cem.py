@@ -134,6 +134,52 @@ def test_gpu_select_is_exact_on_generated_keys():
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("dims,degree,n,n_elite,precision", [
+    (2, 10, 2000, 363, "fp32"),    # config-4 sizes: every elite row resident in LDS
+    (3, 11, 4096, 4096, "fp64"),   # 36 coordinates, elite rows staged in chunks
+    (3, 15, 1200, 700, "fp64"),    # the widest distribution (48 coordinates), chunked
+    (2, 3, 10, 1, "fp64"),         # one elite: zero spread, zero sample covariance
+])
+def test_gpu_update_matches_the_weighted_formula(dims, degree, n, n_elite, precision):
+    """The distribution update on given elites equals the FP64 formula of the
+    oracle (weights, mean, covariance) and its factor equals a library Cholesky of
+    Sigma' + eps I."""
+    from paper_2408_10731_amd import trajam as tj
+    dim = dims * (degree + 1)
+    rng = np.random.default_rng(dim + n_elite)
+    prob = tj.make_problem(dims, degree, 4 * (degree + 1), 10.0, 5.0, 5.0, 1.0, 1, n, precision)
+    solver = tj.Solver(prob)
+    dt = solver.dtype
+    xb = rng.normal(size=(n, dim))
+    caug = rng.uniform(0.0, 50.0, size=n)
+    elite = rng.permutation(n)[:n_elite].astype(np.int32)
+    mu0 = rng.normal(size=dim)
+    A = rng.normal(size=(dim, dim))
+    S0 = A @ A.T / dim + 0.1 * np.eye(dim)
+    if precision == "fp32":   # the formula takes the values the device holds
+        xb, caug, mu0, S0 = (np.float32(a).astype(np.float64) for a in (xb, caug, mu0, S0))
+    print("case: update", dims, degree, n, n_elite, precision, flush=True)
+    d_xb, d_c = torch.as_tensor(xb, dtype=dt, device="cuda"), torch.as_tensor(caug, dtype=dt, device="cuda")
+    d_el = torch.as_tensor(elite, device="cuda")
+    d_mu = torch.as_tensor(mu0, dtype=dt, device="cuda")
+    d_S = torch.as_tensor(S0, dtype=dt, device="cuda")
+    d_L = torch.zeros((dim, dim), dtype=dt, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    tj.trajam_cem_update(solver.handle, n_elite, d_el.data_ptr(), d_xb.data_ptr(), d_c.data_ptr(),
+                         0.6, 2.0, d_mu.data_ptr(), d_S.data_ptr(), d_L.data_ptr(), st)
+    torch.cuda.synchronize()
+    mu1, S1, _ = ocem.weighted_update(mu0, S0, xb[elite], caug[elite], 0.6, 2.0)
+    L1 = np.linalg.cholesky(S1 + ocem.EPS_CHOL * np.eye(dim))
+    tol = 1e-10 if precision == "fp64" else 2e-4
+    got_S = d_S.cpu().numpy()
+    np.testing.assert_allclose(d_mu.cpu().numpy(), mu1, atol=tol * 10)
+    np.testing.assert_allclose(got_S, S1, atol=tol * 10)
+    assert np.array_equal(got_S, got_S.T)
+    np.testing.assert_allclose(d_L.cpu().numpy(), L1, atol=tol * 10)
+    solver.close()
+
+
+@pytest.mark.gpu
 def test_gpu_cem_fp64_matches_oracle_per_iteration():
     w, mu0, S0 = cem_problem(n_obs=20)
     N, Nb, Np, Ne, K = 3, 256, 186, 47, 10

@@ -167,6 +167,34 @@ def test_fp64_residuals_entry_point():
     np.testing.assert_allclose(m.cpu().numpy(), mo, atol=1e-10)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_residuals_independent_of_the_projection_launch_shape(precision):
+    """The residual kernel keeps its own launch shape: with 100 time steps (128
+    threads per sample) every projection shape, including 4 samples per workgroup of
+    the wave kernel, gives the same residuals bit for bit (regression: the residual
+    launch once took the projection's samples-per-workgroup count)."""
+    tj = _tj()
+    w = wl.tiny(dims=2, batch=37, n_obs=7, degree=10, n_steps=100, speed=0.5, seed=5)
+    say("case: residual launch shapes", precision)
+    solver = tj.Solver.for_workload(w, precision=precision)
+    dt = solver.dtype
+    xb = w.xi + np.random.default_rng(3).normal(size=w.xi.shape) * 0.3
+    _, obs = tj.device_workload(w, dt)
+    xbd = torch.as_tensor(xb, dtype=dt, device="cuda").contiguous()
+    outs = []
+    for kernel, spw in [(0, 1), (0, 2), (1, 1), (1, 2), (1, 3), (1, 4)]:
+        solver.set_launch(kernel, spw)
+        r = torch.zeros(w.batch, dtype=dt, device="cuda")
+        solver.residuals(xbd, obs, r)
+        torch.cuda.synchronize()
+        outs.append(r.cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    if precision == "fp64":
+        np.testing.assert_allclose(outs[0], oracle.residuals(w, xb)[0], atol=1e-10)
+    solver.close()
+
+
 def test_fp64_resumable_tile_invariant_and_deterministic():
     w = wl.config1(batch=37)  # ragged for 2 and 4 samples per workgroup
     say("case: resumable / tile invariance")
