@@ -195,6 +195,109 @@ __device__ __forceinline__ T wave_min(T v)
     return fmin(a, b);
 }
 
+// ---- the wave's bounding box in one packed reduction (FP32) --------------------
+// Floats enter as order-preserving int32 images (an involution: a < b iff
+// ord_i(a) < ord_i(b) for non-NaN values), so every step is an integer minimum,
+// which needs no NaN canonicalisation and lets DPP fold into the v_min_i32.
+__device__ __forceinline__ int ord_i(float x)
+{
+    const int b = __float_as_int(x);
+    return b ^ ((b >> 31) & 0x7fffffff);
+}
+__device__ __forceinline__ float ord_f(int k) { return __int_as_float(k ^ ((k >> 31) & 0x7fffffff)); }
+
+__device__ __forceinline__ void swap32(int &a, int &b)
+{
+    auto r = __builtin_amdgcn_permlane32_swap((unsigned)a, (unsigned)b, false, false);
+    a = (int)r[0];
+    b = (int)r[1];
+}
+__device__ __forceinline__ void swap16(int &a, int &b)
+{
+    auto r = __builtin_amdgcn_permlane16_swap((unsigned)a, (unsigned)b, false, false);
+    a = (int)r[0];
+    b = (int)r[1];
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_min_operand(int x)
+{
+    return __builtin_amdgcn_update_dpp(0x7fffffff, x, CTRL, 0xF, 0xF, false);
+}
+
+// Minimum over the 64 lanes of NV (4 or 8) int values at once: the permlane swaps
+// halve the live values (lanes with lane bit 5, then 4, keep the upper half), for
+// NV = 8 a DPP row rotation halves once more on lane bit 3, and DPP steps reduce the
+// one value left inside its row.  Value j ends in every lane l with
+// l / (64 / NV) == j.
+template <int NV>
+__device__ __forceinline__ int wave_min_multi(int (&c)[NV], int lane)
+{
+    static_assert(NV == 4 || NV == 8, "packed reduction width");
+#pragma unroll
+    for (int i = 0; i < NV / 2; ++i) {
+        swap32(c[i], c[i + NV / 2]);
+        c[i] = min(c[i], c[i + NV / 2]);
+    }
+#pragma unroll
+    for (int i = 0; i < NV / 4; ++i) {
+        swap16(c[i], c[i + NV / 4]);
+        c[i] = min(c[i], c[i + NV / 4]);
+    }
+    int v;
+    if constexpr (NV == 8) {
+        int lo = c[0], hi = c[1];
+        asm volatile("" : "+v"(lo), "+v"(hi));
+        const bool up = (lane & 8) != 0;
+        v = min(up ? hi : lo, dpp_min_operand<kDppRor8>(up ? lo : hi));
+    } else {
+        v = min(c[0], dpp_min_operand<kDppRor8>(c[0]));
+    }
+    v = min(v, dpp_min_operand<kDppHalfMirror>(v));
+    v = min(v, dpp_min_operand<kDppXor2>(v));
+    v = min(v, dpp_min_operand<kDppXor1>(v));
+    return v;
+}
+
+// Box of the wave's points over lanes/points with ok (and their time range when DYN):
+// minima of every coordinate and of the negated coordinates in one reduction.  A lane
+// without points contributes +1e30 / -1e30, and NaN coordinates are dropped by the
+// per-lane fmin / fmax, so the keys are never NaN.
+template <int D, bool DYN, int NPT>
+__device__ __forceinline__ void wave_box(const float (&tt)[NPT], const float (&p)[NPT][D], const bool (&ok)[NPT],
+                                         float (&lo)[D], float (&hi)[D], float &tlo, float &thi)
+{
+    constexpr int NQ = D + (DYN ? 1 : 0);
+    constexpr int NV = 2 * NQ <= 4 ? 4 : 8;
+    const float big = 1e30f;
+    int c[NV];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        float mn = big, mx = -big;
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const float x = q < D ? p[i][q < D ? q : 0] : tt[i];
+            if (ok[i]) { mn = fminf(mn, x); mx = fmaxf(mx, x); }
+        }
+        c[q] = ord_i(mn);
+        c[NQ + q] = ord_i(-mx);
+    }
+#pragma unroll
+    for (int j = 2 * NQ; j < NV; ++j) c[j] = 0x7fffffff;
+    const int v = wave_min_multi<NV>(c, threadIdx.x & 63);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const float mn = ord_f(__builtin_amdgcn_readlane(v, (64 / NV) * q));
+        const float mx = -ord_f(__builtin_amdgcn_readlane(v, (64 / NV) * (NQ + q)));
+        if (q < D) {
+            lo[q < D ? q : 0] = mn;
+            hi[q < D ? q : 0] = mx;
+        } else {
+            tlo = mn;
+            thi = mx;
+        }
+    }
+}
+
 // Orders this wave's LDS writes before its later LDS reads (lanes of one wave
 // exchanging data through LDS); no other wave takes part, so no block barrier.
 __device__ __forceinline__ void wave_lds_sync()
@@ -282,6 +385,39 @@ __device__ __forceinline__ void obstacle_inside(const TRAJAM_CONST_AS T *o, cons
         for (int ax = 0; ax < D; ++ax) r[ax] = T(0);
         constexpr int push = (D == 2) ? 0 : 2;
         r[push] = SPH ? -o[kOR] : -o[kOS + push];
+    }
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        R[ax] += r[ax];
+        r2 = fma(r[ax], r[ax], r2);
+        rmax = fmax(rmax, fabs(r[ax]));
+    }
+}
+
+// The same residual as obstacle_inside from the offset dx = p - c(t) the inside test
+// already formed (identical operations), with the obstacle's fields passed as
+// wave-uniform values: rad the radius (spheres), iu the inverse semi-axes and s_push
+// the semi-axis along the push direction (ellipsoids).
+template <typename T, int D, bool SPH>
+__device__ __forceinline__ void obstacle_residual_at(const T (&dx)[D], T rad, const T (&iu)[D], T s_push,
+                                                     T (&R)[D], T &r2, T &rmax)
+{
+    T nn = T(0);
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        const T u = SPH ? dx[ax] : dx[ax] * iu[ax];
+        nn = fma(u, u, nn);
+    }
+    T r[D];
+    if (nn > T(0)) {
+        const T f = SPH ? (T(1) - rad * rsqrt_t(nn)) : (T(1) - rsqrt_t(nn));
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) r[ax] = dx[ax] * f;
+    } else {
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) r[ax] = T(0);
+        constexpr int push = (D == 2) ? 0 : 2;
+        r[push] = SPH ? -rad : -s_push;
     }
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) {
@@ -504,25 +640,28 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, const T *ol, 
 {
     const T big = T(1e30);
     T lo[D], hi[D], tlo = T(0), thi = T(0);
+    if constexpr (sizeof(T) == sizeof(float)) {
+        wave_box<D, DYN, NPT>(tt, p, ok, lo, hi, tlo, thi);
+    } else {
 #pragma unroll
-    for (int ax = 0; ax < D; ++ax) {
-        T mn = big, mx = -big;
+        for (int ax = 0; ax < D; ++ax) {
+            T mn = big, mx = -big;
 #pragma unroll
-        for (int i = 0; i < NPT; ++i)
-            if (ok[i]) { mn = fmin(mn, p[i][ax]); mx = fmax(mx, p[i][ax]); }
-        lo[ax] = wave_min(mn);
-        hi[ax] = wave_max(mx);
-    }
-    if (DYN) {
-        T mn = big, mx = -big;
+            for (int i = 0; i < NPT; ++i)
+                if (ok[i]) { mn = fmin(mn, p[i][ax]); mx = fmax(mx, p[i][ax]); }
+            lo[ax] = wave_min(mn);
+            hi[ax] = wave_max(mx);
+        }
+        if (DYN) {
+            T mn = big, mx = -big;
 #pragma unroll
-        for (int i = 0; i < NPT; ++i)
-            if (ok[i]) { mn = fmin(mn, tt[i]); mx = fmax(mx, tt[i]); }
-        tlo = wave_min(mn);
-        thi = wave_max(mx);
+            for (int i = 0; i < NPT; ++i)
+                if (ok[i]) { mn = fmin(mn, tt[i]); mx = fmax(mx, tt[i]); }
+            tlo = wave_min(mn);
+            thi = wave_max(mx);
+        }
     }
     if (!(lo[0] <= hi[0])) return;  // no point of this wave takes part
-    const TRAJAM_CONST_AS T *aos = (const TRAJAM_CONST_AS T *)aos_g;
     const int lane = threadIdx.x & 63;
     const T tabs = fmax(fabs(tlo), fabs(thi));
     for (int base = 0; base < n_o; base += 64) {
@@ -549,8 +688,8 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, const T *ol, 
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) {
                 cu[ax] = readlane_t<T>(k.c[ax], u);
-                if (DYN) wu[ax] = readlane_t<T>(k.w[ax], u);
-                if (!SPH) iu[ax] = readlane_t<T>(k.is[ax], u);
+                wu[ax] = DYN ? readlane_t<T>(k.w[ax], u) : T(0);
+                iu[ax] = SPH ? T(0) : readlane_t<T>(k.is[ax], u);
             }
             const T nu = SPH ? readlane_t<T>(k.nr2, u) : T(0);
 #pragma unroll
@@ -574,9 +713,12 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, const T *ol, 
                         acc = fma(uu, uu, acc);
                     }
                 }
-                if (acc < T(0))
-                    obstacle_inside<T, D, SPH, DYN>(aos + (size_t)(base + u) * kObstacleRecord, p[i], tt[i], R[i],
-                                                    r2, rmax);
+                if (acc < T(0)) {
+                    // inside: the residual from the chunk's registers (no record reload)
+                    const T rad = SPH ? readlane_t<T>(k.r, u) : T(0);
+                    const T sp = SPH ? T(0) : readlane_t<T>(k.s[D == 2 ? 0 : 2], u);
+                    obstacle_residual_at<T, D, SPH>(dx, rad, iu, sp, R[i], r2, rmax);
+                }
             }
         }
     }
@@ -765,6 +907,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
     const ObsChunk<T, D> oc0 = load_obs_chunk<T, D>(a.obs, a.n_o, 0, threadIdx.x & 63);
     T res_first = T(0), res_last = T(0);
     bool nonfinite = false;
+    const bool res_lane = live && lt == (wpt - 1) * 64;   // lane 0 of the sample's last wave
     int cur = 0;
     for (int k = 0; k < a.iters; ++k) {
         const T *xs = xbuf + (cur * a.tb + ls) * S;
@@ -803,19 +946,36 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
             if (a.use_a) bound_residual<T, D>(acc, a.amax, ra, r2, rmax);
         }
         // ---- F^T r: each lane's rows times its residuals, reduced over the wave
-        bool nz = false;
+        // each residual group (obstacle, velocity, acceleration) enters only when some
+        // lane of the wave has it non-zero; a skipped group adds exact zeros
+        bool nR = false, nV = false, nA = false;
 #pragma unroll
-        for (int ax = 0; ax < D; ++ax) nz = nz || R[ax] != T(0) || rv[ax] != T(0) || ra[ax] != T(0);
+        for (int ax = 0; ax < D; ++ax) {
+            nR = nR || R[ax] != T(0);
+            nV = nV || rv[ax] != T(0);
+            nA = nA || ra[ax] != T(0);
+        }
+        const bool aR = __any(nR), aV = __any(nV), aA = __any(nA);
         T *mypart = part + (ls * wpt + wave_in_s) * V;
-        if (__any(nz)) {
+        if (aR || aV || aA) {
             T c[V];
 #pragma unroll
             for (int i = 0; i < V; ++i) c[i] = T(0);
+            if (aA)
 #pragma unroll
-            for (int ax = 0; ax < D; ++ax)
+                for (int ax = 0; ax < D; ++ax)
 #pragma unroll
-                for (int m = 0; m < NVP; ++m)
-                    c[ax * NVP + m] = fma(phi0[m], R[ax], fma(phi1[m], rv[ax], phi2[m] * ra[ax]));
+                    for (int m = 0; m < NVP; ++m) c[ax * NVP + m] = phi2[m] * ra[ax];
+            if (aV)
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+                    for (int m = 0; m < NVP; ++m) c[ax * NVP + m] = fma(phi1[m], rv[ax], c[ax * NVP + m]);
+            if (aR)
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+                    for (int m = 0; m < NVP; ++m) c[ax * NVP + m] = fma(phi0[m], R[ax], c[ax * NVP + m]);
             const T s = reduce_scatter<T, V>(c, lane);
             if ((lane & ((64 >> LOGV) - 1)) == 0) mypart[lane >> (6 - LOGV)] = s;
         } else if (lane < V) {
@@ -827,23 +987,33 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
 
         // ---- step (c): multiplier (eq lag) and the QP right-hand side defect
         if (owner) {
+            // the partials of the sample's waves (at most 4) are read together
+            T pw[4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) pw[w] = w < wpt ? part[(ls * wpt + w) * V + lt] : T(0);
             T ftr = T(0);
-            for (int w = 0; w < wpt; ++w) ftr += part[(ls * wpt + w) * V + lt];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) ftr += pw[w];
             T gv = T(0);
             if (o_real) {
                 lam_o = fma(-a.rho, ftr, lam_o);
                 gv = o_free ? (xi_o - xb_o + lam_o - a.rho * ftr) : (bnd_o - xb_o);
             }
             gbuf[ls * S + lt] = gv;
-            if (lt == 0) {
-                T rs = T(0);
-                for (int w = 0; w < wpt; ++w) rs += r2p[ls * wpt + w];
-                rs = sqrt(rs);
-                if (a.res) a.res[(size_t)k * a.batch + sample] = rs;
-                if (k == 0) res_first = rs;
-                res_last = rs;
-                nonfinite = nonfinite || !isfinite(rs);
-            }
+        }
+        // the residual norm is the last wave's: off the owners' path to the QP
+        if (res_lane) {
+            T rw[4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) rw[w] = w < wpt ? r2p[ls * wpt + w] : T(0);
+            T rs = T(0);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) rs += rw[w];
+            rs = sqrt(rs);
+            if (a.res) a.res[(size_t)k * a.batch + sample] = rs;
+            if (k == 0) res_first = rs;
+            res_last = rs;
+            nonfinite = nonfinite || !isfinite(rs);
         }
         // ---- step (b): xb_free += W [g_free ; boundary defect]  (eq affine_trans)
         const int nxt = cur ^ 1;
@@ -927,12 +1097,15 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
         nonfinite = nonfinite || !isfinite(xb_o) || !isfinite(lam_o);
     }
     if (a.flags && a.iters > 0) {
-        // fold the per-lane non-finite bits of this sample into its first lane
+        // the residual lane's bits reach the sample's first lane through LDS
+        // (r2p is free after the loop's last barrier)
+        if (res_lane) r2p[ls * wpt] = T((nonfinite ? 1 : 0) + (res_last > res_first ? 2 : 0));
+        __syncthreads();
         const bool anyb = __any(nonfinite && owner);
         if (owner && lt == 0) {
-            uint32_t fl = 0;
+            const int rb = (int)r2p[ls * wpt];
+            uint32_t fl = (uint32_t)rb;
             if (anyb) fl |= 1u;
-            if (res_last > res_first) fl |= 2u;
             a.flags[sample] = fl;
         }
     }
@@ -1030,25 +1203,40 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
             if (a.use_a) bound_residual<T, D>(acc[i], a.amax, ra[i], r2, rmax);
         }
         // ---- F^T r over the wave
-        bool nz = false;
+        // residual groups enter only when some lane has them non-zero (exact zeros skipped)
+        bool nR = false, nV = false, nA = false;
 #pragma unroll
         for (int i = 0; i < TPL; ++i)
 #pragma unroll
-            for (int ax = 0; ax < D; ++ax)
-                nz = nz || R[i][ax] != T(0) || rv[i][ax] != T(0) || ra[i][ax] != T(0);
+            for (int ax = 0; ax < D; ++ax) {
+                nR = nR || R[i][ax] != T(0);
+                nV = nV || rv[i][ax] != T(0);
+                nA = nA || ra[i][ax] != T(0);
+            }
+        const bool aR = __any(nR), aV = __any(nV), aA = __any(nA);
         T ftr = T(0);
-        if (__any(nz)) {
+        if (aR || aV || aA) {
             T c[V];
 #pragma unroll
             for (int j = 0; j < V; ++j) c[j] = T(0);
 #pragma unroll
-            for (int i = 0; i < TPL; ++i)
+            for (int i = 0; i < TPL; ++i) {
+                if (aA)
 #pragma unroll
-                for (int ax = 0; ax < D; ++ax)
+                    for (int ax = 0; ax < D; ++ax)
 #pragma unroll
-                    for (int m = 0; m < NVP; ++m)
-                        c[ax * NVP + m] = fma(phi0[i][m], R[i][ax],
-                                              fma(phi1[i][m], rv[i][ax], fma(phi2[i][m], ra[i][ax], c[ax * NVP + m])));
+                        for (int m = 0; m < NVP; ++m) c[ax * NVP + m] = fma(phi2[i][m], ra[i][ax], c[ax * NVP + m]);
+                if (aV)
+#pragma unroll
+                    for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+                        for (int m = 0; m < NVP; ++m) c[ax * NVP + m] = fma(phi1[i][m], rv[i][ax], c[ax * NVP + m]);
+                if (aR)
+#pragma unroll
+                    for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+                        for (int m = 0; m < NVP; ++m) c[ax * NVP + m] = fma(phi0[i][m], R[i][ax], c[ax * NVP + m]);
+            }
             ftr = reduce_scatter<T, V>(c, lane);
         }
         const T r2w = wave_sum(r2);
