@@ -31,9 +31,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_VALU_OPS = 256 * 64 * 2.4e9  # lane-ops/s, one FMA = one op (no packed FP32)
 # HBM bytes per launch of the main kernel from FETCH_SIZE / WRITE_SIZE counter runs
-# scaled by a copy of known size (profiles/am_project_kernel_cfg2_fp32.md): 918 KiB
+# scaled by a copy of known size (profiles/am_project_kernel_cfg2_fp32.md): 958 KiB
 # read + 1,824 KiB written.  Re-measure whenever the kernel changes.
-TRAFFIC_BYTES_PER_LAUNCH = (918 + 1824) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = (958 + 1824) * 1024
 
 
 def algorithmic_ops_per_traj_iter(w) -> float:
@@ -130,17 +130,22 @@ def ttr_scene(w, solver, xi, obs, net, cap, stream, tol=1e-3, reps=20):
     iw = ws.iterations_to(np.concatenate([trp.cpu().numpy(), trw.cpu().numpy()]), tol)
     out["warm_iters"] = iw
     out["warm_fallbacks"] = int(((fl.cpu().numpy() & 4) != 0).sum())
-    if ic is not None:
+    # a start that never reaches tol within the cap is timed over the whole cap (a
+    # lower bound of its time to tol) and marked as not reached
+    out["cold_reached"], out["warm_reached"] = ic is not None, iw is not None
+    n_cold = ic if ic is not None else cap
+    n_warm = iw if iw is not None else cap
+    if n_cold > 0:
         def cold():
             xb.copy_(xi)
             lam.zero_()
-            solver.project(xi, w.boundary, obs, xb, lam, ic)
+            solver.project(xi, w.boundary, obs, xb, lam, n_cold)
         out["cold_ms_eager"] = _time(cold, reps, stream)
         g = _graph(cold)
         out["cold_ms"] = _time(g.replay, reps, stream)
         del g
-    if iw is not None:
-        rest = max(iw - ws.K0, 0)
+    if n_warm > 0:
+        rest = max(n_warm - ws.K0, 0)
 
         def warm():
             b0, l0, _, _ = ctx.run(xi, w.boundary, obs)
@@ -155,7 +160,8 @@ def ttr_scene(w, solver, xi, obs, net, cap, stream, tol=1e-3, reps=20):
 def time_to_residual(args, w, solver, xi, obs, stream, tol=1e-3, net=None, info=None):
     """The learned warm start against the cold start: on the benchmark scene, and summed
     over 8 held-out scenes of the same family (scene seeds disjoint from the training
-    ones); a scene whose median never reaches tol within the cap counts the cap."""
+    ones); a scene whose median never reaches tol within the cap counts the cap, in
+    iterations and in time."""
     import torch
     from paper_2408_10731_amd import trajam as tj
     from paper_2408_10731_amd import warmstart as ws
@@ -173,12 +179,12 @@ def time_to_residual(args, w, solver, xi, obs, stream, tol=1e-3, net=None, info=
         x_, o_ = tj.device_workload(ws_, torch.float32)
         r = ttr_scene(ws_, s, x_, o_, net, cap, stream, tol, reps=10)
         s.close()
-        per.append({"seed": seed, **{k: r.get(k) for k in ("cold_iters", "warm_iters",
-                                                           "cold_ms", "warm_ms")}})
+        per.append({"seed": seed, **{k: r.get(k) for k in ("cold_iters", "warm_iters", "cold_ms",
+                                                           "warm_ms", "cold_reached", "warm_reached")}})
         tot["cold_iters"] += r["cold_iters"] if r["cold_iters"] is not None else cap
         tot["warm_iters"] += r["warm_iters"] if r["warm_iters"] is not None else cap
-        tot["cold_ms"] += r.get("cold_ms", float("nan"))
-        tot["warm_ms"] += r.get("warm_ms", float("nan"))
+        tot["cold_ms"] += r.get("cold_ms", 0.0)
+        tot["warm_ms"] += r.get("warm_ms", 0.0)
     out["held_out"] = {"scenes": per, "total": tot}
     return out
 
@@ -330,6 +336,8 @@ def main():
     ap.add_argument("--ragged-problems", type=int, default=256, help="0 skips the ragged set")
     ap.add_argument("--ragged-steps", type=int, default=3)
     ap.add_argument("--cem-calls", type=int, default=5, help="0 skips the sampling loop")
+    ap.add_argument("--cem-only", action="store_true",
+                    help="run only the sampling-loop leg and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB buffer 3 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -342,6 +350,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 3}), flush=True)
+        return
+    if args.cem_only:
+        print(json.dumps(cem_bench(args)), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "

@@ -630,17 +630,45 @@ __device__ __forceinline__ ObsChunk<T, D> lds_obs_chunk(const T *ol, int n_o, in
     return k;
 }
 
+// Candidate masks of up to kCullCacheChunks obstacle chunks, kept across iterations.
+// They were built against the wave's box grown by delta when every point of the wave
+// was at pref; while no point has moved more than delta from there (max norm) each
+// point still lies in that grown box, so the masks still hold every obstacle that can
+// contain one of the wave's points, and the box reduction and chunk tests are skipped.
+constexpr int kCullCacheChunks = 4;
+
+template <typename T, int D, int NPT>
+struct CullCache {
+    bool valid = false;
+    T delta = T(0);
+    unsigned long long m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+    T pref[NPT][D] = {};
+};
+
 // Chunks of 64 obstacles (lane j: obstacle base + j) come from the LDS stage `ol`
 // (STAGED) or from the packed records, the first one from `first`, loaded once per
 // launch by the caller.
-template <typename T, int D, bool SPH, bool DYN, int NPT, bool STAGED>
+template <typename T, int D, bool SPH, bool DYN, int NPT, bool STAGED, bool CACHE>
 __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, const T *ol, int n_o, const ObsChunk<T, D> first,
                                                    const T (&tt)[NPT], const T (&p)[NPT][D], const bool (&ok)[NPT],
-                                                   T (&R)[NPT][D], T &r2, T &rmax)
+                                                   T (&R)[NPT][D], T &r2, T &rmax, CullCache<T, D, NPT> &cc)
 {
     const T big = T(1e30);
+    const bool cached = CACHE && n_o <= 64 * kCullCacheChunks;
+    bool rebuild = true;
+    if (cached && cc.valid) {
+        bool moved = false;
+#pragma unroll
+        for (int i = 0; i < NPT; ++i)
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax)
+                moved = moved || (ok[i] && !(fabs(p[i][ax] - cc.pref[i][ax]) <= cc.delta));
+        rebuild = __any(moved);
+    }
     T lo[D], hi[D], tlo = T(0), thi = T(0);
-    if constexpr (sizeof(T) == sizeof(float)) {
+    if (!rebuild) {
+        // masks from the cache below
+    } else if constexpr (sizeof(T) == sizeof(float)) {
         wave_box<D, DYN, NPT>(tt, p, ok, lo, hi, tlo, thi);
     } else {
 #pragma unroll
@@ -661,26 +689,60 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, const T *ol, 
             thi = wave_max(mx);
         }
     }
-    if (!(lo[0] <= hi[0])) return;  // no point of this wave takes part
+    if (rebuild) {
+        if (!(lo[0] <= hi[0])) {  // no point of this wave takes part
+            if (cached) cc.valid = false;
+            return;
+        }
+        if (cached) {
+            T ext = T(0);
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) ext = fmax(ext, hi[ax] - lo[ax]);
+            const T dl = T(0.015) * ext + T(1e-3);
+            const T grow = fma(dl, T(1.0001), T(1e-5));  // also covers the rounding of p - pref
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) {
+                lo[ax] -= grow;
+                hi[ax] += grow;
+            }
+            cc.delta = dl;
+#pragma unroll
+            for (int i = 0; i < NPT; ++i)
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax) cc.pref[i][ax] = p[i][ax];
+            cc.valid = true;
+        }
+    }
     const int lane = threadIdx.x & 63;
     const T tabs = fmax(fabs(tlo), fabs(thi));
-    for (int base = 0; base < n_o; base += 64) {
+    for (int base = 0, ci = 0; base < n_o; base += 64, ++ci) {
         const ObsChunk<T, D> k = STAGED ? lds_obs_chunk<T, D, SPH>(ol, n_o, base, lane)
                                         : (base == 0 ? first : load_obs_chunk<T, D>(aos_g, n_o, base, lane));
-        bool cand = base + lane < n_o;
+        unsigned long long mask;
+        if (rebuild) {
+            bool cand = base + lane < n_o;
 #pragma unroll
-        for (int ax = 0; ax < D; ++ax) {
-            const T e = SPH ? k.r : k.s[ax];
-            T cmin = k.c[ax], cmax = k.c[ax], m = fma(e, T(1.0001), T(1e-4)) + T(1e-5) * fabs(k.c[ax]);
-            if (DYN) {
-                const T c1 = fma(-k.w[ax], tlo, k.c[ax]), c2 = fma(-k.w[ax], thi, k.c[ax]);
-                cmin = fmin(c1, c2);
-                cmax = fmax(c1, c2);
-                m += T(1e-5) * (fabs(k.w[ax]) * tabs + fabs(cmin) + fabs(cmax));
+            for (int ax = 0; ax < D; ++ax) {
+                const T e = SPH ? k.r : k.s[ax];
+                T cmin = k.c[ax], cmax = k.c[ax], m = fma(e, T(1.0001), T(1e-4)) + T(1e-5) * fabs(k.c[ax]);
+                if (DYN) {
+                    const T c1 = fma(-k.w[ax], tlo, k.c[ax]), c2 = fma(-k.w[ax], thi, k.c[ax]);
+                    cmin = fmin(c1, c2);
+                    cmax = fmax(c1, c2);
+                    m += T(1e-5) * (fabs(k.w[ax]) * tabs + fabs(cmin) + fabs(cmax));
+                }
+                cand = cand && (cmin - m <= hi[ax]) && (cmax + m >= lo[ax]);
             }
-            cand = cand && (cmin - m <= hi[ax]) && (cmax + m >= lo[ax]);
+            mask = __ballot(cand);
+            if (cached) {
+                if (ci == 0) cc.m0 = mask;
+                else if (ci == 1) cc.m1 = mask;
+                else if (ci == 2) cc.m2 = mask;
+                else cc.m3 = mask;
+            }
+        } else {
+            mask = ci == 0 ? cc.m0 : ci == 1 ? cc.m1 : ci == 2 ? cc.m2 : cc.m3;
         }
-        unsigned long long mask = __ballot(cand);
         while (mask) {
             const int u = __builtin_ctzll(mask);
             mask &= mask - 1;
@@ -728,14 +790,17 @@ template <typename T, int D, int NPT>
 __device__ __forceinline__ void obstacle_residuals_culled(const T *aos_g, int n_o, int sphere, int dynamic,
                                                           const ObsChunk<T, D> first, const T (&tt)[NPT],
                                                           const T (&p)[NPT][D], const bool (&ok)[NPT],
-                                                          T (&R)[NPT][D], T &r2, T &rmax)
+                                                          T (&R)[NPT][D], T &r2, T &rmax, CullCache<T, D, NPT> &cc)
 {
+    // the cache's reference positions cost NPT * D registers a lane: FP64 launches with
+    // more than two time samples a lane rebuild the masks every iteration instead
+    constexpr bool C = sizeof(T) == sizeof(float) || NPT <= 2;
     if (sphere) {
-        if (dynamic) obstacle_cull_loop<T, D, true, true, NPT, false>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax);
-        else obstacle_cull_loop<T, D, true, false, NPT, false>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax);
+        if (dynamic) obstacle_cull_loop<T, D, true, true, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
+        else obstacle_cull_loop<T, D, true, false, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
     } else {
-        if (dynamic) obstacle_cull_loop<T, D, false, true, NPT, false>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax);
-        else obstacle_cull_loop<T, D, false, false, NPT, false>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax);
+        if (dynamic) obstacle_cull_loop<T, D, false, true, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
+        else obstacle_cull_loop<T, D, false, false, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
     }
 }
 
@@ -746,12 +811,13 @@ __device__ __forceinline__ void obstacle_residuals_staged(const T *ol, const T *
                                                           const bool (&ok)[NPT], T (&R)[NPT][D], T &r2, T &rmax)
 {
     const ObsChunk<T, D> none{};
+    CullCache<T, D, NPT> nc;  // unused: the staged loop rebuilds its masks every call
     if (sphere) {
-        if (dynamic) obstacle_cull_loop<T, D, true, true, NPT, true>(aos_g, ol, n_o, none, tt, p, ok, R, r2, rmax);
-        else obstacle_cull_loop<T, D, true, false, NPT, true>(aos_g, ol, n_o, none, tt, p, ok, R, r2, rmax);
+        if (dynamic) obstacle_cull_loop<T, D, true, true, NPT, true, false>(aos_g, ol, n_o, none, tt, p, ok, R, r2, rmax, nc);
+        else obstacle_cull_loop<T, D, true, false, NPT, true, false>(aos_g, ol, n_o, none, tt, p, ok, R, r2, rmax, nc);
     } else {
-        if (dynamic) obstacle_cull_loop<T, D, false, true, NPT, true>(aos_g, ol, n_o, none, tt, p, ok, R, r2, rmax);
-        else obstacle_cull_loop<T, D, false, false, NPT, true>(aos_g, ol, n_o, none, tt, p, ok, R, r2, rmax);
+        if (dynamic) obstacle_cull_loop<T, D, false, true, NPT, true, false>(aos_g, ol, n_o, none, tt, p, ok, R, r2, rmax, nc);
+        else obstacle_cull_loop<T, D, false, false, NPT, true, false>(aos_g, ol, n_o, none, tt, p, ok, R, r2, rmax, nc);
     }
 }
 
@@ -844,11 +910,15 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
     const int lane = tid & 63;
     const int wpt = a.tpad >> 6;               // waves per sample
     const int ls = tid / a.tpad;               // local sample
-    const int lt = tid - ls * a.tpad;          // time sample (or output index)
+    const int lt = tid - ls * a.tpad;          // lane within the sample (output index)
     const int wave_in_s = lt >> 6;
     const int sample = blockIdx.x * a.tb + ls;
     const bool live = sample < a.batch;
-    const bool valid = live && lt < a.n_p;
+    // the time samples are split evenly over the sample's waves (equal boxes and
+    // obstacle candidates per wave): wave w holds samples w * per_w + lane
+    const int per_w = (a.n_p + wpt - 1) / wpt;
+    const int ti = wave_in_s * per_w + lane;   // time sample of this lane
+    const bool valid = live && lane < per_w && ti < a.n_p;
     const int nf = a.nv - 4;
 
     T *xbuf = smem + L::xbuf(a.tb);
@@ -878,11 +948,11 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
     T phi0[NVP], phi1[NVP], phi2[NVP];
 #pragma unroll
     for (int m = 0; m < NVP; ++m) {
-        phi0[m] = valid ? a.phi[(0 * a.n_p + lt) * NVP + m] : T(0);
-        phi1[m] = valid ? a.phi[(1 * a.n_p + lt) * NVP + m] : T(0);
-        phi2[m] = valid ? a.phi[(2 * a.n_p + lt) * NVP + m] : T(0);
+        phi0[m] = valid ? a.phi[(0 * a.n_p + ti) * NVP + m] : T(0);
+        phi1[m] = valid ? a.phi[(1 * a.n_p + ti) * NVP + m] : T(0);
+        phi2[m] = valid ? a.phi[(2 * a.n_p + ti) * NVP + m] : T(0);
     }
-    const T tt = T(lt) * a.dt;
+    const T tt = T(ti) * a.dt;
 
     // Output lanes: lane lt < S owns coefficient (axis, m) of its sample.
     const bool owner = live && lt < S;
@@ -905,6 +975,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
     __syncthreads();
 
     const ObsChunk<T, D> oc0 = load_obs_chunk<T, D>(a.obs, a.n_o, 0, threadIdx.x & 63);
+    CullCache<T, D, 1> ccache;     // obstacle candidates kept across iterations
     T res_first = T(0), res_last = T(0);
     bool nonfinite = false;
     const bool res_lane = live && lt == (wpt - 1) * 64;   // lane 0 of the sample's last wave
@@ -937,7 +1008,8 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
                 p1[0][ax] = valid ? p[ax] : T(-1e30);
                 R1[0][ax] = T(0);
             }
-            obstacle_residuals_culled<T, D, 1>(a.obs, a.n_o, a.sphere, a.dynamic, oc0, tt1, p1, ok1, R1, r2, rmax);
+            obstacle_residuals_culled<T, D, 1>(a.obs, a.n_o, a.sphere, a.dynamic, oc0, tt1, p1, ok1, R1, r2, rmax,
+                                               ccache);
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) R[ax] = R1[0][ax];
         }
@@ -1163,6 +1235,7 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
     wave_lds_sync();
 
     const ObsChunk<T, D> oc0 = load_obs_chunk<T, D>(a.obs, a.n_o, 0, lane);
+    CullCache<T, D, TPL> ccache;   // obstacle candidates kept across iterations
     T res_first = T(0), res_last = T(0);
     bool nonfinite = false;
     for (int k = 0; k < a.iters; ++k) {
@@ -1196,7 +1269,8 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
         for (int i = 0; i < TPL; ++i)
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) { R[i][ax] = T(0); rv[i][ax] = T(0); ra[i][ax] = T(0); }
-        obstacle_residuals_culled<T, D, TPL>(a.obs, a.n_o, a.sphere, a.dynamic, oc0, tt, p, valid, R, r2, rmax);
+        obstacle_residuals_culled<T, D, TPL>(a.obs, a.n_o, a.sphere, a.dynamic, oc0, tt, p, valid, R, r2, rmax,
+                                             ccache);
 #pragma unroll
         for (int i = 0; i < TPL; ++i) {
             if (a.use_v) bound_residual<T, D>(v[i], a.vmax, rv[i], r2, rmax);
