@@ -135,13 +135,28 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const fl
 }
 
 // db[n] = sum_b d[b][n] (fixed summation order)
-__global__ void colsum_kernel(int rows, int cols, const float *__restrict__ d, float *__restrict__ out)
+// out[n] = sum_b d[b][n]: 64 columns per workgroup and 16 row slices of one wave each
+// (coalesced 256-byte row segments, loads unrolled); the slices' partials are added
+// in slice order, so the result does not depend on timing.
+__global__ __launch_bounds__(1024) void colsum_kernel(int rows, int cols, const float *__restrict__ d,
+                                                      float *__restrict__ out)
 {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= cols) return;
+    __shared__ float part[16][64];
+    const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int sl = threadIdx.x >> 6;
     float s = 0.f;
-    for (int b = 0; b < rows; ++b) s += d[(long)b * cols + n];
-    out[n] = s;
+    if (col < cols) {
+#pragma unroll 8
+        for (int b = sl; b < rows; b += 16) s += d[(long)b * cols + col];
+    }
+    part[sl][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (sl == 0 && col < cols) {
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) t += part[k][threadIdx.x];
+        out[col] = t;
+    }
 }
 
 // dy = 2 (y - t) / count; loss = mean (y - t)^2 (one workgroup, fixed order)
@@ -359,7 +374,7 @@ hipError_t launch_gemm(bool bf16, int M, int N, int K, const float *A, long sam,
 
 hipError_t launch_colsum(int rows, int cols, const float *d, float *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(colsum_kernel, dim3((cols + 255) / 256), dim3(256), 0, st, rows, cols, d, out);
+    hipLaunchKernelGGL(colsum_kernel, dim3((cols + 63) / 64), dim3(1024), 0, st, rows, cols, d, out);
     return hipGetLastError();
 }
 
