@@ -104,6 +104,9 @@ def test_fp64_config1_full_run():
     (3, 15, 150, 6, 5, 0.3, True),    # nvp 16, three waves, moving ellipsoids
     (3, 4, 200, 1, 4, 0.0, False),    # spheres, four waves
     (2, 3, 30, 9, 2, 0.0, False),     # no free coefficient (degree 3)
+    (2, 10, 100, 150, 6, 0.5, False), # three obstacle chunks, candidate masks kept across iterations
+    (3, 9, 80, 100, 4, 0.4, True),    # two chunks of moving ellipsoids
+    (2, 8, 70, 300, 4, 0.0, False),   # five chunks: past the masks kept, rebuilt every iteration
 ])
 def test_fp64_shapes_and_obstacle_models(dims, degree, n_steps, n_obs, batch, speed, per_axis):
     w = wl.tiny(dims=dims, batch=batch, n_obs=n_obs, degree=degree, n_steps=n_steps,
