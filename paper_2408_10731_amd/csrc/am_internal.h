@@ -87,6 +87,10 @@ hipError_t launch_agents_f32(int dims, int nvp, const AmArgs<float> &a, hipStrea
 hipError_t launch_agents_residual_f64(int dims, int nvp, const AmArgs<double> &a, hipStream_t st);
 hipError_t launch_agents_residual_f32(int dims, int nvp, const AmArgs<float> &a, hipStream_t st);
 hipError_t launch_residual_f32(int dims, int nvp, const AmArgs<float> &a, hipStream_t st);
+hipError_t launch_polar_f64(int dims, int nvp, const AmArgs<double> &a, void *al, void *be, void *dd, void *kin,
+                            hipStream_t st);
+hipError_t launch_polar_f32(int dims, int nvp, const AmArgs<float> &a, void *al, void *be, void *dd, void *kin,
+                            hipStream_t st);
 hipError_t launch_pack_obstacles_f64(int dims, int n_o, const double *c, const double *w,
                                      const double *s, double *out, double *soa, hipStream_t st);
 hipError_t launch_pack_obstacles_f32(int dims, int n_o, const float *c, const float *w,

@@ -1848,6 +1848,90 @@ __global__ __launch_bounds__(kMaxThreads) void am_residual_kernel(AmArgs<T> a)
     }
 }
 
+// Materialised polar variables at given coefficients: one workgroup per sample maps
+// its coefficients to p, v, a at every time step (LDS), then writes, per (obstacle,
+// time step), alpha = atan2(u_y, u_x), beta = atan2(|u_xy|, u_z) (pi/2 in 2D) and
+// d = max(1, |u|) of u = (p(t) - c(t)) ./ s (eqs comp_alpha, comp_beta, comp_d, with
+// the angles taken in semi-axis-scaled coordinates), and the kinematic blocks'
+// (alpha, beta, min(1, |v| / bound)) (eqs alpha_v, compute_dv, alpha_a, compute_da).
+// Rows are padded to tpad time steps; padding entries and disabled blocks are 0.
+template <typename T, int D, int NVP>
+__global__ __launch_bounds__(256) void am_polar_kernel(AmArgs<T> a, T *__restrict__ oal, T *__restrict__ obe,
+                                                       T *__restrict__ odd, T *__restrict__ kin)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *pos = reinterpret_cast<T *>(smem_raw);   // [3][D][tpad]: p, v, a
+    const int sample = blockIdx.x;
+    const int tp = a.tpad;
+    const T half_pi = T(1.5707963267948966);
+    const T *x = a.xb + (size_t)sample * D * a.nv;
+    for (int t = threadIdx.x; t < tp; t += blockDim.x) {
+        T q[3][D];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) q[k][ax] = T(0);
+        if (t < a.n_p) {
+            for (int m = 0; m < a.nv; ++m) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const T f = a.phi[((size_t)k * a.n_p + t) * NVP + m];
+#pragma unroll
+                    for (int ax = 0; ax < D; ++ax) q[k][ax] = fma(f, x[ax * a.nv + m], q[k][ax]);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) pos[(k * D + ax) * tp + t] = q[k][ax];
+        if (kin) {
+            T *kr = kin + (size_t)sample * 6 * tp;
+#pragma unroll
+            for (int k = 1; k < 3; ++k) {
+                const T bound = k == 1 ? a.vmax : a.amax;
+                T al = T(0), be = T(0), dv = T(0);
+                if (t < a.n_p && bound > T(0)) {
+                    T nn = T(0);
+#pragma unroll
+                    for (int ax = 0; ax < D; ++ax) nn = fma(q[k][ax], q[k][ax], nn);
+                    al = atan2(q[k][1], q[k][0]);
+                    be = D == 3 ? atan2(hypot(q[k][0], q[k][1]), q[k][D - 1]) : half_pi;
+                    dv = fmin(sqrt(nn) / bound, T(1));
+                }
+                kr[(3 * (k - 1) + 0) * tp + t] = al;
+                kr[(3 * (k - 1) + 1) * tp + t] = be;
+                kr[(3 * (k - 1) + 2) * tp + t] = dv;
+            }
+        }
+    }
+    __syncthreads();
+    if (!oal && !obe && !odd) return;
+    const size_t row0 = (size_t)sample * a.n_o * tp;
+    for (int idx = threadIdx.x; idx < a.n_o * tp; idx += blockDim.x) {
+        const int j = idx / tp, t = idx - (idx / tp) * tp;
+        T al = T(0), be = T(0), dd = T(0);
+        if (t < a.n_p) {
+            const T *o = a.obs + (size_t)j * kObstacleRecord;
+            const T tt = T(t) * a.dt;
+            T u[D], nn = T(0);
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) {
+                // c(t) = c + velocity t; the record holds -velocity
+                const T xt = fma(o[kOW + ax], tt, pos[ax * tp + t] - o[kOC + ax]);
+                u[ax] = xt / o[kOS + ax];
+                nn = fma(u[ax], u[ax], nn);
+            }
+            al = atan2(u[1], u[0]);
+            be = D == 3 ? atan2(hypot(u[0], u[1]), u[D - 1]) : half_pi;
+            dd = fmax(sqrt(nn), T(1));
+        }
+        if (oal) oal[row0 + idx] = al;
+        if (obe) obe[row0 + idx] = be;
+        if (odd) odd[row0 + idx] = dd;
+    }
+}
+
 // Packs the caller's obstacle arrays.  (1) One 16-slot record per obstacle:
 // centre[3], -velocity[3], 1/semi-axes[3], semi-axes[3], -radius^2, radius (radius =
 // first semi-axis, used by the sphere model).  (2) The inside-test fields in groups of
@@ -1949,6 +2033,15 @@ hipError_t launch_residual_t(const AmArgs<T> &a, hipStream_t st)
     const int blocks = (a.batch + a.tb - 1) / a.tb;
     if (a.tb < 1 || threads > kMaxThreads) return hipErrorInvalidValue;
     hipLaunchKernelGGL((am_residual_kernel<T, D, NVP>), dim3(blocks), dim3(threads), lds, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int D, int NVP>
+hipError_t launch_polar_t(const AmArgs<T> &a, void *al, void *be, void *dd, void *kin, hipStream_t st)
+{
+    const size_t lds = sizeof(T) * 3 * D * (size_t)a.tpad;
+    hipLaunchKernelGGL((am_polar_kernel<T, D, NVP>), dim3(a.batch), dim3(256), lds, st, a, (T *)al, (T *)be,
+                       (T *)dd, (T *)kin);
     return hipGetLastError();
 }
 
@@ -2065,6 +2158,18 @@ hipError_t launch_residual_f64(int dims, int nvp, const AmArgs<double> &a, hipSt
 hipError_t launch_residual_f32(int dims, int nvp, const AmArgs<float> &a, hipStream_t st)
 {
     TRAJAM_DISPATCH(launch_residual_t, float, dims, nvp, a, st);
+}
+
+hipError_t launch_polar_f64(int dims, int nvp, const AmArgs<double> &a, void *al, void *be, void *dd, void *kin,
+                            hipStream_t st)
+{
+    TRAJAM_DISPATCH(launch_polar_t, double, dims, nvp, a, al, be, dd, kin, st);
+}
+
+hipError_t launch_polar_f32(int dims, int nvp, const AmArgs<float> &a, void *al, void *be, void *dd, void *kin,
+                            hipStream_t st)
+{
+    TRAJAM_DISPATCH(launch_polar_t, float, dims, nvp, a, al, be, dd, kin, st);
 }
 
 template <typename T>

@@ -730,6 +730,40 @@ extern "C" trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const
     return TRAJAM_OK;
 }
 
+extern "C" trajam_status trajam_polar(trajam_solver *s, int32_t batch, const void *xi_bar, const void *obs_centre,
+                                      const void *obs_vel, const void *obs_axes, void *obs_alpha, void *obs_beta,
+                                      void *obs_d, void *kin, void *stream)
+{
+    if (!s) return TRAJAM_ERR_INVALID;
+    s->err.clear();
+    if (s->prob.n_agents != 1) return fail(s, TRAJAM_ERR_UNSUPPORTED, "trajam_polar is single-robot");
+    if (batch < 0) return fail(s, TRAJAM_ERR_INVALID, "batch must be >= 0");
+    if (batch > s->prob.max_batch) return fail(s, TRAJAM_ERR_CAPACITY, "batch > max_batch");
+    if (batch == 0) return TRAJAM_OK;
+    if (!xi_bar) return fail(s, TRAJAM_ERR_INVALID, "xi_bar must not be NULL");
+    hipStream_t st = (hipStream_t)stream;
+    trajam_status ps = pack(s, obs_centre, obs_vel, obs_axes, st);
+    if (ps != TRAJAM_OK) return ps;
+    const trajam_problem &p = s->prob;
+    if (p.n_obstacles == 0) obs_alpha = obs_beta = obs_d = nullptr;
+    hipError_t e;
+    if (p.precision == TRAJAM_FP64) {
+        AmArgs<double> a;
+        fill_args(s, a, batch, 0);
+        a.dynamic = s->dynamic;
+        a.xb = (double *)xi_bar;
+        e = trajam::launch_polar_f64(p.dims, s->nvp, a, obs_alpha, obs_beta, obs_d, kin, st);
+    } else {
+        AmArgs<float> a;
+        fill_args(s, a, batch, 0);
+        a.dynamic = s->dynamic;
+        a.xb = (float *)xi_bar;
+        e = trajam::launch_polar_f32(p.dims, s->nvp, a, obs_alpha, obs_beta, obs_d, kin, st);
+    }
+    if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("polar launch: ") + hipGetErrorString(e));
+    return TRAJAM_OK;
+}
+
 // ---- sampling loop ------------------------------------------------------------
 
 extern "C" trajam_status trajam_cem_sample(trajam_solver *s, int32_t n, const void *mu, const void *chol,

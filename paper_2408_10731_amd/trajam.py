@@ -47,7 +47,7 @@ EXPORTS = [
     "trajam_cem_select", "trajam_cem_update", "trajam_mlp_param_count", "trajam_mlp_forward",
     "trajam_mlp_backward", "trajam_mlp_infer", "trajam_mlp_pack_infer", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
     "trajam_warm_apply", "trajam_warm_fallback", "trajam_set_obstacles", "trajam_autotune",
-    "trajam_ragged_plan_create", "trajam_ragged_launch", "trajam_ragged_plan_destroy",
+    "trajam_ragged_plan_create", "trajam_ragged_launch", "trajam_ragged_plan_destroy", "trajam_polar",
     "trajam_status_string", "trajam_last_error",
 ]
 
@@ -127,6 +127,8 @@ def load():
     L.trajam_project.restype = ctypes.c_int
     L.trajam_residuals.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
     L.trajam_residuals.restype = ctypes.c_int
+    L.trajam_polar.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.trajam_polar.restype = ctypes.c_int
     L.trajam_fixed_matrices.argtypes = [ctypes.POINTER(Problem), dp, dp, dp, dp, dp]
     L.trajam_fixed_matrices.restype = ctypes.c_int
     L.trajam_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
@@ -226,6 +228,12 @@ def trajam_residuals(handle, batch, xi_bar, obs_centre, obs_vel, obs_axes, res_l
                      stream) -> None:
     _check(load().trajam_residuals(handle, int(batch), xi_bar, obs_centre, obs_vel, obs_axes,
                                    res_l2, res_max, stream), handle)
+
+
+def trajam_polar(handle, batch, xi_bar, obs_centre, obs_vel, obs_axes, obs_alpha, obs_beta, obs_d, kin,
+                 stream) -> None:
+    _check(load().trajam_polar(handle, int(batch), xi_bar, obs_centre, obs_vel, obs_axes, obs_alpha,
+                               obs_beta, obs_d, kin, stream), handle)
 
 
 def trajam_fixed_matrices(problem: Problem):
@@ -445,6 +453,28 @@ class Solver:
         trajam_residuals(self.handle, B, self._t(xi_bar, (B,) + self.sample_shape, "xi_bar"),
                          c, v, a, self._t(res_l2, (B,), "res_l2"),
                          None if res_max is None else self._t(res_max, (B,), "res_max"), st)
+
+    def polar(self, xi_bar, obs, kinematic=True, stream=None):
+        """Polar variables of step (a) at xi_bar: (alpha, beta, d) tensors [B, n_o, n_pad]
+        (None without obstacles) and, with kinematic, [B, 6, n_pad] (alpha_v, beta_v,
+        d_v, alpha_a, beta_a, d_a); n_pad = n_steps rounded up to 64."""
+        import torch
+        if self.n_agents != 1:
+            raise ValueError("polar variables are single-robot")
+        B = xi_bar.shape[0]
+        n_pad = (self.problem.n_steps + 63) // 64 * 64
+        n_o = self.problem.n_obstacles
+        c, v, a = self.obstacles(*(obs or ()))
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        kw = dict(dtype=self.dtype, device=xi_bar.device)
+        al = be = d = None
+        if n_o:
+            al, be, d = (torch.empty((B, n_o, n_pad), **kw) for _ in range(3))
+        kin = torch.empty((B, 6, n_pad), **kw) if kinematic else None
+        ptr = lambda t: None if t is None else t.data_ptr()
+        trajam_polar(self.handle, B, self._t(xi_bar, (B,) + self.sample_shape, "xi_bar"), c, v, a,
+                     ptr(al), ptr(be), ptr(d), ptr(kin), st)
+        return al, be, d, kin
 
     def set_launch(self, kernel: int, samples_per_workgroup: int):
         trajam_set_launch(self.handle, kernel, samples_per_workgroup)

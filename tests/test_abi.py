@@ -78,6 +78,8 @@ def test_null_handles_are_rejected():
                             None) == tj.TRAJAM_ERR_INVALID
     assert L.trajam_residuals(None, 1, None, None, None, None, None, None, None) == \
         tj.TRAJAM_ERR_INVALID
+    assert L.trajam_polar(None, 1, None, None, None, None, None, None, None, None, None) == \
+        tj.TRAJAM_ERR_INVALID
     assert L.trajam_init(None, None) == tj.TRAJAM_ERR_INVALID
     L.trajam_destroy(None)
     assert L.trajam_set_launch(None, 0, 1) == tj.TRAJAM_ERR_INVALID
