@@ -179,6 +179,19 @@ trajam_status trajam_residuals(trajam_solver *s, int32_t batch, const void *xi_b
 trajam_status trajam_fixed_matrices(const trajam_problem *p, double *P, double *Pd,
                                     double *Pdd, double *H, double *W);
 
+/* Contraction of the QP step in the problem's precision: the spectral radius of
+ * I - W~ H_ff, where W~ is the free-coefficient operator as the device applies it
+ * (FP64: W_ff = H_ff^-1; FP32: W_ff rounded to float; BF16_REFINE: the bf16 hi + lo
+ * split of the float W_ff) and H_ff the free block of the QP Hessian (thesis ch. 6:
+ * the QP's fixed KKT matrix, eq over_3).  The delta-form step xb_f += W~ (q - H_ff
+ * xb_f) multiplies its error by I - W~ H_ff, so reduced precision is usable only
+ * when this is well below 1; for joint problems the larger of the mean and the
+ * deviation operators is returned.  Estimated by ||E^256||_F^(1/256) (at most a factor
+ * n_f^(1/512) above the radius).  trajam_init fails with NUMERIC when it is >= 0.5.
+ * Host only: no device work, no handle.  Errors: INVALID (NULL rho or problem),
+ * UNSUPPORTED, NUMERIC (as trajam_init). */
+trajam_status trajam_qp_contraction(const trajam_problem *p, double *rho);
+
 /* Kernel variants of trajam_project.  Both run every iteration of a call in one
  * launch and compute the same arithmetic per sample; they differ in how a sample's
  * time samples map to lanes. */

@@ -64,6 +64,7 @@ struct trajam_solver {
     void *d_Hff = nullptr;   // BF16_REFINE: [16][16] float
     // multi-agent problems
     void *d_W2 = nullptr;    // [nvp][nvp] QP operator of H + n_agents rho P^T P
+    double qp_rho = 0.0;     // contraction of the QP step in the solver's precision
     void *d_xiBag = nullptr; // [n_agents][D][4] boundary coefficients per agent
     std::vector<double> bnd_cache;  // boundary rows the device copy was built from
     std::string err;
@@ -300,6 +301,100 @@ float bf16_value(uint16_t b)
     return x;
 }
 
+// trajam_init rejects a problem class whose QP step contracts its error by less than
+// this factor per iteration in the chosen precision.
+constexpr double kMaxQpContraction = 0.5;
+
+// Hessian seen by the agents' deviations from their mean in a joint problem:
+// H + N rho P^T P (the complete-graph Laplacian of the pair rows, eq A_f).
+std::vector<double> agents_hessian(const trajam_problem &p, const std::vector<double> &P,
+                                   const std::vector<double> &H)
+{
+    const int nv = p.degree + 1, np = p.n_steps;
+    std::vector<double> H2 = H;
+    for (int i = 0; i < nv; ++i)
+        for (int j = 0; j < nv; ++j) {
+            double g = 0.0;
+            for (int k = 0; k < np; ++k) g += P[(size_t)k * nv + i] * P[(size_t)k * nv + j];
+            H2[(size_t)i * nv + j] += p.n_agents * p.rho * g;
+        }
+    return H2;
+}
+
+// Spectral radius of E = I - W~ H_ff, W~ the free-coefficient operator as the device
+// applies it in `precision` (FP64: W_ff; FP32: W_ff rounded to float; BF16_REFINE: the
+// bf16 hi + lo split of the float W_ff).  The delta-form QP step xb_f += W~ (q - H_ff
+// xb_f) contracts its error by E, so this must stay well below 1.  Estimated by the
+// Gelfand formula ||E^k||_F^(1/k) at k = 256 (repeated squaring, renormalised each
+// step): an upper estimate within a factor n_f^(1/512) of the radius.
+double qp_contraction(const std::vector<double> &H, int n, const std::vector<double> &Wff, int precision)
+{
+    const int nv = n + 1, nf = nv - 4;
+    if (nf <= 0) return 0.0;
+    std::vector<double> Wt((size_t)nf * nf), E((size_t)nf * nf), T2((size_t)nf * nf);
+    for (size_t i = 0; i < Wt.size(); ++i) {
+        const double w = Wff[i];
+        if (precision == TRAJAM_FP32) {
+            Wt[i] = (double)(float)w;
+        } else if (precision == TRAJAM_BF16_REFINE) {
+            const float wf = (float)w;
+            const uint16_t hi = bf16_bits(wf), lo = bf16_bits(wf - bf16_value(hi));
+            Wt[i] = (double)bf16_value(hi) + (double)bf16_value(lo);
+        } else {
+            Wt[i] = w;
+        }
+    }
+    for (int a = 0; a < nf; ++a)
+        for (int b = 0; b < nf; ++b) {
+            double acc = a == b ? 1.0 : 0.0;
+            for (int c = 0; c < nf; ++c) acc -= Wt[(size_t)a * nf + c] * H[(size_t)(3 + c) * nv + (3 + b)];
+            E[(size_t)a * nf + b] = acc;
+        }
+    auto fro = [&](const std::vector<double> &M) {
+        double q = 0.0;
+        for (double v : M) q += v * v;
+        return std::sqrt(q);
+    };
+    double nrm = fro(E);
+    if (!(nrm > 0.0)) return 0.0;
+    if (!std::isfinite(nrm)) return INFINITY;
+    double log_scale = std::log(nrm);   // log ||E^k||_F = log_scale + log ||M||_F, M normalised
+    for (double &v : E) v /= nrm;
+    int k = 1;
+    for (int sq = 0; sq < 8; ++sq) {
+        for (int a = 0; a < nf; ++a)
+            for (int b = 0; b < nf; ++b) {
+                double acc = 0.0;
+                for (int c = 0; c < nf; ++c) acc += E[(size_t)a * nf + c] * E[(size_t)c * nf + b];
+                T2[(size_t)a * nf + b] = acc;
+            }
+        k *= 2;
+        log_scale *= 2.0;
+        const double m = fro(T2);
+        if (!(m > 0.0)) return 0.0;   // nilpotent
+        log_scale += std::log(m);
+        for (size_t i = 0; i < E.size(); ++i) E[i] = T2[i] / m;
+    }
+    return std::exp(log_scale / k);
+}
+
+// Largest QP-step contraction of a problem class in its precision (the agents'
+// deviation operator included for joint problems).
+trajam_status problem_contraction(const trajam_problem &p, const std::vector<double> &P,
+                                  const std::vector<double> &H, const std::vector<double> &Wff, double &rho,
+                                  std::string &msg)
+{
+    rho = qp_contraction(H, p.degree, Wff, p.precision);
+    if (p.n_agents > 1) {
+        std::vector<double> H2 = agents_hessian(p, P, H), Wff2, W2;
+        trajam_status st = qp_operator(H2, p.degree, Wff2, W2, msg);
+        if (st != TRAJAM_OK) return st;
+        rho = std::max(rho, qp_contraction(H2, p.degree, Wff2, p.precision));
+    }
+    return TRAJAM_OK;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -364,6 +459,12 @@ trajam_status trajam_init(const trajam_problem *p, trajam_solver **out)
 
     std::string msg;
     st = precompute(*p, s->P, s->Pd, s->Pdd, s->H, s->Wff, s->W, msg);
+    if (st == TRAJAM_OK) st = problem_contraction(*p, s->P, s->H, s->Wff, s->qp_rho, msg);
+    if (st == TRAJAM_OK && !(s->qp_rho < kMaxQpContraction)) {
+        st = TRAJAM_ERR_NUMERIC;
+        msg = "the QP step does not contract in this precision (spectral radius " + std::to_string(s->qp_rho) +
+              " of I - W H_ff); use a higher precision";
+    }
     if (st != TRAJAM_OK) {
         trajam_destroy(s);
         return fail(nullptr, st, msg);
@@ -421,13 +522,7 @@ trajam_status trajam_init(const trajam_problem *p, trajam_solver **out)
     }
     if (e == hipSuccess && p->n_agents > 1) {
         // deviations of the agents from their mean see H + N rho P^T P
-        std::vector<double> H2 = s->H, Wff2, W2;
-        for (int i = 0; i < nv; ++i)
-            for (int j = 0; j < nv; ++j) {
-                double g = 0.0;
-                for (int k = 0; k < np; ++k) g += s->P[(size_t)k * nv + i] * s->P[(size_t)k * nv + j];
-                H2[(size_t)i * nv + j] += p->n_agents * p->rho * g;
-            }
+        std::vector<double> H2 = agents_hessian(*p, s->P, s->H), Wff2, W2;
         st = qp_operator(H2, n, Wff2, W2, msg);
         if (st != TRAJAM_OK) {
             trajam_destroy(s);
@@ -463,6 +558,19 @@ trajam_status trajam_fixed_matrices(const trajam_problem *p, double *P, double *
     if (Pdd) std::memcpy(Pdd, vPdd.data(), sizeof(double) * vPdd.size());
     if (H) std::memcpy(H, vH.data(), sizeof(double) * vH.size());
     if (W && !vW.empty()) std::memcpy(W, vW.data(), sizeof(double) * vW.size());
+    return TRAJAM_OK;
+}
+
+trajam_status trajam_qp_contraction(const trajam_problem *p, double *rho)
+{
+    if (!rho) return fail(nullptr, TRAJAM_ERR_INVALID, "rho must not be NULL");
+    std::string why;
+    trajam_status st = validate(p, why);
+    if (st != TRAJAM_OK) return fail(nullptr, st, why);
+    std::vector<double> vP, vPd, vPdd, vH, vWff, vW;
+    st = precompute(*p, vP, vPd, vPdd, vH, vWff, vW, why);
+    if (st == TRAJAM_OK) st = problem_contraction(*p, vP, vH, vWff, *rho, why);
+    if (st != TRAJAM_OK) return fail(nullptr, st, why);
     return TRAJAM_OK;
 }
 

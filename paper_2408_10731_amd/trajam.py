@@ -48,6 +48,7 @@ EXPORTS = [
     "trajam_mlp_backward", "trajam_mlp_infer", "trajam_mlp_pack_infer", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
     "trajam_warm_apply", "trajam_warm_fallback", "trajam_set_obstacles", "trajam_autotune",
     "trajam_ragged_plan_create", "trajam_ragged_launch", "trajam_ragged_plan_destroy", "trajam_polar",
+    "trajam_qp_contraction",
     "trajam_status_string", "trajam_last_error",
 ]
 
@@ -129,6 +130,8 @@ def load():
     L.trajam_residuals.restype = ctypes.c_int
     L.trajam_polar.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.trajam_polar.restype = ctypes.c_int
+    L.trajam_qp_contraction.argtypes = [ctypes.POINTER(Problem), dp]
+    L.trajam_qp_contraction.restype = ctypes.c_int
     L.trajam_fixed_matrices.argtypes = [ctypes.POINTER(Problem), dp, dp, dp, dp, dp]
     L.trajam_fixed_matrices.restype = ctypes.c_int
     L.trajam_set_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
@@ -234,6 +237,13 @@ def trajam_polar(handle, batch, xi_bar, obs_centre, obs_vel, obs_axes, obs_alpha
                  stream) -> None:
     _check(load().trajam_polar(handle, int(batch), xi_bar, obs_centre, obs_vel, obs_axes, obs_alpha,
                                obs_beta, obs_d, kin, stream), handle)
+
+
+def trajam_qp_contraction(problem: Problem) -> float:
+    """Spectral radius of I - W~ H_ff for the problem's precision (host only)."""
+    out = ctypes.c_double(0.0)
+    _check(load().trajam_qp_contraction(ctypes.byref(problem), ctypes.byref(out)), None)
+    return float(out.value)
 
 
 def trajam_fixed_matrices(problem: Problem):

@@ -128,3 +128,62 @@ def test_boundary_coefficients_reach_boundary_rows():
     x = np.zeros(11)
     x[[0, 1, 2, 10]] = c
     np.testing.assert_allclose(A @ x, b, atol=1e-12)
+
+
+def _bf16_round(x32):
+    """Round float32 values to bfloat16 (nearest, ties to even), returned as float32."""
+    u = np.asarray(x32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+@pytest.mark.parametrize("dims,degree,n_steps,T,n_obs,prec,agents", [
+    (2, 10, 100, 30.0, 50, tj.TRAJAM_FP64, 1),
+    (2, 10, 100, 30.0, 50, tj.TRAJAM_FP32, 1),
+    (3, 15, 150, 20.0, 200, tj.TRAJAM_FP32, 1),
+    (3, 15, 150, 20.0, 200, tj.TRAJAM_BF16_REFINE, 1),
+    (2, 10, 100, 30.0, 50, tj.TRAJAM_BF16_REFINE, 1),
+    (3, 10, 100, 10.0, 20, tj.TRAJAM_FP32, 16),
+    (2, 3, 20, 4.0, 2, tj.TRAJAM_FP32, 1),      # no free coefficient: nothing to contract
+])
+def test_qp_contraction_is_the_spectral_radius(dims, degree, n_steps, T, n_obs, prec, agents):
+    """The library's contraction estimate against numpy's eigenvalues of I - W~ H_ff,
+    built here from the oracle's Hessian with the rounding each precision applies."""
+    pr = _problem(dims=dims, degree=degree, n_steps=n_steps, horizon=T, n_obstacles=n_obs,
+                  v_max=1.5, a_max=2.0, precision=prec, n_agents=agents,
+                  agent_radius=0.3 if agents > 1 else 0.0)
+    rho = tj.trajam_qp_contraction(pr)
+    opr = oracle.problem(dims, degree, n_steps, T, 1.5, 2.0, 1.0, n_obs)
+    _, H = oracle.constraint_matrices(opr)
+    Hs = [H]
+    if agents > 1:
+        P, _, _ = oracle.bernstein(degree, n_steps, T)
+        Hs.append(H + agents * 1.0 * P.T @ P)
+    ref = 0.0
+    for Hm in Hs:
+        Hff = Hm[3:degree, 3:degree]
+        if Hff.size == 0:
+            continue
+        W = np.linalg.inv(Hff)
+        if prec == tj.TRAJAM_FP32:
+            Wt = W.astype(np.float32).astype(np.float64)
+        elif prec == tj.TRAJAM_BF16_REFINE:
+            w32 = W.astype(np.float32)
+            hi = _bf16_round(w32)
+            lo = _bf16_round(w32 - hi)
+            Wt = hi.astype(np.float64) + lo.astype(np.float64)
+        else:
+            Wt = W
+        E = np.eye(Hff.shape[0]) - Wt @ Hff
+        ref = max(ref, np.abs(np.linalg.eigvals(E)).max())
+    if prec == tj.TRAJAM_FP64 or degree == 3:
+        assert rho < 1e-10
+    else:
+        # an upper estimate within n_f^(1/512) of the radius
+        assert ref * (1 - 1e-9) <= rho <= ref * 1.01 + 1e-300, (rho, ref)
+    assert rho < 0.5
+
+
+def test_qp_contraction_rejects_a_null_output():
+    pr = _problem()
+    assert tj.load().trajam_qp_contraction(ctypes.byref(pr), None) == tj.TRAJAM_ERR_INVALID
