@@ -13,8 +13,9 @@ start and from the learned warm start (network trained here first, untimed), the
 roofline of the fused AM kernel (VALU-bound: algorithmic lane-ops / kernel time
 against the chip's 256 CU x 64 lanes x 2.4 GHz), the ragged set of 256 problems
 (half of them multi-agent) in one plan, one graph-replayed planning call of the
-sampling loop, and the FP64 CPU oracle timed on a bounded sample of the main
-workload on the host cores.
+sampling loop, config 3 in FP64 / FP32 / BF16 with the reduced precisions' deviation
+from FP64, and the FP64 CPU oracle timed on a bounded sample of the main workload on
+the host cores.
 """
 from __future__ import annotations
 
@@ -269,6 +270,53 @@ def ragged_bench(args):
     return out
 
 
+def precision_bench(args):
+    """Config 3 (3D, degree 15, 150 steps over 20 s, 200 ellipsoids, 4096 samples, 50 AM
+    iterations, cold start) in each precision: FP64, FP32, and BF16 (the QP product on
+    the matrix cores with hi/lo split, fp32 accumulation and one refinement pass).
+    Reports each precision's time per projection (autotuned shape; the cold-start
+    resets included) and the FP32 / BF16 results' deviation from the FP64 run on the
+    same inputs: the largest waypoint difference over every sample and time step and
+    the largest difference of the final residual."""
+    import torch
+    from paper_2408_10731_amd import trajam as tj
+    from paper_2408_10731_amd import workloads as wl
+
+    w = wl.config3()
+    K = w.iters
+    out, final = {"config": "config 3: 3D, degree 15, 150 steps, 200 ellipsoids, 4096 samples, "
+                            f"{K} AM iterations, cold start"}, {}
+    stream = torch.cuda.current_stream()
+    P = None
+    for prec in ("fp64", "fp32", "bf16"):
+        solver = tj.Solver.for_workload(w, precision=prec, sphere=False)
+        if P is None:
+            P = tj.trajam_fixed_matrices(solver.problem)[0]
+        dt = solver.dtype
+        xi, obs = tj.device_workload(w, dt)
+        xb, lam = xi.clone(), torch.zeros_like(xi)
+        shape = solver.autotune(xi, w.boundary, obs, xb, lam, probe_iters=K)
+        solver.set_obstacles(obs)
+        tr = torch.zeros((K, w.batch), dtype=dt, device="cuda")
+
+        def run():
+            xb.copy_(xi)
+            lam.zero_()
+            solver.project(xi, w.boundary, None, xb, lam, K, res_trace=tr)
+        ms = _time(run, args.precision_steps, stream)
+        run()
+        torch.cuda.synchronize()
+        final[prec] = (np.einsum("tm,bdm->btd", P, xb.double().cpu().numpy()), tr[-1].double().cpu().numpy())
+        out[prec] = {"ms_per_projection": ms, "traj_iters_per_s": w.batch * K / (ms * 1e-3),
+                     "launch_shape": list(shape)}
+        solver.close()
+    for prec in ("fp32", "bf16"):
+        out[prec]["vs_fp64"] = {
+            "waypoint_max_m": float(np.abs(final[prec][0] - final["fp64"][0]).max()),
+            "residual_max": float(np.abs(final[prec][1] - final["fp64"][1]).max())}
+    return out
+
+
 def cem_bench(args):
     """One planning call of the projection-guided sampling loop at config-4 sizes:
     30 iterations, each drawing 2000 samples, projecting them with 15 AM iterations
@@ -336,6 +384,8 @@ def main():
     ap.add_argument("--ragged-problems", type=int, default=256, help="0 skips the ragged set")
     ap.add_argument("--ragged-steps", type=int, default=3)
     ap.add_argument("--cem-calls", type=int, default=5, help="0 skips the sampling loop")
+    ap.add_argument("--precision-steps", type=int, default=3,
+                    help="timed projections per precision of config 3; 0 skips that leg")
     ap.add_argument("--cem-only", action="store_true",
                     help="run only the sampling-loop leg and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -420,6 +470,7 @@ def main():
     ttr = time_to_residual(args, w, solver, xi, obs, stream) if args.ttr_cap > 0 else None
     ragged = ragged_bench(args) if args.ragged_problems > 0 else None
     cem_out = cem_bench(args) if args.cem_calls > 0 else None
+    prec_out = precision_bench(args) if args.precision_steps > 0 else None
 
     out = {
         "metric": "traj-iters/s & time-to-residual<=1e-3, learned warm-start vs cold, 1 MI355X",
@@ -435,6 +486,7 @@ def main():
         "time_to_residual": ttr,
         "ragged": ragged,
         "cem": cem_out,
+        "precision_cfg3": prec_out,
         "wall_s_timed_region": wall,
     }
     if not args.no_cpu:
