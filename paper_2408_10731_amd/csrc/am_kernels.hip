@@ -298,6 +298,45 @@ __device__ __forceinline__ void wave_box(const float (&tt)[NPT], const float (&p
     }
 }
 
+// Boxes of the four 16-lane rows of the wave (points with ok, coordinates and times):
+// the same integer images reduced by the DPP steps inside a row only.  A row without
+// points gets lo > hi.
+template <int D, int NPT>
+__device__ __forceinline__ void row_boxes(const float (&tt)[NPT], const float (&p)[NPT][D], const bool (&ok)[NPT],
+                                          float (&lo)[4][D + 1], float (&hi)[4][D + 1])
+{
+    constexpr int NQ = D + 1;
+    const float big = 1e30f;
+    int c[2 * NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        float mn = big, mx = -big;
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const float x = q < D ? p[i][q < D ? q : 0] : tt[i];
+            if (ok[i]) { mn = fminf(mn, x); mx = fmaxf(mx, x); }
+        }
+        c[q] = ord_i(mn);
+        c[NQ + q] = ord_i(-mx);
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * NQ; ++j) {
+        int v = c[j];
+        v = min(v, dpp_min_operand<kDppRor8>(v));
+        v = min(v, dpp_min_operand<kDppHalfMirror>(v));
+        v = min(v, dpp_min_operand<kDppXor2>(v));
+        v = min(v, dpp_min_operand<kDppXor1>(v));
+        c[j] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            lo[r][q] = ord_f(__builtin_amdgcn_readlane(c[q], 16 * r));
+            hi[r][q] = -ord_f(__builtin_amdgcn_readlane(c[NQ + q], 16 * r));
+        }
+}
+
 // Orders this wave's LDS writes before its later LDS reads (lanes of one wave
 // exchanging data through LDS); no other wave takes part, so no block barrier.
 __device__ __forceinline__ void wave_lds_sync()
@@ -665,9 +704,32 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, const T *ol, 
                 moved = moved || (ok[i] && !(fabs(p[i][ax] - cc.pref[i][ax]) <= cc.delta));
         rebuild = __any(moved);
     }
+    // moving obstacles are swept over a time range: against the four 16-lane rows'
+    // boxes, each with its own shorter range, instead of the whole wave's
+    constexpr bool ROWS = DYN && !STAGED && sizeof(T) == sizeof(float);
     T lo[D], hi[D], tlo = T(0), thi = T(0);
+    T rlo[4][D + 1], rhi[4][D + 1];
     if (!rebuild) {
         // masks from the cache below
+    } else if constexpr (ROWS) {
+        row_boxes<D, NPT>(tt, p, ok, rlo, rhi);
+        // the wave's box is the union of the rows'
+#pragma unroll
+        for (int q = 0; q <= D; ++q) {
+            T mn = rlo[0][q], mx = rhi[0][q];
+#pragma unroll
+            for (int r = 1; r < 4; ++r) {
+                mn = fmin(mn, rlo[r][q]);
+                mx = fmax(mx, rhi[r][q]);
+            }
+            if (q < D) {
+                lo[q < D ? q : 0] = mn;
+                hi[q < D ? q : 0] = mx;
+            } else {
+                tlo = mn;
+                thi = mx;
+            }
+        }
     } else if constexpr (sizeof(T) == sizeof(float)) {
         wave_box<D, DYN, NPT>(tt, p, ok, lo, hi, tlo, thi);
     } else {
@@ -705,6 +767,15 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, const T *ol, 
                 lo[ax] -= grow;
                 hi[ax] += grow;
             }
+            if constexpr (ROWS) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int ax = 0; ax < D; ++ax) {
+                        rlo[r][ax] -= grow;
+                        rhi[r][ax] += grow;
+                    }
+            }
             cc.delta = dl;
 #pragma unroll
             for (int i = 0; i < NPT; ++i)
@@ -721,17 +792,39 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, const T *ol, 
         unsigned long long mask;
         if (rebuild) {
             bool cand = base + lane < n_o;
+            if constexpr (ROWS) {
+                // candidate if its box swept over some row's time range meets that row's box
+                bool any = false;
 #pragma unroll
-            for (int ax = 0; ax < D; ++ax) {
-                const T e = SPH ? k.r : k.s[ax];
-                T cmin = k.c[ax], cmax = k.c[ax], m = fma(e, T(1.0001), T(1e-4)) + T(1e-5) * fabs(k.c[ax]);
-                if (DYN) {
-                    const T c1 = fma(-k.w[ax], tlo, k.c[ax]), c2 = fma(-k.w[ax], thi, k.c[ax]);
-                    cmin = fmin(c1, c2);
-                    cmax = fmax(c1, c2);
-                    m += T(1e-5) * (fabs(k.w[ax]) * tabs + fabs(cmin) + fabs(cmax));
+                for (int r = 0; r < 4; ++r) {
+                    if (!(rlo[r][D] <= rhi[r][D])) continue;   // a row without points
+                    const T ta = rlo[r][D], tb = rhi[r][D], tab = fmax(fabs(ta), fabs(tb));
+                    bool cr = true;
+#pragma unroll
+                    for (int ax = 0; ax < D; ++ax) {
+                        const T e = SPH ? k.r : k.s[ax];
+                        const T c1 = fma(-k.w[ax], ta, k.c[ax]), c2 = fma(-k.w[ax], tb, k.c[ax]);
+                        const T cmin = fmin(c1, c2), cmax = fmax(c1, c2);
+                        const T m = fma(e, T(1.0001), T(1e-4)) + T(1e-5) * fabs(k.c[ax]) +
+                                    T(1e-5) * (fabs(k.w[ax]) * tab + fabs(cmin) + fabs(cmax));
+                        cr = cr && (cmin - m <= rhi[r][ax]) && (cmax + m >= rlo[r][ax]);
+                    }
+                    any = any || cr;
                 }
-                cand = cand && (cmin - m <= hi[ax]) && (cmax + m >= lo[ax]);
+                cand = cand && any;
+            } else {
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax) {
+                    const T e = SPH ? k.r : k.s[ax];
+                    T cmin = k.c[ax], cmax = k.c[ax], m = fma(e, T(1.0001), T(1e-4)) + T(1e-5) * fabs(k.c[ax]);
+                    if (DYN) {
+                        const T c1 = fma(-k.w[ax], tlo, k.c[ax]), c2 = fma(-k.w[ax], thi, k.c[ax]);
+                        cmin = fmin(c1, c2);
+                        cmax = fmax(c1, c2);
+                        m += T(1e-5) * (fabs(k.w[ax]) * tabs + fabs(cmin) + fabs(cmax));
+                    }
+                    cand = cand && (cmin - m <= hi[ax]) && (cmax + m >= lo[ax]);
+                }
             }
             mask = __ballot(cand);
             if (cached) {

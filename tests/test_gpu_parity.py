@@ -261,6 +261,25 @@ def _fp32_check(w, iters, tol_wp=1e-3, tol_res=1e-4, kernel=None):
 
 
 @pytest.mark.parametrize("kernel", [0, 1])
+def test_fp32_config4_moving_circles(kernel):
+    """Config-4 geometry (100 circles moving at up to 1 m/s, 15 AM iterations) on 256
+    samples: moving obstacles are culled against 16-lane row boxes with their own
+    time ranges."""
+    w = wl.config4_scene(7, batch=256)
+    say("case: cfg4 fp32 moving circles, kernel", kernel)
+    _fp32_check(w, 15, kernel=kernel)
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_fp32_moving_ellipsoids_three_waves(kernel):
+    """120 moving ellipsoids in 3D, 150 time steps (three waves / three steps a lane)."""
+    w = wl.tiny(dims=3, batch=16, n_obs=120, degree=9, n_steps=150, speed=0.4, per_axis=True,
+                seed=77)
+    say("case: fp32 moving ellipsoids, kernel", kernel)
+    _fp32_check(w, 20, kernel=kernel)
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
 def test_fp32_config2_full_size(kernel):
     """Config 2 at full size (B = 1024, 50 circles, 50 iterations), the bench launch."""
     w = wl.config2()
