@@ -6,6 +6,7 @@ scalar float/double code, so nothing is lost by keeping the compiler from pairin
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -24,10 +25,10 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-mcode-object-version=5", "-Wall", "-Wn
 
 def build(verbose: bool = False) -> str:
     """Compile every source (always; build products are not trusted) and link."""
-    objs = []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    for src in SOURCES:
+
+    def compile_one(src):
         obj = os.path.join(bdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = [HIPCC, f"--offload-arch={ARCH}", *COMMON, *lang, "-c",
@@ -35,7 +36,11 @@ def build(verbose: bool = False) -> str:
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+        return obj
+
+    # the sources compile independently: one process each
+    with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
+        objs = list(pool.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

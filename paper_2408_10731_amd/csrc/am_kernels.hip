@@ -879,7 +879,11 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, const T *ol, 
     }
 }
 
-template <typename T, int D, int NPT>
+// Obstacle motion of a kernel instance: static obstacles only, moving ones only, or
+// either, chosen at run time (the ragged kernels, whose problems differ).
+constexpr int kObsStatic = 0, kObsMoving = 1, kObsEither = 2;
+
+template <typename T, int D, int NPT, int OM = kObsEither>
 __device__ __forceinline__ void obstacle_residuals_culled(const T *aos_g, int n_o, int sphere, int dynamic,
                                                           const ObsChunk<T, D> first, const T (&tt)[NPT],
                                                           const T (&p)[NPT][D], const bool (&ok)[NPT],
@@ -888,12 +892,13 @@ __device__ __forceinline__ void obstacle_residuals_culled(const T *aos_g, int n_
     // the cache's reference positions cost NPT * D registers a lane: FP64 launches with
     // more than two time samples a lane rebuild the masks every iteration instead
     constexpr bool C = sizeof(T) == sizeof(float) || NPT <= 2;
+    const bool mov = OM == kObsMoving || (OM == kObsEither && dynamic);
     if (sphere) {
-        if (dynamic) obstacle_cull_loop<T, D, true, true, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
-        else obstacle_cull_loop<T, D, true, false, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
+        if (OM != kObsStatic && mov) obstacle_cull_loop<T, D, true, true, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
+        else if (OM != kObsMoving) obstacle_cull_loop<T, D, true, false, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
     } else {
-        if (dynamic) obstacle_cull_loop<T, D, false, true, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
-        else obstacle_cull_loop<T, D, false, false, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
+        if (OM != kObsStatic && mov) obstacle_cull_loop<T, D, false, true, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
+        else if (OM != kObsMoving) obstacle_cull_loop<T, D, false, false, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
     }
 }
 
@@ -989,7 +994,7 @@ struct Lds {
 
 // ----------------------------------------------------------------------------
 // The fused AM kernel: `a.iters` iterations for `a.tb` samples per workgroup.
-template <typename T, int D, int NVP, bool MQP>
+template <typename T, int D, int NVP, bool MQP, int OM>
 __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
 {
     using L = Lds<D, NVP>;
@@ -1101,8 +1106,8 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
                 p1[0][ax] = valid ? p[ax] : T(-1e30);
                 R1[0][ax] = T(0);
             }
-            obstacle_residuals_culled<T, D, 1>(a.obs, a.n_o, a.sphere, a.dynamic, oc0, tt1, p1, ok1, R1, r2, rmax,
-                                               ccache);
+            obstacle_residuals_culled<T, D, 1, OM>(a.obs, a.n_o, a.sphere, a.dynamic, oc0, tt1, p1, ok1, R1, r2,
+                                                   rmax, ccache);
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) R[ax] = R1[0][ax];
         }
@@ -1284,7 +1289,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
 // and the QP update, so the iteration needs no block barrier.  wmat [NVP][NVP] holds
 // the QP operator, xs / gs [D*NVP] this wave's iterate and defect (LDS); db, hff,
 // hfb and the A operands are used by the bf16 matrix-core QP only.
-template <typename T, int D, int NVP, int TPL, bool MQP, typename A>
+template <typename T, int D, int NVP, int TPL, bool MQP, typename A, int OM = kObsEither>
 __device__ __forceinline__ void wave_sample(const A &a, const int sample, const int lane,
                                             const T *wmat, T *xs, T *gs, float *db,
                                             const float *hff, const float *hfb, bf16x4 ahi,
@@ -1362,8 +1367,8 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
         for (int i = 0; i < TPL; ++i)
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) { R[i][ax] = T(0); rv[i][ax] = T(0); ra[i][ax] = T(0); }
-        obstacle_residuals_culled<T, D, TPL>(a.obs, a.n_o, a.sphere, a.dynamic, oc0, tt, p, valid, R, r2, rmax,
-                                             ccache);
+        obstacle_residuals_culled<T, D, TPL, OM>(a.obs, a.n_o, a.sphere, a.dynamic, oc0, tt, p, valid, R, r2, rmax,
+                                                 ccache);
 #pragma unroll
         for (int i = 0; i < TPL; ++i) {
             if (a.use_v) bound_residual<T, D>(v[i], a.vmax, rv[i], r2, rmax);
@@ -1494,7 +1499,7 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
 
 // Wave-per-sample AM kernel: `a.tb` samples per workgroup (= waves per workgroup),
 // each wave independent of the others after the constant set-up.
-template <typename T, int D, int NVP, int TPL, bool MQP>
+template <typename T, int D, int NVP, int TPL, bool MQP, int OM>
 __global__ __launch_bounds__(kMaxThreads) void am_wave_kernel(AmArgs<T> a)
 {
     constexpr int S = D * NVP;
@@ -1528,7 +1533,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_wave_kernel(AmArgs<T> a)
     }
     __syncthreads();
     if (sample >= a.batch) return;  // waves are independent from here on
-    wave_sample<T, D, NVP, TPL, MQP>(a, sample, lane, wmat, xs, gs, db, hff, hfb, ahi, alo);
+    wave_sample<T, D, NVP, TPL, MQP, AmArgs<T>, OM>(a, sample, lane, wmat, xs, gs, db, hff, hfb, ahi, alo);
 }
 
 // ----------------------------------------------------------------------------
@@ -2087,7 +2092,11 @@ hipError_t launch_project_t(const AmArgs<T> &a, hipStream_t st)
     const int blocks = (a.batch + a.tb - 1) / a.tb;
     if (a.tb < 1 || threads > kMaxThreads) return hipErrorInvalidValue;
     if (MQP && (a.tb * D > 16 || a.nv - 4 > 16)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((am_project_kernel<T, D, NVP, MQP>), dim3(blocks), dim3(threads), lds, st, a);
+    // separate instances for static and moving obstacles: each carries one obstacle loop
+    if (a.dynamic)
+        hipLaunchKernelGGL((am_project_kernel<T, D, NVP, MQP, kObsMoving>), dim3(blocks), dim3(threads), lds, st, a);
+    else
+        hipLaunchKernelGGL((am_project_kernel<T, D, NVP, MQP, kObsStatic>), dim3(blocks), dim3(threads), lds, st, a);
     return hipGetLastError();
 }
 template <typename T, int D, int NVP, bool MQP>
@@ -2099,13 +2108,20 @@ hipError_t launch_wave_t(const AmArgs<T> &a, hipStream_t st)
     const int blocks = (a.batch + a.tb - 1) / a.tb;
     const int tpl = (a.n_p + 63) / 64;
     if (a.tb < 1 || threads > kMaxThreads) return hipErrorInvalidValue;
-    switch (tpl) {
-    case 1: hipLaunchKernelGGL((am_wave_kernel<T, D, NVP, 1, MQP>), dim3(blocks), dim3(threads), lds, st, a); break;
-    case 2: hipLaunchKernelGGL((am_wave_kernel<T, D, NVP, 2, MQP>), dim3(blocks), dim3(threads), lds, st, a); break;
-    case 3: hipLaunchKernelGGL((am_wave_kernel<T, D, NVP, 3, MQP>), dim3(blocks), dim3(threads), lds, st, a); break;
-    case 4: hipLaunchKernelGGL((am_wave_kernel<T, D, NVP, 4, MQP>), dim3(blocks), dim3(threads), lds, st, a); break;
-    default: return hipErrorInvalidValue;
+#define TRAJAM_WAVE_LAUNCH(OMV)                                                                                 \
+    switch (tpl) {                                                                                             \
+    case 1: hipLaunchKernelGGL((am_wave_kernel<T, D, NVP, 1, MQP, OMV>), dim3(blocks), dim3(threads), lds, st, a); break; \
+    case 2: hipLaunchKernelGGL((am_wave_kernel<T, D, NVP, 2, MQP, OMV>), dim3(blocks), dim3(threads), lds, st, a); break; \
+    case 3: hipLaunchKernelGGL((am_wave_kernel<T, D, NVP, 3, MQP, OMV>), dim3(blocks), dim3(threads), lds, st, a); break; \
+    case 4: hipLaunchKernelGGL((am_wave_kernel<T, D, NVP, 4, MQP, OMV>), dim3(blocks), dim3(threads), lds, st, a); break; \
+    default: return hipErrorInvalidValue;                                                                      \
     }
+    if (a.dynamic) {
+        TRAJAM_WAVE_LAUNCH(kObsMoving)
+    } else {
+        TRAJAM_WAVE_LAUNCH(kObsStatic)
+    }
+#undef TRAJAM_WAVE_LAUNCH
     return hipGetLastError();
 }
 template <typename T, int D, int NVP>
