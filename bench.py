@@ -32,9 +32,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_VALU_OPS = 256 * 64 * 2.4e9  # lane-ops/s, one FMA = one op (no packed FP32)
 # HBM bytes per launch of the main kernel from FETCH_SIZE / WRITE_SIZE counter runs
-# scaled by a copy of known size (profiles/am_project_kernel_cfg2_fp32.md): 958 KiB
+# scaled by a copy of known size (profiles/am_project_kernel_cfg2_fp32.md): 921 KiB
 # read + 1,824 KiB written.  Re-measure whenever the kernel changes.
-TRAFFIC_BYTES_PER_LAUNCH = (958 + 1824) * 1024
+TRAFFIC_BYTES_PER_LAUNCH = (921 + 1824) * 1024
 
 
 def algorithmic_ops_per_traj_iter(w) -> float:
