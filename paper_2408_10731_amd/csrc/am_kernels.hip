@@ -687,7 +687,7 @@ struct CullCache {
 // Chunks of 64 obstacles (lane j: obstacle base + j) come from the LDS stage `ol`
 // (STAGED) or from the packed records, the first one from `first`, loaded once per
 // launch by the caller.
-template <typename T, int D, bool SPH, bool DYN, int NPT, bool STAGED, bool CACHE>
+template <typename T, int D, bool SPH, bool DYN, int NPT, bool STAGED, bool CACHE, bool ROWSOK = false>
 __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, const T *ol, int n_o, const ObsChunk<T, D> first,
                                                    const T (&tt)[NPT], const T (&p)[NPT][D], const bool (&ok)[NPT],
                                                    T (&R)[NPT][D], T &r2, T &rmax, CullCache<T, D, NPT> &cc)
@@ -706,7 +706,7 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, const T *ol, 
     }
     // moving obstacles are swept over a time range: against the four 16-lane rows'
     // boxes, each with its own shorter range, instead of the whole wave's
-    constexpr bool ROWS = DYN && !STAGED && sizeof(T) == sizeof(float);
+    constexpr bool ROWS = ROWSOK && DYN && !STAGED && sizeof(T) == sizeof(float);
     T lo[D], hi[D], tlo = T(0), thi = T(0);
     T rlo[4][D + 1], rhi[4][D + 1];
     if (!rebuild) {
@@ -893,11 +893,14 @@ __device__ __forceinline__ void obstacle_residuals_culled(const T *aos_g, int n_
     // more than two time samples a lane rebuild the masks every iteration instead
     constexpr bool C = sizeof(T) == sizeof(float) || NPT <= 2;
     const bool mov = OM == kObsMoving || (OM == kObsEither && dynamic);
+    // row boxes only in the moving-obstacle instances: the either-motion (ragged)
+    // kernels keep the smaller whole-wave test, their registers being at the limit
+    constexpr bool RW = OM == kObsMoving;
     if (sphere) {
-        if (OM != kObsStatic && mov) obstacle_cull_loop<T, D, true, true, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
+        if (OM != kObsStatic && mov) obstacle_cull_loop<T, D, true, true, NPT, false, C, RW>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
         else if (OM != kObsMoving) obstacle_cull_loop<T, D, true, false, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
     } else {
-        if (OM != kObsStatic && mov) obstacle_cull_loop<T, D, false, true, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
+        if (OM != kObsStatic && mov) obstacle_cull_loop<T, D, false, true, NPT, false, C, RW>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
         else if (OM != kObsMoving) obstacle_cull_loop<T, D, false, false, NPT, false, C>(aos_g, nullptr, n_o, first, tt, p, ok, R, r2, rmax, cc);
     }
 }
