@@ -1891,7 +1891,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_ragged_kernel(const AmArgs<flo
 __global__ void zero_counter_kernel(int *counter) { *counter = 0; }
 
 // Residual only: steps (a) and the residual norms at the given coefficients.
-template <typename T, int D, int NVP>
+template <typename T, int D, int NVP, int OM>
 __global__ __launch_bounds__(kMaxThreads) void am_residual_kernel(AmArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1926,8 +1926,29 @@ __global__ __launch_bounds__(kMaxThreads) void am_residual_kernel(AmArgs<T> a)
     T R[D], rv[D], ra[D], r2 = T(0), rmax = T(0);
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) R[ax] = T(0);
+    if constexpr (OM == kObsStatic) {
+        // static obstacles: the projection's culled loop (few candidates per wave),
+        // called by every lane of the wave, lanes without a point passing one far away
+        const ObsChunk<T, D> oc0 = load_obs_chunk<T, D>(a.obs, a.n_o, 0, lane);
+        CullCache<T, D, 1> cc;
+        const T tt1[1] = {T(lt) * a.dt};
+        const bool ok1[1] = {valid};
+        T p1[1][D], R1[1][D];
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+            p1[0][ax] = valid ? p[ax] : T(-1e30);
+            R1[0][ax] = T(0);
+        }
+        obstacle_residuals_culled<T, D, 1, kObsStatic>(a.obs, a.n_o, a.sphere, 0, oc0, tt1, p1, ok1, R1, r2, rmax,
+                                                       cc);
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) R[ax] = R1[0][ax];
+    } else {
+        // moving obstacles swept over a wave's time range leave most of them candidates:
+        // every obstacle is tested from its fields in scalar registers instead
+        if (valid) obstacle_residuals1<T, D>(a.obs_soa, a.obs, a.n_o, a.sphere, a.dynamic, T(lt) * a.dt, p, R, r2, rmax);
+    }
     if (valid) {
-        obstacle_residuals1<T, D>(a.obs_soa, a.obs, a.n_o, a.sphere, a.dynamic, T(lt) * a.dt, p, R, r2, rmax);
         if (a.use_v) bound_residual<T, D>(v, a.vmax, rv, r2, rmax);
         if (a.use_a) bound_residual<T, D>(acc, a.amax, ra, r2, rmax);
     }
@@ -2144,7 +2165,10 @@ hipError_t launch_residual_t(const AmArgs<T> &a, hipStream_t st)
     const int threads = a.tb * a.tpad;
     const int blocks = (a.batch + a.tb - 1) / a.tb;
     if (a.tb < 1 || threads > kMaxThreads) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((am_residual_kernel<T, D, NVP>), dim3(blocks), dim3(threads), lds, st, a);
+    if (a.dynamic)
+        hipLaunchKernelGGL((am_residual_kernel<T, D, NVP, kObsMoving>), dim3(blocks), dim3(threads), lds, st, a);
+    else
+        hipLaunchKernelGGL((am_residual_kernel<T, D, NVP, kObsStatic>), dim3(blocks), dim3(threads), lds, st, a);
     return hipGetLastError();
 }
 

@@ -152,13 +152,18 @@ def test_fp64_centre_tie_and_warm_start():
     assert np.abs(lam_g - lam_o).max() <= 1e-9
 
 
-def test_fp64_residuals_entry_point():
+@pytest.mark.parametrize("dims,n_obs,speed,per_axis", [
+    (3, 5, 0.4, True),      # moving ellipsoids: every obstacle tested
+    (3, 5, 0.0, True),      # static ellipsoids: the culled loop
+    (2, 100, 0.0, False),   # static circles in two chunks
+])
+def test_fp64_residuals_entry_point(dims, n_obs, speed, per_axis):
     tj = _tj()
-    w = wl.tiny(dims=3, batch=9, n_obs=5, degree=8, n_steps=70, per_axis=True, speed=0.4,
-                seed=21)
-    say("case: residuals entry")
+    w = wl.tiny(dims=dims, batch=9, n_obs=n_obs, degree=8, n_steps=70, per_axis=per_axis,
+                speed=speed, seed=21)
+    say("case: residuals entry", dims, n_obs, speed, per_axis)
     xb = w.xi + np.random.default_rng(2).normal(size=w.xi.shape) * 0.3
-    solver = tj.Solver.for_workload(w, sphere=False)
+    solver = tj.Solver.for_workload(w, sphere=False if per_axis else None)
     xi, obs = tj.device_workload(w, torch.float64)
     xbd = torch.as_tensor(xb, device="cuda").contiguous()
     r = torch.zeros(w.batch, dtype=torch.float64, device="cuda")
