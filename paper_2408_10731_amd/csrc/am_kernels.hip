@@ -675,6 +675,10 @@ __device__ __forceinline__ ObsChunk<T, D> lds_obs_chunk(const T *ol, int n_o, in
 // point still lies in that grown box, so the masks still hold every obstacle that can
 // contain one of the wave's points, and the box reduction and chunk tests are skipped.
 constexpr int kCullCacheChunks = 4;
+// delta = kCullGrowFrac * (largest extent of the wave's box) + kCullGrowAbs: larger
+// margins keep masks longer but admit more candidates (at config 2, 5 % of the extent
+// grew the candidates from 2.0 to 3.4 per wave; 0.5 % rebuilt too often)
+constexpr float kCullGrowFrac = 0.015f, kCullGrowAbs = 1e-3f;
 
 template <typename T, int D, int NPT>
 struct CullCache {
@@ -760,7 +764,7 @@ __device__ __forceinline__ void obstacle_cull_loop(const T *aos_g, const T *ol, 
             T ext = T(0);
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) ext = fmax(ext, hi[ax] - lo[ax]);
-            const T dl = T(0.015) * ext + T(1e-3);
+            const T dl = T(kCullGrowFrac) * ext + T(kCullGrowAbs);
             const T grow = fma(dl, T(1.0001), T(1e-5));  // also covers the rounding of p - pref
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) {
