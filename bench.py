@@ -14,8 +14,8 @@ roofline of the fused AM kernel (VALU-bound: algorithmic lane-ops / kernel time
 against the chip's 256 CU x 64 lanes x 2.4 GHz), the ragged set of 256 problems
 (half of them multi-agent) in one plan, one graph-replayed planning call of the
 sampling loop, config 3 in FP64 / FP32 / BF16 with the reduced precisions' deviation
-from FP64, and the FP64 CPU oracle timed on a bounded sample of the main workload on
-the host cores.
+from FP64, the materialised polar variables against the HBM peak, and the FP64 CPU
+oracle timed on the main workload on the host cores (about 8 s) and on one thread.
 """
 from __future__ import annotations
 
@@ -358,16 +358,62 @@ def cem_bench(args):
     return out
 
 
-def cpu_baseline(w, iters_sample: int):
+def cpu_baseline(w, iters: int, seconds: float = 8.0, seconds_1t: float = 2.0):
+    """The FP64 C oracle on the host cores: the whole benchmark step (every trajectory,
+    every iteration) repeated until about `seconds` of wall time on all threads, and a
+    64-trajectory slice of it on one thread for about `seconds_1t`."""
     import oracle
     threads = oracle.max_threads()
-    t0 = time.perf_counter()
-    oracle.project(w, iters=iters_sample, n_threads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": w.batch * iters_sample / dt, "unit": "traj-iters/s", "cores": threads,
+
+    def timed(wk, n_threads, budget):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            oracle.project(wk, iters=iters, n_threads=n_threads)
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= budget or reps >= 50:
+                return reps, dt
+    reps, dt = timed(w, threads, seconds)
+    w1 = w.subset(64)
+    reps1, dt1 = timed(w1, 1, seconds_1t)
+    return {"value": reps * w.batch * iters / dt, "unit": "traj-iters/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{w.batch} trajectories x {iters_sample} AM iterations of the same "
-                      f"workload, FP64 C oracle, OpenMP over trajectories ({dt:.1f} s)"}
+            "sample": f"the whole step ({w.batch} trajectories x {iters} AM iterations), {reps} run(s), "
+                      f"FP64 C oracle, OpenMP over trajectories on {threads} threads ({dt:.1f} s)",
+            "value_1thread": reps1 * w1.batch * iters / dt1,
+            "sample_1thread": f"{w1.batch} trajectories x {iters} AM iterations, {reps1} run(s) on one "
+                              f"thread ({dt1:.1f} s)"}
+
+
+def polar_bench(args):
+    """The materialised polar variables (trajam_polar) at config-2 sizes: alpha, d (and
+    beta = pi/2) for 1024 samples x 50 obstacles x 128 padded steps plus the kinematic
+    blocks, FP32; HBM-bound writes, reported against the 8 TB/s peak."""
+    import torch
+    from paper_2408_10731_amd import trajam as tj
+    from paper_2408_10731_amd import workloads as wl
+
+    w = wl.config2()
+    solver = tj.Solver.for_workload(w, precision="fp32")
+    xi, obs = tj.device_workload(w, torch.float32)
+    solver.set_obstacles(obs)
+    n_pad = (w.n_steps + 63) // 64 * 64
+    kw = dict(dtype=torch.float32, device="cuda")
+    al, be, d = (torch.empty((w.batch, w.n_obs, n_pad), **kw) for _ in range(3))
+    kin = torch.empty((w.batch, 6, n_pad), **kw)
+    st = torch.cuda.current_stream()
+
+    def run():
+        tj.trajam_polar(solver.handle, w.batch, xi.data_ptr(), None, None, None, al.data_ptr(),
+                        be.data_ptr(), d.data_ptr(), kin.data_ptr(), st.cuda_stream)
+    ms = _time(run, args.polar_steps, st)
+    written = 4 * (3 * al.numel() + kin.numel())
+    read = 4 * (xi.numel() + 3 * w.n_steps * 12)
+    solver.close()
+    gbs = (written + read) / (ms * 1e-3) / 1e9
+    return {"config": "config 2 sizes: 1024 samples x 50 obstacles x 128 padded steps + kinematic blocks, fp32",
+            "ms_per_call": ms, "bytes_per_call": written + read, "achieved_GBps": gbs,
+            "peak_GBps": 8000.0, "frac": gbs / 8000.0}
 
 
 def main():
@@ -386,6 +432,8 @@ def main():
     ap.add_argument("--cem-calls", type=int, default=5, help="0 skips the sampling loop")
     ap.add_argument("--precision-steps", type=int, default=3,
                     help="timed projections per precision of config 3; 0 skips that leg")
+    ap.add_argument("--polar-steps", type=int, default=10,
+                    help="timed calls of the materialised polar variables; 0 skips that leg")
     ap.add_argument("--cem-only", action="store_true",
                     help="run only the sampling-loop leg and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -471,6 +519,7 @@ def main():
     ragged = ragged_bench(args) if args.ragged_problems > 0 else None
     cem_out = cem_bench(args) if args.cem_calls > 0 else None
     prec_out = precision_bench(args) if args.precision_steps > 0 else None
+    polar_out = polar_bench(args) if args.polar_steps > 0 else None
 
     out = {
         "metric": "traj-iters/s & time-to-residual<=1e-3, learned warm-start vs cold, 1 MI355X",
@@ -487,10 +536,11 @@ def main():
         "ragged": ragged,
         "cem": cem_out,
         "precision_cfg3": prec_out,
+        "polar_materialised": polar_out,
         "wall_s_timed_region": wall,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, 20)
+        out["cpu_baseline"] = cpu_baseline(w, K)
     print(json.dumps(out), flush=True)
     solver.close()
 
