@@ -61,20 +61,10 @@ def _check(w, xb, al, be, d, kin, precision, entries=None):
             np.testing.assert_allclose(e_g, e_o, atol=1e-10 if fp64 else 1e-4 * bound)
 
 
-@pytest.mark.parametrize("dims,speed,per_axis,precision", [
-    (2, 0.5, False, "fp64"),   # moving circles
-    (3, 0.3, True, "fp64"),    # moving ellipsoids
-    (2, 0.0, True, "fp64"),    # static ellipses
-    (2, 0.5, False, "fp32"),
-    (3, 0.3, True, "fp32"),
-])
-def test_polar_variables_match_the_oracle(dims, speed, per_axis, precision):
+def _run_case(w, precision, speed, per_axis):
     from paper_2408_10731_amd import trajam as tj
-    w = wl.tiny(dims=dims, batch=5, n_obs=7, degree=7, n_steps=70, speed=speed, per_axis=per_axis,
-                seed=31 + dims)
     if precision == "fp32":
         w = w.rounded(np.float32)   # the values the FP32 path receives
-    print("case: polar", dims, speed, per_axis, precision, flush=True)
     rng = np.random.default_rng(5)
     xb = w.xi + rng.normal(size=w.xi.shape) * 0.4
     solver = tj.Solver.for_workload(w, precision=precision, sphere=False if per_axis else None)
@@ -84,13 +74,49 @@ def test_polar_variables_match_the_oracle(dims, speed, per_axis, precision):
     _, obs = tj.device_workload(w, dt, static=(speed == 0.0))
     al, be, d, kin = solver.polar(torch.as_tensor(xb, dtype=dt, device="cuda").contiguous(), obs)
     torch.cuda.synchronize()
-    al, be, d, kin = (x.double().cpu().numpy() for x in (al, be, d, kin))
-    n_pad = (w.n_steps + 63) // 64 * 64
-    assert al.shape == (5, 7, n_pad) and kin.shape == (5, 6, n_pad)
-    for arr in (al, be, d, kin):
-        assert not arr[..., w.n_steps:].any()       # padding entries are 0
+    B, n_pad = w.xi.shape[0], (w.n_steps + 63) // 64 * 64
+    kin = kin.double().cpu().numpy()
+    assert kin.shape == (B, 6, n_pad) and not kin[..., w.n_steps:].any()
+    if w.n_obs == 0:
+        assert al is None and be is None and d is None
+        al = be = d = np.zeros((B, 0, n_pad))
+    else:
+        al, be, d = (x.double().cpu().numpy() for x in (al, be, d))
+        assert al.shape == (B, w.n_obs, n_pad)
+        for arr in (al, be, d):
+            assert not arr[..., w.n_steps:].any()       # padding entries are 0
     _check(w, xb, al, be, d, kin, precision)
     solver.close()
+
+
+@pytest.mark.parametrize("dims,speed,per_axis,precision", [
+    (2, 0.5, False, "fp64"),   # moving circles
+    (3, 0.3, True, "fp64"),    # moving ellipsoids
+    (2, 0.0, True, "fp64"),    # static ellipses
+    (2, 0.5, False, "fp32"),
+    (3, 0.3, True, "fp32"),
+])
+def test_polar_variables_match_the_oracle(dims, speed, per_axis, precision):
+    w = wl.tiny(dims=dims, batch=5, n_obs=7, degree=7, n_steps=70, speed=speed, per_axis=per_axis,
+                seed=31 + dims)
+    print("case: polar", dims, speed, per_axis, precision, flush=True)
+    _run_case(w, precision, speed, per_axis)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_polar_ragged_row_passes_and_long_horizon(precision):
+    """150 steps (rows padded to 192, five rows to a 960-thread workgroup) and 19 moving
+    ellipsoids (four row passes, the last one partial), 3D, degree 9."""
+    w = wl.tiny(dims=3, batch=4, n_obs=19, degree=9, n_steps=150, speed=0.3, per_axis=True, seed=41)
+    print("case: polar ragged rows", precision, flush=True)
+    _run_case(w, precision, 0.3, True)
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_polar_without_obstacles_writes_the_kinematic_blocks(dims):
+    w = wl.tiny(dims=dims, batch=3, n_obs=0, degree=6, n_steps=40, seed=43)
+    print("case: polar no obstacles", dims, flush=True)
+    _run_case(w, "fp64", 0.0, False)
 
 
 def test_polar_config2_sampled_and_packed_obstacle_reuse():
