@@ -388,39 +388,47 @@ def cpu_baseline(w, iters: int, seconds: float = 8.0, seconds_1t: float = 2.0):
 def polar_bench(args):
     """The materialised polar variables (trajam_polar) at config-2 sizes: alpha, d (and
     beta = pi/2) for 1024 samples x 50 obstacles x 128 padded steps plus the kinematic
-    blocks, FP32; HBM-bound writes, reported against the 8 TB/s peak."""
+    blocks, FP32; HBM-bound writes, reported against the 8 TB/s peak and against a
+    plain fill of the same bytes, and again at batches 2048, 4096 and 8192."""
     import torch
     from paper_2408_10731_amd import trajam as tj
     from paper_2408_10731_amd import workloads as wl
 
-    w = wl.config2()
-    solver = tj.Solver.for_workload(w, precision="fp32")
-    xi, obs = tj.device_workload(w, torch.float32)
-    solver.set_obstacles(obs)
-    n_pad = (w.n_steps + 63) // 64 * 64
     kw = dict(dtype=torch.float32, device="cuda")
-    al, be, d = (torch.empty((w.batch, w.n_obs, n_pad), **kw) for _ in range(3))
-    kin = torch.empty((w.batch, 6, n_pad), **kw)
     st = torch.cuda.current_stream()
 
-    def run():
-        tj.trajam_polar(solver.handle, w.batch, xi.data_ptr(), None, None, None, al.data_ptr(),
-                        be.data_ptr(), d.data_ptr(), kin.data_ptr(), st.cuda_stream)
-    ms = _time(run, args.polar_steps, st)
-    written = 4 * (3 * al.numel() + kin.numel())
-    read = 4 * (xi.numel() + 3 * w.n_steps * 12)
-    solver.close()
-    gbs = (written + read) / (ms * 1e-3) / 1e9
-    # what a plain write stream of the same size reaches on this chip: torch's fill
-    # kernel over one buffer of the written byte count
-    buf = torch.empty(written // 4, **kw)
-    fill_ms = _time(lambda: buf.fill_(1.0), args.polar_steps, st)
-    del buf
-    fill_gbs = written / (fill_ms * 1e-3) / 1e9
-    return {"config": "config 2 sizes: 1024 samples x 50 obstacles x 128 padded steps + kinematic blocks, fp32",
-            "ms_per_call": ms, "bytes_per_call": written + read, "achieved_GBps": gbs,
-            "peak_GBps": 8000.0, "frac": gbs / 8000.0,
-            "fill_same_bytes_GBps": fill_gbs, "frac_of_fill": gbs / fill_gbs}
+    def measure(w):
+        solver = tj.Solver.for_workload(w, precision="fp32")
+        xi, obs = tj.device_workload(w, torch.float32)
+        solver.set_obstacles(obs)
+        n_pad = (w.n_steps + 63) // 64 * 64
+        al, be, d = (torch.empty((w.batch, w.n_obs, n_pad), **kw) for _ in range(3))
+        kin = torch.empty((w.batch, 6, n_pad), **kw)
+
+        def run():
+            tj.trajam_polar(solver.handle, w.batch, xi.data_ptr(), None, None, None, al.data_ptr(),
+                            be.data_ptr(), d.data_ptr(), kin.data_ptr(), st.cuda_stream)
+        ms = _time(run, args.polar_steps, st)
+        written = 4 * (3 * al.numel() + kin.numel())
+        read = 4 * (xi.numel() + 3 * w.n_steps * 12)
+        solver.close()
+        del al, be, d, kin
+        gbs = (written + read) / (ms * 1e-3) / 1e9
+        # what a plain write stream of the same size reaches on this chip: torch's fill
+        # kernel over one buffer of the written byte count
+        buf = torch.empty(written // 4, **kw)
+        fill_ms = _time(lambda: buf.fill_(1.0), args.polar_steps, st)
+        del buf
+        fill_gbs = written / (fill_ms * 1e-3) / 1e9
+        return {"ms_per_call": ms, "bytes_per_call": written + read, "achieved_GBps": gbs,
+                "peak_GBps": 8000.0, "frac": gbs / 8000.0,
+                "fill_same_bytes_GBps": fill_gbs, "frac_of_fill": gbs / fill_gbs}
+
+    out = {"config": "config 2 sizes: 1024 samples x 50 obstacles x 128 padded steps + kinematic blocks, fp32"}
+    out.update(measure(wl.config2()))
+    # the same geometry at larger batches: how much of a call is the launch's fixed cost
+    out["by_batch"] = [dict(batch=b, **measure(wl.problem2d(20240, 50, b))) for b in (2048, 4096, 8192)]
+    return out
 
 
 def main():
