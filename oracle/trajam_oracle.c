@@ -431,12 +431,18 @@ int orc_project(const orc_problem *pr, int B, const double *xi, const double *oc
         const double *x0 = xi + (size_t)i * D * nv;
         double *FtE = malloc(sizeof(double) * D * nv), *FtR = malloc(sizeof(double) * D * nv);
         double *rhs = malloc(sizeof(double) * N);
+        double *lm_old = malloc(sizeof(double) * D * nv);
         int k, ax, m;
         for (k = 0; k < iters; ++k) {
             double r2, rmax;
+            const double *lq = lm;
             polar_and_residual(&c, xb, FtE, FtR, &r2, &rmax);
             if (res_trace) res_trace[(size_t)k * B + i] = sqrt(r2);
             if (resmax_trace) resmax_trace[(size_t)k * B + i] = rmax;
+            if (g_fault == 8) {                                   /* planted: QP takes lambda^k */
+                memcpy(lm_old, lm, sizeof(double) * D * nv);
+                lq = lm_old;
+            }
             if (!freeze_lambda)
                 for (m = 0; m < D * nv; ++m) {
                     if (g_fault == 4) lm[m] += pr->rho * FtR[m];   /* planted: sign */
@@ -446,14 +452,14 @@ int orc_project(const orc_problem *pr, int B, const double *xi, const double *oc
                 for (m = 0; m < nv; ++m) {
                     double fe = pr->rho * FtE[ax * nv + m];
                     if (g_fault == 1) fe = -fe;                    /* planted: printed sign */
-                    rhs[m] = x0[ax * nv + m] + lm[ax * nv + m] + fe;
+                    rhs[m] = x0[ax * nv + m] + lq[ax * nv + m] + fe;
                 }
                 for (m = 0; m < 4; ++m) rhs[nv + m] = bnd[ax * 4 + m];
                 orc_lu_solve(N, K, piv, rhs);
                 for (m = 0; m < nv; ++m) xb[ax * nv + m] = rhs[m];
             }
         }
-        free(FtE); free(FtR); free(rhs);
+        free(FtE); free(FtR); free(rhs); free(lm_old);
     }
 done:
     free(P); free(Pd); free(Pdd); free(K); free(piv);
@@ -523,7 +529,7 @@ int orc_max_threads(void)
 
 /* ------------------------------------------------------------ multi-agent -- */
 /*
- * Joint projection of N agents (thesis ch. 8, Paper IV, in the projection form of
+ * Joint projection of N agents (thesis ch. 7, Paper IV, in the projection form of
  * ch. 6).  Each agent a has its own trajectory xi_a ([D][n_v]), its own boundary
  * rows, and the single-robot rows of the problem (every obstacle, velocity and
  * acceleration bounds).  In addition every unordered pair a < b and time t has the

@@ -414,6 +414,79 @@ def test_batch_and_thread_invariance():
     np.testing.assert_array_equal(a[0][:3], c[0])
 
 
+def _golden_two_iterates():
+    from fractions import Fraction
+    with open(os.path.join(GOLD, "am_two_iterates.json")) as f:
+        g = json.load(f)
+    pr = g["problem"]
+    w = wl.tiny(dims=2, batch=1, n_obs=1, degree=pr["degree"], n_steps=pr["n_steps"])
+    w.horizon = pr["horizon"]
+    w.v_max, w.a_max, w.rho = pr["v_max"], pr["a_max"], pr["rho"]
+    w.obs_centre = np.array(pr["obs_centre"], dtype=np.float64)
+    w.obs_axes = np.array(pr["obs_axes"], dtype=np.float64)
+    w.obs_vel = np.zeros((1, 2))
+    w.boundary = np.array(pr["boundary"], dtype=np.float64)
+    xi = np.zeros((1, 2, pr["degree"] + 1))
+    xi[0, 0] = pr["xi_x"]
+    w.xi = xi
+    fr = lambda v: float(Fraction(v))
+    return w, g, fr
+
+
+def test_two_iterates_golden_by_hand():
+    """The first two iterates of a tiny one-obstacle problem (degree 4, five time
+    samples, a point inside the circle at k = 0 and k = 1), worked by hand in exact
+    rational arithmetic: waypoints, residual, multiplier lambda^{k+1} = lambda^k - rho
+    F^T r^k (eq lag) and the QP taking that fresh multiplier (eqs affine_trans /
+    matrix_vec, the AM step list's order).  The QP's value with lambda^k instead is
+    recorded beside it and must not match."""
+    w, g, fr = _golden_two_iterates()
+    xb = w.xi.copy()
+    lam = np.zeros_like(xb)
+    P, _, _ = oracle.bernstein(w.degree, w.n_steps, w.horizon)
+    for it, want in enumerate(g["iterates"]):
+        np.testing.assert_allclose(P @ xb[0, 0], [fr(v) for v in want["waypoints_x"]],
+                                   atol=1e-14)
+        xb, lam, tr, _ = oracle.project(w, xi_bar=xb, lam=lam, iters=1)
+        assert abs(tr[0, 0] ** 2 - fr(want["residual_sq"])) <= 1e-14
+        np.testing.assert_allclose(xb[0, 0], [fr(v) for v in want["xi_bar_x"]], atol=1e-13)
+        np.testing.assert_allclose(lam[0, 0], [fr(v) for v in want["lambda_x"]], atol=1e-13)
+        assert np.abs(xb[0, 1]).max() < 1e-13 and np.abs(lam[0, 1]).max() < 1e-13
+        wrong = [fr(v) for v in g["wrong_order"][it]["xi_bar_x"]]
+        if it == 0:
+            assert abs(xb[0, 0, 3] - wrong[3]) > 1e-3
+    # the same two iterates in one call
+    xb2, lam2, tr2, _ = oracle.project(w, iters=2)
+    np.testing.assert_array_equal(xb2, xb)
+    np.testing.assert_array_equal(lam2, lam)
+
+
+def test_qp_stationarity_takes_fresh_multiplier():
+    """KKT stationarity of the QP of one iteration (eqs affine_trans / matrix_vec) with
+    the multiplier of eq lag from the same iteration: on the free coefficients, where
+    the boundary rows' A^T nu vanishes,
+        lambda^{k+1}_f = (xb^{k+1} - xi)_f + rho [F^T F xb^{k+1} - F^T e^{k+1}]_f,
+    with F stacked explicitly and F^T e^{k+1} = F^T F xb^k - F^T r^k taken from the
+    characterization of the polar projections (independent of the oracle's angle
+    form).  Starts from a non-zero multiplier and a state that meets the boundary."""
+    w = wl.tiny(dims=2, batch=2, n_obs=3, seed=9, n_steps=25)
+    P, Pd, Pdd = oracle.bernstein(w.degree, w.n_steps, w.horizon)
+    F = stacked_F(P, Pd, Pdd, w.n_obs)
+    FtF = F.T @ F
+    xb0, lam0, _, _ = oracle.project(w, iters=3)
+    assert np.abs(lam0).max() > 1e-3
+    xb1, lam1, _, _ = oracle.project(w, xi_bar=xb0, lam=lam0, iters=1)
+    free = list(range(3, w.degree))
+    for i in range(w.batch):
+        ftr0 = _algebraic_residual_products(w, xb0[i])
+        assert np.abs(ftr0).max() > 1e-3
+        for ax in range(w.dims):
+            fte1 = FtF @ xb0[i, ax] - ftr0[ax]
+            stat = (xb1[i, ax] - w.xi[i, ax]) + w.rho * (FtF @ xb1[i, ax] - fte1)
+            np.testing.assert_allclose(lam1[i, ax, free], stat[free], atol=1e-10)
+            np.testing.assert_allclose(lam1[i, ax], lam0[i, ax] - w.rho * ftr0[ax], atol=1e-10)
+
+
 # ------------------------------------------------------------- mutation tests
 
 
@@ -424,19 +497,34 @@ def _pins_pass():
         test_multiplier_telescopes()
         test_polar_circle_is_exact_projection_bruteforce()
         test_worked_case_residual_non_increasing_and_small()
+        test_two_iterates_golden_by_hand()
+        test_qp_stationarity_takes_fresh_multiplier()
     except AssertionError:
         return False
     return True
 
 
-@pytest.mark.parametrize("fault", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("fault", [1, 2, 3, 4, 5, 8])
 def test_planted_mistakes_are_caught(fault):
     """Each plausible mistake (printed sign of rho F^T e, a dropped kinematic term,
-    reversed basis columns, a flipped multiplier sign, a dropped d >= 1 bound) planted
-    in the oracle makes at least one pin fail."""
+    reversed basis columns, a flipped multiplier sign, a dropped d >= 1 bound, the QP
+    taking lambda^k instead of the fresh lambda^{k+1}) planted in the oracle makes at
+    least one pin fail."""
     assert _pins_pass()
     oracle.set_fault(fault)
     try:
         assert not _pins_pass()
+    finally:
+        oracle.set_fault(0)
+
+
+def test_stale_multiplier_fault_is_caught_by_the_order_pins():
+    """The step-order mistake (the QP reads lambda^k) passes the older pins, so each of
+    the two order pins must catch it on its own."""
+    oracle.set_fault(8)
+    try:
+        for pin in (test_two_iterates_golden_by_hand, test_qp_stationarity_takes_fresh_multiplier):
+            with pytest.raises(AssertionError):
+                pin()
     finally:
         oracle.set_fault(0)
