@@ -25,11 +25,18 @@ import numpy as np
 
 
 def to_bf16(a):
-    """Round float64 values to the nearest bfloat16 (ties to even), as float64."""
+    """Round values to the nearest bfloat16 (ties to even), returned as float64.
+
+    bfloat16 is the upper half of an IEEE binary32 word, so rounding to nearest even
+    adds 0x7FFF plus the lowest kept bit to the word and drops the low 16 bits; a
+    finite value that rounds past the largest bfloat16 becomes infinity.  A NaN stays
+    a NaN (the carry must not run into its exponent).  Float64 input is first
+    rounded to float32, which is what the kernels hold before their conversion."""
     f = np.asarray(a, dtype=np.float32)
     u = f.view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+    out = u.astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(np.isnan(f), np.nan, out)
 
 
 def _mm(a, b, bf16):

@@ -22,9 +22,11 @@ constexpr int BM = 64, BN = 64, BK = 16;
 typedef short mlp_bf16x4 __attribute__((ext_vector_type(4)));
 typedef float mlp_f32x4 __attribute__((ext_vector_type(4)));
 
+// Round to nearest even; a NaN stays a (quiet) NaN instead of carrying into the sign.
 __device__ __forceinline__ short to_bf16(float x)
 {
     unsigned u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (short)((u >> 16) | 0x40u);
     u += 0x7fffu + ((u >> 16) & 1u);
     return (short)(u >> 16);
 }

@@ -288,6 +288,7 @@ uint16_t bf16_bits(float x)
 {
     uint32_t u;
     std::memcpy(&u, &x, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // NaN stays NaN
     const uint32_t lsb = (u >> 16) & 1u;
     u += 0x7fffu + lsb;  // round to nearest even
     return (uint16_t)(u >> 16);

@@ -268,10 +268,15 @@ def test_gpu_warm_features_apply_and_fallback():
 @pytest.mark.gpu
 def test_gpu_trained_warm_start_gains_over_cold_start():
     """Trained on solver-generated pairs of the 2D 50-circle family (scene seeds
-    disjoint from the held-out ones), the probe-and-jump warm start reaches the
-    batch-median residual 1e-3 in fewer AM iterations (probe included) than the cold
-    start on held-out scenes, summed over the scenes and on most of them; the oracle
-    recomputes the final residuals from the device result."""
+    10,000+, disjoint from the held-out ones), the probe-and-jump warm start against the
+    cold start on a held-out set fixed in advance: the first 16 scene seeds from 90,001,
+    none skipped.  Per scene, each arm's iterations to a batch-median residual <= 1e-3
+    (probe included) and its wall time for exactly those iterations (probe, features,
+    network, jump and check included) are measured; an arm that never reaches the
+    tolerance within K = 200 iterations is charged K iterations and the time of K.
+    The warm start must need fewer iterations and less wall time in total and fewer
+    iterations on most scenes; every scene, including losses, is printed.  The
+    oracle recomputes the warm arm's final residuals from the device result."""
     from paper_2408_10731_amd import trajam as tj, warmstart as ws
     fam = ws.family_scene("cfg2")
     data = ws.generate(fam, np.arange(10_000, 11_024), 64, k0=ws.K0, cap=150)
@@ -282,8 +287,20 @@ def test_gpu_trained_warm_start_gains_over_cold_start():
     print("  loss", [round(c, 5) for c in curve[::4]], flush=True)
     assert curve[-1] < 0.5 * curve[0]
     K = 200
-    cold_tot = warm_tot = wins = 0
-    seeds = (90_001, 90_002, 90_004, 90_006, 90_008)
+    seeds = list(range(90_001, 90_017))
+    it_c = it_w = 0
+    t_c = t_w = 0.0
+    wins = 0
+
+    def timed(fn):
+        fn()   # untimed pass (first-launch effects)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
     for seed in seeds:
         w = fam(seed, 1024)
         solver = tj.Solver.for_workload(w, precision="fp32")
@@ -298,15 +315,52 @@ def test_gpu_trained_warm_start_gains_over_cold_start():
         torch.cuda.synchronize()
         ic = ws.iterations_to(trc.cpu().numpy())
         iw = ws.iterations_to(np.concatenate([trp.cpu().numpy(), trw.cpu().numpy()]))
-        fb = int((fl.cpu().numpy() & 4).astype(bool).sum())
-        print(f"  scene {seed}: cold {ic} iterations, warm {iw}, fallbacks {fb}", flush=True)
-        assert ic is not None and iw is not None
-        cold_tot += ic
-        warm_tot += iw
-        wins += iw < ic
         r_final = oracle.residuals(w.rounded(np.float32), xw.double().cpu().numpy())[0]
-        assert np.median(r_final) <= 1e-3
+        ic = K if ic is None else ic
+        iw = K if iw is None else iw
+        fb = int((fl.cpu().numpy() & 4).astype(bool).sum())
+
+        def cold():
+            xb.copy_(xi)
+            lam.zero_()
+            solver.project(xi, w.boundary, obs, xb, lam, ic)
+
+        def warm():
+            x2, l2, _, _ = ctx.run(xi, w.boundary, obs)
+            if iw > ws.K0:
+                solver.project(xi, w.boundary, obs, x2, l2, iw - ws.K0)
+
+        tc, tw = timed(cold), timed(warm)
+        print(f"  scene {seed}: cold {ic} it {tc:.3f} ms, warm {iw} it {tw:.3f} ms, "
+              f"fallbacks {fb}, oracle final median residual (warm) {np.median(r_final):.1e}"
+              + ("" if iw < ic else "  <- warm not fewer"), flush=True)
+        it_c += ic
+        it_w += iw
+        t_c += tc
+        t_w += tw
+        wins += iw < ic
         solver.close()
-    print(f"  total: cold {cold_tot}, warm {warm_tot} iterations; warm fewer on {wins} of "
-          f"{len(seeds)} scenes", flush=True)
-    assert warm_tot < cold_tot and wins > len(seeds) // 2
+    print(f"  total over {len(seeds)} scenes: cold {it_c} it {t_c:.3f} ms, warm {it_w} it "
+          f"{t_w:.3f} ms; warm fewer iterations on {wins}", flush=True)
+    assert it_w < it_c and t_w < t_c and wins > len(seeds) // 2
+
+
+def test_oracle_bf16_rounding_matches_torch():
+    """Pins oracle.mlp.to_bf16 against torch's float32 -> bfloat16 conversion on the CPU
+    (round to nearest even) over 2e6 random bit patterns -- every exponent, subnormals,
+    negatives, infinities and NaNs -- plus exact ties of both parities, the largest
+    finite float32 (rounds to infinity) and signed zeros."""
+    import torch
+    rng = np.random.default_rng(20240810)
+    bits = rng.integers(0, 2 ** 32, size=2_000_000, dtype=np.uint64).astype(np.uint32)
+    ties = (rng.integers(0, 2 ** 16, size=200_000, dtype=np.uint64).astype(np.uint32) << 16) | 0x8000
+    special = np.array([0x00000000, 0x80000000, 0x7F800000, 0xFF800000, 0x7F7FFFFF, 0xFF7FFFFF,
+                        0x00000001, 0x80008000, 0x00018000, 0x7FC00000, 0x7FFFFFFF, 0xFFFFFFFF,
+                        0x3F808000, 0x3F818000, 0x3F807FFF, 0x3F808001], dtype=np.uint32)
+    f = np.concatenate([bits, ties, special]).view(np.float32)
+    want = torch.from_numpy(f.copy()).to(torch.bfloat16).to(torch.float32).numpy()
+    got = omlp.to_bf16(f).astype(np.float32)
+    nan = np.isnan(want)
+    assert np.array_equal(np.isnan(got), nan)
+    assert np.array_equal(got[~nan].view(np.uint32), want[~nan].view(np.uint32))
+    assert ties.size == 200_000 and np.isinf(omlp.to_bf16(np.float32(3.4028235e38)))
