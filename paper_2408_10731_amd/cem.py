@@ -66,7 +66,7 @@ class Planner:
                              self.caug.data_ptr(), self.sigma, self.gamma, self.mu.data_ptr(),
                              self.Sigma.data_ptr(), self.chol.data_ptr(), st)
         if record is not None:
-            record[-1] = record[-1] + (self.mu.clone(), self.Sigma.clone())
+            record[-1] = record[-1] + (self.mu.clone(), self.Sigma.clone(), self.xb.clone())
 
     def autotune(self, z0, boundary, obs):
         """Pick the projection's launch shape for this planner's batch: draws one batch

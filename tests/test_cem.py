@@ -96,6 +96,62 @@ def test_cem_oracle_improves_cost_on_a_free_scene():
     assert np.all(np.linalg.eigvalsh(tr.Sigma[-1]) > 0)
 
 
+def _accel_cost_by_hodograph(w, xb):
+    """c_1 by the second hodograph: x''(t) = n(n-1)/T^2 sum_m (xi_{m+2} - 2 xi_{m+1} + xi_m)
+    B_{m,n-2}(t/T), evaluated by de Casteljau (no basis matrix)."""
+    n, T = w.degree, w.horizon
+    taus = np.arange(w.n_steps) / (w.n_steps - 1)
+    d2 = (xb[..., 2:] - 2 * xb[..., 1:-1] + xb[..., :-2]) * n * (n - 1) / T ** 2
+    out = np.zeros(xb.shape[0])
+    for tau in taus:
+        b = d2.copy()
+        while b.shape[-1] > 1:
+            b = (1 - tau) * b[..., :-1] + tau * b[..., 1:]
+        out += np.sum(b[..., 0] ** 2, axis=1)
+    return out
+
+
+def test_cem_loop_matches_an_independent_composition():
+    """Alg 3's loop wiring, pinned by a second route through every step: samples from
+    scipy's Cholesky factor, projection and residual by the (separately pinned) C oracle,
+    the acceleration cost by the second hodograph, both selections by Python's sort of
+    (residual key, c_aug, index) and (c_aug, index) tuples, and the covariance update
+    from numpy's weighted covariance about the weighted mean moved to the new mean by
+    the parallel-axis identity.  Catches a wrong index set in any step, the update
+    reading the samples instead of their projections, or a wrong returned trajectory."""
+    import scipy.linalg
+    w, mu0, S0 = cem_problem(n_obs=6, seed=13)
+    D, nv = w.dims, w.n_v
+    N_b, n_proj, n_elite, K, sig, gam, q = 40, 30, 8, 3, 0.5, 1.0, 1e-6
+    z = np.random.default_rng(17).normal(size=(3, N_b, mu0.size))
+    tr = ocem.cem(w, mu0, S0, z, am_iters=K, n_proj=n_proj, n_elite=n_elite, sigma=sig,
+                  gamma=gam, quantum=q)
+    mu, S = mu0.copy(), S0.copy()
+    for l in range(z.shape[0]):
+        L = scipy.linalg.cholesky(S + ocem.EPS_CHOL * np.eye(S.shape[0]), lower=True)
+        xi = (mu[None] + z[l] @ L.T).reshape(-1, D, nv)
+        xb, _, _, _ = oracle.project(w, iters=K, xi=xi)
+        r, _ = oracle.residuals(w, xb)
+        caug = _accel_cost_by_hodograph(w, xb) + r
+        np.testing.assert_allclose(tr.caug[l], caug, rtol=1e-11, atol=1e-11)
+        proj = sorted(range(N_b), key=lambda i: (np.floor(r[i] / q), caug[i], i))[:n_proj]
+        elite = sorted(proj, key=lambda i: (caug[i], i))[:n_elite]
+        assert list(tr.proj_idx[l]) == proj
+        assert list(tr.elite_idx[l]) == elite
+        X = xb.reshape(N_b, -1)[elite]
+        c = caug[elite]
+        wgt = np.exp(-(c - c.min()) / (gam * c.std()))
+        mean_w = np.average(X, axis=0, weights=wgt)
+        mu = (1 - sig) * mu + sig * mean_w
+        cov_w = np.cov(X.T, aweights=wgt, bias=True)
+        off = mean_w - mu
+        S = (1 - sig) * S + sig * (cov_w + np.outer(off, off))
+        np.testing.assert_allclose(tr.mu[l], mu, atol=1e-12)
+        np.testing.assert_allclose(tr.Sigma[l], S, atol=1e-12)
+    np.testing.assert_allclose(tr.best, xb[elite[0]], atol=1e-10)
+    assert abs(tr.best_cost - caug[elite[0]]) < 1e-10
+
+
 # -------------------------------------------------------------------- GPU parity
 
 torch = pytest.importorskip("torch")
@@ -191,7 +247,7 @@ def test_gpu_cem_fp64_matches_oracle_per_iteration():
     rec = []
     best = planner.run(torch.as_tensor(z, device="cuda"), w.boundary, obs, record=rec)
     torch.cuda.synchronize()
-    for l, (proj, elite, res, caug, rkey, mu, Sig) in enumerate(rec):
+    for l, (proj, elite, res, caug, rkey, mu, Sig, _) in enumerate(rec):
         assert np.array_equal(proj.cpu().numpy(), tr.proj_idx[l]), l
         assert np.array_equal(elite.cpu().numpy(), tr.elite_idx[l]), l
         np.testing.assert_allclose(res.cpu().numpy(), tr.res[l], atol=1e-9)
@@ -223,7 +279,8 @@ def test_gpu_cem_fp32_config4_graph_replays():
     rec = []
     eager = planner.run(z, w.boundary, obs, record=rec).clone()
     torch.cuda.synchronize()
-    for proj, elite, res, caug, rkey, mu, Sig in rec:
+    mu_prev, S_prev = mu0, S0
+    for proj, elite, res, caug, rkey, mu, Sig, xb in rec:
         c, k = caug.cpu().numpy(), rkey.cpu().numpy()
         p = proj.cpu().numpy()
         e = elite.cpu().numpy()
@@ -231,9 +288,18 @@ def test_gpu_cem_fp32_config4_graph_replays():
         exp_p = ocem.select((k, c), Np)
         assert np.array_equal(p, exp_p)
         assert np.array_equal(e, p[ocem.select((c[p], p), Ne)])
-    # the distribution update agrees with the FP64 formula on the device's elite set
-    proj, elite, res, caug, rkey, mu, Sig = rec[0]
-    xb0 = None
+        # the distribution update agrees with the FP64 formula on the device's elite set
+        # (inputs: the float values the device held before this update)
+        X = xb.cpu().numpy().astype(np.float64).reshape(Nb, -1)
+        mu1, S1, _ = ocem.weighted_update(mu_prev, S_prev, X[e], c[e].astype(np.float64), 0.5, 1.0)
+        np.testing.assert_allclose(mu.cpu().numpy(), mu1, rtol=1e-5, atol=2e-4)
+        np.testing.assert_allclose(Sig.cpu().numpy(), S1, rtol=1e-5, atol=2e-4)
+        mu_prev = mu.cpu().numpy().astype(np.float64)
+        S_prev = Sig.cpu().numpy().astype(np.float64)
+    # the returned trajectory is the lowest-cost elite of the last iteration
+    c_last, e_last, xb_last = rec[-1][3].cpu().numpy(), rec[-1][1].cpu().numpy(), rec[-1][7]
+    assert c_last[e_last[0]] == c_last[e_last].min()
+    assert torch.equal(eager, xb_last[int(e_last[0])])
     eager_mu = rec[-1][5].cpu().numpy()
     planner.set_distribution(mu0, S0, L0)
     planner.capture(z, w.boundary, obs)
