@@ -90,7 +90,7 @@ typedef struct {
     double rho;            /* augmented-Lagrangian weight, > 0 */
     int32_t n_obstacles;   /* n_o >= 0; each obstacle adds one copy of P to F */
     int32_t n_agents;      /* 1 (single robot) or N in [2, 64] agents planned jointly
-                              (thesis ch. 8): each agent has every single-robot row and
+                              (thesis ch. 7, Paper IV): each agent has every single-robot row and
                               every unordered pair of agents adds one row per time
                               sample keeping them 2 * agent_radius apart; needs
                               precision FP64 or FP32 and degree <= 11 */

@@ -1544,7 +1544,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_wave_kernel(AmArgs<T> a)
 }
 
 // ----------------------------------------------------------------------------
-// Multi-agent joint projection (thesis ch. 8 in the projection form of ch. 6).
+// Multi-agent joint projection (thesis ch. 7, Paper IV, in the projection form of ch. 6).
 // One wave per joint sample, lane a = agent a: each lane keeps its agent's
 // coefficients, multiplier and F^T r in registers and walks the time samples; the
 // basis rows and the obstacles are wave-uniform (scalar loads), and the other
@@ -1977,9 +1977,12 @@ __global__ __launch_bounds__(kMaxThreads) void am_residual_kernel(AmArgs<T> a)
 // Angle and norm of the materialised polar variables.  FP32: atan2 from the ratio of
 // the smaller to the larger magnitude (in [0, 1]), its arctangent by an odd polynomial
 // a P(a^2) whose coefficients were fitted for this kernel (least squares on Chebyshev
-// nodes reweighted towards equal ripple on [0, 1]; largest error 1.4e-7 rad in float
-// arithmetic), then the octant and quadrant corrections, atan2(0, 0) = 0; the square
-// root is the hardware one (1 ulp).  FP64: the library functions.
+// nodes reweighted towards equal ripple on [0, 1]; in float arithmetic the largest
+// error on [0, 1] is 1.3e-7 rad with a correctly rounded reciprocal and 1.9e-7 with
+// the hardware reciprocal's 1-ulp error), then the octant and quadrant corrections
+// (rounding pi - r to float: at most 3.7e-7 rad over the whole circle),
+// atan2(0, 0) = 0; the square root is the hardware one (1 ulp).  FP64: the library
+// functions.
 __device__ __forceinline__ float polar_atan2(float y, float x)
 {
     const float ax = fabsf(x), ay = fabsf(y);

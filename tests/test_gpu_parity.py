@@ -96,6 +96,32 @@ def test_fp64_config1_full_run():
     assert np.abs(r_g - r_o).max() <= 1e-9
 
 
+def test_fp64_config2_full_size_every_iterate():
+    """Config 2 at its full size (2D, degree 10, 100 steps over 30 s, 50 circles,
+    B = 1024) in FP64: all 50 iterates, one call at a time, each against the oracle's
+    iterate; then the same 50 iterations in one launch (trace and final state)."""
+    w = dataclasses.replace(wl.config2(), precision="fp64")
+    say("case: cfg2 fp64 per-iterate, B", w.batch, "K", w.iters)
+    xb_o, lam_o = w.xi.copy(), np.zeros_like(w.xi)
+    xb_g, lam_g = w.xi.copy(), np.zeros_like(w.xi)
+    traces = []
+    worst = 0.0
+    for k in range(w.iters):
+        xb_o, lam_o, tr_o, _ = oracle.project(w, xi_bar=xb_o, lam=lam_o, iters=1)
+        xb_g, lam_g, tr_g, _ = run_gpu(w, 1, xi_bar=xb_g, lam=lam_g)
+        err = max(np.abs(xb_g - xb_o).max(), np.abs(lam_g - lam_o).max(),
+                  np.abs(tr_g - tr_o).max())
+        worst = max(worst, err)
+        assert err <= 1e-9, (k, err)
+        traces.append(tr_o[0])
+    say(f"  worst per-iterate error {worst:.2e}")
+    xb_1, lam_1, tr_1, fl = run_gpu(w, w.iters)
+    assert np.abs(tr_1 - np.array(traces)).max() <= 1e-9
+    assert np.abs(xb_1 - xb_o).max() <= 1e-9
+    assert np.abs(lam_1 - lam_o).max() <= 1e-9
+    assert not np.any(fl & 1)
+
+
 @pytest.mark.parametrize("dims,degree,n_steps,n_obs,batch,speed,per_axis", [
     (2, 5, 9, 2, 3, 0.0, False),      # nvp 8, one partial wave
     (2, 7, 64, 3, 5, 0.5, False),     # exactly one wave, moving obstacles

@@ -1,5 +1,5 @@
 """Pins of the multi-agent oracle (joint projection of N agents with pairwise
-avoidance, thesis ch. 8 in the projection form of ch. 6), each independent of the
+avoidance, thesis ch. 7 (Paper IV) in the projection form of ch. 6), each independent of the
 oracle's joint assembly:
 
 * N = 1 is the single-robot oracle;

@@ -126,6 +126,49 @@ def test_ragged_oracle_parity():
     S.close()
 
 
+def test_ragged_config5_shapes_sampled_oracle_parity():
+    """The largest shapes of the ragged set in one plan: a 2D problem with 300 circles
+    and 2048 samples and a 3D joint problem with 64 agents and 300 spheres (64 joint
+    samples), 50 iterations.  Sampled samples of the full launch against the FP64
+    oracle: final waypoints within 1e-3 m, the residual the oracle recomputes from the
+    GPU's coefficients within 1e-4 of its own, boundary rows within 1e-5 (FP32 state)."""
+    import dataclasses
+    iters = 50
+    w2 = wl.problem2d(5002, 300, 2048, iters).rounded(np.float32)
+    wa = wl.agents3d(5001, 64, 300, 64, iters).rounded(np.float32)
+    say("case: ragged config-5 shapes: 2D n_o 300 B 2048; 3D N 64 n_o 300 B 64")
+    S = Set([w2, wa], iters)
+    plan = S.plan()
+    S.reset()
+    plan.launch()
+    (xb2, _, _), (xba, _, _) = S.results()
+    plan.close()
+    S.close()
+    P, _, _ = oracle.bernstein(w2.degree, w2.n_steps, w2.horizon)
+    idx = np.arange(3, 2048, 128)
+    xo, _, _, _ = oracle.project(w2, iters=iters, xi=w2.xi[idx])
+    ws = w2.subset(2048)
+    ws = dataclasses.replace(ws, xi=np.ascontiguousarray(w2.xi[idx]))
+    wp = np.abs(np.einsum("tm,bdm->btd", P, xb2[idx] - xo)).max()
+    dr = np.abs(oracle.residuals(ws, xb2[idx])[0] - oracle.residuals(ws, xo)[0]).max()
+    say(f"  2D, {idx.size} samples: waypoint err {wp:.2e} m, residual err {dr:.2e}")
+    assert wp <= 1e-3 and dr <= 1e-4
+    for ax in range(2):
+        assert np.abs(xb2[idx, ax, 0] - w2.boundary[ax, 0]).max() <= 1e-5
+        assert np.abs(xb2[idx, ax, -1] - w2.boundary[ax, 3]).max() <= 1e-5
+    ida = np.arange(5, 64, 8)
+    wsa = dataclasses.replace(wa, xi=np.ascontiguousarray(wa.xi[ida]))
+    xoa, _, _, _ = oracle.project_agents(wsa, iters=iters)
+    P, _, _ = oracle.bernstein(wa.degree, wa.n_steps, wa.horizon)
+    wp = np.abs(np.einsum("tm,badm->batd", P, xba[ida] - xoa)).max()
+    dr = np.abs(oracle.residuals_agents(wsa, xba[ida])[0] - oracle.residuals_agents(wsa, xoa)[0]).max()
+    say(f"  3D 64 agents, {ida.size} joint samples: waypoint err {wp:.2e} m, residual err {dr:.2e}")
+    assert wp <= 1e-3 and dr <= 1e-4
+    for a in range(wa.n_agents):
+        assert np.abs(xba[ida, a, :, 0] - wa.boundary[a, :, 0]).max() <= 1e-5
+        assert np.abs(xba[ida, a, :, -1] - wa.boundary[a, :, 3]).max() <= 1e-5
+
+
 def test_ragged_graph_replays_match_eager():
     ws = _mixed(12, 99, (5, 60), (16, 200), iters=20)
     say("case: ragged graph capture,", len(ws), "problems")
