@@ -2083,11 +2083,14 @@ __global__ __launch_bounds__(1024) void am_polar_kernel(AmArgs<T> a, T *__restri
         T al = T(0), be = T(0), dd = T(0);
         if (live_t) {
             T u[D], nn = T(0);
+            // the sphere model scales every axis by 1 / radius (the first semi-axis; the
+            // caller's other entries are ignored and may be anything, zero included)
+            const int sc = a.sphere ? 0 : 1;
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) {
                 // c(t) = c + velocity t; the record holds -velocity and 1 / semi-axis
                 const T xt = fma(o[kOW + ax], tt, pt[ax] - o[kOC + ax]);
-                u[ax] = xt * o[kOI + ax];
+                u[ax] = xt * o[kOI + sc * ax];
                 nn = fma(u[ax], u[ax], nn);
             }
             al = polar_atan2(u[1], u[0]);

@@ -141,3 +141,38 @@ def test_polar_config2_sampled_and_packed_obstacle_reuse():
                        rng.integers(0, w.n_steps, 300)))
     _check(w, xb.double().cpu().numpy(), al, be, d, kin, "fp32", entries)
     solver.close()
+
+
+@pytest.mark.parametrize("dims,other,precision", [(2, "zero", "fp64"), (3, "random", "fp64"),
+                                                  (3, "zero", "fp32")])
+def test_polar_sphere_model_ignores_other_semi_axes(dims, other, precision):
+    """Sphere model: only obs_axes[j][0] (the radius) is read; the other entries may be
+    zero or anything else and the polar variables are those of the sphere, the same as
+    the projection uses.  Compared with the oracle on the true spheres, and bitwise
+    with a call whose other entries equal the radius."""
+    from paper_2408_10731_amd import trajam as tj
+    w = wl.tiny(dims=dims, batch=4, n_obs=6, degree=7, n_steps=70, speed=0.4, seed=47 + dims)
+    if precision == "fp32":
+        w = w.rounded(np.float32)
+    print("case: polar sphere model", dims, other, precision, flush=True)
+    solver = tj.Solver.for_workload(w, precision=precision, sphere=True)
+    dt = solver.dtype
+    rng = np.random.default_rng(9)
+    xb = w.xi + rng.normal(size=w.xi.shape) * 0.4
+    if precision == "fp32":
+        xb = xb.astype(np.float32).astype(np.float64)
+    xbd = torch.as_tensor(xb, dtype=dt, device="cuda").contiguous()
+    _, (c, v, a) = tj.device_workload(w, dt, static=False)
+    a_odd = a.clone()
+    a_odd[:, 1:] = 0.0 if other == "zero" else torch.as_tensor(
+        rng.uniform(0.05, 3.0, size=(w.n_obs, dims - 1)), dtype=dt, device="cuda")
+    ref = solver.polar(xbd, (c, v, a))
+    ref = tuple(x.clone() for x in ref)
+    got = solver.polar(xbd, (c, v, a_odd))
+    torch.cuda.synchronize()
+    for x1, x2 in zip(ref, got):
+        assert torch.equal(x1, x2)
+    al, be, d, kin = (x.double().cpu().numpy() for x in got)
+    assert np.all(np.isfinite(al)) and np.all(np.isfinite(d))
+    _check(w, xb, al, be, d, kin, precision)
+    solver.close()
