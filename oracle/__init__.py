@@ -50,9 +50,14 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = ctypes.CDLL(_LIB)
+        # TRAJAM_ORACLE_LIB: a separately built copy of this oracle (the sanitizer test's
+        # instrumented build), loaded as it is
+        path = os.environ.get("TRAJAM_ORACLE_LIB")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         pp = ctypes.POINTER(Problem)
         L.orc_bernstein.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp, dp]

@@ -114,9 +114,12 @@ def load():
         import torch  # noqa: F401  -- HIP runtime of the process comes from torch
     except ImportError:
         pass
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
-    L = ctypes.CDLL(LIB_PATH)
+    # TRAJAM_LIBRARY: another build of this library (the sanitizer test's instrumented
+    # host code); the in-tree build otherwise
+    path = os.environ.get("TRAJAM_LIBRARY") or LIB_PATH
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() first")
+    L = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     dp = ctypes.POINTER(ctypes.c_double)
     L.trajam_init.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(vp)]
