@@ -383,6 +383,23 @@ trajam_status trajam_mlp_backward(const trajam_mlp_shape *shape, int32_t batch, 
                                   const float *params, const float *x, const float *acts,
                                   const float *dy, float *grads, float *scratch, void *stream);
 
+/* trajam_mlp_backward without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving or training loops, harnesses that forbid hipMalloc).  The two input-gradient
+ * buffers live in a static per-device array of TRAJAM_MLP_NOALLOC_SCRATCH_FLOATS floats
+ * (8 MiB) that the library holds on every GPU it runs on until the process ends; its
+ * device address is looked up on the first call on each device.  Every call on one GPU
+ * shares that array, so calls that overlap in time on one GPU (two streams, two host
+ * threads) race and must be serialized by the caller; a later call may overwrite what
+ * an earlier one left there (nothing in it is meant to outlive a call).  Same arguments,
+ * results and errors as trajam_mlp_backward, plus CAPACITY when 2 * batch * (largest
+ * hidden width) exceeds TRAJAM_MLP_NOALLOC_SCRATCH_FLOATS (for a single-layer network
+ * no workspace is needed). */
+#define TRAJAM_MLP_NOALLOC_SCRATCH_FLOATS 2097152
+trajam_status trajam_mlp_backward_noalloc(const trajam_mlp_shape *shape, int32_t batch, int32_t precision,
+                                          const float *params, const float *x, const float *acts,
+                                          const float *dy, float *grads, void *stream);
+
 /* Mean squared error over count values: loss[0] = mean (y - t)^2, dy = 2 (y - t) / count.
  * Errors: INVALID, DEVICE. */
 trajam_status trajam_mlp_mse(int64_t count, const float *y, const float *target, float *dy,

@@ -125,6 +125,9 @@ hipError_t launch_mlp_infer(int n_layers, const int *width, int batch, const flo
 hipError_t launch_mlp_pack_infer(int n_layers, const int *width, const float *params, float *packed, hipStream_t st);
 hipError_t launch_warm_fallback(int batch, int dim, const float *rw, const float *rc, const float *xs,
                                 const float *ls, float *xb, float *lam, uint32_t *flags, hipStream_t st);
+// Device address (on the current device) and size in floats of the backward pass's
+// static workspace; looked up once per device.
+hipError_t noalloc_scratch(float **ptr, size_t *n_floats);
 
 // Ragged persistent launch (FP32): zeroes the counter, then runs the work queue.
 hipError_t launch_ragged(const AmArgs<float> *probs, const int *offsets, int n_probs, int total, int *counter,

@@ -148,6 +148,30 @@ extern "C" trajam_status trajam_mlp_backward(const trajam_mlp_shape *s, int32_t 
     return TRAJAM_OK;
 }
 
+extern "C" trajam_status trajam_mlp_backward_noalloc(const trajam_mlp_shape *s, int32_t batch,
+                                                     int32_t precision, const float *params,
+                                                     const float *x, const float *acts, const float *dy,
+                                                     float *grads, void *stream)
+{
+    if (!shape_ok(s)) return fail(TRAJAM_ERR_INVALID, "invalid network shape");
+    if (batch < 1 || (precision != 0 && precision != 1)) return fail(TRAJAM_ERR_INVALID, "batch >= 1, precision 0 or 1");
+    int64_t maxw = 1;
+    for (int l = 1; l < s->n_layers; ++l) maxw = std::max<int64_t>(maxw, s->width[l]);
+    const int64_t need = s->n_layers > 1 ? 2 * (int64_t)batch * maxw : 0;
+    if (need > (int64_t)TRAJAM_MLP_NOALLOC_SCRATCH_FLOATS)
+        return fail(TRAJAM_ERR_CAPACITY, "mlp backward without allocation: 2 * batch * largest hidden width = " +
+                                             std::to_string(need) + " floats exceeds the static workspace of " +
+                                             std::to_string((int64_t)TRAJAM_MLP_NOALLOC_SCRATCH_FLOATS));
+    float *ws = nullptr;
+    size_t cap = 0;
+    trajam_status r = dev(trajam::noalloc_scratch(&ws, &cap), "mlp backward workspace address");
+    if (r != TRAJAM_OK) return r;
+    if ((int64_t)cap < (int64_t)TRAJAM_MLP_NOALLOC_SCRATCH_FLOATS)
+        return fail(TRAJAM_ERR_DEVICE, "mlp backward workspace smaller than declared");
+    // the kernels write every workspace entry they read, so nothing needs clearing
+    return trajam_mlp_backward(s, batch, precision, params, x, acts, dy, grads, ws, stream);
+}
+
 extern "C" trajam_status trajam_mlp_mse(int64_t count, const float *y, const float *t, float *dy, float *loss,
                                         void *stream)
 {

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "am_internal.h"
 
 namespace trajam {
@@ -448,6 +450,37 @@ hipError_t launch_warm_fallback(int batch, int dim, const float *rw, const float
     hipLaunchKernelGGL(warm_fallback_kernel, dim3((batch + 3) / 4), dim3(256), 0, st, batch, dim, rw, rc, xs, ls, xb,
                        lam, flags);
     return hipGetLastError();
+}
+
+// Workspace of trajam_mlp_backward_noalloc: the two ping-pong buffers of the input
+// gradients, in a file-scope device array instead of caller memory, for callers that
+// cannot allocate.  Every GPU the library runs on holds its own copy until the process
+// ends.  In host code `scratch` names a host-side stand-in, so the device address is
+// looked up once per device (with that device current) and only that address is ever
+// passed to kernels.
+constexpr size_t kNoallocScratchFloats = size_t(1) << 21;  // 8 MiB
+static __device__ __align__(256) float scratch[kNoallocScratchFloats];
+
+hipError_t noalloc_scratch(float **ptr, size_t *n_floats)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static float *dev_ptr[kMaxDevices] = {};
+    int d = -1;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return e;
+    if (d < 0 || d >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!dev_ptr[d]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        dev_ptr[d] = static_cast<float *>(p);
+    }
+    *ptr = dev_ptr[d];
+    *n_floats = kNoallocScratchFloats;
+    return hipSuccess;
 }
 
 }  // namespace trajam

@@ -38,6 +38,7 @@ FLAG_NONFINITE = 1
 FLAG_GREW = 2
 FLAG_COLD_FALLBACK = 4
 MLP_MAX_LAYERS = 8
+MLP_NOALLOC_SCRATCH_FLOATS = 2097152
 
 # every symbol include/trajam.h declares
 EXPORTS = [
@@ -45,7 +46,7 @@ EXPORTS = [
     "trajam_fixed_matrices", "trajam_set_launch", "trajam_get_launch",
     "trajam_boundary_coefficients", "trajam_cem_sample", "trajam_cem_cost",
     "trajam_cem_select", "trajam_cem_update", "trajam_mlp_param_count", "trajam_mlp_forward",
-    "trajam_mlp_backward", "trajam_mlp_infer", "trajam_mlp_pack_infer", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
+    "trajam_mlp_backward", "trajam_mlp_backward_noalloc", "trajam_mlp_infer", "trajam_mlp_pack_infer", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
     "trajam_warm_apply", "trajam_warm_fallback", "trajam_set_obstacles", "trajam_autotune",
     "trajam_ragged_plan_create", "trajam_ragged_launch", "trajam_ragged_plan_destroy", "trajam_polar",
     "trajam_qp_contraction",
@@ -159,6 +160,8 @@ def load():
     L.trajam_mlp_forward.argtypes = [sp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp]
     L.trajam_mlp_backward.argtypes = [sp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp, vp,
                                       vp]
+    L.trajam_mlp_backward_noalloc.argtypes = [sp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp,
+                                              vp, vp]
     L.trajam_mlp_mse.argtypes = [i64, vp, vp, vp, vp, vp]
     L.trajam_mlp_adam.argtypes = [i64, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float,
                                   ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
@@ -185,6 +188,7 @@ def load():
               "trajam_ragged_launch"):
         getattr(L, f).restype = ctypes.c_int
     for f in ("trajam_mlp_param_count", "trajam_mlp_forward", "trajam_mlp_backward",
+              "trajam_mlp_backward_noalloc",
               "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features", "trajam_warm_apply",
               "trajam_warm_fallback"):
         getattr(L, f).restype = ctypes.c_int
@@ -312,6 +316,12 @@ def trajam_mlp_backward(shape, batch, precision, params, x, acts, dy, grads, scr
                         stream) -> None:
     _check(load().trajam_mlp_backward(ctypes.byref(shape), int(batch), int(precision), params, x,
                                       acts, dy, grads, scratch, stream))
+
+
+def trajam_mlp_backward_noalloc(shape, batch, precision, params, x, acts, dy, grads,
+                                stream) -> None:
+    _check(load().trajam_mlp_backward_noalloc(ctypes.byref(shape), int(batch), int(precision),
+                                              params, x, acts, dy, grads, stream))
 
 
 def trajam_mlp_mse(count, y, target, dy, loss, stream) -> None:
