@@ -275,16 +275,19 @@ void trajam_ragged_plan_destroy(trajam_ragged_plan *plan);
 /* Materialised polar variables of step (a) at the given coefficients (thesis ch. 6,
  * eqs comp_alpha, comp_beta, comp_d for the obstacles; alpha_v, compute_dv and
  * alpha_a, compute_da for the kinematic blocks): the values one AM iteration's polar
- * step takes at xi_bar, for inspection and checking; the projection itself never
- * materialises them.  Single robot only.
+ * step takes at xi_bar, for inspection, checking and consumers that want them in
+ * memory; the projection itself never materialises them.  Single robot only.
  *   xi_bar     device, [batch][dims][n+1]
  *   obstacles  as trajam_project (all NULL: the obstacles packed last)
- *   obs_alpha, obs_beta, obs_d   device, [batch][n_obstacles][n_pad] or NULL each:
- *              u = (p(t) - c(t)) ./ semi-axes, alpha = atan2(u_y, u_x),
- *              beta = atan2(|(u_x, u_y)|, u_z) (pi/2 in 2D), d = max(1, |u|)
- *   kin        device, [batch][6][n_pad] or NULL: alpha_v, beta_v, d_v, alpha_a,
+ *   obs_alpha, obs_beta, obs_d   device, [batch][n_obstacles][n_steps] or NULL each
+ *              (a NULL array is not computed; in 2D beta is the constant pi/2, so
+ *              callers usually pass NULL for it):
+ *              u = (p(t) - c(t)) ./ semi-axes (1 / radius on every axis for the sphere
+ *              model), alpha = atan2(u_y, u_x), beta = atan2(|(u_x, u_y)|, u_z)
+ *              (pi/2 in 2D), d = max(1, |u|)
+ *   kin        device, [batch][6][n_steps] or NULL: alpha_v, beta_v, d_v, alpha_a,
  *              beta_a, d_a with d = min(1, |v| / bound); all 0 for a disabled block
- * n_pad = n_steps rounded up to a multiple of 64; entries past n_steps are 0.  Scalar
+ * Rows are unpadded: entry (b, j, t) is at (b * n_obstacles + j) * n_steps + t.  Scalar
  * type = solver precision.  Errors: INVALID, UNSUPPORTED (n_agents > 1), CAPACITY,
  * DEVICE. */
 trajam_status trajam_polar(trajam_solver *s, int32_t batch, const void *xi_bar, const void *obs_centre,

@@ -60,6 +60,9 @@ constexpr int kStageMaxFloats = 4096;
 
 // Packed obstacle record length (scalars), any dims.
 constexpr int kObstacleRecord = 16;
+// Field offsets in the packed record: centre, -velocity, 1/semi-axes, semi-axes,
+// -radius^2, radius.
+constexpr int kOC = 0, kOW = 3, kOI = 6, kOS = 9, kONR2 = 12, kOR = 13;
 // Inside-test fields per obstacle in the grouped layout, and obstacles per group
 // (one 64-byte scalar load per field and group in float, 64 bytes in double).
 constexpr int kObstacleFields = 10;

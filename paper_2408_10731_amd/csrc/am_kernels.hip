@@ -25,6 +25,8 @@
 #include <hip/hip_bf16.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "am_internal.h"
 
 namespace trajam {
@@ -364,9 +366,6 @@ constexpr int pow2ceil(int x) { return x <= 1 ? 1 : 2 * pow2ceil((x + 1) / 2); }
 // SGPRs (no VGPR, LDS or vector-memory cost).
 #define TRAJAM_CONST_AS __attribute__((address_space(4)))
 
-// Full per-obstacle record (used on the rare inside path): centre, -velocity,
-// 1/semi-axes, semi-axes, -radius^2, radius.
-constexpr int kOC = 0, kOW = 3, kOI = 6, kOS = 9, kONR2 = 12, kOR = 13;
 
 // Inside-test data in groups: kGroupStore<T> obstacles per group, field-major, so
 // that one scalar load brings one field of a whole (sub)group into SGPRs.  Groups
@@ -1974,137 +1973,6 @@ __global__ __launch_bounds__(kMaxThreads) void am_residual_kernel(AmArgs<T> a)
     }
 }
 
-// Angle and norm of the materialised polar variables.  FP32: atan2 from the ratio of
-// the smaller to the larger magnitude (in [0, 1]), its arctangent by an odd polynomial
-// a P(a^2) whose coefficients were fitted for this kernel (least squares on Chebyshev
-// nodes reweighted towards equal ripple on [0, 1]; in float arithmetic the largest
-// error on [0, 1] is 1.3e-7 rad with a correctly rounded reciprocal and 1.9e-7 with
-// the hardware reciprocal's 1-ulp error), then the octant and quadrant corrections
-// (rounding pi - r to float: at most 3.7e-7 rad over the whole circle),
-// atan2(0, 0) = 0; the square root is the hardware one (1 ulp).  FP64: the library
-// functions.
-__device__ __forceinline__ float polar_atan2(float y, float x)
-{
-    const float ax = fabsf(x), ay = fabsf(y);
-    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
-    const float a = mx > 0.f ? mn * __builtin_amdgcn_rcpf(mx) : 0.f;
-    const float s = a * a;
-    float q = -0.004054564982652664f;
-    q = fmaf(q, s, 0.021862955763936043f);
-    q = fmaf(q, s, -0.055912334471940994f);
-    q = fmaf(q, s, 0.0964219868183136f);
-    q = fmaf(q, s, -0.1390863060951233f);
-    q = fmaf(q, s, 0.19946566224098206f);
-    q = fmaf(q, s, -0.33329859375953674f);
-    q = fmaf(q, s, 0.9999993443489075f);
-    float r = a * q;
-    if (ay > ax) r = 1.5707963267948966f - r;
-    if (x < 0.f) r = 3.14159265358979323f - r;
-    return y < 0.f ? -r : r;
-}
-__device__ __forceinline__ double polar_atan2(double y, double x) { return atan2(y, x); }
-__device__ __forceinline__ float polar_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double polar_sqrt(double x) { return sqrt(x); }
-
-// Materialised polar variables at given coefficients: one workgroup (up to 1024
-// threads) per sample maps its coefficients to p, v, a at every time step (LDS), then
-// writes, per (obstacle,
-// time step), alpha = atan2(u_y, u_x), beta = atan2(|u_xy|, u_z) (pi/2 in 2D) and
-// d = max(1, |u|) of u = (p(t) - c(t)) ./ s (eqs comp_alpha, comp_beta, comp_d, with
-// the angles taken in semi-axis-scaled coordinates), and the kinematic blocks'
-// (alpha, beta, min(1, |v| / bound)) (eqs alpha_v, compute_dv, alpha_a, compute_da).
-// Rows are padded to tpad time steps; padding entries and disabled blocks are 0.
-template <typename T, int D, int NVP>
-__global__ __launch_bounds__(1024) void am_polar_kernel(AmArgs<T> a, T *__restrict__ oal, T *__restrict__ obe,
-                                                        T *__restrict__ odd, T *__restrict__ kin)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *pos = reinterpret_cast<T *>(smem_raw);   // [3][D][tpad]: p, v, a
-    const int sample = blockIdx.x;
-    const int tp = a.tpad;
-    const T half_pi = T(1.5707963267948966);
-    const T *x = a.xb + (size_t)sample * D * a.nv;
-    for (int t = threadIdx.x; t < tp; t += blockDim.x) {
-        T q[3][D];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int ax = 0; ax < D; ++ax) q[k][ax] = T(0);
-        if (t < a.n_p) {
-            for (int m = 0; m < a.nv; ++m) {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const T f = a.phi[((size_t)k * a.n_p + t) * NVP + m];
-#pragma unroll
-                    for (int ax = 0; ax < D; ++ax) q[k][ax] = fma(f, x[ax * a.nv + m], q[k][ax]);
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int ax = 0; ax < D; ++ax) pos[(k * D + ax) * tp + t] = q[k][ax];
-        if (kin) {
-            T *kr = kin + (size_t)sample * 6 * tp;
-#pragma unroll
-            for (int k = 1; k < 3; ++k) {
-                const T bound = k == 1 ? a.vmax : a.amax;
-                T al = T(0), be = T(0), dv = T(0);
-                if (t < a.n_p && bound > T(0)) {
-                    T nn = T(0);
-#pragma unroll
-                    for (int ax = 0; ax < D; ++ax) nn = fma(q[k][ax], q[k][ax], nn);
-                    al = polar_atan2(q[k][1], q[k][0]);
-                    be = D == 3 ? polar_atan2(polar_sqrt(fma(q[k][0], q[k][0], q[k][1] * q[k][1])), q[k][D - 1])
-                                : half_pi;
-                    dv = fmin(polar_sqrt(nn) / bound, T(1));
-                }
-                kr[(3 * (k - 1) + 0) * tp + t] = al;
-                kr[(3 * (k - 1) + 1) * tp + t] = be;
-                kr[(3 * (k - 1) + 2) * tp + t] = dv;
-            }
-        }
-    }
-    __syncthreads();
-    if (!oal && !obe && !odd) return;
-    // thread (jl, t): time step t for obstacles jl, jl + jstep, ...; the block holds a
-    // whole number of tpad-long rows, so the lanes of a wave share their obstacle
-    // (wave-uniform fields) and write consecutive time steps (coalesced rows)
-    const int t = threadIdx.x % tp, jl = threadIdx.x / tp, jstep = blockDim.x / tp;
-    const bool live_t = t < a.n_p;
-    const T tt = T(t) * a.dt;
-    T pt[D];
-#pragma unroll
-    for (int ax = 0; ax < D; ++ax) pt[ax] = pos[ax * tp + t];
-    const size_t row0 = (size_t)sample * a.n_o * tp;
-    for (int jv = jl; jv < a.n_o; jv += jstep) {
-        const int j = __builtin_amdgcn_readfirstlane(jv);
-        const T *o = a.obs + (size_t)j * kObstacleRecord;
-        T al = T(0), be = T(0), dd = T(0);
-        if (live_t) {
-            T u[D], nn = T(0);
-            // the sphere model scales every axis by 1 / radius (the first semi-axis; the
-            // caller's other entries are ignored and may be anything, zero included)
-            const int sc = a.sphere ? 0 : 1;
-#pragma unroll
-            for (int ax = 0; ax < D; ++ax) {
-                // c(t) = c + velocity t; the record holds -velocity and 1 / semi-axis
-                const T xt = fma(o[kOW + ax], tt, pt[ax] - o[kOC + ax]);
-                u[ax] = xt * o[kOI + sc * ax];
-                nn = fma(u[ax], u[ax], nn);
-            }
-            al = polar_atan2(u[1], u[0]);
-            be = D == 3 ? polar_atan2(polar_sqrt(fma(u[0], u[0], u[1] * u[1])), u[D - 1]) : half_pi;
-            dd = fmax(polar_sqrt(nn), T(1));
-        }
-        // streaming writes, never read back here: non-temporal stores
-        const size_t at = row0 + (size_t)j * tp + t;
-        if (oal) __builtin_nontemporal_store(al, oal + at);
-        if (obe) __builtin_nontemporal_store(be, obe + at);
-        if (odd) __builtin_nontemporal_store(dd, odd + at);
-    }
-}
-
 // Packs the caller's obstacle arrays.  (1) One 16-slot record per obstacle:
 // centre[3], -velocity[3], 1/semi-axes[3], semi-axes[3], -radius^2, radius (radius =
 // first semi-axis, used by the sphere model).  (2) The inside-test fields in groups of
@@ -2223,17 +2091,6 @@ hipError_t launch_residual_t(const AmArgs<T> &a, hipStream_t st)
     return hipGetLastError();
 }
 
-template <typename T, int D, int NVP>
-hipError_t launch_polar_t(const AmArgs<T> &a, void *al, void *be, void *dd, void *kin, hipStream_t st)
-{
-    const size_t lds = sizeof(T) * 3 * D * (size_t)a.tpad;
-    // whole tpad-long rows, up to 1024 threads: few obstacles a thread and enough waves
-    // in flight to keep the HBM writes streaming
-    const int threads = a.tpad * (1024 / a.tpad);
-    hipLaunchKernelGGL((am_polar_kernel<T, D, NVP>), dim3(a.batch), dim3(threads), lds, st, a, (T *)al, (T *)be,
-                       (T *)dd, (T *)kin);
-    return hipGetLastError();
-}
 
 template <typename T, template <typename, int, int> class F>
 struct Dispatch;
@@ -2350,17 +2207,6 @@ hipError_t launch_residual_f32(int dims, int nvp, const AmArgs<float> &a, hipStr
     TRAJAM_DISPATCH(launch_residual_t, float, dims, nvp, a, st);
 }
 
-hipError_t launch_polar_f64(int dims, int nvp, const AmArgs<double> &a, void *al, void *be, void *dd, void *kin,
-                            hipStream_t st)
-{
-    TRAJAM_DISPATCH(launch_polar_t, double, dims, nvp, a, al, be, dd, kin, st);
-}
-
-hipError_t launch_polar_f32(int dims, int nvp, const AmArgs<float> &a, void *al, void *be, void *dd, void *kin,
-                            hipStream_t st)
-{
-    TRAJAM_DISPATCH(launch_polar_t, float, dims, nvp, a, al, be, dd, kin, st);
-}
 
 template <typename T>
 static hipError_t pack_t(int dims, int n_o, const T *c, const T *w, const T *s, T *out, T *soa,

@@ -477,23 +477,25 @@ class Solver:
                          c, v, a, self._t(res_l2, (B,), "res_l2"),
                          None if res_max is None else self._t(res_max, (B,), "res_max"), st)
 
-    def polar(self, xi_bar, obs, kinematic=True, stream=None):
-        """Polar variables of step (a) at xi_bar: (alpha, beta, d) tensors [B, n_o, n_pad]
-        (None without obstacles) and, with kinematic, [B, 6, n_pad] (alpha_v, beta_v,
-        d_v, alpha_a, beta_a, d_a); n_pad = n_steps rounded up to 64."""
+    def polar(self, xi_bar, obs, kinematic=True, stream=None, beta=True):
+        """Polar variables of step (a) at xi_bar: (alpha, beta, d) tensors [B, n_o, n_steps]
+        (None without obstacles; beta None when `beta` is false) and, with kinematic,
+        [B, 6, n_steps] (alpha_v, beta_v, d_v, alpha_a, beta_a, d_a)."""
         import torch
         if self.n_agents != 1:
             raise ValueError("polar variables are single-robot")
         B = xi_bar.shape[0]
-        n_pad = (self.problem.n_steps + 63) // 64 * 64
+        n_p = self.problem.n_steps
         n_o = self.problem.n_obstacles
         c, v, a = self.obstacles(*(obs or ()))
         st = (stream or torch.cuda.current_stream()).cuda_stream
         kw = dict(dtype=self.dtype, device=xi_bar.device)
         al = be = d = None
         if n_o:
-            al, be, d = (torch.empty((B, n_o, n_pad), **kw) for _ in range(3))
-        kin = torch.empty((B, 6, n_pad), **kw) if kinematic else None
+            al, d = (torch.empty((B, n_o, n_p), **kw) for _ in range(2))
+            if beta:
+                be = torch.empty((B, n_o, n_p), **kw)
+        kin = torch.empty((B, 6, n_p), **kw) if kinematic else None
         ptr = lambda t: None if t is None else t.data_ptr()
         trajam_polar(self.handle, B, self._t(xi_bar, (B,) + self.sample_shape, "xi_bar"), c, v, a,
                      ptr(al), ptr(be), ptr(d), ptr(kin), st)

@@ -72,19 +72,22 @@ def _run_case(w, precision, speed, per_axis):
     if precision == "fp32":
         xb = xb.astype(np.float32).astype(np.float64)
     _, obs = tj.device_workload(w, dt, static=(speed == 0.0))
-    al, be, d, kin = solver.polar(torch.as_tensor(xb, dtype=dt, device="cuda").contiguous(), obs)
+    xbd = torch.as_tensor(xb, dtype=dt, device="cuda").contiguous()
+    al, be, d, kin = solver.polar(xbd, obs)
     torch.cuda.synchronize()
-    B, n_pad = w.xi.shape[0], (w.n_steps + 63) // 64 * 64
+    B = w.xi.shape[0]
     kin = kin.double().cpu().numpy()
-    assert kin.shape == (B, 6, n_pad) and not kin[..., w.n_steps:].any()
+    assert kin.shape == (B, 6, w.n_steps)
     if w.n_obs == 0:
         assert al is None and be is None and d is None
-        al = be = d = np.zeros((B, 0, n_pad))
+        al = be = d = np.zeros((B, 0, w.n_steps))
     else:
+        # beta not requested: alpha and d unchanged, bitwise
+        al2, be2, d2, _ = solver.polar(xbd, None, beta=False)
+        torch.cuda.synchronize()
+        assert be2 is None and torch.equal(al, al2) and torch.equal(d, d2)
         al, be, d = (x.double().cpu().numpy() for x in (al, be, d))
-        assert al.shape == (B, w.n_obs, n_pad)
-        for arr in (al, be, d):
-            assert not arr[..., w.n_steps:].any()       # padding entries are 0
+        assert al.shape == (B, w.n_obs, w.n_steps)
     _check(w, xb, al, be, d, kin, precision)
     solver.close()
 
@@ -105,8 +108,8 @@ def test_polar_variables_match_the_oracle(dims, speed, per_axis, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_polar_ragged_row_passes_and_long_horizon(precision):
-    """150 steps (rows padded to 192, five rows to a 960-thread workgroup) and 19 moving
-    ellipsoids (four row passes, the last one partial), 3D, degree 9."""
+    """150 steps and 19 moving ellipsoids (2,850 elements a sample: one workgroup's
+    threads take about 11 each, crossing rows mid-wave), 3D, degree 9."""
     w = wl.tiny(dims=3, batch=4, n_obs=19, degree=9, n_steps=150, speed=0.3, per_axis=True, seed=41)
     print("case: polar ragged rows", precision, flush=True)
     _run_case(w, precision, 0.3, True)
@@ -175,4 +178,23 @@ def test_polar_sphere_model_ignores_other_semi_axes(dims, other, precision):
     al, be, d, kin = (x.double().cpu().numpy() for x in got)
     assert np.all(np.isfinite(al)) and np.all(np.isfinite(d))
     _check(w, xb, al, be, d, kin, precision)
+    solver.close()
+
+
+def test_polar_many_obstacles_unstaged_and_split_over_workgroups():
+    """2,100 moving ellipsoids (their fields exceed the LDS stage, so they are read from
+    the packed records) and 2 samples (each sample's 84,000 elements split over many
+    workgroups), 3D, FP64: 500 sampled entries against the oracle."""
+    w = wl.tiny(dims=3, batch=2, n_obs=2100, degree=6, n_steps=40, speed=0.3, per_axis=True, seed=53)
+    print("case: polar 2100 obstacles", flush=True)
+    from paper_2408_10731_amd import trajam as tj
+    solver = tj.Solver.for_workload(w, precision="fp64", sphere=False)
+    rng = np.random.default_rng(6)
+    xb = w.xi + rng.normal(size=w.xi.shape) * 0.4
+    _, obs = tj.device_workload(w, torch.float64, static=False)
+    al, be, d, kin = (x.cpu().numpy() for x in solver.polar(torch.as_tensor(xb, device="cuda").contiguous(), obs))
+    entries = list(zip(rng.integers(0, w.batch, 500), rng.integers(0, w.n_obs, 500),
+                       rng.integers(0, w.n_steps, 500)))
+    entries += [(1, w.n_obs - 1, w.n_steps - 1), (0, 0, 0), (1, 0, 0), (0, w.n_obs - 1, w.n_steps - 1)]
+    _check(w, xb, al, be, d, kin, "fp64", entries)
     solver.close()

@@ -1,5 +1,6 @@
 """Bounds the float32 arctangent of the materialised polar kernel (the angles of
-thesis ch. 6 eqs comp_alpha, comp_beta) on the CPU.
+thesis ch. 6 eqs comp_alpha, comp_beta) on the CPU.  (Vectors shorter than FLT_MIN
+are outside these grids: the kernel keeps the larger magnitude at least FLT_MIN.)
 
 The coefficients are read from the kernel source itself, so this checks the
 committed polynomial, and its float32 evaluation (fma steps, the reciprocal, the
@@ -13,18 +14,18 @@ import re
 import numpy as np
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                   "paper_2408_10731_amd", "csrc", "am_kernels.hip")
+                   "paper_2408_10731_amd", "csrc", "polar_kernels.hip")
 f32 = np.float32
 
 
 def _coefficients():
     src = open(SRC).read()
-    head = "__device__ __forceinline__ float polar_atan2(float y, float x)"
+    head = "__device__ __forceinline__ float polar_atan_poly(float a)"
     body = src[src.index(head):]
     body = body[:body.index("\n}\n")]
     lits = [float(v) for v in re.findall(r"(-?\d+\.\d+(?:e-?\d+)?)f", body)]
-    assert len(lits) == 10, lits          # 8 polynomial coefficients, pi/2, pi
-    return lits[:8], lits[8], lits[9]
+    assert len(lits) == 8, lits          # the odd polynomial's 8 coefficients
+    return lits
 
 
 def _fma(a, b, c):
@@ -33,24 +34,26 @@ def _fma(a, b, c):
 
 
 def _atan2(y, x, rcp_shift=0):
-    poly, half_pi, pi = _coefficients()
+    """The kernel's float atan2: ratio min/max with max kept >= FLT_MIN, the polynomial,
+    pi/2 - r above the diagonal, pi - r for x < 0, the sign of y."""
+    poly = _coefficients()
     y = y.astype(f32)
     x = x.astype(f32)
     ax, ay = np.abs(x), np.abs(y)
-    mx, mn = np.maximum(ax, ay), np.minimum(ax, ay)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        rc = (f32(1) / mx).astype(f32)
+    mx = np.maximum(np.maximum(ax, ay), f32(1.17549435e-38)).astype(f32)
+    mn = np.minimum(ax, ay)
+    rc = (f32(1) / mx).astype(f32)
     if rcp_shift:
         rc = np.nextafter(rc, f32(np.inf) if rcp_shift > 0 else f32(0)).astype(f32)
-    a = np.where(mx > 0, (mn * rc).astype(f32), f32(0)).astype(f32)
+    a = (mn * rc).astype(f32)
     s = (a * a).astype(f32)
     q = np.full_like(a, f32(poly[0]))
     for c in poly[1:]:
         q = _fma(q, s, c)
     r = (a * q).astype(f32)
-    r = np.where(ay > ax, (f32(half_pi) - r).astype(f32), r)
-    r = np.where(x < 0, (f32(pi) - r).astype(f32), r)
-    return np.where(y < 0, -r, r).astype(f32)
+    r = np.where(ay > ax, (f32(np.pi / 2) - r).astype(f32), r)
+    r = np.where(x < 0, (f32(np.pi) - r).astype(f32), r)
+    return np.copysign(r, y).astype(f32)
 
 
 def _err(got, y, x):
@@ -79,5 +82,6 @@ def test_full_atan2_error_and_special_cases():
     z = np.zeros(1, dtype=f32)
     assert _atan2(z, z)[0] == 0.0                      # atan2(0, 0) = 0
     assert _atan2(z, -np.ones(1, f32))[0] == f32(np.pi)
+    assert _atan2(-z, -np.ones(1, f32))[0] == -f32(np.pi)   # IEEE: atan2(-0, x < 0) = -pi
     assert _atan2(np.ones(1, f32), z)[0] == f32(np.pi / 2)
     assert _atan2(-np.ones(1, f32), z)[0] == -f32(np.pi / 2)
