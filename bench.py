@@ -1,21 +1,27 @@
 """Benchmark of the MI355X AM projection (one JSON line on stdout).
 
-Workload (one "step"): one full projection of the 2D point-robot problem with
-50 static circles (radius U(0.3, 0.8) m in a 30 x 30 m box), Bernstein degree 10,
-100 time samples over 30 s, batch 1024 samples, 50 AM iterations, FP32, cold start
-(xb = xi, lambda = 0).  Inputs are seeded and synthetic and already resident in
-HBM when the timed region starts.
+Workload (one "step"): one full projection of config 3 -- the 3D point robot among
+200 static ellipsoids (semi-axes U(0.3, 1.0) m each, centres in 20 x 20 x 6 m),
+Bernstein degree 15, 150 time samples over 20 s, batch 4096 samples, 50 AM
+iterations, FP32, cold start (xb = xi, lambda = 0), the residual trace written.
+Inputs are seeded and synthetic and already resident in HBM when the timed region
+starts; the scene's obstacles are packed into the solver once before it.
 
-metric: traj-iters/s = batch * iterations / (wall time of one projection); the
-scene's obstacles are packed into the solver once before the timed region.
-Also reported: time until the batch-median residual first reaches 1e-3 from a cold
-start and from the learned warm start (network trained here first, untimed), the
-roofline of the fused AM kernel (VALU-bound: algorithmic lane-ops / kernel time
-against the chip's 256 CU x 64 lanes x 2.4 GHz), the ragged set of 256 problems
-(half of them multi-agent) in one plan, one graph-replayed planning call of the
-sampling loop, config 3 in FP64 / FP32 / BF16 with the reduced precisions' deviation
-from FP64, the materialised polar variables against the HBM peak, and the FP64 CPU
-oracle timed on the main workload on the host cores (about 8 s) and on one thread.
+metric: traj-iters/s = batch * iterations / (wall time of one projection).
+The roofline of the projection kernel counts the algorithmic work of one
+trajectory-iteration (every obstacle and kinematic element at the lower end of its
+VALU cost, the waypoint map, the F^T contraction and the QP) against the chip's
+non-packed VALU rate; beside it, the VALU issue fraction and the HBM traffic that
+hardware counters (rocprofv3 --pmc, in child processes of this run) give for one
+launch of the same kernel.  Also reported: config 2 (2D, the former headline) with
+the same roofline, the time until the batch-median residual first reaches 1e-3 from
+a cold start and from the learned warm start (network trained here first, untimed),
+the ragged set of 256 problems (half of them multi-agent) in one plan, one
+graph-replayed planning call of the sampling loop, config 3 in FP64 / FP32 / BF16
+with the reduced precisions' deviation from FP64, the materialised polar variables
+against the HBM peak, and the FP64 CPU oracle timed on a bounded sample of the
+headline workload (median of 5 runs) on the host cores and on one thread, with its
+time to the residual tolerance.
 """
 from __future__ import annotations
 
@@ -30,27 +36,30 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_VALU_OPS = 256 * 64 * 2.4e9  # lane-ops/s, one FMA = one op (no packed FP32)
-# HBM bytes per launch of the main kernel from FETCH_SIZE / WRITE_SIZE counter runs
-# scaled by a copy of known size (profiles/am_project_kernel_cfg2_fp32.md): 921 KiB
-# read + 1,824 KiB written.  Re-measure whenever the kernel changes.
-TRAFFIC_BYTES_PER_LAUNCH = (921 + 1824) * 1024
+PEAK_VALU_OPS = 256 * 64 * 2.4e9   # lane-ops/s, one FMA = one op (no packed FP32)
+PEAK_VALU_INSTS = 256 * 2.4e9      # wave64 VALU instructions/s: 4 SIMDs x 16 lanes per CU per clock
+PEAK_HBM = 8.0e12                  # bytes/s
 
 
-def algorithmic_ops_per_traj_iter(w) -> float:
-    """VALU lane-ops one trajectory-iteration needs at minimum.
-
-    * obstacle inside test per (obstacle, time): per axis one subtraction and one
-      FMA (plus one FMA per axis for moving obstacles), i.e. 2D static circle = 4;
-    * waypoint map p, v, a: 3 D n_v FMAs per time sample;
-    * F^T r contraction: 3 D n_v FMAs per time sample;
-    * kinematic tests: 2 (D + 1) per time sample;
-    * multiplier, defect and QP: D n_v (3 + (n_v - 4)).
-    """
+def survey_ops_per_unit(w) -> int:
+    """Algorithmic VALU lane-ops of one trajectory-iteration, counted the way the work
+    is specified, not the way the kernel does it: every (obstacle, time) and every
+    kinematic (block, time) element at the lower end of its cost (12 ops for a 2D
+    circle, 20 for a 3D ellipsoid), the waypoint map plus the F^T contraction
+    (2 D 3 n_p n_v FMAs) and the QP (D n_v (n_v + 4) FMAs); an FMA counts once.  The
+    kernel skips every inside test that exact culling proves zero, so it can do this
+    work faster than the VALU peak allows (frac > 1)."""
     D, nv, np_, no = w.dims, w.n_v, w.n_steps, w.n_obs
-    dyn = bool(np.any(w.obs_vel))
-    per_obs = D * (3 if dyn else 2) + (0 if np.all(w.obs_axes == w.obs_axes[:, :1]) else D)
-    return (no * np_ * per_obs + np_ * (6 * D * nv + 2 * (D + 1)) + D * nv * (3 + max(nv - 4, 0)))
+    kin = (w.v_max > 0) + (w.a_max > 0)
+    elements = no * np_ + kin * np_
+    per_el = 20 if D == 3 else 12
+    return elements * per_el + 2 * D * 3 * np_ * nv + D * nv * (nv + 4)
+
+
+def state_bytes_per_launch(w, K, word=4) -> int:
+    """Bytes one launch must move: xi, xb, lambda read, xb, lambda written, the
+    residual trace written."""
+    return 5 * w.batch * w.dims * w.n_v * word + K * w.batch * word
 
 
 def median_time_to_residual(trace: np.ndarray, tol: float = 1e-3):
@@ -160,7 +169,7 @@ def ttr_scene(w, solver, xi, obs, net, cap, stream, tol=1e-3, reps=20):
 
 def time_to_residual(args, w, solver, xi, obs, stream, tol=1e-3, net=None, info=None):
     """The learned warm start against the cold start: on the benchmark scene, and summed
-    over 8 held-out scenes of the same family (scene seeds disjoint from the training
+    over the 16 held-out scenes 90,001-90,016 of the same family (scene seeds disjoint from the training
     ones); a scene whose median never reaches tol within the cap counts the cap, in
     iterations and in time."""
     import torch
@@ -174,7 +183,7 @@ def time_to_residual(args, w, solver, xi, obs, stream, tol=1e-3, net=None, info=
     out = {"tol": tol, "cap": cap, "probe_iters": ws.K0, "warm_training": info,
            "scene": ttr_scene(w, solver, xi, obs, net, cap, stream, tol)}
     per, tot = [], {"cold_iters": 0, "warm_iters": 0, "cold_ms": 0.0, "warm_ms": 0.0}
-    for seed in range(90_001, 90_009):
+    for seed in range(90_001, 90_017):
         ws_ = wl.config2(batch=w.batch, seed=seed)
         s = tj.Solver.for_workload(ws_, precision="fp32")
         x_, o_ = tj.device_workload(ws_, torch.float32)
@@ -358,38 +367,72 @@ def cem_bench(args):
     return out
 
 
-def cpu_baseline(w, iters: int, seconds: float = 8.0, seconds_1t: float = 2.0):
-    """The FP64 C oracle on the host cores: the whole benchmark step (every trajectory,
-    every iteration) repeated until about `seconds` of wall time on all threads, and a
-    64-trajectory slice of it on one thread for about `seconds_1t`."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, iters: int, tol: float = 1e-3, cap: int = 300):
+    """The FP64 C oracle (untuned) on the host cores, on a bounded sample of the
+    headline workload: 128 of its trajectories x its AM iterations on all threads, and
+    4 trajectories x 10 iterations on one thread, each the median of 5 runs; and its
+    time to the residual tolerance on 32 trajectories (iterated 10 at a time until the
+    batch-median residual first reaches tol, capped like the GPU run), median of 3."""
     import oracle
     threads = oracle.max_threads()
 
-    def timed(wk, n_threads, budget):
-        reps, t0 = 0, time.perf_counter()
-        while True:
-            oracle.project(wk, iters=iters, n_threads=n_threads)
-            reps += 1
-            dt = time.perf_counter() - t0
-            if dt >= budget or reps >= 50:
-                return reps, dt
-    reps, dt = timed(w, threads, seconds)
-    w1 = w.subset(64)
-    reps1, dt1 = timed(w1, 1, seconds_1t)
-    return {"value": reps * w.batch * iters / dt, "unit": "traj-iters/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"the whole step ({w.batch} trajectories x {iters} AM iterations), {reps} run(s), "
-                      f"FP64 C oracle, OpenMP over trajectories on {threads} threads ({dt:.1f} s)",
-            "value_1thread": reps1 * w1.batch * iters / dt1,
-            "sample_1thread": f"{w1.batch} trajectories x {iters} AM iterations, {reps1} run(s) on one "
-                              f"thread ({dt1:.1f} s)"}
+    def rate(wk, k, n_threads, runs=5):
+        vals = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            oracle.project(wk, iters=k, n_threads=n_threads)
+            vals.append(wk.batch * k / (time.perf_counter() - t0))
+        return float(np.median(vals))
+
+    ws = w.subset(128)
+    value = rate(ws, iters, threads)
+    value_1t = rate(w.subset(4), 10, 1)
+    wt = w.subset(32)
+    ttr_s, ttr_it = [], None
+    for _ in range(3):
+        xb, lam = wt.xi.copy(), np.zeros_like(wt.xi)
+        t0, done, it = time.perf_counter(), None, 0
+        while it < cap and done is None:
+            xb, lam, tr, _ = oracle.project(wt, xi_bar=xb, lam=lam, iters=10, n_threads=threads)
+            hit = np.nonzero(np.median(tr, axis=1) <= tol)[0]
+            if hit.size:
+                done = it + int(hit[0]) + 1
+            it += 10
+        ttr_s.append(time.perf_counter() - t0)
+        ttr_it = done
+    return {"value": value, "unit": "traj-iters/s", "cores": threads, "kind": "oracle",
+            "sample": f"{ws.batch} of the {w.batch} trajectories x {iters} AM iterations, FP64 C oracle, "
+                      f"OpenMP over trajectories on {threads} threads, median of 5 runs",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "value_1thread": value_1t,
+            "sample_1thread": "4 trajectories x 10 AM iterations on one thread, median of 5 runs",
+            "time_to_residual": {"tol": tol, "cap": cap, "trajectories": wt.batch,
+                                 "iterations": ttr_it, "reached": ttr_it is not None,
+                                 "seconds": float(np.median(ttr_s)),
+                                 "note": "batch-median residual, checked every 10 iterations (the time "
+                                         "runs to the end of the 10-iteration block that reaches tol)"}}
 
 
 def polar_bench(args):
-    """The materialised polar variables (trajam_polar) at config-2 sizes: alpha, d (and
-    beta = pi/2) for 1024 samples x 50 obstacles x 128 padded steps plus the kinematic
-    blocks, FP32; HBM-bound writes, reported against the 8 TB/s peak and against a
-    plain fill of the same bytes, and again at batches 2048, 4096 and 8192."""
+    """The materialised polar variables (trajam_polar, unpadded [batch][n_o][n_steps]
+    rows) against the HBM peak: config 3 (3D: alpha, beta and d of 4096 samples x 200
+    ellipsoids x 150 steps, 1.47 GB, plus the kinematic blocks) and config 2 (2D:
+    alpha and d of 1024 x 50 x 100 -- beta is the constant pi/2 in 2D and is not
+    written), FP32, the latter also at batches 2048-8192.  Useful bytes are the
+    arrays' entries that carry information (in 2D the kinematic beta rows are
+    constant and not counted); the bytes the kernel writes, those rows included, and
+    a plain fill of the same size are reported beside them."""
     import torch
     from paper_2408_10731_amd import trajam as tj
     from paper_2408_10731_amd import workloads as wl
@@ -398,37 +441,207 @@ def polar_bench(args):
     st = torch.cuda.current_stream()
 
     def measure(w):
-        solver = tj.Solver.for_workload(w, precision="fp32")
+        solver = tj.Solver.for_workload(w, precision="fp32", sphere=False if w.dims == 3 else None)
         xi, obs = tj.device_workload(w, torch.float32)
         solver.set_obstacles(obs)
-        n_pad = (w.n_steps + 63) // 64 * 64
-        al, be, d = (torch.empty((w.batch, w.n_obs, n_pad), **kw) for _ in range(3))
-        kin = torch.empty((w.batch, 6, n_pad), **kw)
+        n = w.batch * w.n_obs * w.n_steps
+        al, d = torch.empty(n, **kw), torch.empty(n, **kw)
+        be = torch.empty(n, **kw) if w.dims == 3 else None
+        kin = torch.empty((w.batch, 6, w.n_steps), **kw)
+        ptr = lambda t: None if t is None else t.data_ptr()
 
         def run():
             tj.trajam_polar(solver.handle, w.batch, xi.data_ptr(), None, None, None, al.data_ptr(),
-                            be.data_ptr(), d.data_ptr(), kin.data_ptr(), st.cuda_stream)
+                            ptr(be), d.data_ptr(), kin.data_ptr(), st.cuda_stream)
         ms = _time(run, args.polar_steps, st)
-        written = 4 * (3 * al.numel() + kin.numel())
-        read = 4 * (xi.numel() + 3 * w.n_steps * 12)
+        arrays = 3 if w.dims == 3 else 2
+        kin_rows = 6 if w.dims == 3 else 4
+        useful = 4 * (arrays * n + kin_rows * w.batch * w.n_steps)
+        written = 4 * (arrays * n + kin.numel())
+        read = 4 * (xi.numel() + 3 * w.n_steps * 16)
         solver.close()
         del al, be, d, kin
-        gbs = (written + read) / (ms * 1e-3) / 1e9
-        # what a plain write stream of the same size reaches on this chip: torch's fill
-        # kernel over one buffer of the written byte count
+        gbs = useful / (ms * 1e-3) / 1e9
+        # a plain write stream of the same size on this chip: torch's fill kernel
         buf = torch.empty(written // 4, **kw)
         fill_ms = _time(lambda: buf.fill_(1.0), args.polar_steps, st)
         del buf
         fill_gbs = written / (fill_ms * 1e-3) / 1e9
-        return {"ms_per_call": ms, "bytes_per_call": written + read, "achieved_GBps": gbs,
-                "peak_GBps": 8000.0, "frac": gbs / 8000.0,
-                "fill_same_bytes_GBps": fill_gbs, "frac_of_fill": gbs / fill_gbs}
+        return {"ms_per_call": ms, "useful_bytes": useful, "written_bytes": written, "read_bytes": read,
+                "achieved_GBps": gbs, "peak_GBps": PEAK_HBM / 1e9, "frac_useful": gbs * 1e9 / PEAK_HBM,
+                "written_GBps": (written + read) / (ms * 1e-3) / 1e9,
+                "fill_same_bytes_GBps": fill_gbs, "frac_of_fill": (written / (ms * 1e-3) / 1e9) / fill_gbs}
 
-    out = {"config": "config 2 sizes: 1024 samples x 50 obstacles x 128 padded steps + kinematic blocks, fp32"}
-    out.update(measure(wl.config2()))
-    # the same geometry at larger batches: how much of a call is the launch's fixed cost
-    out["by_batch"] = [dict(batch=b, **measure(wl.problem2d(20240, 50, b))) for b in (2048, 4096, 8192)]
+    out = {"cfg3": {"config": "config 3: 4096 samples x 200 ellipsoids x 150 steps, alpha, beta, d "
+                              "+ kinematic blocks, fp32", **measure(wl.config3())},
+           "cfg2": {"config": "config 2: 1024 samples x 50 circles x 100 steps, alpha and d (beta = pi/2 "
+                              "not written) + kinematic blocks, fp32", **measure(wl.config2())}}
+    # the same 2D geometry at larger batches: how much of a call is the launch's fixed cost
+    out["cfg2"]["by_batch"] = [dict(batch=b, **measure(wl.problem2d(20240, 50, b))) for b in (2048, 4096, 8192)]
     return out
+
+
+COUNTER_PASSES = (
+    ("FETCH_SIZE",),
+    ("WRITE_SIZE",),
+    ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES",
+     "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_SMEM"),
+)
+PROBE_COPY_MIB = 64
+
+
+def _read_counters(outdir):
+    """{(kernel name, dispatch id): {counter: value}} from rocprofv3's CSV output."""
+    import csv
+    import glob
+    rows = {}
+    for path in glob.glob(os.path.join(outdir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                key = (r["Kernel_Name"], int(r["Dispatch_Id"]))
+                rows.setdefault(key, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    return rows
+
+
+def _last(rows, pred):
+    keys = sorted((k for k in rows if pred(k[0])), key=lambda k: k[1])
+    return rows[keys[-1]] if keys else None
+
+
+def hw_counters(probe_args, kernel_prefix, launch_ms, algorithmic_bytes, timeout=150):
+    """HBM traffic and VALU issue of one launch of the projection kernel, measured in
+    this run: three rocprofv3 --pmc passes (FETCH_SIZE; WRITE_SIZE; eight SQ counters),
+    each over a child process that repeats the timed step's launch twice and then
+    copies PROBE_COPY_MIB MiB once.  The byte counters are scaled by what they read
+    for that copy of known size; the last dispatch of the kernel is the one reported.
+    Returns (traffic bytes or None, details)."""
+    import shutil
+    import subprocess
+    import tempfile
+    prof = shutil.which("rocprofv3")
+    if prof is None:
+        return None, {"error": "rocprofv3 not found"}
+    vals, copy = {}, {}
+    env = dict(os.environ, TMPDIR="/tmp")
+    for counters in COUNTER_PASSES:
+        d = tempfile.mkdtemp(prefix="trajam_pmc_", dir="/tmp")
+        cmd = ["timeout", "-s", "KILL", str(timeout), prof, "--pmc", *counters, "--output-format", "csv",
+               "-d", d, "-o", "p", "--", sys.executable, os.path.abspath(__file__), *probe_args]
+        print("bench: counter pass " + " ".join(counters), file=sys.stderr, flush=True)
+        r = subprocess.run(cmd, cwd="/tmp", env=env, capture_output=True, text=True)
+        rows = _read_counters(d)
+        shutil.rmtree(d, ignore_errors=True)
+        # names read "void trajam::(anonymous namespace)::am_wave_kernel<float, 3, ...>(...)"
+        k = _last(rows, lambda n: f"::{kernel_prefix}<" in n or n.startswith(kernel_prefix + "<"))
+        c = _last(rows, lambda n: "copyBuffer" in n)
+        if k is None:
+            return None, {"error": f"no {kernel_prefix} dispatch in the {counters[0]} pass "
+                                   f"(rocprofv3 exit {r.returncode}): {r.stderr[-300:]}"}
+        vals.update(k)
+        if c is not None:
+            copy.update(c)
+    out = {"kernel": kernel_prefix, "passes": [list(c) for c in COUNTER_PASSES]}
+    traffic = None
+    nbytes = PROBE_COPY_MIB << 20
+    if copy.get("FETCH_SIZE") and copy.get("WRITE_SIZE"):
+        fs = nbytes / (copy["FETCH_SIZE"] * 1024.0)
+        wsc = nbytes / (copy["WRITE_SIZE"] * 1024.0)
+        rd = vals["FETCH_SIZE"] * 1024.0 * fs
+        wr = vals["WRITE_SIZE"] * 1024.0 * wsc
+        traffic = rd + wr
+        out.update({"fetch_KiB": vals["FETCH_SIZE"], "write_KiB": vals["WRITE_SIZE"],
+                    "copy_fetch_KiB": copy["FETCH_SIZE"], "copy_write_KiB": copy["WRITE_SIZE"],
+                    "fetch_scale": fs, "write_scale": wsc, "read_bytes": rd, "written_bytes": wr,
+                    "algorithmic_bytes": algorithmic_bytes,
+                    "traffic_over_algorithmic": traffic / algorithmic_bytes})
+    else:
+        out["error_traffic"] = "no copy dispatch to calibrate the byte counters"
+    sq = {k: v for k, v in vals.items() if k.startswith("SQ_")}
+    out["sq"] = sq
+    if sq.get("SQ_INSTS_VALU"):
+        out["valu_insts"] = sq["SQ_INSTS_VALU"]
+        out["valu_issue_frac"] = sq["SQ_INSTS_VALU"] / (launch_ms * 1e-3 * PEAK_VALU_INSTS)
+        if sq.get("SQ_WAVES"):
+            out["valu_insts_per_wave"] = sq["SQ_INSTS_VALU"] / sq["SQ_WAVES"]
+    return traffic, out
+
+
+def probe(args):
+    """Child of hw_counters: the headline step's launch twice, then a copy of known
+    size (the byte counters' calibration).  Prints nothing on stdout."""
+    import torch
+    from paper_2408_10731_amd import trajam as tj
+    from paper_2408_10731_amd import workloads as wl
+    k, spw = (int(x) for x in args.probe_launch.split(","))
+    w = wl.config3() if args.probe == "cfg3" else wl.config2(batch=args.batch)
+    K = args.iters
+    solver = tj.Solver.for_workload(w, precision="fp32", sphere=False if args.probe == "cfg3" else None)
+    xi, obs = tj.device_workload(w, torch.float32)
+    solver.set_launch(k, spw)
+    solver.set_obstacles(obs)
+    xb, lam = xi.clone(), torch.zeros_like(xi)
+    tr = torch.zeros((K, w.batch), dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        xb.copy_(xi)
+        lam.zero_()
+        solver.project(xi, w.boundary, None, xb, lam, K, res_trace=tr)
+    torch.cuda.synchronize()
+    a = torch.ones(PROBE_COPY_MIB << 18, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    solver.close()
+
+
+def projection_leg(w, K, steps, warmup, sphere=None):
+    """Times one workload's projection (autotuned launch shape, obstacles packed once,
+    cold-start resets inside the step): returns the timing and the solver state."""
+    import torch
+    from paper_2408_10731_amd import trajam as tj
+    solver = tj.Solver.for_workload(w, precision="fp32", sphere=sphere)
+    xi, obs = tj.device_workload(w, torch.float32)
+    xb = xi.clone()
+    lam = torch.zeros_like(xi)
+    trace = torch.zeros((K, w.batch), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    # launch shape from the autotuner (setup, untimed), then the scene's obstacles,
+    # packed once before timing
+    kern, spw = solver.autotune(xi, w.boundary, obs, xb, lam, probe_iters=K)
+    solver.set_obstacles(obs)
+    for _ in range(warmup):
+        xb.copy_(xi)
+        lam.zero_()
+        solver.project(xi, w.boundary, None, xb, lam, K, res_trace=trace)
+    torch.cuda.synchronize()
+    # per-launch kernel time (events on the launch stream), then the timed region
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for i in range(steps):
+        xb.copy_(xi)
+        lam.zero_()
+        ev[i][0].record(stream)
+        solver.project(xi, w.boundary, None, xb, lam, K, res_trace=trace)
+        ev[i][1].record(stream)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_per_step = t_start.elapsed_time(t_end) / steps
+    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    kname = "am_project_kernel" if kern == 0 else "am_wave_kernel"
+    ops = survey_ops_per_unit(w)
+    achieved = ops * w.batch * K / (launch_ms * 1e-3)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12,
+            "unit": "Tlane-ops/s", "frac": achieved / PEAK_VALU_OPS, "traffic": None,
+            "kernel": f"{kname}<float,{w.dims},...>, {spw} sample(s)/workgroup",
+            "ops_per_traj_iter": ops, "units_per_launch": w.batch * K, "launch_ms": launch_ms}
+    return {"solver": solver, "xi": xi, "obs": obs, "xb": xb, "lam": lam, "ms_per_step": ms_per_step,
+            "launch_ms": launch_ms, "wall": wall, "kern": kern, "spw": spw, "kname": kname,
+            "roofline": roof, "value": w.batch * K / (ms_per_step * 1e-3)}
 
 
 def main():
@@ -439,6 +652,11 @@ def main():
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-counters", action="store_true",
+                    help="skip the rocprofv3 counter passes (traffic and VALU issue become null)")
+    ap.add_argument("--probe", choices=["cfg3", "cfg2"], default=None,
+                    help="internal: the counter passes' child process")
+    ap.add_argument("--probe-launch", default="1,1", help="internal: kernel,samples-per-workgroup")
     ap.add_argument("--ttr-cap", type=int, default=300)
     ap.add_argument("--ws-scenes", type=int, default=2048)
     ap.add_argument("--ws-epochs", type=int, default=20)
@@ -451,6 +669,8 @@ def main():
                     help="timed calls of the materialised polar variables; 0 skips that leg")
     ap.add_argument("--cem-only", action="store_true",
                     help="run only the sampling-loop leg and print its JSON (profiling)")
+    ap.add_argument("--polar-only", action="store_true",
+                    help="run only the materialised-polar leg and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB buffer 3 times (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -464,8 +684,14 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 3}), flush=True)
         return
+    if args.probe:
+        probe(args)
+        return
     if args.cem_only:
         print(json.dumps(cem_bench(args)), flush=True)
+        return
+    if args.polar_only:
+        print(json.dumps(polar_bench(args)), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -474,63 +700,32 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2408_10731_amd import trajam as tj
     from paper_2408_10731_amd import workloads as wl
 
-    w = wl.config2(batch=args.batch)
     K = args.iters
-    solver = tj.Solver.for_workload(w, precision="fp32")
-    xi, obs = tj.device_workload(w, torch.float32)
-    xb = xi.clone()
-    lam = torch.zeros_like(xi)
-    trace = torch.zeros((K, w.batch), dtype=torch.float32, device="cuda")
-    stream = torch.cuda.current_stream()
-    # launch shape from the autotuner (setup, untimed), then the scene's obstacles,
-    # packed once before timing
-    kern, spw = solver.autotune(xi, w.boundary, obs, xb, lam, probe_iters=K)
-    solver.set_obstacles(obs)
+    # headline: config 3 (the largest single-problem configuration), FP32
+    w3 = wl.config3()
+    h = projection_leg(w3, K, args.steps, args.warmup, sphere=False)
+    roofline = h["roofline"]
+    counters = None
+    if not args.no_counters:
+        probe_args = ["--probe", "cfg3", "--probe-launch", f"{h['kern']},{h['spw']}", "--iters", str(K)]
+        traffic, counters = hw_counters(probe_args, h["kname"], h["launch_ms"],
+                                        state_bytes_per_launch(w3, K))
+        roofline["traffic"] = traffic
+        if counters.get("valu_issue_frac") is not None:
+            roofline["valu_issue_frac"] = counters["valu_issue_frac"]
 
-    def step():
-        xb.copy_(xi)
-        lam.zero_()
-        solver.project(xi, w.boundary, None, xb, lam, K, res_trace=trace)
+    # config 2 (2D, 1024 samples, 50 circles, 50 iterations): the former headline
+    w2 = wl.config2(batch=args.batch)
+    c2 = projection_leg(w2, K, args.steps, args.warmup)
+    cfg2 = {"workload": "2D point robot, 50 static circles r~U(0.3,0.8) m in 30x30 m, Bernstein degree 10, "
+                        f"100 steps over 30 s, batch {w2.batch}, {K} AM iterations, cold start, fp32",
+            "value": c2["value"], "ms_per_step": c2["ms_per_step"], "roofline": c2["roofline"]}
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    # per-launch kernel time (events on the launch stream), then the timed region
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    t_start.record(stream)
-    for i in range(args.steps):
-        xb.copy_(xi)
-        lam.zero_()
-        ev[i][0].record(stream)
-        solver.project(xi, w.boundary, None, xb, lam, K, res_trace=trace)
-        ev[i][1].record(stream)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    total_ms = t_start.elapsed_time(t_end)
-    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    ms_per_step = total_ms / args.steps
-    value = w.batch * K / (ms_per_step * 1e-3)
-
-    ops = algorithmic_ops_per_traj_iter(w) * w.batch * K
-    achieved = ops / (launch_ms * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12,
-                "unit": "Tops/s", "frac": achieved / PEAK_VALU_OPS,
-                "traffic": TRAFFIC_BYTES_PER_LAUNCH,
-                "kernel": ("am_project_kernel<float,2,12>" if kern == 0 else
-                           "am_wave_kernel<float,2,12,2>") + f", {spw} sample(s)/workgroup",
-                "ops_per_traj_iter": algorithmic_ops_per_traj_iter(w),
-                "launch_ms": launch_ms}
-
-    ttr = time_to_residual(args, w, solver, xi, obs, stream) if args.ttr_cap > 0 else None
+    ttr = (time_to_residual(args, w2, c2["solver"], c2["xi"], c2["obs"], torch.cuda.current_stream())
+           if args.ttr_cap > 0 else None)
+    c2["solver"].close()
     ragged = ragged_bench(args) if args.ragged_problems > 0 else None
     cem_out = cem_bench(args) if args.cem_calls > 0 else None
     prec_out = precision_bench(args) if args.precision_steps > 0 else None
@@ -538,26 +733,28 @@ def main():
 
     out = {
         "metric": "traj-iters/s & time-to-residual<=1e-3, learned warm-start vs cold, 1 MI355X",
-        "value": value, "unit": "traj-iters/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "value": h["value"], "unit": "traj-iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": h["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "2D point robot, 50 static circles r~U(0.3,0.8) m in 30x30 m, "
-                               "Bernstein degree 10, 100 steps over 30 s, batch 1024, "
-                               "50 AM iterations, cold start",
-                   "batch": w.batch, "iterations": K, "obstacles": w.n_obs,
-                   "timesteps": w.n_steps, "degree": w.degree, "precision": "fp32"},
+        "config": {"workload": "config 3: 3D point robot, 200 static ellipsoids (semi-axes U(0.3,1.0) m "
+                               "each) in 20x20x6 m, Bernstein degree 15, 150 steps over 20 s, batch 4096, "
+                               f"{K} AM iterations, cold start, fp32",
+                   "batch": w3.batch, "iterations": K, "obstacles": w3.n_obs,
+                   "timesteps": w3.n_steps, "degree": w3.degree, "precision": "fp32"},
         "roofline": roofline,
+        "counters": counters,
+        "config2": cfg2,
         "time_to_residual": ttr,
         "ragged": ragged,
         "cem": cem_out,
         "precision_cfg3": prec_out,
         "polar_materialised": polar_out,
-        "wall_s_timed_region": wall,
+        "wall_s_timed_region": h["wall"],
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, K)
+        out["cpu_baseline"] = cpu_baseline(w3, K)
     print(json.dumps(out), flush=True)
-    solver.close()
+    h["solver"].close()
 
 
 if __name__ == "__main__":
