@@ -36,6 +36,17 @@ class Problem(ctypes.Structure):
     ]
 
 
+class Cont(ctypes.Structure):
+    """Penalty continuation parameters (see orc_project_cont)."""
+    _fields_ = [
+        ("n_levels", ctypes.c_int),
+        ("growth", ctypes.c_double),
+        ("window", ctypes.c_int),
+        ("stall", ctypes.c_double),
+        ("tol", ctypes.c_double),
+    ]
+
+
 def build(force: bool = True) -> str:
     """Compile the C oracle with gcc (-O2, no fast-math, OpenMP over trajectories)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -82,6 +93,9 @@ def lib():
                                          ctypes.c_int]
         L.orc_residuals_agents.argtypes = [pp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp,
                                            dp, dp, dp, dp, dp, ctypes.c_int]
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.orc_project_cont.argtypes = [pp, ctypes.POINTER(Cont), ctypes.c_int, dp, dp, dp, dp, dp, dp, dp,
+                                       ip, ip, dp, ctypes.c_int, dp, ip, ctypes.c_int]
         L.orc_set_fault.argtypes = [ctypes.c_int]
         L.orc_set_fault.restype = None
         L.orc_max_threads.restype = ctypes.c_int
@@ -287,3 +301,36 @@ def residuals_agents(w, xi_bar, n_threads=0):
     if rc != 0:
         raise ValueError("oracle rejected the problem")
     return r2, mx
+
+
+# ------------------------------------------------------- rho-continuation --
+
+
+def project_cont(w, n_levels, growth, window, stall, tol, iters=None, xi_bar=None, lam=None,
+                 state=None, n_threads=0, xi=None):
+    """AM projection with penalty continuation (orc_project_cont).  state: None (cold:
+    level 0, count 0, no reference) or (level [B] int, count [B] int, ref [B] float).
+    Returns (xi_bar, lam, res_trace [K, B], level_trace [K, B], (level, count, ref))."""
+    pr = problem_of(w)
+    xi = _f64(w.xi if xi is None else xi)
+    B = xi.shape[0]
+    xb = _f64(xi if xi_bar is None else xi_bar).copy()
+    lm = np.zeros_like(xi) if lam is None else _f64(lam).copy()
+    K = int(w.iters if iters is None else iters)
+    if state is None:
+        lev, cnt, ref = np.zeros(B, np.int32), np.zeros(B, np.int32), np.zeros(B)
+    else:
+        lev, cnt, ref = (np.ascontiguousarray(state[0], np.int32).copy(),
+                         np.ascontiguousarray(state[1], np.int32).copy(), _f64(state[2]).copy())
+    tr = np.zeros((max(K, 1), B)); lt = np.zeros((max(K, 1), B), np.int32)
+    cc = Cont(int(n_levels), float(growth), int(window), float(stall), float(tol))
+    ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    rc = lib().orc_project_cont(ctypes.byref(pr), ctypes.byref(cc), B, _p(xi),
+                                _p(_f64(w.obs_centre).reshape(-1, w.dims)),
+                                _p(_f64(w.obs_vel).reshape(-1, w.dims)),
+                                _p(_f64(w.obs_axes).reshape(-1, w.dims)), _p(_f64(w.boundary)),
+                                _p(xb), _p(lm), ip(lev), ip(cnt), _p(ref), K, _p(tr), ip(lt),
+                                int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle rejected the problem or the continuation")
+    return xb, lm, tr[:K], lt[:K], (lev, cnt, ref)

@@ -466,6 +466,106 @@ done:
     return rc;
 }
 
+/* ------------------------------------------------------ rho-continuation -- */
+
+/* Penalty continuation (thesis ch. 4, Alg 1: the penalty weights are raised while the
+ * residuals stay above a threshold; ch. 7: the QP inverse is precomputed for ten
+ * increasing penalties and used in later iterations).  Readings taken here: a ladder of
+ * n_levels penalties rho_l = rho * growth^l; per trajectory a level (starting at the
+ * state passed in), an iteration count since the last check and the residual at that
+ * check (0 = none yet).  Iteration k runs steps 1-6 with rho_level in the multiplier
+ * update and in the QP (its own KKT matrix [I + rho_l F^T F, A^T; A, 0]); then the count
+ * is raised, and when it reaches `window` the check compares res^k with the reference:
+ * if a reference exists, res^k > tol and res^k > stall * reference, the level goes up
+ * by one (at most n_levels - 1); the reference becomes res^k and the count restarts.
+ * With one level (or growth 1) this is orc_project exactly. */
+typedef struct {
+    int n_levels;      /* >= 1 */
+    double growth;     /* rho_l = rho * growth^l */
+    int window;        /* iterations between checks, >= 1 */
+    double stall;      /* raise the level when res > stall * res at the previous check */
+    double tol;        /* ... and res > tol */
+} orc_cont;
+
+int orc_project_cont(const orc_problem *pr, const orc_cont *cc, int B, const double *xi,
+                     const double *oc, const double *ow, const double *os, const double *bnd,
+                     double *xi_bar, double *lam, int *level, int *count, double *ref, int iters,
+                     double *res_trace, int *level_trace, int n_threads)
+{
+    int D = pr->dims, nv = pr->degree + 1, np = pr->n_steps, N = nv + 4, L = cc->n_levels;
+    double *P, *Pd, *Pdd, *K, *rhos;
+    int *piv, rc = 0, i, l;
+    orc_ctx c;
+    if ((D != 2 && D != 3) || pr->degree < 3 || np < 2 || B < 0 || iters < 0 || L < 1 ||
+        cc->window < 1 || !(cc->growth >= 1.0))
+        return -1;
+    P = malloc(sizeof(double) * np * nv);
+    Pd = malloc(sizeof(double) * np * nv);
+    Pdd = malloc(sizeof(double) * np * nv);
+    K = malloc(sizeof(double) * N * N * L);
+    piv = malloc(sizeof(int) * N * L);
+    rhos = malloc(sizeof(double) * L);
+    if (orc_bernstein(pr->degree, np, pr->horizon, P, Pd, Pdd) != 0) {
+        rc = -1;
+        goto done;
+    }
+    /* one KKT matrix and LU per penalty of the ladder */
+    for (l = 0; l < L; ++l) {
+        orc_problem pl = *pr;
+        rhos[l] = pr->rho * pow(cc->growth, (double)l);
+        pl.rho = rhos[l];
+        if (orc_kkt_matrix(&pl, K + (size_t)l * N * N) != 0 ||
+            orc_lu_factor(N, K + (size_t)l * N * N, piv + (size_t)l * N) != 0) {
+            rc = -1;
+            goto done;
+        }
+    }
+    c.pr = pr; c.nv = nv; c.np = np; c.D = D;
+    c.P = P; c.Pd = Pd; c.Pdd = Pdd; c.oc = oc; c.ow = ow; c.os = os;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (i = 0; i < B; ++i) {
+        double *xb = xi_bar + (size_t)i * D * nv, *lm = lam + (size_t)i * D * nv;
+        const double *x0 = xi + (size_t)i * D * nv;
+        double *FtE = malloc(sizeof(double) * D * nv), *FtR = malloc(sizeof(double) * D * nv);
+        double *rhs = malloc(sizeof(double) * N);
+        int k, ax, m;
+        for (k = 0; k < iters; ++k) {
+            double r2, res;
+            const int lv = level[i];
+            const double rho = rhos[lv];
+            const double *Kl = K + (size_t)lv * N * N;
+            const int *pl = piv + (size_t)lv * N;
+            polar_and_residual(&c, xb, FtE, FtR, &r2, NULL);
+            res = sqrt(r2);
+            if (res_trace) res_trace[(size_t)k * B + i] = res;
+            if (level_trace) level_trace[(size_t)k * B + i] = lv;
+            for (m = 0; m < D * nv; ++m) lm[m] -= rho * FtR[m];
+            for (ax = 0; ax < D; ++ax) {
+                for (m = 0; m < nv; ++m) rhs[m] = x0[ax * nv + m] + lm[ax * nv + m] + rho * FtE[ax * nv + m];
+                for (m = 0; m < 4; ++m) rhs[nv + m] = bnd[ax * 4 + m];
+                orc_lu_solve(N, Kl, pl, rhs);
+                for (m = 0; m < nv; ++m) xb[ax * nv + m] = rhs[m];
+            }
+            /* the check after the iteration decides the penalty of the next one */
+            count[i] += 1;
+            if (count[i] >= cc->window) {
+                int up = ref[i] > 0.0 && res > cc->tol && res > cc->stall * ref[i];
+                if (g_fault == 9) up = ref[i] > 0.0 && res > cc->tol && res < cc->stall * ref[i];
+                if (up && level[i] < L - 1) level[i] += 1;
+                ref[i] = res;
+                count[i] = 0;
+            }
+        }
+        free(FtE); free(FtR); free(rhs);
+    }
+done:
+    free(P); free(Pd); free(Pdd); free(K); free(piv); free(rhos);
+    return rc;
+}
+
 /* Steps 1-4 only, at the given coefficients: res_l2[B], res_max[B]. */
 int orc_residuals(const orc_problem *pr, int B, const double *xi_bar, const double *oc,
                   const double *ow, const double *os, double *res_l2, double *res_max,
