@@ -167,6 +167,59 @@ def ttr_scene(w, solver, xi, obs, net, cap, stream, tol=1e-3, reps=20):
     return out
 
 
+CONTINUATION = (10, 2.0, 10, 0.9, 1e-3)   # levels, growth, window, stall ratio, tol
+
+
+def continuation_leg(w, cap, stream, tol=1e-3, reps=10):
+    """The benchmark scene from a cold start, plain and with the penalty continuation
+    (a ladder of 10 penalties rho 2^l, a check every 10 iterations raising a sample's
+    penalty while its residual is above tol and above 0.9 x its residual at the
+    previous check): the first iteration at which the batch-median residual is <= tol,
+    the iteration from which it stays <= tol up to the cap, the fraction of samples
+    within tol at the cap, and the graph-replayed time of the projection to the cap."""
+    import torch
+    from paper_2408_10731_amd import trajam as tj
+    solver = tj.Solver.for_workload(w, precision="fp32")
+    xi, obs = tj.device_workload(w, torch.float32)
+    solver.set_launch(1, 1)
+    solver.set_obstacles(obs)
+    solver.set_continuation(*CONTINUATION)
+    xb, lam = xi.clone(), torch.zeros_like(xi)
+    state = solver.cont_state(w.batch)
+    tr = torch.zeros((cap, w.batch), dtype=torch.float32, device="cuda")
+
+    def metrics(trace):
+        med = np.median(trace, axis=1)
+        hit = np.nonzero(med <= tol)[0]
+        bad = np.nonzero(med > tol)[0]
+        stay = (None if bad.size and bad[-1] == len(med) - 1 else (int(bad[-1]) + 2 if bad.size else 1))
+        return {"first": int(hit[0]) + 1 if hit.size else None, "stays_from": stay,
+                "frac_within_tol_at_cap": float(np.mean(trace[-1] <= tol)),
+                "median_at_cap": float(med[-1])}
+
+    out = {"ladder": dict(zip(("levels", "growth", "window", "stall_ratio", "tol"), CONTINUATION)), "cap": cap}
+    for name, cont in (("plain", False), ("continuation", True)):
+        def run():
+            xb.copy_(xi)
+            lam.zero_()
+            if cont:
+                state.zero_()
+                solver.project_continuation(xi, w.boundary, None, xb, lam, state, cap, res_trace=tr)
+            else:
+                solver.project(xi, w.boundary, None, xb, lam, cap, res_trace=tr)
+        run()
+        torch.cuda.synchronize()
+        m = metrics(tr.cpu().numpy())
+        g = _graph(run)
+        m["ms_to_cap"] = _time(g.replay, reps, stream)
+        del g
+        if cont:
+            m["levels_at_cap"] = np.bincount(solver.cont_levels(state)[0], minlength=CONTINUATION[0]).tolist()
+        out[name] = m
+    solver.close()
+    return out
+
+
 def time_to_residual(args, w, solver, xi, obs, stream, tol=1e-3, net=None, info=None):
     """The learned warm start against the cold start: on the benchmark scene, and summed
     over the 16 held-out scenes 90,001-90,016 of the same family (scene seeds disjoint from the training
@@ -725,6 +778,7 @@ def main():
 
     ttr = (time_to_residual(args, w2, c2["solver"], c2["xi"], c2["obs"], torch.cuda.current_stream())
            if args.ttr_cap > 0 else None)
+    cont = continuation_leg(w2, args.ttr_cap, torch.cuda.current_stream()) if args.ttr_cap > 0 else None
     c2["solver"].close()
     ragged = ragged_bench(args) if args.ragged_problems > 0 else None
     cem_out = cem_bench(args) if args.cem_calls > 0 else None
@@ -745,6 +799,7 @@ def main():
         "counters": counters,
         "config2": cfg2,
         "time_to_residual": ttr,
+        "continuation": cont,
         "ragged": ragged,
         "cem": cem_out,
         "precision_cfg3": prec_out,

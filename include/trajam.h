@@ -155,6 +155,53 @@ trajam_status trajam_project(trajam_solver *s, int32_t batch, const void *xi,
                              void *lambda, int32_t iters, void *res_trace, uint32_t *flags,
                              void *stream);
 
+/* ---- penalty continuation ------------------------------------------------------
+ * Thesis ch. 4 (Alg 1) raises the penalty weights while the residuals stay above a
+ * threshold; ch. 7 precomputes the QP inverse for ten increasing penalties and uses
+ * them in later iterations.  Here: a ladder of `levels` penalties rho * growth^l
+ * (l = 0 .. levels-1), each with its own fixed QP operator computed in double on the
+ * host; every sample carries a level, an iteration count and a reference residual.
+ * An iteration runs steps (a), (c), (b) with its level's penalty in the multiplier
+ * update and its level's operator in the QP; then the count rises, and when it
+ * reaches `window` the level goes up by one (at most levels - 1) if the iteration's
+ * residual is above `tol` and above stall_ratio times the reference (0 before the
+ * first check), the reference becomes that residual and the count restarts. */
+#define TRAJAM_CONT_MAX_LEVELS 16
+typedef struct {
+    int32_t levels;      /* 1 .. TRAJAM_CONT_MAX_LEVELS; 1 = the plain iteration */
+    double growth;       /* >= 1: rho_l = rho * growth^l */
+    int32_t window;      /* >= 1: iterations between checks */
+    double stall_ratio;  /* >= 0: a check raises the level when res > stall_ratio * reference */
+    double tol;          /* >= 0: ... and res > tol */
+} trajam_continuation;
+
+/* Per-sample state, caller-owned device memory [batch]; zero it before a sample's first
+ * call (level 0, no reference) and pass it back unchanged to continue. */
+typedef struct {
+    int32_t level;   /* index into the ladder */
+    int32_t count;   /* iterations since the last check */
+    double ref;      /* residual at the last check; 0 before the first */
+} trajam_cont_state;
+
+/* Computes and uploads the ladder's QP operators (host FP64, each checked like
+ * trajam_init's) and enables trajam_project_continuation; c == NULL disables it.
+ * Single robot, precision FP64 or FP32.  Allocates device memory (call at set-up).
+ * Errors: INVALID (bad parameters), UNSUPPORTED (multi-agent or BF16_REFINE),
+ * NUMERIC (a level's QP step does not contract in the solver's precision), DEVICE. */
+trajam_status trajam_set_continuation(trajam_solver *s, const trajam_continuation *c);
+
+/* trajam_project with the penalty continuation set by trajam_set_continuation; the
+ * iteration's state is (xi_bar, lambda, state), so a call with iters = a followed by
+ * one with iters = b equals one with a + b.  Runs the wave-per-sample kernel (its tuned
+ * samples per workgroup when that variant is the tuned one).  Arguments and errors as
+ * trajam_project, plus state (device, [batch] trajam_cont_state, in/out) and INVALID
+ * when no continuation is set. */
+trajam_status trajam_project_continuation(trajam_solver *s, int32_t batch, const void *xi,
+                                          const double *boundary_host, const void *obs_centre,
+                                          const void *obs_vel, const void *obs_axes, void *xi_bar,
+                                          void *lambda, trajam_cont_state *state, int32_t iters,
+                                          void *res_trace, uint32_t *flags, void *stream);
+
 /* Steps (a) and the residual norm only, at the given coefficients, without
  * touching any multiplier (thesis Alg 3, "compute the residuals set r").
  *   xi_bar   device, [batch][dims][n+1] ([batch][N][dims][n+1] for N > 1 agents)

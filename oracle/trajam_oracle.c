@@ -473,12 +473,14 @@ done:
  * increasing penalties and used in later iterations).  Readings taken here: a ladder of
  * n_levels penalties rho_l = rho * growth^l; per trajectory a level (starting at the
  * state passed in), an iteration count since the last check and the residual at that
- * check (0 = none yet).  Iteration k runs steps 1-6 with rho_level in the multiplier
- * update and in the QP (its own KKT matrix [I + rho_l F^T F, A^T; A, 0]); then the count
- * is raised, and when it reaches `window` the check compares res^k with the reference:
- * if a reference exists, res^k > tol and res^k > stall * reference, the level goes up
- * by one (at most n_levels - 1); the reference becomes res^k and the count restarts.
- * With one level (or growth 1) this is orc_project exactly. */
+ * check (0 before the first check).  Iteration k runs steps 1-6 with rho_level in the
+ * multiplier update and in the QP (its own KKT matrix [I + rho_l F^T F, A^T; A, 0]);
+ * then the count is raised, and when it reaches `window` the check compares res^k with
+ * the reference: if res^k > tol and res^k > stall * reference, the level goes up by one
+ * (at most n_levels - 1); the reference becomes res^k and the count restarts.  (So the
+ * first check raises the level whenever the residual is still above tol: the threshold
+ * rule of Alg 1, with no earlier residual to show progress.)  With one level (or
+ * growth 1) this is orc_project exactly. */
 typedef struct {
     int n_levels;      /* >= 1 */
     double growth;     /* rho_l = rho * growth^l */
@@ -552,8 +554,8 @@ int orc_project_cont(const orc_problem *pr, const orc_cont *cc, int B, const dou
             /* the check after the iteration decides the penalty of the next one */
             count[i] += 1;
             if (count[i] >= cc->window) {
-                int up = ref[i] > 0.0 && res > cc->tol && res > cc->stall * ref[i];
-                if (g_fault == 9) up = ref[i] > 0.0 && res > cc->tol && res < cc->stall * ref[i];
+                int up = res > cc->tol && res > cc->stall * ref[i];
+                if (g_fault == 9) up = res > cc->tol && res < cc->stall * ref[i];
                 if (up && level[i] < L - 1) level[i] += 1;
                 ref[i] = res;
                 count[i] = 0;

@@ -51,6 +51,20 @@ struct AmArgs {
     T pair_r;               // combined radius of a pair (twice the agent radius)
     const T *W2;            // [NVP][NVP] QP operator of H + n_agents rho P^T P (agent deviations)
     const T *xiB_ag;        // [n_agents][D][4] boundary coefficients per agent
+    // Penalty continuation (single robot, wave-per-sample kernel; cont_levels = 0: off):
+    // per-level penalties and QP operators, and the per-sample state ContState[batch].
+    int cont_levels, cont_window;
+    T cont_stall, cont_tol;
+    const T *cont_rho;      // [levels]
+    const T *cont_W;        // [levels][NVP][NVP]
+    void *cont_state;       // [batch] ContState, in/out
+};
+
+// Per-sample state of the penalty continuation (the C ABI's trajam_cont_state).
+struct ContState {
+    int32_t level;   // index into the penalty ladder
+    int32_t count;   // iterations since the last check
+    double ref;      // residual at the last check (0 before the first)
 };
 
 // Obstacle fields per obstacle in the multi-agent kernels' LDS stage, and the largest

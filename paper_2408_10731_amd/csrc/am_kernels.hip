@@ -1342,7 +1342,23 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
     CullCache<T, D, TPL> ccache;   // obstacle candidates kept across iterations
     T res_first = T(0), res_last = T(0);
     bool nonfinite = false;
+    // Penalty continuation (thesis ch. 4 Alg 1, ch. 7): this sample's level on the
+    // penalty ladder, the iterations since the last check and the residual then.  The
+    // level's penalty enters the multiplier update and its QP operator the QP; after
+    // each iteration the count rises, and every cont_window iterations the level goes
+    // up by one when the residual is above cont_tol and above cont_stall times the
+    // reference (0 before the first check).  All wave-uniform.
+    const bool cont = a.cont_levels > 0;
+    ContState *cst = cont ? reinterpret_cast<ContState *>(a.cont_state) + sample : nullptr;
+    int c_lev = 0, c_cnt = 0;
+    T c_ref = T(0);
+    if (cont) {
+        c_lev = cst->level;
+        c_cnt = cst->count;
+        c_ref = (T)cst->ref;
+    }
     for (int k = 0; k < a.iters; ++k) {
+        const T rho = cont ? a.cont_rho[c_lev] : a.rho;
         // ---- step (a): waypoints and polar steps
         T p[TPL][D], v[TPL][D], acc[TPL][D];
 #pragma unroll
@@ -1422,8 +1438,8 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
         if (owner) {
             T gv = T(0);
             if (o_real) {
-                lam_o = fma(-a.rho, ftr, lam_o);
-                gv = o_free ? (xi_o - xb_o + lam_o - a.rho * ftr) : (bnd_o - xb_o);
+                lam_o = fma(-rho, ftr, lam_o);
+                gv = o_free ? (xi_o - xb_o + lam_o - rho * ftr) : (bnd_o - xb_o);
             }
             gs[o] = gv;
         }
@@ -1433,6 +1449,18 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
             if (k == 0) res_first = rs;
             res_last = rs;
             nonfinite = nonfinite || !isfinite(rs);
+        }
+        const int c_lev_k = c_lev;   // the level this iteration's QP uses
+        if (cont) {
+            // the check after the iteration decides the next one's penalty (lane 0's
+            // residual, so the decision is uniform)
+            const T rs = readlane_t<T>(sqrt(r2w), 0);
+            if (++c_cnt >= a.cont_window) {
+                if (rs > a.cont_tol && rs > a.cont_stall * c_ref && c_lev < a.cont_levels - 1)
+                    ++c_lev;
+                c_ref = rs;
+                c_cnt = 0;
+            }
         }
         wave_lds_sync();
         // ---- step (b): the fixed-matrix QP on the defect (eq affine_trans)
@@ -1473,11 +1501,17 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
             else if (o_real) xb_o = bnd_o;
         } else {
             if (o_free) {
-                const T *wr = wmat + (o_m - 3) * NVP;
                 const T *g = gs + o_ax * NVP;
                 T d = T(0);
+                if (cont) {   // the level's operator, from the (cached) table
+                    const T *wr = a.cont_W + ((size_t)c_lev_k * NVP + (o_m - 3)) * NVP;
 #pragma unroll
-                for (int m = 0; m < NVP; ++m) d = fma(wr[m], g[m], d);
+                    for (int m = 0; m < NVP; ++m) d = fma(wr[m], g[m], d);
+                } else {
+                    const T *wr = wmat + (o_m - 3) * NVP;
+#pragma unroll
+                    for (int m = 0; m < NVP; ++m) d = fma(wr[m], g[m], d);
+                }
                 xb_o += d;
             } else if (o_real) {
                 xb_o = bnd_o;
@@ -1491,6 +1525,11 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
         a.xb[gidx] = xb_o;
         a.lam[gidx] = lam_o;
         nonfinite = nonfinite || !isfinite(xb_o) || !isfinite(lam_o);
+    }
+    if (cont && lane == 0) {
+        cst->level = c_lev;
+        cst->count = c_cnt;
+        cst->ref = (double)c_ref;
     }
     if (a.flags && a.iters > 0) {
         const bool anyb = __any(nonfinite);

@@ -67,6 +67,11 @@ struct trajam_solver {
     double qp_rho = 0.0;     // contraction of the QP step in the solver's precision
     void *d_xiBag = nullptr; // [n_agents][D][4] boundary coefficients per agent
     std::vector<double> bnd_cache;  // boundary rows the device copy was built from
+    // penalty continuation (trajam_set_continuation)
+    trajam_continuation cont{};
+    bool cont_on = false;
+    void *d_cont_W = nullptr;    // [levels][nvp][nvp]
+    void *d_cont_rho = nullptr;  // [levels]
     std::string err;
 };
 
@@ -436,6 +441,8 @@ void trajam_destroy(trajam_solver *s)
     if (s->d_Hff) (void)hipFree(s->d_Hff);
     if (s->d_W2) (void)hipFree(s->d_W2);
     if (s->d_xiBag) (void)hipFree(s->d_xiBag);
+    if (s->d_cont_W) (void)hipFree(s->d_cont_W);
+    if (s->d_cont_rho) (void)hipFree(s->d_cont_rho);
     delete s;
 }
 
@@ -791,6 +798,132 @@ extern "C" trajam_status trajam_project(trajam_solver *s, int32_t batch, const v
         a.res = (float *)res_trace;
         a.flags = flags;
         e = trajam::launch_project_f32(p.dims, s->nvp, s->variant, p.precision == TRAJAM_BF16_REFINE, a, st);
+    }
+    if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("AM launch: ") + hipGetErrorString(e));
+    return TRAJAM_OK;
+}
+
+extern "C" trajam_status trajam_set_continuation(trajam_solver *s, const trajam_continuation *c)
+{
+    if (!s) return TRAJAM_ERR_INVALID;
+    s->err.clear();
+    if (!c) {   // off
+        s->cont_on = false;
+        return TRAJAM_OK;
+    }
+    const trajam_problem &p = s->prob;
+    if (p.n_agents != 1) return fail(s, TRAJAM_ERR_UNSUPPORTED, "penalty continuation is single-robot");
+    if (p.precision == TRAJAM_BF16_REFINE)
+        return fail(s, TRAJAM_ERR_UNSUPPORTED, "penalty continuation needs precision FP64 or FP32");
+    if (c->levels < 1 || c->levels > TRAJAM_CONT_MAX_LEVELS || !(c->growth >= 1.0) || !std::isfinite(c->growth) ||
+        c->window < 1 || !(c->stall_ratio >= 0.0) || !std::isfinite(c->stall_ratio) || !(c->tol >= 0.0) ||
+        !std::isfinite(c->tol))
+        return fail(s, TRAJAM_ERR_INVALID,
+                    "continuation: levels in [1, 16], growth >= 1, window >= 1, stall_ratio >= 0, tol >= 0");
+    const int n = p.degree, nv = n + 1, nf = nv - 4, nvp = s->nvp, L = c->levels;
+    std::vector<double> Wt((size_t)L * nvp * nvp, 0.0), rt(L);
+    for (int l = 0; l < L; ++l) {
+        trajam_problem pl = p;
+        pl.rho = p.rho * std::pow(c->growth, (double)l);   // the ladder rho * growth^l
+        rt[l] = pl.rho;
+        std::vector<double> P, Pd, Pdd, H, Wff, W;
+        std::string msg;
+        trajam_status st = precompute(pl, P, Pd, Pdd, H, Wff, W, msg);
+        double qr = 0.0;
+        if (st == TRAJAM_OK) st = problem_contraction(pl, P, H, Wff, qr, msg);
+        if (st == TRAJAM_OK && !(qr < kMaxQpContraction)) {
+            st = TRAJAM_ERR_NUMERIC;
+            msg = "the QP step of penalty level " + std::to_string(l) + " does not contract in this precision";
+        }
+        if (st != TRAJAM_OK) return fail(s, st, msg);
+        for (int a = 0; a < nf; ++a)
+            for (int m = 0; m < nv; ++m) Wt[((size_t)l * nvp + a) * nvp + m] = W[(size_t)a * nv + m];
+    }
+    if (s->d_cont_W) (void)hipFree(s->d_cont_W);
+    if (s->d_cont_rho) (void)hipFree(s->d_cont_rho);
+    s->d_cont_W = s->d_cont_rho = nullptr;
+    const bool f64 = p.precision == TRAJAM_FP64;
+    hipError_t e = f64 ? upload<double>(&s->d_cont_W, Wt) : upload<float>(&s->d_cont_W, Wt);
+    if (e == hipSuccess) e = f64 ? upload<double>(&s->d_cont_rho, rt) : upload<float>(&s->d_cont_rho, rt);
+    if (e != hipSuccess) {
+        s->cont_on = false;
+        return fail(s, TRAJAM_ERR_DEVICE, std::string("continuation tables: ") + hipGetErrorString(e));
+    }
+    s->cont = *c;
+    s->cont_on = true;
+    return TRAJAM_OK;
+}
+
+extern "C" trajam_status trajam_project_continuation(trajam_solver *s, int32_t batch, const void *xi,
+                                                     const double *boundary_host, const void *obs_centre,
+                                                     const void *obs_vel, const void *obs_axes, void *xi_bar,
+                                                     void *lambda, trajam_cont_state *state, int32_t iters,
+                                                     void *res_trace, uint32_t *flags, void *stream)
+{
+    if (!s) return TRAJAM_ERR_INVALID;
+    s->err.clear();
+    if (!s->cont_on) return fail(s, TRAJAM_ERR_INVALID, "no penalty continuation set (trajam_set_continuation)");
+    if (batch < 0 || iters < 0) return fail(s, TRAJAM_ERR_INVALID, "batch and iters must be >= 0");
+    if (batch > s->prob.max_batch) return fail(s, TRAJAM_ERR_CAPACITY, "batch > max_batch");
+    if (batch == 0 || iters == 0) return TRAJAM_OK;
+    if (!xi || !xi_bar || !lambda || !boundary_host || !state)
+        return fail(s, TRAJAM_ERR_INVALID, "xi, xi_bar, lambda, state and boundary must not be NULL");
+    for (int i = 0; i < s->prob.dims * 4; ++i)
+        if (!std::isfinite(boundary_host[i])) return fail(s, TRAJAM_ERR_INVALID, "non-finite boundary value");
+    hipStream_t st = (hipStream_t)stream;
+    trajam_status ps = pack(s, obs_centre, obs_vel, obs_axes, st);
+    if (ps != TRAJAM_OK) return ps;
+    const trajam_problem &p = s->prob;
+    // the wave-per-sample kernel carries the continuation; its tuned shape when it is
+    // the tuned variant, one sample a workgroup otherwise
+    const int spw = s->variant == TRAJAM_KERNEL_WAVE ? s->tb : 1;
+    hipError_t e;
+    if (p.precision == TRAJAM_FP64) {
+        AmArgs<double> a;
+        fill_args(s, a, batch, iters);
+        a.tb = spw;
+        a.dynamic = s->dynamic;
+        for (int ax = 0; ax < p.dims; ++ax) {
+            double c4[4];
+            boundary_coeffs(p.degree, p.horizon, boundary_host + 4 * ax, c4);
+            for (int i = 0; i < 4; ++i) a.xiB[ax][i] = c4[i];
+        }
+        a.xi = (const double *)xi;
+        a.xb = (double *)xi_bar;
+        a.lam = (double *)lambda;
+        a.res = (double *)res_trace;
+        a.flags = flags;
+        a.cont_levels = s->cont.levels;
+        a.cont_window = s->cont.window;
+        a.cont_stall = s->cont.stall_ratio;
+        a.cont_tol = s->cont.tol;
+        a.cont_rho = (const double *)s->d_cont_rho;
+        a.cont_W = (const double *)s->d_cont_W;
+        a.cont_state = state;
+        e = trajam::launch_project_f64(p.dims, s->nvp, TRAJAM_KERNEL_WAVE, a, st);
+    } else {
+        AmArgs<float> a;
+        fill_args(s, a, batch, iters);
+        a.tb = spw;
+        a.dynamic = s->dynamic;
+        for (int ax = 0; ax < p.dims; ++ax) {
+            double c4[4];
+            boundary_coeffs(p.degree, p.horizon, boundary_host + 4 * ax, c4);
+            for (int i = 0; i < 4; ++i) a.xiB[ax][i] = (float)c4[i];
+        }
+        a.xi = (const float *)xi;
+        a.xb = (float *)xi_bar;
+        a.lam = (float *)lambda;
+        a.res = (float *)res_trace;
+        a.flags = flags;
+        a.cont_levels = s->cont.levels;
+        a.cont_window = s->cont.window;
+        a.cont_stall = (float)s->cont.stall_ratio;
+        a.cont_tol = (float)s->cont.tol;
+        a.cont_rho = (const float *)s->d_cont_rho;
+        a.cont_W = (const float *)s->d_cont_W;
+        a.cont_state = state;
+        e = trajam::launch_project_f32(p.dims, s->nvp, TRAJAM_KERNEL_WAVE, false, a, st);
     }
     if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("AM launch: ") + hipGetErrorString(e));
     return TRAJAM_OK;

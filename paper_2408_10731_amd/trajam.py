@@ -49,7 +49,7 @@ EXPORTS = [
     "trajam_mlp_backward", "trajam_mlp_backward_noalloc", "trajam_mlp_infer", "trajam_mlp_pack_infer", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
     "trajam_warm_apply", "trajam_warm_fallback", "trajam_set_obstacles", "trajam_autotune",
     "trajam_ragged_plan_create", "trajam_ragged_launch", "trajam_ragged_plan_destroy", "trajam_polar",
-    "trajam_qp_contraction",
+    "trajam_qp_contraction", "trajam_set_continuation", "trajam_project_continuation",
     "trajam_status_string", "trajam_last_error",
 ]
 
@@ -76,6 +76,19 @@ class Problem(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("obstacle_model", ctypes.c_int32),
     ]
+
+
+class Continuation(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int32),
+        ("growth", ctypes.c_double),
+        ("window", ctypes.c_int32),
+        ("stall_ratio", ctypes.c_double),
+        ("tol", ctypes.c_double),
+    ]
+
+
+CONT_MAX_LEVELS = 16
 
 
 class MlpShape(ctypes.Structure):
@@ -182,6 +195,11 @@ def load():
     L.trajam_ragged_plan_create.argtypes = [ctypes.POINTER(RaggedItem), ctypes.c_int32,
                                             ctypes.c_int32, ctypes.POINTER(vp)]
     L.trajam_ragged_launch.argtypes = [vp, vp]
+    L.trajam_set_continuation.argtypes = [vp, ctypes.POINTER(Continuation)]
+    L.trajam_set_continuation.restype = ctypes.c_int
+    L.trajam_project_continuation.argtypes = [vp, ctypes.c_int32, vp, dp, vp, vp, vp, vp, vp, vp,
+                                              ctypes.c_int32, vp, vp, vp]
+    L.trajam_project_continuation.restype = ctypes.c_int
     L.trajam_ragged_plan_destroy.argtypes = [vp]
     L.trajam_ragged_plan_destroy.restype = None
     for f in ("trajam_set_obstacles", "trajam_autotune", "trajam_ragged_plan_create",
@@ -232,6 +250,19 @@ def trajam_project(handle, batch, xi, boundary_host, obs_centre, obs_vel, obs_ax
     _check(load().trajam_project(handle, int(batch), xi, _dp(b), obs_centre, obs_vel,
                                  obs_axes, xi_bar, lam, int(iters), res_trace, flags, stream),
            handle)
+
+
+def trajam_set_continuation(handle, cont) -> None:
+    """cont: a Continuation, or None to switch the continuation off."""
+    _check(load().trajam_set_continuation(handle, None if cont is None else ctypes.byref(cont)), handle)
+
+
+def trajam_project_continuation(handle, batch, xi, boundary_host, obs_centre, obs_vel, obs_axes,
+                                xi_bar, lam, state, iters, res_trace, flags, stream) -> None:
+    b = np.ascontiguousarray(boundary_host, dtype=np.float64)
+    _check(load().trajam_project_continuation(handle, int(batch), xi, _dp(b), obs_centre, obs_vel,
+                                              obs_axes, xi_bar, lam, state, int(iters), res_trace,
+                                              flags, stream), handle)
 
 
 def trajam_residuals(handle, batch, xi_bar, obs_centre, obs_vel, obs_axes, res_l2, res_max,
@@ -500,6 +531,45 @@ class Solver:
         trajam_polar(self.handle, B, self._t(xi_bar, (B,) + self.sample_shape, "xi_bar"), c, v, a,
                      ptr(al), ptr(be), ptr(d), ptr(kin), st)
         return al, be, d, kin
+
+    def set_continuation(self, levels, growth, window, stall_ratio, tol):
+        """Penalty ladder rho * growth^l (l < levels) with the per-sample stall check;
+        levels = 0 switches it off."""
+        if levels == 0:
+            trajam_set_continuation(self.handle, None)
+        else:
+            trajam_set_continuation(self.handle, Continuation(int(levels), float(growth), int(window),
+                                                              float(stall_ratio), float(tol)))
+
+    @staticmethod
+    def cont_state(batch, device="cuda"):
+        """Zeroed per-sample continuation state: [batch, 2] float64 (16 bytes a sample:
+        int32 level, int32 count, then the float64 reference residual)."""
+        import torch
+        return torch.zeros((batch, 2), dtype=torch.float64, device=device)
+
+    @staticmethod
+    def cont_levels(state):
+        """(level, count, reference) of a state tensor, on the host."""
+        import torch
+        raw = state.detach().cpu().contiguous()
+        ints = raw.view(torch.int32).reshape(raw.shape[0], 4)
+        return ints[:, 0].numpy().copy(), ints[:, 1].numpy().copy(), raw[:, 1].numpy().copy()
+
+    def project_continuation(self, xi, boundary, obs, xi_bar, lam, state, iters, res_trace=None,
+                             flags=None, stream=None):
+        import torch
+        B = xi.shape[0]
+        shape = (B,) + self.sample_shape
+        c, v, a = self.obstacles(*(obs or ()))
+        if state.dtype != torch.float64 or tuple(state.shape) != (B, 2) or not state.is_cuda:
+            raise ValueError("state must be a [batch, 2] float64 CUDA tensor (Solver.cont_state)")
+        st = (stream or torch.cuda.current_stream()).cuda_stream
+        trajam_project_continuation(self.handle, B, self._t(xi, shape, "xi"), boundary, c, v, a,
+                                    self._t(xi_bar, shape, "xi_bar"), self._t(lam, shape, "lambda"),
+                                    state.data_ptr(), iters,
+                                    None if res_trace is None else self._t(res_trace, (iters, B), "res_trace"),
+                                    None if flags is None else flags.data_ptr(), st)
 
     def set_launch(self, kernel: int, samples_per_workgroup: int):
         trajam_set_launch(self.handle, kernel, samples_per_workgroup)
