@@ -481,7 +481,21 @@ trajam_status trajam_warm_apply(int32_t batch, int32_t dims, int32_t n_coeffs, c
                                 float out_scale, const float *xi, const float *xb, const float *lam,
                                 float *xb_out, float *lam_out, void *stream);
 
-/* Per-sample fallback: where res_warm[b] (residual of the jumped state xb) is not
+/* Fused warm jump on the matrix cores: trajam_warm_features, the network and
+ * trajam_warm_apply in one launch, 16 samples per workgroup, every product on
+ * v_mfma_f32_16x16x16_bf16 (weights and activations rounded to bf16, fp32 accumulation,
+ * bias and ReLU in fp32).  The parameters are first packed by trajam_warm_pack_mfma
+ * (flat fp32 layout in, the matrix-core operand order out; packed == NULL only returns
+ * the byte size in *packed_bytes).  Network: 1..4 layers, every width <= 256, width[0] =
+ * 2 dims nv, last width = dims nv.  Outputs must not alias xb or lam.
+ * Errors: INVALID, UNSUPPORTED (shape), DEVICE. */
+trajam_status trajam_warm_pack_mfma(const trajam_mlp_shape *shape, const float *params, void *packed,
+                                    int64_t *packed_bytes, void *stream);
+trajam_status trajam_warm_jump(const trajam_mlp_shape *shape, int32_t batch, int32_t dims, int32_t n_coeffs,
+                               const void *packed, float in_scale, float out_scale, const float *xi,
+                               const float *xb, const float *lam, float *xb_out, float *lam_out, void *stream);
+
+/* Per-sample fallback: where res_warm[b] (residual of the jumped state xb) is not/* Per-sample fallback: where res_warm[b] (residual of the jumped state xb) is not
  * below res_cold[b] (the probe's last residual), or is NaN, or the jumped state is
  * not finite, the sample keeps the probe state (xb = xb_src, lam = lam_src) and
  * flags[b] = TRAJAM_FLAG_COLD_FALLBACK; otherwise flags[b] = 0 (flags may be NULL).

@@ -142,6 +142,12 @@ hipError_t launch_mlp_infer(int n_layers, const int *width, int batch, const flo
 hipError_t launch_mlp_pack_infer(int n_layers, const int *width, const float *params, float *packed, hipStream_t st);
 hipError_t launch_warm_fallback(int batch, int dim, const float *rw, const float *rc, const float *xs,
                                 const float *ls, float *xb, float *lam, uint32_t *flags, hipStream_t st);
+// Fused warm jump on the matrix cores (features, network, jump; mlp_kernels.hip).
+long warm_jump_packed_bytes(int n_layers, const int *width);
+hipError_t launch_warm_pack_mfma(int n_layers, const int *width, const float *params, void *packed, hipStream_t st);
+hipError_t launch_warm_jump(int n_layers, const int *width, int batch, int dims, int nv, const void *packed,
+                            float in_scale, float out_scale, const float *xi, const float *xb, const float *lam,
+                            float *xbo, float *lamo, hipStream_t st);
 // Device address (on the current device) and size in floats of the backward pass's
 // static workspace; looked up once per device.
 hipError_t noalloc_scratch(float **ptr, size_t *n_floats);

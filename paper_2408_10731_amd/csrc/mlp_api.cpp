@@ -211,6 +211,38 @@ extern "C" trajam_status trajam_warm_apply(int32_t batch, int32_t dims, int32_t 
                "warm apply");
 }
 
+extern "C" trajam_status trajam_warm_pack_mfma(const trajam_mlp_shape *s, const float *params, void *packed,
+                                               int64_t *packed_bytes, void *stream)
+{
+    if (!shape_ok(s) || !packed_bytes) return fail(TRAJAM_ERR_INVALID, "invalid network shape or NULL size");
+    const long need = trajam::warm_jump_packed_bytes(s->n_layers, s->width);
+    if (need < 0) return fail(TRAJAM_ERR_UNSUPPORTED, "warm jump: 1..4 layers, every width <= 256");
+    *packed_bytes = need;
+    if (!packed) return TRAJAM_OK;   // size query
+    if (!params) return fail(TRAJAM_ERR_INVALID, "NULL parameters");
+    return dev(trajam::launch_warm_pack_mfma(s->n_layers, s->width, params, packed, (hipStream_t)stream),
+               "warm pack");
+}
+
+extern "C" trajam_status trajam_warm_jump(const trajam_mlp_shape *s, int32_t batch, int32_t dims, int32_t nv,
+                                          const void *packed, float in_scale, float out_scale, const float *xi,
+                                          const float *xb, const float *lam, float *xb_out, float *lam_out,
+                                          void *stream)
+{
+    if (!shape_ok(s)) return fail(TRAJAM_ERR_INVALID, "invalid network shape");
+    if (trajam::warm_jump_packed_bytes(s->n_layers, s->width) < 0)
+        return fail(TRAJAM_ERR_UNSUPPORTED, "warm jump: 1..4 layers, every width <= 256");
+    if (batch < 0 || dims < 2 || dims > 3 || nv < 4) return fail(TRAJAM_ERR_INVALID, "batch >= 0, dims 2 or 3, nv >= 4");
+    if (s->width[0] != 2 * dims * nv || s->width[s->n_layers] != dims * nv)
+        return fail(TRAJAM_ERR_INVALID, "warm jump: widths must be 2 dims nv in and dims nv out");
+    if (batch == 0) return TRAJAM_OK;
+    if (!packed || !xi || !xb || !lam || !xb_out || !lam_out) return fail(TRAJAM_ERR_INVALID, "NULL pointer");
+    if (xb_out == xb || lam_out == lam) return fail(TRAJAM_ERR_INVALID, "outputs must not alias xb or lam");
+    return dev(trajam::launch_warm_jump(s->n_layers, s->width, batch, dims, nv, packed, in_scale, out_scale, xi, xb,
+                                        lam, xb_out, lam_out, (hipStream_t)stream),
+               "warm jump");
+}
+
 extern "C" trajam_status trajam_warm_fallback(int32_t batch, int32_t dims, int32_t nv, const float *rw,
                                               const float *rc, const float *xb_src, const float *lam_src,
                                               float *xb, float *lam, uint32_t *flags, void *stream)

@@ -359,6 +359,112 @@ __global__ void warm_fallback_kernel(int batch, int dim, const float *__restrict
     if (lane == 0 && flags) flags[b] = bad ? 4u : 0u;
 }
 
+// ---- fused warm jump on the matrix cores -----------------------------------------
+// Features, the whole network and the jump for 16 samples per workgroup in one launch:
+// X = [(xb - xi), lam] * in_scale (bf16) in LDS, each layer a row of 16 x 16 output
+// tiles of v_mfma_f32_16x16x16_bf16 (the workgroup's 4 waves take the tiles round
+// robin; fp32 accumulation, bias and ReLU in the epilogue, the hidden activations back
+// to LDS as bf16), the linear output y kept in fp32, then xb_out = xb + out_scale * y on
+// the free coefficients with lam_out = xb_out - xi there, boundary coefficients and
+// their multipliers unchanged (as trajam_warm_apply).  Weights come pre-packed in the
+// MFMA B-operand order (trajam_warm_pack_mfma): one 8-byte load per lane and tile step.
+constexpr int kJumpRows = 16;       // samples per workgroup (one MFMA row tile)
+constexpr int kJumpMaxWidth = 256;  // every width, padded to 16
+constexpr int kJumpMaxLayers = 4;
+
+struct JumpShape {
+    int n_layers;
+    int width[kJumpMaxLayers + 1];
+    long woff[kJumpMaxLayers];  // byte offsets of each layer's packed weights
+    long boff[kJumpMaxLayers];  // byte offsets of each layer's bias (fp32, padded to 16)
+};
+
+__host__ __device__ constexpr int ceil16(int x) { return (x + 15) / 16; }
+
+// Pack layer l of the flat fp32 parameters (W [out][in] row-major, then b [out]) into the
+// B-operand order: tile (nt, kt), lane, 4 bf16 (rows k = kt*16 + 4(lane/16) + i of
+// column n = nt*16 + lane%16), zero outside the matrix; bias padded with zeros.
+__global__ void warm_pack_layer_kernel(int in, int out, const float *__restrict__ src, short *__restrict__ wdst,
+                                       float *__restrict__ bdst)
+{
+    const int KT = ceil16(in), NT = ceil16(out);
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long nw = (long)NT * KT * 64 * 4;
+    if (i < nw) {
+        const int q = (int)(i & 3), lane = (int)((i >> 2) & 63);
+        const long tile = i >> 8;
+        const int kt = (int)(tile % KT), nt = (int)(tile / KT);
+        const int n = nt * 16 + (lane & 15), k = kt * 16 + 4 * (lane >> 4) + q;
+        wdst[i] = to_bf16((n < out && k < in) ? src[(long)n * in + k] : 0.f);
+    } else if (i < nw + NT * 16) {
+        const int n = (int)(i - nw);
+        bdst[n] = n < out ? src[(long)out * in + n] : 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void warm_jump_kernel(JumpShape sh, int batch, int dims, int nv,
+                                                        const unsigned char *__restrict__ packed, float in_scale,
+                                                        float out_scale, const float *__restrict__ xi,
+                                                        const float *__restrict__ xb, const float *__restrict__ lam,
+                                                        float *__restrict__ xbo, float *__restrict__ lamo)
+{
+    constexpr int R = kJumpRows, LD = kJumpMaxWidth + 8;   // +8 bf16: rows on distinct banks
+    __shared__ __align__(16) short act[2][R][LD];
+    __shared__ float yout[R][kJumpMaxWidth];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int s0 = blockIdx.x * R;
+    const int dim = dims * nv, w0 = sh.width[0];
+    for (int e = tid; e < R * ceil16(w0) * 16; e += 256) {
+        const int s = e / (ceil16(w0) * 16), f = e - s * ceil16(w0) * 16;
+        float v = 0.f;
+        if (s0 + s < batch && f < w0 && f < 2 * dim) {
+            const long g = (long)(s0 + s) * dim + (f < dim ? f : f - dim);
+            v = (f < dim ? xb[g] - xi[g] : lam[g]) * in_scale;
+        }
+        act[0][s][f] = to_bf16(v);
+    }
+    __syncthreads();
+    int cur = 0;
+    const int r16 = lane & 15, kq = 4 * (lane >> 4);
+    for (int l = 0; l < sh.n_layers; ++l) {
+        const int in = sh.width[l], out = sh.width[l + 1];
+        const int KT = ceil16(in), NT = ceil16(out);
+        const bool last = l == sh.n_layers - 1;
+        const mlp_bf16x4 *W = reinterpret_cast<const mlp_bf16x4 *>(packed + sh.woff[l]);
+        const float *bias = reinterpret_cast<const float *>(packed + sh.boff[l]);
+        for (int nt = wv; nt < NT; nt += 4) {
+            mlp_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const mlp_bf16x4 *Wt = W + (long)nt * KT * 64 + lane;
+            for (int kt = 0; kt < KT; ++kt) {
+                const mlp_bf16x4 a = *reinterpret_cast<const mlp_bf16x4 *>(&act[cur][r16][kt * 16 + kq]);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, Wt[kt * 64], acc, 0, 0, 0);
+            }
+            const int n = nt * 16 + r16;
+            const float bn = bias[n];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = kq + q;
+                const float v = acc[q] + bn;
+                if (last) yout[m][n] = v;
+                else act[cur ^ 1][m][n] = to_bf16(n < out ? fmaxf(v, 0.f) : 0.f);
+            }
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    for (int e = tid; e < R * dim; e += 256) {
+        const int s = e / dim, c = e - s * dim;
+        if (s0 + s >= batch) continue;
+        const long g = (long)(s0 + s) * dim + c;
+        const int m = c % nv;
+        const bool bnd = m <= 2 || m == nv - 1;
+        const float x = xb[g];
+        const float xn = bnd ? x : fmaf(yout[s][c], out_scale, x);
+        xbo[g] = xn;
+        lamo[g] = bnd ? lam[g] : xn - xi[g];
+    }
+}
+
 }  // namespace
 
 hipError_t launch_gemm(bool bf16, int M, int N, int K, const float *A, long sam, long sak, const float *B,
@@ -441,6 +547,63 @@ hipError_t launch_warm_apply(int batch, int dims, int nv, const float *y, float 
     const long total = (long)batch * dims * nv;
     hipLaunchKernelGGL(warm_apply_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, batch, dims, nv,
                        y, out_scale, xi, xb, lam, xbo, lamo);
+    return hipGetLastError();
+}
+
+// Byte layout of the packed jump parameters (host): per layer the B-operand tiles
+// (NT * KT * 64 * 4 bf16), then the bias (NT * 16 fp32), each 16-byte aligned.
+static long jump_layout(int n_layers, const int *width, JumpShape &sh)
+{
+    long off = 0;
+    sh.n_layers = n_layers;
+    for (int l = 0; l <= n_layers; ++l) sh.width[l] = width[l];
+    for (int l = 0; l < n_layers; ++l) {
+        const long KT = ceil16(width[l]), NT = ceil16(width[l + 1]);
+        sh.woff[l] = off;
+        off += NT * KT * 64 * 4 * 2;
+        off = (off + 15) / 16 * 16;
+        sh.boff[l] = off;
+        off += NT * 16 * 4;
+        off = (off + 15) / 16 * 16;
+    }
+    return off;
+}
+
+long warm_jump_packed_bytes(int n_layers, const int *width)
+{
+    if (n_layers < 1 || n_layers > kJumpMaxLayers) return -1;
+    for (int l = 0; l <= n_layers; ++l)
+        if (width[l] < 1 || width[l] > kJumpMaxWidth) return -1;
+    JumpShape sh{};
+    return jump_layout(n_layers, width, sh);
+}
+
+hipError_t launch_warm_pack_mfma(int n_layers, const int *width, const float *params, void *packed, hipStream_t st)
+{
+    JumpShape sh{};
+    jump_layout(n_layers, width, sh);
+    long poff = 0;
+    for (int l = 0; l < n_layers; ++l) {
+        const int in = width[l], out = width[l + 1];
+        const long n = (long)ceil16(out) * ceil16(in) * 256 + ceil16(out) * 16;
+        hipLaunchKernelGGL(warm_pack_layer_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out,
+                           params + poff, reinterpret_cast<short *>((unsigned char *)packed + sh.woff[l]),
+                           reinterpret_cast<float *>((unsigned char *)packed + sh.boff[l]));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        poff += (long)in * out + out;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_warm_jump(int n_layers, const int *width, int batch, int dims, int nv, const void *packed,
+                            float in_scale, float out_scale, const float *xi, const float *xb, const float *lam,
+                            float *xbo, float *lamo, hipStream_t st)
+{
+    JumpShape sh{};
+    jump_layout(n_layers, width, sh);
+    hipLaunchKernelGGL(warm_jump_kernel, dim3((batch + kJumpRows - 1) / kJumpRows), dim3(256), 0, st, sh, batch,
+                       dims, nv, (const unsigned char *)packed, in_scale, out_scale, xi, xb, lam, xbo, lamo);
     return hipGetLastError();
 }
 

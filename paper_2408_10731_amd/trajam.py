@@ -47,7 +47,7 @@ EXPORTS = [
     "trajam_boundary_coefficients", "trajam_cem_sample", "trajam_cem_cost",
     "trajam_cem_select", "trajam_cem_update", "trajam_mlp_param_count", "trajam_mlp_forward",
     "trajam_mlp_backward", "trajam_mlp_backward_noalloc", "trajam_mlp_infer", "trajam_mlp_pack_infer", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
-    "trajam_warm_apply", "trajam_warm_fallback", "trajam_set_obstacles", "trajam_autotune",
+    "trajam_warm_apply", "trajam_warm_fallback", "trajam_warm_pack_mfma", "trajam_warm_jump", "trajam_set_obstacles", "trajam_autotune",
     "trajam_ragged_plan_create", "trajam_ragged_launch", "trajam_ragged_plan_destroy", "trajam_polar",
     "trajam_qp_contraction", "trajam_set_continuation", "trajam_project_continuation",
     "trajam_status_string", "trajam_last_error",
@@ -195,6 +195,11 @@ def load():
     L.trajam_ragged_plan_create.argtypes = [ctypes.POINTER(RaggedItem), ctypes.c_int32,
                                             ctypes.c_int32, ctypes.POINTER(vp)]
     L.trajam_ragged_launch.argtypes = [vp, vp]
+    L.trajam_warm_pack_mfma.argtypes = [sp, vp, vp, ctypes.POINTER(i64), vp]
+    L.trajam_warm_pack_mfma.restype = ctypes.c_int
+    L.trajam_warm_jump.argtypes = [sp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_float,
+                                   ctypes.c_float, vp, vp, vp, vp, vp, vp]
+    L.trajam_warm_jump.restype = ctypes.c_int
     L.trajam_set_continuation.argtypes = [vp, ctypes.POINTER(Continuation)]
     L.trajam_set_continuation.restype = ctypes.c_int
     L.trajam_project_continuation.argtypes = [vp, ctypes.c_int32, vp, dp, vp, vp, vp, vp, vp, vp,
@@ -353,6 +358,20 @@ def trajam_mlp_backward_noalloc(shape, batch, precision, params, x, acts, dy, gr
                                 stream) -> None:
     _check(load().trajam_mlp_backward_noalloc(ctypes.byref(shape), int(batch), int(precision),
                                               params, x, acts, dy, grads, stream))
+
+
+def trajam_warm_pack_mfma(shape, params, packed, stream) -> int:
+    """Packs the flat fp32 parameters for trajam_warm_jump; packed None: size query.
+    Returns the packed size in bytes."""
+    n = ctypes.c_int64()
+    _check(load().trajam_warm_pack_mfma(ctypes.byref(shape), params, packed, ctypes.byref(n), stream))
+    return int(n.value)
+
+
+def trajam_warm_jump(shape, batch, dims, nv, packed, in_scale, out_scale, xi, xb, lam, xb_out, lam_out,
+                     stream) -> None:
+    _check(load().trajam_warm_jump(ctypes.byref(shape), int(batch), int(dims), int(nv), packed,
+                                   float(in_scale), float(out_scale), xi, xb, lam, xb_out, lam_out, stream))
 
 
 def trajam_mlp_mse(count, y, target, dy, loss, stream) -> None:

@@ -217,9 +217,9 @@ def train(net: Net, data: Dataset, epochs: int, batch: int = 1024, lr: float = 1
 
 class WarmContext:
     """The warm start of one solver: every buffer allocated once, `run` only launches
-    kernels (probe projection, features, the fused network inference, jump, residual,
-    check), so it can be captured in a graph together with the projection that
-    continues from it."""
+    kernels (probe projection; features, network and jump fused in one matrix-core
+    launch; residual; check), so it can be captured in a graph together with the
+    projection that continues from it."""
 
     def __init__(self, solver: "tj.Solver", net: Net, max_batch: int, k0: int = K0):
         import torch
@@ -227,25 +227,24 @@ class WarmContext:
         D, nv = solver.dims, solver.nv
         self.dim = D * nv
         assert net.widths[0] == 2 * self.dim and net.widths[-1] == self.dim
-        assert max(net.widths) <= 512
+        assert max(net.widths) <= 256
         assert max_batch <= net.max_batch
         shape = (max_batch, D, nv)
         self.xp = torch.zeros(shape, device="cuda")
         self.lp = torch.zeros(shape, device="cuda")
         self.xw = torch.zeros(shape, device="cuda")
         self.lw = torch.zeros(shape, device="cuda")
-        self.x = torch.zeros((max_batch, 2 * self.dim), device="cuda")
-        self.y = torch.zeros((max_batch, self.dim), device="cuda")
-        self.packed = torch.zeros_like(net.params)
+        nbytes = tj.trajam_warm_pack_mfma(net.shape, None, None, None)
+        self.packed = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
         self.refresh()
         self.trace = torch.zeros((self.k0, max_batch), device="cuda")
         self.rw = torch.zeros(max_batch, device="cuda")
         self.flags = torch.zeros(max_batch, dtype=torch.int32, device="cuda")
 
     def refresh(self):
-        """Re-pack the network's parameters for inference (after training steps)."""
+        """Re-pack the network's parameters for the matrix-core jump (after training)."""
         import torch
-        tj.trajam_mlp_pack_infer(self.net.shape, self.net.params.data_ptr(), self.packed.data_ptr(),
+        tj.trajam_warm_pack_mfma(self.net.shape, self.net.params.data_ptr(), self.packed.data_ptr(),
                                  torch.cuda.current_stream().cuda_stream)
 
     def run(self, xi, boundary, obs):
@@ -261,14 +260,8 @@ class WarmContext:
         xp.copy_(xi)
         lp.zero_()
         s.project(xi, boundary, obs, xp, lp, self.k0, res_trace=tr)
-        x = self.x[:B]
-        tj.trajam_warm_features(B, D, nv, xi.data_ptr(), xp.data_ptr(), lp.data_ptr(),
-                                1.0 / IN_SCALE, x.data_ptr(), st)
-        y = self.y[:B]
-        tj.trajam_mlp_infer(self.net.shape, B, self.packed.data_ptr(), x.data_ptr(), y.data_ptr(),
-                            st)
-        tj.trajam_warm_apply(B, D, nv, y.data_ptr(), OUT_SCALE, xi.data_ptr(), xp.data_ptr(),
-                             lp.data_ptr(), xw.data_ptr(), lw.data_ptr(), st)
+        tj.trajam_warm_jump(self.net.shape, B, D, nv, self.packed.data_ptr(), 1.0 / IN_SCALE, OUT_SCALE,
+                            xi.data_ptr(), xp.data_ptr(), lp.data_ptr(), xw.data_ptr(), lw.data_ptr(), st)
         rw = self.rw[:B]
         s.residuals(xw, obs, rw)
         fl = self.flags[:B]

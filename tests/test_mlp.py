@@ -266,6 +266,48 @@ def test_gpu_warm_features_apply_and_fallback():
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("widths,batch,D,nv", [([44, 256, 256, 22], 1024, 2, 11), ([44, 256, 256, 22], 37, 2, 11),
+                                               ([96, 160, 48], 21, 3, 16), ([32, 40, 16], 5, 2, 8)])
+def test_gpu_fused_warm_jump_matches_oracle(widths, batch, D, nv):
+    """The matrix-core warm jump (features, bf16 network, jump in one launch) against the
+    FP64 oracle of the same steps with both operands of every product rounded to bf16
+    (oracle.mlp.forward(bf16=True), the decision of ReLU in the kernel's precision):
+    the jumped free coefficients within 2e-3 relative to the largest step, boundary
+    coefficients and their multipliers unchanged, free multipliers xb_out - xi."""
+    from paper_2408_10731_amd import trajam as tj
+    rng = np.random.default_rng(batch + nv)
+    dim = D * nv
+    params = (rng.normal(size=omlp.n_params(widths)) * 0.15).astype(np.float32)
+    xi = rng.normal(size=(batch, D, nv)).astype(np.float32)
+    xb = (xi + 0.3 * rng.normal(size=xi.shape)).astype(np.float32)
+    lam = (0.2 * rng.normal(size=xi.shape)).astype(np.float32)
+    in_s, out_s = 0.7, 1.3
+    shape = tj.mlp_shape(widths)
+    st = torch.cuda.current_stream().cuda_stream
+    print("case: warm jump", widths, batch, flush=True)
+    dp = torch.as_tensor(params, device="cuda")
+    n = tj.trajam_warm_pack_mfma(shape, None, None, st)
+    packed = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    tj.trajam_warm_pack_mfma(shape, dp.data_ptr(), packed.data_ptr(), st)
+    dxi, dxb, dl = (torch.as_tensor(a, device="cuda") for a in (xi, xb, lam))
+    xo, lo = torch.empty_like(dxb), torch.empty_like(dl)
+    tj.trajam_warm_jump(shape, batch, D, nv, packed.data_ptr(), in_s, out_s, dxi.data_ptr(), dxb.data_ptr(),
+                        dl.data_ptr(), xo.data_ptr(), lo.data_ptr(), st)
+    torch.cuda.synchronize()
+    x = np.concatenate([(xb - xi).reshape(batch, dim), lam.reshape(batch, dim)], 1).astype(np.float64) * in_s
+    y, _ = omlp.forward(params.astype(np.float64), widths, x, bf16=True)
+    want = xb.astype(np.float64) + out_s * y.reshape(batch, D, nv)
+    got_x, got_l = xo.double().cpu().numpy(), lo.double().cpu().numpy()
+    bnd = [0, 1, 2, nv - 1]
+    free = list(range(3, nv - 1))
+    assert np.array_equal(got_x[:, :, bnd], xb[:, :, bnd]) and np.array_equal(got_l[:, :, bnd], lam[:, :, bnd])
+    scale = max(1.0, np.abs(out_s * y).max())
+    err = np.abs(got_x[:, :, free] - want[:, :, free]).max() / scale
+    assert err <= 2e-3, err
+    np.testing.assert_allclose(got_l[:, :, free], got_x[:, :, free] - xi[:, :, free], atol=1e-6)
+
+
+@pytest.mark.gpu
 def test_gpu_trained_warm_start_gains_over_cold_start():
     """Trained on solver-generated pairs of the 2D 50-circle family (scene seeds
     10,000+, disjoint from the held-out ones), the probe-and-jump warm start against the
