@@ -105,10 +105,10 @@ def train_warm_start(w, scenes, epochs, seed0=20_000, batch=512):
     t0 = time.perf_counter()
     data = ws.generate(ws.family_scene("cfg2"), list(range(seed0, seed0 + scenes)), 64,
                        k0=ws.K0, cap=150)
-    net = ws.Net(ws.widths_for(w), seed=0, precision=0, max_batch=max(batch, w.batch))
+    net = ws.Net(ws.widths_for(w), seed=0, precision=1, max_batch=max(batch, w.batch))
     curve = ws.train(net, data, epochs=epochs, batch=batch, lr=1e-3)
     torch.cuda.synchronize()
-    info = {"pairs": int(data.x.shape[0]), "scenes": scenes, "epochs": epochs,
+    info = {"pairs": int(data.x.shape[0]), "scenes": scenes, "epochs": epochs, "precision": "bf16 matrix cores",
             "loss_first": curve[0], "loss_last": curve[-1],
             "seconds": time.perf_counter() - t0}
     return net, info
@@ -249,6 +249,59 @@ def time_to_residual(args, w, solver, xi, obs, stream, tol=1e-3, net=None, info=
         tot["cold_ms"] += r.get("cold_ms", 0.0)
         tot["warm_ms"] += r.get("warm_ms", 0.0)
     out["held_out"] = {"scenes": per, "total": tot}
+    return out
+
+
+PEAK_BF16_MFMA = 2.5e15   # dense bf16 matrix-core FLOP/s of MI355X
+
+
+def mfma_bench(args):
+    """The matrix-core kernels of the warm start at sizes where their products are
+    large enough to time: one training step (forward, backward, Adam) of the network
+    [44, 256, 256, 22] in bf16 at batch 16384, and the fused warm jump at batch 4096.
+    Algorithmic FLOPs: 2 B sum(in out) forward, twice that backward (weight and input
+    gradients); achieved FLOP/s against the dense bf16 peak."""
+    import torch
+    from paper_2408_10731_amd import trajam as tj
+    from paper_2408_10731_amd import warmstart as ws
+    widths = [44, 256, 256, 22]
+    macs = sum(widths[l] * widths[l + 1] for l in range(len(widths) - 1))
+    st = torch.cuda.current_stream()
+    out = {"network": widths, "peak_TFLOPs": PEAK_BF16_MFMA / 1e12}
+    B = 16384
+    net = ws.Net(widths, seed=0, precision=1, max_batch=B)
+    g = torch.Generator(device="cuda").manual_seed(2)
+    x = torch.randn((B, widths[0]), device="cuda", generator=g)
+    t = torch.randn((B, widths[-1]), device="cuda", generator=g)
+    ms = _time(lambda: net.train_step(x, t, 1e-4), args.mfma_steps, st)
+    fl = 6.0 * B * macs
+    # bytes each product must move with fp32 activations in HBM: forward reads its
+    # input and writes its output; the loss reads y, t and writes dy; the weight
+    # gradient reads d and the layer input, the input gradient reads d and the mask and
+    # writes the new d
+    w = widths
+    per_row = sum(w[l] + w[l + 1] for l in range(len(w) - 1)) + 3 * w[-1]
+    per_row += sum(w[l + 1] + w[l] + (3 * w[l] + w[l + 1] if l > 0 else 0) for l in range(len(w) - 1))
+    nbytes = 4.0 * B * per_row
+    out["train_step"] = {"batch": B, "ms": ms, "gflop": fl / 1e9, "achieved_TFLOPs": fl / (ms * 1e-3) / 1e12,
+                         "frac_of_peak": fl / (ms * 1e-3) / PEAK_BF16_MFMA, "algorithmic_MB": nbytes / 1e6,
+                         "hbm_GBs": nbytes / (ms * 1e-3) / 1e9, "hbm_frac": nbytes / (ms * 1e-3) / 8e12}
+    Bj, D, nv = 4096, 2, 11
+    shape = tj.mlp_shape(widths)
+    n = tj.trajam_warm_pack_mfma(shape, None, None, st.cuda_stream)
+    packed = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    tj.trajam_warm_pack_mfma(shape, net.params.data_ptr(), packed.data_ptr(), st.cuda_stream)
+    xi = torch.randn((Bj, D, nv), device="cuda", generator=g)
+    xb, lam = xi + 0.1, torch.zeros_like(xi)
+    xo, lo = torch.empty_like(xi), torch.empty_like(xi)
+
+    def jump():
+        tj.trajam_warm_jump(shape, Bj, D, nv, packed.data_ptr(), 1.0, 1.0, xi.data_ptr(), xb.data_ptr(),
+                            lam.data_ptr(), xo.data_ptr(), lo.data_ptr(), st.cuda_stream)
+    ms = _time(jump, args.mfma_steps, st)
+    fl = 2.0 * Bj * macs
+    out["warm_jump"] = {"batch": Bj, "ms": ms, "gflop": fl / 1e9, "achieved_TFLOPs": fl / (ms * 1e-3) / 1e12,
+                        "frac_of_peak": fl / (ms * 1e-3) / PEAK_BF16_MFMA}
     return out
 
 
@@ -722,6 +775,9 @@ def main():
                     help="timed calls of the materialised polar variables; 0 skips that leg")
     ap.add_argument("--cem-only", action="store_true",
                     help="run only the sampling-loop leg and print its JSON (profiling)")
+    ap.add_argument("--mfma-steps", type=int, default=10, help="timed calls of the matrix-core leg; 0 skips it")
+    ap.add_argument("--mfma-only", action="store_true",
+                    help="run only the matrix-core leg and print its JSON (profiling)")
     ap.add_argument("--polar-only", action="store_true",
                     help="run only the materialised-polar leg and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -745,6 +801,9 @@ def main():
         return
     if args.polar_only:
         print(json.dumps(polar_bench(args)), flush=True)
+        return
+    if args.mfma_only:
+        print(json.dumps(mfma_bench(args)), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -784,6 +843,7 @@ def main():
     cem_out = cem_bench(args) if args.cem_calls > 0 else None
     prec_out = precision_bench(args) if args.precision_steps > 0 else None
     polar_out = polar_bench(args) if args.polar_steps > 0 else None
+    mfma_out = mfma_bench(args) if args.mfma_steps > 0 else None
 
     out = {
         "metric": "traj-iters/s & time-to-residual<=1e-3, learned warm-start vs cold, 1 MI355X",
@@ -804,6 +864,7 @@ def main():
         "cem": cem_out,
         "precision_cfg3": prec_out,
         "polar_materialised": polar_out,
+        "matrix_cores": mfma_out,
         "wall_s_timed_region": h["wall"],
     }
     if not args.no_cpu:

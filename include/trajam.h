@@ -428,7 +428,10 @@ trajam_status trajam_mlp_infer(const trajam_mlp_shape *shape, int32_t batch, con
 
 /* grads [n_params] = d loss / d params given dy = d loss / d y [batch][width[L]], the
  * input x and the activations of the forward call.  scratch: 2 * batch * max hidden
- * width floats.  Errors: INVALID, DEVICE. */
+ * width floats (NULL allowed for a single-layer network): the two input-gradient
+ * buffers, the idle one of which also holds the partial weight gradients when a
+ * weight-gradient product (K = batch) is split over the batch; the partials are added
+ * in a fixed order, so the result does not depend on timing.  Errors: INVALID, DEVICE. */
 trajam_status trajam_mlp_backward(const trajam_mlp_shape *shape, int32_t batch, int32_t precision,
                                   const float *params, const float *x, const float *acts,
                                   const float *dy, float *grads, float *scratch, void *stream);
@@ -451,7 +454,10 @@ trajam_status trajam_mlp_backward_noalloc(const trajam_mlp_shape *shape, int32_t
                                           const float *dy, float *grads, void *stream);
 
 /* Mean squared error over count values: loss[0] = mean (y - t)^2, dy = 2 (y - t) / count.
- * Errors: INVALID, DEVICE. */
+ * loss is a device array of TRAJAM_MLP_MSE_LOSS_FLOATS floats: loss[1..] is the
+ * workspace of the per-workgroup partial sums (added in a fixed order, so the loss does
+ * not depend on timing), overwritten by every call.  Errors: INVALID, DEVICE. */
+#define TRAJAM_MLP_MSE_LOSS_FLOATS 513
 trajam_status trajam_mlp_mse(int64_t count, const float *y, const float *target, float *dy,
                              float *loss, void *stream);
 
@@ -495,7 +501,7 @@ trajam_status trajam_warm_jump(const trajam_mlp_shape *shape, int32_t batch, int
                                const void *packed, float in_scale, float out_scale, const float *xi,
                                const float *xb, const float *lam, float *xb_out, float *lam_out, void *stream);
 
-/* Per-sample fallback: where res_warm[b] (residual of the jumped state xb) is not/* Per-sample fallback: where res_warm[b] (residual of the jumped state xb) is not
+/* Per-sample fallback: where res_warm[b] (residual of the jumped state xb) is not
  * below res_cold[b] (the probe's last residual), or is NaN, or the jumped state is
  * not finite, the sample keeps the probe state (xb = xb_src, lam = lam_src) and
  * flags[b] = TRAJAM_FLAG_COLD_FALLBACK; otherwise flags[b] = 0 (flags may be NULL).

@@ -126,9 +126,18 @@ hipError_t launch_cem_update(bool f64, int n_elite, int dim, const int32_t *elit
                              void *Sigma, void *L, hipStream_t st);
 
 // Warm-start network kernels (mlp_kernels.hip).
+// Split of a product over K: the number of slices (1 = no split) whose partial products
+// fit in `space` floats (M N each, plus M row sums in bf16 mode), and the K range of
+// one slice.
+int gemm_plan_slices(bool bf16, int M, int N, int K, long space, int *k_chunk);
+// C = A B (epilogue epi on the last slice only when slices == 1); with slices > 1 the
+// product of K slice z goes to C + z c_slice.  rowsum (bf16 mode only, may be NULL):
+// rowsum[z rs_slice + m] = sum over slice z's k of A(m, k), in fp32.
 hipError_t launch_gemm(bool bf16, int M, int N, int K, const float *A, long sam, long sak, const float *B,
                        long sbk, long sbn, float *C, int ldc, int epi, const float *bias, const float *mask,
-                       int ldm, hipStream_t st);
+                       int ldm, hipStream_t st, int slices = 1, int k_chunk = 0, long c_slice = 0,
+                       float *rowsum = nullptr, long rs_slice = 0);
+hipError_t launch_slice_sum(long n, int slices, const float *part, long stride, float *out, hipStream_t st);
 hipError_t launch_colsum(int rows, int cols, const float *d, float *out, hipStream_t st);
 hipError_t launch_mse(long count, const float *y, const float *t, float *dy, float *loss, hipStream_t st);
 hipError_t launch_adam(long n, float *p, const float *g, float *m, float *v, int step, float lr, float b1,

@@ -121,18 +121,40 @@ extern "C" trajam_status trajam_mlp_backward(const trajam_mlp_shape *s, int32_t 
     }
     const float *d = dy;
     float *bufs[2] = {scratch, scratch ? scratch + (int64_t)batch * maxw : nullptr};
+    // the idle input-gradient buffer (batch * maxw floats) takes the partial products
+    // of a weight gradient split over the batch (none for a single-layer network)
+    const long space = (L > 1 && scratch) ? (long)batch * maxw : 0;
+    const bool bf = precision == 1;
     int which = 0;
     for (int l = L - 1; l >= 0; --l) {
         const int in = s->width[l], out = s->width[l + 1];
         const float *a_prev = (l == 0) ? x : acts + aoff[l];
         float *gW = grads + poff[l], *gb = gW + (int64_t)out * in;
-        // dW = d^T a_prev  (M = out, N = in, K = batch)
-        trajam_status r = dev(trajam::launch_gemm(precision == 1, out, in, batch, d, 1, out, a_prev, in, 1, gW, in,
-                                                  0, nullptr, nullptr, 0, st),
-                              "mlp weight gradient");
+        // dW = d^T a_prev  (M = out, N = in, K = batch); in bf16 mode the bias gradient
+        // (the sum of d over the batch) comes out of the same pass over d
+        int k_chunk = batch;
+        const int S = trajam::gemm_plan_slices(bf, out, in, batch, space, &k_chunk);
+        trajam_status r;
+        if (S == 1) {
+            r = dev(trajam::launch_gemm(bf, out, in, batch, d, 1, out, a_prev, in, 1, gW, in, 0, nullptr, nullptr, 0,
+                                        st, 1, batch, 0, bf ? gb : nullptr, 0),
+                    "mlp weight gradient");
+        } else {
+            float *part = bufs[which], *rpart = part + (long)S * out * in;
+            r = dev(trajam::launch_gemm(bf, out, in, batch, d, 1, out, a_prev, in, 1, part, in, 0, nullptr, nullptr,
+                                        0, st, S, k_chunk, (long)out * in, bf ? rpart : nullptr, out),
+                    "mlp weight gradient");
+            if (r == TRAJAM_OK)
+                r = dev(trajam::launch_slice_sum((long)out * in, S, part, (long)out * in, gW, st),
+                        "mlp weight gradient sum");
+            if (r == TRAJAM_OK && bf)
+                r = dev(trajam::launch_slice_sum(out, S, rpart, out, gb, st), "mlp bias gradient sum");
+        }
         if (r != TRAJAM_OK) return r;
-        r = dev(trajam::launch_colsum(batch, out, d, gb, st), "mlp bias gradient");
-        if (r != TRAJAM_OK) return r;
+        if (!bf) {
+            r = dev(trajam::launch_colsum(batch, out, d, gb, st), "mlp bias gradient");
+            if (r != TRAJAM_OK) return r;
+        }
         if (l > 0) {
             // d_prev = (d W) * [a_prev > 0]  (M = batch, N = in, K = out)
             float *dn = bufs[which];

@@ -39,6 +39,7 @@ FLAG_GREW = 2
 FLAG_COLD_FALLBACK = 4
 MLP_MAX_LAYERS = 8
 MLP_NOALLOC_SCRATCH_FLOATS = 2097152
+MLP_MSE_LOSS_FLOATS = 513        # loss[0] and the partial sums of trajam_mlp_mse
 
 # every symbol include/trajam.h declares
 EXPORTS = [

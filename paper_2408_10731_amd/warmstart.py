@@ -79,7 +79,7 @@ class Net:
         self.scratch = torch.zeros(2 * maxw * self.max_batch, device=dev)
         self.y = torch.zeros((self.max_batch, self.widths[-1]), device=dev)
         self.dy = torch.zeros_like(self.y)
-        self.loss = torch.zeros(1, device=dev)
+        self.loss = torch.zeros(tj.MLP_MSE_LOSS_FLOATS, device=dev)   # [0] is the loss
 
     def _st(self):
         return self.torch.cuda.current_stream().cuda_stream
@@ -108,7 +108,7 @@ class Net:
         tj.trajam_mlp_adam(self.n, self.params.data_ptr(), self.grads.data_ptr(),
                            self.m.data_ptr(), self.v.data_ptr(), self.step_count, lr, 0.9, 0.999,
                            1e-8, self._st())
-        return self.loss
+        return self.loss[:1]
 
 
 @dataclasses.dataclass

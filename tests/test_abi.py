@@ -187,3 +187,11 @@ def test_qp_contraction_is_the_spectral_radius(dims, degree, n_steps, T, n_obs, 
 def test_qp_contraction_rejects_a_null_output():
     pr = _problem()
     assert tj.load().trajam_qp_contraction(ctypes.byref(pr), None) == tj.TRAJAM_ERR_INVALID
+
+
+def test_header_constants_match_the_binding():
+    src = open(os.path.join(ROOT, "include", "trajam.h")).read()
+    defs = {k: int(v) for k, v in re.findall(r"#define TRAJAM_([A-Z_0-9]+) (\d+)u?\b", src)}
+    for name in ("FLAG_NONFINITE", "FLAG_GREW", "FLAG_COLD_FALLBACK", "MLP_MAX_LAYERS",
+                 "MLP_NOALLOC_SCRATCH_FLOATS", "MLP_MSE_LOSS_FLOATS", "CONT_MAX_LEVELS"):
+        assert defs[name] == getattr(tj, name), name

@@ -71,11 +71,14 @@ def _rel(a, b):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("widths,batch", [([526, 256, 256, 22], 300), ([5, 7, 3], 1),
-                                          ([33, 65, 17], 129)])
+                                          ([33, 65, 17], 129), ([44, 256, 256, 22], 8192),
+                                          ([30, 17], 2000)])
 @pytest.mark.parametrize("precision,tol", [(0, 1e-4), (1, 1e-3)])
 def test_gpu_forward_and_gradients_match_oracle(widths, batch, precision, tol):
     """Forward output, loss and every parameter gradient against the FP64 oracle on
-    the same float32 weights and inputs.  In bf16 mode the oracle rounds each
+    the same float32 weights and inputs.  Batch 8192 splits each weight gradient over
+    the batch (partial products added by a second kernel); the single-layer network
+    runs without a workspace.  In bf16 mode the oracle rounds each
     product's operands to bf16 like the kernel (so the ReLU decisions agree) and the
     only difference left is fp32 accumulation; the error of the bf16 mode against
     the unrounded FP64 network is checked separately below (<= 2e-2)."""
@@ -112,7 +115,7 @@ def test_gpu_forward_and_gradients_match_oracle(widths, batch, precision, tol):
     acts_d = torch.zeros(max(hid, 1) * batch, device="cuda")
     Y = torch.zeros((batch, widths[-1]), device="cuda")
     dY = torch.zeros_like(Y)
-    L = torch.zeros(1, device="cuda")
+    L = torch.zeros(tj.MLP_MSE_LOSS_FLOATS, device="cuda")
     G = torch.zeros_like(P)
     scr = torch.zeros(2 * batch * max(widths[1:-1] + [1]), device="cuda")
     tj.trajam_mlp_forward(shape, batch, precision, P.data_ptr(), X.data_ptr(), acts_d.data_ptr(),
@@ -122,7 +125,7 @@ def test_gpu_forward_and_gradients_match_oracle(widths, batch, precision, tol):
                            dY.data_ptr(), G.data_ptr(), scr.data_ptr(), st)
     torch.cuda.synchronize()
     assert _rel(Y.cpu().numpy(), y_o) <= tol
-    assert abs(L.item() - loss_o) <= tol * abs(loss_o)
+    assert abs(L[0].item() - loss_o) <= tol * abs(loss_o)
     g = G.cpu().numpy()
     off = 0
     for l in range(len(widths) - 1):
@@ -151,7 +154,7 @@ def test_gpu_bf16_mode_error_against_fp64_network():
     P, X, T = (torch.as_tensor(a, device="cuda") for a in (p32, x, t))
     acts_d = torch.zeros(512 * batch, device="cuda")
     Y = torch.zeros((batch, 22), device="cuda")
-    dY, L, G = torch.zeros_like(Y), torch.zeros(1, device="cuda"), torch.zeros_like(P)
+    dY, L, G = torch.zeros_like(Y), torch.zeros(tj.MLP_MSE_LOSS_FLOATS, device="cuda"), torch.zeros_like(P)
     scr = torch.zeros(2 * batch * 256, device="cuda")
     tj.trajam_mlp_forward(shape, batch, 1, P.data_ptr(), X.data_ptr(), acts_d.data_ptr(), Y.data_ptr(), st)
     tj.trajam_mlp_mse(batch * 22, Y.data_ptr(), T.data_ptr(), dY.data_ptr(), L.data_ptr(), st)
