@@ -672,6 +672,44 @@ def hw_counters(probe_args, kernel_prefix, launch_ms, algorithmic_bytes, timeout
     return traffic, out
 
 
+MFMA_COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
+N_SIMD = 1024   # 256 CUs x 4 SIMDs
+
+
+def mfma_counters(child_args, families, calls, timeout=150):
+    """Matrix-core counters measured in this run: one rocprofv3 --pmc pass over a
+    child `bench.py <child_args>` that makes `calls` calls of each measured operation.
+    Per kernel family (a name fragment -> a label): bf16 matrix-core FLOPs issued per
+    call (MOPS x 512, including the zero padding of edge tiles) and the matrix cores'
+    busy fraction while the family's dispatches run (busy cycles over GRBM_GUI_ACTIVE
+    per XCD x 1024 SIMDs)."""
+    import shutil
+    import subprocess
+    import tempfile
+    prof = shutil.which("rocprofv3")
+    if prof is None:
+        return {"error": "rocprofv3 not found"}
+    d = tempfile.mkdtemp(prefix="trajam_mfma_", dir="/tmp")
+    cmd = ["timeout", "-s", "KILL", str(timeout), prof, "--pmc", *MFMA_COUNTERS, "--output-format", "csv",
+           "-d", d, "-o", "p", "--", sys.executable, os.path.abspath(__file__), *child_args]
+    print("bench: matrix-core counter pass " + " ".join(child_args), file=sys.stderr, flush=True)
+    r = subprocess.run(cmd, cwd="/tmp", env=dict(os.environ, TMPDIR="/tmp"), capture_output=True, text=True)
+    rows = _read_counters(d)
+    shutil.rmtree(d, ignore_errors=True)
+    out = {"counters": list(MFMA_COUNTERS), "calls": calls}
+    for fam, label in families:
+        ks = [v for (n, _), v in rows.items() if f"::{fam}" in n]
+        if not ks:
+            out[label] = {"error": f"no {fam} dispatch (rocprofv3 exit {r.returncode}): {r.stderr[-300:]}"}
+            continue
+        mops = sum(v.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) for v in ks)
+        busy = sum(v.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for v in ks)
+        gui = sum(v.get("GRBM_GUI_ACTIVE", 0.0) for v in ks) / 8.0
+        out[label] = {"kernel": fam, "dispatches": len(ks), "mfma_gflop_per_call": mops * 512 / calls / 1e9,
+                      "mfma_busy_frac": busy / (gui * N_SIMD) if gui > 0 else None}
+    return out
+
+
 def probe(args):
     """Child of hw_counters: the headline step's launch twice, then a copy of known
     size (the byte counters' calibration).  Prints nothing on stdout."""
@@ -681,12 +719,13 @@ def probe(args):
     k, spw = (int(x) for x in args.probe_launch.split(","))
     w = wl.config3() if args.probe == "cfg3" else wl.config2(batch=args.batch)
     K = args.iters
-    solver = tj.Solver.for_workload(w, precision="fp32", sphere=False if args.probe == "cfg3" else None)
-    xi, obs = tj.device_workload(w, torch.float32)
+    solver = tj.Solver.for_workload(w, precision=args.probe_precision,
+                                    sphere=False if args.probe == "cfg3" else None)
+    xi, obs = tj.device_workload(w, solver.dtype)
     solver.set_launch(k, spw)
     solver.set_obstacles(obs)
     xb, lam = xi.clone(), torch.zeros_like(xi)
-    tr = torch.zeros((K, w.batch), dtype=torch.float32, device="cuda")
+    tr = torch.zeros((K, w.batch), dtype=solver.dtype, device="cuda")
     for _ in range(2):
         xb.copy_(xi)
         lam.zero_()
@@ -763,6 +802,7 @@ def main():
     ap.add_argument("--probe", choices=["cfg3", "cfg2"], default=None,
                     help="internal: the counter passes' child process")
     ap.add_argument("--probe-launch", default="1,1", help="internal: kernel,samples-per-workgroup")
+    ap.add_argument("--probe-precision", choices=["fp32", "bf16"], default="fp32", help="internal")
     ap.add_argument("--ttr-cap", type=int, default=300)
     ap.add_argument("--ws-scenes", type=int, default=2048)
     ap.add_argument("--ws-epochs", type=int, default=20)
@@ -844,6 +884,21 @@ def main():
     prec_out = precision_bench(args) if args.precision_steps > 0 else None
     polar_out = polar_bench(args) if args.polar_steps > 0 else None
     mfma_out = mfma_bench(args) if args.mfma_steps > 0 else None
+    if mfma_out is not None and not args.no_counters:
+        # one untimed and two timed calls of each in the child
+        mfma_out["counters"] = mfma_counters(["--mfma-only", "--mfma-steps", "2"],
+                                             [("gemm_mfma_kernel", "train_step"), ("warm_jump_kernel", "warm_jump")], 3)
+    if prec_out is not None and not args.no_counters:
+        k, spw = prec_out["bf16"]["launch_shape"][:2]
+        fam = "am_project_kernel" if k == 0 else "am_wave_kernel"
+        c = mfma_counters(["--probe", "cfg3", "--probe-precision", "bf16", "--probe-launch", f"{k},{spw}",
+                           "--iters", str(wl.config3().iters)], [(fam, "projection")], 2)
+        proj = c.get("projection", {})
+        if "mfma_gflop_per_call" in proj:
+            ms = prec_out["bf16"]["ms_per_projection"]
+            proj["achieved_TFLOPs"] = proj["mfma_gflop_per_call"] * 1e9 / (ms * 1e-3) / 1e12
+            proj["frac_of_bf16_peak"] = proj["achieved_TFLOPs"] * 1e12 / PEAK_BF16_MFMA
+        prec_out["bf16"]["matrix_cores"] = c
 
     out = {
         "metric": "traj-iters/s & time-to-residual<=1e-3, learned warm-start vs cold, 1 MI355X",
