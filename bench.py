@@ -380,9 +380,52 @@ def ragged_bench(args):
                   "the resets"}
     del g
     plan.close()
+    # the multi-agent half alone (its own plan): the agents kernel's time and roofline
+    agent_items = [it for it, w in zip(items, ws) if w.n_agents > 1]
+    agent_ws = [w for w in ws if w.n_agents > 1]
+    if agent_items:
+        aplan = tj.RaggedPlan(agent_items, K)
+        reset()
+        aplan.launch()
+        torch.cuda.synchronize()
+        ams = []
+        for _ in range(args.ragged_steps):
+            reset()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            aplan.launch()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ams.append(e0.elapsed_time(e1))
+        aplan.close()
+        a_ms = float(np.mean(ams))
+        ops = sum(w.batch * agents_ops_per_unit(w) for w in agent_ws) * K
+        out["multi_agent"] = {
+            "problems": len(agent_ws), "joint_samples": sum(w.batch for w in agent_ws),
+            "agents_mean": float(np.mean([w.n_agents for w in agent_ws])), "launch_ms": a_ms,
+            "roofline": {"bound": "alu", "achieved": ops / (a_ms * 1e-3) / 1e12, "peak": PEAK_VALU_OPS / 1e12,
+                         "unit": "Tlane-ops/s", "frac": ops / (a_ms * 1e-3) / PEAK_VALU_OPS,
+                         "ops_per_launch": ops}}
+        if not args.no_counters:
+            _, c = hw_counters(["--probe", "ragged", "--ragged-problems", str(args.ragged_problems),
+                                "--iters", str(K)], "am_ragged_kernel", a_ms, 1)
+            out["multi_agent"]["counters"] = {k: c.get(k) for k in ("sq", "valu_insts", "valu_issue_frac",
+                                                                    "valu_insts_per_wave", "error")}
     for s in solvers:
         s.close()
     return out
+
+
+def agents_ops_per_unit(w) -> int:
+    """Algorithmic VALU lane-ops of one joint sample's AM iteration in a multi-agent
+    problem, at the lower end of each element's cost: every (agent, obstacle, time) and
+    every unordered (agent pair, time) clearance test at 2 D + 1 ops (a difference, a
+    squared norm, a compare), the two kinematic bounds of every agent at D + 1, the
+    waypoint map and the F^T contraction (2 D 3 n_v FMAs per agent and time) and the QP
+    (D n_v (n_v + 4) per agent); an FMA counts once."""
+    D, nv, npt, no, N = w.dims, w.n_v, w.n_steps, w.n_obs, w.n_agents
+    per_t = (N * no + N * (N - 1) // 2) * (2 * D + 1) + 2 * N * (D + 1) + 2 * D * 3 * nv * N
+    return npt * per_t + N * D * nv * (nv + 4)
 
 
 def precision_bench(args):
@@ -710,12 +753,45 @@ def mfma_counters(child_args, families, calls, timeout=150):
     return out
 
 
+def probe_ragged(args):
+    """Child of hw_counters for the multi-agent half of the ragged set: its plan
+    launched twice, then the copy of known size."""
+    import torch
+    from paper_2408_10731_amd import trajam as tj
+    from paper_2408_10731_amd import workloads as wl
+    ws = [w for w in wl.config5(args.ragged_problems, iters=args.iters) if w.n_agents > 1]
+    items, solvers = [], []
+    for w in ws:
+        s = tj.Solver.for_workload(w, precision="fp32")
+        xi, obs = tj.device_workload(w, torch.float32)
+        s.set_obstacles(obs)
+        items.append((s, xi, w.boundary, xi.clone(), torch.zeros_like(xi)))
+        solvers.append(s)
+    plan = tj.RaggedPlan(items, args.iters)
+    for _ in range(2):
+        for it in items:
+            it[3].copy_(it[1])
+            it[4].zero_()
+        plan.launch()
+    torch.cuda.synchronize()
+    a = torch.ones(PROBE_COPY_MIB << 18, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    plan.close()
+    for s in solvers:
+        s.close()
+
+
 def probe(args):
     """Child of hw_counters: the headline step's launch twice, then a copy of known
     size (the byte counters' calibration).  Prints nothing on stdout."""
     import torch
     from paper_2408_10731_amd import trajam as tj
     from paper_2408_10731_amd import workloads as wl
+    if args.probe == "ragged":
+        probe_ragged(args)
+        return
     k, spw = (int(x) for x in args.probe_launch.split(","))
     w = wl.config3() if args.probe == "cfg3" else wl.config2(batch=args.batch)
     K = args.iters
@@ -799,7 +875,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-counters", action="store_true",
                     help="skip the rocprofv3 counter passes (traffic and VALU issue become null)")
-    ap.add_argument("--probe", choices=["cfg3", "cfg2"], default=None,
+    ap.add_argument("--probe", choices=["cfg3", "cfg2", "ragged"], default=None,
                     help="internal: the counter passes' child process")
     ap.add_argument("--probe-launch", default="1,1", help="internal: kernel,samples-per-workgroup")
     ap.add_argument("--probe-precision", choices=["fp32", "bf16"], default="fp32", help="internal")

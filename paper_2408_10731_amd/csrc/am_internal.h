@@ -72,6 +72,10 @@ struct ContState {
 __host__ __device__ constexpr int stage_fields(int dims, bool sphere) { return sphere ? 2 * dims + 2 : 4 * dims; }
 constexpr int kStageMaxFloats = 4096;
 
+// Per-wave LDS scalars of the multi-agent kernels' position exchange (128 entries x
+// 4: every agent's position at entries a and a + N).
+constexpr int kAgentPosScalars = 512;
+
 // Packed obstacle record length (scalars), any dims.
 constexpr int kObstacleRecord = 16;
 // Field offsets in the packed record: centre, -velocity, 1/semi-axes, semi-axes,

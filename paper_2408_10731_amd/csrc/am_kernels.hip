@@ -586,6 +586,22 @@ __device__ __forceinline__ double readlane_t<double>(double v, int l)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+template <typename T>
+__device__ __forceinline__ T shfl_t(T v, int src);
+template <>
+__device__ __forceinline__ float shfl_t<float>(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+template <>
+__device__ __forceinline__ double shfl_t<double>(double v, int src)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // The same obstacle polar step for the points of one wave, with exact culling: the
 // wave's points span a small box (a stretch of one trajectory), and an obstacle
 // whose bounding box -- swept over the wave's time range for moving obstacles, and
@@ -1604,10 +1620,11 @@ __global__ __launch_bounds__(kMaxThreads) void am_wave_kernel(AmArgs<T> a)
 // Polar step of every (agent, obstacle), kinematic bound and pair row at time t for
 // this lane's position p, velocity v, acceleration acc.  Adds the summed position
 // residual to S and the velocity / acceleration residuals to rv / ra.
+// px: this wave's LDS area of kAgentPosScalars for the agents' positions.
 template <typename T, int D, typename A>
-__device__ __forceinline__ void agents_rows(const A &a, const T *ol, int lane, bool active, T tt, const T (&p)[D],
-                                            const T (&v)[D], const T (&acc)[D], T (&S)[D], T (&rv)[D],
-                                            T (&ra)[D], T &r2, T &rmax)
+__device__ __forceinline__ void agents_rows(const A &a, const T *ol, T *px, int lane, bool active, T tt,
+                                            const T (&p)[D], const T (&v)[D], const T (&acc)[D], T (&S)[D],
+                                            T (&rv)[D], T (&ra)[D], T &r2, T &rmax)
 {
     const int N = a.n_agents;
     {
@@ -1631,40 +1648,83 @@ __device__ __forceinline__ void agents_rows(const A &a, const T *ol, int lane, b
         if (a.use_v) bound_residual<T, D>(v, a.vmax, rv, r2, rmax);
         if (a.use_a) bound_residual<T, D>(acc, a.amax, ra, r2, rmax);
     }
+    // Pair rows, each unordered pair evaluated once: at offset o = 1 .. N/2 lane a takes
+    // partner b = (a + o) mod N, so every lane does about N/2 clearance tests instead
+    // of N - 1.  The partner's row is the exact negation of lane a's (x_ba = -x_ab and
+    // the same scale factor), handed over with a lane rotation by o when some pair at
+    // this offset is near; at o = N/2 (N even) both lanes of a pair meet it, so each
+    // keeps its own row.  Positions are published in LDS twice over (entries a and
+    // a + N), so partner a + o needs no wrap, and read four offsets at a time.
     const T R = a.pair_r, R2 = R * R;
-    for (int b = 0; b < N; ++b) {
-        T x[D], nn = T(0);
+    if (active) {
 #pragma unroll
         for (int ax = 0; ax < D; ++ax) {
-            x[ax] = p[ax] - readlane_t<T>(p[ax], b);
-            nn = fma(x[ax], x[ax], nn);
-        }
-        if (active && b != lane && nn < R2) {
-            T r[D];
-            if (nn > T(0)) {
-                const T f = T(1) - R * rsqrt_t(nn);
-#pragma unroll
-                for (int ax = 0; ax < D; ++ax) r[ax] = x[ax] * f;
-            } else {
-#pragma unroll
-                for (int ax = 0; ax < D; ++ax) r[ax] = T(0);
-                r[D == 2 ? 0 : 2] = lane < b ? -R : R;
-            }
-            T rr = T(0);
-#pragma unroll
-            for (int ax = 0; ax < D; ++ax) {
-                S[ax] += r[ax];
-                rr = fma(r[ax], r[ax], rr);
-                rmax = fmax(rmax, fabs(r[ax]));
-            }
-            if (lane < b) r2 += rr;
+            px[4 * lane + ax] = p[ax];
+            px[4 * (lane + N) + ax] = p[ax];
         }
     }
+    wave_lds_sync();
+    const int half = N >> 1;
+    // lanes past N are inactive: they read entry lane + o < 128, whatever it holds
+    const T *pq = px + 4 * lane;
+    for (int o0 = 1; o0 <= half; o0 += 4) {
+        T x[4][D];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int o = min(o0 + j, half);   // past half: a repeated offset, skipped below
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) x[j][ax] = p[ax] - pq[4 * o + ax];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int o = o0 + j;
+            if (o > half) break;
+            T nn = T(0);
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) nn = fma(x[j][ax], x[j][ax], nn);
+            const bool near = active && nn < R2;
+            const bool mid = 2 * o == N;
+            T r[D];
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) r[ax] = T(0);
+            if (near) {
+                const int b = lane + o < N ? lane + o : lane + o - N;
+                if (nn > T(0)) {
+                    const T f = T(1) - R * rsqrt_t(nn);
+#pragma unroll
+                    for (int ax = 0; ax < D; ++ax) r[ax] = x[j][ax] * f;
+                } else {
+                    // coincident agents: a fixed axis and the lane order give the direction
+                    r[D == 2 ? 0 : 2] = lane < b ? -R : R;
+                }
+                T rr = T(0);
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax) {
+                    S[ax] += r[ax];
+                    rr = fma(r[ax], r[ax], rr);
+                    rmax = fmax(rmax, fabs(r[ax]));
+                }
+                if (!mid || lane < b) r2 += rr;
+            }
+            if (!mid && __any(near)) {
+                // the lane whose partner at this offset is this lane
+                int src = lane - o;
+                src = src < 0 ? src + N : src;
+                src = active ? src : lane;
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax) {
+                    const T g = shfl_t<T>(r[ax], src);
+                    if (active) S[ax] -= g;
+                }
+            }
+        }
+    }
+    wave_lds_sync();  // every lane has read the positions before the next time step
 }
 
 // One joint sample's whole projection on one wavefront (n_agents <= 64 lanes).
 template <typename T, int D, int NVP, typename A>
-__device__ __forceinline__ void agents_sample(const A &a, const int sample, const int lane, T *ol)
+__device__ __forceinline__ void agents_sample(const A &a, const int sample, const int lane, T *ol, T *px)
 {
     if (ol) stage_obstacles<T, D>(ol, a.obs, a.n_o, a.sphere, lane);
     const int N = a.n_agents, nv = a.nv, n_p = a.n_p;
@@ -1696,30 +1756,32 @@ __device__ __forceinline__ void agents_sample(const A &a, const int sample, cons
             for (int m = 0; m < NVP; ++m) ftr[ax][m] = T(0);
         T r2 = T(0), rmax = T(0);
         for (int t = 0; t < n_p; ++t) {
-            const TRAJAM_CONST_AS T *r0 = phi + (size_t)(0 * n_p + t) * NVP;
-            const TRAJAM_CONST_AS T *r1 = phi + (size_t)(1 * n_p + t) * NVP;
-            const TRAJAM_CONST_AS T *rr = phi + (size_t)(2 * n_p + t) * NVP;
+            T ph[3][NVP];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int m = 0; m < NVP; ++m) ph[d][m] = phi[(size_t)(d * n_p + t) * NVP + m];
             T p[D], v[D], acc[D];
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) {
                 T sp = T(0), sv = T(0), sa = T(0);
 #pragma unroll
                 for (int m = 0; m < NVP; ++m) {
-                    sp = fma(r0[m], xb[ax][m], sp);
-                    sv = fma(r1[m], xb[ax][m], sv);
-                    sa = fma(rr[m], xb[ax][m], sa);
+                    sp = fma(ph[0][m], xb[ax][m], sp);
+                    sv = fma(ph[1][m], xb[ax][m], sv);
+                    sa = fma(ph[2][m], xb[ax][m], sa);
                 }
                 p[ax] = sp;
                 v[ax] = sv;
                 acc[ax] = sa;
             }
             T S[D], rv[D], ra[D];
-            agents_rows<T, D, A>(a, ol, lane, active, T(t) * a.dt, p, v, acc, S, rv, ra, r2, rmax);
+            agents_rows<T, D, A>(a, ol, px, lane, active, T(t) * a.dt, p, v, acc, S, rv, ra, r2, rmax);
 #pragma unroll
             for (int ax = 0; ax < D; ++ax)
 #pragma unroll
                 for (int m = 0; m < NVP; ++m)
-                    ftr[ax][m] = fma(r0[m], S[ax], fma(r1[m], rv[ax], fma(rr[m], ra[ax], ftr[ax][m])));
+                    ftr[ax][m] = fma(ph[0][m], S[ax], fma(ph[1][m], rv[ax], fma(ph[2][m], ra[ax], ftr[ax][m])));
         }
         const T r2w = wave_sum(r2);
         if (lane == 0) {
@@ -1795,7 +1857,7 @@ __device__ __forceinline__ void agents_sample(const A &a, const int sample, cons
 
 // Residual only, at the given joint coefficients: res[sample] = 2-norm, res_max.
 template <typename T, int D, int NVP, typename A>
-__device__ __forceinline__ void agents_residual(const A &a, const int sample, const int lane, T *ol)
+__device__ __forceinline__ void agents_residual(const A &a, const int sample, const int lane, T *ol, T *px)
 {
     if (ol) stage_obstacles<T, D>(ol, a.obs, a.n_o, a.sphere, lane);
     const int N = a.n_agents, nv = a.nv, n_p = a.n_p;
@@ -1824,7 +1886,7 @@ __device__ __forceinline__ void agents_residual(const A &a, const int sample, co
             acc[ax] = sa;
         }
         T S[D], rv[D], ra[D];
-        agents_rows<T, D, A>(a, ol, lane, active, T(t) * a.dt, p, v, acc, S, rv, ra, r2, rmax);
+        agents_rows<T, D, A>(a, ol, px, lane, active, T(t) * a.dt, p, v, acc, S, rv, ra, r2, rmax);
     }
     const T r2w = wave_sum(r2), mx = wave_max(rmax);
     if (lane == 0) {
@@ -1833,15 +1895,16 @@ __device__ __forceinline__ void agents_residual(const A &a, const int sample, co
     }
 }
 
-// a.cull_lds: per-wave LDS stage of the obstacles (floats per wave), 0 = no culling.
+// Per-wave LDS of the multi-agent kernels: a.cull_lds scalars of obstacle stage (0 =
+// no culling), then kAgentPosScalars for the agents' positions.
 template <typename T, int D, int NVP>
 __global__ __launch_bounds__(kMaxThreads) void am_agents_kernel(AmArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int sample = blockIdx.x * a.tb + (threadIdx.x >> 6);
     if (sample >= a.batch) return;  // whole waves leave together
-    T *ol = a.cull_lds ? reinterpret_cast<T *>(smem_raw) + (threadIdx.x >> 6) * a.cull_lds : nullptr;
-    agents_sample<T, D, NVP, AmArgs<T>>(a, sample, threadIdx.x & 63, ol);
+    T *slot = reinterpret_cast<T *>(smem_raw) + (threadIdx.x >> 6) * (a.cull_lds + kAgentPosScalars);
+    agents_sample<T, D, NVP, AmArgs<T>>(a, sample, threadIdx.x & 63, a.cull_lds ? slot : nullptr, slot + a.cull_lds);
 }
 
 template <typename T, int D, int NVP>
@@ -1850,8 +1913,9 @@ __global__ __launch_bounds__(kMaxThreads) void am_agents_residual_kernel(AmArgs<
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int sample = blockIdx.x * a.tb + (threadIdx.x >> 6);
     if (sample >= a.batch) return;
-    T *ol = a.cull_lds ? reinterpret_cast<T *>(smem_raw) + (threadIdx.x >> 6) * a.cull_lds : nullptr;
-    agents_residual<T, D, NVP, AmArgs<T>>(a, sample, threadIdx.x & 63, ol);
+    T *slot = reinterpret_cast<T *>(smem_raw) + (threadIdx.x >> 6) * (a.cull_lds + kAgentPosScalars);
+    agents_residual<T, D, NVP, AmArgs<T>>(a, sample, threadIdx.x & 63, a.cull_lds ? slot : nullptr,
+                                          slot + a.cull_lds);
 }
 
 // ----------------------------------------------------------------------------
@@ -1912,10 +1976,12 @@ __global__ __launch_bounds__(kMaxThreads) void am_ragged_kernel(const AmArgs<flo
         const int nvp = a.nv <= 8 ? 8 : 12;
         const int tpl = (a.n_p + 63) >> 6;
         if constexpr (AGENTS) {
-            // per-wave obstacle stage: wl points at this wave's LDS slot (cull_lds floats)
+            // this wave's LDS slot: the obstacle stage (cull_lds floats, at most the
+            // plan's largest), the agents' positions at the slot's end
             float *ol = a.cull_lds ? wl : nullptr;
-            if (a.dims == 2) { if (nvp == 8) agents_sample<float, 2, 8, RaggedArgs>(a, sample, lane, ol); else agents_sample<float, 2, 12, RaggedArgs>(a, sample, lane, ol); }
-            else             { if (nvp == 8) agents_sample<float, 3, 8, RaggedArgs>(a, sample, lane, ol); else agents_sample<float, 3, 12, RaggedArgs>(a, sample, lane, ol); }
+            float *px = wl + wave_lds - kAgentPosScalars;
+            if (a.dims == 2) { if (nvp == 8) agents_sample<float, 2, 8, RaggedArgs>(a, sample, lane, ol, px); else agents_sample<float, 2, 12, RaggedArgs>(a, sample, lane, ol, px); }
+            else             { if (nvp == 8) agents_sample<float, 3, 8, RaggedArgs>(a, sample, lane, ol, px); else agents_sample<float, 3, 12, RaggedArgs>(a, sample, lane, ol, px); }
             wave_lds_sync();  // the next unit restages
             continue;
         } else {
@@ -2159,7 +2225,7 @@ hipError_t launch_agents_t(int dims, int nvp, const AmArgs<T> &a, bool residual,
     if (a.cull_lds < 0 || (size_t)a.cull_lds * sizeof(T) * a.tb > (size_t)kStageMaxFloats * sizeof(float) * 4)
         return hipErrorInvalidValue;
     const dim3 grid((a.batch + a.tb - 1) / a.tb), block(64 * a.tb);
-    const size_t lds = sizeof(T) * (size_t)a.cull_lds * a.tb;
+    const size_t lds = sizeof(T) * (size_t)(a.cull_lds + kAgentPosScalars) * a.tb;
 #define TRAJAM_AGENTS(DD, NN)                                                                            \
     if (dims == DD && nvp == NN) {                                                                       \
         if (residual) hipLaunchKernelGGL((am_agents_residual_kernel<T, DD, NN>), grid, block, lds, st, a); \
@@ -2199,9 +2265,10 @@ hipError_t launch_ragged(const AmArgs<float> *probs, const int *offsets, int n_p
     if (e != hipSuccess) return e;
     if (agents) {
         if (agent_stage < 0 || agent_stage > kStageMaxFloats) return hipErrorInvalidValue;
-        const size_t lds = sizeof(float) * (size_t)agent_stage * (kMaxThreads / 64);
+        const int wave_lds = agent_stage + kAgentPosScalars;
+        const size_t lds = sizeof(float) * (size_t)wave_lds * (kMaxThreads / 64);
         hipLaunchKernelGGL(am_ragged_kernel<true>, dim3(blocks), dim3(kMaxThreads), lds, st, probs, offsets, n_probs,
-                           total, counter, agent_stage);
+                           total, counter, wave_lds);
     } else {
         const size_t lds = sizeof(float) * (size_t)kRaggedWaveLds * (kMaxThreads / 64);
         hipLaunchKernelGGL(am_ragged_kernel<false>, dim3(blocks), dim3(kMaxThreads), lds, st, probs, offsets,
