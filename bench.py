@@ -252,6 +252,106 @@ def time_to_residual(args, w, solver, xi, obs, stream, tol=1e-3, net=None, info=
     return out
 
 
+def warm_cfg4_bench(args, tol=1e-3):
+    """The learned warm start where config 4 uses it: inside the sampling loop among
+    moving obstacles.  A network is trained (bf16, matrix cores) on solver-generated
+    pairs of config-4 scenes (seeds from 40,000, disjoint from the held-out ones); then
+      - time to residual, cold against warm, on the 16 held-out config-4 scenes
+        90,001-90,016 (2000 samples each, the planner's first-iteration distribution:
+        straight line plus N(0, 0.5^2) per coefficient; a scene whose median never
+        reaches tol within the cap counts the cap, in iterations and in time);
+      - one planning call of the loop (30 iterations x 2000 samples x 15 AM
+        iterations) on the benchmark scene, cold and with the warm start (3-iteration
+        probe, jump, fallback, 12 more iterations: the same 15 AM iterations a
+        projection), on the same draws: time per call (graph replay), and per CEM
+        iteration the batch-median residual after the 15 iterations and the first
+        iteration at which it is <= tol."""
+    import torch
+    from paper_2408_10731_amd import cem
+    from paper_2408_10731_amd import trajam as tj
+    from paper_2408_10731_amd import warmstart as ws
+    from paper_2408_10731_amd import workloads as wl
+
+    stream = torch.cuda.current_stream()
+    cap = args.ttr_cap
+    t0 = time.perf_counter()
+    data = ws.generate(ws.family_scene("cfg4"), list(range(40_000, 40_000 + args.ws4_scenes)), 64,
+                       k0=ws.K0, cap=150)
+    t_gen = time.perf_counter() - t0
+    w4 = wl.config4(batch=2000)
+    net = ws.Net(ws.widths_for(w4), seed=0, precision=1, max_batch=2000)
+    curve = ws.train(net, data, epochs=args.ws_epochs, batch=512, lr=1e-3)
+    torch.cuda.synchronize()
+    out = {"tol": tol, "cap": cap, "probe_iters": ws.K0,
+           "training": {"family": "config 4 (100 moving circles)", "scenes": args.ws4_scenes,
+                        "pairs": int(data.x.shape[0]), "epochs": args.ws_epochs, "precision": "bf16 matrix cores",
+                        "loss_first": curve[0], "loss_last": curve[-1], "generate_s": t_gen,
+                        "seconds": time.perf_counter() - t0}}
+    per, tot = [], {"cold_iters": 0, "warm_iters": 0, "cold_ms": 0.0, "warm_ms": 0.0, "warm_wins_iters": 0,
+                    "warm_wins_time": 0}
+    for seed in range(90_001, 90_017):
+        w_ = wl.config4_scene(seed, batch=2000)
+        s_ = tj.Solver.for_workload(w_, precision="fp32")
+        x_, o_ = tj.device_workload(w_, torch.float32)
+        r = ttr_scene(w_, s_, x_, o_, net, cap, stream, tol, reps=10)
+        s_.close()
+        ci = r["cold_iters"] if r["cold_iters"] is not None else cap
+        wi = r["warm_iters"] if r["warm_iters"] is not None else cap
+        per.append({"seed": seed, **{k: r.get(k) for k in ("cold_iters", "warm_iters", "cold_ms", "warm_ms",
+                                                           "cold_reached", "warm_reached", "warm_fallbacks")}})
+        tot["cold_iters"] += ci
+        tot["warm_iters"] += wi
+        tot["cold_ms"] += r.get("cold_ms", 0.0)
+        tot["warm_ms"] += r.get("warm_ms", 0.0)
+        tot["warm_wins_iters"] += int(wi < ci)
+        tot["warm_wins_time"] += int(r.get("warm_ms", 0.0) < r.get("cold_ms", 0.0))
+    out["held_out"] = {"scenes": per, "total": tot}
+
+    # one planning call, cold and warm, on the same draws
+    w = wl.config4(batch=4)
+    D, nv = w.dims, w.n_v
+    N, Nb, Np, Ne, K = 30, 2000, 1454, 363, 15
+    mu0 = wl.line_samples(np.random.default_rng(0), 1, w.degree, w.boundary[:, 0],
+                          w.boundary[:, 3], 0.0)[0].reshape(-1)
+    S0 = 0.25 * np.eye(D * nv)
+    L0 = np.linalg.cholesky(S0 + 1e-10 * np.eye(D * nv))
+    z = torch.as_tensor(np.random.default_rng(1).normal(size=(N, Nb, D * nv)), dtype=torch.float32,
+                        device="cuda")
+    calls = {}
+    for arm in ("cold", "warm"):
+        solver = tj.Solver.for_workload(w, precision="fp32", max_batch=Nb)
+        _, obs = tj.device_workload(w, torch.float32)
+        ctx = ws.WarmContext(solver, net, Nb) if arm == "warm" else None
+        planner = cem.Planner(solver, Nb, Np, Ne, K, warm=ctx)
+        planner.set_distribution(mu0, S0, L0)
+        rec = []
+        planner.run(z, w.boundary, obs, record=rec)
+        torch.cuda.synchronize()
+        med = np.array([np.median(r[8].cpu().numpy(), axis=1) for r in rec])   # [N, K]
+        first = [int(np.nonzero(m <= tol)[0][0]) + 1 if np.any(m <= tol) else None for m in med]
+        best_cost = float(rec[-1][3].cpu().numpy()[int(rec[-1][1][0])])
+        planner.set_distribution(mu0, S0, L0)
+        planner.capture(z, w.boundary, obs)
+
+        def call():
+            planner.set_distribution(mu0, S0, L0)
+            planner.replay()
+        ms = _time(call, args.cem_calls, stream)
+        calls[arm] = {"ms_per_planning_call": ms,
+                      "median_residual_after_15": [float(m[-1]) for m in med],
+                      "cem_iterations_reaching_tol": int(sum(f is not None for f in first)),
+                      "first_iteration_at_tol": first,
+                      "best_c_aug": best_cost}
+        if arm == "warm":
+            calls[arm]["fallbacks_last_iteration"] = int(((planner.flags.cpu().numpy() & 4) != 0).sum())
+        del planner
+        solver.close()
+    out["planning_call"] = {"config": "30 CEM iterations x 2000 samples x 15 AM iterations, 100 moving "
+                                      "circles, 1454 projected / 363 elite, fp32, same draws for both arms",
+                            **calls}
+    return out
+
+
 PEAK_BF16_MFMA = 2.5e15   # dense bf16 matrix-core FLOP/s of MI355X
 
 
@@ -891,6 +991,8 @@ def main():
                     help="timed calls of the materialised polar variables; 0 skips that leg")
     ap.add_argument("--cem-only", action="store_true",
                     help="run only the sampling-loop leg and print its JSON (profiling)")
+    ap.add_argument("--ws4-scenes", type=int, default=8192,
+                    help="config-4 training scenes of the warm start in the sampling loop; 0 skips that leg")
     ap.add_argument("--mfma-steps", type=int, default=10, help="timed calls of the matrix-core leg; 0 skips it")
     ap.add_argument("--mfma-only", action="store_true",
                     help="run only the matrix-core leg and print its JSON (profiling)")
@@ -957,6 +1059,7 @@ def main():
     c2["solver"].close()
     ragged = ragged_bench(args) if args.ragged_problems > 0 else None
     cem_out = cem_bench(args) if args.cem_calls > 0 else None
+    warm4 = warm_cfg4_bench(args) if args.ws4_scenes > 0 and args.cem_calls > 0 and args.ttr_cap > 0 else None
     prec_out = precision_bench(args) if args.precision_steps > 0 else None
     polar_out = polar_bench(args) if args.polar_steps > 0 else None
     mfma_out = mfma_bench(args) if args.mfma_steps > 0 else None
@@ -996,6 +1099,7 @@ def main():
         "precision_cfg3": prec_out,
         "polar_materialised": polar_out,
         "matrix_cores": mfma_out,
+        "warm_start_config4": warm4,
         "wall_s_timed_region": h["wall"],
     }
     if not args.no_cpu:

@@ -15,13 +15,22 @@ from . import trajam as tj
 
 
 class Planner:
+    """warm: a warmstart.WarmContext of the same solver (max batch >= n_samples).  With
+    it every projection starts from the learned warm start -- its probe's k0 cold
+    iterations, the network's jump and the per-sample cold fallback -- and continues
+    for am_iters - k0 iterations, so a projection still costs am_iters AM iterations."""
+
     def __init__(self, solver: "tj.Solver", n_samples: int, n_proj: int, n_elite: int,
-                 am_iters: int, sigma: float = 0.5, gamma: float = 1.0, quantum: float = 1e-6):
+                 am_iters: int, sigma: float = 0.5, gamma: float = 1.0, quantum: float = 1e-6,
+                 warm=None):
         import torch
         self.s = solver
         self.torch = torch
         self.N_b, self.n_proj, self.n_elite = int(n_samples), int(n_proj), int(n_elite)
         self.K = int(am_iters)
+        self.warm = warm
+        if warm is not None and not (warm.solver is solver and 0 < warm.k0 < self.K):
+            raise ValueError("warm start: a context of this solver with 0 < k0 < am_iters")
         self.sigma, self.gamma, self.quantum = float(sigma), float(gamma), float(quantum)
         D, nv, dt = solver.dims, solver.nv, solver.dtype
         self.dim = D * nv
@@ -37,6 +46,8 @@ class Planner:
         self.mu = torch.zeros(self.dim, dtype=dt, device=dev)
         self.Sigma = torch.zeros((self.dim, self.dim), dtype=dt, device=dev)
         self.chol = torch.zeros_like(self.Sigma)
+        self.trace = torch.zeros((self.K, self.N_b), dtype=dt, device=dev)  # residual per AM iteration
+        self.flags = None   # warm start: the last projection's fallback flags
         self.graph = None
 
     def set_distribution(self, mu0, Sigma0, chol0):
@@ -52,7 +63,16 @@ class Planner:
                              z_l.data_ptr(), self.xi.data_ptr(), self.xb.data_ptr(),
                              self.lam.data_ptr(), st)
         # obstacles were packed once for the whole call (None reuses them)
-        self.s.project(self.xi, boundary, None, self.xb, self.lam, self.K, stream=stream)
+        if self.warm is None:
+            self.s.project(self.xi, boundary, None, self.xb, self.lam, self.K, res_trace=self.trace,
+                           stream=stream)
+        else:
+            k0 = self.warm.k0
+            _, _, fl, _ = self.warm.run(self.xi, boundary, None, xb_out=self.xb, lam_out=self.lam,
+                                        trace_out=self.trace[:k0])
+            self.s.project(self.xi, boundary, None, self.xb, self.lam, self.K - k0, res_trace=self.trace[k0:],
+                           stream=stream)
+            self.flags = fl
         self.s.residuals(self.xb, None, self.res, stream=stream)
         tj.trajam_cem_cost(h, self.N_b, self.xb.data_ptr(), self.res.data_ptr(), self.quantum,
                            self.caug.data_ptr(), self.rkey.data_ptr(), st)
@@ -66,7 +86,7 @@ class Planner:
                              self.caug.data_ptr(), self.sigma, self.gamma, self.mu.data_ptr(),
                              self.Sigma.data_ptr(), self.chol.data_ptr(), st)
         if record is not None:
-            record[-1] = record[-1] + (self.mu.clone(), self.Sigma.clone(), self.xb.clone())
+            record[-1] = record[-1] + (self.mu.clone(), self.Sigma.clone(), self.xb.clone(), self.trace.clone())
 
     def autotune(self, z0, boundary, obs):
         """Pick the projection's launch shape for this planner's batch: draws one batch

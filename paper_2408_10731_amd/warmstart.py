@@ -247,16 +247,21 @@ class WarmContext:
         tj.trajam_warm_pack_mfma(self.net.shape, self.net.params.data_ptr(), self.packed.data_ptr(),
                                  torch.cuda.current_stream().cuda_stream)
 
-    def run(self, xi, boundary, obs):
+    def run(self, xi, boundary, obs, xb_out=None, lam_out=None, trace_out=None):
         """(xb_w, lam_w, flags, probe_trace) for the samples xi [B, D, n_v]: the state
-        after the probe and the jump; the projection continues from it."""
+        after the probe and the jump; the projection continues from it.  xb_out, lam_out
+        [B, D, n_v] and trace_out [k0, B] (contiguous device tensors) receive the state
+        and the probe's residual trace in place of the context's own buffers."""
         import torch
         s = self.solver
         B = xi.shape[0]
         D, nv = s.dims, s.nv
         st = torch.cuda.current_stream().cuda_stream
-        xp, lp, xw, lw = self.xp[:B], self.lp[:B], self.xw[:B], self.lw[:B]
-        tr = self.trace[:, :B]
+        xp, lp = self.xp[:B], self.lp[:B]
+        xw = self.xw[:B] if xb_out is None else xb_out
+        lw = self.lw[:B] if lam_out is None else lam_out
+        tr = self.trace[:, :B] if trace_out is None else trace_out
+        assert xw.is_contiguous() and lw.is_contiguous() and tr.is_contiguous()
         xp.copy_(xi)
         lp.zero_()
         s.project(xi, boundary, obs, xp, lp, self.k0, res_trace=tr)

@@ -247,7 +247,7 @@ def test_gpu_cem_fp64_matches_oracle_per_iteration():
     rec = []
     best = planner.run(torch.as_tensor(z, device="cuda"), w.boundary, obs, record=rec)
     torch.cuda.synchronize()
-    for l, (proj, elite, res, caug, rkey, mu, Sig, _) in enumerate(rec):
+    for l, (proj, elite, res, caug, rkey, mu, Sig, _, _) in enumerate(rec):
         assert np.array_equal(proj.cpu().numpy(), tr.proj_idx[l]), l
         assert np.array_equal(elite.cpu().numpy(), tr.elite_idx[l]), l
         np.testing.assert_allclose(res.cpu().numpy(), tr.res[l], atol=1e-9)
@@ -280,7 +280,7 @@ def test_gpu_cem_fp32_config4_graph_replays():
     eager = planner.run(z, w.boundary, obs, record=rec).clone()
     torch.cuda.synchronize()
     mu_prev, S_prev = mu0, S0
-    for proj, elite, res, caug, rkey, mu, Sig, xb in rec:
+    for proj, elite, res, caug, rkey, mu, Sig, xb, _ in rec:
         c, k = caug.cpu().numpy(), rkey.cpu().numpy()
         p = proj.cpu().numpy()
         e = elite.cpu().numpy()
@@ -309,3 +309,54 @@ def test_gpu_cem_fp32_config4_graph_replays():
         torch.cuda.synchronize()
         assert torch.equal(out, eager), rep
         assert np.array_equal(planner.mu.cpu().numpy(), eager_mu), rep
+
+
+@pytest.mark.gpu
+def test_gpu_cem_warm_start_composes_the_library_calls():
+    """The planner with the learned warm start: each projection is the warm context's
+    probe, jump and fallback followed by am_iters - k0 iterations; the first CEM
+    iteration's projected samples, multipliers and residual trace equal that sequence
+    run by hand on the same draws (same kernels, same order: bitwise), and the fallback
+    flags are 0 or TRAJAM_FLAG_COLD_FALLBACK."""
+    from paper_2408_10731_amd import cem, trajam as tj
+    from paper_2408_10731_amd import warmstart as ws
+    w = wl.config4(batch=4)
+    D, nv = w.dims, w.n_v
+    mu0 = wl.line_samples(np.random.default_rng(0), 1, w.degree, w.boundary[:, 0],
+                          w.boundary[:, 3], 0.0)[0].reshape(-1)
+    S0 = 0.25 * np.eye(D * nv)
+    L0 = np.linalg.cholesky(S0 + ocem.EPS_CHOL * np.eye(D * nv))
+    N, Nb, Np, Ne, K = 2, 512, 372, 93, 15
+    z = torch.as_tensor(np.random.default_rng(12).normal(size=(N, Nb, D * nv)), dtype=torch.float32,
+                        device="cuda")
+    print("case: cem warm start composition", flush=True)
+    w0 = dataclasses.replace(w, xi=np.zeros((Nb, D, nv)))
+    solver = tj.Solver.for_workload(w0, max_batch=Nb, precision="fp32")
+    _, obs = tj.device_workload(w0, solver.dtype, static=False)
+    net = ws.Net(ws.widths_for(w), seed=3, precision=1, max_batch=Nb)
+    ctx = ws.WarmContext(solver, net, Nb)
+    planner = cem.Planner(solver, Nb, Np, Ne, K, warm=ctx)
+    planner.set_distribution(mu0, S0, L0)
+    rec = []
+    planner.run(z, w.boundary, obs, record=rec)
+    torch.cuda.synchronize()
+    fl = planner.flags.cpu().numpy()
+    assert set(np.unique(fl)) <= {0, tj.FLAG_COLD_FALLBACK}
+    # by hand: the first iteration from the initial distribution
+    st = torch.cuda.current_stream().cuda_stream
+    mu = torch.as_tensor(mu0, dtype=torch.float32, device="cuda")
+    L = torch.as_tensor(L0, dtype=torch.float32, device="cuda")
+    xi = torch.zeros((Nb, D, nv), device="cuda")
+    xb, lam = torch.zeros_like(xi), torch.zeros_like(xi)
+    tj.trajam_cem_sample(solver.handle, Nb, mu.data_ptr(), L.data_ptr(), z[0].data_ptr(), xi.data_ptr(),
+                         xb.data_ptr(), lam.data_ptr(), st)
+    solver.set_obstacles(obs)
+    xw, lw, _, tr = ctx.run(xi, w.boundary, None)
+    trc = torch.zeros((K - ws.K0, Nb), device="cuda")
+    solver.project(xi, w.boundary, None, xw, lw, K - ws.K0, res_trace=trc)
+    torch.cuda.synchronize()
+    got_xb, got_tr = rec[0][7], rec[0][8]
+    assert torch.equal(got_xb, xw)
+    assert torch.equal(got_tr[:ws.K0], tr)
+    assert torch.equal(got_tr[ws.K0:], trc)
+    solver.close()
