@@ -349,6 +349,48 @@ def warm_cfg4_bench(args, tol=1e-3):
     out["planning_call"] = {"config": "30 CEM iterations x 2000 samples x 15 AM iterations, 100 moving "
                                       "circles, 1454 projected / 363 elite, fp32, same draws for both arms",
                             **calls}
+    return out, net
+
+
+def mpc_bench(args, net=None, tol=1e-3):
+    """Receding-horizon loop on the config-4 benchmark scene (100 moving circles):
+    1000 samples, 10 AM iterations a control cycle (the thesis's MPC budget), the time
+    origin moving 1 s a cycle, 20 cycles.  Three starts of a cycle: the multipliers
+    carried over from the preceding cycle (the thesis), cleared, and the learned warm
+    start (network of the config-4 leg).  Per arm: the batch-median residual after each
+    cycle, the cycles whose median reaches tol, and the wall time of a cycle (host
+    included: the executed state is read back every cycle)."""
+    import torch
+    from paper_2408_10731_amd import mpc
+    from paper_2408_10731_amd import trajam as tj
+    from paper_2408_10731_amd import warmstart as ws
+    from paper_2408_10731_amd import workloads as wl
+
+    w = wl.config4(batch=1000)
+    K, delta, n_cyc = 10, 1.0, args.mpc_cycles
+    arms = [("reuse_multipliers", True, False), ("clear_multipliers", False, False)]
+    if net is not None:
+        arms.append(("learned_warm_start", False, True))
+    out = {"config": f"config-4 scene, {w.batch} samples, {K} AM iterations a cycle, delta {delta} s, "
+                     f"{n_cyc} cycles, fp32", "tol": tol}
+    for name, keep, learned in arms:
+        s = tj.Solver.for_workload(w, precision="fp32")
+        xi0 = torch.as_tensor(w.xi, dtype=torch.float32, device="cuda")
+        ctx = ws.WarmContext(s, net, w.batch) if learned else None
+        m = mpc.MPC(s, xi0, w.boundary, (w.obs_centre, w.obs_vel, w.obs_axes), K, delta, keep_lambda=keep,
+                    warm=ctx)
+        med, wall = [], []
+        for _ in range(n_cyc):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = m.cycle()
+            torch.cuda.synchronize()
+            wall.append(time.perf_counter() - t0)
+            med.append(float(np.median(r["res"].cpu().numpy())))
+        out[name] = {"median_residual_per_cycle": med, "cycles_at_tol": int(sum(x <= tol for x in med)),
+                     "mean_median_residual": float(np.mean(med)),
+                     "ms_per_cycle": 1e3 * float(np.median(wall[1:] if len(wall) > 1 else wall))}
+        s.close()
     return out
 
 
@@ -991,6 +1033,7 @@ def main():
                     help="timed calls of the materialised polar variables; 0 skips that leg")
     ap.add_argument("--cem-only", action="store_true",
                     help="run only the sampling-loop leg and print its JSON (profiling)")
+    ap.add_argument("--mpc-cycles", type=int, default=20, help="control cycles of the MPC leg; 0 skips it")
     ap.add_argument("--ws4-scenes", type=int, default=8192,
                     help="config-4 training scenes of the warm start in the sampling loop; 0 skips that leg")
     ap.add_argument("--mfma-steps", type=int, default=10, help="timed calls of the matrix-core leg; 0 skips it")
@@ -1059,7 +1102,9 @@ def main():
     c2["solver"].close()
     ragged = ragged_bench(args) if args.ragged_problems > 0 else None
     cem_out = cem_bench(args) if args.cem_calls > 0 else None
-    warm4 = warm_cfg4_bench(args) if args.ws4_scenes > 0 and args.cem_calls > 0 and args.ttr_cap > 0 else None
+    warm4, net4 = ((warm_cfg4_bench(args) if args.ws4_scenes > 0 and args.cem_calls > 0 and args.ttr_cap > 0
+                    else (None, None)))
+    mpc_out = mpc_bench(args, net4) if args.mpc_cycles > 0 else None
     prec_out = precision_bench(args) if args.precision_steps > 0 else None
     polar_out = polar_bench(args) if args.polar_steps > 0 else None
     mfma_out = mfma_bench(args) if args.mfma_steps > 0 else None
@@ -1100,6 +1145,7 @@ def main():
         "polar_materialised": polar_out,
         "matrix_cores": mfma_out,
         "warm_start_config4": warm4,
+        "mpc": mpc_out,
         "wall_s_timed_region": h["wall"],
     }
     if not args.no_cpu:

@@ -359,6 +359,23 @@ trajam_status trajam_polar(trajam_solver *s, int32_t batch, const void *xi_bar, 
 trajam_status trajam_cem_sample(trajam_solver *s, int32_t n, const void *mu, const void *chol,
                                 const void *z, void *xi, void *xi_bar, void *lambda, void *stream);
 
+/* Receding-horizon control (thesis ch. 5, Paper II, Implementation Details: an MPC on
+ * the batch optimizer that starts every control cycle from the preceding cycle's
+ * solution, multipliers included).  Between two cycles the time origin moves on by
+ * delta seconds: every sample's coefficients xi_bar [batch][n_agents][D][n_v] (the
+ * layout of trajam_project) are re-expressed as the Bernstein coefficients of the same
+ * polynomials on the window [delta, delta + T] (T the horizon; delta < 0 or > T
+ * extrapolates), written to xi_next and xi_bar_next (the next cycle's samples and
+ * its starting iterate), and lambda_next = lambda if keep_lambda, else 0 (lambda may
+ * then be NULL).  Storage in the solver's state precision (double for FP64, else
+ * float); FP64 arithmetic.  Outputs may alias the inputs (each coefficient row is read
+ * whole before it is written).  The next cycle's boundary rows (the executed
+ * trajectory's state at delta) and obstacles are the caller's.  Errors: INVALID,
+ * CAPACITY (batch > max_batch), UNSUPPORTED (degree above 15), DEVICE. */
+trajam_status trajam_mpc_shift(trajam_solver *s, int32_t batch, double delta, int32_t keep_lambda,
+                               const void *xi_bar, const void *lambda, void *xi_next, void *xi_bar_next,
+                               void *lambda_next, void *stream);
+
 /* Augmented cost of Alg 3: c_aug[i] = sum_t |Pdd xb_i(t)|^2 + res[i], and the residual
  * key res_key[i] = floor(res[i] / quantum) (int32, clamped), the resolution at which
  * residuals are compared.  xi_bar [n][dims][degree+1], res [n] (from trajam_residuals),

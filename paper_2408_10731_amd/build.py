@@ -14,8 +14,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtrajam.so")
-SOURCES = ["am_kernels.hip", "polar_kernels.hip", "cem_kernels.hip", "mlp_kernels.hip", "trajam_api.cpp",
-           "mlp_api.cpp"]
+SOURCES = ["am_kernels.hip", "polar_kernels.hip", "cem_kernels.hip", "mlp_kernels.hip", "mpc_kernels.hip",
+           "trajam_api.cpp", "mlp_api.cpp"]
 ARCH = os.environ.get("TRAJAM_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -129,6 +129,16 @@ hipError_t launch_cem_update(bool f64, int n_elite, int dim, const int32_t *elit
                              const void *caug, double sigma, double gamma, double eps, void *mu,
                              void *Sigma, void *L, hipStream_t st);
 
+// Receding-horizon window shift (mpc_kernels.hip): S[j][m] row-major, padded to
+// kShiftMaxCoeffs; passed by value.
+constexpr int kShiftMaxCoeffs = 16;
+struct ShiftMatrix {
+    double s[kShiftMaxCoeffs * kShiftMaxCoeffs];
+    int nv;
+};
+hipError_t launch_mpc_shift(bool fp64, int rows, const ShiftMatrix &S, const void *xb, const void *lam,
+                            void *xi_next, void *xb_next, void *lam_next, int keep_lambda, hipStream_t st);
+
 // Warm-start network kernels (mlp_kernels.hip).
 // Split of a product over K: the number of slices (1 = no split) whose partial products
 // fit in `space` floats (M N each, plus M row sums in bf16 mode), and the K range of

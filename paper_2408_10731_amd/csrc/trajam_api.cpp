@@ -1008,6 +1008,52 @@ extern "C" trajam_status trajam_polar(trajam_solver *s, int32_t batch, const voi
 
 // ---- sampling loop ------------------------------------------------------------
 
+namespace {
+
+// Bernstein coefficients of the window [d, 1 + d] (in units of the horizon) from those
+// of [0, 1]: the blossom of the polynomial at n - j arguments d and j arguments 1 + d,
+// evaluated by de Casteljau steps; row j of S, column k, from the unit control
+// polygon e_k.
+void shift_blossom(int n, double d, double *S /* [kShiftMaxCoeffs][kShiftMaxCoeffs] */)
+{
+    double pts[trajam::kShiftMaxCoeffs];
+    for (int i = 0; i < trajam::kShiftMaxCoeffs * trajam::kShiftMaxCoeffs; ++i) S[i] = 0.0;
+    for (int k = 0; k <= n; ++k)
+        for (int j = 0; j <= n; ++j) {
+            for (int i = 0; i <= n; ++i) pts[i] = i == k ? 1.0 : 0.0;
+            for (int r = 1; r <= n; ++r) {
+                const double t = r <= n - j ? d : 1.0 + d;
+                for (int i = 0; i <= n - r; ++i) pts[i] = (1.0 - t) * pts[i] + t * pts[i + 1];
+            }
+            S[j * trajam::kShiftMaxCoeffs + k] = pts[0];
+        }
+}
+
+}  // namespace
+
+extern "C" trajam_status trajam_mpc_shift(trajam_solver *s, int32_t batch, double delta, int32_t keep_lambda,
+                                          const void *xi_bar, const void *lambda, void *xi_next,
+                                          void *xi_bar_next, void *lambda_next, void *stream)
+{
+    if (!s) return TRAJAM_ERR_INVALID;
+    s->err.clear();
+    if (batch < 0 || !std::isfinite(delta) || (keep_lambda != 0 && keep_lambda != 1))
+        return fail(s, TRAJAM_ERR_INVALID, "batch >= 0, finite delta, keep_lambda 0 or 1 required");
+    if (batch > s->prob.max_batch) return fail(s, TRAJAM_ERR_CAPACITY, "batch > max_batch");
+    if (batch == 0) return TRAJAM_OK;
+    if (!xi_bar || !xi_next || !xi_bar_next || !lambda_next || (keep_lambda && !lambda))
+        return fail(s, TRAJAM_ERR_INVALID, "NULL pointer");
+    if (s->nv > trajam::kShiftMaxCoeffs) return fail(s, TRAJAM_ERR_UNSUPPORTED, "degree above 15");
+    trajam::ShiftMatrix S;
+    S.nv = s->nv;
+    shift_blossom(s->prob.degree, delta / s->prob.horizon, S.s);
+    const int rows = batch * s->prob.n_agents * s->prob.dims;
+    hipError_t e = trajam::launch_mpc_shift(s->prob.precision == TRAJAM_FP64, rows, S, xi_bar, lambda, xi_next,
+                                            xi_bar_next, lambda_next, keep_lambda, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(s, TRAJAM_ERR_DEVICE, std::string("mpc shift: ") + hipGetErrorString(e));
+    return TRAJAM_OK;
+}
+
 extern "C" trajam_status trajam_cem_sample(trajam_solver *s, int32_t n, const void *mu, const void *chol,
                                            const void *z, void *xi, void *xi_bar, void *lambda, void *stream)
 {

@@ -47,7 +47,7 @@ EXPORTS = [
     "trajam_fixed_matrices", "trajam_set_launch", "trajam_get_launch",
     "trajam_boundary_coefficients", "trajam_cem_sample", "trajam_cem_cost",
     "trajam_cem_select", "trajam_cem_update", "trajam_mlp_param_count", "trajam_mlp_forward",
-    "trajam_mlp_backward", "trajam_mlp_backward_noalloc", "trajam_mlp_infer", "trajam_mlp_pack_infer", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
+    "trajam_mpc_shift", "trajam_mlp_backward", "trajam_mlp_backward_noalloc", "trajam_mlp_infer", "trajam_mlp_pack_infer", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
     "trajam_warm_apply", "trajam_warm_fallback", "trajam_warm_pack_mfma", "trajam_warm_jump", "trajam_set_obstacles", "trajam_autotune",
     "trajam_ragged_plan_create", "trajam_ragged_launch", "trajam_ragged_plan_destroy", "trajam_polar",
     "trajam_qp_contraction", "trajam_set_continuation", "trajam_project_continuation",
@@ -160,6 +160,8 @@ def load():
     L.trajam_boundary_coefficients.restype = ctypes.c_int
     L.trajam_cem_sample.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
     L.trajam_cem_sample.restype = ctypes.c_int
+    L.trajam_mpc_shift.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, vp, vp, vp, vp, vp, vp]
+    L.trajam_mpc_shift.restype = ctypes.c_int
     L.trajam_cem_cost.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_double, vp, vp, vp]
     L.trajam_cem_cost.restype = ctypes.c_int
     L.trajam_cem_select.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32,
@@ -315,6 +317,12 @@ def trajam_boundary_coefficients(problem: Problem, b4) -> np.ndarray:
     out = np.zeros(4)
     _check(load().trajam_boundary_coefficients(ctypes.byref(problem), _dp(b), _dp(out)))
     return out
+
+
+def trajam_mpc_shift(handle, batch, delta, keep_lambda, xi_bar, lam, xi_next, xi_bar_next, lam_next,
+                     stream) -> None:
+    _check(load().trajam_mpc_shift(handle, int(batch), float(delta), int(bool(keep_lambda)), xi_bar, lam,
+                                   xi_next, xi_bar_next, lam_next, stream), handle)
 
 
 def trajam_cem_sample(handle, n, mu, chol, z, xi, xi_bar, lam, stream) -> None:
