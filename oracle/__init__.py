@@ -33,6 +33,9 @@ class Problem(ctypes.Structure):
         ("a_max", ctypes.c_double),
         ("rho", ctypes.c_double),
         ("n_obs", ctypes.c_int),
+        ("workspace", ctypes.c_int),
+        ("ws_lo", ctypes.c_double * 3),
+        ("ws_hi", ctypes.c_double * 3),
     ]
 
 
@@ -113,15 +116,22 @@ def _f64(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
-def problem(dims, degree, n_steps, horizon, v_max, a_max, rho, n_obs) -> Problem:
-    return Problem(int(dims), int(degree), int(n_steps), float(horizon), float(v_max),
-                   float(a_max), float(rho), int(n_obs))
+def problem(dims, degree, n_steps, horizon, v_max, a_max, rho, n_obs, workspace=None) -> Problem:
+    """workspace: None, or (lo [D], hi [D]) bounds on every position coordinate."""
+    pr = Problem(int(dims), int(degree), int(n_steps), float(horizon), float(v_max),
+                 float(a_max), float(rho), int(n_obs))
+    if workspace is not None:
+        lo, hi = (np.asarray(x, dtype=np.float64) for x in workspace)
+        pr.workspace = 1
+        for ax in range(int(dims)):
+            pr.ws_lo[ax], pr.ws_hi[ax] = float(lo[ax]), float(hi[ax])
+    return pr
 
 
 def problem_of(w) -> Problem:
     """Problem struct from a workload object (duck-typed: any object with the fields)."""
     return problem(w.dims, w.degree, w.n_steps, w.horizon, w.v_max, w.a_max, w.rho,
-                   w.obs_centre.shape[0])
+                   w.obs_centre.shape[0], getattr(w, "workspace", None))
 
 
 def set_fault(code: int) -> None:

@@ -58,6 +58,9 @@ typedef struct {
     double a_max;      /* <= 0 removes the acceleration block from F */
     double rho;        /* penalty weight of the augmented Lagrangian */
     int n_obs;         /* n_o obstacles (each contributes one copy of P to F) */
+    int workspace;     /* 1: workspace bounds G xb <= tau, G = [-P; P], tau = [-ws_lo; ws_hi]
+                          per axis (Paper III eq bound_con), through a slack variable */
+    double ws_lo[3], ws_hi[3];
 } orc_problem;
 
 /* Deliberate-mistake switch used only by the mutation tests: each code plants
@@ -126,6 +129,8 @@ int orc_constraint_matrices(const orc_problem *pr, double *A, double *H)
             double ff = 0.0;
             for (k = 0; k < np; ++k) {
                 ff += (double)pr->n_obs * P[k * nv + i] * P[k * nv + j];
+                /* the rows G = [-P; P] of the workspace bounds: G^T G = 2 P^T P */
+                if (pr->workspace) ff += 2.0 * P[k * nv + i] * P[k * nv + j];
                 if (pr->v_max > 0.0) ff += Pd[k * nv + i] * Pd[k * nv + j];
                 if (pr->a_max > 0.0) ff += Pdd[k * nv + i] * Pdd[k * nv + j];
             }
@@ -370,18 +375,37 @@ static void polar_and_residual(const orc_ctx *c, const double *xb, double *FtE,
                 if (fabs(ra[ax]) > mx) mx = fabs(ra[ax]);
             }
         }
+        /* workspace bounds (Paper III, eq bound_con and the slack step of its AM list):
+         * per axis the row values g = G xb are (-p, p) with bounds tau = (-lo, hi); the
+         * slack s = max(0, -g + tau) makes e_G = tau - s and the residual r_G = g - e_G.
+         * F^T e gains G^T e_G = P^T (e_hi - e_lo); F^T r gains P^T (r_hi - r_lo). */
+        double ew[3] = {0, 0, 0}, rw[3] = {0, 0, 0};
+        if (pr->workspace)
+            for (ax = 0; ax < D; ++ax) {
+                double g_lo = -p[ax], t_lo = -pr->ws_lo[ax];
+                double g_hi = p[ax], t_hi = pr->ws_hi[ax];
+                double s_lo = fmax(0.0, -g_lo + t_lo), s_hi = fmax(0.0, -g_hi + t_hi);
+                if (g_fault == 10) s_lo = fmax(0.0, g_lo - t_lo);   /* planted: slack sign */
+                double e_lo = t_lo - s_lo, e_hi = t_hi - s_hi;
+                double r_lo = g_lo - e_lo, r_hi = g_hi - e_hi;
+                ew[ax] = e_hi - e_lo;
+                rw[ax] = r_hi - r_lo;
+                acc += r_lo * r_lo + r_hi * r_hi;
+                if (fabs(r_lo) > mx) mx = fabs(r_lo);
+                if (fabs(r_hi) > mx) mx = fabs(r_hi);
+            }
         for (ax = 0; ax < D; ++ax)
             for (m = 0; m < nv; ++m) {
                 /* F^T stacks P^T once per obstacle, then Pd^T and Pdd^T */
                 double pm = c->P[t * nv + m];
                 if (g_fault == 3) pm = c->P[t * nv + (nv - 1 - m)]; /* planted: column order */
                 if (FtE) {
-                    FtE[ax * nv + m] += pm * eo[ax];
+                    FtE[ax * nv + m] += pm * eo[ax] + c->P[t * nv + m] * ew[ax];
                     if (g_fault != 2) FtE[ax * nv + m] += c->Pd[t * nv + m] * ev[ax];
                     FtE[ax * nv + m] += c->Pdd[t * nv + m] * ea[ax];
                 }
                 if (FtR)
-                    FtR[ax * nv + m] += pm * ro[ax] + c->Pd[t * nv + m] * rv[ax] +
+                    FtR[ax * nv + m] += pm * ro[ax] + c->P[t * nv + m] * rw[ax] + c->Pd[t * nv + m] * rv[ax] +
                                         c->Pdd[t * nv + m] * ra[ax];
             }
     }

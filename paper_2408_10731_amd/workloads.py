@@ -50,6 +50,7 @@ class Workload:
     precision: str = "fp64"
     n_agents: int = 1
     agent_radius: float = 0.0
+    workspace: Optional[np.ndarray] = None  # [2, D] (lo, hi) bounds on every position, or None
 
     @property
     def n_v(self) -> int:
