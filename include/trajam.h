@@ -98,6 +98,13 @@ typedef struct {
     int32_t max_batch;     /* largest batch a call may pass (>= 1) */
     int32_t precision;     /* a trajam_precision value */
     int32_t obstacle_model; /* a trajam_obstacle_model value */
+    /* Workspace bounds (Paper III, eq bound_con): 1 adds the rows G = [-P; P] per axis,
+     * lo[ax] <= p_ax(t) <= hi[ax] at every time sample, handled by the slack step
+     * s = max(0, -G xb + tau) of the AM iteration (each row's residual is its
+     * violation) and 2 rho P^T P in the fixed matrix; 0: none (lo, hi unused).  The
+     * materialized polar variables of trajam_polar do not cover these rows. */
+    int32_t workspace;
+    double ws_lo[3], ws_hi[3];   /* per axis, lo <= hi, finite; entries past dims unused */
 } trajam_problem;
 
 typedef struct trajam_solver trajam_solver; /* opaque; owns device constants */

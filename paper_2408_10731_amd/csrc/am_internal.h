@@ -58,6 +58,9 @@ struct AmArgs {
     const T *cont_rho;      // [levels]
     const T *cont_W;        // [levels][NVP][NVP]
     void *cont_state;       // [batch] ContState, in/out
+    // Workspace bounds (rows G = [-P; P]): use_ws = 0 when the problem has none.
+    int use_ws;
+    T ws_lo[3], ws_hi[3];
 };
 
 // Per-sample state of the penalty continuation (the C ABI's trajam_cont_state).

@@ -964,6 +964,24 @@ __device__ __forceinline__ void bound_residual(const T (&v)[D], T bound, T (&r)[
     }
 }
 
+// Workspace rows G = [-P; P] (Paper III, eq bound_con, and the slack step of its AM
+// list): with the slack s = max(0, -G xb + tau) the residual of the row p <= hi is
+// max(0, p - hi) and that of -p <= -lo is max(0, lo - p); G^T r adds their difference,
+// p - clamp(p, lo, hi), to the position rows R, and their squares to r2.
+// (BND: the bound arrays of the launch arguments, in whichever address space they sit)
+template <typename T, int D, typename BND>
+__device__ __forceinline__ void workspace_residual(const T (&p)[D], const BND &lo, const BND &hi, T (&R)[D], T &r2,
+                                                   T &rmax)
+{
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        const T r = p[ax] - fmin(fmax(p[ax], (T)lo[ax]), (T)hi[ax]);
+        R[ax] += r;
+        r2 = fma(r, r, r2);
+        rmax = fmax(rmax, fabs(r));
+    }
+}
+
 // ---- bf16 matrix-core QP step (TRAJAM_BF16_REFINE) ----------------------------
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -1136,6 +1154,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_project_kernel(AmArgs<T> a)
         if (valid) {
             if (a.use_v) bound_residual<T, D>(v, a.vmax, rv, r2, rmax);
             if (a.use_a) bound_residual<T, D>(acc, a.amax, ra, r2, rmax);
+            if (a.use_ws) workspace_residual(p, a.ws_lo, a.ws_hi, R, r2, rmax);
         }
         // ---- F^T r: each lane's rows times its residuals, reduced over the wave
         // each residual group (obstacle, velocity, acceleration) enters only when some
@@ -1411,6 +1430,7 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
         for (int i = 0; i < TPL; ++i) {
             if (a.use_v) bound_residual<T, D>(v[i], a.vmax, rv[i], r2, rmax);
             if (a.use_a) bound_residual<T, D>(acc[i], a.amax, ra[i], r2, rmax);
+            if (a.use_ws && valid[i]) workspace_residual(p[i], a.ws_lo, a.ws_hi, R[i], r2, rmax);
         }
         // ---- F^T r over the wave
         // residual groups enter only when some lane has them non-zero (exact zeros skipped)
@@ -1647,6 +1667,7 @@ __device__ __forceinline__ void agents_rows(const A &a, const T *ol, T *px, int 
     if (active) {
         if (a.use_v) bound_residual<T, D>(v, a.vmax, rv, r2, rmax);
         if (a.use_a) bound_residual<T, D>(acc, a.amax, ra, r2, rmax);
+        if (a.use_ws) workspace_residual(p, a.ws_lo, a.ws_hi, S, r2, rmax);
     }
     // Pair rows, each unordered pair evaluated once: at offset o = 1 .. N/2 lane a takes
     // partner b = (a + o) mod N, so every lane does about N/2 clearance tests instead
@@ -2059,6 +2080,7 @@ __global__ __launch_bounds__(kMaxThreads) void am_residual_kernel(AmArgs<T> a)
     if (valid) {
         if (a.use_v) bound_residual<T, D>(v, a.vmax, rv, r2, rmax);
         if (a.use_a) bound_residual<T, D>(acc, a.amax, ra, r2, rmax);
+        if (a.use_ws) workspace_residual(p, a.ws_lo, a.ws_hi, R, r2, rmax);
     }
     const T s = wave_sum(r2);
     const T mx = wave_max(rmax);

@@ -118,6 +118,13 @@ trajam_status validate(const trajam_problem *p, std::string &why)
         why = "unknown obstacle model";
         return TRAJAM_ERR_INVALID;
     }
+    if (p->workspace != 0 && p->workspace != 1) { why = "workspace must be 0 or 1"; return TRAJAM_ERR_INVALID; }
+    if (p->workspace)
+        for (int ax = 0; ax < p->dims; ++ax)
+            if (!std::isfinite(p->ws_lo[ax]) || !std::isfinite(p->ws_hi[ax]) || !(p->ws_lo[ax] <= p->ws_hi[ax])) {
+                why = "workspace bounds must be finite with lo <= hi";
+                return TRAJAM_ERR_INVALID;
+            }
     if (p->n_agents < 1 || p->n_agents > 64) { why = "n_agents must be in [1, 64]"; return TRAJAM_ERR_INVALID; }
     if (p->n_agents > 1) {
         if (!(p->agent_radius > 0.0) || !std::isfinite(p->agent_radius)) {
@@ -269,7 +276,8 @@ trajam_status precompute(const trajam_problem &pr, std::vector<double> &P, std::
             double ff = 0.0;
             for (int k = 0; k < np; ++k) {
                 const size_t ri = (size_t)k * nv;
-                ff += p->n_obstacles * P[ri + i] * P[ri + j];
+                // every obstacle adds a copy of P to F; the workspace rows G = [-P; P] two
+                ff += (p->n_obstacles + (p->workspace ? 2 : 0)) * P[ri + i] * P[ri + j];
                 if (p->v_max > 0.0) ff += Pd[ri + i] * Pd[ri + j];
                 if (p->a_max > 0.0) ff += Pdd[ri + i] * Pdd[ri + j];
             }
@@ -644,6 +652,11 @@ void fill_args(const trajam_solver *s, AmArgs<T> &a, int batch, int iters)
     a.pair_r = (T)(2.0 * p.agent_radius);
     a.W2 = (const T *)s->d_W2;
     a.xiB_ag = (const T *)s->d_xiBag;
+    a.use_ws = p.workspace;
+    for (int ax = 0; ax < 3; ++ax) {
+        a.ws_lo[ax] = (T)(ax < p.dims ? p.ws_lo[ax] : 0.0);
+        a.ws_hi[ax] = (T)(ax < p.dims ? p.ws_hi[ax] : 0.0);
+    }
 }
 
 // Samples per workgroup of the single-robot residual kernel (roundup64(n_steps)

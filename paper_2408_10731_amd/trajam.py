@@ -76,6 +76,9 @@ class Problem(ctypes.Structure):
         ("max_batch", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("obstacle_model", ctypes.c_int32),
+        ("workspace", ctypes.c_int32),
+        ("ws_lo", ctypes.c_double * 3),
+        ("ws_hi", ctypes.c_double * 3),
     ]
 
 
@@ -448,11 +451,18 @@ def trajam_ragged_plan_destroy(plan) -> None:
 
 def make_problem(dims, degree, n_steps, horizon, v_max, a_max, rho, n_obstacles,
                  max_batch, precision="fp64", sphere=True, n_agents=1,
-                 agent_radius=0.0) -> Problem:
-    return Problem(int(dims), int(degree), int(n_steps), float(horizon), float(v_max),
-                   float(a_max), float(rho), int(n_obstacles), int(n_agents),
-                   float(agent_radius), int(max_batch), PRECISIONS.get(precision, precision),
-                   TRAJAM_SPHERE if sphere else TRAJAM_ELLIPSOID)
+                 agent_radius=0.0, workspace=None) -> Problem:
+    """workspace: None, or (lo [D], hi [D]) bounds on every position coordinate."""
+    pr = Problem(int(dims), int(degree), int(n_steps), float(horizon), float(v_max),
+                 float(a_max), float(rho), int(n_obstacles), int(n_agents),
+                 float(agent_radius), int(max_batch), PRECISIONS.get(precision, precision),
+                 TRAJAM_SPHERE if sphere else TRAJAM_ELLIPSOID)
+    if workspace is not None:
+        lo, hi = (np.asarray(x, dtype=np.float64) for x in workspace)
+        pr.workspace = 1
+        for ax in range(int(dims)):
+            pr.ws_lo[ax], pr.ws_hi[ax] = float(lo[ax]), float(hi[ax])
+    return pr
 
 
 class Solver:
@@ -479,7 +489,8 @@ class Solver:
             sphere = bool(np.all(w.obs_axes == w.obs_axes[:, :1]))
         return cls(make_problem(w.dims, w.degree, w.n_steps, w.horizon, w.v_max, w.a_max,
                                 w.rho, w.n_obs, max_batch or w.batch, prec, sphere,
-                                n_agents=w.n_agents, agent_radius=w.agent_radius))
+                                n_agents=w.n_agents, agent_radius=w.agent_radius,
+                                workspace=getattr(w, "workspace", None)))
 
     def close(self):
         if getattr(self, "handle", None):
