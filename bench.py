@@ -1096,6 +1096,15 @@ def main():
                         f"100 steps over 30 s, batch {w2.batch}, {K} AM iterations, cold start, fp32",
             "value": c2["value"], "ms_per_step": c2["ms_per_step"], "roofline": c2["roofline"]}
 
+    # config 2 inside the workspace band |y - 15| <= 1.2 (rows G = [-P; P] with slack)
+    import dataclasses
+    w2b = dataclasses.replace(w2, workspace=np.array(((-1.0, 13.8), (31.0, 16.2))))
+    c2b = projection_leg(w2b, K, args.steps, args.warmup)
+    c2b["solver"].close()
+    cfg2["workspace_band"] = {"workload": "config 2 with workspace bounds x in [-1, 31], y in [13.8, 16.2]",
+                              "value": c2b["value"], "ms_per_step": c2b["ms_per_step"],
+                              "launch_ms": c2b["launch_ms"]}
+
     ttr = (time_to_residual(args, w2, c2["solver"], c2["xi"], c2["obs"], torch.cuda.current_stream())
            if args.ttr_cap > 0 else None)
     cont = continuation_leg(w2, args.ttr_cap, torch.cuda.current_stream()) if args.ttr_cap > 0 else None
