@@ -315,8 +315,7 @@ def warm_cfg4_bench(args, tol=1e-3):
                           w.boundary[:, 3], 0.0)[0].reshape(-1)
     S0 = 0.25 * np.eye(D * nv)
     L0 = np.linalg.cholesky(S0 + 1e-10 * np.eye(D * nv))
-    z = torch.as_tensor(np.random.default_rng(1).normal(size=(N, Nb, D * nv)), dtype=torch.float32,
-                        device="cuda")
+    z = cem.draw(N, Nb, D * nv, key=1)
     calls = {}
     for arm in ("cold", "warm"):
         solver = tj.Solver.for_workload(w, precision="fp32", max_batch=Nb)
@@ -637,8 +636,7 @@ def cem_bench(args):
                           w.boundary[:, 3], 0.0)[0].reshape(-1)
     S0 = 0.25 * np.eye(D * nv)
     L0 = np.linalg.cholesky(S0 + 1e-10 * np.eye(D * nv))
-    z = torch.as_tensor(np.random.default_rng(1).normal(size=(N, Nb, D * nv)),
-                        dtype=torch.float32, device="cuda")
+    z = cem.draw(N, Nb, D * nv, key=1)   # the library's counter-based generator
     planner.set_distribution(mu0, S0, L0)
     shape = planner.autotune(z[0], w.boundary, obs)
     planner.set_distribution(mu0, S0, L0)
@@ -651,7 +649,8 @@ def cem_bench(args):
 
     ms = _time(call, args.cem_calls, stream)
     out = {"config": "30 CEM iterations x 2000 samples x 15 AM iterations, 100 moving "
-                     "circles, 1454 projected / 363 elite, fp32, one graph replay per call",
+                     "circles, 1454 projected / 363 elite, fp32, one graph replay per call; draws from "
+                     "the library's Philox4x64-10 stream (key 1)",
            "ms_per_planning_call": ms, "traj_iters_per_s": N * Nb * K / (ms * 1e-3),
            "launch_shape": list(shape)}
     solver.close()

@@ -383,6 +383,19 @@ trajam_status trajam_mpc_shift(trajam_solver *s, int32_t batch, double delta, in
                                const void *xi_bar, const void *lambda, void *xi_next, void *xi_bar_next,
                                void *lambda_next, void *stream);
 
+/* The sampling loop's standard normal draws from an in-library counter-based
+ * generator (thesis ch. 6, Alg 3 draws N_b samples per iteration): z[i], i < count, of
+ * the stream (key, counter).  Block b = i / 4 is Philox4x64 with 10 rounds (Salmon,
+ * Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC 2011) of the
+ * 256-bit counter (counter + b mod 2^64, 0, 0, 0) under the 128-bit key (key, 0); its
+ * words x_0..x_3 give the uniforms u_j = (floor(x_j / 2^11) + 1/2) 2^-53 and the
+ * normals sqrt(-2 ln u_0) (cos, sin)(2 pi u_1), sqrt(-2 ln u_2) (cos, sin)(2 pi u_3)
+ * (Box-Muller), in FP64 arithmetic, stored as double (fp64 = 1) or float (0).  The
+ * draws of CEM iteration l with N_b samples of dimension D n_v are z[l N_b D n_v + ...]
+ * of one stream, so a run is reproduced by (key, counter).  No solver needed; errors
+ * through trajam_last_error(NULL): INVALID, DEVICE. */
+trajam_status trajam_normals(int64_t count, uint64_t key, uint64_t counter, int32_t fp64, void *z, void *stream);
+
 /* Augmented cost of Alg 3: c_aug[i] = sum_t |Pdd xb_i(t)|^2 + res[i], and the residual
  * key res_key[i] = floor(res[i] / quantum) (int32, clamped), the resolution at which
  * residuals are compared.  xi_bar [n][dims][degree+1], res [n] (from trajam_residuals),

@@ -14,6 +14,16 @@ import numpy as np
 from . import trajam as tj
 
 
+def draw(n_iterations: int, n_samples: int, dim: int, key: int, counter: int = 0, fp64: bool = False):
+    """The loop's standard normal draws z [n_iterations, n_samples, dim] from the
+    library's counter-based generator (one stream, iteration after iteration)."""
+    import torch
+    z = torch.empty((n_iterations, n_samples, dim), dtype=torch.float64 if fp64 else torch.float32,
+                    device="cuda")
+    tj.trajam_normals(z.numel(), key, counter, fp64, z.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    return z
+
+
 class Planner:
     """warm: a warmstart.WarmContext of the same solver (max batch >= n_samples).  With
     it every projection starts from the learned warm start -- its probe's k0 cold

@@ -142,6 +142,9 @@ struct ShiftMatrix {
 hipError_t launch_mpc_shift(bool fp64, int rows, const ShiftMatrix &S, const void *xb, const void *lam,
                             void *xi_next, void *xb_next, void *lam_next, int keep_lambda, hipStream_t st);
 
+// Counter-based standard normals (cem_kernels.hip): Philox4x64-10 and Box-Muller.
+hipError_t launch_normals(bool f64, long count, uint64_t key, uint64_t counter, void *z, hipStream_t st);
+
 // Warm-start network kernels (mlp_kernels.hip).
 // Split of a product over K: the number of slices (1 = no split) whose partial products
 // fit in `space` floats (M N each, plus M row sums in bf16 mode), and the K range of

@@ -415,7 +415,62 @@ hipError_t update_t(int n_elite, int dim, const int32_t *elite, const void *xb, 
     return update_launch<T, 48, 5>(n_elite, dim, elite, xb, caug, sigma, gamma, eps, mu, Sigma, L, st);
 }
 
+// ---- counter-based draws (Philox4x64-10, Salmon et al. SC 2011; Box-Muller) ----
+// Block b of the stream (key, counter): the 256-bit counter (counter + b mod 2^64, 0, 0,
+// 0) under the key (key, 0), ten rounds; its four words give uniforms
+// (floor(x / 2^11) + 1/2) 2^-53 and, in pairs, four standard normals (FP64 arithmetic,
+// stored in the output's precision).
+constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull, kPhiloxM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull, kPhiloxW1 = 0xBB67AE8584CAA73Bull;
+
+template <typename T>
+__global__ __launch_bounds__(256) void normals_kernel(long count, uint64_t key, uint64_t counter, T *__restrict__ z)
+{
+    const long b = (long)blockIdx.x * 256 + threadIdx.x;
+    if (4 * b >= count) return;
+    uint64_t c0 = counter + (uint64_t)b, c1 = 0, c2 = 0, c3 = 0, k0 = key, k1 = 0;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += kPhiloxW0;
+            k1 += kPhiloxW1;
+        }
+        const uint64_t hi0 = __umul64hi(kPhiloxM0, c0), lo0 = kPhiloxM0 * c0;
+        const uint64_t hi1 = __umul64hi(kPhiloxM1, c2), lo1 = kPhiloxM1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    const uint64_t w[4] = {c0, c1, c2, c3};
+    double zz[4];
+#pragma unroll
+    for (int j = 0; j < 4; j += 2) {
+        const double u0 = ((double)(w[j] >> 11) + 0.5) * 0x1p-53;
+        const double u1 = ((double)(w[j + 1] >> 11) + 0.5) * 0x1p-53;
+        const double r = sqrt(-2.0 * log(u0));
+        double sn, cs;
+        sincos(2.0 * M_PI * u1, &sn, &cs);
+        zz[j] = r * cs;
+        zz[j + 1] = r * sn;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (4 * b + j < count) z[4 * b + j] = (T)zz[j];
+}
+
 }  // namespace
+
+hipError_t launch_normals(bool f64, long count, uint64_t key, uint64_t counter, void *z, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const long blocks = (count + 3) / 4;
+    const dim3 grid((unsigned)((blocks + 255) / 256));
+    if (f64) hipLaunchKernelGGL(normals_kernel<double>, grid, dim3(256), 0, st, count, key, counter, (double *)z);
+    else hipLaunchKernelGGL(normals_kernel<float>, grid, dim3(256), 0, st, count, key, counter, (float *)z);
+    return hipGetLastError();
+}
 
 hipError_t launch_cem_sample(bool f64, int n, int dim, const void *mu, const void *L, const void *z,
                              void *xi, void *xb, void *lam, hipStream_t st)

@@ -1067,6 +1067,26 @@ extern "C" trajam_status trajam_mpc_shift(trajam_solver *s, int32_t batch, doubl
     return TRAJAM_OK;
 }
 
+extern "C" trajam_status trajam_normals(int64_t count, uint64_t key, uint64_t counter, int32_t fp64, void *z,
+                                        void *stream)
+{
+    if (count < 0 || (fp64 != 0 && fp64 != 1)) {
+        trajam::set_thread_error("count >= 0 and fp64 0 or 1 required");
+        return TRAJAM_ERR_INVALID;
+    }
+    if (count == 0) return TRAJAM_OK;
+    if (!z) {
+        trajam::set_thread_error("NULL output");
+        return TRAJAM_ERR_INVALID;
+    }
+    hipError_t e = trajam::launch_normals(fp64 == 1, count, key, counter, z, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        trajam::set_thread_error(std::string("normals: ") + hipGetErrorString(e));
+        return TRAJAM_ERR_DEVICE;
+    }
+    return TRAJAM_OK;
+}
+
 extern "C" trajam_status trajam_cem_sample(trajam_solver *s, int32_t n, const void *mu, const void *chol,
                                            const void *z, void *xi, void *xi_bar, void *lambda, void *stream)
 {

@@ -47,7 +47,7 @@ EXPORTS = [
     "trajam_fixed_matrices", "trajam_set_launch", "trajam_get_launch",
     "trajam_boundary_coefficients", "trajam_cem_sample", "trajam_cem_cost",
     "trajam_cem_select", "trajam_cem_update", "trajam_mlp_param_count", "trajam_mlp_forward",
-    "trajam_mpc_shift", "trajam_mlp_backward", "trajam_mlp_backward_noalloc", "trajam_mlp_infer", "trajam_mlp_pack_infer", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
+    "trajam_mpc_shift", "trajam_normals", "trajam_mlp_backward", "trajam_mlp_backward_noalloc", "trajam_mlp_infer", "trajam_mlp_pack_infer", "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features",
     "trajam_warm_apply", "trajam_warm_fallback", "trajam_warm_pack_mfma", "trajam_warm_jump", "trajam_set_obstacles", "trajam_autotune",
     "trajam_ragged_plan_create", "trajam_ragged_launch", "trajam_ragged_plan_destroy", "trajam_polar",
     "trajam_qp_contraction", "trajam_set_continuation", "trajam_project_continuation",
@@ -165,6 +165,8 @@ def load():
     L.trajam_cem_sample.restype = ctypes.c_int
     L.trajam_mpc_shift.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, vp, vp, vp, vp, vp, vp]
     L.trajam_mpc_shift.restype = ctypes.c_int
+    L.trajam_normals.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32, vp, vp]
+    L.trajam_normals.restype = ctypes.c_int
     L.trajam_cem_cost.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_double, vp, vp, vp]
     L.trajam_cem_cost.restype = ctypes.c_int
     L.trajam_cem_select.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, ctypes.c_int32,
@@ -326,6 +328,11 @@ def trajam_mpc_shift(handle, batch, delta, keep_lambda, xi_bar, lam, xi_next, xi
                      stream) -> None:
     _check(load().trajam_mpc_shift(handle, int(batch), float(delta), int(bool(keep_lambda)), xi_bar, lam,
                                    xi_next, xi_bar_next, lam_next, stream), handle)
+
+
+def trajam_normals(count, key, counter, fp64, z, stream) -> None:
+    _check(load().trajam_normals(int(count), int(key) & (2 ** 64 - 1), int(counter) & (2 ** 64 - 1),
+                                 int(bool(fp64)), z, stream))
 
 
 def trajam_cem_sample(handle, n, mu, chol, z, xi, xi_bar, lam, stream) -> None:

@@ -360,3 +360,29 @@ def test_gpu_cem_warm_start_composes_the_library_calls():
     assert torch.equal(got_tr[:ws.K0], tr)
     assert torch.equal(got_tr[ws.K0:], trc)
     solver.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("fp64", [True, False])
+def test_gpu_normals_match_the_oracle_generator(fp64):
+    """The library's counter-based draws against the oracle's generator written from
+    the same published definition: FP64 within 1e-13 relative (the device's log and
+    sincos against numpy's), FP32 the float rounding of the same values; a ragged count
+    and counters near the 64-bit wrap."""
+    from oracle import rng as orng
+    from paper_2408_10731_amd import cem, trajam as tj
+    print("case: normals", fp64, flush=True)
+    for count, key, counter in ((4001, 7, 0), (37, 2 ** 64 - 3, 2 ** 64 - 4), (1, 0, 5)):
+        z = torch.empty(count, dtype=torch.float64 if fp64 else torch.float32, device="cuda")
+        tj.trajam_normals(count, key, counter, fp64, z.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        exp = orng.normals(count, key, counter)
+        got = z.cpu().numpy().astype(np.float64)
+        if fp64:
+            np.testing.assert_allclose(got, exp, rtol=1e-13, atol=1e-13)
+        else:
+            np.testing.assert_allclose(got, exp.astype(np.float32).astype(np.float64), rtol=2.5e-7, atol=1e-7)
+    # the loop's draws are one stream, iteration after iteration
+    zz = cem.draw(3, 50, 22, key=11, counter=4, fp64=True)
+    np.testing.assert_allclose(zz.cpu().numpy().reshape(-1), orng.normals(3 * 50 * 22, 11, 4), rtol=1e-13,
+                               atol=1e-13)
