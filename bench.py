@@ -446,7 +446,7 @@ def mfma_bench(args):
     return out
 
 
-def ragged_bench(args):
+def ragged_bench(args, net=None):
     """Ragged set of many independent problems in one plan: n_obs ~ U{5..300}, batch ~
     U{32..2048}; even problems are 2D single robots (config-2 geometry), odd ones 3D
     multi-agent problems with N ~ U{16..64} agents (pair clearance 0.6 m; a batch entry
@@ -521,6 +521,11 @@ def ragged_bench(args):
                   "the resets"}
     del g
     plan.close()
+    # the learned warm start on the single-robot half, with the cold fallback, against
+    # the cold plan of the same problems: the config-2 network (one obstacle count) and
+    # one trained on the half's own family (circle counts 5..300, held-out seeds)
+    if net is not None:
+        out["warm_single_robot"] = ragged_warm(args, ws, items, K, net)
     # the multi-agent half alone (its own plan): the agents kernel's time and roofline
     agent_items = [it for it, w in zip(items, ws) if w.n_agents > 1]
     agent_ws = [w for w in ws if w.n_agents > 1]
@@ -556,6 +561,70 @@ def ragged_bench(args):
         s.close()
     return out
 
+
+
+
+def ragged_warm(args, ws, items, K, net_cfg2):
+    import torch
+    from paper_2408_10731_amd import warmstart as ws_mod
+    two = [(w, it) for w, it in zip(ws, items) if w.n_agents == 1]
+    t0 = time.perf_counter()
+    fams = [ws_mod.family_scene(f"2d-n{n}") for n in (5, 40, 80, 120, 160, 200, 250, 300)]
+    data = ws_mod.generate_mixed(fams, list(range(60_000, 60_000 + args.ws_scenes)), 64, k0=ws_mod.K0, cap=150)
+    net_mix = ws_mod.Net(ws_mod.widths_for(two[0][0]), seed=0, precision=1, max_batch=512)
+    curve = ws_mod.train(net_mix, data, epochs=args.ws_epochs, batch=512, lr=1e-3)
+    torch.cuda.synchronize()
+    training = {"pairs": int(data.x.shape[0]), "scenes": args.ws_scenes, "epochs": args.ws_epochs,
+                "circle_counts": [5, 40, 80, 120, 160, 200, 250, 300], "scene_seeds": [60_000, 60_000 + args.ws_scenes - 1],
+                "loss_first": curve[0], "loss_last": curve[-1], "seconds": time.perf_counter() - t0}
+    del data
+
+    def first(tr):
+        med = np.median(tr, axis=1)
+        hit = np.nonzero(med <= 1e-3)[0]
+        return int(hit[0]) + 1 if hit.size else None
+
+    res = {"problems": len(two), "samples": int(sum(w.batch for w, _ in two)), "iterations": K,
+           "tol": 1e-3, "ragged_family_training": training}
+    cold = None
+    for name, net in (("cfg2_network", net_cfg2), ("ragged_family_network", net_mix)):
+        rws = ws_mod.RaggedWarmStart([it[0] for _, it in two], [it[1] for _, it in two],
+                                     [w.boundary for w, _ in two], net, K)
+        t_w, t_c = [], []
+        for _ in range(max(2, args.ragged_steps)):
+            for fn, acc in ((rws.run, t_w), (rws.run_cold, t_c)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                acc.append(time.perf_counter() - t0)
+        rws.run()
+        torch.cuda.synchronize()
+        wtr = [t.cpu().numpy() for t in rws.traces()]
+        fl = rws.FL.cpu().numpy()
+        if cold is None:
+            rws.run_cold()
+            torch.cuda.synchronize()
+            ctr = [t.cpu().numpy() for t in rws.traces(cold=True)]
+            fc = [first(t) for t in ctr]
+            cold = {"problems_at_tol": int(sum(f is not None for f in fc)),
+                    "iterations_to_tol_capped": int(sum(f if f is not None else K for f in fc)),
+                    "mean_final_median_residual": float(np.mean([np.median(t[-1]) for t in ctr])),
+                    "ms_per_set": 1e3 * float(np.median(t_c))}
+            res["cold"] = cold
+        fw = [first(t) for t in wtr]
+        res[name] = {
+            "problems_at_tol": int(sum(f is not None for f in fw)),
+            "iterations_to_tol_capped": int(sum(f if f is not None else K for f in fw)),
+            "fewer_iterations_than_cold": int(sum((a if a is not None else K) < (b if b is not None else K)
+                                                  for a, b in zip(fw, fc))),
+            "more_iterations_than_cold": int(sum((a if a is not None else K) > (b if b is not None else K)
+                                                 for a, b in zip(fw, fc))),
+            "mean_final_median_residual": float(np.mean([np.median(t[-1]) for t in wtr])),
+            "fallbacks": int(((fl & 4) != 0).sum()),
+            "ms_per_set": 1e3 * float(np.median(t_w))}
+        rws.close()
+    return res
 
 def agents_ops_per_unit(w) -> int:
     """Algorithmic VALU lane-ops of one joint sample's AM iteration in a multi-agent
@@ -1104,11 +1173,13 @@ def main():
                               "value": c2b["value"], "ms_per_step": c2b["ms_per_step"],
                               "launch_ms": c2b["launch_ms"]}
 
-    ttr = (time_to_residual(args, w2, c2["solver"], c2["xi"], c2["obs"], torch.cuda.current_stream())
+    net2, info2 = (train_warm_start(w2, args.ws_scenes, args.ws_epochs) if args.ttr_cap > 0 else (None, None))
+    ttr = (time_to_residual(args, w2, c2["solver"], c2["xi"], c2["obs"], torch.cuda.current_stream(),
+                            net=net2, info=info2)
            if args.ttr_cap > 0 else None)
     cont = continuation_leg(w2, args.ttr_cap, torch.cuda.current_stream()) if args.ttr_cap > 0 else None
     c2["solver"].close()
-    ragged = ragged_bench(args) if args.ragged_problems > 0 else None
+    ragged = ragged_bench(args, net2) if args.ragged_problems > 0 else None
     cem_out = cem_bench(args) if args.cem_calls > 0 else None
     warm4, net4 = ((warm_cfg4_bench(args) if args.ws4_scenes > 0 and args.cem_calls > 0 and args.ttr_cap > 0
                     else (None, None)))

@@ -194,6 +194,18 @@ def generate(scene_fn, seeds, samples_per_scene, k0=K0, cap=150, tol=1e-3, chunk
     return Dataset(torch.cat(xs).contiguous(), torch.cat(ts).contiguous(), len(seeds))
 
 
+def generate_mixed(scene_fns, seeds, samples_per_scene, k0=K0, cap=150, tol=1e-3, chunk=256):
+    """Pairs from several scene families that differ in their obstacle count (each
+    family on its own pool of solvers, `generate`), the seeds dealt out round-robin;
+    one dataset."""
+    import torch
+    seeds = [int(x) for x in seeds]
+    parts = [generate(fn, seeds[i::len(scene_fns)], samples_per_scene, k0, cap, tol, chunk)
+             for i, fn in enumerate(scene_fns) if seeds[i::len(scene_fns)]]
+    return Dataset(torch.cat([d.x for d in parts]).contiguous(), torch.cat([d.t for d in parts]).contiguous(),
+                   len(seeds))
+
+
 def train(net: Net, data: Dataset, epochs: int, batch: int = 1024, lr: float = 1e-3,
           seed: int = 0):
     """Minibatch Adam on the mean squared error; returns the per-epoch mean loss."""
@@ -289,4 +301,117 @@ def family_scene(family: str):
         return lambda seed, batch: wl.config2(batch=batch, seed=seed)
     if family == "cfg4":
         return lambda seed, batch: wl.config4_scene(seed, batch=batch)
+    if family.startswith("2d-n"):
+        # the config-2 geometry with a given number of circles (the single-robot
+        # problems of the ragged set draw it from 5..300)
+        n_obs = int(family[4:])
+        return lambda seed, batch: wl.problem2d(seed, n_obs, batch)
     raise ValueError(family)
+
+
+class RaggedWarmStart:
+    """The learned warm start for the single-robot problems of a ragged set (all of one
+    family: the network's dims and n_v), with the per-sample cold fallback:
+
+        probe:    one ragged launch of k0 iterations over every problem from (xi, 0);
+        jump:     one fused launch over all the problems' samples;
+        check:    per problem the residual of the jumped state against the probe's last
+                  residual (trajam_residuals, trajam_warm_fallback);
+        continue: one ragged launch of iters - k0 iterations from the checked state.
+
+    The problems' samples and states live in shared buffers, problem after problem, so
+    the jump is one launch; `states()` gives each problem's (xi_bar, lambda) views.  A
+    cold plan of `iters` iterations over the same problems is built beside it for
+    comparison (`run_cold`).  Every method only launches kernels (capturable)."""
+
+    def __init__(self, solvers, xis, boundaries, net: Net, iters: int, k0: int = K0, trace: bool = True):
+        import torch
+        self.solvers, self.net, self.k0, self.K = list(solvers), net, int(k0), int(iters)
+        D, nv = self.solvers[0].dims, self.solvers[0].nv
+        if any(s.dims != D or s.nv != nv or s.n_agents != 1 for s in self.solvers):
+            raise ValueError("one family of single-robot problems")
+        if not 0 < self.k0 < self.K:
+            raise ValueError("0 < k0 < iters")
+        self.D, self.nv = D, nv
+        sizes = [int(x.shape[0]) for x in xis]
+        self.off = np.concatenate([[0], np.cumsum(sizes)]).astype(int)
+        Bt = int(self.off[-1])
+        dev = "cuda"
+        self.X = torch.cat([x.reshape(-1, D, nv) for x in xis]).contiguous()
+        self.XB, self.LAM = torch.zeros_like(self.X), torch.zeros_like(self.X)
+        self.XW, self.LW = torch.zeros_like(self.X), torch.zeros_like(self.X)
+        self.RW = torch.zeros(Bt, device=dev)
+        self.FL = torch.zeros(Bt, dtype=torch.int32, device=dev)
+        # per problem: the probe's trace [k0][B_i], the continuation's [K - k0][B_i] and
+        # the cold plan's [K][B_i], each a contiguous chunk
+        self.TP = torch.zeros(self.k0 * Bt, device=dev)
+        self.TC = torch.zeros((self.K - self.k0) * Bt if trace else 1, device=dev)
+        self.TK = torch.zeros(self.K * Bt if trace else 1, device=dev)
+        self.boundaries = [np.asarray(b, dtype=np.float64) for b in boundaries]
+        v = self._views
+        self.probe = tj.RaggedPlan([(s, v(self.X, i), self.boundaries[i], v(self.XB, i), v(self.LAM, i),
+                                     self._trace(self.TP, self.k0, i)) for i, s in enumerate(self.solvers)],
+                                   self.k0)
+        self.rest = tj.RaggedPlan([(s, v(self.X, i), self.boundaries[i], v(self.XW, i), v(self.LW, i))
+                                   + ((self._trace(self.TC, self.K - self.k0, i),) if trace else ())
+                                   for i, s in enumerate(self.solvers)], self.K - self.k0)
+        self.cold = tj.RaggedPlan([(s, v(self.X, i), self.boundaries[i], v(self.XB, i), v(self.LAM, i))
+                                   + ((self._trace(self.TK, self.K, i),) if trace else ())
+                                   for i, s in enumerate(self.solvers)], self.K)
+        nbytes = tj.trajam_warm_pack_mfma(net.shape, None, None, None)
+        self.packed = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
+        tj.trajam_warm_pack_mfma(net.shape, net.params.data_ptr(), self.packed.data_ptr(),
+                                 torch.cuda.current_stream().cuda_stream)
+
+    def _views(self, T, i):
+        return T[self.off[i]:self.off[i + 1]]
+
+    def _trace(self, T, k, i):
+        B0, B1 = int(self.off[i]), int(self.off[i + 1])
+        return T[k * B0:k * B1].view(k, B1 - B0)
+
+    def traces(self, cold: bool = False):
+        """Per problem, the residual trace [K, B_i] of the last run (warm: probe rows then
+        the continuation's)."""
+        import torch
+        out = []
+        for i in range(len(self.solvers)):
+            if cold:
+                out.append(self._trace(self.TK, self.K, i))
+            else:
+                out.append(torch.cat([self._trace(self.TP, self.k0, i), self._trace(self.TC, self.K - self.k0, i)]))
+        return out
+
+    def states(self, cold: bool = False):
+        v = self._views
+        return [(v(self.XB, i), v(self.LAM, i)) if cold else (v(self.XW, i), v(self.LW, i))
+                for i in range(len(self.solvers))]
+
+    def run(self):
+        import torch
+        st = torch.cuda.current_stream().cuda_stream
+        self.XB.copy_(self.X)
+        self.LAM.zero_()
+        self.probe.launch()
+        Bt = int(self.off[-1])
+        tj.trajam_warm_jump(self.net.shape, Bt, self.D, self.nv, self.packed.data_ptr(), 1.0 / IN_SCALE, OUT_SCALE,
+                            self.X.data_ptr(), self.XB.data_ptr(), self.LAM.data_ptr(), self.XW.data_ptr(),
+                            self.LW.data_ptr(), st)
+        for i, s in enumerate(self.solvers):
+            xw, lw = self._views(self.XW, i), self._views(self.LW, i)
+            rw, fl = self._views(self.RW, i), self._views(self.FL, i)
+            s.residuals(xw, None, rw)
+            rc = self._trace(self.TP, self.k0, i)[self.k0 - 1]
+            tj.trajam_warm_fallback(int(rw.shape[0]), self.D, self.nv, rw.data_ptr(), rc.data_ptr(),
+                                    self._views(self.XB, i).data_ptr(), self._views(self.LAM, i).data_ptr(),
+                                    xw.data_ptr(), lw.data_ptr(), fl.data_ptr(), st)
+        self.rest.launch()
+
+    def run_cold(self):
+        self.XB.copy_(self.X)
+        self.LAM.zero_()
+        self.cold.launch()
+
+    def close(self):
+        for p in (self.probe, self.rest, self.cold):
+            p.close()

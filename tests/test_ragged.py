@@ -266,3 +266,68 @@ def test_autotune_picks_cached_valid_launch(tmp_path):
         s.close()
     finally:
         os.environ.pop("TRAJAM_AUTOTUNE_CACHE", None)
+
+
+@pytest.mark.gpu
+def test_ragged_warm_start_composes_the_library_calls():
+    """The ragged set's learned warm start: one probe launch over every problem, one
+    fused jump over all samples, per problem the residual check and fallback, one
+    continuation launch -- equal (bitwise) to the same steps made problem by problem
+    with single launches; the cold plan equals single cold launches; fallback flags
+    are 0 or TRAJAM_FLAG_COLD_FALLBACK."""
+    import torch
+    from paper_2408_10731_amd import trajam as tj
+    from paper_2408_10731_amd import warmstart as ws
+    print("case: ragged warm start", flush=True)
+    problems = [wl.problem2d(700 + k, n_obs, b, 10) for k, (n_obs, b) in
+                enumerate([(5, 40), (60, 300), (200, 77), (13, 129), (300, 33)])]
+    K = 10
+    solvers, xis = [], []
+    for w in problems:
+        s = tj.Solver.for_workload(w, precision="fp32")
+        xi, obs = tj.device_workload(w, torch.float32)
+        s.set_obstacles(obs)
+        solvers.append(s)
+        xis.append(xi)
+    Bt = sum(w.batch for w in problems)
+    net = ws.Net(ws.widths_for(problems[0]), seed=5, precision=1, max_batch=Bt)
+    rw = ws.RaggedWarmStart(solvers, xis, [w.boundary for w in problems], net, K)
+    rw.run()
+    torch.cuda.synchronize()
+    warm = [(a.clone(), b.clone()) for a, b in rw.states()]
+    warm_tr = [t.clone() for t in rw.traces()]
+    fl = rw.FL.cpu().numpy()
+    assert set(np.unique(fl)) <= {0, tj.FLAG_COLD_FALLBACK}
+    rw.run_cold()
+    torch.cuda.synchronize()
+    cold = [(a.clone(), b.clone()) for a, b in rw.states(cold=True)]
+    # by hand, problem by problem
+    nbytes = tj.trajam_warm_pack_mfma(net.shape, None, None, None)
+    packed = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    tj.trajam_warm_pack_mfma(net.shape, net.params.data_ptr(), packed.data_ptr(), st)
+    for i, (w, s, xi) in enumerate(zip(problems, solvers, xis)):
+        s.set_launch(1, 1)   # the wave-per-sample kernel, whose arithmetic the ragged kernel runs
+        xb, lam = xi.clone(), torch.zeros_like(xi)
+        trp = torch.zeros((ws.K0, w.batch), device="cuda")
+        s.project(xi, w.boundary, None, xb, lam, ws.K0, res_trace=trp)
+        xw, lw = torch.empty_like(xb), torch.empty_like(lam)
+        tj.trajam_warm_jump(net.shape, w.batch, 2, w.n_v, packed.data_ptr(), 1.0, 1.0, xi.data_ptr(),
+                            xb.data_ptr(), lam.data_ptr(), xw.data_ptr(), lw.data_ptr(), st)
+        r = torch.zeros(w.batch, device="cuda")
+        s.residuals(xw, None, r)
+        f = torch.zeros(w.batch, dtype=torch.int32, device="cuda")
+        tj.trajam_warm_fallback(w.batch, 2, w.n_v, r.data_ptr(), trp[ws.K0 - 1].data_ptr(), xb.data_ptr(),
+                                lam.data_ptr(), xw.data_ptr(), lw.data_ptr(), f.data_ptr(), st)
+        trc = torch.zeros((K - ws.K0, w.batch), device="cuda")
+        s.project(xi, w.boundary, None, xw, lw, K - ws.K0, res_trace=trc)
+        xc, lc = xi.clone(), torch.zeros_like(xi)
+        s.project(xi, w.boundary, None, xc, lc, K)
+        torch.cuda.synchronize()
+        assert torch.equal(warm[i][0], xw) and torch.equal(warm[i][1], lw), i
+        assert torch.equal(warm_tr[i], torch.cat([trp, trc])), i
+        assert np.array_equal(fl[rw.off[i]:rw.off[i + 1]], f.cpu().numpy()), i
+        assert torch.equal(cold[i][0], xc) and torch.equal(cold[i][1], lc), i
+    rw.close()
+    for s in solvers:
+        s.close()
