@@ -320,3 +320,98 @@ def config5(n_problems: int = 256, seed: Optional[int] = None, iters: int = 50,
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
+
+
+@dataclasses.dataclass
+class HeadingWorkload:
+    """A problem of the heading / multi-circle variant (Paper II: a rectangular robot
+    modelled by circles on its heading axis, a tracking-and-smoothness cost, crowds of
+    elliptical obstacles) plus a batch of initial states.
+
+    xi0 [B, 5, n_v]: per sample the initial coefficients of x, c, y, s, psi (c and s:
+    the slack copies of cos psi and sin psi).  x_des [2, n_steps]: the desired
+    positions at the time steps t_k = k T / (n_steps - 1)."""
+
+    name: str
+    degree: int
+    n_steps: int
+    horizon: float
+    v_max: float
+    a_max: float
+    rho: float
+    radii: np.ndarray        # [n_c] circle offsets along the heading axis
+    obs_centre: np.ndarray   # [n_o, 2] at t = 0
+    obs_vel: np.ndarray      # [n_o, 2] constant velocity
+    obs_axes: np.ndarray     # [n_o, 2] semi-axes (inflated by the footprint circles' radius)
+    boundary: np.ndarray     # [2, 4] rows (p0, v0, a0, pf) of x and y
+    boundary_psi: np.ndarray  # [2] (psi(0), psi(T))
+    x_des: np.ndarray        # [2, n_steps]
+    xi0: np.ndarray          # [B, 5, n_v]
+    iters: int
+
+    @property
+    def n_v(self) -> int:
+        return self.degree + 1
+
+    @property
+    def n_obs(self) -> int:
+        return int(self.obs_centre.shape[0])
+
+    @property
+    def n_circles(self) -> int:
+        return int(self.radii.shape[0])
+
+    @property
+    def batch(self) -> int:
+        return int(self.xi0.shape[0])
+
+
+def heading_scene(seed: int, n_obs: int = 30, n_circles: int = 4, batch: int = 1000,
+                  iters: int = 10, flow: str = "static", degree: int = 10, n_steps: int = 100) -> HeadingWorkload:
+    """Paper II's crowd benchmarks as synthetic scenes: a 1.2 m x 0.6 m robot (n_circles
+    circles of radius 0.3 m spread along its length) tracks the straight line from
+    (0, 0) to (20, 0) at 1 m/s over T = 20 s through a crowd of n_obs people (radius
+    0.25 m, so the semi-axes are 0.55 m) placed in [3, 17] x [-3, 3].  flow: "static"
+    (benchmark 1), "same" (the crowd walks along +x at up to 0.3 m/s, benchmark 2) or
+    "opposite" (along -x at up to 1 m/s, benchmark 3).  v_max = 2 m/s, a_max = 2 m/s^2.
+    Initial states: the line with lateral offsets drawn per sample (a smooth bump of
+    amplitude ~ N(0, 1.5) m plus coefficient noise N(0, 0.3)), the heading coefficients
+    N(0, 0.2) rad with psi fixed to 0 at both ends, c and s the cosine and sine of the
+    heading coefficients."""
+    rng = _rng(seed)
+    T = 20.0
+    start, goal = np.array([0.0, 0.0]), np.array([20.0, 0.0])
+    radii = (np.linspace(-0.45, 0.45, n_circles) if n_circles > 1 else np.zeros(1))
+    centre = np.zeros((max(n_obs, 0), 2))
+    for j in range(n_obs):
+        while True:
+            c = rng.uniform((3.0, -3.0), (17.0, 3.0))
+            if np.linalg.norm(c - start) > 2.0 and np.linalg.norm(c - goal) > 2.0:
+                break
+        centre[j] = c
+    vel = np.zeros_like(centre)
+    if flow == "same":
+        vel[:, 0] = rng.uniform(0.0, 0.3, n_obs)
+    elif flow == "opposite":
+        vel[:, 0] = -rng.uniform(0.0, 1.0, n_obs)
+    elif flow != "static":
+        raise ValueError(flow)
+    axes = np.full((n_obs, 2), 0.55)
+    nv = degree + 1
+    frac = np.arange(nv) / degree
+    bump = np.sin(np.pi * frac)
+    xi0 = np.zeros((batch, 5, nv))
+    xi0[:, 0] = start[0] + frac * (goal[0] - start[0]) + rng.normal(0.0, 0.3, (batch, nv))
+    xi0[:, 2] = rng.normal(0.0, 1.5, (batch, 1)) * bump + rng.normal(0.0, 0.3, (batch, nv))
+    psi = rng.normal(0.0, 0.2, (batch, nv))
+    psi[:, 0] = psi[:, -1] = 0.0
+    xi0[:, 4] = psi
+    xi0[:, 1] = np.cos(psi)
+    xi0[:, 3] = np.sin(psi)
+    bnd = np.zeros((2, 4))
+    bnd[:, 0], bnd[:, 3] = start, goal
+    bnd[:, 1] = (goal - start) / T
+    t = np.linspace(0.0, T, n_steps)
+    x_des = start[:, None] + (goal - start)[:, None] * (t / T)[None, :]
+    return HeadingWorkload(f"heading-{flow}-n{n_obs}-c{n_circles}-b{batch}", degree, n_steps, T, 2.0, 2.0,
+                           1.0, radii, centre, vel, axes, bnd, np.zeros(2), x_des, xi0, iters)
