@@ -38,8 +38,10 @@ Readings (each listed in the design notes):
     objective is min(1, |v| / v_max), which is taken;
   - angles of an ellipse in coordinates scaled by its semi-axes, d = max(1, |scaled|)
     (as in the main path); a point at an obstacle's centre takes atan2(+0, +0) = 0;
-  - initial alpha, d come from the polar step of the input state; lam = lam_psi = 0
-    unless given; one rho for every block;
+  - the input state is first made to satisfy the boundary rows (its coefficients that
+    the rows involve, 0, 1, 2 and n of x and y, 0 and n of psi, are solved for; the
+    others are kept); initial alpha, d come from the polar step of that state;
+    lam = lam_psi = 0 unless given; one rho for every block;
   - boundary rows: position, velocity, acceleration at t = 0 and position at T for x
     and y; heading at t = 0 and T.
 """
@@ -166,6 +168,22 @@ def group_rows(ops, xi):
     return ops.F @ np.concatenate([xi[0], xi[1]]), ops.F @ np.concatenate([xi[2], xi[3]])
 
 
+def meet_boundary(w, ops, st):
+    """The state with the coefficients that the boundary rows involve solved for, so
+    that A xi = b and A_psi xi_psi = b_psi hold; the other coefficients unchanged."""
+    nv = w.n_v
+    out = np.array(st, dtype=np.float64).copy()
+    fixed = [0, 1, 2, nv - 1]
+    other = [k for k in range(nv) if k not in fixed]
+    Ab = ops.A[:, :nv]
+    for row, grp in ((0, 0), (2, 1)):
+        rhs = w.boundary[grp] - Ab[:, other] @ out[row, other]
+        out[row, fixed] = np.linalg.solve(Ab[:, fixed], rhs)
+    fp, op = [0, nv - 1], list(range(1, nv - 1))
+    out[4, fp] = np.linalg.solve(ops.Apsi[:, fp], w.boundary_psi - ops.Apsi[:, op] @ out[4, op])
+    return out
+
+
 def iterate(w, iters=None, state=None, lam=None):
     """Alg 2 on every sample.  state, lam [B, 5, n_v] (rows x, c, y, s, psi) default to
     w.xi0 and zeros.  Returns (state, lam, trace [iters, B, 2]) with trace[k, b] the two
@@ -178,6 +196,7 @@ def iterate(w, iters=None, state=None, lam=None):
     trace = np.zeros((K, B, 2))
     nv = w.n_v
     for i in range(B):
+        st[i] = meet_boundary(w, ops, st[i])
         xi, xps = st[i, :4].copy(), st[i, 4].copy()
         la, lps = lm[i, :4].copy(), lm[i, 4].copy()
         gx, gy = g_vectors(w, ops, polar_step(w, ops, xi, xps))

@@ -293,3 +293,20 @@ def test_residuals_fall_on_a_crowd():
     best = np.argmin(tr[-1, :, 0])
     assert tr[-1, best, 0] < 0.5 * tr[0, best, 0]
     assert tr[-1, :, 1].max() < 0.2 * tr[0, :, 1].max()
+
+
+def test_initial_state_meets_the_boundary_rows():
+    """The initialization reading: the coefficients the boundary rows involve are solved
+    for (checked with scipy's polynomials), the others are the input's."""
+    w = tiny(10)
+    ops = oh.operators(w)
+    st = w.xi0[0] + 0.3
+    out = oh.meet_boundary(w, ops, st)
+    T, nv = w.horizon, w.n_v
+    for row, grp in ((0, 0), (2, 1)):
+        got = [bpoly(out[row], T, nu)(t) for nu, t in ((0, 0.0), (1, 0.0), (2, 0.0), (0, T))]
+        np.testing.assert_allclose(got, w.boundary[grp], atol=1e-12)
+        np.testing.assert_array_equal(out[row, 3:nv - 1], st[row, 3:nv - 1])
+    np.testing.assert_allclose([bpoly(out[4], T)(0.0), bpoly(out[4], T)(T)], w.boundary_psi, atol=1e-12)
+    np.testing.assert_array_equal(out[4, 1:nv - 1], st[4, 1:nv - 1])
+    np.testing.assert_array_equal(out[[1, 3]], st[[1, 3]])
