@@ -548,6 +548,73 @@ trajam_status trajam_warm_fallback(int32_t batch, int32_t dims, int32_t n_coeffs
                                    const float *lam_src, float *xb, float *lam, uint32_t *flags,
                                    void *stream);
 
+/* ------------------------------------------------------------------------------
+ * Heading / multi-circle variant (thesis ch. 5, Paper II: Problem Formulation, the
+ * reformulated problem eqs reform_cost..d_bound, the augmented Lagrangian eq
+ * reform_formulation and Alg 2).  A rectangular robot is n_c circles at offsets r_m on
+ * its heading axis; it tracks x_des(t) with the cost sum_t (xdd^2 + ydd^2 + psidd^2 +
+ * |p - p_des|^2) under |v| <= v_max, |a| <= a_max and every circle outside every
+ * axis-aligned elliptical obstacle.  Per sample the state is the Bernstein
+ * coefficients of x, c, y, s (c, s: slack copies of cos psi, sin psi) and psi, and the
+ * multipliers of the same rows.  One iteration, in Alg 2's order:
+ *   1. xi      <- the QP with the fixed matrix Q + rho F'F of each position group
+ *                 (x with c, y with s) under A xi = b;
+ *   2. psi_t   <- atan2(s, c) at the time steps, on the branch nearest the current
+ *                 heading; xi_psi <- the QP with the fixed matrix Pdd'Pdd + rho P'P of
+ *                 eq compute_convex_surrogate under A_psi xi_psi = b_psi;
+ *   3-4.        the polar step: angles and radii of every (circle, obstacle, step)
+ *                 row (centre x + r_m cos psi, angles scaled by the semi-axes, d >= 1)
+ *                 and of the velocity / acceleration rows (d <= 1) (eqs zeta_2..compute_da);
+ *   5. lam     <- lam - rho F'(F xi - g); lam_psi <- lam_psi - rho P'(P xi_psi - psi_t).
+ * Before the first iteration the state's coefficients fixed by the boundary rows
+ * (0, 1, 2, n of x and y; 0, n of psi) are set from them and the first polar step is
+ * taken at that state.  Residuals of an iterate: |F xi - g| over both groups and
+ * |psi_t - P xi_psi|.
+ *
+ * Layouts: state, lambda [batch][5][degree + 1] (rows x, c, y, s, psi), res_trace
+ * [iters][batch][2], all device memory in the handle's precision (double for
+ * TRAJAM_FP64, float for TRAJAM_FP32). */
+#define TRAJAM_HEADING_MAX_CIRCLES 8
+
+typedef struct trajam_heading trajam_heading;
+
+typedef struct {
+    int32_t degree;      /* Bernstein degree n in [4, 11] */
+    int32_t n_steps;     /* time steps t_k = k T / (n_steps - 1), in [n + 1, 128] */
+    double horizon;      /* T [s] > 0 */
+    double v_max;        /* > 0 [m/s] */
+    double a_max;        /* > 0 [m/s^2] */
+    double rho;          /* > 0, one penalty weight for every block */
+    int32_t n_circles;   /* footprint circles, in [1, 8] */
+    double radii[TRAJAM_HEADING_MAX_CIRCLES];  /* offsets r_m [m] on the heading axis */
+    int32_t n_obstacles; /* >= 0; fixes the row count of F, hence the QP operator */
+    int32_t precision;   /* TRAJAM_FP64 or TRAJAM_FP32 */
+    int32_t max_batch;   /* >= 1 */
+} trajam_heading_problem;
+
+/* Handle with both fixed QP operators (inverses of the free blocks, computed in FP64
+ * on the host) and the basis tables on the current device.  Errors (message through
+ * trajam_last_error(NULL)): INVALID, NUMERIC, DEVICE. */
+trajam_status trajam_heading_create(const trajam_heading_problem *p, trajam_heading **out);
+void trajam_heading_destroy(trajam_heading *h);
+const char *trajam_heading_last_error(const trajam_heading *h);
+
+/* The scene, from HOST memory (copied before the call returns; it first waits for the
+ * device, since a projection in flight reads the tables): boundary [10] = (x0, vx0,
+ * ax0, xf, y0, vy0, ay0, yf, psi0, psif); x_des [2][n_steps] desired x and y at the
+ * time steps; obstacles [n_obstacles][6] = (cx, cy, vx, vy, a, b): centre at t = 0 [m],
+ * constant velocity [m/s], semi-axes [m] > 0 (inflated by the footprint circles'
+ * radius).  Errors: INVALID, DEVICE. */
+trajam_status trajam_heading_set_scene(trajam_heading *h, const double *boundary, const double *x_des,
+                                       const double *obstacles);
+
+/* `iters` iterations of Alg 2 for every sample, in place: state and lambda are read
+ * as the start and hold the result (zero lambda for a cold start).  res_trace may be
+ * NULL.  With iters = 0 the state's boundary coefficients are set and nothing else.
+ * Errors: INVALID (no scene, negative sizes, NULL), CAPACITY, DEVICE. */
+trajam_status trajam_heading_project(trajam_heading *h, int32_t batch, void *state, void *lambda, int32_t iters,
+                                     void *res_trace, void *stream);
+
 /* Static description of a status code.  Never NULL. */
 const char *trajam_status_string(trajam_status st);
 

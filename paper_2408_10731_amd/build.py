@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtrajam.so")
 SOURCES = ["am_kernels.hip", "polar_kernels.hip", "cem_kernels.hip", "mlp_kernels.hip", "mpc_kernels.hip",
-           "trajam_api.cpp", "mlp_api.cpp"]
+           "heading_kernels.hip", "trajam_api.cpp", "mlp_api.cpp", "heading_api.cpp"]
 ARCH = os.environ.get("TRAJAM_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

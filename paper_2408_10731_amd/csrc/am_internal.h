@@ -188,4 +188,23 @@ hipError_t launch_ragged(const AmArgs<float> *probs, const int *offsets, int n_p
 // Dynamic LDS bytes of one AM workgroup.
 size_t project_lds_bytes(int dims, int nvp, int tpad, int tb, size_t scalar);
 
+// Heading / multi-circle variant (heading_kernels.hip).  Device tables in the
+// solver's precision: phi [3][n_steps][kHeadingMaxCoeffs] (P, Pd, Pdd), x_des
+// [2][n_steps], obs [n_obs][8] (cx, cy, vx, vy, a, b, 1/a, 1/b), W [2 kHeadingMaxCoeffs
+// - 4]^2 (inverse of the free block of one position group's Q + rho F'F: free x
+// coefficients 3..n-1, then c 0..n), Wpsi [kHeadingMaxCoeffs]^2 (free psi coefficients
+// 1..n-1).
+constexpr int kHeadingMaxCoeffs = 12;
+constexpr int kHeadingMaxCircles = 8;
+struct HeadingArgs {
+    const void *phi, *x_des, *obs, *W, *Wpsi;
+    double radii[kHeadingMaxCircles];
+    double bcoef[2][4];   // coefficients 0, 1, 2, n of x and y fixed by the boundary rows
+    double bpsi[2];       // coefficients 0, n of psi
+    double dt, v_max, a_max, rho;
+    int n_circles, n_obs, nv, n_steps;
+};
+hipError_t launch_heading(bool fp64, const HeadingArgs &a, int batch, int iters, void *state, void *lam,
+                          void *trace, hipStream_t st);
+
 }  // namespace trajam

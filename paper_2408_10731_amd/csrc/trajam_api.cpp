@@ -411,6 +411,20 @@ trajam_status problem_contraction(const trajam_problem &p, const std::vector<dou
 
 }  // namespace
 
+namespace trajam {
+// Host helpers shared with the heading variant's entry points (heading_api.cpp).
+void host_basis(int n, int np, double T, std::vector<double> &P, std::vector<double> &Pd,
+                std::vector<double> &Pdd)
+{
+    basis(n, np, T, P, Pd, Pdd);
+}
+bool host_spd_inverse(int n, const std::vector<double> &A, std::vector<double> &Ainv)
+{
+    return spd_inverse(n, A, Ainv);
+}
+void host_boundary_coeffs(int n, double T, const double *b4, double *c4) { boundary_coeffs(n, T, b4, c4); }
+}  // namespace trajam
+
 extern "C" {
 
 const char *trajam_status_string(trajam_status st)

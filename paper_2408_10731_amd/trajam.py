@@ -51,6 +51,8 @@ EXPORTS = [
     "trajam_warm_apply", "trajam_warm_fallback", "trajam_warm_pack_mfma", "trajam_warm_jump", "trajam_set_obstacles", "trajam_autotune",
     "trajam_ragged_plan_create", "trajam_ragged_launch", "trajam_ragged_plan_destroy", "trajam_polar",
     "trajam_qp_contraction", "trajam_set_continuation", "trajam_project_continuation",
+    "trajam_heading_create", "trajam_heading_destroy", "trajam_heading_set_scene", "trajam_heading_project",
+    "trajam_heading_last_error",
     "trajam_status_string", "trajam_last_error",
 ]
 
@@ -97,6 +99,25 @@ CONT_MAX_LEVELS = 16
 
 class MlpShape(ctypes.Structure):
     _fields_ = [("n_layers", ctypes.c_int32), ("width", ctypes.c_int32 * (8 + 1))]
+
+
+HEADING_MAX_CIRCLES = 8
+
+
+class HeadingProblem(ctypes.Structure):
+    _fields_ = [
+        ("degree", ctypes.c_int32),
+        ("n_steps", ctypes.c_int32),
+        ("horizon", ctypes.c_double),
+        ("v_max", ctypes.c_double),
+        ("a_max", ctypes.c_double),
+        ("rho", ctypes.c_double),
+        ("n_circles", ctypes.c_int32),
+        ("radii", ctypes.c_double * HEADING_MAX_CIRCLES),
+        ("n_obstacles", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+    ]
 
 
 class RaggedItem(ctypes.Structure):
@@ -223,6 +244,16 @@ def load():
               "trajam_mlp_mse", "trajam_mlp_adam", "trajam_warm_features", "trajam_warm_apply",
               "trajam_warm_fallback"):
         getattr(L, f).restype = ctypes.c_int
+    L.trajam_heading_create.argtypes = [ctypes.POINTER(HeadingProblem), ctypes.POINTER(vp)]
+    L.trajam_heading_create.restype = ctypes.c_int
+    L.trajam_heading_destroy.argtypes = [vp]
+    L.trajam_heading_destroy.restype = None
+    L.trajam_heading_set_scene.argtypes = [vp, dp, dp, dp]
+    L.trajam_heading_set_scene.restype = ctypes.c_int
+    L.trajam_heading_project.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp]
+    L.trajam_heading_project.restype = ctypes.c_int
+    L.trajam_heading_last_error.argtypes = [vp]
+    L.trajam_heading_last_error.restype = ctypes.c_char_p
     L.trajam_status_string.argtypes = [ctypes.c_int]
     L.trajam_status_string.restype = ctypes.c_char_p
     L.trajam_last_error.argtypes = [vp]
@@ -693,3 +724,101 @@ def device_workload(w, dtype, device="cuda", static=None):
         static = not np.any(w.obs_vel)
     v = None if static else torch.as_tensor(w.obs_vel, dtype=dtype, device=device).contiguous()
     return xi, (c, v, a)
+
+
+# ------------------------------------------------------- heading variant --
+
+
+def _hcheck(st: int, handle=None):
+    if st != TRAJAM_OK:
+        L = load()
+        msg = (L.trajam_heading_last_error(handle) if handle else L.trajam_last_error(None)).decode()
+        raise TrajamError(st, f"{L.trajam_status_string(st).decode()}: {msg}")
+
+
+def trajam_heading_create(problem: HeadingProblem):
+    h = ctypes.c_void_p()
+    _hcheck(load().trajam_heading_create(ctypes.byref(problem), ctypes.byref(h)))
+    return h
+
+
+def trajam_heading_destroy(handle) -> None:
+    load().trajam_heading_destroy(handle)
+
+
+def trajam_heading_set_scene(handle, boundary, x_des, obstacles) -> None:
+    b = np.ascontiguousarray(boundary, dtype=np.float64).reshape(-1)
+    xd = np.ascontiguousarray(x_des, dtype=np.float64)
+    ob = np.ascontiguousarray(obstacles, dtype=np.float64).reshape(-1)
+    if b.size != 10:
+        raise ValueError("boundary needs 10 values")
+    _hcheck(load().trajam_heading_set_scene(handle, _dp(b), _dp(xd), _dp(ob) if ob.size else None), handle)
+
+
+def trajam_heading_project(handle, batch, state, lam, iters, res_trace, stream) -> None:
+    _hcheck(load().trajam_heading_project(handle, int(batch), state, lam, int(iters), res_trace, stream), handle)
+
+
+def make_heading_problem(degree, n_steps, horizon, v_max, a_max, rho, radii, n_obstacles, max_batch,
+                         precision="fp32") -> HeadingProblem:
+    p = HeadingProblem()
+    p.degree, p.n_steps = int(degree), int(n_steps)
+    p.horizon, p.v_max, p.a_max, p.rho = float(horizon), float(v_max), float(a_max), float(rho)
+    r = np.asarray(radii, dtype=np.float64).reshape(-1)
+    if not 1 <= r.size <= HEADING_MAX_CIRCLES:
+        raise ValueError("1..8 footprint circles")
+    p.n_circles = int(r.size)
+    for m, v in enumerate(r):
+        p.radii[m] = float(v)
+    p.n_obstacles = int(n_obstacles)
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.max_batch = int(max_batch)
+    return p
+
+
+class HeadingSolver:
+    """One trajam_heading handle (Paper II's heading / multi-circle variant): the scene
+    is set from a HeadingWorkload; `project` runs Alg 2 in place on torch tensors
+    state, lam [B, 5, n_v] (rows x, c, y, s, psi)."""
+
+    def __init__(self, w, precision="fp32", max_batch=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("trajam needs a ROCm GPU; torch.cuda.is_available() is False")
+        self.problem = make_heading_problem(w.degree, w.n_steps, w.horizon, w.v_max, w.a_max, w.rho, w.radii,
+                                            w.n_obs, max_batch or max(w.batch, 1), precision)
+        self.dtype = torch.float64 if self.problem.precision == TRAJAM_FP64 else torch.float32
+        self.nv = w.degree + 1
+        self.handle = trajam_heading_create(self.problem)
+        self.set_scene(w)
+
+    def set_scene(self, w):
+        bnd = np.concatenate([np.asarray(w.boundary, dtype=np.float64).reshape(-1),
+                              np.asarray(w.boundary_psi, dtype=np.float64).reshape(-1)])
+        obs = np.concatenate([w.obs_centre, w.obs_vel, w.obs_axes], axis=1) if w.n_obs else np.zeros((0, 6))
+        trajam_heading_set_scene(self.handle, bnd, w.x_des, obs)
+
+    def project(self, state, lam, iters, res_trace=None):
+        import torch
+        for t in (state, lam) + ((res_trace,) if res_trace is not None else ()):
+            if t.dtype != self.dtype or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("contiguous device tensors of the solver's precision required")
+        B = state.shape[0]
+        if tuple(state.shape[1:]) != (5, self.nv) or lam.shape != state.shape:
+            raise ValueError("state and lam must be [B, 5, n_v]")
+        if res_trace is not None and tuple(res_trace.shape) != (int(iters), B, 2):
+            raise ValueError("res_trace must be [iters, B, 2]")
+        st = torch.cuda.current_stream().cuda_stream
+        trajam_heading_project(self.handle, B, state.data_ptr(), lam.data_ptr(), iters,
+                               res_trace.data_ptr() if res_trace is not None else None, st)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            trajam_heading_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
