@@ -626,6 +626,72 @@ def ragged_warm(args, ws, items, K, net_cfg2):
         rws.close()
     return res
 
+def heading_ops_per_unit(w) -> int:
+    """Algorithmic VALU lane-ops of one sample's iteration of the heading / multi-circle
+    variant, at the lower end of each element's cost: every (circle, obstacle, time)
+    row at 5 ops (two differences, a squared norm, a compare), the two kinematic rows
+    at 3 each and the two heading rows at 2 per time step, the evaluation of x, c, y, s,
+    psi and the derivatives (10 n_v FMAs per time step) and the contractions over time
+    (15 n_v), and both QP products; an FMA counts once."""
+    nv, npt = w.n_v, w.n_steps
+    nfx = 2 * nv - 4
+    per_t = w.n_circles * w.n_obs * 5 + 2 * 3 + 2 + 25 * nv
+    return npt * per_t + 2 * nfx * nfx + (nv - 2) ** 2
+
+
+def heading_bench(args):
+    """Paper II's setting for the heading / multi-circle variant: one control cycle of
+    10 iterations over 1000 samples in a crowd of 30 (4 footprint circles), FP32, HIP
+    events around the launch on the current stream; the per-iteration time over a grid
+    of circle and obstacle counts (the thesis's computation-time scaling figure); the
+    two residuals of the best sample (its convergence figure)."""
+    import torch
+    from paper_2408_10731_amd import trajam as tj
+    from paper_2408_10731_amd import workloads as wl
+
+    stream = torch.cuda.current_stream()
+    out = {"config": "Paper II crowd: 1000 samples, 30 people (semi-axes 0.55 m), 4 circles on a 1.2 m "
+                     "robot, degree 10, 100 steps over 20 s, 10 iterations a call, FP32"}
+
+    def timed(w, iters, reps):
+        s = tj.HeadingSolver(w, precision="fp32")
+        x0 = torch.as_tensor(w.xi0, dtype=torch.float32, device="cuda").contiguous()
+        st, lm = x0.clone(), torch.zeros_like(x0)
+
+        def call():
+            s.project(st, lm, iters)
+        ms = _time(call, reps, stream)
+        st.copy_(x0)
+        lm.zero_()
+        tr = torch.zeros((iters, w.batch, 2), dtype=torch.float32, device="cuda")
+        s.project(st, lm, iters, tr)
+        torch.cuda.synchronize()
+        s.close()
+        return ms, tr.cpu().numpy()
+
+    w = wl.heading_scene(20_001, n_obs=30, n_circles=4, batch=1000, flow="static")
+    ms, tr = timed(w, 10, args.heading_reps)
+    ops = w.batch * 10 * heading_ops_per_unit(w)
+    out["ms_per_call"] = ms
+    out["ms_per_iteration"] = ms / 10
+    out["traj_iters_per_s"] = w.batch * 10 / (ms * 1e-3)
+    out["roofline"] = {"bound": "alu", "achieved": ops / (ms * 1e-3) / 1e12, "peak": PEAK_VALU_OPS / 1e12,
+                       "unit": "Tlane-ops/s", "frac": ops / (ms * 1e-3) / PEAK_VALU_OPS,
+                       "ops_per_unit": heading_ops_per_unit(w)}
+    _, tr50 = timed(w, 50, 1)
+    best = int(np.argmin(tr50[-1, :, 0]))
+    out["best_sample_residuals"] = {f"iter_{k}": [float(tr50[k - 1, best, 0]), float(tr50[k - 1, best, 1])]
+                                    for k in (1, 5, 10, 20, 50)}
+    grid = {}
+    for nc in (1, 2, 4, 8):
+        for no in (10, 30, 50):
+            wg = wl.heading_scene(20_002, n_obs=no, n_circles=nc, batch=1000)
+            mg, _ = timed(wg, 10, max(3, args.heading_reps // 4))
+            grid[f"c{nc}_o{no}"] = mg / 10
+    out["ms_per_iteration_grid"] = grid
+    return out
+
+
 def agents_ops_per_unit(w) -> int:
     """Algorithmic VALU lane-ops of one joint sample's AM iteration in a multi-agent
     problem, at the lower end of each element's cost: every (agent, obstacle, time) and
@@ -1090,6 +1156,8 @@ def main():
     ap.add_argument("--probe-launch", default="1,1", help="internal: kernel,samples-per-workgroup")
     ap.add_argument("--probe-precision", choices=["fp32", "bf16"], default="fp32", help="internal")
     ap.add_argument("--ttr-cap", type=int, default=300)
+    ap.add_argument("--heading-reps", type=int, default=20,
+                    help="timed calls of the heading / multi-circle leg (0 skips it)")
     ap.add_argument("--ws-scenes", type=int, default=2048)
     ap.add_argument("--ws-epochs", type=int, default=20)
     ap.add_argument("--ragged-problems", type=int, default=256, help="0 skips the ragged set")
@@ -1184,6 +1252,7 @@ def main():
     warm4, net4 = ((warm_cfg4_bench(args) if args.ws4_scenes > 0 and args.cem_calls > 0 and args.ttr_cap > 0
                     else (None, None)))
     mpc_out = mpc_bench(args, net4) if args.mpc_cycles > 0 else None
+    heading_out = heading_bench(args) if args.heading_reps > 0 else None
     prec_out = precision_bench(args) if args.precision_steps > 0 else None
     polar_out = polar_bench(args) if args.polar_steps > 0 else None
     mfma_out = mfma_bench(args) if args.mfma_steps > 0 else None
@@ -1225,6 +1294,7 @@ def main():
         "matrix_cores": mfma_out,
         "warm_start_config4": warm4,
         "mpc": mpc_out,
+        "heading_multi_circle": heading_out,
         "wall_s_timed_region": h["wall"],
     }
     if not args.no_cpu:

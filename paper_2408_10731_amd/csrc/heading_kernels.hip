@@ -32,12 +32,57 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
 }
 
+// Sum over the wave, the same value in every lane: within each row of 16 lanes by DPP
+// (pairs, quads, half-row and row mirrors), then the four row sums read as scalars.
+template <int C>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), C, 0xF, 0xF, false));
+}
+template <int C>
+__device__ __forceinline__ double dpp(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), C, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), C, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_value(float v, int l)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp<0x141>(v);   // row_half_mirror
+    v += dpp<0x140>(v);   // row_mirror
+    return ((lane_value(v, 0) + lane_value(v, 16)) + lane_value(v, 32)) + lane_value(v, 48);
+}
+
+// (|w|, w / |w|) of w = (u, v), with (0, (1, 0)) at the origin (atan2(+0, +0) = 0).
+// FP32 through the hardware reciprocal square root; FP64 by division.
+__device__ __forceinline__ void norm_dir(float u, float v, float &rn, float &cu, float &sv)
+{
+    const float s2 = fmaf(u, u, v * v);
+    const float ri = s2 > 0.0f ? __builtin_amdgcn_rsqf(s2) : 0.0f;
+    rn = s2 * ri;
+    cu = s2 > 0.0f ? u * ri : 1.0f;
+    sv = v * ri;
+}
+__device__ __forceinline__ void norm_dir(double u, double v, double &rn, double &cu, double &sv)
+{
+    rn = sqrt(u * u + v * v);
+    cu = rn > 0.0 ? u / rn : 1.0;
+    sv = rn > 0.0 ? v / rn : 0.0;
 }
 
 __device__ __forceinline__ float unwrap_pi2(float) { return 6.28318530717958647692f; }
@@ -71,51 +116,66 @@ template <typename T>
 __device__ __forceinline__ void ball_row(T vx, T vy, T bound, T &ex, T &ey)
 {
     // target bound * min(1, |v| / bound) * (cos, sin)(atan2(vy, vx)); atan2(0, 0) = 0
-    const T n = sqrt(vx * vx + vy * vy);
-    const T d = n / bound < (T)1 ? n / bound : (T)1;
-    const T cx = n > (T)0 ? vx / n : (T)1;
-    const T sy = n > (T)0 ? vy / n : (T)0;
+    T n, cx, sy;
+    norm_dir(vx, vy, n, cx, sy);
+    const T d = n < bound ? n / bound : (T)1;
     ex = vx - bound * d * cx;
     ey = vy - bound * d * sy;
 }
 
+// The rows of a lane's two time steps together (two independent chains per obstacle).
 template <typename T>
-__device__ __forceinline__ Rows<T> polar_rows(const HeadingArgs &a, const Step<T> &p, T t, T cps, T sps)
+__device__ __forceinline__ void polar_rows2(const HeadingArgs &a, const Step<T> *p, const T *t, const T *cps,
+                                            const T *sps, const bool *on, Rows<T> *r)
 {
-    Rows<T> r{};
     const T *ob = (const T *)a.obs;
-    for (int m = 0; m < a.n_circles; ++m) {
-        const T rm = (T)a.radii[m];
-        const T px = p.x + rm * cps, py = p.y + rm * sps;   // circle centre on the heading
-        const T fx = p.x + rm * p.c, fy = p.y + rm * p.s;   // the row value F xi (slack)
-        T sx = 0, sy = 0, q = 0;
-        for (int j = 0; j < a.n_obs; ++j) {
-            const T *o = ob + (size_t)j * 8;    // cx, cy, vx, vy, a, b, 1/a, 1/b
-            const T xo = fma(o[2], t, o[0]), yo = fma(o[3], t, o[1]);
-            const T u = (px - xo) * o[6], v = (py - yo) * o[7];
-            const T rn = sqrt(u * u + v * v);
-            const T d = rn > (T)1 ? rn : (T)1;
-            const T ca = rn > (T)0 ? u / rn : (T)1;
-            const T sa = rn > (T)0 ? v / rn : (T)0;
-            const T ex = fx - (xo + o[4] * d * ca);
-            const T ey = fy - (yo + o[5] * d * sa);
-            sx += ex;
-            sy += ey;
-            q = fma(ex, ex, fma(ey, ey, q));
+    T px[2][kHeadingMaxCircles], py[2][kHeadingMaxCircles];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        r[h] = Rows<T>{};
+#pragma unroll
+        for (int m = 0; m < kHeadingMaxCircles; ++m) {
+            const T rm = (T)a.radii[m];
+            px[h][m] = p[h].x + rm * cps[h];   // circle centre on the heading
+            py[h][m] = p[h].y + rm * sps[h];
         }
-        r.rx += sx;
-        r.ry += sy;
-        r.rc = fma(rm, sx, r.rc);
-        r.rs = fma(rm, sy, r.rs);
-        r.sq += q;
     }
-    const T ec = p.c - cps, es = p.s - sps;
-    r.rc += ec;
-    r.rs += es;
-    ball_row(p.vx, p.vy, (T)a.v_max, r.evx, r.evy);
-    ball_row(p.ax, p.ay, (T)a.a_max, r.eax, r.eay);
-    r.sq += ec * ec + es * es + r.evx * r.evx + r.evy * r.evy + r.eax * r.eax + r.eay * r.eay;
-    return r;
+    for (int j = 0; j < a.n_obs; ++j) {
+        const T *o = ob + (size_t)j * 8;    // cx, cy, vx, vy, a, b, 1/a, 1/b
+#pragma unroll
+        for (int m = 0; m < kHeadingMaxCircles; ++m) {
+            if (m < a.n_circles) {   // uniform
+                const T rm = (T)a.radii[m];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const T xo = fma(o[2], t[h], o[0]), yo = fma(o[3], t[h], o[1]);
+                    const T u = (px[h][m] - xo) * o[6], v = (py[h][m] - yo) * o[7];
+                    T rn, ca, sa;
+                    norm_dir(u, v, rn, ca, sa);
+                    const T d = rn > (T)1 ? rn : (T)1;
+                    // the row value F xi uses the slack: x + r_m c, y + r_m s
+                    const T ex = fma(rm, p[h].c, p[h].x) - (xo + o[4] * d * ca);
+                    const T ey = fma(rm, p[h].s, p[h].y) - (yo + o[5] * d * sa);
+                    r[h].rx += ex;
+                    r[h].ry += ey;
+                    r[h].rc = fma(rm, ex, r[h].rc);
+                    r[h].rs = fma(rm, ey, r[h].rs);
+                    r[h].sq = fma(ex, ex, fma(ey, ey, r[h].sq));
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const T ec = p[h].c - cps[h], es = p[h].s - sps[h];
+        r[h].rc += ec;
+        r[h].rs += es;
+        ball_row(p[h].vx, p[h].vy, (T)a.v_max, r[h].evx, r[h].evy);
+        ball_row(p[h].ax, p[h].ay, (T)a.a_max, r[h].eax, r[h].eay);
+        r[h].sq += ec * ec + es * es + r[h].evx * r[h].evx + r[h].evy * r[h].evy + r[h].eax * r[h].eax +
+                   r[h].eay * r[h].eay;
+        if (!on[h]) r[h] = Rows<T>{};
+    }
 }
 
 template <typename T>
@@ -204,17 +264,9 @@ __global__ __launch_bounds__(256) void heading_kernel(HeadingArgs a, int batch, 
     // Writes V = lam + T - rho F'(F xi - g) (position groups).
     T dpsi[2] = {0, 0};
     auto polar_and_contract = [&](bool update, int k_iter) {
-        T sq = 0, sq2 = 0;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            if (on[h]) {
-                rw[h] = polar_rows(a, st[h], tt[h], cps[h], sps[h]);
-                sq += rw[h].sq;
-                sq2 = fma(dpsi[h], dpsi[h], sq2);
-            } else {
-                rw[h] = Rows<T>{};
-            }
-        }
+        polar_rows2(a, st, tt, cps, sps, on, rw);
+        T sq = rw[0].sq + rw[1].sq;
+        T sq2 = fma(dpsi[0], dpsi[0], dpsi[1] * dpsi[1]);
 #pragma unroll
         for (int k = 0; k < kHV; ++k) {
             if (k >= nv) continue;   // uniform
