@@ -628,14 +628,17 @@ def ragged_warm(args, ws, items, K, net_cfg2):
 
 def heading_ops_per_unit(w) -> int:
     """Algorithmic VALU lane-ops of one sample's iteration of the heading / multi-circle
-    variant, at the lower end of each element's cost: every (circle, obstacle, time)
-    row at 5 ops (two differences, a squared norm, a compare), the two kinematic rows
-    at 3 each and the two heading rows at 2 per time step, the evaluation of x, c, y, s,
-    psi and the derivatives (10 n_v FMAs per time step) and the contractions over time
-    (15 n_v), and both QP products; an FMA counts once."""
+    variant.  Every (circle, obstacle, time) row enters F (no pair can be skipped), so
+    each takes the whole polar step: the obstacle's position (2), the offset and its
+    scaling (4), the norm, its reciprocal square root, the radius and d (5), the
+    direction (2), the target (4), the residual (2) and the sums F'(F xi - g) and
+    |F xi - g|^2 need (6): 25 ops.  The two kinematic rows take 12 each, the two heading
+    rows 4 (cos, sin, two residuals); per time step the evaluation of x, c, y, s, psi
+    and the derivatives (10 n_v FMAs) and the contractions over time (15 n_v); both QP
+    products once per sample.  An FMA counts once."""
     nv, npt = w.n_v, w.n_steps
     nfx = 2 * nv - 4
-    per_t = w.n_circles * w.n_obs * 5 + 2 * 3 + 2 + 25 * nv
+    per_t = w.n_circles * w.n_obs * 25 + 2 * 12 + 4 + 25 * nv
     return npt * per_t + 2 * nfx * nfx + (nv - 2) ** 2
 
 
