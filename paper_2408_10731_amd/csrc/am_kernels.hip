@@ -1640,9 +1640,12 @@ __global__ __launch_bounds__(kMaxThreads) void am_wave_kernel(AmArgs<T> a)
 // Polar step of every (agent, obstacle), kinematic bound and pair row at time t for
 // this lane's position p, velocity v, acceleration acc.  Adds the summed position
 // residual to S and the velocity / acceleration residuals to rv / ra.
-// px: this wave's LDS area of kAgentPosScalars for the agents' positions.
+// px: this wave's LDS area of kAgentPosScalars for the agents' positions.  The lane
+// serves agent `ag` of the half-wave `h` (h = 0 unless the wave's two halves take two
+// time steps of one joint sample: then lane = 32 h + ag and every exchange between
+// agents stays within the half).
 template <typename T, int D, typename A>
-__device__ __forceinline__ void agents_rows(const A &a, const T *ol, T *px, int lane, bool active, T tt,
+__device__ __forceinline__ void agents_rows(const A &a, const T *ol, T *px, int lane, int ag, int h, bool active, T tt,
                                             const T (&p)[D], const T (&v)[D], const T (&acc)[D], T (&S)[D],
                                             T (&rv)[D], T (&ra)[D], T &r2, T &rmax)
 {
@@ -1677,17 +1680,19 @@ __device__ __forceinline__ void agents_rows(const A &a, const T *ol, T *px, int 
     // keeps its own row.  Positions are published in LDS twice over (entries a and
     // a + N), so partner a + o needs no wrap, and read four offsets at a time.
     const T R = a.pair_r, R2 = R * R;
+    const int e0 = 64 * h + ag;   // this agent's entry in the half's table
     if (active) {
 #pragma unroll
         for (int ax = 0; ax < D; ++ax) {
-            px[4 * lane + ax] = p[ax];
-            px[4 * (lane + N) + ax] = p[ax];
+            px[4 * e0 + ax] = p[ax];
+            px[4 * (e0 + N) + ax] = p[ax];
         }
     }
     wave_lds_sync();
     const int half = N >> 1;
-    // lanes past N are inactive: they read entry lane + o < 128, whatever it holds
-    const T *pq = px + 4 * lane;
+    // agents past N are inactive: they read entry 64 h + ag + o < 128 (ag + o < 96 with
+    // one half, < 48 with two), whatever it holds
+    const T *pq = px + 4 * e0;
     for (int o0 = 1; o0 <= half; o0 += 4) {
         T x[4][D];
 #pragma unroll
@@ -1709,14 +1714,14 @@ __device__ __forceinline__ void agents_rows(const A &a, const T *ol, T *px, int 
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) r[ax] = T(0);
             if (near) {
-                const int b = lane + o < N ? lane + o : lane + o - N;
+                const int b = ag + o < N ? ag + o : ag + o - N;
                 if (nn > T(0)) {
                     const T f = T(1) - R * rsqrt_t(nn);
 #pragma unroll
                     for (int ax = 0; ax < D; ++ax) r[ax] = x[j][ax] * f;
                 } else {
                     // coincident agents: a fixed axis and the lane order give the direction
-                    r[D == 2 ? 0 : 2] = lane < b ? -R : R;
+                    r[D == 2 ? 0 : 2] = ag < b ? -R : R;
                 }
                 T rr = T(0);
 #pragma unroll
@@ -1725,13 +1730,13 @@ __device__ __forceinline__ void agents_rows(const A &a, const T *ol, T *px, int 
                     rr = fma(r[ax], r[ax], rr);
                     rmax = fmax(rmax, fabs(r[ax]));
                 }
-                if (!mid || lane < b) r2 += rr;
+                if (!mid || ag < b) r2 += rr;
             }
             if (!mid && __any(near)) {
                 // the lane whose partner at this offset is this lane
-                int src = lane - o;
+                int src = ag - o;
                 src = src < 0 ? src + N : src;
-                src = active ? src : lane;
+                src = active ? 32 * h + src : lane;
 #pragma unroll
                 for (int ax = 0; ax < D; ++ax) {
                     const T g = shfl_t<T>(r[ax], src);
@@ -1749,12 +1754,18 @@ __device__ __forceinline__ void agents_sample(const A &a, const int sample, cons
 {
     if (ol) stage_obstacles<T, D>(ol, a.obs, a.n_o, a.sphere, lane);
     const int N = a.n_agents, nv = a.nv, n_p = a.n_p;
-    const bool active = lane < N;
+    // N <= 32: the wave's halves take the even and the odd time steps of the sample
+    // (lane 32 h + ag serves agent ag at times 2 s + h); both halves hold the agent's
+    // whole state and apply the same QP step
+    const bool split = N <= 32;
+    const int h = split ? (lane >> 5) : 0;
+    const int ag = split ? (lane & 31) : lane;
+    const bool active = ag < N;
     const TRAJAM_CONST_AS T *phi = (const TRAJAM_CONST_AS T *)a.phi;
     const TRAJAM_CONST_AS T *W1 = (const TRAJAM_CONST_AS T *)a.W;
     const TRAJAM_CONST_AS T *W2 = (const TRAJAM_CONST_AS T *)a.W2;
     T xi[D][NVP], xb[D][NVP], lam[D][NVP], bnd[D][4];
-    const size_t base = ((size_t)sample * N + (active ? lane : 0)) * D * nv;
+    const size_t base = ((size_t)sample * N + (active ? ag : 0)) * D * nv;
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) {
 #pragma unroll
@@ -1765,7 +1776,7 @@ __device__ __forceinline__ void agents_sample(const A &a, const int sample, cons
             lam[ax][m] = real ? a.lam[base + ax * nv + m] : T(0);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bnd[ax][i] = active ? a.xiB_ag[((active ? lane : 0) * D + ax) * 4 + i] : T(0);
+        for (int i = 0; i < 4; ++i) bnd[ax][i] = active ? a.xiB_ag[((active ? ag : 0) * D + ax) * 4 + i] : T(0);
     }
     T res_first = T(0), res_last = T(0);
     bool nonfinite = false;
@@ -1776,12 +1787,19 @@ __device__ __forceinline__ void agents_sample(const A &a, const int sample, cons
 #pragma unroll
             for (int m = 0; m < NVP; ++m) ftr[ax][m] = T(0);
         T r2 = T(0), rmax = T(0);
-        for (int t = 0; t < n_p; ++t) {
-            T ph[3][NVP];
+        for (int t0 = 0; t0 < n_p; t0 += split ? 2 : 1) {
+            const int t = t0 + h;
+            const bool on = active && t < n_p;
+            // basis rows of the wave's time steps (uniform: scalar loads, SGPR operands)
+            const int t1 = (split && t0 + 1 < n_p) ? t0 + 1 : t0;
+            T ph[3][NVP], pk[3][NVP];
 #pragma unroll
             for (int d = 0; d < 3; ++d)
 #pragma unroll
-                for (int m = 0; m < NVP; ++m) ph[d][m] = phi[(size_t)(d * n_p + t) * NVP + m];
+                for (int m = 0; m < NVP; ++m) {
+                    ph[d][m] = phi[(size_t)(d * n_p + t0) * NVP + m];
+                    pk[d][m] = phi[(size_t)(d * n_p + t1) * NVP + m];
+                }
             T p[D], v[D], acc[D];
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) {
@@ -1792,17 +1810,47 @@ __device__ __forceinline__ void agents_sample(const A &a, const int sample, cons
                     sv = fma(ph[1][m], xb[ax][m], sv);
                     sa = fma(ph[2][m], xb[ax][m], sa);
                 }
+                if (split) {   // the odd half's step
+                    T qp = T(0), qv = T(0), qa = T(0);
+#pragma unroll
+                    for (int m = 0; m < NVP; ++m) {
+                        qp = fma(pk[0][m], xb[ax][m], qp);
+                        qv = fma(pk[1][m], xb[ax][m], qv);
+                        qa = fma(pk[2][m], xb[ax][m], qa);
+                    }
+                    sp = h ? qp : sp;
+                    sv = h ? qv : sv;
+                    sa = h ? qa : sa;
+                }
                 p[ax] = sp;
                 v[ax] = sv;
                 acc[ax] = sa;
             }
             T S[D], rv[D], ra[D];
-            agents_rows<T, D, A>(a, ol, px, lane, active, T(t) * a.dt, p, v, acc, S, rv, ra, r2, rmax);
+            agents_rows<T, D, A>(a, ol, px, lane, ag, h, on, T(t) * a.dt, p, v, acc, S, rv, ra, r2, rmax);
+            if (split) {   // each half adds its own step's rows
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax) {
+                    const T s0 = h ? T(0) : S[ax], v0 = h ? T(0) : rv[ax], a0 = h ? T(0) : ra[ax];
+                    const T s1 = h ? S[ax] : T(0), v1 = h ? rv[ax] : T(0), a1 = h ? ra[ax] : T(0);
+#pragma unroll
+                    for (int m = 0; m < NVP; ++m)
+                        ftr[ax][m] = fma(ph[0][m], s0, fma(ph[1][m], v0, fma(ph[2][m], a0,
+                                     fma(pk[0][m], s1, fma(pk[1][m], v1, fma(pk[2][m], a1, ftr[ax][m]))))));
+                }
+            } else {
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+                    for (int m = 0; m < NVP; ++m)
+                        ftr[ax][m] = fma(ph[0][m], S[ax], fma(ph[1][m], rv[ax], fma(ph[2][m], ra[ax], ftr[ax][m])));
+            }
+        }
+        if (split) {   // F^T r over both halves' time steps, the same sum in both halves
 #pragma unroll
             for (int ax = 0; ax < D; ++ax)
 #pragma unroll
-                for (int m = 0; m < NVP; ++m)
-                    ftr[ax][m] = fma(ph[0][m], S[ax], fma(ph[1][m], rv[ax], fma(ph[2][m], ra[ax], ftr[ax][m])));
+                for (int m = 0; m < NVP; ++m) ftr[ax][m] += shfl_t<T>(ftr[ax][m], lane ^ 32);
         }
         const T r2w = wave_sum(r2);
         if (lane == 0) {
@@ -1833,7 +1881,7 @@ __device__ __forceinline__ void agents_sample(const A &a, const int sample, cons
         for (int ax = 0; ax < D; ++ax) {
             T um[NVP];
 #pragma unroll
-            for (int m = 0; m < NVP; ++m) um[m] = (m < nv) ? wave_sum(u[ax][m]) * invN : T(0);
+            for (int m = 0; m < NVP; ++m) um[m] = (m < nv) ? wave_sum(h ? T(0) : u[ax][m]) * invN : T(0);
 #pragma unroll
             for (int f = 0; f < NVP - 4; ++f) {
                 if (f < nv - 4) {
@@ -1854,7 +1902,7 @@ __device__ __forceinline__ void agents_sample(const A &a, const int sample, cons
             }
         }
     }
-    if (active) {
+    if (active && h == 0) {
 #pragma unroll
         for (int ax = 0; ax < D; ++ax)
 #pragma unroll
@@ -1907,7 +1955,7 @@ __device__ __forceinline__ void agents_residual(const A &a, const int sample, co
             acc[ax] = sa;
         }
         T S[D], rv[D], ra[D];
-        agents_rows<T, D, A>(a, ol, px, lane, active, T(t) * a.dt, p, v, acc, S, rv, ra, r2, rmax);
+        agents_rows<T, D, A>(a, ol, px, lane, lane, 0, active, T(t) * a.dt, p, v, acc, S, rv, ra, r2, rmax);
     }
     const T r2w = wave_sum(r2), mx = wave_max(rmax);
     if (lane == 0) {
