@@ -129,27 +129,23 @@ __device__ __forceinline__ void polar_rows2(const HeadingArgs &a, const Step<T> 
                                             const T *sps, const bool *on, Rows<T> *r)
 {
     const T *ob = (const T *)a.obs;
-    T px[2][kHeadingMaxCircles], py[2][kHeadingMaxCircles];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        r[h] = Rows<T>{};
+    for (int h = 0; h < 2; ++h) r[h] = Rows<T>{};
+    for (int m = 0; m < a.n_circles; ++m) {
+        const T rm = (T)a.radii[m];
+        T px[2], py[2];
 #pragma unroll
-        for (int m = 0; m < kHeadingMaxCircles; ++m) {
-            const T rm = (T)a.radii[m];
-            px[h][m] = p[h].x + rm * cps[h];   // circle centre on the heading
-            py[h][m] = p[h].y + rm * sps[h];
+        for (int h = 0; h < 2; ++h) {
+            px[h] = p[h].x + rm * cps[h];   // circle centre on the heading
+            py[h] = p[h].y + rm * sps[h];
         }
-    }
-    for (int j = 0; j < a.n_obs; ++j) {
-        const T *o = ob + (size_t)j * 8;    // cx, cy, vx, vy, a, b, 1/a, 1/b
-#pragma unroll
-        for (int m = 0; m < kHeadingMaxCircles; ++m) {
-            if (m < a.n_circles) {   // uniform
-                const T rm = (T)a.radii[m];
+        for (int j = 0; j < a.n_obs; ++j) {
+            const T *o = ob + (size_t)j * 8;    // cx, cy, vx, vy, a, b, 1/a, 1/b
+            {
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const T xo = fma(o[2], t[h], o[0]), yo = fma(o[3], t[h], o[1]);
-                    const T u = (px[h][m] - xo) * o[6], v = (py[h][m] - yo) * o[7];
+                    const T u = (px[h] - xo) * o[6], v = (py[h] - yo) * o[7];
                     T rn, ca, sa;
                     norm_dir(u, v, rn, ca, sa);
                     const T d = rn > (T)1 ? rn : (T)1;
@@ -267,6 +263,8 @@ __global__ __launch_bounds__(256) void heading_kernel(HeadingArgs a, int batch, 
         polar_rows2(a, st, tt, cps, sps, on, rw);
         T sq = rw[0].sq + rw[1].sq;
         T sq2 = fma(dpsi[0], dpsi[0], dpsi[1] * dpsi[1]);
+        // lane k keeps coefficient k's sums (selects, no branch), then updates once
+        T cfx = 0, cfc = 0, cfy = 0, cfs = 0, ctx = 0, cty = 0, clp = 0;
 #pragma unroll
         for (int k = 0; k < kHV; ++k) {
             if (k >= nv) continue;   // uniform
@@ -291,19 +289,28 @@ __global__ __launch_bounds__(256) void heading_kernel(HeadingArgs a, int batch, 
             tx = wave_sum(tx);
             ty = wave_sum(ty);
             if (update) lp = wave_sum(lp);
-            if (lane == k) {
-                if (update) {
-                    LM[0][k] -= rho * fx;
-                    LM[1][k] -= rho * fc;
-                    LM[2][k] -= rho * fy;
-                    LM[3][k] -= rho * fs;
-                    LM[4][k] -= rho * lp;
-                }
-                V[0][k] = LM[0][k] + tx - rho * fx;
-                V[1][k] = LM[1][k] - rho * fc;
-                V[2][k] = LM[2][k] + ty - rho * fy;
-                V[3][k] = LM[3][k] - rho * fs;
+            const bool mine = lane == k;
+            cfx = mine ? fx : cfx;
+            cfc = mine ? fc : cfc;
+            cfy = mine ? fy : cfy;
+            cfs = mine ? fs : cfs;
+            ctx = mine ? tx : ctx;
+            cty = mine ? ty : cty;
+            clp = mine ? lp : clp;
+        }
+        if (lane < nv) {
+            const int k = lane;
+            if (update) {
+                LM[0][k] -= rho * cfx;
+                LM[1][k] -= rho * cfc;
+                LM[2][k] -= rho * cfy;
+                LM[3][k] -= rho * cfs;
+                LM[4][k] -= rho * clp;
             }
+            V[0][k] = LM[0][k] + ctx - rho * cfx;
+            V[1][k] = LM[1][k] - rho * cfc;
+            V[2][k] = LM[2][k] + cty - rho * cfy;
+            V[3][k] = LM[3][k] - rho * cfs;
         }
         if (trace && update) {
             sq = wave_sum(sq);
@@ -320,18 +327,30 @@ __global__ __launch_bounds__(256) void heading_kernel(HeadingArgs a, int batch, 
     eval_psi();
     polar_and_contract(false, 0);
 
-    const T *W = (const T *)a.W;        // [kHF][kHF]: free x coefficients 3..n-1, then c 0..n
-    const T *Wp = (const T *)a.Wpsi;    // [kHV][kHV]: free psi coefficients 1..n-1
+    // this lane's rows of both QP operators, held for the launch: W [kHF][kHF] (free x
+    // coefficients 3..n-1, then c 0..n; row lane & 31), W_psi [kHV][kHV] (free psi
+    // coefficients 1..n-1; row lane)
+    T wrow[kHF], wprow[kHV];
+    {
+        const T *W = (const T *)a.W;
+        const T *Wp = (const T *)a.Wpsi;
+        const int i = lane & 31;
+#pragma unroll
+        for (int j = 0; j < kHF; ++j) wrow[j] = (i < nfx && j < nfx) ? W[(size_t)i * kHF + j] : (T)0;
+#pragma unroll
+        for (int j = 0; j < kHV; ++j) wprow[j] = (lane < n - 1 && j < n - 1) ? Wp[(size_t)lane * kHV + j] : (T)0;
+    }
     const T two_pi = unwrap_pi2((T)0);
     for (int it = 0; it < iters; ++it) {
         // step 1: the position / slack QP of both groups (lanes 0..31: x, 32..63: y)
         {
             const int g = lane >> 5, i = lane & 31;
             T d = 0;
-            if (i < nfx) {
-                for (int j = 0; j < nfx; ++j) {
+#pragma unroll
+            for (int j = 0; j < kHF; ++j) {
+                if (j < nfx) {   // uniform
                     const T vj = j < nfp ? V[2 * g][3 + j] : V[2 * g + 1][j - nfp];
-                    d = fma(W[(size_t)i * kHF + j], vj, d);
+                    d = fma(wrow[j], vj, d);
                 }
             }
             wave_sync_lds();
@@ -343,7 +362,7 @@ __global__ __launch_bounds__(256) void heading_kernel(HeadingArgs a, int batch, 
         }
         // step 2: heading target and the surrogate QP
         eval_pos();
-        T pt[2];
+        T pt[2], cr = 0;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const T th = atan2(st[h].s, st[h].c);
@@ -357,14 +376,16 @@ __global__ __launch_bounds__(256) void heading_kernel(HeadingArgs a, int batch, 
                 for (int h = 0; h < 2; ++h)
                     if (on[h]) r = fma(-Pddr[h][k], st[h].psidd, fma(rho * Pr[h][k], pt[h] - st[h].psi, r));
                 r = wave_sum(r);
-                if (lane == k) V[4][k] = LM[4][k] + r;
+                cr = lane == k ? r : cr;
             }
         }
+        if (lane < nv) V[4][lane] = LM[4][lane] + cr;
         wave_sync_lds();
         {
             T d = 0;
-            if (lane < n - 1)
-                for (int j = 0; j < n - 1; ++j) d = fma(Wp[(size_t)lane * kHV + j], V[4][1 + j], d);
+#pragma unroll
+            for (int j = 0; j < kHV; ++j)
+                if (j < n - 1) d = fma(wprow[j], V[4][1 + j], d);   // zero rows past n - 2
             wave_sync_lds();
             if (lane < n - 1) XI[4][1 + lane] += d;
             wave_sync_lds();
