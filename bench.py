@@ -692,6 +692,17 @@ def heading_bench(args):
             mg, _ = timed(wg, 10, max(3, args.heading_reps // 4))
             grid[f"c{nc}_o{no}"] = mg / 10
     out["ms_per_iteration_grid"] = grid
+    # the thesis's batch sweep of its batch optimizer (batch 5 .. 1000; its GPU, JAX and
+    # obstacle count are not ours: context, not a target)
+    sweep = {}
+    for B in (5, 200, 400, 600, 800, 1000):
+        wb = wl.heading_scene(20_003, n_obs=30, n_circles=4, batch=B)
+        mb, _ = timed(wb, 10, max(3, args.heading_reps // 2))
+        sweep[str(B)] = mb / 10
+    out["ms_per_iteration_by_batch"] = sweep
+    out["thesis_ms_per_iteration_by_batch"] = {"5": 1.6, "200": 1.7, "400": 2.6, "600": 3.3, "800": 3.9, "1000": 4.5,
+                                               "note": "printed table of the thesis; GPU model not stated, Python + "
+                                                       "JAX, obstacle count not stated"}
     return out
 
 

@@ -4,7 +4,7 @@
 // x, c, y, s (c, s: slack copies of cos psi, sin psi) and psi, and the multipliers of
 // the same five rows.
 //
-// One wave64 per sample, time step t on lanes t and t - 64 (n_t <= 128).  Both QPs are
+// One workgroup of two wave64s per sample, time step t on thread t (n_t <= 128).  Both QPs are
 // applied in delta form: with A xi = b already met, the step is
 //     xi_f += W (lam + T(xi) - rho F'(F xi - g))_f
 // (W: the inverse of the free block of Q + rho F'F, T(xi) = P'(x_des - x) - Pdd'Pdd xi
@@ -13,8 +13,8 @@
 // whose right-hand sides are contractions over time of per-step residuals, small near
 // a fixed point, which keeps FP32 accurate.  F'(F xi - g) of the state after the polar
 // step is at once the multiplier update and the next position step's residual.
-// Coefficient vectors live in LDS (one slice per wave); the contractions over time are
-// wave reductions; every exchange between the lanes of a wave orders LDS only.
+// Coefficient vectors live in LDS; a contraction over time is a DPP sum in each wave,
+// the two waves' sums added in a fixed order after a workgroup barrier.
 #include <hip/hip_runtime.h>
 
 #include "am_internal.h"
@@ -123,228 +123,192 @@ __device__ __forceinline__ void ball_row(T vx, T vy, T bound, T &ex, T &ey)
     ey = vy - bound * d * sy;
 }
 
-// The rows of a lane's two time steps together (two independent chains per obstacle).
+// The rows of one time step.
 template <typename T>
-__device__ __forceinline__ void polar_rows2(const HeadingArgs &a, const Step<T> *p, const T *t, const T *cps,
-                                            const T *sps, const bool *on, Rows<T> *r)
+__device__ __forceinline__ Rows<T> polar_rows(const HeadingArgs &a, const Step<T> &p, T t, T cps, T sps)
 {
     const T *ob = (const T *)a.obs;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) r[h] = Rows<T>{};
+    Rows<T> r{};
     for (int m = 0; m < a.n_circles; ++m) {
         const T rm = (T)a.radii[m];
-        T px[2], py[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            px[h] = p[h].x + rm * cps[h];   // circle centre on the heading
-            py[h] = p[h].y + rm * sps[h];
-        }
+        const T px = p.x + rm * cps, py = p.y + rm * sps;   // circle centre on the heading
+        const T fx = fma(rm, p.c, p.x), fy = fma(rm, p.s, p.y);   // the row value F xi (slack)
         for (int j = 0; j < a.n_obs; ++j) {
             const T *o = ob + (size_t)j * 8;    // cx, cy, vx, vy, a, b, 1/a, 1/b
-            {
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const T xo = fma(o[2], t[h], o[0]), yo = fma(o[3], t[h], o[1]);
-                    const T u = (px[h] - xo) * o[6], v = (py[h] - yo) * o[7];
-                    T rn, ca, sa;
-                    norm_dir(u, v, rn, ca, sa);
-                    const T d = rn > (T)1 ? rn : (T)1;
-                    // the row value F xi uses the slack: x + r_m c, y + r_m s
-                    const T ex = fma(rm, p[h].c, p[h].x) - (xo + o[4] * d * ca);
-                    const T ey = fma(rm, p[h].s, p[h].y) - (yo + o[5] * d * sa);
-                    r[h].rx += ex;
-                    r[h].ry += ey;
-                    r[h].rc = fma(rm, ex, r[h].rc);
-                    r[h].rs = fma(rm, ey, r[h].rs);
-                    r[h].sq = fma(ex, ex, fma(ey, ey, r[h].sq));
-                }
-            }
+            const T xo = fma(o[2], t, o[0]), yo = fma(o[3], t, o[1]);
+            const T u = (px - xo) * o[6], v = (py - yo) * o[7];
+            T rn, ca, sa;
+            norm_dir(u, v, rn, ca, sa);
+            const T d = rn > (T)1 ? rn : (T)1;
+            const T ex = fx - (xo + o[4] * d * ca);
+            const T ey = fy - (yo + o[5] * d * sa);
+            r.rx += ex;
+            r.ry += ey;
+            r.rc = fma(rm, ex, r.rc);
+            r.rs = fma(rm, ey, r.rs);
+            r.sq = fma(ex, ex, fma(ey, ey, r.sq));
         }
     }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const T ec = p[h].c - cps[h], es = p[h].s - sps[h];
-        r[h].rc += ec;
-        r[h].rs += es;
-        ball_row(p[h].vx, p[h].vy, (T)a.v_max, r[h].evx, r[h].evy);
-        ball_row(p[h].ax, p[h].ay, (T)a.a_max, r[h].eax, r[h].eay);
-        r[h].sq += ec * ec + es * es + r[h].evx * r[h].evx + r[h].evy * r[h].evy + r[h].eax * r[h].eax +
-                   r[h].eay * r[h].eay;
-        if (!on[h]) r[h] = Rows<T>{};
-    }
+    const T ec = p.c - cps, es = p.s - sps;
+    r.rc += ec;
+    r.rs += es;
+    ball_row(p.vx, p.vy, (T)a.v_max, r.evx, r.evy);
+    ball_row(p.ax, p.ay, (T)a.a_max, r.eax, r.eay);
+    r.sq += ec * ec + es * es + r.evx * r.evx + r.evy * r.evy + r.eax * r.eax + r.eay * r.eay;
+    return r;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void heading_kernel(HeadingArgs a, int batch, int iters, T *state, T *lam,
-                                                      T *trace)
+__device__ __forceinline__ void block_sync_lds()
 {
-    __shared__ T lds[4][3][5][kHV];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int b = blockIdx.x * 4 + wave;
-    if (b >= batch) return;   // whole wave; no workgroup barrier below
-    T(*XI)[kHV] = lds[wave][0];
-    T(*LM)[kHV] = lds[wave][1];
-    T(*V)[kHV] = lds[wave][2];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+constexpr int kHThreads = 128;   // two waves, one time step each thread
+constexpr int kParts = 8;        // contraction vectors per wave (7 used by the polar step, 1 by psi)
+
+template <typename T>
+__global__ __launch_bounds__(kHThreads) void heading_kernel(HeadingArgs a, int iters, int batch, T *state, T *lam,
+                                                            T *trace)
+{
+    __shared__ T XI[5][kHV], LM[5][kHV], V[5][kHV];
+    __shared__ T part[2][kParts][kHV];   // per wave: the sums its lanes k captured
+    __shared__ T red[2][2];              // per wave: the squared residuals
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int b = blockIdx.x;            // the grid is the batch: no workgroup leaves early
     const int nv = a.nv, nt = a.n_steps, n = nv - 1, nfp = nv - 4, nfx = 2 * nv - 4;
     const T rho = (T)a.rho;
     const T *phi = (const T *)a.phi;      // [3][n_t][kHV]: P, Pd, Pdd
     const T *xdes = (const T *)a.x_des;   // [2][n_t]
 
-    for (int i = lane; i < 5 * kHV; i += 64) {
-        const int r = i / kHV, k = i % kHV;
+    if (tid < 5 * kHV) {
+        const int r = tid / kHV, k = tid % kHV;
         XI[r][k] = k < nv ? state[((size_t)b * 5 + r) * nv + k] : (T)0;
         LM[r][k] = k < nv ? lam[((size_t)b * 5 + r) * nv + k] : (T)0;
         V[r][k] = 0;
     }
-    wave_sync_lds();
+    block_sync_lds();
     // the boundary rows fix coefficients 0, 1, 2, n of x and y and 0, n of psi
-    if (lane < 2) {
-        XI[2 * lane][0] = (T)a.bcoef[lane][0];
-        XI[2 * lane][1] = (T)a.bcoef[lane][1];
-        XI[2 * lane][2] = (T)a.bcoef[lane][2];
-        XI[2 * lane][n] = (T)a.bcoef[lane][3];
-    } else if (lane == 2) {
+    if (tid < 2) {
+        XI[2 * tid][0] = (T)a.bcoef[tid][0];
+        XI[2 * tid][1] = (T)a.bcoef[tid][1];
+        XI[2 * tid][2] = (T)a.bcoef[tid][2];
+        XI[2 * tid][n] = (T)a.bcoef[tid][3];
+    } else if (tid == 2) {
         XI[4][0] = (T)a.bpsi[0];
         XI[4][n] = (T)a.bpsi[1];
     }
-    wave_sync_lds();
+    block_sync_lds();
 
-    // basis rows of this lane's (up to) two time steps
-    T Pr[2][kHV], Pdr[2][kHV], Pddr[2][kHV], tt[2], xd[2], yd[2];
-    bool on[2];
+    // this thread's time step and basis rows
+    const bool on = tid < nt;
+    const int tc = on ? tid : 0;
+    T Pr[kHV], Pdr[kHV], Pddr[kHV];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int t = lane + 64 * h;
-        on[h] = t < nt;
-        const int tc = on[h] ? t : 0;
-#pragma unroll
-        for (int k = 0; k < kHV; ++k) {
-            Pr[h][k] = on[h] ? phi[((size_t)0 * nt + tc) * kHV + k] : (T)0;
-            Pdr[h][k] = on[h] ? phi[((size_t)1 * nt + tc) * kHV + k] : (T)0;
-            Pddr[h][k] = on[h] ? phi[((size_t)2 * nt + tc) * kHV + k] : (T)0;
-        }
-        tt[h] = (T)a.dt * (T)tc;
-        xd[h] = on[h] ? xdes[tc] : (T)0;
-        yd[h] = on[h] ? xdes[nt + tc] : (T)0;
+    for (int k = 0; k < kHV; ++k) {
+        Pr[k] = on ? phi[((size_t)0 * nt + tc) * kHV + k] : (T)0;
+        Pdr[k] = on ? phi[((size_t)1 * nt + tc) * kHV + k] : (T)0;
+        Pddr[k] = on ? phi[((size_t)2 * nt + tc) * kHV + k] : (T)0;
     }
-
-    Step<T> st[2];
-    Rows<T> rw[2];
-    T cps[2], sps[2];
-
-    auto eval_pos = [&]() {
+    const T tt = (T)a.dt * (T)tc;
+    const T xd = on ? xdes[tc] : (T)0, yd = on ? xdes[nt + tc] : (T)0;
+    // this thread's rows of the QP operators, held for the launch: W [kHF][kHF] (free x
+    // coefficients 3..n-1, then c 0..n; wave g applies group g, row lane), W_psi
+    // [kHV][kHV] (free psi coefficients 1..n-1; wave 0, row lane)
+    T wrow[kHF], wprow[kHV];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            st[h].x = dot_row(Pr[h], XI[0], nv);
-            st[h].c = dot_row(Pr[h], XI[1], nv);
-            st[h].y = dot_row(Pr[h], XI[2], nv);
-            st[h].s = dot_row(Pr[h], XI[3], nv);
-            st[h].vx = dot_row(Pdr[h], XI[0], nv);
-            st[h].vy = dot_row(Pdr[h], XI[2], nv);
-            st[h].ax = dot_row(Pddr[h], XI[0], nv);
-            st[h].ay = dot_row(Pddr[h], XI[2], nv);
-        }
+    for (int j = 0; j < kHF; ++j)
+        wrow[j] = (lane < nfx && j < nfx) ? ((const T *)a.W)[(size_t)lane * kHF + j] : (T)0;
+#pragma unroll
+    for (int j = 0; j < kHV; ++j)
+        wprow[j] = (wave == 0 && lane < n - 1 && j < n - 1) ? ((const T *)a.Wpsi)[(size_t)lane * kHV + j] : (T)0;
+
+    Step<T> st;
+    T cps = 1, sps = 0, dpsi = 0;
+    auto eval_pos = [&]() {
+        st.x = dot_row(Pr, XI[0], nv);
+        st.c = dot_row(Pr, XI[1], nv);
+        st.y = dot_row(Pr, XI[2], nv);
+        st.s = dot_row(Pr, XI[3], nv);
+        st.vx = dot_row(Pdr, XI[0], nv);
+        st.vy = dot_row(Pdr, XI[2], nv);
+        st.ax = dot_row(Pddr, XI[0], nv);
+        st.ay = dot_row(Pddr, XI[2], nv);
     };
     auto eval_psi = [&]() {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            st[h].psi = dot_row(Pr[h], XI[4], nv);
-            st[h].psidd = dot_row(Pddr[h], XI[4], nv);
-            cps[h] = cos(st[h].psi);
-            sps[h] = sin(st[h].psi);
-        }
+        st.psi = dot_row(Pr, XI[4], nv);
+        st.psidd = dot_row(Pddr, XI[4], nv);
+        cps = cos(st.psi);
+        sps = sin(st.psi);
     };
     // polar step at the current state, then per coefficient k the contractions
-    // F'(F xi - g) of both groups and the tracking terms; lane k keeps coefficient k.
-    // With `update`, also lam -= rho F'(F xi - g) and lam_psi -= rho P'(psi - psi_t).
-    // Writes V = lam + T - rho F'(F xi - g) (position groups).
-    T dpsi[2] = {0, 0};
+    // F'(F xi - g) of both groups and the tracking terms (lane k of each wave keeps its
+    // wave's sums of coefficient k; thread k adds the two waves').  With `update`, also
+    // lam -= rho F'(F xi - g) and lam_psi -= rho P'(psi - psi_t).  Writes
+    // V = lam + T - rho F'(F xi - g) of the position groups.
     auto polar_and_contract = [&](bool update, int k_iter) {
-        polar_rows2(a, st, tt, cps, sps, on, rw);
-        T sq = rw[0].sq + rw[1].sq;
-        T sq2 = fma(dpsi[0], dpsi[0], dpsi[1] * dpsi[1]);
-        // lane k keeps coefficient k's sums (selects, no branch), then updates once
-        T cfx = 0, cfc = 0, cfy = 0, cfs = 0, ctx = 0, cty = 0, clp = 0;
+        Rows<T> rw = on ? polar_rows(a, st, tt, cps, sps) : Rows<T>{};
+        T c[7] = {0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < kHV; ++k) {
             if (k >= nv) continue;   // uniform
-            T fx = 0, fc = 0, fy = 0, fs = 0, tx = 0, ty = 0, lp = 0;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const T p = Pr[h][k], pd = Pdr[h][k], pdd = Pddr[h][k];
-                fx = fma(p, rw[h].rx, fma(pd, rw[h].evx, fma(pdd, rw[h].eax, fx)));
-                fy = fma(p, rw[h].ry, fma(pd, rw[h].evy, fma(pdd, rw[h].eay, fy)));
-                fc = fma(p, rw[h].rc, fc);
-                fs = fma(p, rw[h].rs, fs);
-                if (on[h]) {
-                    tx = fma(p, xd[h] - st[h].x, fma(-pdd, st[h].ax, tx));
-                    ty = fma(p, yd[h] - st[h].y, fma(-pdd, st[h].ay, ty));
-                }
-                lp = fma(p, dpsi[h], lp);
-            }
-            fx = wave_sum(fx);
-            fc = wave_sum(fc);
-            fy = wave_sum(fy);
-            fs = wave_sum(fs);
-            tx = wave_sum(tx);
-            ty = wave_sum(ty);
-            if (update) lp = wave_sum(lp);
+            const T p = Pr[k], pd = Pdr[k], pdd = Pddr[k];
+            T f[7];
+            f[0] = wave_sum(fma(p, rw.rx, fma(pd, rw.evx, pdd * rw.eax)));
+            f[1] = wave_sum(p * rw.rc);
+            f[2] = wave_sum(fma(p, rw.ry, fma(pd, rw.evy, pdd * rw.eay)));
+            f[3] = wave_sum(p * rw.rs);
+            f[4] = wave_sum(on ? fma(p, xd - st.x, -pdd * st.ax) : (T)0);
+            f[5] = wave_sum(on ? fma(p, yd - st.y, -pdd * st.ay) : (T)0);
+            f[6] = update ? wave_sum(p * dpsi) : (T)0;
             const bool mine = lane == k;
-            cfx = mine ? fx : cfx;
-            cfc = mine ? fc : cfc;
-            cfy = mine ? fy : cfy;
-            cfs = mine ? fs : cfs;
-            ctx = mine ? tx : ctx;
-            cty = mine ? ty : cty;
-            clp = mine ? lp : clp;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) c[q] = mine ? f[q] : c[q];
         }
         if (lane < nv) {
-            const int k = lane;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) part[wave][q][lane] = c[q];
+        }
+        const T sq = wave_sum(rw.sq), sq2 = wave_sum(dpsi * dpsi);
+        if (lane == 0) {
+            red[wave][0] = sq;
+            red[wave][1] = sq2;
+        }
+        block_sync_lds();
+        if (tid < nv) {
+            const int k = tid;
+            T s[7];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) s[q] = part[0][q][k] + part[1][q][k];
             if (update) {
-                LM[0][k] -= rho * cfx;
-                LM[1][k] -= rho * cfc;
-                LM[2][k] -= rho * cfy;
-                LM[3][k] -= rho * cfs;
-                LM[4][k] -= rho * clp;
+                LM[0][k] -= rho * s[0];
+                LM[1][k] -= rho * s[1];
+                LM[2][k] -= rho * s[2];
+                LM[3][k] -= rho * s[3];
+                LM[4][k] -= rho * s[6];
             }
-            V[0][k] = LM[0][k] + ctx - rho * cfx;
-            V[1][k] = LM[1][k] - rho * cfc;
-            V[2][k] = LM[2][k] + cty - rho * cfy;
-            V[3][k] = LM[3][k] - rho * cfs;
+            V[0][k] = LM[0][k] + s[4] - rho * s[0];
+            V[1][k] = LM[1][k] - rho * s[1];
+            V[2][k] = LM[2][k] + s[5] - rho * s[2];
+            V[3][k] = LM[3][k] - rho * s[3];
         }
-        if (trace && update) {
-            sq = wave_sum(sq);
-            sq2 = wave_sum(sq2);
-            if (lane == 0) {
-                trace[((size_t)k_iter * batch + b) * 2 + 0] = sqrt(sq);
-                trace[((size_t)k_iter * batch + b) * 2 + 1] = sqrt(sq2);
-            }
+        if (trace && update && tid == 0) {
+            trace[((size_t)k_iter * batch + b) * 2 + 0] = sqrt(red[0][0] + red[1][0]);
+            trace[((size_t)k_iter * batch + b) * 2 + 1] = sqrt(red[0][1] + red[1][1]);
         }
-        wave_sync_lds();
+        block_sync_lds();
     };
 
     eval_pos();
     eval_psi();
     polar_and_contract(false, 0);
 
-    // this lane's rows of both QP operators, held for the launch: W [kHF][kHF] (free x
-    // coefficients 3..n-1, then c 0..n; row lane & 31), W_psi [kHV][kHV] (free psi
-    // coefficients 1..n-1; row lane)
-    T wrow[kHF], wprow[kHV];
-    {
-        const T *W = (const T *)a.W;
-        const T *Wp = (const T *)a.Wpsi;
-        const int i = lane & 31;
-#pragma unroll
-        for (int j = 0; j < kHF; ++j) wrow[j] = (i < nfx && j < nfx) ? W[(size_t)i * kHF + j] : (T)0;
-#pragma unroll
-        for (int j = 0; j < kHV; ++j) wprow[j] = (lane < n - 1 && j < n - 1) ? Wp[(size_t)lane * kHV + j] : (T)0;
-    }
     const T two_pi = unwrap_pi2((T)0);
     for (int it = 0; it < iters; ++it) {
-        // step 1: the position / slack QP of both groups (lanes 0..31: x, 32..63: y)
+        // step 1: the position / slack QP (wave 0: group x, wave 1: group y)
         {
-            const int g = lane >> 5, i = lane & 31;
+            const int g = wave;
             T d = 0;
 #pragma unroll
             for (int j = 0; j < kHF; ++j) {
@@ -353,52 +317,47 @@ __global__ __launch_bounds__(256) void heading_kernel(HeadingArgs a, int batch, 
                     d = fma(wrow[j], vj, d);
                 }
             }
-            wave_sync_lds();
-            if (i < nfx) {
-                if (i < nfp) XI[2 * g][3 + i] += d;
-                else XI[2 * g + 1][i - nfp] += d;
+            if (lane < nfx) {
+                if (lane < nfp) XI[2 * g][3 + lane] += d;
+                else XI[2 * g + 1][lane - nfp] += d;
             }
-            wave_sync_lds();
+            block_sync_lds();
         }
         // step 2: heading target and the surrogate QP
         eval_pos();
-        T pt[2], cr = 0;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const T th = atan2(st[h].s, st[h].c);
-            pt[h] = on[h] ? th + two_pi * rint((st[h].psi - th) / two_pi) : (T)0;
-        }
-#pragma unroll
-        for (int k = 0; k < kHV; ++k) {
-            if (k < nv) {   // uniform
-                T r = 0;
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-                    if (on[h]) r = fma(-Pddr[h][k], st[h].psidd, fma(rho * Pr[h][k], pt[h] - st[h].psi, r));
-                r = wave_sum(r);
-                cr = lane == k ? r : cr;
-            }
-        }
-        if (lane < nv) V[4][lane] = LM[4][lane] + cr;
-        wave_sync_lds();
+        const T th = atan2(st.s, st.c);
+        const T pt = on ? th + two_pi * rint((st.psi - th) / two_pi) : (T)0;
         {
-            T d = 0;
+            T c = 0;
 #pragma unroll
-            for (int j = 0; j < kHV; ++j)
-                if (j < n - 1) d = fma(wprow[j], V[4][1 + j], d);   // zero rows past n - 2
-            wave_sync_lds();
-            if (lane < n - 1) XI[4][1 + lane] += d;
-            wave_sync_lds();
+            for (int k = 0; k < kHV; ++k) {
+                if (k < nv) {   // uniform
+                    const T r = wave_sum(on ? fma(-Pddr[k], st.psidd, rho * Pr[k] * (pt - st.psi)) : (T)0);
+                    c = lane == k ? r : c;
+                }
+            }
+            if (lane < nv) part[wave][7][lane] = c;
+            block_sync_lds();
+            if (wave == 0) {
+                T d = 0;
+#pragma unroll
+                for (int j = 0; j < kHV; ++j)
+                    if (j < n - 1) {   // zero rows past n - 2
+                        const T vj = LM[4][1 + j] + part[0][7][1 + j] + part[1][7][1 + j];
+                        d = fma(wprow[j], vj, d);
+                    }
+                if (lane < n - 1) XI[4][1 + lane] += d;
+            }
+            block_sync_lds();
         }
         eval_psi();
-#pragma unroll
-        for (int h = 0; h < 2; ++h) dpsi[h] = on[h] ? st[h].psi - pt[h] : (T)0;
+        dpsi = on ? st.psi - pt : (T)0;
         // steps 3-5: polar step at the new state, multipliers, the next step's residual
         polar_and_contract(true, it);
     }
 
-    for (int i = lane; i < 5 * nv; i += 64) {
-        const int r = i / nv, k = i % nv;
+    if (tid < 5 * nv) {
+        const int r = tid / nv, k = tid % nv;
         state[((size_t)b * 5 + r) * nv + k] = XI[r][k];
         lam[((size_t)b * 5 + r) * nv + k] = LM[r][k];
     }
@@ -410,12 +369,12 @@ hipError_t launch_heading(bool fp64, const HeadingArgs &a, int batch, int iters,
                           void *trace, hipStream_t st)
 {
     if (batch <= 0) return hipSuccess;
-    const dim3 grid((batch + 3) / 4), block(256);
+    const dim3 grid(batch), block(kHThreads);
     if (fp64)
-        heading_kernel<double><<<grid, block, 0, st>>>(a, batch, iters, (double *)state, (double *)lam,
+        heading_kernel<double><<<grid, block, 0, st>>>(a, iters, batch, (double *)state, (double *)lam,
                                                         (double *)trace);
     else
-        heading_kernel<float><<<grid, block, 0, st>>>(a, batch, iters, (float *)state, (float *)lam,
+        heading_kernel<float><<<grid, block, 0, st>>>(a, iters, batch, (float *)state, (float *)lam,
                                                       (float *)trace);
     return hipGetLastError();
 }
