@@ -706,6 +706,58 @@ def heading_bench(args):
     return out
 
 
+def heading_mpc_bench(args, delta=0.5, iters=10, horizon_s=20.0):
+    """Paper II's MPC over batch sizes (its batch-size table, on synthetic crowds): per
+    batch size, the same scenes (static crowd of 30, 4 circles, seeds 21,001 ..), the
+    robot executing delta = 0.5 s of the chosen sample each control cycle (10 AM
+    iterations, multipliers carried over) for 20 s.  A run succeeds when no footprint
+    circle of the executed motion (checked every 0.05 s) enters a person's ellipse.
+    Reports the success rate, the tracking error against the desired line and the
+    acceleration of the executed motion, and the time per cycle, for next samples moved
+    on from the cycle's results and for samples drawn afresh each cycle."""
+    from paper_2408_10731_amd import mpc as mp
+    from paper_2408_10731_amd import workloads as wl
+
+    n_cyc = int(round(horizon_s / delta))
+    seeds = list(range(21_001, 21_001 + args.heading_mpc_scenes))
+    out = {"config": f"static crowd of 30, 4 circles, {len(seeds)} scenes, {n_cyc} cycles of {delta} s, "
+                     f"{iters} iterations a cycle, FP32, multipliers carried over",
+           "by_batch": {}}
+    ts = np.linspace(0.0, delta, 11)[:-1]
+    for mode, B in [("moved_on", b) for b in (1, 200, 1000)] + [("redrawn", b) for b in (1, 50, 200, 1000)]:
+        ok_runs, errs, accs, cyc_ms = 0, [], [], []
+        for sd in seeds:
+            w = wl.heading_scene(sd, n_obs=30, n_circles=4, batch=B, flow="static")
+            m = mp.HeadingMPC(w, iters, delta, redraw_seed=(sd + 7) if mode == "redrawn" else None)
+            ok = True
+            t0 = time.perf_counter()
+            for c in range(n_cyc):
+                o = m.cycle()
+                coef, centre = o["coefficients"], o["obs_centre"]
+                for t in ts:
+                    p, _, a = mp.trajectory_state(coef[[0, 2]], w.horizon, t)
+                    psi = float(mp.trajectory_state(coef[[4]], w.horizon, t)[0][0])
+                    oc = centre + w.obs_vel * t
+                    for r in w.radii:
+                        q = p + r * np.array([np.cos(psi), np.sin(psi)])
+                        if np.any(np.sum(((q[None] - oc) / w.obs_axes) ** 2, axis=1) < 1.0):
+                            ok = False
+                    tk = c * delta + t
+                    line = w.x_des[:, 0] + (w.x_des[:, -1] - w.x_des[:, 0]) * min(1.0, tk / w.horizon)
+                    errs.append(float(np.linalg.norm(p - line)))
+                    accs.append(float(np.linalg.norm(a)))
+            cyc_ms.append(1e3 * (time.perf_counter() - t0) / n_cyc)
+            ok_runs += ok
+            m.close()
+        out["by_batch"].setdefault(mode, {})[str(B)] = {"success_rate": ok_runs / len(seeds),
+                                   "tracking_error_m": [float(np.mean(errs)), float(np.max(errs)), float(np.min(errs))],
+                                   "acceleration": [float(np.mean(accs)), float(np.max(accs)), float(np.min(accs))],
+                                   "ms_per_cycle": float(np.median(cyc_ms))}
+    out["thesis_success_rate_by_batch"] = {"1": 0.016, "200": 0.8, "400": 0.88, "600": 0.9, "800": 0.95, "1000": 1.0,
+                                           "note": "printed table of the thesis; its simulator and crowds, not these"}
+    return out
+
+
 def agents_ops_per_unit(w) -> int:
     """Algorithmic VALU lane-ops of one joint sample's AM iteration in a multi-agent
     problem, at the lower end of each element's cost: every (agent, obstacle, time) and
@@ -1172,6 +1224,8 @@ def main():
     ap.add_argument("--ttr-cap", type=int, default=300)
     ap.add_argument("--heading-reps", type=int, default=20,
                     help="timed calls of the heading / multi-circle leg (0 skips it)")
+    ap.add_argument("--heading-mpc-scenes", type=int, default=20,
+                    help="crowd scenes of the heading variant's receding-horizon leg (0 skips it)")
     ap.add_argument("--ws-scenes", type=int, default=2048)
     ap.add_argument("--ws-epochs", type=int, default=20)
     ap.add_argument("--ragged-problems", type=int, default=256, help="0 skips the ragged set")
@@ -1267,6 +1321,8 @@ def main():
                     else (None, None)))
     mpc_out = mpc_bench(args, net4) if args.mpc_cycles > 0 else None
     heading_out = heading_bench(args) if args.heading_reps > 0 else None
+    if heading_out is not None and args.heading_mpc_scenes > 0:
+        heading_out["receding_horizon"] = heading_mpc_bench(args)
     prec_out = precision_bench(args) if args.precision_steps > 0 else None
     polar_out = polar_bench(args) if args.polar_steps > 0 else None
     mfma_out = mfma_bench(args) if args.mfma_steps > 0 else None

@@ -615,6 +615,17 @@ trajam_status trajam_heading_set_scene(trajam_heading *h, const double *boundary
 trajam_status trajam_heading_project(trajam_heading *h, int32_t batch, void *state, void *lambda, int32_t iters,
                                      void *res_trace, void *stream);
 
+/* Receding horizon for the heading variant (thesis ch. 5, Paper II, Implementation
+ * Details: each control cycle starts from the preceding one's solution, both
+ * multipliers included): every row of every sample of `state` (x, c, y, s, psi) is
+ * re-expressed, in place, on the window moved on by delta seconds (the same
+ * polynomial, S(delta) as for trajam_mpc_shift); lambda's rows are carried over
+ * unchanged (keep_lambda = 1) or cleared (0).  The next cycle's boundary rows, desired
+ * path and obstacles are the caller's (trajam_heading_set_scene).  Errors: INVALID,
+ * CAPACITY, DEVICE. */
+trajam_status trajam_heading_shift(trajam_heading *h, int32_t batch, double delta, int32_t keep_lambda, void *state,
+                                   void *lambda, void *stream);
+
 /* Static description of a status code.  Never NULL. */
 const char *trajam_status_string(trajam_status st);
 

@@ -230,3 +230,56 @@ def residuals(w, state):
         fx, fy = group_rows(ops, xi)
         out[i] = np.sqrt(np.sum((fx - gx) ** 2) + np.sum((fy - gy) ** 2))
     return out
+
+
+@dataclasses.dataclass
+class Cycle:
+    state: np.ndarray     # [B, 5, n_v] the cycle's starting state
+    result: np.ndarray    # [B, 5, n_v] after K iterations
+    lam: np.ndarray       # [B, 5, n_v]
+    trace: np.ndarray     # [K, B, 2]
+    boundary: np.ndarray  # [2, 4] the cycle's boundary rows of x and y
+    boundary_psi: np.ndarray
+    executed: int
+
+
+def mpc(w, n_cycles, delta, iters, keep_lambda=True, redraw_seed=None):
+    """Paper II's receding-horizon loop on the heading variant (Implementation Details:
+    each control cycle starts from the preceding one's solution, lam and lam_psi
+    included).  One cycle: Alg 2 for `iters` iterations; the executed sample is the one
+    of lowest final |F xi - g| at a 1e-6 resolution (ties: the lowest index); its
+    position, velocity, acceleration (x, y) and heading at delta become the next start
+    rows (the final rows stay); the obstacles move on by delta; the desired path is the
+    window `delta` later (workloads.desired_window, an input); every row of every sample
+    is re-expressed on the shifted window, xi_next = S(delta) xi per row, and the
+    multipliers are carried over or cleared.  Readings as in oracle/mpc.py.
+    redraw_seed: the next cycle's samples are drawn afresh instead (workloads.heading_samples
+    around the line from the new start to the goal, heading about the new start's, from
+    numpy's PCG64 seeded with redraw_seed; an input), the multipliers still carried over."""
+    from . import mpc as om
+    from paper_2408_10731_amd.workloads import desired_window, heading_samples
+    S = om.shift_matrix(w.degree, w.horizon, delta)
+    rng = np.random.Generator(np.random.PCG64(redraw_seed)) if redraw_seed is not None else None
+    st = np.array(w.xi0, dtype=np.float64)
+    lam = np.zeros_like(st)
+    bnd = np.array(w.boundary, dtype=np.float64)
+    bpsi = np.array(w.boundary_psi, dtype=np.float64)
+    centre = np.array(w.obs_centre, dtype=np.float64)
+    out = []
+    for c in range(n_cycles):
+        wc = dataclasses.replace(w, xi0=st, boundary=bnd, boundary_psi=bpsi, obs_centre=centre,
+                                 x_des=desired_window(w, c * delta))
+        res, lam2, tr = iterate(wc, iters, state=st, lam=lam)
+        i = om.executed_sample(tr[-1, :, 0])
+        out.append(Cycle(st, res, lam2, tr, bnd, bpsi, i))
+        p, v, a = om.state_at(res[i][[0, 2]], w.horizon, delta)
+        psi = om.state_at(res[i][[4]], w.horizon, delta)[0][0]
+        bnd = bnd.copy()
+        bnd[:, 0], bnd[:, 1], bnd[:, 2] = p, v, a
+        bpsi = np.array([psi, bpsi[1]])
+        centre = centre + np.array(w.obs_vel, dtype=np.float64) * delta
+        st = np.einsum("jk,brk->brj", S, res)
+        if rng is not None:
+            st = heading_samples(rng, st.shape[0], bnd[:, 0], w.boundary[:, 3], w.degree, bpsi[0])
+        lam = lam2.copy() if keep_lambda else np.zeros_like(lam2)
+    return out

@@ -17,6 +17,7 @@ void host_basis(int n, int np, double T, std::vector<double> &P, std::vector<dou
 bool host_spd_inverse(int n, const std::vector<double> &A, std::vector<double> &Ainv);
 void host_boundary_coeffs(int n, double T, const double *b4, double *c4);
 void set_thread_error(const std::string &msg);
+void host_shift_matrix(int n, double d, double *S);
 }  // namespace trajam
 
 struct trajam_heading {
@@ -275,6 +276,27 @@ trajam_status trajam_heading_project(trajam_heading *h, int32_t batch, void *sta
     hipError_t e = trajam::launch_heading(h->prob.precision == TRAJAM_FP64, h->args, batch, iters, state, lambda,
                                           iters > 0 ? res_trace : nullptr, (hipStream_t)stream);
     if (e != hipSuccess) return hfail(h, TRAJAM_ERR_DEVICE, std::string("heading: ") + hipGetErrorString(e));
+    return TRAJAM_OK;
+}
+
+trajam_status trajam_heading_shift(trajam_heading *h, int32_t batch, double delta, int32_t keep_lambda, void *state,
+                                   void *lambda, void *stream)
+{
+    if (!h) return TRAJAM_ERR_INVALID;
+    h->err.clear();
+    if (batch < 0 || !std::isfinite(delta) || (keep_lambda != 0 && keep_lambda != 1))
+        return hfail(h, TRAJAM_ERR_INVALID, "batch >= 0, finite delta, keep_lambda 0 or 1 required");
+    if (batch > h->prob.max_batch) return hfail(h, TRAJAM_ERR_CAPACITY, "batch > max_batch");
+    if (batch == 0) return TRAJAM_OK;
+    if (!state || !lambda) return hfail(h, TRAJAM_ERR_INVALID, "NULL pointer");
+    trajam::ShiftMatrix S;
+    S.nv = h->nv;
+    trajam::host_shift_matrix(h->prob.degree, delta / h->prob.horizon, S.s);
+    // each row of a sample (x, c, y, s, psi) is read whole before it is written, so the
+    // shift runs in place
+    hipError_t e = trajam::launch_mpc_shift(h->prob.precision == TRAJAM_FP64, batch * 5, S, state, lambda, state,
+                                            state, lambda, keep_lambda, (hipStream_t)stream);
+    if (e != hipSuccess) return hfail(h, TRAJAM_ERR_DEVICE, std::string("heading shift: ") + hipGetErrorString(e));
     return TRAJAM_OK;
 }
 

@@ -12,9 +12,8 @@ namespace {
 // One thread per (sample, [agent,] axis) row of n_v coefficients: the row is read
 // whole into registers before it is written, so the outputs may alias the inputs.
 template <typename T>
-__global__ __launch_bounds__(256) void mpc_shift_kernel(int rows, ShiftMatrix S, const T *__restrict__ xb,
-                                                        const T *__restrict__ lam, T *xi_next, T *xb_next,
-                                                        T *lam_next, int keep_lambda)
+__global__ __launch_bounds__(256) void mpc_shift_kernel(int rows, ShiftMatrix S, const T *xb, const T *lam,
+                                                        T *xi_next, T *xb_next, T *lam_next, int keep_lambda)
 {
     const int r = blockIdx.x * 256 + threadIdx.x;
     if (r >= rows) return;

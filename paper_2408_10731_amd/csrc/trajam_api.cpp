@@ -1058,6 +1058,11 @@ void shift_blossom(int n, double d, double *S /* [kShiftMaxCoeffs][kShiftMaxCoef
 
 }  // namespace
 
+namespace trajam {
+// The shift matrix S(d) for the heading variant's entry points (heading_api.cpp).
+void host_shift_matrix(int n, double d, double *S) { shift_blossom(n, d, S); }
+}  // namespace trajam
+
 extern "C" trajam_status trajam_mpc_shift(trajam_solver *s, int32_t batch, double delta, int32_t keep_lambda,
                                           const void *xi_bar, const void *lambda, void *xi_next,
                                           void *xi_bar_next, void *lambda_next, void *stream)

@@ -111,3 +111,67 @@ class MPC:
                             self.lam.data_ptr(), self.xi.data_ptr(), self.xb.data_ptr(), self.lam.data_ptr(), st)
         self.cycles += 1
         return out
+
+
+class HeadingMPC:
+    """The receding-horizon loop of the heading / multi-circle variant (Paper II,
+    Implementation Details: every control cycle starts from the preceding one's state
+    with both multipliers, lam and lam_psi, carried over).  One cycle: the scene of the
+    window (start rows, desired path, obstacles moved on), `iters` iterations of Alg 2
+    in the library, the executed sample (lowest final |F xi - g| at a 1e-6 resolution,
+    ties by the lowest index), its state at delta as the next start rows (x, y: position,
+    velocity, acceleration; psi), and trajam_heading_shift of every sample.  Marshalling
+    and control logic only; the host evaluates the executed sample at delta."""
+
+    def __init__(self, w, iters: int, delta: float, keep_lambda: bool = True, precision: str = "fp32",
+                 redraw_seed=None):
+        import torch
+        from . import workloads as wl
+        self.torch, self.wl = torch, wl
+        self.w = w
+        self.K, self.delta, self.keep_lambda = int(iters), float(delta), bool(keep_lambda)
+        self.s = tj.HeadingSolver(w, precision=precision)
+        dt = self.s.dtype
+        self.state = torch.as_tensor(w.xi0, dtype=dt, device="cuda").contiguous()
+        self.lam = torch.zeros_like(self.state)
+        self.trace = torch.zeros((self.K, self.state.shape[0], 2), dtype=dt, device="cuda")
+        self.boundary = np.array(w.boundary, dtype=np.float64)
+        self.boundary_psi = np.array(w.boundary_psi, dtype=np.float64)
+        self.centre = np.array(w.obs_centre, dtype=np.float64)
+        # redraw_seed: each next cycle starts from samples drawn afresh around the line
+        # from the new start to the goal (an input), the multipliers still carried over
+        self.rng = np.random.Generator(np.random.PCG64(redraw_seed)) if redraw_seed is not None else None
+        self.cycles = 0
+
+    def cycle(self):
+        """Run one control cycle; returns the executed sample, its coefficients [5, n_v]
+        (host), the cycle's boundary rows, obstacle centres at its start and residual
+        trace [K, B, 2] (device)."""
+        import dataclasses
+        w = self.w
+        elapsed = self.cycles * self.delta
+        wc = dataclasses.replace(w, boundary=self.boundary, boundary_psi=self.boundary_psi,
+                                 obs_centre=self.centre, x_des=self.wl.desired_window(w, elapsed))
+        self.s.set_scene(wc)
+        self.s.project(self.state, self.lam, self.K, self.trace)
+        r = self.trace[-1, :, 0].double().cpu().numpy()
+        i = int(np.argmin(np.floor(r / QUANTUM)))
+        coef = self.state[i].double().cpu().numpy()
+        out = {"executed": i, "coefficients": coef, "boundary": self.boundary.copy(),
+               "boundary_psi": self.boundary_psi.copy(), "obs_centre": self.centre.copy(), "trace": self.trace}
+        p, v, a = trajectory_state(coef[[0, 2]], w.horizon, self.delta)
+        psi = float(trajectory_state(coef[[4]], w.horizon, self.delta)[0][0])
+        self.boundary = self.boundary.copy()
+        self.boundary[:, 0], self.boundary[:, 1], self.boundary[:, 2] = p, v, a
+        self.boundary_psi = np.array([psi, self.boundary_psi[1]])
+        self.centre = self.centre + np.asarray(w.obs_vel, dtype=np.float64) * self.delta
+        self.s.shift(self.state, self.lam, self.delta, self.keep_lambda)
+        if self.rng is not None:
+            fresh = self.wl.heading_samples(self.rng, self.state.shape[0], self.boundary[:, 0], w.boundary[:, 3],
+                                            w.degree, self.boundary_psi[0])
+            self.state.copy_(self.torch.as_tensor(fresh, dtype=self.state.dtype, device="cuda"))
+        self.cycles += 1
+        return out
+
+    def close(self):
+        self.s.close()

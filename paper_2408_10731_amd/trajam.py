@@ -52,7 +52,7 @@ EXPORTS = [
     "trajam_ragged_plan_create", "trajam_ragged_launch", "trajam_ragged_plan_destroy", "trajam_polar",
     "trajam_qp_contraction", "trajam_set_continuation", "trajam_project_continuation",
     "trajam_heading_create", "trajam_heading_destroy", "trajam_heading_set_scene", "trajam_heading_project",
-    "trajam_heading_last_error",
+    "trajam_heading_last_error", "trajam_heading_shift",
     "trajam_status_string", "trajam_last_error",
 ]
 
@@ -252,6 +252,8 @@ def load():
     L.trajam_heading_set_scene.restype = ctypes.c_int
     L.trajam_heading_project.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp]
     L.trajam_heading_project.restype = ctypes.c_int
+    L.trajam_heading_shift.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, vp, vp, vp]
+    L.trajam_heading_shift.restype = ctypes.c_int
     L.trajam_heading_last_error.argtypes = [vp]
     L.trajam_heading_last_error.restype = ctypes.c_char_p
     L.trajam_status_string.argtypes = [ctypes.c_int]
@@ -759,6 +761,11 @@ def trajam_heading_project(handle, batch, state, lam, iters, res_trace, stream) 
     _hcheck(load().trajam_heading_project(handle, int(batch), state, lam, int(iters), res_trace, stream), handle)
 
 
+def trajam_heading_shift(handle, batch, delta, keep_lambda, state, lam, stream) -> None:
+    _hcheck(load().trajam_heading_shift(handle, int(batch), float(delta), int(bool(keep_lambda)), state, lam,
+                                        stream), handle)
+
+
 def make_heading_problem(degree, n_steps, horizon, v_max, a_max, rho, radii, n_obstacles, max_batch,
                          precision="fp32") -> HeadingProblem:
     p = HeadingProblem()
@@ -811,6 +818,13 @@ class HeadingSolver:
         st = torch.cuda.current_stream().cuda_stream
         trajam_heading_project(self.handle, B, state.data_ptr(), lam.data_ptr(), iters,
                                res_trace.data_ptr() if res_trace is not None else None, st)
+
+    def shift(self, state, lam, delta, keep_lambda=True):
+        """Receding horizon: state and lam [B, 5, n_v] re-expressed in place on the window
+        moved on by delta (the multipliers kept or cleared)."""
+        import torch
+        st = torch.cuda.current_stream().cuda_stream
+        trajam_heading_shift(self.handle, state.shape[0], delta, keep_lambda, state.data_ptr(), lam.data_ptr(), st)
 
     def close(self):
         if getattr(self, "handle", None):

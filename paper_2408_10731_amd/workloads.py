@@ -366,6 +366,26 @@ class HeadingWorkload:
         return int(self.xi0.shape[0])
 
 
+def heading_samples(rng, batch: int, start, goal, degree: int, psi0: float = 0.0) -> np.ndarray:
+    """Initial states [batch, 5, n_v] of the heading variant around the line from start
+    to goal: x along the line plus N(0, 0.3^2) per coefficient, y with a lateral bump of
+    amplitude N(0, 1.5^2) plus N(0, 0.3^2), heading coefficients psi0 + N(0, 0.2^2), c and
+    s their cosines and sines."""
+    start, goal = np.asarray(start, dtype=np.float64), np.asarray(goal, dtype=np.float64)
+    nv = degree + 1
+    frac = np.arange(nv) / degree
+    bump = np.sin(np.pi * frac)
+    xi0 = np.zeros((batch, 5, nv))
+    xi0[:, 0] = start[0] + frac * (goal[0] - start[0]) + rng.normal(0.0, 0.3, (batch, nv))
+    xi0[:, 2] = (start[1] + frac * (goal[1] - start[1]) + rng.normal(0.0, 1.5, (batch, 1)) * bump
+                 + rng.normal(0.0, 0.3, (batch, nv)))
+    psi = psi0 + rng.normal(0.0, 0.2, (batch, nv))
+    xi0[:, 4] = psi
+    xi0[:, 1] = np.cos(psi)
+    xi0[:, 3] = np.sin(psi)
+    return xi0
+
+
 def heading_scene(seed: int, n_obs: int = 30, n_circles: int = 4, batch: int = 1000,
                   iters: int = 10, flow: str = "static", degree: int = 10, n_steps: int = 100) -> HeadingWorkload:
     """Paper II's crowd benchmarks as synthetic scenes: a 1.2 m x 0.6 m robot (n_circles
@@ -397,15 +417,9 @@ def heading_scene(seed: int, n_obs: int = 30, n_circles: int = 4, batch: int = 1
     elif flow != "static":
         raise ValueError(flow)
     axes = np.full((n_obs, 2), 0.55)
-    nv = degree + 1
-    frac = np.arange(nv) / degree
-    bump = np.sin(np.pi * frac)
-    xi0 = np.zeros((batch, 5, nv))
-    xi0[:, 0] = start[0] + frac * (goal[0] - start[0]) + rng.normal(0.0, 0.3, (batch, nv))
-    xi0[:, 2] = rng.normal(0.0, 1.5, (batch, 1)) * bump + rng.normal(0.0, 0.3, (batch, nv))
-    psi = rng.normal(0.0, 0.2, (batch, nv))
+    xi0 = heading_samples(rng, batch, start, goal, degree)
+    psi = xi0[:, 4]
     psi[:, 0] = psi[:, -1] = 0.0
-    xi0[:, 4] = psi
     xi0[:, 1] = np.cos(psi)
     xi0[:, 3] = np.sin(psi)
     bnd = np.zeros((2, 4))
@@ -415,3 +429,13 @@ def heading_scene(seed: int, n_obs: int = 30, n_circles: int = 4, batch: int = 1
     x_des = start[:, None] + (goal - start)[:, None] * (t / T)[None, :]
     return HeadingWorkload(f"heading-{flow}-n{n_obs}-c{n_circles}-b{batch}", degree, n_steps, T, 2.0, 2.0,
                            1.0, radii, centre, vel, axes, bnd, np.zeros(2), x_des, xi0, iters)
+
+
+def desired_window(w: HeadingWorkload, elapsed: float) -> np.ndarray:
+    """The desired positions [2, n_steps] of the window that starts `elapsed` seconds
+    after w's: the straight line from w.x_des's first point to its last at w's constant
+    speed, held at the last point once reached."""
+    t = np.linspace(0.0, w.horizon, w.n_steps)
+    p0, pf = w.x_des[:, 0], w.x_des[:, -1]
+    frac = np.minimum(1.0, (elapsed + t) / w.horizon)
+    return p0[:, None] + (pf - p0)[:, None] * frac[None, :]

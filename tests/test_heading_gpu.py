@@ -169,3 +169,28 @@ def test_heading_iters0_empty_batch_and_errors():
         tj.trajam_heading_project(h, 1, big.data_ptr(), big.data_ptr(), 1, None, None)
     assert e.value.status == tj.TRAJAM_ERR_INVALID
     tj.trajam_heading_destroy(h)
+
+
+def test_heading_receding_horizon_matches_the_oracle():
+    """Paper II's MPC on the heading variant (FP64): each cycle's executed sample, its
+    result, multipliers and next start rows against the oracle's loop, cycle by cycle,
+    carrying the multipliers over and clearing them, with the next samples moved on or
+    drawn afresh."""
+    from paper_2408_10731_amd import mpc as mp
+    w = wl.heading_scene(17, n_obs=6, n_circles=3, batch=12, flow="opposite")
+    kappa = coefficient_kappa(w)
+    for keep, redraw in ((True, None), (False, None), (True, 77)):
+        say("case: heading receding horizon FP64, 3 cycles, keep_lambda", keep, "redraw", redraw)
+        ref = oh.mpc(w, 3, 0.5, 6, keep_lambda=keep, redraw_seed=redraw)
+        m = mp.HeadingMPC(w, 6, 0.5, keep_lambda=keep, precision="fp64", redraw_seed=redraw)
+        for k, c in enumerate(ref):
+            g_state = m.state.cpu().numpy()
+            out = m.cycle()
+            assert out["executed"] == c.executed, k
+            assert waypoint_rel(w, g_state, c.state) <= 1e-9
+            np.testing.assert_allclose(out["boundary"], c.boundary, atol=1e-9)
+            np.testing.assert_allclose(out["boundary_psi"], c.boundary_psi, atol=1e-9)
+            res_g = torch.as_tensor(out["coefficients"])
+            assert waypoint_rel(w, res_g.numpy()[None], c.result[c.executed][None]) <= 1e-9
+            assert rel(out["trace"].cpu().numpy(), c.trace) <= 1e-9
+        m.close()

@@ -310,3 +310,32 @@ def test_initial_state_meets_the_boundary_rows():
     np.testing.assert_allclose([bpoly(out[4], T)(0.0), bpoly(out[4], T)(T)], w.boundary_psi, atol=1e-12)
     np.testing.assert_array_equal(out[4, 1:nv - 1], st[4, 1:nv - 1])
     np.testing.assert_array_equal(out[[1, 3]], st[[1, 3]])
+
+
+def test_receding_horizon_cycle_hands_over_the_executed_state():
+    """One cycle of the heading MPC oracle: the next start rows are the executed sample's
+    position, velocity, acceleration and heading at delta, and the next cycle's samples
+    are the results' polynomials moved on by delta (both checked with scipy's
+    polynomials); the first cycle is Alg 2 from the input state."""
+    w = tiny(11, n_obs=3, n_c=2, batch=4, flow="same")
+    T, d = w.horizon, 0.8
+    cyc = oh.mpc(w, 2, d, 5)
+    first = oh.iterate(w, 5)
+    np.testing.assert_array_equal(cyc[0].result, first[0])
+    res, i = cyc[0].result, cyc[0].executed
+    assert i == int(np.argmin(np.floor(cyc[0].trace[-1, :, 0] / 1e-6)))
+    for grp, row in ((0, 0), (1, 2)):
+        got = [bpoly(res[i, row], T, nu)(d) for nu in (0, 1, 2)]
+        np.testing.assert_allclose(cyc[1].boundary[grp, :3], got, atol=1e-10)
+        assert cyc[1].boundary[grp, 3] == w.boundary[grp, 3]
+    assert abs(cyc[1].boundary_psi[0] - bpoly(res[i, 4], T)(d)) < 1e-10
+    tq = np.linspace(0.0, T - d, 7)
+    for b in range(w.batch):
+        for r in range(5):
+            np.testing.assert_allclose(bpoly(cyc[1].state[b, r], T)(tq), bpoly(res[b, r], T)(tq + d), atol=1e-9)
+    # the second cycle is Alg 2 from the shifted samples with the first cycle's multipliers
+    wc = dataclasses.replace(w, xi0=cyc[1].state, boundary=cyc[1].boundary, boundary_psi=cyc[1].boundary_psi,
+                             obs_centre=w.obs_centre + w.obs_vel * d, x_des=wl.desired_window(w, d))
+    again = oh.iterate(wc, 5, state=cyc[1].state, lam=cyc[0].lam)
+    np.testing.assert_array_equal(again[0], cyc[1].result)
+    np.testing.assert_array_equal(again[1], cyc[1].lam)
