@@ -1341,21 +1341,23 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
     constexpr int LOGV = (V >= 64) ? 6 : (V >= 32) ? 5 : (V >= 16) ? 4 : 3;
     constexpr int OSH = 6 - LOGV;
     const int nf = a.nv - 4;
-    // This lane's time samples and their basis rows (registers for the launch).
-    T tt[TPL], phi0[TPL][NVP], phi1[TPL][NVP], phi2[TPL][NVP];
+    // This lane's time samples: the position rows of the basis in registers for the
+    // launch; the derivative rows are read from the (cache-resident) table where they
+    // are used, a row at a time, which keeps the wave at two per SIMD.  Lanes past n_p
+    // read row 0 and discard what it gives.
+    T tt[TPL], phi0[TPL][NVP];
     bool valid[TPL];
+    const T *drow[TPL];   // the lane's first-derivative row; the second follows n_p rows later
 #pragma unroll
     for (int i = 0; i < TPL; ++i) {
         const int t = lane + 64 * i;
         valid[i] = t < a.n_p;
         tt[i] = T(t) * a.dt;
+        drow[i] = a.phi + (size_t)(1 * a.n_p + (valid[i] ? t : 0)) * NVP;
 #pragma unroll
-        for (int m = 0; m < NVP; ++m) {
-            phi0[i][m] = valid[i] ? a.phi[(0 * a.n_p + t) * NVP + m] : T(0);
-            phi1[i][m] = valid[i] ? a.phi[(1 * a.n_p + t) * NVP + m] : T(0);
-            phi2[i][m] = valid[i] ? a.phi[(2 * a.n_p + t) * NVP + m] : T(0);
-        }
+        for (int m = 0; m < NVP; ++m) phi0[i][m] = valid[i] ? a.phi[(0 * a.n_p + t) * NVP + m] : T(0);
     }
+    const size_t d2 = (size_t)a.n_p * NVP;   // from a first-derivative row to its second
 
     const int o = lane >> OSH;
     const bool owner = (lane & ((1 << OSH) - 1)) == 0 && o < S;
@@ -1401,17 +1403,26 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) { p[i][ax] = T(0); v[i][ax] = T(0); acc[i][ax] = T(0); }
 #pragma unroll
-        for (int ax = 0; ax < D; ++ax)
+        for (int i = 0; i < TPL; ++i) {
+            T r1[NVP], r2r[NVP];
 #pragma unroll
             for (int m = 0; m < NVP; ++m) {
-                const T c = xs[ax * NVP + m];
-#pragma unroll
-                for (int i = 0; i < TPL; ++i) {
-                    p[i][ax] = fma(phi0[i][m], c, p[i][ax]);
-                    v[i][ax] = fma(phi1[i][m], c, v[i][ax]);
-                    acc[i][ax] = fma(phi2[i][m], c, acc[i][ax]);
-                }
+                r1[m] = drow[i][m];
+                r2r[m] = drow[i][d2 + m];
             }
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+                for (int m = 0; m < NVP; ++m) {
+                    const T c = xs[ax * NVP + m];
+                    p[i][ax] = fma(phi0[i][m], c, p[i][ax]);
+                    v[i][ax] = fma(r1[m], c, v[i][ax]);
+                    acc[i][ax] = fma(r2r[m], c, acc[i][ax]);
+                }
+            if (!valid[i])
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax) { v[i][ax] = T(0); acc[i][ax] = T(0); }
+        }
         // Lanes past n_p sit at -1e30: never inside an obstacle, and far from the
         // padding sentinels at +1e30 as well.
 #pragma unroll
@@ -1451,16 +1462,24 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
             for (int j = 0; j < V; ++j) c[j] = T(0);
 #pragma unroll
             for (int i = 0; i < TPL; ++i) {
-                if (aA)
+                if (aA) {
+                    T row[NVP];
+#pragma unroll
+                    for (int m = 0; m < NVP; ++m) row[m] = drow[i][d2 + m];
 #pragma unroll
                     for (int ax = 0; ax < D; ++ax)
 #pragma unroll
-                        for (int m = 0; m < NVP; ++m) c[ax * NVP + m] = fma(phi2[i][m], ra[i][ax], c[ax * NVP + m]);
-                if (aV)
+                        for (int m = 0; m < NVP; ++m) c[ax * NVP + m] = fma(row[m], ra[i][ax], c[ax * NVP + m]);
+                }
+                if (aV) {
+                    T row[NVP];
+#pragma unroll
+                    for (int m = 0; m < NVP; ++m) row[m] = drow[i][m];
 #pragma unroll
                     for (int ax = 0; ax < D; ++ax)
 #pragma unroll
-                        for (int m = 0; m < NVP; ++m) c[ax * NVP + m] = fma(phi1[i][m], rv[i][ax], c[ax * NVP + m]);
+                        for (int m = 0; m < NVP; ++m) c[ax * NVP + m] = fma(row[m], rv[i][ax], c[ax * NVP + m]);
+                }
                 if (aR)
 #pragma unroll
                     for (int ax = 0; ax < D; ++ax)
