@@ -1342,10 +1342,14 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
     constexpr int OSH = 6 - LOGV;
     const int nf = a.nv - 4;
     // This lane's time samples: the position rows of the basis in registers for the
-    // launch; the derivative rows are read from the (cache-resident) table where they
-    // are used, a row at a time, which keeps the wave at two per SIMD.  Lanes past n_p
-    // read row 0 and discard what it gives.
-    T tt[TPL], phi0[TPL][NVP];
+    // launch.  In the plain FP32 kernel the derivative rows are read from the
+    // (cache-resident) table where they are used, a row at a time, which keeps the
+    // config-3 wave at two per SIMD; in FP64 and with the matrix-core QP they stay in
+    // registers too (there the loads cost more than the occupancy they would buy).
+    // Lanes past n_p read row 0 and discard what it gives.
+    constexpr bool kHold = sizeof(T) == 8 || MQP;
+    constexpr int HR = kHold ? TPL : 1;
+    T tt[TPL], phi0[TPL][NVP], phi1[HR][NVP], phi2[HR][NVP];
     bool valid[TPL];
     const T *drow[TPL];   // the lane's first-derivative row; the second follows n_p rows later
 #pragma unroll
@@ -1358,6 +1362,15 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
         for (int m = 0; m < NVP; ++m) phi0[i][m] = valid[i] ? a.phi[(0 * a.n_p + t) * NVP + m] : T(0);
     }
     const size_t d2 = (size_t)a.n_p * NVP;   // from a first-derivative row to its second
+    if constexpr (kHold) {
+#pragma unroll
+        for (int i = 0; i < HR; ++i)
+#pragma unroll
+            for (int m = 0; m < NVP; ++m) {
+                phi1[i][m] = valid[i] ? drow[i][m] : T(0);
+                phi2[i][m] = valid[i] ? drow[i][d2 + m] : T(0);
+            }
+    }
 
     const int o = lane >> OSH;
     const bool owner = (lane & ((1 << OSH) - 1)) == 0 && o < S;
@@ -1402,26 +1415,41 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
         for (int i = 0; i < TPL; ++i)
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) { p[i][ax] = T(0); v[i][ax] = T(0); acc[i][ax] = T(0); }
-#pragma unroll
-        for (int i = 0; i < TPL; ++i) {
-            T r1[NVP], r2r[NVP];
-#pragma unroll
-            for (int m = 0; m < NVP; ++m) {
-                r1[m] = drow[i][m];
-                r2r[m] = drow[i][d2 + m];
-            }
+        if constexpr (kHold) {
 #pragma unroll
             for (int ax = 0; ax < D; ++ax)
 #pragma unroll
                 for (int m = 0; m < NVP; ++m) {
                     const T c = xs[ax * NVP + m];
-                    p[i][ax] = fma(phi0[i][m], c, p[i][ax]);
-                    v[i][ax] = fma(r1[m], c, v[i][ax]);
-                    acc[i][ax] = fma(r2r[m], c, acc[i][ax]);
-                }
-            if (!valid[i])
 #pragma unroll
-                for (int ax = 0; ax < D; ++ax) { v[i][ax] = T(0); acc[i][ax] = T(0); }
+                    for (int i = 0; i < TPL; ++i) {
+                        p[i][ax] = fma(phi0[i][m], c, p[i][ax]);
+                        v[i][ax] = fma(phi1[i < HR ? i : 0][m], c, v[i][ax]);
+                        acc[i][ax] = fma(phi2[i < HR ? i : 0][m], c, acc[i][ax]);
+                    }
+                }
+        } else {
+#pragma unroll
+            for (int i = 0; i < TPL; ++i) {
+                T r1[NVP], r2r[NVP];
+#pragma unroll
+                for (int m = 0; m < NVP; ++m) {
+                    r1[m] = drow[i][m];
+                    r2r[m] = drow[i][d2 + m];
+                }
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+                    for (int m = 0; m < NVP; ++m) {
+                        const T c = xs[ax * NVP + m];
+                        p[i][ax] = fma(phi0[i][m], c, p[i][ax]);
+                        v[i][ax] = fma(r1[m], c, v[i][ax]);
+                        acc[i][ax] = fma(r2r[m], c, acc[i][ax]);
+                    }
+                if (!valid[i])
+#pragma unroll
+                    for (int ax = 0; ax < D; ++ax) { v[i][ax] = T(0); acc[i][ax] = T(0); }
+            }
         }
         // Lanes past n_p sit at -1e30: never inside an obstacle, and far from the
         // padding sentinels at +1e30 as well.
@@ -1462,23 +1490,38 @@ __device__ __forceinline__ void wave_sample(const A &a, const int sample, const 
             for (int j = 0; j < V; ++j) c[j] = T(0);
 #pragma unroll
             for (int i = 0; i < TPL; ++i) {
-                if (aA) {
-                    T row[NVP];
+                if constexpr (kHold) {
+                    if (aA)
 #pragma unroll
-                    for (int m = 0; m < NVP; ++m) row[m] = drow[i][d2 + m];
+                        for (int ax = 0; ax < D; ++ax)
 #pragma unroll
-                    for (int ax = 0; ax < D; ++ax)
+                            for (int m = 0; m < NVP; ++m)
+                                c[ax * NVP + m] = fma(phi2[i < HR ? i : 0][m], ra[i][ax], c[ax * NVP + m]);
+                    if (aV)
 #pragma unroll
-                        for (int m = 0; m < NVP; ++m) c[ax * NVP + m] = fma(row[m], ra[i][ax], c[ax * NVP + m]);
-                }
-                if (aV) {
-                    T row[NVP];
+                        for (int ax = 0; ax < D; ++ax)
 #pragma unroll
-                    for (int m = 0; m < NVP; ++m) row[m] = drow[i][m];
+                            for (int m = 0; m < NVP; ++m)
+                                c[ax * NVP + m] = fma(phi1[i < HR ? i : 0][m], rv[i][ax], c[ax * NVP + m]);
+                } else {
+                    if (aA) {
+                        T row[NVP];
 #pragma unroll
-                    for (int ax = 0; ax < D; ++ax)
+                        for (int m = 0; m < NVP; ++m) row[m] = drow[i][d2 + m];
 #pragma unroll
-                        for (int m = 0; m < NVP; ++m) c[ax * NVP + m] = fma(row[m], rv[i][ax], c[ax * NVP + m]);
+                        for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+                            for (int m = 0; m < NVP; ++m) c[ax * NVP + m] = fma(row[m], ra[i][ax], c[ax * NVP + m]);
+                    }
+                    if (aV) {
+                        T row[NVP];
+#pragma unroll
+                        for (int m = 0; m < NVP; ++m) row[m] = drow[i][m];
+#pragma unroll
+                        for (int ax = 0; ax < D; ++ax)
+#pragma unroll
+                            for (int m = 0; m < NVP; ++m) c[ax * NVP + m] = fma(row[m], rv[i][ax], c[ax * NVP + m]);
+                    }
                 }
                 if (aR)
 #pragma unroll
