@@ -714,7 +714,8 @@ def heading_mpc_bench(args, delta=0.5, iters=10, horizon_s=20.0):
     circle of the executed motion (checked every 0.05 s) enters a person's ellipse.
     Reports the success rate, the tracking error against the desired line and the
     acceleration of the executed motion, and the time per cycle, for next samples moved
-    on from the cycle's results and for samples drawn afresh each cycle."""
+    on from the cycle's results and for samples drawn afresh each cycle; the latter also
+    with 30 and 100 iterations a cycle (the thesis's budget is 40 ms a cycle)."""
     from paper_2408_10731_amd import mpc as mp
     from paper_2408_10731_amd import workloads as wl
 
@@ -724,11 +725,13 @@ def heading_mpc_bench(args, delta=0.5, iters=10, horizon_s=20.0):
                      f"{iters} iterations a cycle, FP32, multipliers carried over",
            "by_batch": {}}
     ts = np.linspace(0.0, delta, 11)[:-1]
-    for mode, B in [("moved_on", b) for b in (1, 200, 1000)] + [("redrawn", b) for b in (1, 50, 200, 1000)]:
+    runs = ([("moved_on", b, iters) for b in (1, 200, 1000)] + [("redrawn", b, iters) for b in (1, 50, 200, 1000)]
+            + [("redrawn", b, k) for k in (30, 100) for b in (200, 1000)])
+    for mode, B, its in runs:
         ok_runs, errs, accs, cyc_ms = 0, [], [], []
         for sd in seeds:
             w = wl.heading_scene(sd, n_obs=30, n_circles=4, batch=B, flow="static")
-            m = mp.HeadingMPC(w, iters, delta, redraw_seed=(sd + 7) if mode == "redrawn" else None)
+            m = mp.HeadingMPC(w, its, delta, redraw_seed=(sd + 7) if mode == "redrawn" else None)
             ok = True
             t0 = time.perf_counter()
             for c in range(n_cyc):
@@ -749,7 +752,8 @@ def heading_mpc_bench(args, delta=0.5, iters=10, horizon_s=20.0):
             cyc_ms.append(1e3 * (time.perf_counter() - t0) / n_cyc)
             ok_runs += ok
             m.close()
-        out["by_batch"].setdefault(mode, {})[str(B)] = {"success_rate": ok_runs / len(seeds),
+        key = mode if its == iters else f"{mode}_{its}_iterations"
+        out["by_batch"].setdefault(key, {})[str(B)] = {"success_rate": ok_runs / len(seeds),
                                    "tracking_error_m": [float(np.mean(errs)), float(np.max(errs)), float(np.min(errs))],
                                    "acceleration": [float(np.mean(accs)), float(np.max(accs)), float(np.min(accs))],
                                    "ms_per_cycle": float(np.median(cyc_ms))}
